@@ -1,0 +1,308 @@
+"""Sparse-grid combination solve, its adjoint and the full-grid solve (oracle).
+
+Test infrastructure only (see the package docstring).
+
+Discrete problem of one component (paper eq. 9, algebraic form of Prop. 1):
+unknown u_c[i,k] is the coefficient of psi_i(t) phi_k(x) (time index outer),
+
+    S_c = A_{jt} (x) M_{jx} + B_{jt} (x) K_{jx},      S_c u_c = b_c,
+
+    b_c[i,k] = sum_{n,m} W[i,n] (Phi^T M^J)[k,m] f[n,m]
+               + psi_i'(0) (Phi^T M^J v0)[k] - g[i] (Phi^T K^J u0)[k],
+
+with W, g as in ``timemat`` and Phi the nodal prolongation level jx -> J
+(the data f, u0, v0 are nodal values on the finest grid, read as their
+P1/Q1 interpolants in space and P1 interpolant in time; boundary values 0).
+
+Combination (eq. 19) and lift (Sec. 2.1, the solution of (1) is u + u0):
+
+    U[n,m] = u0[m] + sum_c s_c sum_{i,k} u_c[i,k] psi_i(t_n) phi_k(x_m).
+
+S_c is factorised by SuperLU.  Because the time matrices become badly
+conditioned as 2^jt grows, the solve is refined iteratively with the
+residual b - S x accumulated in 80-bit long double until the correction is
+below 1e-15 of the solution (at most 10 sweeps).
+
+The adjoint applies the explicit transposes of the three linear steps:
+y_c = s_c Psi^T g Phi,  z_c = S_c^{-T} y_c,
+df = sum_c W^T z_c (Phi^T M^J),  dv0 = sum_c (d0^T z_c)(Phi^T M^J),
+du0 = sum_n g[n,:] - sum_c (g^T z_c)(Phi^T K^J).
+"""
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import levels, space, timemat
+
+
+class Problem:
+    """The data of eq. (1) that fix the discrete operator.
+
+    d in {1,2}; lengths: side lengths of Omega = prod (0, len_i);
+    ncell, c_vals: piecewise-constant wave speed on a uniform block grid
+    (x fastest); T: final time; L: sparse level (components C_L)."""
+
+    def __init__(self, d, lengths, ncell, c_vals, T, L):
+        if d not in (1, 2) or len(lengths) != d or len(ncell) != d:
+            raise ValueError("d must be 1 or 2 with one length/ncell per axis")
+        if T <= 0 or L < 2:
+            raise ValueError("need T > 0 and L >= 2")
+        self.d = d
+        self.T = float(T)
+        self.L = int(L)
+        self.J = levels.finest_level(L)
+        self.medium = space.Medium(lengths, ncell, c_vals)
+        self.comps = levels.components(L)
+        self._cache = {}
+
+    # ----- sizes -------------------------------------------------------
+    @property
+    def nt_fine(self):
+        return 2 ** self.J + 1
+
+    @property
+    def ns_fine(self):
+        return (2 ** self.J - 1) ** self.d
+
+    def fine_shape(self):
+        n = 2 ** self.J - 1
+        return (self.nt_fine,) + (n,) * self.d
+
+    # ----- cached operators --------------------------------------------
+    def _get(self, key, make):
+        if key not in self._cache:
+            self._cache[key] = make()
+        return self._cache[key]
+
+    def mass(self, j):
+        return self._get(("M", j), lambda: space.mass(j, self.medium))
+
+    def stiff(self, j):
+        return self._get(("K", j), lambda: space.stiff(j, self.medium))
+
+    def phi(self, j, J=None):
+        J = self.J if J is None else J
+        return self._get(("Phi", j, J), lambda: space.interp(j, J, self.medium))
+
+    def tmat(self, jt):
+        return self._get(("T", jt), lambda: timemat.time_matrices(jt, self.T))
+
+    def wload(self, jt, J=None):
+        J = self.J if J is None else J
+        return self._get(("W", jt, J), lambda: timemat.load_weights(jt, J, self.T))
+
+    def psi_nodes(self, jt, J=None):
+        J = self.J if J is None else J
+        return self._get(("Psi", jt, J), lambda: timemat.eval_at_nodes(jt, J, self.T))
+
+    def cross_mass(self, jx):
+        """(Phi^T M^J)[k,m] = (phi^J_m, phi^jx_k), exact by nesting."""
+        return self._get(("MJc", jx), lambda: (self.phi(jx).T @ self.mass(self.J)).tocsr())
+
+    def cross_stiff(self, jx):
+        """(Phi^T K^J)[k,m] = (c^2 grad phi^J_m, grad phi^jx_k), exact by nesting."""
+        return self._get(("KJc", jx), lambda: (self.phi(jx).T @ self.stiff(self.J)).tocsr())
+
+    def system(self, jx, jt):
+        """Sparse S_c = A (x) M + B (x) K (time index outer), CSR."""
+        def make():
+            tm = self.tmat(jt)
+            return (sp.kron(sp.csr_matrix(tm["A"]), self.mass(jx))
+                    + sp.kron(sp.csr_matrix(tm["B"]), self.stiff(jx))).tocsr()
+        return self._get(("S", jx, jt), make)
+
+    def factor(self, jx, jt):
+        return self._get(("LU", jx, jt), lambda: spla.splu(self.system(jx, jt).tocsc()))
+
+    # ----- the three linear steps --------------------------------------
+    def load(self, jx, jt, f, u0, v0):
+        """b_c of eq. (9) from nodal fine-grid data; shape (2^jt+1, n_space)."""
+        f = np.asarray(f, dtype=np.float64).reshape(self.nt_fine, self.ns_fine)
+        u0 = np.asarray(u0, dtype=np.float64).reshape(self.ns_fine)
+        v0 = np.asarray(v0, dtype=np.float64).reshape(self.ns_fine)
+        tm = self.tmat(jt)
+        MJc = self.cross_mass(jx)
+        b = self.wload(jt) @ np.asarray((MJc @ f.T).T)
+        b += np.outer(tm["d0"], MJc @ v0)
+        b -= np.outer(tm["g"], self.cross_stiff(jx) @ u0)
+        return b
+
+    def solve(self, jx, jt, b, transpose=False):
+        """u = S_c^{-1} b (or S_c^{-T} b) with long-double residual refinement."""
+        S = self.system(jx, jt)
+        if transpose:
+            S = self._get(("ST", jx, jt), lambda: S.T.tocsr())
+        lu = self.factor(jx, jt)
+        trans = "T" if transpose else "N"
+        rhs = np.asarray(b, dtype=np.float64).reshape(-1)
+        x = lu.solve(rhs, trans=trans)
+        for _ in range(10):
+            r = _residual_longdouble(S, x, rhs)
+            dx = lu.solve(np.asarray(r, dtype=np.float64), trans=trans)
+            x = x + dx
+            if np.linalg.norm(dx) <= 1e-15 * max(np.linalg.norm(x), 1e-300):
+                break
+        return x.reshape(np.shape(b))
+
+    def prolong(self, jx, jt, u):
+        """Nodal values on the finest grid of sum_{i,k} u[i,k] psi_i phi_k."""
+        Y = self.psi_nodes(jt) @ u                    # (NT, n_space(jx))
+        return np.asarray((self.phi(jx) @ Y.T).T)     # (NT, NS)
+
+    # ----- forward / adjoint -------------------------------------------
+    def component_solutions(self, f, u0, v0):
+        return [self.solve(jx, jt, self.load(jx, jt, f, u0, v0))
+                for jx, jt, _ in self.comps]
+
+    def combine(self, sols, u0):
+        U = np.tile(np.asarray(u0, dtype=np.float64).reshape(1, self.ns_fine),
+                    (self.nt_fine, 1))
+        for (jx, jt, s), u in zip(self.comps, sols):
+            U += s * self.prolong(jx, jt, u)
+        return U
+
+    def forward(self, f, u0, v0):
+        """U on the finest grid, shape (2^J+1, n^d) flattened in space."""
+        return self.combine(self.component_solutions(f, u0, v0), u0)
+
+    def adjoint(self, g):
+        """(df, du0, dv0) = F^T g for the linear map F: (f,u0,v0) -> U."""
+        g = np.asarray(g, dtype=np.float64).reshape(self.nt_fine, self.ns_fine)
+        df = np.zeros_like(g)
+        du0 = g.sum(axis=0)
+        dv0 = np.zeros(self.ns_fine)
+        for jx, jt, s in self.comps:
+            y = s * (self.psi_nodes(jt).T @ np.asarray((self.phi(jx).T @ g.T).T))
+            z = self.solve(jx, jt, y, transpose=True)
+            tm = self.tmat(jt)
+            MJc = self.cross_mass(jx)
+            df += np.asarray((MJc.T @ (self.wload(jt).T @ z).T).T)
+            dv0 += MJc.T @ (tm["d0"] @ z)
+            du0 -= self.cross_stiff(jx).T @ (tm["g"] @ z)
+        return df, du0, dv0
+
+    def full_grid(self, j, f, u0, v0):
+        """P_{j,j} (eq. 10 with jx = jt = j <= J) plus u0, on the finest grid."""
+        u = self.solve(j, j, self.load(j, j, f, u0, v0))
+        U = np.tile(np.asarray(u0, dtype=np.float64).reshape(1, self.ns_fine),
+                    (self.nt_fine, 1))
+        return U + self.prolong(j, j, u)
+
+
+def _residual_longdouble(S, x, b):
+    """b - S x with every product and sum in 80-bit long double."""
+    S = S.tocsr()
+    if np.any(S.indptr[:-1] == S.indptr[1:]):
+        raise ValueError("system matrix has an empty row")
+    prod = S.data.astype(np.longdouble) * x.astype(np.longdouble)[S.indices]
+    rows = np.add.reduceat(prod, S.indptr[:-1])  # segmented row sums
+    return b.astype(np.longdouble) - rows
+
+
+# ----------------------------------------------------------------------
+# Extras used only by the convergence-rate pins: the load of eq. (9) built
+# from closed-form data by quadrature (so that only the discretisation error
+# is measured), and the L^2(Q_T) error of the combined solution.
+# ----------------------------------------------------------------------
+
+_NQ = 5
+_QX, _QW = np.polynomial.legendre.leggauss(_NQ)
+
+
+def fine_quadrature(J, length):
+    """Gauss points/weights on every element of the level-J mesh of (0,length)."""
+    h = length / 2 ** J
+    left = h * np.arange(2 ** J)
+    pts = (left[:, None] + 0.5 * h * (_QX[None, :] + 1.0)).reshape(-1)
+    wts = np.tile(0.5 * h * _QW, 2 ** J)
+    return pts, wts
+
+
+def load_exact(prob, jx, jt, f_fn, u0_fn, v0_fn, grad_u0_fn):
+    """b_c of eq. (9) for closed-form data, by quadrature on the finest mesh.
+
+    f_fn(t, *x) and the initial data are vectorised callables on tensor grids;
+    grad_u0_fn returns the list of partial derivatives.  Only c == const
+    problems use this (c^2 is taken from block 0)."""
+    from . import basis
+    J = prob.J
+    T = prob.T
+    c2 = float(prob.medium.c.reshape(-1)[0]) ** 2
+    tq, tw = fine_quadrature(J, T)
+    dpsi = basis.time_basis(jt, T, tq, 1) * (tw * np.exp(-tq / T))[:, None]
+    d0 = basis.time_basis(jt, T, np.array([0.0]), 1)[0]
+    g = dpsi.sum(axis=0)
+    axes = []
+    for ax in range(prob.d):
+        xq, xw = fine_quadrature(J, prob.medium.lengths[ax])
+        axes.append((xq, xw, basis.hat_1d(jx, prob.medium.lengths[ax], xq),
+                     basis.hat_1d_deriv(jx, prob.medium.lengths[ax], xq)))
+    if prob.d == 1:
+        xq, xw, ph, dph = axes[0]
+        F = f_fn(tq[:, None], xq[None, :])                      # (t, x)
+        b = dpsi.T @ (F @ (ph * xw[:, None]))
+        b += np.outer(d0, (v0_fn(xq) * xw) @ ph)
+        (du,) = grad_u0_fn(xq)
+        b -= np.outer(g, c2 * (du * xw) @ dph)
+        return b
+    (xq, xw, phx, dphx), (yq, yw, phy, dphy) = axes
+    F = f_fn(tq[:, None, None], xq[None, None, :], yq[None, :, None])  # (t,y,x)
+    P = np.einsum("tyx,xk->tyk", F, phx * xw[:, None])
+    P = np.einsum("tyk,yl->tlk", P, phy * yw[:, None])
+    b = np.einsum("ti,tlk->ilk", dpsi, P).reshape(dpsi.shape[1], -1)
+    V = v0_fn(xq[None, :], yq[:, None]) * yw[:, None] * xw[None, :]
+    b += np.outer(d0, (phy.T @ V @ phx).reshape(-1))
+    ux, uy = grad_u0_fn(xq[None, :], yq[:, None])
+    W2 = yw[:, None] * xw[None, :]
+    Ku0 = phy.T @ (c2 * ux * W2) @ dphx + dphy.T @ (c2 * uy * W2) @ phx
+    b -= np.outer(g, Ku0.reshape(-1))
+    return b
+
+
+def combined_at(prob, sols, tq, xqs, u0_fn=None):
+    """Combined solution sum_c s_c u_c(x,t) (+ u0) on a tensor grid of points."""
+    from . import basis
+    out = 0.0
+    for (jx, jt, s), u in zip(prob.comps, sols):
+        Pt = basis.time_basis(jt, prob.T, tq, 0)
+        if prob.d == 1:
+            Px = basis.hat_1d(jx, prob.medium.lengths[0], xqs[0])
+            out = out + s * (Pt @ u @ Px.T)
+        else:
+            Px = basis.hat_1d(jx, prob.medium.lengths[0], xqs[0])
+            Py = basis.hat_1d(jx, prob.medium.lengths[1], xqs[1])
+            n = 2 ** jx - 1
+            V = np.einsum("ti,iyx->tyx", Pt, u.reshape(-1, n, n))
+            V = np.einsum("tyx,qx->tyq", V, Px)
+            out = out + s * np.einsum("tyq,py->tpq", V, Py)
+    if u0_fn is not None:
+        if prob.d == 1:
+            out = out + u0_fn(xqs[0])[None, :]
+        else:
+            out = out + u0_fn(xqs[0][None, :], xqs[1][:, None])[None, :, :]
+    return out
+
+
+def l2_error(prob, sols, u_fn, u0_fn=None, comps=None):
+    """(||u - u_h||, ||u||) in L^2(Q_T) by Gauss quadrature on the finest mesh.
+
+    sols/comps: component solutions and their (jx, jt, sign) list (default:
+    the problem's components)."""
+    saved = prob.comps
+    if comps is not None:
+        prob.comps = comps
+    try:
+        J = prob.J
+        tq, tw = fine_quadrature(J, prob.T)
+        xs = [fine_quadrature(J, prob.medium.lengths[a]) for a in range(prob.d)]
+        uh = combined_at(prob, sols, tq, [x[0] for x in xs], u0_fn)
+    finally:
+        prob.comps = saved
+    if prob.d == 1:
+        ue = u_fn(tq[:, None], xs[0][0][None, :])
+        W = tw[:, None] * xs[0][1][None, :]
+    else:
+        ue = u_fn(tq[:, None, None], xs[0][0][None, None, :], xs[1][0][None, :, None])
+        W = tw[:, None, None] * xs[1][1][None, :, None] * xs[0][1][None, None, :]
+    return np.sqrt(np.sum(W * (ue - uh) ** 2)), np.sqrt(np.sum(W * ue ** 2))
