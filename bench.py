@@ -1,0 +1,202 @@
+"""Benchmark: combined space-time DoFs/s of the sparse-grid wave solver.
+
+Workload: d=2, Omega=(0,1)^2, L=10, c=1, T=1, manufactured
+u = sin(pi x) sin(pi y) sin(pi t) (f = pi^2 u, u0 = 0, v0 = pi sin sin),
+adjoint cotangent g ~ N(0,1) (seed 0); all synthetic, FP64, inputs resident
+in HBM before timing.
+
+A step is one pass of the whole hot path: forward (load restriction, 17
+component solves, combination) and adjoint (restriction of g, transposed
+solves, df/du0/dv0), replayed from one captured HIP graph (the batched form).
+value = N_sparse DoFs per step / seconds per step.
+
+Also reported (config): forward-only DoFs/s, the per-component plain loop,
+fwd+adj/fwd, and the per-stage times from HIP events on the launch stream.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "combined space–time DoFs/sec at d=2 L=10 (plain vs batched); fwd+adj/fwd"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--L", type=int, default=10)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(spec, data, budget_s):
+    """Time the oracle (forward: load, solve, prolongation per component) on
+    the components of the same workload, smallest first, until the budget is
+    used; single-threaded BLAS."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import Problem
+    with threadpool_limits(limits=1):
+        prob = Problem(*spec.args())
+        order = sorted(prob.comps, key=lambda c: (2 ** c[0] - 1) ** spec.d * (2 ** c[1] + 1))
+        dofs = 0
+        done = []
+        t0 = time.perf_counter()
+        U = np.zeros((spec.nt(), (spec.nx()) ** spec.d))
+        for jx, jt, s in order:
+            b = prob.load(jx, jt, data["f"], data["u0"], data["v0"])
+            u = prob.solve(jx, jt, b)
+            U += s * prob.prolong(jx, jt, u)
+            dofs += u.size
+            done.append(f"({jx},{jt})")
+            if time.perf_counter() - t0 > budget_s:
+                break
+        el = time.perf_counter() - t0
+    return {"value": dofs / el, "unit": "DoF/s", "cores": 1, "kind": "oracle",
+            "sample": (f"forward load+solve+prolongation of {len(done)} of "
+                       f"{len(prob.comps)} components {' '.join(done)} "
+                       f"({dofs} DoFs, {el:.1f} s, smallest first, 1 BLAS thread)")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    import paper_2606_09688_amd as sg
+    import workloads
+
+    dev = "cuda:0"
+    spec, data = workloads.c3(L=args.L)
+    to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    f, u0, v0, g = (to(data[k]) for k in ("f", "u0", "v0", "g"))
+    sv = sg.SparseGridWave(*spec.args())
+    U = torch.empty(sv.shape, dtype=torch.float64, device=dev)
+    df = torch.empty(sv.shape, dtype=torch.float64, device=dev)
+    du0 = torch.empty(sv.space_shape, dtype=torch.float64, device=dev)
+    dv0 = torch.empty(sv.space_shape, dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream()
+    nfull = sv.n_full
+
+    # ---- batched: forward + adjoint in one captured graph ------------------
+    with torch.cuda.stream(stream):
+        sv.capture(f, u0, v0, U, g, df, du0, dv0, stream=stream)
+        for _ in range(args.warmup):
+            sv.replay(stream=stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(args.steps):
+            sv.replay(stream=stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.steps
+
+    # ---- eager runs with stage events (forward, adjoint) --------------------
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(15)]
+    sv.set_events(ev)
+    reps = max(3, args.steps // 2)
+    stage = {k: 0.0 for k in ("fwd", "load_restrict", "solves", "combine", "adj",
+                              "adj_restrict", "adj_solves", "df_prolong")}
+    with torch.cuda.stream(stream):
+        sv.solve(f, u0, v0, out=U, stream=stream)
+        sv.adjoint(g, df, du0, dv0, stream=stream)
+    stream.synchronize()
+    for _ in range(reps):
+        with torch.cuda.stream(stream):
+            sv.solve(f, u0, v0, out=U, stream=stream)
+            sv.adjoint(g, df, du0, dv0, stream=stream)
+        stream.synchronize()
+        el = lambda a, b: ev[a].elapsed_time(ev[b]) * 1e-3
+        stage["fwd"] += el(0, 6)
+        stage["load_restrict"] += el(1, 2)
+        stage["solves"] += el(3, 4)
+        stage["combine"] += el(5, 6)
+        stage["adj"] += el(7, 14)
+        stage["adj_restrict"] += el(8, 9)
+        stage["adj_solves"] += el(10, 11)
+        stage["df_prolong"] += el(12, 13)
+    sv.set_events(None)
+    stage = {k: v / reps for k, v in stage.items()}
+
+    # ---- plain per-component loop (forward) ---------------------------------
+    Up = torch.empty_like(U)
+    with torch.cuda.stream(stream):
+        sv.solve(f, u0, v0, out=Up, plain=True, stream=stream)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(args.plain_steps):
+            sv.solve(f, u0, v0, out=Up, plain=True, stream=stream)
+    stream.synchronize()
+    t_plain = (time.perf_counter() - t0) / args.plain_steps
+    plain_diff = float((Up - U).norm() / U.norm())
+
+    # dominant fine-grid kernel: each streams 8 bytes per fine-grid value
+    kern = {"k_restrict (load of f)": stage["load_restrict"],
+            "k_prolong (combination into U)": stage["combine"],
+            "k_restrict (cotangent g)": stage["adj_restrict"],
+            "k_prolong (df, with mass stencil)": stage["df_prolong"]}
+    name = max(kern, key=kern.get)
+    bytes_alg = 8.0 * nfull
+    achieved = bytes_alg / kern[name] / 1e9
+    ns = sv.n_sparse
+    out = {
+        "metric": METRIC,
+        "value": ns / t_step,
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"d=2 Omega=(0,1)^2 L={args.L} c=1 T=1, u=sin(pi x)sin(pi y)sin(pi t), "
+                         "g~N(0,1) seed 0; step = forward + adjoint (hipGraph)"),
+            "n_sparse": ns,
+            "n_full": nfull,
+            "batched_fwd_adj_dofs_per_s": ns / t_step,
+            "eager_fwd_dofs_per_s": ns / stage["fwd"],
+            "plain_fwd_dofs_per_s": ns / t_plain,
+            "batched_fwd_over_plain_fwd_speedup": t_plain / stage["fwd"],
+            "fwd_adj_over_fwd": (stage["fwd"] + stage["adj"]) / stage["fwd"],
+            "plain_vs_fused_rel_l2": plain_diff,
+            "stage_ms": {k: v * 1e3 for k, v in stage.items()},
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": name,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, data, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+/*
+ * sgwave.h - C ABI of the MI355X space-time sparse-grid wave solver.
+ *
+ * The library computes the sparse-grid combination solution of the linear
+ * wave equation (Ferrari, Moiola, Perinati, Perugia, "A space-time
+ * sparse-grid method for the wave equation"):
+ *
+ *   problem (1):     u_tt - div(c^2 grad u) = f on Omega x (0,T), u = 0 on the
+ *                    boundary, u(0) = u0, u_t(0) = v0;
+ *   component solve: the Galerkin problem (9) on V^x_{jx} (x) V^t_{jt}
+ *                    (P1 / Q1 in space, quadratic C^1 splines with w(0) = 0 in
+ *                    time, exponentially weighted coercive form (6));
+ *   combination:     eq. (19), +1 on jx+jt = L and -1 on jx+jt = L-1
+ *                    (jx, jt >= 1), plus the lift by u0 (Sec. 2.1).
+ *
+ * Level convention: level j has 2^j uniform intervals per axis of Omega and
+ * of (0,T); the finest level of sparse level L is J = L-1 (the paper's J is
+ * L-2 with h_0 = 1/2).
+ *
+ * Data layout (all buffers FP64, contiguous, device memory, caller-owned):
+ *   fine space-time array  [nt][ny][nx]  x fastest; nt = 2^J + 1 time nodes
+ *                          t_n = n T / 2^J including t = 0 and t = T;
+ *                          nx = ny = 2^J - 1 interior nodes (ny = 1 when d = 1);
+ *                          values on the spatial boundary are implicitly 0.
+ *   fine space array       [ny][nx].
+ * Input data are read as nodal values of their piecewise-linear (P1 in time,
+ * P1/Q1 in space) interpolants on the finest grid.  The output U holds the
+ * nodal values of u^CF + u0; U[0] equals u0.
+ *
+ * Ownership: the caller owns every data buffer; the library owns the handle,
+ * its tables and its device workspace (allocated once in sg_assemble).
+ * sg_solve / sg_adjoint never allocate, never synchronise the host, and are
+ * stream ordered; one handle must not be used by two streams at once.
+ * Errors are returned as status codes; sg_last_error() gives a message for
+ * the calling thread.  No C++ exception crosses this interface.
+ */
+#ifndef SGWAVE_H
+#define SGWAVE_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sg_problem sg_problem;
+
+typedef enum {
+  SG_OK = 0,
+  SG_EINVAL = -1,   /* invalid argument (sizes, c <= 0, T <= 0, L < 2, NULL) */
+  SG_ENOMEM = -2,   /* device or host allocation failed (assemble only)      */
+  SG_EDEVICE = -3,  /* a HIP runtime call failed                             */
+  SG_ENOTSUP = -4,  /* configuration outside what this build implements     */
+  SG_ESTATE = -5    /* call not valid in the handle's current state          */
+} sg_status;
+
+/*
+ * Build the discrete operator of problem (1) for sparse level L.
+ *   d       spatial dimension, 1 or 2.
+ *   len     side lengths of Omega = (0,len[0]) [x (0,len[1])], host pointer.
+ *   ncell   number of uniform wave-speed blocks per axis, host pointer.
+ *   c_vals  c on the blocks (x fastest), ncell[0]*ncell[1] values > 0, host.
+ *           2^(L-1) must be a multiple of every ncell[i] (the finest mesh
+ *           resolves the blocks).
+ *   T       final time > 0.   L  sparse level, 2 <= L <= 16.
+ * On success *out receives a handle bound to the current HIP device; all
+ * tables are uploaded and all workspace is allocated here.
+ */
+sg_status sg_assemble(int d, const double *len, const int *ncell,
+                      const double *c_vals, double T, int L, sg_problem **out);
+
+/*
+ * Forward solve: U = u0 + sum_c s_c P_c(f, u0, v0) on the finest grid
+ * (component solves of eq. (9), combination eq. (19), lift).  f and U are
+ * fine space-time arrays, u0 and v0 fine space arrays (device pointers).
+ * This is the fused path: one streaming pass over f, batched component
+ * solves, one streaming pass writing U.  U may not alias f.
+ */
+sg_status sg_solve(sg_problem *p, const double *f, const double *u0,
+                   const double *v0, double *U, hipStream_t stream);
+
+/*
+ * The same result computed by the literal per-component loop: for each
+ * component, restrict from f, solve, and accumulate into U (2 fine-grid
+ * passes per component).  Reference point for the fused path's speedup.
+ */
+sg_status sg_solve_plain(sg_problem *p, const double *f, const double *u0,
+                         const double *v0, double *U, hipStream_t stream);
+
+/*
+ * Adjoint of the forward map F: (f,u0,v0) -> U.  g has the layout of U;
+ * df the layout of f; du0, dv0 fine space arrays.  Computes
+ * (df, du0, dv0) = F^T g (transposed combination, transposed component
+ * solves, transposed load).  Any output pointer may be NULL to skip it.
+ */
+sg_status sg_adjoint(sg_problem *p, const double *g, double *df, double *du0,
+                     double *dv0, hipStream_t stream);
+
+/*
+ * Capture sg_solve (and, if g != NULL, sg_adjoint) for fixed buffers into a
+ * HIP graph owned by the handle, replacing any earlier capture.  The stream
+ * must not be capturing already.  sg_graph_launch replays it on a stream.
+ */
+sg_status sg_graph_capture(sg_problem *p, const double *f, const double *u0,
+                           const double *v0, double *U, const double *g,
+                           double *df, double *du0, double *dv0,
+                           hipStream_t stream);
+sg_status sg_graph_launch(sg_problem *p, hipStream_t stream);
+
+/*
+ * Stage timing: when ev is not NULL, sg_solve and sg_adjoint record
+ * ev[i] (caller-created hipEvent_t, at least SG_NUM_EVENTS of them) on the
+ * call's stream at these points (not during graph capture):
+ *   0 forward begin        1 before the load restriction   2 after it
+ *   3 before the solves    4 after the solves              5 before the
+ *   combination pass       6 after it (forward end)
+ *   7 adjoint begin        8 before the cotangent restriction 9 after it
+ *  10 before the solves   11 after them   12 before the df pass 13 after it
+ *  14 adjoint end
+ * Pass ev = NULL to stop recording.
+ */
+#define SG_NUM_EVENTS 15
+sg_status sg_set_events(sg_problem *p, hipEvent_t *ev, int n);
+
+/*
+ * Sizes: nt = 2^J+1, n = 2^J-1 interior nodes per axis, n_sparse = sum of
+ * the component dimensions (the paper's N^sparse_DoFs), n_full = nt * n^d.
+ * Any output pointer may be NULL.
+ */
+sg_status sg_query(const sg_problem *p, int *nt, int *n, long long *n_sparse,
+                   long long *n_full, int *n_components);
+
+/*
+ * Component c (0 <= c < n_components): levels, sign and dimensions.  The
+ * order is the library's internal order (stable for a given L).
+ */
+sg_status sg_component_info(const sg_problem *p, int c, int *jx, int *jt,
+                            int *sign, int *n_space, int *n_time);
+
+/*
+ * Copy the coefficients of component c from the last sg_solve (stage 0: the
+ * right-hand side b_c of eq. (9); stage 1: the solution u_c) into host memory
+ * `out` of n_time * n_space doubles, time index outer.  Synchronises the
+ * device.  For tests of intermediate stages.
+ */
+sg_status sg_component_copy(sg_problem *p, int c, int stage, double *out);
+
+/*
+ * Host-only introspection of the tables the library builds (no device use).
+ * sg_host_time_level: time matrices of level b on (0,T) (Prop. 1, eq. (30)):
+ *   A, B   banded [2^b+1][5], entry (i, j) at [i][j-i+2] (high parts);
+ *   Alo, Blo low parts: A + Alo, B + Blo hold the entries to about 32 digits;
+ *   Dlo,Dhi psi_i'(t_i), psi_i'(t_{i+1}) at the level-b nodes;
+ *   g      int_0^T psi_i' e^{-t/T} dt.   Each array holds 2^b+1 rows.
+ * sg_host_taps: tap table of level b on the fine time grid of level J
+ *   (kind 0: P1 load taps, kind 1: spline evaluation taps): q0[2^J+1],
+ *   w[3*(2^J+1)]; slab n couples to time index q0[n]+k with weight w[3n+k].
+ * Any output pointer may be NULL.
+ */
+sg_status sg_host_time_level(int b, double T, double *A, double *Alo, double *B,
+                             double *Blo, double *Dlo, double *Dhi, double *g);
+sg_status sg_host_taps(int kind, int b, int J, double T, int *q0, double *w);
+
+/* Release the handle and all device memory it owns.  NULL is accepted. */
+sg_status sg_destroy(sg_problem *p);
+
+/* Message describing the last error of the calling thread ("" if none). */
+const char *sg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGWAVE_H */

@@ -18,10 +18,11 @@ Combination (eq. 19) and lift (Sec. 2.1, the solution of (1) is u + u0):
 
     U[n,m] = u0[m] + sum_c s_c sum_{i,k} u_c[i,k] psi_i(t_n) phi_k(x_m).
 
-S_c is factorised by SuperLU.  Because the time matrices become badly
-conditioned as 2^jt grows, the solve is refined iteratively with the
-residual b - S x accumulated in 80-bit long double until the correction is
-below 1e-15 of the solution (at most 10 sweeps).
+S_c is factorised by SuperLU.  The discrete solution of long time levels is
+sensitive to last-bit changes of the time-matrix entries, so the solve is
+refined iteratively against the exact system: A and B are known to ~32
+digits (hi + lo, see ``timemat.time_matrices_dd``) and the residual
+b - S x is accumulated in double-double (``ddarith``).
 
 The adjoint applies the explicit transposes of the three linear steps:
 y_c = s_c Psi^T g Phi,  z_c = S_c^{-T} y_c,
@@ -33,7 +34,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from . import levels, space, timemat
+from . import ddarith, levels, space, timemat
 
 
 class Problem:
@@ -86,7 +87,15 @@ class Problem:
         return self._get(("Phi", j, J), lambda: space.interp(j, J, self.medium))
 
     def tmat(self, jt):
-        return self._get(("T", jt), lambda: timemat.time_matrices(jt, self.T))
+        """Time load vectors g, d0 of level jt."""
+        def make():
+            g, d0 = timemat.time_vectors(jt, self.T)
+            return {"g": g, "d0": d0}
+        return self._get(("T", jt), make)
+
+    def tmat_dd(self, jt):
+        """Double-double banded A, B of level jt (hi, lo parts)."""
+        return self._get(("Tdd", jt), lambda: timemat.time_matrices_dd(jt, self.T))
 
     def wload(self, jt, J=None):
         J = self.J if J is None else J
@@ -104,12 +113,18 @@ class Problem:
         """(Phi^T K^J)[k,m] = (c^2 grad phi^J_m, grad phi^jx_k), exact by nesting."""
         return self._get(("KJc", jx), lambda: (self.phi(jx).T @ self.stiff(self.J)).tocsr())
 
+    def time_sparse(self, jt, name):
+        """High part of A or B of level jt as a sparse matrix."""
+        band = self.tmat_dd(jt)[name + "_hi"]
+        n = band.shape[0]
+        return sp.diags([band[max(0, -(k - 2)):n - max(0, k - 2), k] for k in range(5)],
+                        [k - 2 for k in range(5)], shape=(n, n), format="csr")
+
     def system(self, jx, jt):
-        """Sparse S_c = A (x) M + B (x) K (time index outer), CSR."""
+        """Sparse S_c = A (x) M + B (x) K (time index outer), CSR (high parts)."""
         def make():
-            tm = self.tmat(jt)
-            return (sp.kron(sp.csr_matrix(tm["A"]), self.mass(jx))
-                    + sp.kron(sp.csr_matrix(tm["B"]), self.stiff(jx))).tocsr()
+            return (sp.kron(self.time_sparse(jt, "A"), self.mass(jx))
+                    + sp.kron(self.time_sparse(jt, "B"), self.stiff(jx))).tocsr()
         return self._get(("S", jx, jt), make)
 
     def factor(self, jx, jt):
@@ -129,21 +144,66 @@ class Problem:
         return b
 
     def solve(self, jx, jt, b, transpose=False):
-        """u = S_c^{-1} b (or S_c^{-T} b) with long-double residual refinement."""
-        S = self.system(jx, jt)
-        if transpose:
-            S = self._get(("ST", jx, jt), lambda: S.T.tocsr())
+        """u = S_c^{-1} b (or S_c^{-T} b).  SuperLU of the high parts, then
+        refinement with the residual formed in double-double from the exact
+        time matrices until the correction is below 1e-17 of the solution."""
         lu = self.factor(jx, jt)
         trans = "T" if transpose else "N"
-        rhs = np.asarray(b, dtype=np.float64).reshape(-1)
-        x = lu.solve(rhs, trans=trans)
-        for _ in range(10):
-            r = _residual_longdouble(S, x, rhs)
-            dx = lu.solve(np.asarray(r, dtype=np.float64), trans=trans)
+        rhs = np.asarray(b, dtype=np.float64)
+        shape = rhs.shape
+        nt = 2 ** jt + 1
+        rhs = rhs.reshape(nt, -1)
+        x = lu.solve(rhs.reshape(-1), trans=trans).reshape(nt, -1)
+        for _ in range(12):
+            r = self._residual_dd(jx, jt, x, rhs, transpose)
+            dx = lu.solve(r.reshape(-1), trans=trans).reshape(nt, -1)
             x = x + dx
-            if np.linalg.norm(dx) <= 1e-15 * max(np.linalg.norm(x), 1e-300):
+            if np.abs(dx).max() <= 1e-17 * max(np.abs(x).max(), 1e-300):
                 break
-        return x.reshape(np.shape(b))
+        return x.reshape(shape)
+
+    def _padded(self, jx, which):
+        """Rows of M or K as (cols, vals) padded to the longest row."""
+        def make():
+            A = (self.mass(jx) if which == "M" else self.stiff(jx)).tocsr()
+            nnz = np.diff(A.indptr)
+            width = int(nnz.max())
+            cols = np.zeros((A.shape[0], width), dtype=np.int64)
+            vals = np.zeros((A.shape[0], width))
+            for k in range(A.shape[0]):
+                a, b = A.indptr[k], A.indptr[k + 1]
+                cols[k, :b - a] = A.indices[a:b]
+                vals[k, :b - a] = A.data[a:b]
+            return cols, vals
+        return self._get(("pad", jx, which), make)
+
+    def _residual_dd(self, jx, jt, X, Bv, transpose):
+        """b - S x with S = A (x) M + B (x) K (or its transpose), every product
+        and sum in double-double, A and B taken as hi + lo."""
+        dd = self.tmat_dd(jt)
+        nt = X.shape[0]
+        rh, rl = Bv.copy(), np.zeros_like(Bv)
+        for tname, sname in (("A", "M"), ("B", "K")):
+            cols, vals = self._padded(jx, sname)   # M, K are symmetric
+            Yh, Yl = ddarith.zeros(X.shape)
+            for slot in range(cols.shape[1]):
+                ph, pl = ddarith.two_prod(X[:, cols[:, slot]], vals[None, :, slot])
+                Yh, Yl = ddarith.add(Yh, Yl, ph, pl)
+            Th, Tl = dd[tname + "_hi"], dd[tname + "_lo"]
+            for k in range(5):
+                off = k - 2
+                i = np.arange(max(0, -off), min(nt, nt - off))
+                if transpose:
+                    # (A^T)[i, i+off] = A[i+off, i] = band[i+off, 2-off]
+                    ah = Th[i + off, 2 - off][:, None]
+                    al = Tl[i + off, 2 - off][:, None]
+                else:
+                    ah = Th[i, k][:, None]
+                    al = Tl[i, k][:, None]
+                ph, pl = ddarith.mul(ah, al, Yh[i + off], Yl[i + off])
+                sh, sl = ddarith.add(rh[i], rl[i], -ph, -pl)
+                rh[i], rl[i] = sh, sl
+        return rh + rl
 
     def prolong(self, jx, jt, u):
         """Nodal values on the finest grid of sum_{i,k} u[i,k] psi_i phi_k."""
@@ -188,16 +248,6 @@ class Problem:
         U = np.tile(np.asarray(u0, dtype=np.float64).reshape(1, self.ns_fine),
                     (self.nt_fine, 1))
         return U + self.prolong(j, j, u)
-
-
-def _residual_longdouble(S, x, b):
-    """b - S x with every product and sum in 80-bit long double."""
-    S = S.tocsr()
-    if np.any(S.indptr[:-1] == S.indptr[1:]):
-        raise ValueError("system matrix has an empty row")
-    prod = S.data.astype(np.longdouble) * x.astype(np.longdouble)[S.indices]
-    rows = np.add.reduceat(prod, S.indptr[:-1])  # segmented row sums
-    return b.astype(np.longdouble) - rows
 
 
 # ----------------------------------------------------------------------

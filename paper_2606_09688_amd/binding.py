@@ -1,0 +1,244 @@
+"""ctypes binding of libsgwave.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts torch
+tensors to device pointers and the current HIP stream to a stream handle.
+There is no CPU fallback: if the shared library is missing or the tensors are
+not FP64 device tensors, the calls raise.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgwave.so")
+
+SG_OK = 0
+_STATUS = {0: "SG_OK", -1: "SG_EINVAL", -2: "SG_ENOMEM", -3: "SG_EDEVICE",
+           -4: "SG_ENOTSUP", -5: "SG_ESTATE"}
+
+_lib = None
+
+_c_dp = ctypes.POINTER(ctypes.c_double)
+_c_ip = ctypes.POINTER(ctypes.c_int)
+_c_llp = ctypes.POINTER(ctypes.c_longlong)
+
+# name -> (restype, argtypes); mirrors include/sgwave.h
+SIGNATURES = {
+    "sg_assemble": (ctypes.c_int, [ctypes.c_int, _c_dp, _c_ip, _c_dp, ctypes.c_double,
+                                   ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "sg_solve": (ctypes.c_int, [ctypes.c_void_p] * 6),
+    "sg_solve_plain": (ctypes.c_int, [ctypes.c_void_p] * 6),
+    "sg_adjoint": (ctypes.c_int, [ctypes.c_void_p] * 6),
+    "sg_graph_capture": (ctypes.c_int, [ctypes.c_void_p] * 10),
+    "sg_graph_launch": (ctypes.c_int, [ctypes.c_void_p] * 2),
+    "sg_query": (ctypes.c_int, [ctypes.c_void_p, _c_ip, _c_ip, _c_llp, _c_llp, _c_ip]),
+    "sg_component_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_ip, _c_ip,
+                                         _c_ip, _c_ip, _c_ip]),
+    "sg_component_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_dp]),
+    "sg_host_time_level": (ctypes.c_int, [ctypes.c_int, ctypes.c_double] + [_c_dp] * 7),
+    "sg_host_taps": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_double, _c_ip, _c_dp]),
+    "sg_set_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                     ctypes.c_int]),
+    "sg_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sg_last_error": (ctypes.c_char_p, []),
+}
+
+
+class SGError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libsgwave.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_2606_09688_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status, what):
+    if status != SG_OK:
+        msg = lib().sg_last_error().decode(errors="replace")
+        raise SGError(f"{what} failed with {_STATUS.get(status, status)}: {msg}")
+
+
+def _ptr(t, shape, name, allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA/HIP tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def host_time_level(b, T):
+    """Dict of A, Alo, B, Blo (banded), Dlo, Dhi, g of level b (host introspection)."""
+    import numpy as np
+    nq = 2 ** b + 1
+    out = {k: np.zeros((nq, 5)) for k in ("A", "Alo", "B", "Blo")}
+    out.update({k: np.zeros(nq) for k in ("Dlo", "Dhi", "g")})
+    dp = lambda a: a.ctypes.data_as(_c_dp)
+    check(lib().sg_host_time_level(b, float(T), *[dp(out[k]) for k in
+                                                 ("A", "Alo", "B", "Blo", "Dlo", "Dhi", "g")]),
+          "sg_host_time_level")
+    return out
+
+
+def host_taps(kind, b, J, T):
+    """(q0, w) tap table (kind 0: P1 load taps, 1: spline taps)."""
+    import numpy as np
+    n = 2 ** J + 1
+    q0 = np.zeros(n, dtype=np.int32)
+    w = np.zeros((n, 3))
+    check(lib().sg_host_taps(kind, b, J, float(T), q0.ctypes.data_as(_c_ip),
+                             w.ctypes.data_as(_c_dp)), "sg_host_taps")
+    return q0, w
+
+
+class SparseGridWave:
+    """One assembled problem (sg_assemble) bound to the current HIP device.
+
+    d: 1 or 2; lengths: side lengths; ncell: wave-speed blocks per axis;
+    c_vals: block speeds (x fastest); T: final time; L: sparse level.
+    Arrays: f, U, g, df have shape (nt, n) / (nt, n, n); u0, v0 shape (n,) / (n, n).
+    """
+
+    def __init__(self, d, lengths, ncell, c_vals, T, L):
+        import numpy as np
+        L_ = lib()
+        self.d = int(d)
+        ln = (ctypes.c_double * d)(*[float(v) for v in lengths])
+        nc = (ctypes.c_int * d)(*[int(v) for v in ncell])
+        cv = np.ascontiguousarray(np.asarray(c_vals, dtype=np.float64).reshape(-1))
+        h = ctypes.c_void_p()
+        check(L_.sg_assemble(d, ln, nc, cv.ctypes.data_as(_c_dp), float(T), int(L),
+                             ctypes.byref(h)), "sg_assemble")
+        self._h = h
+        nt, n, nc_ = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        ns, nf = ctypes.c_longlong(), ctypes.c_longlong()
+        check(L_.sg_query(h, ctypes.byref(nt), ctypes.byref(n), ctypes.byref(ns),
+                          ctypes.byref(nf), ctypes.byref(nc_)), "sg_query")
+        self.nt, self.n = nt.value, n.value
+        self.n_sparse, self.n_full = ns.value, nf.value
+        self.n_components = nc_.value
+        self.space_shape = (self.n,) * self.d
+        self.shape = (self.nt,) + self.space_shape
+        self.T = float(T)
+        self.L = int(L)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.sg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- components -----------------------------------------------------
+    def components(self):
+        out = []
+        for c in range(self.n_components):
+            v = [ctypes.c_int() for _ in range(5)]
+            check(lib().sg_component_info(self._h, c, *[ctypes.byref(x) for x in v]),
+                  "sg_component_info")
+            out.append(tuple(x.value for x in v))  # (jx, jt, sign, n_space, n_time)
+        return out
+
+    def component(self, c, stage):
+        """Host copy of component c after the last solve (0: RHS, 1: solution)."""
+        import numpy as np
+        jx, jt, s, nsp, nq = self.components()[c]
+        out = np.zeros((nq, nsp))
+        check(lib().sg_component_copy(self._h, c, stage, out.ctypes.data_as(_c_dp)),
+              "sg_component_copy")
+        return out
+
+    # ---- solves ---------------------------------------------------------
+    def solve(self, f, u0, v0, out=None, plain=False, stream=None):
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=f.device)
+        fn = lib().sg_solve_plain if plain else lib().sg_solve
+        check(fn(self._h, _ptr(f, self.shape, "f"), _ptr(u0, self.space_shape, "u0"),
+                 _ptr(v0, self.space_shape, "v0"), _ptr(out, self.shape, "U"),
+                 _stream(stream)), "sg_solve")
+        return out
+
+    def adjoint(self, g, df=None, du0=None, dv0=None, want=(True, True, True), stream=None):
+        dev = g.device
+        if df is None and want[0]:
+            df = torch.empty(self.shape, dtype=torch.float64, device=dev)
+        if du0 is None and want[1]:
+            du0 = torch.empty(self.space_shape, dtype=torch.float64, device=dev)
+        if dv0 is None and want[2]:
+            dv0 = torch.empty(self.space_shape, dtype=torch.float64, device=dev)
+        check(lib().sg_adjoint(self._h, _ptr(g, self.shape, "g"),
+                               _ptr(df, self.shape, "df", True),
+                               _ptr(du0, self.space_shape, "du0", True),
+                               _ptr(dv0, self.space_shape, "dv0", True), _stream(stream)),
+              "sg_adjoint")
+        return df, du0, dv0
+
+    def capture(self, f, u0, v0, U, g=None, df=None, du0=None, dv0=None, stream=None):
+        """Capture forward (+ adjoint when g is given) into a HIP graph."""
+        s = stream if stream is not None else torch.cuda.current_stream()
+        check(lib().sg_graph_capture(
+            self._h, _ptr(f, self.shape, "f"), _ptr(u0, self.space_shape, "u0"),
+            _ptr(v0, self.space_shape, "v0"), _ptr(U, self.shape, "U"),
+            _ptr(g, self.shape, "g", True), _ptr(df, self.shape, "df", True),
+            _ptr(du0, self.space_shape, "du0", True),
+            _ptr(dv0, self.space_shape, "dv0", True), _stream(s)), "sg_graph_capture")
+
+    def set_events(self, events):
+        """Record the SG_NUM_EVENTS stage events (torch.cuda.Event list) or None."""
+        if events is None:
+            check(lib().sg_set_events(self._h, None, 0), "sg_set_events")
+            return
+        arr = (ctypes.c_void_p * len(events))(*[e.cuda_event for e in events])
+        check(lib().sg_set_events(self._h, arr, len(events)), "sg_set_events")
+
+    def replay(self, stream=None):
+        check(lib().sg_graph_launch(self._h, _stream(stream)), "sg_graph_launch")
+
+
+class SGWaveFunction(torch.autograd.Function):
+    """U = F(f, u0, v0); backward applies the hand-written adjoint F^T."""
+
+    @staticmethod
+    def forward(ctx, solver, f, u0, v0):
+        ctx.solver = solver
+        return solver.solve(f.contiguous(), u0.contiguous(), v0.contiguous())
+
+    @staticmethod
+    def backward(ctx, gU):
+        df, du0, dv0 = ctx.solver.adjoint(gU.contiguous())
+        return None, df, du0, dv0
+
+
+def sgwave(solver, f, u0, v0):
+    """Differentiable forward map (autograd through the adjoint)."""
+    return SGWaveFunction.apply(solver, f, u0, v0)

@@ -1,0 +1,936 @@
+// C ABI of the sparse-grid wave solver: plan construction (sg_assemble) and
+// the stream-ordered forward / adjoint pipelines.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sgwave.h"
+#include "kernels.hpp"
+#include "tables.hpp"
+
+using namespace sg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sg_status fail(sg_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define HIPCHK(expr)                                                             \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return fail(SG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Comp {
+  int a, b, sign;
+  int nsp, nq;
+  long long off;  // offset into the component buffers
+};
+
+// one restriction or prolongation pass: geometry + channel table + work lists
+struct Pass {
+  Geometry geo;
+  Channel *d_ch = nullptr;        // [2J]
+  std::vector<Channel> h_ch;
+  WorkItem *d_red = nullptr;      // in-tile levels (reduce)
+  int n_red = 0;
+  long long tot_red = 0;
+  WorkItem *d_crs = nullptr;      // coarse levels
+  int n_crs = 0;
+  long long tot_crs = 0;
+};
+
+struct GemmList {
+  GemmDesc *d = nullptr;
+  int n = 0, tiles = 0;
+};
+
+struct SolveList {
+  SolveDesc *d = nullptr;
+  int n = 0;
+  long long threads = 0;
+};
+
+struct CompList {
+  CompDesc *d = nullptr;
+  int n = 0;
+  long long total = 0;
+};
+
+}  // namespace
+
+struct sg_problem {
+  int device = 0;
+  int d = 1;
+  double len[2] = {1, 1};
+  int ncell[2] = {1, 1};
+  std::vector<double> c;
+  double T = 1;
+  int L = 2, J = 1, N = 2;
+  bool const_c = true;
+  double c2 = 1;
+  std::vector<Comp> comps;
+  long long nsparse = 0;
+  long long nsp_fine = 0;
+
+  std::vector<void *> allocs;
+  template <class T>
+  T *dalloc(size_t n) {
+    void *p = nullptr;
+    if (n == 0) n = 1;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) return nullptr;
+    allocs.push_back(p);
+    return static_cast<T *>(p);
+  }
+
+  // tables
+  KernelTables *d_kt = nullptr;
+  ModeTables *d_mt = nullptr;
+  std::vector<double *> dst;      // per spatial level (const c)
+  double *d_ce = nullptr;         // fine-element c^2
+  // buffers (N^sparse each)
+  double *bufZ = nullptr, *bufB = nullptr, *bufT = nullptr, *bufS = nullptr,
+         *bufU = nullptr, *bufW = nullptr, *scratch = nullptr;
+  // level fields [3][nsp_a] per level (row 0 meaningful)
+  std::vector<double *> mv_lv, ku_lv, fv_lv, fu_lv;
+  double *gsum = nullptr;          // [3][nsp_J]
+  double *fine2 = nullptr;         // [2][nsp_fine]
+  double *part = nullptr;          // partial blocks
+  double *cpart = nullptr;         // per-slab coarse partials
+  double *S0 = nullptr;            // coarse level-A0 arrays
+  double *Cpro = nullptr;          // prolongation coarse array
+  // passes
+  Pass load, prol, adjr, adjp, fieldr, fieldp;
+  std::vector<Pass> plain_load, plain_prol;
+  // descriptor lists
+  GemmList gx, gy, giy, gix;       // fused (all components)
+  std::vector<GemmList> pgx, pgy, pgiy, pgix;
+  SolveList sfwd, sadj;
+  std::vector<SolveList> psfwd;
+  CompList cload, cadj;
+  std::vector<CompList> pcload;
+  LevelDesc *d_lev = nullptr;
+  int nlev = 0;
+  long long lev_total = 0;
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int refine_nq = 33;
+  // optional stage events (not recorded while capturing)
+  std::vector<hipEvent_t> ev;
+  bool capturing = false;
+};
+
+namespace {
+
+template <class T>
+sg_status upload(sg_problem *p, const std::vector<T> &h, T **out) {
+  T *d = p->dalloc<T>(h.size());
+  if (!d) return fail(SG_ENOMEM, "hipMalloc failed");
+  if (!h.empty()) HIPCHK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  *out = d;
+  return SG_OK;
+}
+
+Geometry make_geometry(int d, int J, int ntf, int chunk_target_wg) {
+  Geometry g{};
+  g.d = d;
+  g.J = J;
+  g.N = 1 << J;
+  g.nxf = g.N - 1;
+  g.ntf = ntf;
+  g.TS = d == 2 ? 32 : 256;
+  g.lts = d == 2 ? 5 : 8;
+  g.ntile = g.N >= g.TS ? g.N / g.TS : 1;
+  g.R = std::min(g.lts, J - 1);
+  g.A0 = J - g.R;
+  const int tb = d == 2 ? 2 : 8;
+  const int ntileD = d == 2 ? g.ntile * g.ntile : g.ntile;
+  int nch = std::max(1, chunk_target_wg / ntileD);
+  int chunk = (ntf + nch - 1) / nch;
+  chunk = ((chunk + tb - 1) / tb) * tb;
+  if (chunk < tb) chunk = tb;
+  g.chunk = chunk;
+  g.nchunk = (ntf + chunk - 1) / chunk;
+  return g;
+}
+
+int level_nodes(const Geometry &g, int r) {  // in-tile nodes per axis, mode 0
+  return r == 0 ? g.TS : (g.TS >> r) + 1;
+}
+
+// Build the channel table of a pass.  `spec(a,k)` returns (active, nq, taps
+// pointer pair, data pointer, scale).
+struct ChanSpec {
+  int active = 0;
+  int nq = 3;
+  const int *q0 = nullptr;
+  const double *w = nullptr;
+  const std::vector<int> *hq0 = nullptr;  // host copy to size partial blocks
+  double *data = nullptr;
+  double scale = 1.0;
+};
+
+template <class F>
+sg_status build_pass(sg_problem *p, Pass &P, const Geometry &geo, F spec,
+                     long long *part_need) {
+  P.geo = geo;
+  const int J = geo.J;
+  P.h_ch.assign(2 * J, Channel{});
+  long long off = 0;
+  std::vector<WorkItem> red, crs;
+  long long tred = 0, tcrs = 0;
+  const int ntileD = geo.d == 2 ? geo.ntile * geo.ntile : geo.ntile;
+  for (int a = 1; a <= J; ++a) {
+    for (int k = 0; k < 2; ++k) {
+      ChanSpec cs = spec(a, k);
+      Channel &C = P.h_ch[(a - 1) * 2 + k];
+      C.active = cs.active;
+      C.a = a;
+      C.nq = cs.nq;
+      C.q0 = cs.q0;
+      C.w = cs.w;
+      C.data = cs.data;
+      C.scale = cs.scale;
+      C.qb = 0;
+      C.part_off = 0;
+      if (!cs.active) continue;
+      const int na = (1 << a) - 1;
+      const long long nspa = geo.d == 2 ? (long long)na * na : na;
+      const long long cntw = (long long)cs.nq * nspa;
+      const int r = J - a;
+      if (a >= geo.A0) {
+        // partial block capacity: max over chunks of touched time nodes
+        const std::vector<int> &q0 = *cs.hq0;
+        int qb = 0;
+        for (int c = 0; c < geo.nchunk; ++c) {
+          const int n0 = c * geo.chunk, n1 = std::min(n0 + geo.chunk, geo.ntf);
+          qb = std::max(qb, q0[n1 - 1] + 2 - q0[n0] + 1);
+        }
+        C.qb = qb;
+        C.part_off = off;
+        const int nr = level_nodes(geo, r);
+        const long long sz = geo.d == 2 ? (long long)nr * nr : nr;
+        off += (long long)geo.nchunk * ntileD * qb * sz;
+        red.push_back(WorkItem{(a - 1) * 2 + k, 0, tred, cntw});
+        tred += cntw;
+      } else {
+        crs.push_back(WorkItem{(a - 1) * 2 + k, 0, tcrs, cntw});
+        tcrs += cntw;
+      }
+    }
+  }
+  *part_need = std::max(*part_need, off);
+  sg_status st;
+  if ((st = upload(p, P.h_ch, &P.d_ch)) != SG_OK) return st;
+  P.n_red = (int)red.size();
+  P.tot_red = tred;
+  if ((st = upload(p, red, &P.d_red)) != SG_OK) return st;
+  P.n_crs = (int)crs.size();
+  P.tot_crs = tcrs;
+  if ((st = upload(p, crs, &P.d_crs)) != SG_OK) return st;
+  return SG_OK;
+}
+
+void mark(sg_problem *p, int id, hipStream_t s) {
+  if (!p->capturing && id < (int)p->ev.size()) (void)hipEventRecord(p->ev[id], s);
+}
+
+sg_status run_restrict(sg_problem *p, const Pass &P, const double *X, int stencil,
+                       hipStream_t s, int ev_begin = -1) {
+  const Geometry &g = P.geo;
+  RestrictArgs ra{};
+  ra.g = g;
+  ra.X = X;
+  ra.stencil = stencil;
+  const double hx = p->len[0] / p->N, hy = (p->d == 2 ? p->len[1] : 1.0) / p->N;
+  ra.sx = hx / 6.0;
+  ra.sy = hy / 6.0;
+  ra.ch = P.d_ch;
+  ra.part = p->part;
+  ra.coarse = g.A0 > 1 ? p->cpart : nullptr;
+  if (ev_begin >= 0) mark(p, ev_begin, s);
+  HIPCHK(launch_restrict(ra, s));
+  if (ev_begin >= 0) mark(p, ev_begin + 1, s);
+  if (P.n_red) HIPCHK(launch_reduce(g, P.d_ch, p->part, P.d_red, P.n_red, P.tot_red, s));
+  if (g.A0 > 1 && P.n_crs) {
+    HIPCHK(launch_coarse_assemble(g, p->cpart, p->S0, s));
+    HIPCHK(launch_coarse_restrict(g, P.d_ch, p->S0, P.d_crs, P.n_crs, P.tot_crs, s));
+  }
+  return SG_OK;
+}
+
+sg_status run_prolong(sg_problem *p, const Pass &P, const double *base, double *out,
+                      int accumulate, int stencil, hipStream_t s, int ev_begin = -1) {
+  const Geometry &g = P.geo;
+  ProlongArgs pa{};
+  pa.g = g;
+  pa.ch = P.d_ch;
+  pa.coarse = nullptr;
+  if (g.A0 > 1 && P.n_crs) {
+    HIPCHK(launch_prolong_coarse(g, P.d_ch, p->Cpro, stencil, s));
+    pa.coarse = p->Cpro;
+  }
+  pa.base = base;
+  pa.out = out;
+  pa.accumulate = accumulate;
+  pa.stencil = stencil;
+  const double hx = p->len[0] / p->N, hy = (p->d == 2 ? p->len[1] : 1.0) / p->N;
+  pa.sx = hx / 6.0;
+  pa.sy = hy / 6.0;
+  if (ev_begin >= 0) mark(p, ev_begin, s);
+  HIPCHK(launch_prolong(pa, s));
+  if (ev_begin >= 0) mark(p, ev_begin + 1, s);
+  return SG_OK;
+}
+
+// DST descriptor lists for a set of components: x-transform src->dst
+sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList &gx,
+                           GemmList &gy, GemmList &giy, GemmList &gix) {
+  std::vector<GemmDesc> vx, vy, viy, vix;
+  int tx = 0, ty = 0, tiy = 0, tix = 0;
+  for (int ci : cset) {
+    const Comp &C = p->comps[ci];
+    const int na = (1 << C.a) - 1;
+    const double *Q = p->dst[C.a];
+    const int ny = p->d == 2 ? na : 1;
+    auto tiles = [](int M, int N) { return ((M + 63) / 64) * ((N + 63) / 64); };
+    // forward x: T = B * Q   ([nq*ny x na] x [na x na])
+    {
+      GemmDesc g{};
+      g.A = p->bufB + C.off; g.B = Q; g.C = p->bufT + C.off;
+      g.M = C.nq * ny; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
+      g.batch = 1; g.tm = (g.M + 63) / 64; g.tn = (g.N + 63) / 64; g.tile0 = tx;
+      tx += tiles(g.M, g.N);
+      vx.push_back(g);
+    }
+    // inverse x: U = T * Q
+    {
+      GemmDesc g{};
+      g.A = p->bufT + C.off; g.B = Q; g.C = p->bufU + C.off;
+      g.M = C.nq * ny; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
+      g.batch = 1; g.tm = (g.M + 63) / 64; g.tn = (g.N + 63) / 64; g.tile0 = tix;
+      tix += tiles(g.M, g.N);
+      vix.push_back(g);
+    }
+    if (p->d == 2) {
+      const long long slab = (long long)na * na;
+      // forward y: S_i = Q * T_i
+      GemmDesc g{};
+      g.A = Q; g.B = p->bufT + C.off; g.C = p->bufS + C.off;
+      g.M = na; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
+      g.sA = 0; g.sB = slab; g.sC = slab;
+      g.batch = C.nq; g.tm = (na + 63) / 64; g.tn = (na + 63) / 64; g.tile0 = ty;
+      ty += C.nq * tiles(na, na);
+      vy.push_back(g);
+      // inverse y: T_i = Q * S_i
+      GemmDesc h = g;
+      h.B = p->bufS + C.off; h.C = p->bufT + C.off; h.tile0 = tiy;
+      tiy += C.nq * tiles(na, na);
+      viy.push_back(h);
+    }
+  }
+  sg_status st;
+  if ((st = upload(p, vx, &gx.d)) != SG_OK) return st;
+  gx.n = (int)vx.size(); gx.tiles = tx;
+  if ((st = upload(p, vix, &gix.d)) != SG_OK) return st;
+  gix.n = (int)vix.size(); gix.tiles = tix;
+  if ((st = upload(p, vy, &gy.d)) != SG_OK) return st;
+  gy.n = (int)vy.size(); gy.tiles = ty;
+  if ((st = upload(p, viy, &giy.d)) != SG_OK) return st;
+  giy.n = (int)viy.size(); giy.tiles = tiy;
+  return SG_OK;
+}
+
+sg_status build_solve_list(sg_problem *p, const std::vector<int> &cset, int transpose,
+                           SolveList &L) {
+  std::vector<SolveDesc> v;
+  long long th = 0;
+  for (int ci : cset) {
+    const Comp &C = p->comps[ci];
+    SolveDesc sd{};
+    sd.rhs = (p->d == 2 ? p->bufS : p->bufT) + C.off;
+    sd.scratch = p->scratch + 7 * C.off;
+    sd.nq = C.nq;
+    sd.nmodes = C.nsp;
+    sd.b = C.b;
+    sd.a = C.a;
+    // refinement sweeps against the double-double time matrices: the double
+    // LU is a preconditioner whose quality drops as the time level grows
+    sd.refine = C.nq < p->refine_nq ? 0 : (C.nq <= 513 ? 2 : (C.nq <= 2049 ? 3 : 5));
+    sd.transpose = transpose;
+    sd.c2 = p->c2;
+    sd.thread0 = th;
+    th += C.nsp;
+    v.push_back(sd);
+  }
+  sg_status st;
+  if ((st = upload(p, v, &L.d)) != SG_OK) return st;
+  L.n = (int)v.size();
+  L.threads = th;
+  return SG_OK;
+}
+
+sg_status run_solves(sg_problem *p, const GemmList &gx, const GemmList &gy,
+                     const SolveList &sl, const GemmList &giy, const GemmList &gix,
+                     hipStream_t s) {
+  HIPCHK(launch_gemm(gx.d, gx.n, gx.tiles, s));
+  if (p->d == 2) HIPCHK(launch_gemm(gy.d, gy.n, gy.tiles, s));
+  HIPCHK(launch_time_solve(sl.d, sl.n, sl.threads, p->d_kt, p->d_mt, p->d, s));
+  if (p->d == 2) HIPCHK(launch_gemm(giy.d, giy.n, giy.tiles, s));
+  HIPCHK(launch_gemm(gix.d, gix.n, gix.tiles, s));
+  return SG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sg_last_error(void) { return g_last_error.c_str(); }
+
+sg_status sg_destroy(sg_problem *p) {
+  if (!p) return SG_OK;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->device);
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  for (void *a : p->allocs) (void)hipFree(a);
+  (void)hipSetDevice(cur);
+  delete p;
+  return SG_OK;
+}
+
+sg_status sg_assemble(int d, const double *len, const int *ncell, const double *c_vals,
+                      double T, int L, sg_problem **out) {
+  g_last_error.clear();
+  if (!out) return fail(SG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (d != 1 && d != 2) return fail(SG_EINVAL, "d must be 1 or 2");
+  if (!len || !ncell || !c_vals) return fail(SG_EINVAL, "NULL argument");
+  if (!(T > 0) || !std::isfinite(T)) return fail(SG_EINVAL, "T must be > 0");
+  if (L < 2 || L > 16) return fail(SG_EINVAL, "L must be in [2,16]");
+  const int J = L - 1, N = 1 << J;
+  int ncl = 1;
+  for (int i = 0; i < d; ++i) {
+    if (!(len[i] > 0) || !std::isfinite(len[i])) return fail(SG_EINVAL, "lengths must be > 0");
+    if (ncell[i] < 1) return fail(SG_EINVAL, "ncell must be >= 1");
+    if (N % ncell[i] != 0)
+      return fail(SG_EINVAL, "2^(L-1) must be a multiple of ncell (finest mesh resolves c)");
+    ncl *= ncell[i];
+  }
+  for (int i = 0; i < ncl; ++i)
+    if (!(c_vals[i] > 0) || !std::isfinite(c_vals[i]))
+      return fail(SG_EINVAL, "wave speed must be positive and finite");
+
+  sg_problem *p = new (std::nothrow) sg_problem();
+  if (!p) return fail(SG_ENOMEM, "host allocation failed");
+  auto bail = [&](sg_status st) {
+    std::string msg = g_last_error;
+    sg_destroy(p);
+    g_last_error = msg;
+    return st;
+  };
+  if (hipGetDevice(&p->device) != hipSuccess) return bail(fail(SG_EDEVICE, "no HIP device"));
+  p->d = d;
+  p->len[0] = len[0];
+  p->len[1] = d == 2 ? len[1] : 1.0;
+  p->ncell[0] = ncell[0];
+  p->ncell[1] = d == 2 ? ncell[1] : 1;
+  p->c.assign(c_vals, c_vals + ncl);
+  p->T = T;
+  p->L = L;
+  p->J = J;
+  p->N = N;
+  p->const_c = std::all_of(p->c.begin(), p->c.end(), [&](double v) { return v == p->c[0]; });
+  p->c2 = p->c[0] * p->c[0];
+  if (!p->const_c)
+    return bail(fail(SG_ENOTSUP, "variable wave speed is not implemented in this build"));
+  if (const char *e = getenv("SG_REFINE_NQ")) p->refine_nq = atoi(e);
+
+  // components: +1 on jx + jt = L (jx = 1..L-1), -1 on jx + jt = L-1 (jx = 1..L-2)
+  long long off = 0;
+  auto add = [&](int a, int b, int sgn) {
+    Comp c{};
+    c.a = a;
+    c.b = b;
+    c.sign = sgn;
+    const int na = (1 << a) - 1;
+    c.nsp = d == 2 ? na * na : na;
+    c.nq = (1 << b) + 1;
+    c.off = off;
+    off += (long long)c.nsp * c.nq;
+    p->comps.push_back(c);
+  };
+  for (int a = 1; a <= J; ++a) add(a, L - a, +1);
+  for (int a = 1; a <= J - 1; ++a) add(a, L - 1 - a, -1);
+  p->nsparse = off;
+  p->nsp_fine = d == 2 ? (long long)(N - 1) * (N - 1) : (N - 1);
+  const int ntf = N + 1;
+  auto comp_index = [&](int a, int k) -> int {  // k=0 plus, 1 minus
+    if (k == 0) return a - 1;
+    if (a > J - 1) return -1;
+    return J + a - 1;
+  };
+
+  sg_status st;
+  // ---- time levels, tap tables ------------------------------------------
+  KernelTables kt{};
+  std::map<int, std::pair<const int *, const double *>> p1tab, sptab;
+  std::map<int, std::vector<int>> p1q0, spq0;
+  for (int b = 1; b <= J; ++b) {
+    TimeLevel tl = time_level(b, T);
+    double *dA, *dB, *dAl, *dBl, *dlo, *dhi, *dg;
+    if ((st = upload(p, tl.A, &dA)) || (st = upload(p, tl.B, &dB)) ||
+        (st = upload(p, tl.Alo, &dAl)) || (st = upload(p, tl.Blo, &dBl)) ||
+        (st = upload(p, tl.Dlo, &dlo)) || (st = upload(p, tl.Dhi, &dhi)) ||
+        (st = upload(p, tl.g, &dg)))
+      return bail(st);
+    kt.A[b] = dA; kt.B[b] = dB; kt.Alo[b] = dAl; kt.Blo[b] = dBl;
+    kt.Dlo[b] = dlo; kt.Dhi[b] = dhi; kt.g[b] = dg;
+    Taps t1 = p1_taps(b, J, T), t2 = spline_taps(b, J, T);
+    int *q1, *q2;
+    double *w1, *w2;
+    if ((st = upload(p, t1.q0, &q1)) || (st = upload(p, t1.w, &w1)) ||
+        (st = upload(p, t2.q0, &q2)) || (st = upload(p, t2.w, &w2)))
+      return bail(st);
+    p1tab[b] = {q1, w1};
+    sptab[b] = {q2, w2};
+    p1q0[b] = t1.q0;
+    spq0[b] = t2.q0;
+  }
+  Taps ts = sum_taps(J);
+  int *qsum;
+  double *wsum;
+  if ((st = upload(p, ts.q0, &qsum)) || (st = upload(p, ts.w, &wsum))) return bail(st);
+  // field taps on a 2-slab geometry: channel k picks slab k into node 0
+  std::vector<int> fq0 = {0, 0};
+  std::vector<double> fw0 = {1, 0, 0, 0, 0, 0}, fw1 = {0, 0, 0, 1, 0, 0};
+  int *dfq0;
+  double *dfw0, *dfw1;
+  if ((st = upload(p, fq0, &dfq0)) || (st = upload(p, fw0, &dfw0)) ||
+      (st = upload(p, fw1, &dfw1)))
+    return bail(st);
+  if ((st = upload(p, std::vector<KernelTables>{kt}, &p->d_kt))) return bail(st);
+
+  // ---- spatial tables ---------------------------------------------------
+  ModeTables mt{};
+  p->dst.assign(J + 1, nullptr);
+  for (int a = 1; a <= J; ++a) {
+    std::vector<double> m, k;
+    p1_eigen(a, p->len[0], m, k);
+    double *dm, *dk;
+    if ((st = upload(p, m, &dm)) || (st = upload(p, k, &dk))) return bail(st);
+    mt.mx[a] = dm; mt.kx[a] = dk;
+    if (d == 2) {
+      p1_eigen(a, p->len[1], m, k);
+      if ((st = upload(p, m, &dm)) || (st = upload(p, k, &dk))) return bail(st);
+      mt.my[a] = dm; mt.ky[a] = dk;
+    }
+    if ((st = upload(p, dst_matrix(a), &p->dst[a]))) return bail(st);
+  }
+  if ((st = upload(p, std::vector<ModeTables>{mt}, &p->d_mt))) return bail(st);
+  // per fine element c^2 (the finest mesh resolves the blocks)
+  {
+    std::vector<double> ce;
+    if (d == 1) {
+      ce.resize(N);
+      for (int e = 0; e < N; ++e) {
+        const double v = p->c[(long long)e * ncell[0] / N];
+        ce[e] = v * v;
+      }
+    } else {
+      ce.resize((size_t)N * N);
+      for (int ey = 0; ey < N; ++ey)
+        for (int ex = 0; ex < N; ++ex) {
+          const int bx = (int)((long long)ex * ncell[0] / N), by = (int)((long long)ey * ncell[1] / N);
+          const double v = p->c[(size_t)by * ncell[0] + bx];
+          ce[(size_t)ey * N + ex] = v * v;
+        }
+    }
+    if ((st = upload(p, ce, &p->d_ce))) return bail(st);
+  }
+
+  // ---- buffers ------------------------------------------------------------
+  const long long ns = p->nsparse;
+  if (!(p->bufZ = p->dalloc<double>(ns)) || !(p->bufB = p->dalloc<double>(ns)) ||
+      !(p->bufT = p->dalloc<double>(ns)) || !(p->bufS = p->dalloc<double>(ns)) ||
+      !(p->bufU = p->dalloc<double>(ns)) || !(p->bufW = p->dalloc<double>(ns)) ||
+      !(p->scratch = p->dalloc<double>(7 * ns)))
+    return bail(fail(SG_ENOMEM, "hipMalloc of component buffers failed"));
+  p->mv_lv.assign(J + 1, nullptr);
+  p->ku_lv.assign(J + 1, nullptr);
+  p->fv_lv.assign(J + 1, nullptr);
+  p->fu_lv.assign(J + 1, nullptr);
+  for (int a = 1; a <= J; ++a) {
+    const long long na = (1 << a) - 1, nspa = d == 2 ? na * na : na;
+    if (!(p->mv_lv[a] = p->dalloc<double>(3 * nspa)) ||
+        !(p->ku_lv[a] = p->dalloc<double>(3 * nspa)) ||
+        !(p->fv_lv[a] = p->dalloc<double>(3 * nspa)) ||
+        !(p->fu_lv[a] = p->dalloc<double>(3 * nspa)))
+      return bail(fail(SG_ENOMEM, "hipMalloc of level fields failed"));
+    HIPCHK(hipMemset(p->fv_lv[a], 0, 3 * nspa * sizeof(double)));
+    HIPCHK(hipMemset(p->fu_lv[a], 0, 3 * nspa * sizeof(double)));
+  }
+  if (!(p->gsum = p->dalloc<double>(3 * p->nsp_fine)) ||
+      !(p->fine2 = p->dalloc<double>(2 * p->nsp_fine)))
+    return bail(fail(SG_ENOMEM, "hipMalloc of fine fields failed"));
+
+  // ---- passes ---------------------------------------------------------------
+  const Geometry geo = make_geometry(d, J, ntf, 1024);
+  const Geometry geof = make_geometry(d, J, 2, 1);
+  long long part_need = 0;
+  auto chan_comp = [&](int a, int k, bool spline, double *buf, bool signed_, int only) {
+    ChanSpec cs;
+    const int ci = comp_index(a, k);
+    if (ci < 0) return cs;
+    if (only >= 0 && ci != only) return cs;
+    const Comp &C = p->comps[ci];
+    cs.active = 1;
+    cs.nq = C.nq;
+    auto &tab = spline ? sptab[C.b] : p1tab[C.b];
+    cs.q0 = tab.first;
+    cs.w = tab.second;
+    cs.hq0 = spline ? &spq0[C.b] : &p1q0[C.b];
+    cs.data = buf + C.off;
+    cs.scale = signed_ ? (double)C.sign : 1.0;
+    return cs;
+  };
+  if ((st = build_pass(p, p->load, geo,
+                       [&](int a, int k) { return chan_comp(a, k, false, p->bufZ, false, -1); },
+                       &part_need)))
+    return bail(st);
+  if ((st = build_pass(p, p->prol, geo,
+                       [&](int a, int k) { return chan_comp(a, k, true, p->bufU, true, -1); },
+                       &part_need)))
+    return bail(st);
+  std::vector<int> sum_q0(ts.q0);
+  if ((st = build_pass(p, p->adjr, geo,
+                       [&](int a, int k) {
+                         if (a == J && k == 1) {
+                           ChanSpec cs;
+                           cs.active = 1;
+                           cs.nq = 3;
+                           cs.q0 = qsum;
+                           cs.w = wsum;
+                           cs.hq0 = &sum_q0;
+                           cs.data = p->gsum;
+                           return cs;
+                         }
+                         return chan_comp(a, k, true, p->bufZ, true, -1);
+                       },
+                       &part_need)))
+    return bail(st);
+  if ((st = build_pass(p, p->adjp, geo,
+                       [&](int a, int k) { return chan_comp(a, k, false, p->bufZ, false, -1); },
+                       &part_need)))
+    return bail(st);
+  auto field = [&](std::vector<double *> &v0, std::vector<double *> &v1) {
+    return [&](int a, int k) {
+      ChanSpec cs;
+      cs.active = 1;
+      cs.nq = 3;
+      cs.q0 = dfq0;
+      cs.w = k == 0 ? dfw0 : dfw1;
+      cs.hq0 = &fq0;
+      cs.data = k == 0 ? v0[a] : v1[a];
+      return cs;
+    };
+  };
+  if ((st = build_pass(p, p->fieldr, geof, field(p->mv_lv, p->ku_lv), &part_need))) return bail(st);
+  if ((st = build_pass(p, p->fieldp, geof, field(p->fv_lv, p->fu_lv), &part_need))) return bail(st);
+  const int ncomp = (int)p->comps.size();
+  p->plain_load.resize(ncomp);
+  p->plain_prol.resize(ncomp);
+  for (int ci = 0; ci < ncomp; ++ci) {
+    if ((st = build_pass(p, p->plain_load[ci], geo,
+                         [&](int a, int k) { return chan_comp(a, k, false, p->bufZ, false, ci); },
+                         &part_need)))
+      return bail(st);
+    if ((st = build_pass(p, p->plain_prol[ci], geo,
+                         [&](int a, int k) { return chan_comp(a, k, true, p->bufU, true, ci); },
+                         &part_need)))
+      return bail(st);
+  }
+  if (!(p->part = p->dalloc<double>(part_need)))
+    return bail(fail(SG_ENOMEM, "hipMalloc of partial blocks failed"));
+  {
+    const int ntileD = d == 2 ? geo.ntile * geo.ntile : geo.ntile;
+    const int nR = level_nodes(geo, geo.R);
+    const long long szR = d == 2 ? (long long)nR * nR : nR;
+    const long long na0 = (1 << geo.A0) - 1, nsp0 = d == 2 ? na0 * na0 : na0;
+    const long long need = std::max((long long)ntileD * ntf * szR, 1LL);
+    if (!(p->cpart = p->dalloc<double>(need)) || !(p->S0 = p->dalloc<double>(ntf * nsp0)) ||
+        !(p->Cpro = p->dalloc<double>(ntf * nsp0)))
+      return bail(fail(SG_ENOMEM, "hipMalloc of coarse buffers failed"));
+  }
+
+  // ---- descriptor lists -------------------------------------------------------
+  std::vector<int> all(ncomp);
+  for (int i = 0; i < ncomp; ++i) all[i] = i;
+  if ((st = build_gemm_lists(p, all, p->gx, p->gy, p->giy, p->gix))) return bail(st);
+  if ((st = build_solve_list(p, all, 0, p->sfwd))) return bail(st);
+  if ((st = build_solve_list(p, all, 1, p->sadj))) return bail(st);
+  p->pgx.resize(ncomp); p->pgy.resize(ncomp); p->pgiy.resize(ncomp); p->pgix.resize(ncomp);
+  p->psfwd.resize(ncomp);
+  p->pcload.resize(ncomp);
+  for (int ci = 0; ci < ncomp; ++ci) {
+    std::vector<int> one = {ci};
+    if ((st = build_gemm_lists(p, one, p->pgx[ci], p->pgy[ci], p->pgiy[ci], p->pgix[ci])))
+      return bail(st);
+    if ((st = build_solve_list(p, one, 0, p->psfwd[ci]))) return bail(st);
+  }
+  // post-processing lists
+  {
+    std::vector<CompDesc> vl, va;
+    long long tl = 0;
+    for (int ci = 0; ci < ncomp; ++ci) {
+      const Comp &C = p->comps[ci];
+      CompDesc cd{};
+      cd.data = p->bufB + C.off;
+      cd.z = p->bufZ + C.off;
+      cd.mv = p->mv_lv[C.a];
+      cd.ku = p->ku_lv[C.a];
+      cd.a = C.a; cd.b = C.b; cd.nq = C.nq; cd.nsp = C.nsp; cd.sign = C.sign;
+      cd.start = tl;
+      tl += (long long)C.nq * C.nsp;
+      vl.push_back(cd);
+      CompDesc ca = cd;
+      ca.data = p->bufZ + C.off;
+      ca.z = p->bufW + C.off;
+      ca.mv = nullptr;
+      ca.ku = nullptr;
+      va.push_back(ca);
+      CompDesc one = cd;
+      one.start = 0;
+      if ((st = upload(p, std::vector<CompDesc>{one}, &p->pcload[ci].d))) return bail(st);
+      p->pcload[ci].n = 1;
+      p->pcload[ci].total = (long long)C.nq * C.nsp;
+    }
+    if ((st = upload(p, vl, &p->cload.d))) return bail(st);
+    p->cload.n = ncomp;
+    p->cload.total = tl;
+    if ((st = upload(p, va, &p->cadj.d))) return bail(st);
+    p->cadj.n = ncomp;
+    p->cadj.total = tl;
+    std::vector<LevelDesc> lv;
+    long long tt = 0;
+    for (int a = 1; a <= J; ++a) {
+      LevelDesc L{};
+      L.a = a;
+      const int na = (1 << a) - 1;
+      L.nsp = d == 2 ? na * na : na;
+      L.c0 = comp_index(a, 0);
+      L.c1 = comp_index(a, 1);
+      L.fv = p->fv_lv[a];
+      L.fu = p->fu_lv[a];
+      L.start = tt;
+      tt += L.nsp;
+      lv.push_back(L);
+    }
+    if ((st = upload(p, lv, &p->d_lev))) return bail(st);
+    p->nlev = J;
+    p->lev_total = tt;
+  }
+  HIPCHK(hipDeviceSynchronize());
+  *out = p;
+  return SG_OK;
+}
+
+sg_status sg_query(const sg_problem *p, int *nt, int *n, long long *n_sparse,
+                   long long *n_full, int *n_components) {
+  if (!p) return fail(SG_EINVAL, "NULL handle");
+  if (nt) *nt = p->N + 1;
+  if (n) *n = p->N - 1;
+  if (n_sparse) *n_sparse = p->nsparse;
+  if (n_full) *n_full = (long long)(p->N + 1) * p->nsp_fine;
+  if (n_components) *n_components = (int)p->comps.size();
+  return SG_OK;
+}
+
+sg_status sg_component_info(const sg_problem *p, int c, int *jx, int *jt, int *sign,
+                            int *n_space, int *n_time) {
+  if (!p) return fail(SG_EINVAL, "NULL handle");
+  if (c < 0 || c >= (int)p->comps.size()) return fail(SG_EINVAL, "component index out of range");
+  const Comp &C = p->comps[c];
+  if (jx) *jx = C.a;
+  if (jt) *jt = C.b;
+  if (sign) *sign = C.sign;
+  if (n_space) *n_space = C.nsp;
+  if (n_time) *n_time = C.nq;
+  return SG_OK;
+}
+
+sg_status sg_component_copy(sg_problem *p, int c, int stage, double *out) {
+  if (!p || !out) return fail(SG_EINVAL, "NULL argument");
+  if (c < 0 || c >= (int)p->comps.size()) return fail(SG_EINVAL, "component index out of range");
+  if (stage != 0 && stage != 1) return fail(SG_EINVAL, "stage must be 0 or 1");
+  const Comp &C = p->comps[c];
+  HIPCHK(hipDeviceSynchronize());
+  const double *src = (stage == 0 ? p->bufB : p->bufU) + C.off;
+  HIPCHK(hipMemcpy(out, src, (size_t)C.nq * C.nsp * sizeof(double), hipMemcpyDeviceToHost));
+  return SG_OK;
+}
+
+static sg_status forward_fields(sg_problem *p, const double *u0, const double *v0,
+                                hipStream_t s) {
+  const double hx = p->len[0] / p->N, hy = p->len[1] / p->N;
+  // fine M v0 and K u0, then their restriction to every level (q = 0 row)
+  HIPCHK(launch_fine_stencils(p->d, p->N, p->d_ce, hx, hy, v0, u0, p->fine2,
+                              p->fine2 + p->nsp_fine, nullptr, 0, s));
+  return run_restrict(p, p->fieldr, p->fine2, 0, s);
+}
+
+sg_status sg_solve(sg_problem *p, const double *f, const double *u0, const double *v0,
+                   double *U, hipStream_t s) {
+  if (!p) return fail(SG_EINVAL, "NULL handle");
+  if (!f || !u0 || !v0 || !U) return fail(SG_EINVAL, "NULL data pointer");
+  if (U == f) return fail(SG_EINVAL, "U must not alias f");
+  sg_status st;
+  mark(p, 0, s);
+  if ((st = forward_fields(p, u0, v0, s))) return st;
+  if ((st = run_restrict(p, p->load, f, 1, s, 1))) return st;
+  HIPCHK(launch_post_load(p->cload.d, p->cload.n, p->cload.total, p->d_kt, s));
+  mark(p, 3, s);
+  if ((st = run_solves(p, p->gx, p->gy, p->sfwd, p->giy, p->gix, s))) return st;
+  mark(p, 4, s);
+  return run_prolong(p, p->prol, u0, U, 0, 0, s, 5);
+}
+
+sg_status sg_solve_plain(sg_problem *p, const double *f, const double *u0,
+                         const double *v0, double *U, hipStream_t s) {
+  if (!p) return fail(SG_EINVAL, "NULL handle");
+  if (!f || !u0 || !v0 || !U) return fail(SG_EINVAL, "NULL data pointer");
+  if (U == f) return fail(SG_EINVAL, "U must not alias f");
+  sg_status st;
+  HIPCHK(launch_broadcast(U, u0, p->N + 1, p->nsp_fine, s));
+  if ((st = forward_fields(p, u0, v0, s))) return st;
+  for (size_t ci = 0; ci < p->comps.size(); ++ci) {
+    if ((st = run_restrict(p, p->plain_load[ci], f, 1, s))) return st;
+    HIPCHK(launch_post_load(p->pcload[ci].d, 1, p->pcload[ci].total, p->d_kt, s));
+    if ((st = run_solves(p, p->pgx[ci], p->pgy[ci], p->psfwd[ci], p->pgiy[ci], p->pgix[ci], s)))
+      return st;
+    if ((st = run_prolong(p, p->plain_prol[ci], nullptr, U, 1, 0, s))) return st;
+  }
+  return SG_OK;
+}
+
+sg_status sg_adjoint(sg_problem *p, const double *g, double *df, double *du0, double *dv0,
+                     hipStream_t s) {
+  if (!p) return fail(SG_EINVAL, "NULL handle");
+  if (!g) return fail(SG_EINVAL, "NULL cotangent");
+  sg_status st;
+  mark(p, 7, s);
+  // y_c = s_c Psi^T g Phi (+ time sum of g for du0)
+  if ((st = run_restrict(p, p->adjr, g, 0, s, 8))) return st;
+  // z_c = S_c^{-T} y_c : transforms read bufB, so stage y_c there
+  HIPCHK(hipMemcpyAsync(p->bufB, p->bufZ, p->nsparse * sizeof(double),
+                        hipMemcpyDeviceToDevice, s));
+  mark(p, 10, s);
+  HIPCHK(launch_gemm(p->gx.d, p->gx.n, p->gx.tiles, s));
+  if (p->d == 2) HIPCHK(launch_gemm(p->gy.d, p->gy.n, p->gy.tiles, s));
+  HIPCHK(launch_time_solve(p->sadj.d, p->sadj.n, p->sadj.threads, p->d_kt, p->d_mt, p->d, s));
+  if (p->d == 2) HIPCHK(launch_gemm(p->giy.d, p->giy.n, p->giy.tiles, s));
+  HIPCHK(launch_gemm(p->gix.d, p->gix.n, p->gix.tiles, s));
+  mark(p, 11, s);
+  // the inverse x-transform wrote bufU; move z_c to bufW
+  HIPCHK(hipMemcpyAsync(p->bufW, p->bufU, p->nsparse * sizeof(double),
+                        hipMemcpyDeviceToDevice, s));
+  // zeta_c = D^T z_c, level fields for du0 / dv0
+  HIPCHK(launch_post_adjoint(p->cadj.d, p->cadj.n, p->cadj.total, p->d_kt, s));
+  if (df) {
+    if ((st = run_prolong(p, p->adjp, nullptr, df, 0, 1, s, 12))) return st;
+  }
+  if (du0 || dv0) {
+    HIPCHK(launch_adjoint_fields(p->d_lev, p->nlev, p->lev_total, p->cadj.d, p->d_kt, s));
+    if ((st = run_prolong(p, p->fieldp, nullptr, p->fine2, 0, 0, s))) return st;
+    const double hx = p->len[0] / p->N, hy = p->len[1] / p->N;
+    HIPCHK(launch_fine_stencils(p->d, p->N, p->d_ce, hx, hy, p->fine2, p->fine2 + p->nsp_fine,
+                                dv0, du0, p->gsum, 1, s));
+  }
+  mark(p, 14, s);
+  return SG_OK;
+}
+
+sg_status sg_set_events(sg_problem *p, hipEvent_t *ev, int n) {
+  if (!p) return fail(SG_EINVAL, "NULL handle");
+  p->ev.clear();
+  if (ev == nullptr) return SG_OK;
+  if (n < SG_NUM_EVENTS) return fail(SG_EINVAL, "need SG_NUM_EVENTS events");
+  p->ev.assign(ev, ev + n);
+  return SG_OK;
+}
+
+sg_status sg_host_time_level(int b, double T, double *A, double *Alo, double *B,
+                             double *Blo, double *Dlo, double *Dhi, double *g) {
+  if (b < 1 || b > 15 || !(T > 0)) return fail(SG_EINVAL, "need 1 <= b <= 15 and T > 0");
+  const TimeLevel tl = time_level(b, T);
+  const size_t n = tl.nq;
+  if (A) std::memcpy(A, tl.A.data(), 5 * n * sizeof(double));
+  if (B) std::memcpy(B, tl.B.data(), 5 * n * sizeof(double));
+  if (Alo) std::memcpy(Alo, tl.Alo.data(), 5 * n * sizeof(double));
+  if (Blo) std::memcpy(Blo, tl.Blo.data(), 5 * n * sizeof(double));
+  if (Dlo) std::memcpy(Dlo, tl.Dlo.data(), n * sizeof(double));
+  if (Dhi) std::memcpy(Dhi, tl.Dhi.data(), n * sizeof(double));
+  if (g) std::memcpy(g, tl.g.data(), n * sizeof(double));
+  return SG_OK;
+}
+
+sg_status sg_host_taps(int kind, int b, int J, double T, int *q0, double *w) {
+  if (kind < 0 || kind > 1 || b < 1 || b > J || J > 15 || !(T > 0))
+    return fail(SG_EINVAL, "need kind in {0,1}, 1 <= b <= J <= 15, T > 0");
+  const Taps t = kind == 0 ? p1_taps(b, J, T) : spline_taps(b, J, T);
+  if (q0) std::memcpy(q0, t.q0.data(), t.q0.size() * sizeof(int));
+  if (w) std::memcpy(w, t.w.data(), t.w.size() * sizeof(double));
+  return SG_OK;
+}
+
+sg_status sg_graph_capture(sg_problem *p, const double *f, const double *u0,
+                           const double *v0, double *U, const double *g, double *df,
+                           double *du0, double *dv0, hipStream_t s) {
+  if (!p) return fail(SG_EINVAL, "NULL handle");
+  if (s == nullptr) return fail(SG_ESTATE, "graph capture needs a non-default stream");
+  if (p->gexec) {
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+  }
+  if (p->graph) {
+    (void)hipGraphDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  p->capturing = true;
+  sg_status st = sg_solve(p, f, u0, v0, U, s);
+  if (st == SG_OK && g != nullptr) st = sg_adjoint(p, g, df, du0, dv0, s);
+  p->capturing = false;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &graph);
+  if (st != SG_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return fail(SG_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  p->graph = graph;
+  HIPCHK(hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0));
+  return SG_OK;
+}
+
+sg_status sg_graph_launch(sg_problem *p, hipStream_t s) {
+  if (!p) return fail(SG_EINVAL, "NULL handle");
+  if (!p->gexec) return fail(SG_ESTATE, "no captured graph");
+  HIPCHK(hipGraphLaunch(p->gexec, s));
+  return SG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Kernel argument structures and launch wrappers (host side declarations).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "plan.hpp"
+
+namespace sg {
+
+// ---- fine-grid streaming restriction ------------------------------------
+// Z_c[q][K] = sum_n sum_m w_c(n,q) phi^a_K(x_m) (S X_n)[m] for every active
+// channel c, S = identity or the fine mass matrix (stencil = 1).
+struct RestrictArgs {
+  Geometry g;
+  const double *X;       // [ntf][nxf^d]
+  int stencil;           // 0 identity, 1 mass
+  double sx, sy;         // h_x/6, h_y/6 of the finest mesh
+  const Channel *ch;     // [2*J]
+  double *part;          // partial blocks of the in-tile levels
+  double *coarse;        // per-slab partials at level A0 (if A0 > 1)
+};
+
+// ---- fine-grid streaming prolongation ------------------------------------
+// out[n][m] (+)= base[m] + S( sum_c scale_c sum_q w_c(n,q) (Phi_a Y_c[q])(x_m) )
+struct ProlongArgs {
+  Geometry g;
+  const Channel *ch;     // [2*J]
+  const double *coarse;  // C[n][(2^A0-1)^d] (if A0 > 1)
+  const double *base;    // [nxf^d] or null
+  double *out;           // [ntf][nxf^d]
+  int accumulate;        // 1: add to existing out
+  int stencil;           // 0 none, 1 mass
+  double sx, sy;
+};
+
+struct WorkItem {        // flattened per-channel work (reduce / coarse kernels)
+  int ch;                // channel index
+  int pad;
+  long long start;       // first global element
+  long long count;
+};
+
+struct GemmDesc {
+  const double *A;
+  const double *B;
+  double *C;
+  int M, N, K;
+  int lda, ldb, ldc;
+  long long sA, sB, sC;
+  int batch, tm, tn;
+  int tile0;
+};
+
+struct SolveDesc {
+  double *rhs;           // [nq][nmodes], overwritten with the solution
+  double *scratch;       // 6 * nq * nmodes doubles
+  int nq, nmodes;
+  int b, a;              // time level, spatial level
+  int refine;            // refinement sweeps with a double-double residual
+  int transpose;         // solve with the transposed time matrices
+  double c2;             // wave speed squared (constant-speed path)
+  long long thread0;     // first global thread
+};
+
+struct ModeTables {      // 1-D P1 eigenvalues per level and axis (unit c)
+  const double *mx[kMaxLevels + 1];
+  const double *kx[kMaxLevels + 1];
+  const double *my[kMaxLevels + 1];
+  const double *ky[kMaxLevels + 1];
+};
+
+struct CompDesc {        // one component for the small post-processing kernels
+  double *data;          // output [nq][nsp]: load b_c, or adjoint zeta_c
+  const double *z;       // input [nq][nsp]: restricted data Z_c, or adjoint z_c
+  const double *mv;      // level-a field Phi^T M v0 (load only)
+  const double *ku;      // level-a field Phi^T K u0 (load only)
+  int a, b, nq, nsp;
+  int sign;
+  int pad;
+  long long start;       // first global element of this component's work
+};
+
+struct LevelDesc {       // adjoint fields of one spatial level
+  int a, nsp;
+  int c0, c1;            // component indices at this level (-1 if none)
+  double *fv;            // sum_c psi_0'(0) z_c[0]
+  double *fu;            // sum_c sum_i g_c[i] z_c[i]
+  long long start;
+};
+
+// launch wrappers (return hipError_t of the launch)
+hipError_t launch_restrict(const RestrictArgs &a, hipStream_t s);
+hipError_t launch_reduce(const Geometry &g, const Channel *ch, const double *part,
+                         const WorkItem *items, int nitems, long long total,
+                         hipStream_t s);
+hipError_t launch_coarse_assemble(const Geometry &g, const double *coarse_part,
+                                  double *S0, hipStream_t s);
+hipError_t launch_coarse_restrict(const Geometry &g, const Channel *ch,
+                                  const double *S0, const WorkItem *items,
+                                  int nitems, long long total, hipStream_t s);
+hipError_t launch_prolong_coarse(const Geometry &g, const Channel *ch,
+                                 double *C, int mode, hipStream_t s);
+hipError_t launch_prolong(const ProlongArgs &a, hipStream_t s);
+hipError_t launch_fine_stencils(int d, int N, const double *ce, double hx,
+                                double hy, const double *v_in, const double *u_in,
+                                double *mv_out, double *ku_out,
+                                const double *gsum, int mode, hipStream_t s);
+hipError_t launch_post_load(const CompDesc *cd, int ncomp, long long total,
+                            const KernelTables *kt, hipStream_t s);
+hipError_t launch_post_adjoint(const CompDesc *cd, int ncomp, long long total,
+                               const KernelTables *kt, hipStream_t s);
+hipError_t launch_adjoint_fields(const LevelDesc *ld, int nlev, long long total,
+                                 const CompDesc *cd, const KernelTables *kt,
+                                 hipStream_t s);
+hipError_t launch_gemm(const GemmDesc *descs, int ndesc, int total_tiles,
+                       hipStream_t s);
+hipError_t launch_time_solve(const SolveDesc *sd, int nsd, long long total,
+                             const KernelTables *kt, const ModeTables *mt, int d,
+                             hipStream_t s);
+hipError_t launch_fill(double *p, long long n, double v, hipStream_t s);
+hipError_t launch_broadcast(double *out, const double *base, int nt, long long nsp,
+                            hipStream_t s);
+
+}  // namespace sg

@@ -1,0 +1,292 @@
+// Host-side tables of the discrete operator.  See tables.hpp.
+//
+// Time space (paper Sec. 2.2 and Rem. 1, p_t = 2 with C^1 continuity):
+// clamped uniform knots tau = (0,0,0,h,...,(N-1)h,T,T,T), N = 2^b, basis
+// B_0..B_{N+1}; B_0 is the only function nonzero at t = 0 and is dropped
+// (w(0) = 0), leaving psi_i = B_{i+1}, i = 0..N.
+//
+// Accuracy.  Every evaluation happens in the local coordinate s in [0,1] of
+// an element with knots measured in units of h from the element start (small
+// integers), so no cancellation t - tau occurs.  On element e the three
+// nonzero B-splines are exact quadratics in s; with t = T (e+s)/N the weight
+// is e^{-t/T} = e^{-e/N} e^{-s/N}, and every integral is a combination of the
+// moments I_k = int_0^1 s^k e^{-s/N} ds, evaluated by their series in
+// double-double.  The time matrices A_b, B_b are kept as double-double
+// (hi + lo): the discrete solution of long time levels is sensitive to
+// last-bit perturbations of their entries, and the solver's refinement uses
+// the exact entries.  Everything else is rounded once to double.
+#include "tables.hpp"
+
+#include <cmath>
+#include <stdexcept>
+
+#include "dd.hpp"
+
+namespace sg {
+
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    long double z = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) /
+                         (n + 0.5L));
+    long double dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        long double pk = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1);
+      long double dz = p1 / dp;
+      z -= dz;
+      if (fabsl(dz) < 1e-19L) break;
+    }
+    x[i] = (double)z;
+    w[i] = (double)(2 / ((1 - z * z) * dp * dp));
+  }
+}
+
+// knot tau_k of the clamped uniform knot vector with N intervals, in units of h
+static int ref_knot(int N, int k) {
+  if (k <= 2) return 0;
+  if (k >= N + 2) return N;
+  return k - 2;
+}
+
+// Values / derivatives (in units of 1/h, 1/h^2) of B_e, B_{e+1}, B_{e+2} at
+// the local coordinate s of element e, knots relative to the element start.
+static void spline_ref(int N, int e, double s, double v[3], double d1[3], double d2[3]) {
+  const int sp = e + 2;  // knot span
+  const double tm1 = ref_knot(N, sp - 1) - e, t0 = ref_knot(N, sp) - e,
+               t1 = ref_knot(N, sp + 1) - e, t2 = ref_knot(N, sp + 2) - e;
+  const double dl = t1 - t0, da = t1 - tm1, db = t2 - t0;
+  const double n0 = (t1 - s) / dl, n1 = (s - t0) / dl;
+  v[0] = (t1 - s) / da * n0;
+  v[1] = (s - tm1) / da * n0 + (t2 - s) / db * n1;
+  v[2] = (s - t0) / db * n1;
+  d1[0] = -2.0 * n0 / da;
+  d1[1] = 2.0 * (n0 / da - n1 / db);
+  d1[2] = 2.0 * n1 / db;
+  d2[0] = 2.0 / (dl * da);
+  d2[1] = -2.0 / dl * (1.0 / da + 1.0 / db);
+  d2[2] = 2.0 / (dl * db);
+}
+
+// Exact quadratic coefficients c[f][k] (B_{e+f}(s) = sum_k c[f][k] s^k).
+static void local_poly(int N, int e, double c[3][3]) {
+  double v0[3], v5[3], v1[3], d1[3], d2[3];
+  spline_ref(N, e, 0.0, v0, d1, d2);
+  spline_ref(N, e, 0.5, v5, d1, d2);
+  spline_ref(N, e, 1.0, v1, d1, d2);
+  for (int f = 0; f < 3; ++f) {
+    c[f][0] = v0[f];
+    c[f][2] = 2.0 * (v1[f] - 2.0 * v5[f] + v0[f]);
+    c[f][1] = v1[f] - v0[f] - c[f][2];
+  }
+}
+
+void spline_local(int b, double T, int e, double t, double v[3], double d1[3],
+                  double d2[3]) {
+  const int N = 1 << b;
+  const double h = T / N;
+  spline_ref(N, e, t / h - e, v, d1, d2);
+  for (int f = 0; f < 3; ++f) {
+    d1[f] /= h;
+    d2[f] /= h * h;
+  }
+}
+
+TimeLevel time_level(int b, double T) {
+  TimeLevel L;
+  const int N = 1 << b;
+  L.b = b;
+  L.nq = N + 1;
+  const ddv lam(1.0 / N);
+  ddv I[5];
+  for (int k = 0; k < 5; ++k) I[k] = moment(k, lam);
+  const ddv E1 = exp_neg(lam);
+  std::vector<ddv> Ar((size_t)L.nq * 5), Br((size_t)L.nq * 5), gr(L.nq);
+  ddv Ee(1.0);  // e^{-e/N}
+  for (int e = 0; e < N; ++e) {
+    double c[3][3];
+    local_poly(N, e, c);
+    for (int fi = 0; fi < 3; ++fi) {
+      const int i = e + fi - 1;  // B_{e+fi} = psi_{e+fi-1}
+      if (i < 0) continue;
+      const double di0 = c[fi][1], di1 = 2.0 * c[fi][2];  // B' = di0 + di1 s
+      const ddv gi = ddv(di0) * I[0] + ddv(di1) * I[1];
+      gr[i] += Ee * gi;
+      for (int fj = 0; fj < 3; ++fj) {
+        const int j = e + fj - 1;
+        if (j < 0) continue;
+        const double dd2 = 2.0 * c[fj][2];  // B''
+        const ddv a = ddv(dd2) * gi;
+        ddv bb(0.0);
+        for (int k = 0; k < 3; ++k)
+          bb += ddv(c[fj][k]) * (ddv(di0) * I[k] + ddv(di1) * I[k + 1]);
+        Ar[(size_t)i * 5 + (j - i + 2)] += Ee * a;
+        Br[(size_t)i * 5 + (j - i + 2)] += Ee * bb;
+      }
+    }
+    Ee = Ee * E1;
+  }
+  // penalty psi_j'(0) psi_i'(0): only psi_0 = B_1 has a slope at 0 (2/h)
+  Ar[2] += ddv(4.0);
+  const ddv NT = ddv((double)N) / ddv(T);
+  const ddv sc = NT * NT;  // A scales as (N/T)^2; B and g do not depend on T
+  L.A.assign((size_t)L.nq * 5, 0.0);
+  L.Alo.assign((size_t)L.nq * 5, 0.0);
+  L.B.assign((size_t)L.nq * 5, 0.0);
+  L.Blo.assign((size_t)L.nq * 5, 0.0);
+  for (size_t k = 0; k < Ar.size(); ++k) {
+    const ddv a = sc * Ar[k];
+    L.A[k] = a.hi;
+    L.Alo[k] = a.lo;
+    L.B[k] = Br[k].hi;
+    L.Blo[k] = Br[k].lo;
+  }
+  L.g.resize(L.nq);
+  for (int i = 0; i < L.nq; ++i) L.g[i] = gr[i].value();
+  const double nt = NT.value();
+  L.d0 = 2.0 * nt;
+  // psi_i'(t_i) and psi_i'(t_{i+1}) from the local slopes at element ends
+  L.Dlo.assign(L.nq, 0.0);
+  L.Dhi.assign(L.nq, 0.0);
+  double v[3], d1[3], d2[3];
+  for (int i = 0; i <= N; ++i) {
+    for (int side = 0; side < 2; ++side) {
+      const int q = i + side;
+      if (q > N) continue;
+      const int e = q < N ? q : N - 1;
+      spline_ref(N, e, q < N ? 0.0 : 1.0, v, d1, d2);
+      const int f = (i + 1) - e;
+      const double val = (f >= 0 && f <= 2) ? d1[f] * nt : 0.0;
+      (side == 0 ? L.Dlo : L.Dhi)[i] = val;
+    }
+  }
+  return L;
+}
+
+static void normalise_taps(int nq, int n, int qmin, const double *vals, int nv,
+                           Taps &tp) {
+  int q0 = qmin;
+  if (q0 > nq - 3) q0 = nq - 3;
+  if (q0 < 0) q0 = 0;
+  tp.q0[n] = q0;
+  for (int k = 0; k < 3; ++k) tp.w[3 * (size_t)n + k] = 0.0;
+  for (int k = 0; k < nv; ++k) {
+    const int slot = qmin + k - q0;
+    if (vals[k] == 0.0) continue;
+    if (slot < 0 || slot > 2) throw std::runtime_error("tap outside window");
+    tp.w[3 * (size_t)n + slot] = vals[k];
+  }
+}
+
+Taps p1_taps(int b, int J, double T) {
+  const int N = 1 << J, nq = (1 << b) + 1, s = 1 << (J - b);
+  // fine weighted P1 mass on element n: (T/N) e^{-n/N} int phi_a phi_b e^{-s/N}
+  const ddv lam(1.0 / N);
+  const ddv I0 = moment(0, lam), I1 = moment(1, lam), I2 = moment(2, lam);
+  const ddv m00 = I0 - ddv(2.0) * I1 + I2, m01 = I1 - I2, m11 = I2;
+  const ddv E1 = exp_neg(lam), hT = ddv(T) / ddv((double)N);
+  std::vector<ddv> md(N + 1), mo(N);
+  ddv Ee(1.0);
+  for (int e = 0; e < N; ++e) {
+    const ddv f = hT * Ee;
+    md[e] += f * m00;
+    md[e + 1] += f * m11;
+    mo[e] = f * m01;
+    Ee = Ee * E1;
+  }
+  auto lam_q = [&](int q, int n) {  // P1 hat of level-b node q at fine node n
+    const int dist = n > q * s ? n - q * s : q * s - n;
+    return dist >= s ? 0.0 : 1.0 - (double)dist / s;
+  };
+  Taps tp;
+  tp.q0.assign(N + 1, 0);
+  tp.w.assign(3 * (size_t)(N + 1), 0.0);
+  for (int n = 0; n <= N; ++n) {
+    double vals[8] = {0};
+    int qmin = -1, nv = 0;
+    const int qa = (n - 1 - s) / s - 1, qz = (n + 1 + s) / s + 1;
+    for (int q = qa < 0 ? 0 : qa; q <= qz && q < nq; ++q) {
+      ddv acc = ddv(lam_q(q, n)) * md[n];
+      if (n > 0) acc += ddv(lam_q(q, n - 1)) * mo[n - 1];
+      if (n < N) acc += ddv(lam_q(q, n + 1)) * mo[n];
+      if (acc.hi != 0.0) {
+        if (qmin < 0) qmin = q;
+        vals[q - qmin] = acc.value();
+        nv = q - qmin + 1;
+      }
+    }
+    if (nv > 3) throw std::runtime_error("P1 taps wider than 3");
+    normalise_taps(nq, n, qmin, vals, nv, tp);
+  }
+  return tp;
+}
+
+Taps spline_taps(int b, int J, double T) {
+  (void)T;
+  const int N = 1 << J, nb = 1 << b, s = 1 << (J - b);
+  Taps tp;
+  tp.q0.assign(N + 1, 0);
+  tp.w.assign(3 * (size_t)(N + 1), 0.0);
+  double v[3], d1[3], d2[3];
+  for (int n = 0; n <= N; ++n) {
+    int e = n / s;
+    if (e > nb - 1) e = nb - 1;
+    spline_ref(nb, e, (double)(n - e * s) / s, v, d1, d2);
+    // B_{e+k} is psi_{e+k-1}; B_0 (k=0 when e=0) is not in the space
+    double vals[3];
+    int qmin = e - 1, nv = 3;
+    for (int k = 0; k < 3; ++k) vals[k] = v[k];
+    if (e == 0) {
+      vals[0] = v[1];
+      vals[1] = v[2];
+      qmin = 0;
+      nv = 2;
+    }
+    normalise_taps(nb + 1, n, qmin, vals, nv, tp);
+  }
+  return tp;
+}
+
+Taps sum_taps(int J) {
+  const int N = 1 << J;
+  Taps tp;
+  tp.q0.assign(N + 1, 0);
+  tp.w.assign(3 * (size_t)(N + 1), 0.0);
+  for (int n = 0; n <= N; ++n) tp.w[3 * (size_t)n] = 1.0;
+  return tp;
+}
+
+void p1_eigen(int a, double len, std::vector<double> &m, std::vector<double> &k) {
+  const int n = 1 << a;
+  const long double h = (long double)len / n;
+  const long double pi = 3.14159265358979323846264338327950288L;
+  m.resize(n - 1);
+  k.resize(n - 1);
+  for (int j = 1; j < n; ++j) {
+    const long double th = pi * j / n;
+    const long double sh = sinl(th / 2);
+    m[j - 1] = (double)(h / 6 * (4 + 2 * cosl(th)));
+    k[j - 1] = (double)(4 / h * sh * sh);
+  }
+}
+
+std::vector<double> dst_matrix(int a) {
+  const int n = 1 << a, m = n - 1;
+  const long double pi = 3.14159265358979323846264338327950288L;
+  const long double sc = sqrtl(2.0L / n);
+  std::vector<double> Q((size_t)m * m);
+  for (int j = 1; j < n; ++j)
+    for (int k = 1; k < n; ++k) {
+      const long long r = ((long long)j * k) % (2 * n);  // sin(pi r / n)
+      Q[(size_t)(j - 1) * m + (k - 1)] = (double)(sc * sinl(pi * r / n));
+    }
+  return Q;
+}
+
+}  // namespace sg

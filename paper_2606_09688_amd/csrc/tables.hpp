@@ -1,0 +1,57 @@
+// Host-side tables of the discrete operator (time matrices, tap tables,
+// spatial eigenvalues, sine transforms).  Pure C++, no HIP calls.
+#pragma once
+
+#include <vector>
+
+namespace sg {
+
+// Gauss-Legendre nodes/weights on [-1,1] (Newton iteration on P_n).
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
+
+// Quadratic C^1 B-splines on the clamped uniform knot vector of level b of
+// (0,T), basis psi_i = B_{i+1}, i = 0..2^b.  On element e (t in
+// [e h, (e+1) h]) the nonzero functions are B_e, B_{e+1}, B_{e+2}; these
+// return their values / first / second derivatives at t in v[0..2].
+void spline_local(int b, double T, int e, double t, double v[3], double d1[3],
+                  double d2[3]);
+
+struct TimeLevel {
+  int b = 0, nq = 0;
+  std::vector<double> A, B;      // banded [nq][5], column j-i+2 (high parts)
+  std::vector<double> Alo, Blo;  // low parts: A = A + Alo exactly to ~32 digits
+  std::vector<double> Dlo, Dhi;  // psi_i'(t_i), psi_i'(t_{i+1})
+  std::vector<double> g;         // int psi_i' e^{-t/T}
+  double d0 = 0;                 // psi_0'(0) (psi_i'(0) = 0 for i > 0)
+};
+
+// Time matrices of Prop. 1 / eq. (30) for level b:
+//   A[i][j] = (psi_j'', psi_i')_{L2_e} + psi_j'(0) psi_i'(0),
+//   B[i][j] = (psi_j, psi_i')_{L2_e},   weight e^{-t/T},
+// from exact moment integrals in double-double (see tables.cpp).
+TimeLevel time_level(int b, double T);
+
+// Tap tables on the finest time grid (level J): for each fine node n,
+// q0[n] and w[3n..3n+2] such that the coupling of slab n to time index q is
+// w[k] for q = q0[n]+k.
+struct Taps {
+  std::vector<int> q0;
+  std::vector<double> w;
+};
+// P1 taps of level b: (Lambda_b^T M_e)[q][n], M_e the weighted P1 mass on
+// the fine time grid, Lambda_b the P1 hats of level b at fine nodes.
+Taps p1_taps(int b, int J, double T);
+// Spline taps of level b: psi^b_q(t_n).
+Taps spline_taps(int b, int J, double T);
+// Time-sum taps: q0 = 0, w = (1,0,0) for every n (sum over slabs).
+Taps sum_taps(int J);
+
+// 1-D P1 eigenvalues on (0,len) at level a (unit wave speed):
+// m_k = h/6 (4 + 2 cos(k pi/n)), kappa_k = 4/h sin^2(k pi/(2n)), k = 1..n-1.
+void p1_eigen(int a, double len, std::vector<double> &m, std::vector<double> &k);
+
+// Orthonormal DST-I matrix of level a: Q[j][k] = sqrt(2/n) sin(pi j k/n),
+// j,k = 1..n-1, n = 2^a (symmetric, Q Q = I), row-major (n-1)^2.
+std::vector<double> dst_matrix(int a);
+
+}  // namespace sg

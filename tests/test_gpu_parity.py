@@ -1,0 +1,175 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
+
+Bar: relative l2 error <= 1e-10 (FP64) for U, df, du0, dv0 and the
+component right-hand sides / solutions.  Sizes span several spatial tiles,
+time chunks, the coarse (below-tile) levels and ragged tails.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import Problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def rel(a, b):
+    a = np.asarray(a).reshape(-1)
+    b = np.asarray(b).reshape(-1)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _solver(spec):
+    import paper_2606_09688_amd as sg
+    return sg.SparseGridWave(spec.d, spec.lengths, spec.ncell, spec.c_vals, spec.T, spec.L)
+
+
+def _dev(x):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+CASES = [
+    # (d, lengths, c, T, L)
+    (1, [1.0], 1.0, 1.0, 2),
+    (1, [1.0], 1.0, 1.0, 3),
+    (1, [2.0], 0.7, 1.3, 6),
+    (1, [1.0], 1.0, 2.0, 9),
+    (1, [1.0], 1.3, 1.0, 11),     # 4 tiles, coarse levels below the tile
+    (2, [1.0, 1.0], 1.0, 1.0, 2),
+    (2, [1.0, 1.0], 1.0, 1.0, 3),
+    (2, [1.0, 0.8], 0.9, 1.5, 5),
+    (2, [1.0, 1.0], 1.0, 1.0, 7),  # 2x2 tiles
+    (2, [1.2, 1.0], 1.1, 0.9, 8),  # 4x4 tiles, coarse levels below the tile
+]
+
+
+def _case(d, lengths, c, T, L, seed):
+    spec = workloads.Spec(d, lengths, [1] * d, [c], T, L)
+    return spec, workloads.random_data(spec, seed)
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"d{c[0]}L{c[4]}")
+def test_forward_and_adjoint_parity(case):
+    torch = _torch()
+    d, lengths, c, T, L = case
+    spec, data = _case(d, lengths, c, T, L, seed=100 + L)
+    print(f"case d={d} L={L} c={c} T={T}", flush=True)
+    orc = Problem(*spec.args())
+    U_ref = orc.forward(data["f"], data["u0"], data["v0"]).reshape(spec.shape())
+    df_ref, du0_ref, dv0_ref = orc.adjoint(data["g"])
+    sv = _solver(spec)
+    f, u0, v0, g = (_dev(data[k]) for k in ("f", "u0", "v0", "g"))
+    U = sv.solve(f, u0, v0)
+    torch.cuda.synchronize()
+    e = rel(U.cpu().numpy(), U_ref)
+    print(f"  forward rel l2 {e:.3e}", flush=True)
+    assert e <= TOL
+    # intermediate stages of every component
+    for ci, (jx, jt, s) in enumerate(orc.comps):
+        info = sv.components()[ci]
+        assert info[:3] == (jx, jt, s)
+        b_ref = orc.load(jx, jt, data["f"], data["u0"], data["v0"])
+        assert rel(sv.component(ci, 0), b_ref) <= TOL, (jx, jt)
+        u_ref = orc.solve(jx, jt, b_ref)
+        assert rel(sv.component(ci, 1), u_ref) <= TOL, (jx, jt)
+    df, du0, dv0 = sv.adjoint(g)
+    torch.cuda.synchronize()
+    for name, got, ref in (("df", df, df_ref), ("du0", du0, du0_ref), ("dv0", dv0, dv0_ref)):
+        e = rel(got.cpu().numpy(), ref)
+        print(f"  adjoint {name} rel l2 {e:.3e}", flush=True)
+        assert e <= TOL, name
+
+
+@pytest.mark.parametrize("case", [CASES[2], CASES[4], CASES[7], CASES[9]],
+                         ids=lambda c: f"d{c[0]}L{c[4]}")
+def test_plain_loop_and_graph_match_fused(case):
+    """The per-component loop and the captured graph give the fused result
+    (plain: to roundoff of the different summation order; graph: bitwise),
+    over several replays with eager work in between."""
+    torch = _torch()
+    d, lengths, c, T, L = case
+    spec, data = _case(d, lengths, c, T, L, seed=7)
+    sv = _solver(spec)
+    f, u0, v0, g = (_dev(data[k]) for k in ("f", "u0", "v0", "g"))
+    U = sv.solve(f, u0, v0)
+    df, du0, dv0 = sv.adjoint(g)
+    Up = sv.solve(f, u0, v0, plain=True)
+    torch.cuda.synchronize()
+    assert rel(Up.cpu().numpy(), U.cpu().numpy()) <= 1e-13
+    s = torch.cuda.Stream()
+    Ug = torch.empty_like(U)
+    dfg, du0g, dv0g = torch.empty_like(df), torch.empty_like(du0), torch.empty_like(dv0)
+    with torch.cuda.stream(s):
+        sv.capture(f, u0, v0, Ug, g, dfg, du0g, dv0g, stream=s)
+    for rep in range(3):
+        Ug.zero_()
+        dfg.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            sv.replay(stream=s)
+        s.synchronize()
+        assert torch.equal(Ug, U), rep
+        assert torch.equal(dfg, df) and torch.equal(du0g, du0) and torch.equal(dv0g, dv0), rep
+        _ = (f * 2.0).sum().item()  # unrelated eager work between replays
+
+
+def test_manufactured_c1_against_closed_form():
+    """c1 (d=1, L=6): U matches the oracle to 1e-10 and the closed-form
+    solution sin(pi x) sin(pi t) to the discretisation error."""
+    torch = _torch()
+    spec, data = workloads.c1()
+    sv = _solver(spec)
+    U = sv.solve(_dev(data["f"]), _dev(data["u0"]), _dev(data["v0"])).cpu().numpy()
+    orc = Problem(*spec.args())
+    U_ref = orc.forward(data["f"], data["u0"], data["v0"])
+    assert rel(U, U_ref) <= TOL
+    t, (x,) = workloads.grids(spec)
+    exact = np.outer(np.sin(math.pi * t), np.sin(math.pi * x))
+    assert np.abs(U - exact).max() < 3e-3
+
+
+def test_autograd_uses_adjoint():
+    torch = _torch()
+    import paper_2606_09688_amd as sg
+    spec, data = _case(1, [1.0], 1.0, 1.0, 6, seed=3)
+    sv = _solver(spec)
+    f = _dev(data["f"]).requires_grad_(True)
+    u0 = _dev(data["u0"]).requires_grad_(True)
+    v0 = _dev(data["v0"]).requires_grad_(True)
+    U = sg.sgwave(sv, f, u0, v0)
+    Uobs = _dev(data["g"])
+    loss = 0.5 * ((U - Uobs) ** 2).sum()
+    loss.backward()
+    orc = Problem(*spec.args())
+    Uc = orc.forward(data["f"], data["u0"], data["v0"]).reshape(spec.shape())
+    df, du0, dv0 = orc.adjoint(Uc - data["g"])
+    assert rel(f.grad.cpu().numpy(), df) <= TOL
+    assert rel(u0.grad.cpu().numpy(), du0) <= TOL
+    assert rel(v0.grad.cpu().numpy(), dv0) <= TOL
+
+
+def test_invalid_arguments_raise():
+    _torch()
+    import paper_2606_09688_amd as sg
+    with pytest.raises(sg.SGError):
+        sg.SparseGridWave(1, [1.0], [1], [-1.0], 1.0, 5)
+    with pytest.raises(sg.SGError):
+        sg.SparseGridWave(1, [1.0], [1], [1.0], 0.0, 5)
+    with pytest.raises(sg.SGError):
+        sg.SparseGridWave(3, [1.0] * 3, [1] * 3, [1.0], 1.0, 5)
+    with pytest.raises(sg.SGError):
+        sg.SparseGridWave(1, [1.0], [3], [1.0, 1.0, 1.0], 1.0, 5)  # 16 % 3 != 0

@@ -1,0 +1,87 @@
+"""CPU tests of the HIP library's host side: exported symbols and the tables
+it builds, checked against the oracle (no device calls)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import timemat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sgwave.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sg_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2606_09688_amd as sg
+    L = ctypes.CDLL(sg.LIB_PATH)
+    names = _declared()
+    assert "sg_assemble" in names and "sg_adjoint" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+@pytest.mark.parametrize("b,T", [(1, 1.0), (2, 1.0), (4, 2.0), (7, 0.5)])
+def test_host_time_matrices_match_oracle(b, T):
+    """Banded A_b, B_b (Prop. 1), derivative values and g of the library's
+    host code equal the oracle's independent Cox-de Boor / quadrature ones."""
+    import paper_2606_09688_amd as sg
+    h = sg.host_time_level(b, T)
+    Dlo, Dhi, g = h["Dlo"], h["Dhi"], h["g"]
+    tm = timemat.time_matrices(b, T)
+    dd = timemat.time_matrices_dd(b, T)
+    n = 2 ** b + 1
+    for name in ("A", "B"):
+        # double-double entries agree with the oracle's 40-digit ones
+        diff = (h[name] - dd[name + "_hi"]) + (h[name + "lo"] - dd[name + "_lo"])
+        assert np.abs(diff).max() <= 1e-29 * np.abs(dd[name + "_hi"]).max(), name
+    assert np.allclose(g, tm["g"], rtol=1e-14, atol=1e-15)
+    # psi_i'(t_q) at the level-b nodes from the oracle's basis derivatives
+    from oracle import basis
+    tq = T * np.arange(n) / 2 ** b
+    dpsi = basis.time_basis(b, T, np.clip(tq, 0, T), 1)  # (q, i)
+    for i in range(n):
+        assert abs(Dlo[i] - dpsi[i, i]) <= 1e-12 * abs(dpsi).max()
+        if i + 1 < n:
+            assert abs(Dhi[i] - dpsi[i + 1, i]) <= 1e-12 * abs(dpsi).max()
+    assert tm["d0"][0] == pytest.approx(Dlo[0], rel=1e-14)
+
+
+def _dense_taps(q0, w, nq):
+    n = len(q0)
+    M = np.zeros((nq, n))
+    for k in range(n):
+        for o in range(3):
+            if w[k, o] != 0:
+                M[q0[k] + o, k] += w[k, o]
+    return M
+
+
+@pytest.mark.parametrize("b,J,T", [(1, 3, 1.0), (2, 5, 1.0), (3, 3, 2.0), (4, 7, 0.8)])
+def test_host_taps_compose_to_oracle_load_and_evaluation(b, J, T):
+    """P1 taps followed by the derivative values D_b reproduce the oracle's
+    load factor W (eq. 9 with P1-in-time data); spline taps equal the
+    oracle's basis values at the fine nodes; the windows are monotone with
+    unit steps as the streaming kernels assume."""
+    import paper_2606_09688_amd as sg
+    nq = 2 ** b + 1
+    q0, w = sg.host_taps(0, b, J, T)
+    assert np.all(np.diff(q0) >= 0) and np.all(np.diff(q0) <= 1)
+    assert q0.min() >= 0 and q0.max() <= nq - 3
+    P1 = _dense_taps(q0, w, nq)                     # (q, n)
+    h = sg.host_time_level(b, T)
+    D = np.diag(h["Dlo"]) + np.diag(h["Dhi"][:-1], 1)         # D[i, q] nonzero at q = i, i+1
+    W = timemat.load_weights(b, J, T)
+    assert np.abs(D @ P1 - W).max() <= 1e-13 * np.abs(W).max()
+    q0s, ws = sg.host_taps(1, b, J, T)
+    assert np.all(np.diff(q0s) >= 0) and np.all(np.diff(q0s) <= 1)
+    Psi = _dense_taps(q0s, ws, nq).T                # (n, i)
+    assert np.abs(Psi - timemat.eval_at_nodes(b, J, T)).max() <= 1e-15

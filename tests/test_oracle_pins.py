@@ -67,6 +67,61 @@ def test_time_matrix_identities_eq2_eq3(jt, T):
     assert np.abs(i - j).max() <= 2
 
 
+@pytest.mark.parametrize("jt,T", [(1, 1.0), (3, 1.3), (8, 2.0)])
+def test_exact_time_matrices(jt, T):
+    """The 32-digit time matrices satisfy eqs. (2)-(3) to 1e-30 (checked in
+    40-digit arithmetic), agree with the independent double-precision
+    quadrature to rounding, and their low parts are below half an ulp."""
+    d = timemat.time_matrices_dd(jt, T)
+    assert d["identity_A"] < 1e-30 and d["identity_B"] < 1e-30
+    tm = timemat.time_matrices(jt, T)
+    for name in ("A", "B"):
+        hi = timemat.band_to_dense(d[name + "_hi"])
+        lo = timemat.band_to_dense(d[name + "_lo"])
+        assert np.abs(hi - tm[name]).max() <= 2e-15 * np.abs(tm[name]).max()
+        assert np.all(np.abs(lo) <= 0.5 * np.spacing(np.abs(hi)) + 1e-300)
+
+
+def test_long_time_solve_matches_40_digit_elimination():
+    """N_t = 1025 (one spatial mode): the refined oracle solve equals a
+    40-digit banded Gaussian elimination of the same system A m + B k."""
+    import mpmath
+    prob = Problem(1, [1.0], [1], [1.0], 1.0, 11)
+    jx, jt = 1, 10
+    rng = np.random.default_rng(21)
+    b = rng.standard_normal((2 ** jt + 1, 1))
+    x = prob.solve(jx, jt, b)[:, 0]
+    m = prob.mass(jx).toarray()[0, 0]
+    k = prob.stiff(jx).toarray()[0, 0]
+    d = prob.tmat_dd(jt)
+    n = 2 ** jt + 1
+    with mpmath.workdps(40):
+        M = [[mpmath.mpf(d["A_hi"][i, c]) + mpmath.mpf(d["A_lo"][i, c])
+              for c in range(5)] for i in range(n)]
+        Bm = [[mpmath.mpf(d["B_hi"][i, c]) + mpmath.mpf(d["B_lo"][i, c])
+               for c in range(5)] for i in range(n)]
+        S = [[M[i][c] * mpmath.mpf(m) + Bm[i][c] * mpmath.mpf(k) for c in range(5)]
+             for i in range(n)]
+        r = [mpmath.mpf(v) for v in b[:, 0]]
+        for i in range(n):           # banded elimination, no pivoting
+            for kk in (1, 2):
+                if i + kk >= n:
+                    continue
+                lmul = S[i + kk][2 - kk] / S[i][2]
+                for c in range(3):
+                    S[i + kk][2 - kk + c] -= lmul * S[i][2 + c]
+                r[i + kk] -= lmul * r[i]
+        xs = [mpmath.mpf(0)] * n
+        for i in range(n - 1, -1, -1):
+            acc = r[i]
+            for kk in (1, 2):
+                if i + kk < n:
+                    acc -= S[i][2 + kk] * xs[i + kk]
+            xs[i] = acc / S[i][2]
+        xr = np.array([float(v) for v in xs])
+    assert np.linalg.norm(x - xr) <= 1e-13 * np.linalg.norm(xr)
+
+
 def test_time_basis_textbook():
     """Clamped quadratic B-splines: partition of unity, only B_0 is nonzero at
     t=0, C^1 at interior knots, and on interior elements the uniform pieces
@@ -92,7 +147,7 @@ def test_time_basis_textbook():
     assert np.allclose(vals[:, e], (1 + 2 * s - 2 * s ** 2) / 2, atol=1e-15)
     assert np.allclose(vals[:, e + 1], s ** 2 / 2, atol=1e-15)
     # the local evaluator agrees with the full recursion
-    loc = timemat._span_values(jt, T, e, (e + s) * h, 1)[1]
+    loc = timemat._span_values(jt, T, e, s, 1)[1]
     assert np.allclose(loc, basis.time_basis(jt, T, (e + s) * h, 1)[:, e - 1:e + 2])
 
 
@@ -278,7 +333,7 @@ def test_component_system_matches_bilinear_form_eq6():
     evaluated term by term by an independent space-time quadrature."""
     prob = Problem(1, [1.0], [3], [1.0, 0.6, 1.7], 1.3, 5)
     for jx, jt in [(2, 2), (1, 3), (3, 1)]:
-        S = prob.system(jx, jt).toarray()
+        S = prob.system(jx, jt).toarray()   # high parts of A, B
         Sb = _brute_bilinear(prob, jx, jt)
         assert np.abs(S - Sb).max() <= 1e-12 * np.abs(Sb).max()
         # coercivity, eq. (8): symmetric part positive definite
