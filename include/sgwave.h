@@ -138,10 +138,12 @@ sg_status sg_component_info(const sg_problem *p, int c, int *jx, int *jt,
                             int *sign, int *n_space, int *n_time);
 
 /*
- * Copy the coefficients of component c from the last sg_solve (stage 0: the
- * right-hand side b_c of eq. (9); stage 1: the solution u_c) into host memory
- * `out` of n_time * n_space doubles, time index outer.  Synchronises the
- * device.  For tests of intermediate stages.
+ * Copy the coefficients of component c into host memory `out` of
+ * n_time * n_space doubles (time index outer); synchronises the device.
+ * stage 0: right-hand side b_c of eq. (9) of the last sg_solve;
+ * stage 1: its solution u_c;  stage 2: the adjoint right-hand side
+ * s_c Psi^T g Phi of the last sg_adjoint;  stage 3: its solution
+ * S_c^{-T} (s_c Psi^T g Phi).  For tests of intermediate stages.
  */
 sg_status sg_component_copy(sg_problem *p, int c, int stage, double *out);
 

@@ -218,6 +218,10 @@ class SparseGridWave:
         if events is None:
             check(lib().sg_set_events(self._h, None, 0), "sg_set_events")
             return
+        for e in events:      # torch creates the underlying event on first record
+            if not e.cuda_event:
+                e.record()
+        torch.cuda.synchronize()
         arr = (ctypes.c_void_p * len(events))(*[e.cuda_event for e in events])
         check(lib().sg_set_events(self._h, arr, len(events)), "sg_set_events")
 

@@ -101,7 +101,7 @@ struct sg_problem {
   double *d_ce = nullptr;         // fine-element c^2
   // buffers (N^sparse each)
   double *bufZ = nullptr, *bufB = nullptr, *bufT = nullptr, *bufS = nullptr,
-         *bufU = nullptr, *bufW = nullptr, *scratch = nullptr;
+         *bufU = nullptr, *bufW = nullptr, *bufY = nullptr, *scratch = nullptr;
   // level fields [3][nsp_a] per level (row 0 meaningful)
   std::vector<double *> mv_lv, ku_lv, fv_lv, fu_lv;
   double *gsum = nullptr;          // [3][nsp_J]
@@ -115,6 +115,7 @@ struct sg_problem {
   std::vector<Pass> plain_load, plain_prol;
   // descriptor lists
   GemmList gx, gy, giy, gix;       // fused (all components)
+  GemmList agx, agix;              // adjoint: x-transform from bufZ, inverse into bufW
   std::vector<GemmList> pgx, pgy, pgiy, pgix;
   SolveList sfwd, sadj;
   std::vector<SolveList> psfwd;
@@ -243,9 +244,16 @@ sg_status build_pass(sg_problem *p, Pass &P, const Geometry &geo, F spec,
   return SG_OK;
 }
 
-void mark(sg_problem *p, int id, hipStream_t s) {
-  if (!p->capturing && id < (int)p->ev.size()) (void)hipEventRecord(p->ev[id], s);
+sg_status mark(sg_problem *p, int id, hipStream_t s) {
+  if (!p->capturing && id < (int)p->ev.size()) HIPCHK(hipEventRecord(p->ev[id], s));
+  return SG_OK;
 }
+
+#define MARK(p, id, s)                          \
+  do {                                          \
+    sg_status st_ = mark(p, id, s);             \
+    if (st_ != SG_OK) return st_;               \
+  } while (0)
 
 sg_status run_restrict(sg_problem *p, const Pass &P, const double *X, int stencil,
                        hipStream_t s, int ev_begin = -1) {
@@ -260,9 +268,9 @@ sg_status run_restrict(sg_problem *p, const Pass &P, const double *X, int stenci
   ra.ch = P.d_ch;
   ra.part = p->part;
   ra.coarse = g.A0 > 1 ? p->cpart : nullptr;
-  if (ev_begin >= 0) mark(p, ev_begin, s);
+  if (ev_begin >= 0) MARK(p, ev_begin, s);
   HIPCHK(launch_restrict(ra, s));
-  if (ev_begin >= 0) mark(p, ev_begin + 1, s);
+  if (ev_begin >= 0) MARK(p, ev_begin + 1, s);
   if (P.n_red) HIPCHK(launch_reduce(g, P.d_ch, p->part, P.d_red, P.n_red, P.tot_red, s));
   if (g.A0 > 1 && P.n_crs) {
     HIPCHK(launch_coarse_assemble(g, p->cpart, p->S0, s));
@@ -289,15 +297,18 @@ sg_status run_prolong(sg_problem *p, const Pass &P, const double *base, double *
   const double hx = p->len[0] / p->N, hy = (p->d == 2 ? p->len[1] : 1.0) / p->N;
   pa.sx = hx / 6.0;
   pa.sy = hy / 6.0;
-  if (ev_begin >= 0) mark(p, ev_begin, s);
+  if (ev_begin >= 0) MARK(p, ev_begin, s);
   HIPCHK(launch_prolong(pa, s));
-  if (ev_begin >= 0) mark(p, ev_begin + 1, s);
+  if (ev_begin >= 0) MARK(p, ev_begin + 1, s);
   return SG_OK;
 }
 
 // DST descriptor lists for a set of components: x-transform src->dst
 sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList &gx,
-                           GemmList &gy, GemmList &giy, GemmList &gix) {
+                           GemmList &gy, GemmList &giy, GemmList &gix,
+                           double *x_in = nullptr, double *x_out = nullptr) {
+  if (!x_in) x_in = p->bufB;
+  if (!x_out) x_out = p->bufU;
   std::vector<GemmDesc> vx, vy, viy, vix;
   int tx = 0, ty = 0, tiy = 0, tix = 0;
   for (int ci : cset) {
@@ -309,7 +320,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
     // forward x: T = B * Q   ([nq*ny x na] x [na x na])
     {
       GemmDesc g{};
-      g.A = p->bufB + C.off; g.B = Q; g.C = p->bufT + C.off;
+      g.A = x_in + C.off; g.B = Q; g.C = p->bufT + C.off;
       g.M = C.nq * ny; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
       g.batch = 1; g.tm = (g.M + 63) / 64; g.tn = (g.N + 63) / 64; g.tile0 = tx;
       tx += tiles(g.M, g.N);
@@ -318,7 +329,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
     // inverse x: U = T * Q
     {
       GemmDesc g{};
-      g.A = p->bufT + C.off; g.B = Q; g.C = p->bufU + C.off;
+      g.A = p->bufT + C.off; g.B = Q; g.C = x_out + C.off;
       g.M = C.nq * ny; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
       g.batch = 1; g.tm = (g.M + 63) / 64; g.tn = (g.N + 63) / 64; g.tile0 = tix;
       tix += tiles(g.M, g.N);
@@ -368,7 +379,8 @@ sg_status build_solve_list(sg_problem *p, const std::vector<int> &cset, int tran
     sd.a = C.a;
     // refinement sweeps against the double-double time matrices: the double
     // LU is a preconditioner whose quality drops as the time level grows
-    sd.refine = C.nq < p->refine_nq ? 0 : (C.nq <= 513 ? 2 : (C.nq <= 2049 ? 3 : 5));
+    // (a sweep stops early once the correction is below 1e-17 of the solution)
+    sd.refine = C.nq < p->refine_nq ? 0 : (C.nq <= 513 ? 4 : 8);
     sd.transpose = transpose;
     sd.c2 = p->c2;
     sd.thread0 = th;
@@ -567,6 +579,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   if (!(p->bufZ = p->dalloc<double>(ns)) || !(p->bufB = p->dalloc<double>(ns)) ||
       !(p->bufT = p->dalloc<double>(ns)) || !(p->bufS = p->dalloc<double>(ns)) ||
       !(p->bufU = p->dalloc<double>(ns)) || !(p->bufW = p->dalloc<double>(ns)) ||
+      !(p->bufY = p->dalloc<double>(ns)) ||
       !(p->scratch = p->dalloc<double>(7 * ns)))
     return bail(fail(SG_ENOMEM, "hipMalloc of component buffers failed"));
   p->mv_lv.assign(J + 1, nullptr);
@@ -633,7 +646,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
                        &part_need)))
     return bail(st);
   if ((st = build_pass(p, p->adjp, geo,
-                       [&](int a, int k) { return chan_comp(a, k, false, p->bufZ, false, -1); },
+                       [&](int a, int k) { return chan_comp(a, k, false, p->bufY, false, -1); },
                        &part_need)))
     return bail(st);
   auto field = [&](std::vector<double *> &v0, std::vector<double *> &v1) {
@@ -680,6 +693,11 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   std::vector<int> all(ncomp);
   for (int i = 0; i < ncomp; ++i) all[i] = i;
   if ((st = build_gemm_lists(p, all, p->gx, p->gy, p->giy, p->gix))) return bail(st);
+  {
+    GemmList dy, diy;
+    if ((st = build_gemm_lists(p, all, p->agx, dy, diy, p->agix, p->bufZ, p->bufW)))
+      return bail(st);
+  }
   if ((st = build_solve_list(p, all, 0, p->sfwd))) return bail(st);
   if ((st = build_solve_list(p, all, 1, p->sadj))) return bail(st);
   p->pgx.resize(ncomp); p->pgy.resize(ncomp); p->pgiy.resize(ncomp); p->pgix.resize(ncomp);
@@ -707,7 +725,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
       tl += (long long)C.nq * C.nsp;
       vl.push_back(cd);
       CompDesc ca = cd;
-      ca.data = p->bufZ + C.off;
+      ca.data = p->bufY + C.off;
       ca.z = p->bufW + C.off;
       ca.mv = nullptr;
       ca.ku = nullptr;
@@ -775,10 +793,11 @@ sg_status sg_component_info(const sg_problem *p, int c, int *jx, int *jt, int *s
 sg_status sg_component_copy(sg_problem *p, int c, int stage, double *out) {
   if (!p || !out) return fail(SG_EINVAL, "NULL argument");
   if (c < 0 || c >= (int)p->comps.size()) return fail(SG_EINVAL, "component index out of range");
-  if (stage != 0 && stage != 1) return fail(SG_EINVAL, "stage must be 0 or 1");
+  if (stage < 0 || stage > 3) return fail(SG_EINVAL, "stage must be 0..3");
   const Comp &C = p->comps[c];
   HIPCHK(hipDeviceSynchronize());
-  const double *src = (stage == 0 ? p->bufB : p->bufU) + C.off;
+  const double *bufs[4] = {p->bufB, p->bufU, p->bufZ, p->bufW};
+  const double *src = bufs[stage] + C.off;
   HIPCHK(hipMemcpy(out, src, (size_t)C.nq * C.nsp * sizeof(double), hipMemcpyDeviceToHost));
   return SG_OK;
 }
@@ -798,13 +817,13 @@ sg_status sg_solve(sg_problem *p, const double *f, const double *u0, const doubl
   if (!f || !u0 || !v0 || !U) return fail(SG_EINVAL, "NULL data pointer");
   if (U == f) return fail(SG_EINVAL, "U must not alias f");
   sg_status st;
-  mark(p, 0, s);
+  MARK(p, 0, s);
   if ((st = forward_fields(p, u0, v0, s))) return st;
   if ((st = run_restrict(p, p->load, f, 1, s, 1))) return st;
   HIPCHK(launch_post_load(p->cload.d, p->cload.n, p->cload.total, p->d_kt, s));
-  mark(p, 3, s);
+  MARK(p, 3, s);
   if ((st = run_solves(p, p->gx, p->gy, p->sfwd, p->giy, p->gix, s))) return st;
-  mark(p, 4, s);
+  MARK(p, 4, s);
   return run_prolong(p, p->prol, u0, U, 0, 0, s, 5);
 }
 
@@ -831,22 +850,17 @@ sg_status sg_adjoint(sg_problem *p, const double *g, double *df, double *du0, do
   if (!p) return fail(SG_EINVAL, "NULL handle");
   if (!g) return fail(SG_EINVAL, "NULL cotangent");
   sg_status st;
-  mark(p, 7, s);
+  MARK(p, 7, s);
   // y_c = s_c Psi^T g Phi (+ time sum of g for du0)
   if ((st = run_restrict(p, p->adjr, g, 0, s, 8))) return st;
-  // z_c = S_c^{-T} y_c : transforms read bufB, so stage y_c there
-  HIPCHK(hipMemcpyAsync(p->bufB, p->bufZ, p->nsparse * sizeof(double),
-                        hipMemcpyDeviceToDevice, s));
-  mark(p, 10, s);
-  HIPCHK(launch_gemm(p->gx.d, p->gx.n, p->gx.tiles, s));
+  // z_c = S_c^{-T} y_c  (y_c in bufZ, z_c into bufW)
+  MARK(p, 10, s);
+  HIPCHK(launch_gemm(p->agx.d, p->agx.n, p->agx.tiles, s));
   if (p->d == 2) HIPCHK(launch_gemm(p->gy.d, p->gy.n, p->gy.tiles, s));
   HIPCHK(launch_time_solve(p->sadj.d, p->sadj.n, p->sadj.threads, p->d_kt, p->d_mt, p->d, s));
   if (p->d == 2) HIPCHK(launch_gemm(p->giy.d, p->giy.n, p->giy.tiles, s));
-  HIPCHK(launch_gemm(p->gix.d, p->gix.n, p->gix.tiles, s));
-  mark(p, 11, s);
-  // the inverse x-transform wrote bufU; move z_c to bufW
-  HIPCHK(hipMemcpyAsync(p->bufW, p->bufU, p->nsparse * sizeof(double),
-                        hipMemcpyDeviceToDevice, s));
+  HIPCHK(launch_gemm(p->agix.d, p->agix.n, p->agix.tiles, s));
+  MARK(p, 11, s);
   // zeta_c = D^T z_c, level fields for du0 / dv0
   HIPCHK(launch_post_adjoint(p->cadj.d, p->cadj.n, p->cadj.total, p->d_kt, s));
   if (df) {
@@ -859,7 +873,7 @@ sg_status sg_adjoint(sg_problem *p, const double *g, double *df, double *du0, do
     HIPCHK(launch_fine_stencils(p->d, p->N, p->d_ce, hx, hy, p->fine2, p->fine2 + p->nsp_fine,
                                 dv0, du0, p->gsum, 1, s));
   }
-  mark(p, 14, s);
+  MARK(p, 14, s);
   return SG_OK;
 }
 

@@ -1,5 +1,7 @@
 // Double-double arithmetic for the host-side tables (about 32 significant
 // digits).  Error-free transformations with std::fma; Dekker/Knuth style.
+// Contraction is switched off inside every helper: fusing a rounded product
+// into a later addition breaks the error-free transformations.
 #pragma once
 
 #include <cmath>
@@ -15,19 +17,23 @@ struct ddv {
 };
 
 inline ddv quick_two_sum(double a, double b) {
+#pragma clang fp contract(off)
   const double s = a + b;
   return {s, b - (s - a)};
 }
 inline ddv two_sum(double a, double b) {
+#pragma clang fp contract(off)
   const double s = a + b;
   const double bb = s - a;
   return {s, (a - (s - bb)) + (b - bb)};
 }
 inline ddv two_prod(double a, double b) {
+#pragma clang fp contract(off)
   const double p = a * b;
   return {p, std::fma(a, b, -p)};
 }
 inline ddv operator+(ddv a, ddv b) {
+#pragma clang fp contract(off)
   ddv s = two_sum(a.hi, b.hi);
   ddv t = two_sum(a.lo, b.lo);
   s.lo += t.hi;
@@ -38,11 +44,13 @@ inline ddv operator+(ddv a, ddv b) {
 inline ddv operator-(ddv a) { return {-a.hi, -a.lo}; }
 inline ddv operator-(ddv a, ddv b) { return a + (-b); }
 inline ddv operator*(ddv a, ddv b) {
+#pragma clang fp contract(off)
   ddv p = two_prod(a.hi, b.hi);
   p.lo += a.hi * b.lo + a.lo * b.hi;
   return quick_two_sum(p.hi, p.lo);
 }
 inline ddv operator/(ddv a, ddv b) {
+#pragma clang fp contract(off)
   const double q1 = a.hi / b.hi;
   ddv r = a - b * ddv(q1);
   const double q2 = r.hi / b.hi;

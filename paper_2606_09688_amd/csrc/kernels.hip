@@ -899,37 +899,49 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ descs
 
 // ---- per-mode banded time solve ------------------------------------------
 
+// Double-double helpers.  Floating-point contraction must stay off inside
+// them: a product p = a*b fused with a later subtraction (acc - p) into one
+// FMA uses the unrounded product while the error term assumes the rounded
+// one, which silently destroys the error-free transformation.
 struct dd {
   double h, l;
 };
 __device__ __forceinline__ dd two_sum(double a, double b) {
+#pragma clang fp contract(off)
   const double s = a + b;
   const double bb = s - a;
   return {s, (a - (s - bb)) + (b - bb)};
 }
 __device__ __forceinline__ dd two_prod(double a, double b) {
+#pragma clang fp contract(off)
   const double p = a * b;
   return {p, fma(a, b, -p)};
 }
 __device__ __forceinline__ dd dd_add(dd x, dd y) {
+#pragma clang fp contract(off)
   dd s = two_sum(x.h, y.h);
   s.l += x.l + y.l;
   return two_sum(s.h, s.l);
 }
 // (p * q) * x with p, q, x doubles, as a double-double
 __device__ __forceinline__ dd triple(double p, double q, double x) {
+#pragma clang fp contract(off)
   const dd pq = two_prod(p, q);
   dd r = two_prod(pq.h, x);
   r.l = fma(pq.l, x, r.l);
   return r;
 }
 
-// One thread per spatial mode: (m A_b + kappa B_b) u = r (or the transpose),
-// pentadiagonal LU without pivoting (the symmetric parts of A_b and B_b are
-// positive definite, Prop. 1), factors kept in scratch for the refinement.
-__global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__ sds, int nsd, long long total,
-                             const KernelTables *__restrict__ kt,
-                             const ModeTables *__restrict__ mt, int d) {
+// One thread per spatial mode: (m A_b + kappa B_b) u = r, or its transpose.
+// E = m A_b + kappa B_b is factored E = L U without pivoting in causal
+// (increasing time) order - the symmetric parts of A_b and B_b are positive
+// definite (Prop. 1).  The transposed (adjoint) system uses the same factors,
+// E^T = U^T L^T, which keeps the elimination causal for the backward-in-time
+// adjoint.  The solution is refined against the double-double time matrices.
+__global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__ sds,
+                                                   int nsd, long long total,
+                                                   const KernelTables *__restrict__ kt,
+                                                   const ModeTables *__restrict__ mt, int d) {
   const long long gid = gid64();
   if (gid >= total) return;
   int di = 0;
@@ -947,106 +959,117 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
     m = mt->my[a][jy] * mt->mx[a][jx];
     kap = S.c2 * (mt->ky[a][jy] * mt->mx[a][jx] + mt->my[a][jy] * mt->kx[a][jx]);
   }
-  const double *Ab = kt->A[b];
-  const double *Bb = kt->B[b];
+  const double *Ab = kt->A[b], *Bb = kt->B[b], *Al = kt->Alo[b], *Bl = kt->Blo[b];
   const bool tr = S.transpose != 0;
-  // matrix entries (band storage [row][col-row+2]); kappa and m kept separate
-  // for the exact residual
-  auto aent = [&](int i, int off) -> double {
-    const int r = tr ? i + off : i, c = tr ? 2 - off : off + 2;
-    return Ab[r * 5 + c];
-  };
-  auto bent = [&](int i, int off) -> double {
-    const int r = tr ? i + off : i, c = tr ? 2 - off : off + 2;
-    return Bb[r * 5 + c];
-  };
+  // entry (i, i+off) of E (band storage [row][off+2])
   auto ent = [&](int i, int off) -> double {
     const int jj = i + off;
     if (jj < 0 || jj >= nq) return 0.0;
-    return m * aent(i, off) + kap * bent(i, off);
+    return m * Ab[i * 5 + off + 2] + kap * Bb[i * 5 + off + 2];
   };
   double *rhs = S.rhs;
   const long long plane = (long long)nq * nm;
   double *L1 = S.scratch, *L2 = L1 + plane, *UD = L2 + plane, *U1 = UD + plane,
          *U2 = U1 + plane, *Y = U2 + plane, *B0 = Y + plane;
-  // factor + forward substitution
-  double dm2 = 1.0, u1m2 = 0.0, u2m2 = 0.0, ym2 = 0.0;
-  double dm1 = 1.0, u1m1 = 0.0, u2m1 = 0.0, ym1 = 0.0;
-  for (int i = 0; i < nq; ++i) {
-    const long long o = (long long)i * nm + j;
-    double am2 = ent(i, -2), am1 = ent(i, -1), a0 = ent(i, 0), ap1 = ent(i, 1),
-           ap2 = ent(i, 2);
-    const double l2 = (i >= 2) ? am2 / dm2 : 0.0;
-    am1 -= l2 * u1m2;
-    a0 -= l2 * u2m2;
-    const double l1 = (i >= 1) ? am1 / dm1 : 0.0;
-    a0 -= l1 * u1m1;
-    ap1 -= l1 * u2m1;
-    const double r = rhs[o];
-    if (S.refine) B0[o] = r;
-    const double y = r - l2 * ym2 - l1 * ym1;
-    L1[o] = l1;
-    L2[o] = l2;
-    UD[o] = 1.0 / a0;
-    U1[o] = ap1;
-    U2[o] = ap2;
-    Y[o] = y;
-    dm2 = dm1; u1m2 = u1m1; u2m2 = u2m1; ym2 = ym1;
-    dm1 = a0; u1m1 = ap1; u2m1 = ap2; ym1 = y;
+  // factor E = L U
+  {
+    double dm2 = 1.0, u1m2 = 0.0, u2m2 = 0.0;
+    double dm1 = 1.0, u1m1 = 0.0, u2m1 = 0.0;
+    for (int i = 0; i < nq; ++i) {
+      const long long o = (long long)i * nm + j;
+      double am2 = ent(i, -2), am1 = ent(i, -1), a0 = ent(i, 0), ap1 = ent(i, 1),
+             ap2 = ent(i, 2);
+      const double l2 = (i >= 2) ? am2 / dm2 : 0.0;
+      am1 -= l2 * u1m2;
+      a0 -= l2 * u2m2;
+      const double l1 = (i >= 1) ? am1 / dm1 : 0.0;
+      a0 -= l1 * u1m1;
+      ap1 -= l1 * u2m1;
+      L1[o] = l1;
+      L2[o] = l2;
+      UD[o] = 1.0 / a0;
+      U1[o] = ap1;
+      U2[o] = ap2;
+      dm2 = dm1; u1m2 = u1m1; u2m2 = u2m1;
+      dm1 = a0; u1m1 = ap1; u2m1 = ap2;
+    }
   }
-  double xp1 = 0.0, xp2 = 0.0;
-  for (int i = nq - 1; i >= 0; --i) {
-    const long long o = (long long)i * nm + j;
-    const double x = (Y[o] - U1[o] * xp1 - U2[o] * xp2) * UD[o];
-    rhs[o] = x;
-    xp2 = xp1;
-    xp1 = x;
-  }
-  // iterative refinement: residual of (m A + kappa B) with the double-double
-  // time matrices (A + Alo, B + Blo), accumulated in double-double
-  const double *Al = kt->Alo[b];
-  const double *Bl = kt->Blo[b];
-  auto aloe = [&](int i, int off) -> double {
-    const int r = tr ? i + off : i, c = tr ? 2 - off : off + 2;
-    return Al[r * 5 + c];
+  auto at = [&](const double *P, int i) -> double {
+    return (i >= 0 && i < nq) ? P[(long long)i * nm + j] : 0.0;
   };
-  auto bloe = [&](int i, int off) -> double {
-    const int r = tr ? i + off : i, c = tr ? 2 - off : off + 2;
-    return Bl[r * 5 + c];
+  // x <- op(E)^{-1} r: r read from R (R may be Y: each entry is read before
+  // it is overwritten), result added (add) or stored into rhs; returns max|x|
+  auto apply_inverse = [&](const double *R, bool add) -> double {
+    double xm = 0.0;
+    if (!tr) {
+      double ym2 = 0.0, ym1 = 0.0;
+      for (int i = 0; i < nq; ++i) {
+        const long long o = (long long)i * nm + j;
+        const double y = R[o] - L2[o] * ym2 - L1[o] * ym1;
+        Y[o] = y;
+        ym2 = ym1;
+        ym1 = y;
+      }
+      double xp1 = 0.0, xp2 = 0.0;
+      for (int i = nq - 1; i >= 0; --i) {
+        const long long o = (long long)i * nm + j;
+        const double x = (Y[o] - U1[o] * xp1 - U2[o] * xp2) * UD[o];
+        rhs[o] = add ? rhs[o] + x : x;
+        xm = fmax(xm, fabs(x));
+        xp2 = xp1;
+        xp1 = x;
+      }
+    } else {
+      // U^T w = r (forward), then L^T z = w (backward)
+      double wm2 = 0.0, wm1 = 0.0;
+      for (int i = 0; i < nq; ++i) {
+        const long long o = (long long)i * nm + j;
+        const double w = (R[o] - at(U1, i - 1) * wm1 - at(U2, i - 2) * wm2) * UD[o];
+        Y[o] = w;
+        wm2 = wm1;
+        wm1 = w;
+      }
+      double zp1 = 0.0, zp2 = 0.0;
+      for (int i = nq - 1; i >= 0; --i) {
+        const long long o = (long long)i * nm + j;
+        const double z = Y[o] - at(L1, i + 1) * zp1 - at(L2, i + 2) * zp2;
+        rhs[o] = add ? rhs[o] + z : z;
+        xm = fmax(xm, fabs(z));
+        zp2 = zp1;
+        zp1 = z;
+      }
+    }
+    return xm;
   };
+  if (S.refine)
+    for (int i = 0; i < nq; ++i) B0[(long long)i * nm + j] = rhs[(long long)i * nm + j];
+  apply_inverse(rhs, false);
+  if (!S.refine) return;
+  // refinement: r = b - op(E) x with E from the double-double time matrices,
+  // accumulated in double-double, then x += op(E)^{-1} r
   for (int it = 0; it < S.refine; ++it) {
-    double ym2r = 0.0, ym1r = 0.0;
+#pragma clang fp contract(off)
+    double xmax = 0.0;
     for (int i = 0; i < nq; ++i) {
       const long long o = (long long)i * nm + j;
       dd acc = {B0[o], 0.0};
       for (int off = -2; off <= 2; ++off) {
         const int jj = i + off;
         if (jj < 0 || jj >= nq) continue;
+        // op(E)[i][jj] = E[i][jj] (or E[jj][i] for the transpose)
+        const int r = tr ? jj : i, c = tr ? 2 - off : off + 2;
         const double x = rhs[(long long)jj * nm + j];
-        dd t1 = triple(m, aent(i, off), x);
-        dd t2 = triple(kap, bent(i, off), x);
-        t1.l = fma(m * aloe(i, off), x, t1.l);
-        t2.l = fma(kap * bloe(i, off), x, t2.l);
+        dd t1 = triple(m, Ab[r * 5 + c], x);
+        dd t2 = triple(kap, Bb[r * 5 + c], x);
+        t1.l = fma(m * Al[r * 5 + c], x, t1.l);
+        t2.l = fma(kap * Bl[r * 5 + c], x, t2.l);
         acc = dd_add(acc, {-t1.h, -t1.l});
         acc = dd_add(acc, {-t2.h, -t2.l});
       }
-      const double r = acc.h + acc.l;
-      const double y = r - L2[o] * ym2r - L1[o] * ym1r;
-      Y[o] = y;
-      ym2r = ym1r;
-      ym1r = y;
+      Y[o] = acc.h + acc.l;  // residual, consumed in place by apply_inverse
+      xmax = fmax(xmax, fabs(rhs[o]));
     }
-    double dp1 = 0.0, dp2 = 0.0, dmax = 0.0, xmax = 0.0;
-    for (int i = nq - 1; i >= 0; --i) {
-      const long long o = (long long)i * nm + j;
-      const double dlt = (Y[o] - U1[o] * dp1 - U2[o] * dp2) * UD[o];
-      const double xn = rhs[o] + dlt;
-      rhs[o] = xn;
-      dmax = fmax(dmax, fabs(dlt));
-      xmax = fmax(xmax, fabs(xn));
-      dp2 = dp1;
-      dp1 = dlt;
-    }
+    const double dmax = apply_inverse(Y, true);
     if (dmax <= 1e-17 * xmax) break;
   }
 }
