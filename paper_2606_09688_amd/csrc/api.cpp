@@ -102,6 +102,7 @@ struct sg_problem {
   // buffers (N^sparse each)
   double *bufZ = nullptr, *bufB = nullptr, *bufT = nullptr, *bufS = nullptr,
          *bufU = nullptr, *bufW = nullptr, *bufY = nullptr, *scratch = nullptr;
+  double *fac = nullptr;           // 5 planes per component: LU factors per mode
   // level fields [3][nsp_a] per level (row 0 meaningful)
   std::vector<double *> mv_lv, ku_lv, fv_lv, fu_lv;
   double *gsum = nullptr;          // [3][nsp_J]
@@ -188,6 +189,7 @@ sg_status build_pass(sg_problem *p, Pass &P, const Geometry &geo, F spec,
                      long long *part_need) {
   P.geo = geo;
   const int J = geo.J;
+  if (2 * J > kChanMax) return fail(SG_EINVAL, "too many levels for the channel table");
   P.h_ch.assign(2 * J, Channel{});
   long long off = 0;
   std::vector<WorkItem> red, crs;
@@ -207,6 +209,12 @@ sg_status build_pass(sg_problem *p, Pass &P, const Geometry &geo, F spec,
       C.qb = 0;
       C.part_off = 0;
       if (!cs.active) continue;
+      if (a == J) {
+        // the streaming kernels keep the level-J coefficient window fixed
+        bool fixed = cs.nq == 3;
+        for (int n = 0; fixed && n < geo.ntf; ++n) fixed = (*cs.hq0)[n] == 0;
+        if (!fixed) return fail(SG_EINVAL, "internal: finest-level channel must have q0 = 0");
+      }
       const int na = (1 << a) - 1;
       const long long nspa = geo.d == 2 ? (long long)na * na : na;
       const long long cntw = (long long)cs.nq * nspa;
@@ -265,7 +273,7 @@ sg_status run_restrict(sg_problem *p, const Pass &P, const double *X, int stenci
   const double hx = p->len[0] / p->N, hy = (p->d == 2 ? p->len[1] : 1.0) / p->N;
   ra.sx = hx / 6.0;
   ra.sy = hy / 6.0;
-  ra.ch = P.d_ch;
+  std::copy(P.h_ch.begin(), P.h_ch.end(), ra.ch);
   ra.part = p->part;
   ra.coarse = g.A0 > 1 ? p->cpart : nullptr;
   if (ev_begin >= 0) MARK(p, ev_begin, s);
@@ -284,7 +292,7 @@ sg_status run_prolong(sg_problem *p, const Pass &P, const double *base, double *
   const Geometry &g = P.geo;
   ProlongArgs pa{};
   pa.g = g;
-  pa.ch = P.d_ch;
+  std::copy(P.h_ch.begin(), P.h_ch.end(), pa.ch);
   pa.coarse = nullptr;
   if (g.A0 > 1 && P.n_crs) {
     HIPCHK(launch_prolong_coarse(g, P.d_ch, p->Cpro, stencil, s));
@@ -372,19 +380,20 @@ sg_status build_solve_list(sg_problem *p, const std::vector<int> &cset, int tran
     const Comp &C = p->comps[ci];
     SolveDesc sd{};
     sd.rhs = (p->d == 2 ? p->bufS : p->bufT) + C.off;
-    sd.scratch = p->scratch + 7 * C.off;
+    sd.fac = p->fac + 5 * C.off;
+    sd.scratch = p->scratch + 2 * C.off;
     sd.nq = C.nq;
     sd.nmodes = C.nsp;
     sd.b = C.b;
     sd.a = C.a;
     // refinement sweeps against the double-double time matrices: the double
     // LU is a preconditioner whose quality drops as the time level grows
-    // (a sweep stops early once the correction is below 1e-17 of the solution)
+    // (the sweeps stop early once the correction is negligible)
     sd.refine = C.nq < p->refine_nq ? 0 : (C.nq <= 513 ? 4 : 8);
     sd.transpose = transpose;
     sd.c2 = p->c2;
     sd.thread0 = th;
-    th += C.nsp;
+    th += (C.nsp + 63) / 64 * 64;
     v.push_back(sd);
   }
   sg_status st;
@@ -580,7 +589,8 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
       !(p->bufT = p->dalloc<double>(ns)) || !(p->bufS = p->dalloc<double>(ns)) ||
       !(p->bufU = p->dalloc<double>(ns)) || !(p->bufW = p->dalloc<double>(ns)) ||
       !(p->bufY = p->dalloc<double>(ns)) ||
-      !(p->scratch = p->dalloc<double>(7 * ns)))
+      !(p->fac = p->dalloc<double>(5 * ns)) ||
+      !(p->scratch = p->dalloc<double>(2 * ns)))
     return bail(fail(SG_ENOMEM, "hipMalloc of component buffers failed"));
   p->mv_lv.assign(J + 1, nullptr);
   p->ku_lv.assign(J + 1, nullptr);
@@ -700,6 +710,9 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   }
   if ((st = build_solve_list(p, all, 0, p->sfwd))) return bail(st);
   if ((st = build_solve_list(p, all, 1, p->sadj))) return bail(st);
+  // LU factors of every mode's time matrix, shared by all later solves
+  HIPCHK(launch_time_factor(p->sfwd.d, p->sfwd.n, p->sfwd.threads, p->d_kt, p->d_mt, d,
+                            nullptr));
   p->pgx.resize(ncomp); p->pgy.resize(ncomp); p->pgiy.resize(ncomp); p->pgix.resize(ncomp);
   p->psfwd.resize(ncomp);
   p->pcload.resize(ncomp);

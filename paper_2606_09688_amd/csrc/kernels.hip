@@ -62,10 +62,20 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
   constexpr int EPT = L0 / NT;
   constexpr int UP = SH::upper;
   constexpr int KMAX = (SH::max_upper_size + NT - 1) / NT;
+  constexpr int PF = (TB * INSZ + NT - 1) / NT;   // prefetched inputs per thread
+  constexpr int NCI = 2 * (SH::LTS + 1);          // in-tile channels, li = 2 r + k
+  constexpr int NTAP = NCI * (TB + 1);            // staged tap entries per batch
   static_assert(L0 % NT == 0, "tile must be a multiple of the block");
+  static_assert(NTAP <= NT, "one thread per staged tap entry");
   __shared__ double s_in[TB * INSZ];
   __shared__ double s_lv[TB * SH::total];
   __shared__ double s_acc[2 * 3 * UP];
+  // taps of the in-tile channels for slabs nb-1 .. nb+TB-1: s_q[li][s] is
+  // q0 of slab nb-1+s (-1 outside the chunk), s_w[li][s] the weights of
+  // slab nb+s
+  __shared__ int s_q[NCI][TB + 1];
+  __shared__ double s_w[NCI][TB][3];
+  __shared__ int s_qlo[NCI];
 
   const Geometry g = A.g;
   const int tid = threadIdx.x;
@@ -80,39 +90,103 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
   const int R = g.R;
 
   for (int i = tid; i < 2 * 3 * UP; i += NT) s_acc[i] = 0.0;
+  if (tid < NCI) {
+    const int r = tid >> 1, k = tid & 1;
+    int q = 0;
+    if (r <= R) {
+      const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
+      if (C.active) q = C.q0[n0];
+    }
+    s_qlo[tid] = q;
+  }
   double racc[EPT][2][3];
 #pragma unroll
   for (int e = 0; e < EPT; ++e)
 #pragma unroll
     for (int k = 0; k < 2; ++k) racc[e][k][0] = racc[e][k][1] = racc[e][k][2] = 0.0;
 
-  const Channel *ch0 = A.ch + (g.J - 1) * 2;  // channels of level a = J
-  auto part_index = [&](const Channel &C, int r, int q) -> long long {
-    const int qlo = C.q0[n0];
+  // partial block of in-tile channel li at level offset r, time index q
+  auto part_index = [&](int li, int r, int q) -> long long {
+    const Channel &C = A.ch[(g.J - r - 1) * 2 + (li & 1)];
     return C.part_off +
-           (((long long)chunk * ntileD + tile) * C.qb + (q - qlo)) * (long long)SH::size(r);
+           (((long long)chunk * ntileD + tile) * C.qb + (q - s_qlo[li])) * (long long)SH::size(r);
   };
 
+  // tap entry staged by this thread: channel li = tid / (TB+1), slab offset
+  // my_s; its table pointers are resolved once (independent loads per batch)
+  const int my_s = tid % (TB + 1);
+  const int *my_q0 = nullptr;
+  const double *my_w = nullptr;
+  if (tid < NTAP) {
+    const int li = tid / (TB + 1), r = li >> 1;
+    if (r <= R) {
+      const Channel &C = A.ch[(g.J - r - 1) * 2 + (li & 1)];
+      if (C.active) {
+        my_q0 = C.q0;
+        my_w = C.w;
+      }
+    }
+  }
+  // register prefetch of one batch (input slabs with halo + tap entries)
+  double pin[PF];
+  int pq = -1;
+  double pw0 = 0.0, pw1 = 0.0, pw2 = 0.0;
+  auto fetch = [&](int nb) {
+    const int cnt = min(TB, n1 - nb);
+#pragma unroll
+    for (int e = 0; e < PF; ++e) {
+      const int idx = tid + e * NT;
+      double v = 0.0;
+      if (idx < cnt * INSZ) {
+        const int s = idx / INSZ, loc = idx - s * INSZ;
+        const int ix = loc % NIN, iy = loc / NIN;
+        const int px = TS * tx - 1 + ix;
+        const int py = TS * ty - 1 + iy;
+        if (interior(px, g.nxf) && (D == 1 || interior(py, g.nxf))) {
+          long long off = (long long)(nb + s) * nsp + (px - 1);
+          if (D == 2) off += (long long)(py - 1) * g.nxf;
+          v = A.X[off];
+        }
+      }
+      pin[e] = v;
+    }
+    pq = -1;
+    pw0 = pw1 = pw2 = 0.0;
+    const int n = nb - 1 + my_s;
+    if (my_q0 != nullptr && n >= n0 && n < n1) {
+      pq = my_q0[n];
+      if (my_s > 0) {
+        pw0 = my_w[3 * n];
+        pw1 = my_w[3 * n + 1];
+        pw2 = my_w[3 * n + 2];
+      }
+    }
+  };
+
+  fetch(n0);
+  int last_cnt = 0;
   for (int nb = n0; nb < n1; nb += TB) {
     const int cnt = min(TB, n1 - nb);
-    // (1) input slabs with a one-node halo (zero outside the interior)
-    for (int idx = tid; idx < cnt * INSZ; idx += NT) {
-      const int s = idx / INSZ, loc = idx - s * INSZ;
-      const int ix = loc % NIN, iy = loc / NIN;
-      const int px = TS * tx - 1 + ix;
-      const int py = TS * ty - 1 + iy;
-      double v = 0.0;
-      if (interior(px, g.nxf) && (D == 1 || interior(py, g.nxf))) {
-        long long off = (long long)(nb + s) * nsp + (px - 1);
-        if (D == 2) off += (long long)(py - 1) * g.nxf;
-        v = A.X[off];
+    last_cnt = cnt;
+    // (1) staged batch -> LDS, then start fetching the next batch
+#pragma unroll
+    for (int e = 0; e < PF; ++e) {
+      const int idx = tid + e * NT;
+      if (idx < TB * INSZ) s_in[idx] = pin[e];
+    }
+    if (tid < NTAP) {
+      const int li = tid / (TB + 1), s = tid - li * (TB + 1);
+      s_q[li][s] = pq;
+      if (s > 0) {
+        s_w[li][s - 1][0] = pw0;
+        s_w[li][s - 1][1] = pw1;
+        s_w[li][s - 1][2] = pw2;
       }
-      s_in[idx] = v;
     }
     __syncthreads();
+    if (nb + TB < n1) fetch(nb + TB);
     // (2) level 0 (fine nodes, optional mass stencil) and its accumulation
     for (int s = 0; s < cnt; ++s) {
-      const int n = nb + s;
       const double *in = s_in + s * INSZ;
       double val[EPT];
 #pragma unroll
@@ -141,23 +215,19 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
       }
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
-        const Channel &C = ch0[k];
-        if (!C.active) continue;
-        const int q0n = C.q0[n];
-        if (n > n0) {
-          const int qp = C.q0[n - 1];
-          if (q0n > qp) {
-            const long long base = part_index(C, 0, qp);
+        if (!A.ch[(g.J - 1) * 2 + k].active) continue;
+        const int q0n = s_q[k][s + 1], qp = s_q[k][s];
+        if (qp >= 0 && q0n > qp) {
+          const long long base = part_index(k, 0, qp);
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-              A.part[base + tid + e * NT] = racc[e][k][0];
-              racc[e][k][0] = racc[e][k][1];
-              racc[e][k][1] = racc[e][k][2];
-              racc[e][k][2] = 0.0;
-            }
+          for (int e = 0; e < EPT; ++e) {
+            A.part[base + tid + e * NT] = racc[e][k][0];
+            racc[e][k][0] = racc[e][k][1];
+            racc[e][k][1] = racc[e][k][2];
+            racc[e][k][2] = 0.0;
           }
         }
-        const double w0 = C.w[3 * n], w1 = C.w[3 * n + 1], w2 = C.w[3 * n + 2];
+        const double w0 = s_w[k][s][0], w1 = s_w[k][s][1], w2 = s_w[k][s][2];
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
           racc[e][k][0] += w0 * val[e];
@@ -205,32 +275,27 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
     }
     // (4) accumulate levels r >= 1 into their time nodes (ring of 3 slots)
     for (int r = 1; r <= R; ++r) {
-      const int a = g.J - r;
       const int sz = SH::size(r);
       const int aoff = SH::offset(r) - SH::size(0);
       for (int k = 0; k < 2; ++k) {
-        const Channel &C = A.ch[(a - 1) * 2 + k];
-        if (!C.active) continue;
+        const int li = 2 * r + k;
+        if (!A.ch[(g.J - r - 1) * 2 + k].active) continue;
         double *acc = s_acc + (size_t)k * 3 * UP + aoff;
         for (int s = 0; s < cnt; ++s) {
-          const int n = nb + s;
-          const int q0n = C.q0[n];
-          if (n > n0) {
-            const int qp = C.q0[n - 1];
-            if (q0n > qp) {
-              const long long base = part_index(C, r, qp);
-              double *sl = acc + (qp % 3) * UP;
+          const int q0n = s_q[li][s + 1], qp = s_q[li][s];
+          if (qp >= 0 && q0n > qp) {
+            const long long base = part_index(li, r, qp);
+            double *sl = acc + (qp % 3) * UP;
 #pragma unroll
-              for (int kk = 0; kk < KMAX; ++kk) {
-                const int j = tid + kk * NT;
-                if (j < sz) {
-                  A.part[base + j] = sl[j];
-                  sl[j] = 0.0;
-                }
+            for (int kk = 0; kk < KMAX; ++kk) {
+              const int j = tid + kk * NT;
+              if (j < sz) {
+                A.part[base + j] = sl[j];
+                sl[j] = 0.0;
               }
             }
           }
-          const double w0 = C.w[3 * n], w1 = C.w[3 * n + 1], w2 = C.w[3 * n + 2];
+          const double w0 = s_w[li][s][0], w1 = s_w[li][s][1], w2 = s_w[li][s][2];
           double *a0 = acc + (q0n % 3) * UP;
           double *a1 = acc + ((q0n + 1) % 3) * UP;
           double *a2 = acc + ((q0n + 2) % 3) * UP;
@@ -257,31 +322,31 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
     }
     __syncthreads();
   }
-  // final flush of the open time nodes
+  // final flush of the open time nodes (s_q still holds the last batch)
   for (int k = 0; k < 2; ++k) {
-    const Channel &C = ch0[k];
+    const Channel &C = A.ch[(g.J - 1) * 2 + k];
     if (!C.active) continue;
-    const int ql = C.q0[n1 - 1];
+    const int ql = s_q[k][last_cnt];
 #pragma unroll
     for (int o = 0; o < 3; ++o) {
       if (ql + o >= C.nq) break;
-      const long long base = part_index(C, 0, ql + o);
+      const long long base = part_index(k, 0, ql + o);
 #pragma unroll
       for (int e = 0; e < EPT; ++e) A.part[base + tid + e * NT] = racc[e][k][o];
     }
   }
   for (int r = 1; r <= R; ++r) {
-    const int a = g.J - r;
     const int sz = SH::size(r);
     const int aoff = SH::offset(r) - SH::size(0);
     for (int k = 0; k < 2; ++k) {
-      const Channel &C = A.ch[(a - 1) * 2 + k];
+      const int li = 2 * r + k;
+      const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
       if (!C.active) continue;
-      const int ql = C.q0[n1 - 1];
+      const int ql = s_q[li][last_cnt];
       for (int o = 0; o < 3; ++o) {
         const int q = ql + o;
         if (q >= C.nq) break;
-        const long long base = part_index(C, r, q);
+        const long long base = part_index(li, r, q);
         const double *sl = s_acc + (size_t)k * 3 * UP + aoff + (q % 3) * UP;
         for (int kk = 0; kk < KMAX; ++kk) {
           const int j = tid + kk * NT;
@@ -501,10 +566,21 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
   constexpr int NO = ipow(TS, D);          // output points per slab
   constexpr int EPTO = NO / NT;
   constexpr int NF = TS + 2 * MODE;
+  constexpr int RS = TB + 2;               // coefficient ring slots per channel
+  constexpr int NCI = 2 * (SH::LTS + 1);   // in-tile channels, li = 2 r + k
+  constexpr int NTAP = NCI * (TB + 1);
   static_assert(NO % NT == 0, "tile must be a multiple of the block");
+  static_assert(NTAP <= NT, "one thread per staged tap entry");
   __shared__ double s_v[TB * UP];
-  __shared__ double s_coef[2 * 3 * UP];
+  __shared__ double s_coef[2 * RS * UP];
   __shared__ double s_f[MODE ? TB * L0 : 1];
+  __shared__ int s_q[NCI][TB + 1];         // q0 of slabs nb-1 .. nb+TB-1 (-1: none)
+  __shared__ double s_w[NCI][TB][3];       // weights of slabs nb .. nb+TB-1
+  // coarse-level values (levels a < A0, already summed) at the in-tile
+  // level-A0 nodes of the batch; used only when A0 > 1, and then R = LTS
+  constexpr int SZR = SH::size(SH::LTS);
+  static_assert(NTAP + TB * SZR <= NT, "coarse staging threads follow the tap threads");
+  __shared__ double s_co[TB * SZR];
 
   const Geometry g = A.g;
   const int tid = threadIdx.x;
@@ -516,7 +592,6 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
   const int n1 = min(n0 + g.chunk, g.ntf);
   const long long nsp = (D == 2) ? (long long)g.nxf * g.nxf : g.nxf;
   const int R = g.R;
-  const Channel *ch0 = A.ch + (g.J - 1) * 2;
 
   // coefficient of channel C at time index q for the node with global
   // positions (Px, Py) of its level (zero outside the interior)
@@ -538,47 +613,138 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
   for (int e = 0; e < EPT0; ++e) {
     basev[e] = 0.0;
     const int p = tid + e * NT;
-    if (p < L0 && A.base != nullptr) {
+    if (!MODE && p < L0 && A.base != nullptr) {
       const int Px = lo0x + p % NF, Py = (D == 2) ? lo0y + p / NF : 0;
       if (interior(Px, g.nxf) && (D == 1 || interior(Py, g.nxf)))
         basev[e] = A.base[(D == 2 ? (long long)(Py - 1) * g.nxf : 0) + (Px - 1)];
     }
   }
 
+  // tap entry staged by this thread (see k_restrict)
+  const int my_s = tid % (TB + 1);
+  const int *my_q0 = nullptr;
+  const double *my_w = nullptr;
+  if (tid < NTAP) {
+    const int li = tid / (TB + 1), r = li >> 1;
+    if (r <= R) {
+      const Channel &C = A.ch[(g.J - r - 1) * 2 + (li & 1)];
+      if (C.active) {
+        my_q0 = C.q0;
+        my_w = C.w;
+      }
+    }
+  }
+  // tap entries and coarse values of the next batch, prefetched in registers
+  int pq = -1;
+  double pw0 = 0.0, pw1 = 0.0, pw2 = 0.0, pco = 0.0;
+  const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
+  const int co_i = tid - NTAP;  // coarse entry staged by this thread (if >= 0)
+  auto fetch_taps = [&](int nb) {
+    pq = -1;
+    pw0 = pw1 = pw2 = 0.0;
+    const int n = nb - 1 + my_s;
+    if (my_q0 != nullptr && n >= n0 && n < n1) {
+      pq = my_q0[n];
+      if (my_s > 0) {
+        pw0 = my_w[3 * n];
+        pw1 = my_w[3 * n + 1];
+        pw2 = my_w[3 * n + 2];
+      }
+    }
+    pco = 0.0;
+    if (use_coarse && co_i >= 0 && co_i < TB * SZR) {
+      const int s = co_i / SZR, j = co_i - s * SZR;
+      constexpr int nrR = SH::nodes(SH::LTS);
+      const int Px = tile_lo(TS, tx, SH::LTS, MODE) + j % nrR;
+      const int Py = (D == 2) ? tile_lo(TS, ty, SH::LTS, MODE) + j / nrR : 0;
+      const int n0a = (1 << g.A0) - 1;
+      if (nb + s < n1 && interior(Px, n0a) && (D == 1 || interior(Py, n0a))) {
+        const long long nsp0 = (D == 2) ? (long long)n0a * n0a : n0a;
+        pco = A.coarse[(long long)(nb + s) * nsp0 +
+                       (D == 2 ? (long long)(Py - 1) * n0a : 0) + (Px - 1)];
+      }
+    }
+  };
+  // level-J channels belong to time level b = 1 (q0 = 0 on every slab), so
+  // their coefficient window is loaded once
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const Channel &C = A.ch[(g.J - 1) * 2 + k];
+    if (!C.active) continue;
+#pragma unroll
+    for (int e = 0; e < EPT0; ++e) {
+      const int p = tid + e * NT;
+      if (p >= L0) continue;
+      const int Px = lo0x + p % NF, Py = (D == 2) ? lo0y + p / NF : 0;
+      rc[e][k][0] = coef(C, 0, Px, Py);
+      rc[e][k][1] = coef(C, 1, Px, Py);
+      rc[e][k][2] = coef(C, 2, Px, Py);
+    }
+  }
+
+  fetch_taps(n0);
   for (int nb = n0; nb < n1; nb += TB) {
     const int cnt = min(TB, n1 - nb);
-    // phase A: owners evaluate every level r >= 1 in time (ring of 3 coefficients)
+    if (tid < NTAP) {
+      const int li = tid / (TB + 1), s = tid - li * (TB + 1);
+      s_q[li][s] = pq;
+      if (s > 0) {
+        s_w[li][s - 1][0] = pw0;
+        s_w[li][s - 1][1] = pw1;
+        s_w[li][s - 1][2] = pw2;
+      }
+    } else if (co_i < TB * SZR) {
+      s_co[co_i] = pco;
+    }
+    __syncthreads();
+    if (nb + TB < n1) fetch_taps(nb + TB);
+    // phase A: owners evaluate every level r >= 1 in time.  The coefficients
+    // a batch needs beyond those already in the ring are gathered first (all
+    // loads of one level in flight together), then the slabs are evaluated.
     for (int r = 1; r <= R; ++r) {
-      const int a = g.J - r, nr = SH::nodes(r), sz = SH::size(r);
+      const int nr = SH::nodes(r), sz = SH::size(r);
       const int aoff = SH::offset(r) - SH::size(0);
       const int lox = tile_lo(TS, tx, r, MODE), loy = tile_lo(TS, ty, r, MODE);
       for (int s = 0; s < cnt; ++s)
+#pragma unroll
         for (int kk = 0; kk < KMAX; ++kk) {
           const int j = tid + kk * NT;
           if (j < sz) s_v[s * UP + aoff + j] = 0.0;
         }
       for (int k = 0; k < 2; ++k) {
-        const Channel &C = A.ch[(a - 1) * 2 + k];
+        const int li = 2 * r + k;
+        const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
         if (!C.active) continue;
-        double *ring = s_coef + (size_t)k * 3 * UP + aoff;
+        double *ring = s_coef + (size_t)k * RS * UP + aoff;
+        const int qhi = s_q[li][cnt] + 2;
+        const int qnew = s_q[li][0] >= 0 ? s_q[li][0] + 3 : s_q[li][1];
+        double cv[RS][KMAX];
+#pragma unroll
+        for (int o = 0; o < RS; ++o)
+#pragma unroll
+          for (int kk = 0; kk < KMAX; ++kk) {
+            const int j = tid + kk * NT, q = qnew + o;
+            cv[o][kk] = (q <= qhi && j < sz)
+                            ? coef(C, q, lox + j % nr, (D == 2) ? loy + j / nr : 0)
+                            : 0.0;
+          }
+#pragma unroll
+        for (int o = 0; o < RS; ++o)
+#pragma unroll
+          for (int kk = 0; kk < KMAX; ++kk) {
+            const int j = tid + kk * NT, q = qnew + o;
+            if (q <= qhi && j < sz) ring[(q % RS) * UP + j] = cv[o][kk];
+          }
         for (int s = 0; s < cnt; ++s) {
-          const int n = nb + s;
-          const int q0n = C.q0[n];
-          const bool first = (n == n0);
-          const bool adv = !first && q0n > C.q0[n - 1];
+          const int q0n = s_q[li][s + 1];
+          const double w0 = s_w[li][s][0], w1 = s_w[li][s][1], w2 = s_w[li][s][2];
+          const double *c0 = ring + (q0n % RS) * UP;
+          const double *c1 = ring + ((q0n + 1) % RS) * UP;
+          const double *c2 = ring + ((q0n + 2) % RS) * UP;
+#pragma unroll
           for (int kk = 0; kk < KMAX; ++kk) {
             const int j = tid + kk * NT;
-            if (j >= sz) continue;
-            const int Px = lox + j % nr, Py = (D == 2) ? loy + j / nr : 0;
-            if (first) {
-              for (int o = 0; o < 3; ++o) ring[((q0n + o) % 3) * UP + j] = coef(C, q0n + o, Px, Py);
-            } else if (adv) {
-              ring[((q0n + 2) % 3) * UP + j] = coef(C, q0n + 2, Px, Py);
-            }
-            const double v = C.w[3 * n] * ring[(q0n % 3) * UP + j] +
-                             C.w[3 * n + 1] * ring[((q0n + 1) % 3) * UP + j] +
-                             C.w[3 * n + 2] * ring[((q0n + 2) % 3) * UP + j];
-            s_v[s * UP + aoff + j] += C.scale * v;
+            if (j < sz) s_v[s * UP + aoff + j] += C.scale * (w0 * c0[j] + w1 * c1[j] + w2 * c2[j]);
           }
         }
       }
@@ -594,14 +760,7 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
         const int Px = lox + j % nr, Py = (D == 2) ? loy + j / nr : 0;
         double base = 0.0;
         if (r == R) {
-          if (g.A0 > 1 && A.coarse != nullptr) {
-            const int n0a = (1 << g.A0) - 1;
-            if (interior(Px, n0a) && (D == 1 || interior(Py, n0a))) {
-              const long long nsp0 = (D == 2) ? (long long)n0a * n0a : n0a;
-              base = A.coarse[(long long)(nb + s) * nsp0 +
-                              (D == 2 ? (long long)(Py - 1) * n0a : 0) + (Px - 1)];
-            }
-          }
+          if (use_coarse) base = s_co[s * SZR + j];
         } else {
           const int pn = SH::nodes(r + 1);
           const int paoff = SH::offset(r + 1) - SH::size(0);
@@ -628,28 +787,12 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
       for (int e = 0; e < EPT0; ++e) tv[e] = 0.0;
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
-        const Channel &C = ch0[k];
+        const Channel &C = A.ch[(g.J - 1) * 2 + k];
         if (!C.active) continue;
-        const int q0n = C.q0[n];
-        const bool first = (n == n0);
-        const bool adv = !first && q0n > C.q0[n - 1];
+        const double w0 = s_w[k][s][0], w1 = s_w[k][s][1], w2 = s_w[k][s][2];
 #pragma unroll
-        for (int e = 0; e < EPT0; ++e) {
-          const int p = tid + e * NT;
-          if (p >= L0) continue;
-          const int Px = lo0x + p % NF, Py = (D == 2) ? lo0y + p / NF : 0;
-          if (first) {
-            rc[e][k][0] = coef(C, q0n, Px, Py);
-            rc[e][k][1] = coef(C, q0n + 1, Px, Py);
-            rc[e][k][2] = coef(C, q0n + 2, Px, Py);
-          } else if (adv) {
-            rc[e][k][0] = rc[e][k][1];
-            rc[e][k][1] = rc[e][k][2];
-            rc[e][k][2] = coef(C, q0n + 2, Px, Py);
-          }
-          tv[e] += C.scale * (C.w[3 * n] * rc[e][k][0] + C.w[3 * n + 1] * rc[e][k][1] +
-                              C.w[3 * n + 2] * rc[e][k][2]);
-        }
+        for (int e = 0; e < EPT0; ++e)
+          tv[e] += C.scale * (w0 * rc[e][k][0] + w1 * rc[e][k][1] + w2 * rc[e][k][2]);
       }
 #pragma unroll
       for (int e = 0; e < EPT0; ++e) {
@@ -669,8 +812,6 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
             v += 0.25 * (par[yl * pn + xl] + par[yl * pn + xh] + par[yh * pn + xl] +
                          par[yh * pn + xh]);
           }
-        } else if (g.A0 > 1 && A.coarse != nullptr) {
-          // not reachable: R = 0 only when J = 1 (no coarse levels)
         }
         const bool in = interior(Px, g.nxf) && (D == 1 || interior(Py, g.nxf));
         if (MODE) {
@@ -935,22 +1076,28 @@ __device__ __forceinline__ dd triple(double p, double q, double x) {
 // One thread per spatial mode: (m A_b + kappa B_b) u = r, or its transpose.
 // E = m A_b + kappa B_b is factored E = L U without pivoting in causal
 // (increasing time) order - the symmetric parts of A_b and B_b are positive
-// definite (Prop. 1).  The transposed (adjoint) system uses the same factors,
-// E^T = U^T L^T, which keeps the elimination causal for the backward-in-time
-// adjoint.  The solution is refined against the double-double time matrices.
-__global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__ sds,
-                                                   int nsd, long long total,
-                                                   const KernelTables *__restrict__ kt,
-                                                   const ModeTables *__restrict__ mt, int d) {
-  const long long gid = gid64();
-  if (gid >= total) return;
-  int di = 0;
-  while (di + 1 < nsd && sds[di + 1].thread0 <= gid) ++di;
-  const SolveDesc &S = sds[di];
-  const int j = (int)(gid - S.thread0);
-  const int a = S.a, b = S.b, nq = S.nq, nm = S.nmodes;
-  const int na = (1 << a) - 1;
-  double m, kap;
+// definite (Prop. 1).  The factors depend only on (m, kappa, b) and are
+// computed once when the plan is built.  The transposed (adjoint) system uses
+// the same factors, E^T = U^T L^T, which keeps the elimination causal for the
+// backward-in-time adjoint.  The solution is refined against the
+// double-double time matrices.
+//
+// Every descriptor starts at a multiple of 64 threads and blocks are one wave,
+// so the descriptor, its tables and the time level are wave-uniform.
+
+__device__ __forceinline__ int find_solve(const SolveDesc *sds, int nsd, long long wbase) {
+  int lo = 0, hi = nsd - 1;  // last descriptor with thread0 <= wbase
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sds[mid].thread0 <= wbase) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void mode_scalars(const SolveDesc &S, int j,
+                                             const ModeTables *mt, int d, double &m,
+                                             double &kap) {
+  const int a = S.a, na = (1 << a) - 1;
   if (d == 1) {
     m = mt->mx[a][j];
     kap = S.c2 * mt->kx[a][j];
@@ -959,118 +1106,224 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
     m = mt->my[a][jy] * mt->mx[a][jx];
     kap = S.c2 * (mt->ky[a][jy] * mt->mx[a][jx] + mt->my[a][jy] * mt->kx[a][jx]);
   }
-  const double *Ab = kt->A[b], *Bb = kt->B[b], *Al = kt->Alo[b], *Bl = kt->Blo[b];
-  const bool tr = S.transpose != 0;
-  // entry (i, i+off) of E (band storage [row][off+2])
+}
+
+__global__ void __launch_bounds__(64) k_time_factor(const SolveDesc *__restrict__ sds,
+                                                    int nsd, long long total,
+                                                    const KernelTables *__restrict__ kt,
+                                                    const ModeTables *__restrict__ mt, int d) {
+  const long long wbase = (long long)blockIdx.x * 64;
+  const SolveDesc &S = sds[find_solve(sds, nsd, wbase)];
+  const long long gid = wbase + threadIdx.x;
+  const int j = (int)(gid - S.thread0);
+  if (gid >= total || j >= S.nmodes) return;
+  const int b = S.b, nq = S.nq, nm = S.nmodes;
+  double m, kap;
+  mode_scalars(S, j, mt, d, m, kap);
+  const double *Ab = kt->A[b], *Bb = kt->B[b];
   auto ent = [&](int i, int off) -> double {
     const int jj = i + off;
     if (jj < 0 || jj >= nq) return 0.0;
     return m * Ab[i * 5 + off + 2] + kap * Bb[i * 5 + off + 2];
   };
+  const long long plane = (long long)nq * nm;
+  double *L1 = S.fac, *L2 = L1 + plane, *UD = L2 + plane, *U1 = UD + plane, *U2 = U1 + plane;
+  double dm2 = 1.0, u1m2 = 0.0, u2m2 = 0.0;
+  double dm1 = 1.0, u1m1 = 0.0, u2m1 = 0.0;
+  for (int i = 0; i < nq; ++i) {
+    const long long o = (long long)i * nm + j;
+    double am2 = ent(i, -2), am1 = ent(i, -1), a0 = ent(i, 0), ap1 = ent(i, 1),
+           ap2 = ent(i, 2);
+    const double l2 = (i >= 2) ? am2 / dm2 : 0.0;
+    am1 -= l2 * u1m2;
+    a0 -= l2 * u2m2;
+    const double l1 = (i >= 1) ? am1 / dm1 : 0.0;
+    a0 -= l1 * u1m1;
+    ap1 -= l1 * u2m1;
+    L1[o] = l1;
+    L2[o] = l2;
+    UD[o] = 1.0 / a0;
+    U1[o] = ap1;
+    U2[o] = ap2;
+    dm2 = dm1; u1m2 = u1m1; u2m2 = u2m1;
+    dm1 = a0; u1m1 = ap1; u2m1 = ap2;
+  }
+}
+
+__global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__ sds,
+                                                   int nsd, long long total,
+                                                   const KernelTables *__restrict__ kt,
+                                                   const ModeTables *__restrict__ mt, int d) {
+  constexpr int CH = 16;  // rows per register chunk of a substitution
+  constexpr int CR = 8;   // rows per register chunk of the residual
+  const long long wbase = (long long)blockIdx.x * 64;
+  const SolveDesc &S = sds[find_solve(sds, nsd, wbase)];
+  const long long gid = wbase + threadIdx.x;
+  const int j = (int)(gid - S.thread0);
+  if (gid >= total || j >= S.nmodes) return;
+  const int b = S.b, nq = S.nq, nm = S.nmodes;
+  double m, kap;
+  mode_scalars(S, j, mt, d, m, kap);
+  const double *Ab = kt->A[b], *Bb = kt->B[b], *Al = kt->Alo[b], *Bl = kt->Blo[b];
+  const bool tr = S.transpose != 0;
   double *rhs = S.rhs;
   const long long plane = (long long)nq * nm;
-  double *L1 = S.scratch, *L2 = L1 + plane, *UD = L2 + plane, *U1 = UD + plane,
-         *U2 = U1 + plane, *Y = U2 + plane, *B0 = Y + plane;
-  // factor E = L U
-  {
-    double dm2 = 1.0, u1m2 = 0.0, u2m2 = 0.0;
-    double dm1 = 1.0, u1m1 = 0.0, u2m1 = 0.0;
-    for (int i = 0; i < nq; ++i) {
-      const long long o = (long long)i * nm + j;
-      double am2 = ent(i, -2), am1 = ent(i, -1), a0 = ent(i, 0), ap1 = ent(i, 1),
-             ap2 = ent(i, 2);
-      const double l2 = (i >= 2) ? am2 / dm2 : 0.0;
-      am1 -= l2 * u1m2;
-      a0 -= l2 * u2m2;
-      const double l1 = (i >= 1) ? am1 / dm1 : 0.0;
-      a0 -= l1 * u1m1;
-      ap1 -= l1 * u2m1;
-      L1[o] = l1;
-      L2[o] = l2;
-      UD[o] = 1.0 / a0;
-      U1[o] = ap1;
-      U2[o] = ap2;
-      dm2 = dm1; u1m2 = u1m1; u2m2 = u2m1;
-      dm1 = a0; u1m1 = ap1; u2m1 = ap2;
-    }
-  }
-  auto at = [&](const double *P, int i) -> double {
-    return (i >= 0 && i < nq) ? P[(long long)i * nm + j] : 0.0;
-  };
-  // x <- op(E)^{-1} r: r read from R (R may be Y: each entry is read before
-  // it is overwritten), result added (add) or stored into rhs; returns max|x|
+  const double *L1 = S.fac, *L2 = L1 + plane, *UD = L2 + plane, *U1 = UD + plane,
+               *U2 = U1 + plane;
+  double *Y = S.scratch, *B0 = Y + plane;
+  auto idx = [&](int i) -> long long { return (long long)i * nm + j; };
+
+  // x <- op(E)^{-1} r, r read from R (R may be Y: a chunk is read before it is
+  // written), result added to (add) or stored into rhs; returns max |x|
   auto apply_inverse = [&](const double *R, bool add) -> double {
     double xm = 0.0;
     if (!tr) {
+      // L y = r (forward)
       double ym2 = 0.0, ym1 = 0.0;
-      for (int i = 0; i < nq; ++i) {
-        const long long o = (long long)i * nm + j;
-        const double y = R[o] - L2[o] * ym2 - L1[o] * ym1;
-        Y[o] = y;
-        ym2 = ym1;
-        ym1 = y;
+      for (int i0 = 0; i0 < nq; i0 += CH) {
+        double rr[CH], l1[CH], l2[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int i = i0 + k;
+          if (i < nq) {
+            rr[k] = R[idx(i)];
+            l1[k] = L1[idx(i)];
+            l2[k] = L2[idx(i)];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int i = i0 + k;
+          if (i < nq) {
+            const double y = rr[k] - l2[k] * ym2 - l1[k] * ym1;
+            Y[idx(i)] = y;
+            ym2 = ym1;
+            ym1 = y;
+          }
+        }
       }
+      // U x = y (backward)
       double xp1 = 0.0, xp2 = 0.0;
-      for (int i = nq - 1; i >= 0; --i) {
-        const long long o = (long long)i * nm + j;
-        const double x = (Y[o] - U1[o] * xp1 - U2[o] * xp2) * UD[o];
-        rhs[o] = add ? rhs[o] + x : x;
-        xm = fmax(xm, fabs(x));
-        xp2 = xp1;
-        xp1 = x;
+      for (int i1 = nq - 1; i1 >= 0; i1 -= CH) {
+        double yy[CH], u1[CH], u2[CH], ud[CH], old[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int i = i1 - k;
+          if (i >= 0) {
+            yy[k] = Y[idx(i)];
+            u1[k] = U1[idx(i)];
+            u2[k] = U2[idx(i)];
+            ud[k] = UD[idx(i)];
+            old[k] = add ? rhs[idx(i)] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int i = i1 - k;
+          if (i >= 0) {
+            const double x = (yy[k] - u1[k] * xp1 - u2[k] * xp2) * ud[k];
+            rhs[idx(i)] = add ? old[k] + x : x;
+            xm = fmax(xm, fabs(x));
+            xp2 = xp1;
+            xp1 = x;
+          }
+        }
       }
     } else {
-      // U^T w = r (forward), then L^T z = w (backward)
+      // U^T w = r (forward)
       double wm2 = 0.0, wm1 = 0.0;
-      for (int i = 0; i < nq; ++i) {
-        const long long o = (long long)i * nm + j;
-        const double w = (R[o] - at(U1, i - 1) * wm1 - at(U2, i - 2) * wm2) * UD[o];
-        Y[o] = w;
-        wm2 = wm1;
-        wm1 = w;
+      for (int i0 = 0; i0 < nq; i0 += CH) {
+        double rr[CH], u1[CH], u2[CH], ud[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int i = i0 + k;
+          if (i < nq) {
+            rr[k] = R[idx(i)];
+            u1[k] = i >= 1 ? U1[idx(i - 1)] : 0.0;
+            u2[k] = i >= 2 ? U2[idx(i - 2)] : 0.0;
+            ud[k] = UD[idx(i)];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int i = i0 + k;
+          if (i < nq) {
+            const double w = (rr[k] - u1[k] * wm1 - u2[k] * wm2) * ud[k];
+            Y[idx(i)] = w;
+            wm2 = wm1;
+            wm1 = w;
+          }
+        }
       }
+      // L^T z = w (backward)
       double zp1 = 0.0, zp2 = 0.0;
-      for (int i = nq - 1; i >= 0; --i) {
-        const long long o = (long long)i * nm + j;
-        const double z = Y[o] - at(L1, i + 1) * zp1 - at(L2, i + 2) * zp2;
-        rhs[o] = add ? rhs[o] + z : z;
-        xm = fmax(xm, fabs(z));
-        zp2 = zp1;
-        zp1 = z;
+      for (int i1 = nq - 1; i1 >= 0; i1 -= CH) {
+        double yy[CH], l1[CH], l2[CH], old[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int i = i1 - k;
+          if (i >= 0) {
+            yy[k] = Y[idx(i)];
+            l1[k] = i + 1 < nq ? L1[idx(i + 1)] : 0.0;
+            l2[k] = i + 2 < nq ? L2[idx(i + 2)] : 0.0;
+            old[k] = add ? rhs[idx(i)] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int i = i1 - k;
+          if (i >= 0) {
+            const double z = yy[k] - l1[k] * zp1 - l2[k] * zp2;
+            rhs[idx(i)] = add ? old[k] + z : z;
+            xm = fmax(xm, fabs(z));
+            zp2 = zp1;
+            zp1 = z;
+          }
+        }
       }
     }
     return xm;
   };
   if (S.refine)
-    for (int i = 0; i < nq; ++i) B0[(long long)i * nm + j] = rhs[(long long)i * nm + j];
+    for (int i = 0; i < nq; ++i) B0[idx(i)] = rhs[idx(i)];
   apply_inverse(rhs, false);
-  if (!S.refine) return;
   // refinement: r = b - op(E) x with E from the double-double time matrices,
-  // accumulated in double-double, then x += op(E)^{-1} r
+  // accumulated in double-double, then x += op(E)^{-1} r; stop once the
+  // correction is below 1e-15 of the solution (the next one would be below
+  // the rounding of x itself)
   for (int it = 0; it < S.refine; ++it) {
 #pragma clang fp contract(off)
     double xmax = 0.0;
-    for (int i = 0; i < nq; ++i) {
-      const long long o = (long long)i * nm + j;
-      dd acc = {B0[o], 0.0};
-      for (int off = -2; off <= 2; ++off) {
-        const int jj = i + off;
-        if (jj < 0 || jj >= nq) continue;
-        // op(E)[i][jj] = E[i][jj] (or E[jj][i] for the transpose)
-        const int r = tr ? jj : i, c = tr ? 2 - off : off + 2;
-        const double x = rhs[(long long)jj * nm + j];
-        dd t1 = triple(m, Ab[r * 5 + c], x);
-        dd t2 = triple(kap, Bb[r * 5 + c], x);
-        t1.l = fma(m * Al[r * 5 + c], x, t1.l);
-        t2.l = fma(kap * Bl[r * 5 + c], x, t2.l);
-        acc = dd_add(acc, {-t1.h, -t1.l});
-        acc = dd_add(acc, {-t2.h, -t2.l});
+    for (int i0 = 0; i0 < nq; i0 += CR) {
+      double res[CR];
+#pragma unroll
+      for (int k = 0; k < CR; ++k) {
+        const int i = i0 + k;
+        if (i >= nq) continue;
+        dd acc = {B0[idx(i)], 0.0};
+#pragma unroll
+        for (int off = -2; off <= 2; ++off) {
+          const int jj = i + off;
+          if (jj < 0 || jj >= nq) continue;
+          // op(E)[i][jj] = E[i][jj] (or E[jj][i] for the transpose)
+          const int r = tr ? jj : i, c = tr ? 2 - off : off + 2;
+          const double x = rhs[idx(jj)];
+          if (off == 0) xmax = fmax(xmax, fabs(x));
+          dd t1 = triple(m, Ab[r * 5 + c], x);
+          dd t2 = triple(kap, Bb[r * 5 + c], x);
+          t1.l = fma(m * Al[r * 5 + c], x, t1.l);
+          t2.l = fma(kap * Bl[r * 5 + c], x, t2.l);
+          acc = dd_add(acc, {-t1.h, -t1.l});
+          acc = dd_add(acc, {-t2.h, -t2.l});
+        }
+        res[k] = acc.h + acc.l;
       }
-      Y[o] = acc.h + acc.l;  // residual, consumed in place by apply_inverse
-      xmax = fmax(xmax, fabs(rhs[o]));
+#pragma unroll
+      for (int k = 0; k < CR; ++k)
+        if (i0 + k < nq) Y[idx(i0 + k)] = res[k];
     }
     const double dmax = apply_inverse(Y, true);
-    if (dmax <= 1e-17 * xmax) break;
+    if (dmax <= 1e-15 * xmax) break;
   }
 }
 
@@ -1207,6 +1460,15 @@ hipError_t launch_adjoint_fields(const LevelDesc *ld, int nlev, long long total,
 hipError_t launch_gemm(const GemmDesc *descs, int ndesc, int total_tiles, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gemm, dim3(total_tiles), dim3(256), 0, s, descs, ndesc);
+  return hipGetLastError();
+}
+
+hipError_t launch_time_factor(const SolveDesc *sd, int nsd, long long total,
+                              const KernelTables *kt, const ModeTables *mt, int d,
+                              hipStream_t s) {
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_time_factor, dim3(blocks_for(total, 64)), dim3(64), 0, s, sd, nsd,
+                     total, kt, mt, d);
   return hipGetLastError();
 }
 

@@ -7,6 +7,10 @@
 
 namespace sg {
 
+// Channel table passed by value (kernel argument segment): the streaming
+// kernels read it through scalar loads that cannot alias their stores.
+constexpr int kChanMax = 2 * kMaxLevels;
+
 // ---- fine-grid streaming restriction ------------------------------------
 // Z_c[q][K] = sum_n sum_m w_c(n,q) phi^a_K(x_m) (S X_n)[m] for every active
 // channel c, S = identity or the fine mass matrix (stencil = 1).
@@ -15,22 +19,22 @@ struct RestrictArgs {
   const double *X;       // [ntf][nxf^d]
   int stencil;           // 0 identity, 1 mass
   double sx, sy;         // h_x/6, h_y/6 of the finest mesh
-  const Channel *ch;     // [2*J]
   double *part;          // partial blocks of the in-tile levels
   double *coarse;        // per-slab partials at level A0 (if A0 > 1)
+  Channel ch[kChanMax];  // channel (a-1)*2+k, entries >= 2J unused
 };
 
 // ---- fine-grid streaming prolongation ------------------------------------
 // out[n][m] (+)= base[m] + S( sum_c scale_c sum_q w_c(n,q) (Phi_a Y_c[q])(x_m) )
 struct ProlongArgs {
   Geometry g;
-  const Channel *ch;     // [2*J]
   const double *coarse;  // C[n][(2^A0-1)^d] (if A0 > 1)
   const double *base;    // [nxf^d] or null
   double *out;           // [ntf][nxf^d]
   int accumulate;        // 1: add to existing out
   int stencil;           // 0 none, 1 mass
   double sx, sy;
+  Channel ch[kChanMax];
 };
 
 struct WorkItem {        // flattened per-channel work (reduce / coarse kernels)
@@ -53,13 +57,15 @@ struct GemmDesc {
 
 struct SolveDesc {
   double *rhs;           // [nq][nmodes], overwritten with the solution
-  double *scratch;       // 6 * nq * nmodes doubles
+  double *fac;           // 5 planes [nq][nmodes]: L1, L2, 1/U0, U1, U2 of E = L U
+  double *scratch;       // 2 planes [nq][nmodes]
   int nq, nmodes;
   int b, a;              // time level, spatial level
-  int refine;            // refinement sweeps with a double-double residual
+  int refine;            // maximum refinement sweeps (double-double residual)
   int transpose;         // solve with the transposed time matrices
   double c2;             // wave speed squared (constant-speed path)
-  long long thread0;     // first global thread
+  long long thread0;     // first global thread, a multiple of 64 (one wave
+                         // never spans two descriptors)
 };
 
 struct ModeTables {      // 1-D P1 eigenvalues per level and axis (unit c)
@@ -114,6 +120,9 @@ hipError_t launch_adjoint_fields(const LevelDesc *ld, int nlev, long long total,
                                  hipStream_t s);
 hipError_t launch_gemm(const GemmDesc *descs, int ndesc, int total_tiles,
                        hipStream_t s);
+hipError_t launch_time_factor(const SolveDesc *sd, int nsd, long long total,
+                              const KernelTables *kt, const ModeTables *mt, int d,
+                              hipStream_t s);
 hipError_t launch_time_solve(const SolveDesc *sd, int nsd, long long total,
                              const KernelTables *kt, const ModeTables *mt, int d,
                              hipStream_t s);
