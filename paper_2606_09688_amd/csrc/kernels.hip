@@ -53,23 +53,81 @@ __device__ __forceinline__ long long gid64() {
 
 // --------------------------------------------------------- restriction -----
 
-template <int D, int TS, int TB, int NT>
+// Zero-halo LDS layout of the in-tile levels (one copy per slab).  Level r
+// keeps its nodes(r)^D values at padded index (jy+1)*pn(r) + (jx+1); the halo
+// entries stay zero, so the full-weighting stencil of a level-(r+1) node reads
+// padded entries (2jy+dy)*pn(r) + 2jx+dx, dx, dy in {0,1,2}, without tests.
+// Level 0 gets two halo entries on the far side (its coarse neighbour reaches
+// one node past the tile).
+template <int D, int TS, int MODE>
+struct Pad {
+  using SH = Shape<D, TS, MODE>;
+  __host__ __device__ static constexpr int pn(int r) { return SH::nodes(r) + (r == 0 ? 3 : 2); }
+  __host__ __device__ static constexpr int psize(int r) { return ipow(pn(r), D); }
+  __host__ __device__ static constexpr int poff(int r) { return r == 0 ? 0 : poff(r - 1) + psize(r - 1); }
+  static constexpr int total = poff(SH::LTS + 1);
+};
+
+// Upper-level nodes (levels r = 1..LTS of the tile) are owned by threads:
+// thread t owns upper nodes u = t and u = t + NT.  An owned node knows its
+// level, its row-major index j in the level and its relative coordinates.
+template <int D, int TS, int MODE>
+struct Owned {
+  int r = 0;  // 0: no node in this slot
+  int j = 0, jx = 0, jy = 0;
+  __device__ void set(int u) {
+    using SH = Shape<D, TS, MODE>;
+    r = 0;
+    int base = 0;
+#pragma unroll
+    for (int rr = 1; rr <= SH::LTS; ++rr) {
+      const int sz = SH::size(rr);
+      if (r == 0 && u >= base && u < base + sz) {
+        r = rr;
+        j = u - base;
+        jx = j % SH::nodes(rr);
+        jy = (D == 2) ? j / SH::nodes(rr) : 0;
+      }
+      base += sz;
+    }
+  }
+};
+
+// Full weighting of a level-(r) node from the padded level r-1 array (PN is
+// a constant once the level loop is unrolled).
+template <int D>
+__device__ __forceinline__ double full_weight(const double *src, int PN, int jx, int jy) {
+  if (D == 1) {
+    const double *p = src + 2 * jx;
+    return 0.5 * (p[0] + p[2]) + p[1];
+  } else {
+    const double *p = src + 2 * jy * PN + 2 * jx;
+    const double r0 = 0.5 * (p[0] + p[2]) + p[1];
+    const double r1 = 0.5 * (p[PN] + p[PN + 2]) + p[PN + 1];
+    const double r2 = 0.5 * (p[2 * PN] + p[2 * PN + 2]) + p[2 * PN + 1];
+    return 0.5 * (r0 + r2) + r1;
+  }
+}
+
+template <int D, int TS, int TB, int NT, int STENCIL>
 __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
   using SH = Shape<D, TS, 0>;
+  using PD = Pad<D, TS, 0>;
+  constexpr int LTS = SH::LTS;
   constexpr int NIN = TS + 2;
   constexpr int INSZ = ipow(NIN, D);
   constexpr int L0 = SH::size(0);
-  constexpr int EPT = L0 / NT;
-  constexpr int UP = SH::upper;
-  constexpr int KMAX = (SH::max_upper_size + NT - 1) / NT;
+  constexpr int EPT = L0 / NT;                    // fine points per thread
   constexpr int PF = (TB * INSZ + NT - 1) / NT;   // prefetched inputs per thread
-  constexpr int NCI = 2 * (SH::LTS + 1);          // in-tile channels, li = 2 r + k
+  constexpr int NCI = 2 * (LTS + 1);              // in-tile channels, li = 2 r + k
   constexpr int NTAP = NCI * (TB + 1);            // staged tap entries per batch
-  static_assert(L0 % NT == 0, "tile must be a multiple of the block");
+  constexpr int PT = PD::total;
+  static_assert(L0 % NT == 0 && (D == 1 || TS % EPT == 0 || EPT == 1), "tile / block shape");
+  static_assert(D == 1 ? EPT == 1 : (NT % TS == 0 && TS % EPT == 0), "column strips");
   static_assert(NTAP <= NT, "one thread per staged tap entry");
+  static_assert(SH::upper <= 2 * NT, "two owned upper nodes per thread");
   __shared__ double s_in[TB * INSZ];
-  __shared__ double s_lv[TB * SH::total];
-  __shared__ double s_acc[2 * 3 * UP];
+  __shared__ double s_lv[TB * PT];
   // taps of the in-tile channels for slabs nb-1 .. nb+TB-1: s_q[li][s] is
   // q0 of slab nb-1+s (-1 outside the chunk), s_w[li][s] the weights of
   // slab nb+s
@@ -88,8 +146,9 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
   const int ntileD = (D == 2) ? g.ntile * g.ntile : g.ntile;
   const long long nsp = (D == 2) ? (long long)g.nxf * g.nxf : g.nxf;
   const int R = g.R;
+  const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
 
-  for (int i = tid; i < 2 * 3 * UP; i += NT) s_acc[i] = 0.0;
+  for (int i = tid; i < TB * PT; i += NT) s_lv[i] = 0.0;
   if (tid < NCI) {
     const int r = tid >> 1, k = tid & 1;
     int q = 0;
@@ -99,21 +158,22 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
     }
     s_qlo[tid] = q;
   }
-  double racc[EPT][2][3];
-#pragma unroll
-  for (int e = 0; e < EPT; ++e)
-#pragma unroll
-    for (int k = 0; k < 2; ++k) racc[e][k][0] = racc[e][k][1] = racc[e][k][2] = 0.0;
 
-  // partial block of in-tile channel li at level offset r, time index q
-  auto part_index = [&](int li, int r, int q) -> long long {
-    const Channel &C = A.ch[(g.J - r - 1) * 2 + (li & 1)];
-    return C.part_off +
-           (((long long)chunk * ntileD + tile) * C.qb + (q - s_qlo[li])) * (long long)SH::size(r);
-  };
+  // fine points of this thread: column strip x, rows y0 .. y0+EPT-1 (2-D)
+  const int fx = (D == 2) ? tid % TS : tid;
+  const int fy0 = (D == 2) ? (tid / TS) * EPT : 0;
+  double fmask[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int px = TS * tx + fx, py = TS * ty + fy0 + e;
+    fmask[e] = (interior(px, g.nxf) && (D == 1 || interior(py, g.nxf))) ? 1.0 : 0.0;
+  }
+  // owned upper nodes
+  Owned<D, TS, 0> own[2];
+  own[0].set(tid);
+  own[1].set(tid + NT);
 
-  // tap entry staged by this thread: channel li = tid / (TB+1), slab offset
-  // my_s; its table pointers are resolved once (independent loads per batch)
+  // tap entry staged by this thread: channel li = tid / (TB+1), slab offset my_s
   const int my_s = tid % (TB + 1);
   const int *my_q0 = nullptr;
   const double *my_w = nullptr;
@@ -127,29 +187,30 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
       }
     }
   }
-  // register prefetch of one batch (input slabs with halo + tap entries)
+  // input gather offsets (slab-relative, -1 outside the interior)
+  int in_s[PF];
+  int in_off[PF];
+#pragma unroll
+  for (int e = 0; e < PF; ++e) {
+    const int idx = tid + e * NT;
+    const int s = idx / INSZ, loc = idx - s * INSZ;
+    const int ix = loc % NIN, iy = loc / NIN;
+    const int px = TS * tx - 1 + ix;
+    const int py = TS * ty - 1 + iy;
+    in_s[e] = idx < TB * INSZ ? s : TB;
+    in_off[e] = (interior(px, g.nxf) && (D == 1 || interior(py, g.nxf)))
+                    ? (px - 1) + (D == 2 ? (py - 1) * g.nxf : 0)
+                    : -1;
+  }
   double pin[PF];
   int pq = -1;
   double pw0 = 0.0, pw1 = 0.0, pw2 = 0.0;
   auto fetch = [&](int nb) {
     const int cnt = min(TB, n1 - nb);
 #pragma unroll
-    for (int e = 0; e < PF; ++e) {
-      const int idx = tid + e * NT;
-      double v = 0.0;
-      if (idx < cnt * INSZ) {
-        const int s = idx / INSZ, loc = idx - s * INSZ;
-        const int ix = loc % NIN, iy = loc / NIN;
-        const int px = TS * tx - 1 + ix;
-        const int py = TS * ty - 1 + iy;
-        if (interior(px, g.nxf) && (D == 1 || interior(py, g.nxf))) {
-          long long off = (long long)(nb + s) * nsp + (px - 1);
-          if (D == 2) off += (long long)(py - 1) * g.nxf;
-          v = A.X[off];
-        }
-      }
-      pin[e] = v;
-    }
+    for (int e = 0; e < PF; ++e)
+      pin[e] = (in_s[e] < cnt && in_off[e] >= 0) ? A.X[(long long)(nb + in_s[e]) * nsp + in_off[e]]
+                                                 : 0.0;
     pq = -1;
     pw0 = pw1 = pw2 = 0.0;
     const int n = nb - 1 + my_s;
@@ -163,7 +224,24 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
     }
   };
 
+  double racc0[EPT][2][3];
+  double racc[2][2][3];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) racc0[e][k][0] = racc0[e][k][1] = racc0[e][k][2] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) racc[i][k][0] = racc[i][k][1] = racc[i][k][2] = 0.0;
+
+  const long long blk = (long long)chunk * ntileD + tile;
+  auto part_at = [&](const Channel &C, int li, int r, int q, int j) -> long long {
+    return C.part_off + (blk * C.qb + (q - s_qlo[li])) * (long long)SH::size(r) + j;
+  };
+
   fetch(n0);
+  __syncthreads();  // zeroed halos and s_qlo
   int last_cnt = 0;
   for (int nb = n0; nb < n1; nb += TB) {
     const int cnt = min(TB, n1 - nb);
@@ -175,184 +253,114 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
       if (idx < TB * INSZ) s_in[idx] = pin[e];
     }
     if (tid < NTAP) {
-      const int li = tid / (TB + 1), s = tid - li * (TB + 1);
-      s_q[li][s] = pq;
-      if (s > 0) {
-        s_w[li][s - 1][0] = pw0;
-        s_w[li][s - 1][1] = pw1;
-        s_w[li][s - 1][2] = pw2;
+      const int li = tid / (TB + 1);
+      s_q[li][my_s] = pq;
+      if (my_s > 0) {
+        s_w[li][my_s - 1][0] = pw0;
+        s_w[li][my_s - 1][1] = pw1;
+        s_w[li][my_s - 1][2] = pw2;
       }
     }
     __syncthreads();
     if (nb + TB < n1) fetch(nb + TB);
-    // (2) level 0 (fine nodes, optional mass stencil) and its accumulation
+    // (2) fine level: optional mass stencil, accumulation, level-0 array
     for (int s = 0; s < cnt; ++s) {
       const double *in = s_in + s * INSZ;
-      double val[EPT];
+      double m[EPT];
+      if (D == 1) {
+        m[0] = STENCIL ? A.sx * (in[fx] + in[fx + 2] + 4.0 * in[fx + 1]) * fmask[0] : in[fx + 1];
+      } else if (STENCIL) {
+        double h[EPT + 2];
+#pragma unroll
+        for (int i = 0; i < EPT + 2; ++i) {
+          const double *row = in + (fy0 + i) * NIN + fx;
+          h[i] = row[0] + row[2] + 4.0 * row[1];
+        }
+        const double sxy = A.sx * A.sy;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) m[e] = sxy * (h[e] + h[e + 2] + 4.0 * h[e + 1]) * fmask[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) m[e] = in[(fy0 + e + 1) * NIN + fx + 1];
+      }
+      double *l0 = s_lv + s * PT;
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        const int p = tid + e * NT;
-        const int ix = p % TS, iy = (D == 2) ? p / TS : 0;
-        const int px = TS * tx + ix, py = TS * ty + iy;
-        double v = 0.0;
-        if (interior(px, g.nxf) && (D == 1 || interior(py, g.nxf))) {
-          if (A.stencil) {
-            if (D == 1) {
-              v = A.sx * (in[ix] + 4.0 * in[ix + 1] + in[ix + 2]);
-            } else {
-              const double *r0 = in + iy * NIN + ix, *r1 = r0 + NIN, *r2 = r1 + NIN;
-              const double c0 = r0[0] + 4.0 * r0[1] + r0[2];
-              const double c1 = r1[0] + 4.0 * r1[1] + r1[2];
-              const double c2 = r2[0] + 4.0 * r2[1] + r2[2];
-              v = A.sy * A.sx * (c0 + 4.0 * c1 + c2);
-            }
-          } else {
-            v = (D == 1) ? in[ix + 1] : in[(iy + 1) * NIN + ix + 1];
-          }
-        }
-        val[e] = v;
-        s_lv[s * SH::total + p] = v;
+        if (D == 1) l0[fx + 1] = m[0];
+        else l0[(fy0 + e + 1) * PD::pn(0) + fx + 1] = m[e];
       }
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         if (!A.ch[(g.J - 1) * 2 + k].active) continue;
-        const int q0n = s_q[k][s + 1], qp = s_q[k][s];
-        if (qp >= 0 && q0n > qp) {
-          const long long base = part_index(k, 0, qp);
-#pragma unroll
-          for (int e = 0; e < EPT; ++e) {
-            A.part[base + tid + e * NT] = racc[e][k][0];
-            racc[e][k][0] = racc[e][k][1];
-            racc[e][k][1] = racc[e][k][2];
-            racc[e][k][2] = 0.0;
-          }
-        }
         const double w0 = s_w[k][s][0], w1 = s_w[k][s][1], w2 = s_w[k][s][2];
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-          racc[e][k][0] += w0 * val[e];
-          racc[e][k][1] += w1 * val[e];
-          racc[e][k][2] += w2 * val[e];
+          racc0[e][k][0] += w0 * m[e];
+          racc0[e][k][1] += w1 * m[e];
+          racc0[e][k][2] += w2 * m[e];
         }
       }
     }
     __syncthreads();
-    // (3) restriction pyramid r = 1..R (full weighting, partial at tile edges)
-    for (int r = 1; r <= R; ++r) {
-      const int nr = SH::nodes(r), np = SH::nodes(r - 1), sz = SH::size(r);
-      const int lox = tile_lo(TS, tx, r, 0), plox = tile_lo(TS, tx, r - 1, 0);
-      const int loy = tile_lo(TS, ty, r, 0), ploy = tile_lo(TS, ty, r - 1, 0);
-      for (int idx = tid; idx < cnt * sz; idx += NT) {
-        const int s = idx / sz, j = idx - s * sz;
-        const int jx = j % nr, jy = (D == 2) ? j / nr : 0;
-        const double *src = s_lv + s * SH::total + SH::offset(r - 1);
-        double acc = 0.0;
-        const int cx = 2 * (lox + jx) - plox;
-        if (D == 1) {
+    // (3) levels r = 1..R: owners restrict from level r-1 and accumulate
 #pragma unroll
-          for (int dx = -1; dx <= 1; ++dx) {
-            const int sx_ = cx + dx;
-            if (sx_ >= 0 && sx_ < np) acc += (dx == 0 ? 1.0 : 0.5) * src[sx_];
-          }
-        } else {
-          const int cy = 2 * (loy + jy) - ploy;
+    for (int r = 1; r <= LTS; ++r) {
+      if (r > R) break;
 #pragma unroll
-          for (int dy = -1; dy <= 1; ++dy) {
-            const int sy_ = cy + dy;
-            if (sy_ < 0 || sy_ >= np) continue;
-            double row = 0.0;
+      for (int i = 0; i < 2; ++i) {
+        if (own[i].r != r) continue;
+        for (int s = 0; s < cnt; ++s) {
+          const double *src = s_lv + s * PT + PD::poff(r - 1);
+          const double v = full_weight<D>(src, PD::pn(r - 1), own[i].jx, own[i].jy);
+          s_lv[s * PT + PD::poff(r) + (D == 2 ? (own[i].jy + 1) * PD::pn(r) : 0) + own[i].jx + 1] = v;
 #pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-              const int sx_ = cx + dx;
-              if (sx_ >= 0 && sx_ < np) row += (dx == 0 ? 1.0 : 0.5) * src[sy_ * np + sx_];
+          for (int k = 0; k < 2; ++k) {
+            const int li = 2 * r + k;
+            const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
+            if (!C.active) continue;
+            const int q0n = s_q[li][s + 1], qp = s_q[li][s];
+            if (qp >= 0 && q0n > qp) {
+              A.part[part_at(C, li, r, qp, own[i].j)] = racc[i][k][0];
+              racc[i][k][0] = racc[i][k][1];
+              racc[i][k][1] = racc[i][k][2];
+              racc[i][k][2] = 0.0;
             }
-            acc += (dy == 0 ? 1.0 : 0.5) * row;
+            racc[i][k][0] += s_w[li][s][0] * v;
+            racc[i][k][1] += s_w[li][s][1] * v;
+            racc[i][k][2] += s_w[li][s][2] * v;
           }
+          if (r == R && use_coarse)
+            A.coarse[((long long)tile * g.ntf + nb + s) * SH::size(r) + own[i].j] = v;
         }
-        s_lv[s * SH::total + SH::offset(r) + j] = acc;
       }
       __syncthreads();
     }
-    // (4) accumulate levels r >= 1 into their time nodes (ring of 3 slots)
-    for (int r = 1; r <= R; ++r) {
-      const int sz = SH::size(r);
-      const int aoff = SH::offset(r) - SH::size(0);
-      for (int k = 0; k < 2; ++k) {
-        const int li = 2 * r + k;
-        if (!A.ch[(g.J - r - 1) * 2 + k].active) continue;
-        double *acc = s_acc + (size_t)k * 3 * UP + aoff;
-        for (int s = 0; s < cnt; ++s) {
-          const int q0n = s_q[li][s + 1], qp = s_q[li][s];
-          if (qp >= 0 && q0n > qp) {
-            const long long base = part_index(li, r, qp);
-            double *sl = acc + (qp % 3) * UP;
-#pragma unroll
-            for (int kk = 0; kk < KMAX; ++kk) {
-              const int j = tid + kk * NT;
-              if (j < sz) {
-                A.part[base + j] = sl[j];
-                sl[j] = 0.0;
-              }
-            }
-          }
-          const double w0 = s_w[li][s][0], w1 = s_w[li][s][1], w2 = s_w[li][s][2];
-          double *a0 = acc + (q0n % 3) * UP;
-          double *a1 = acc + ((q0n + 1) % 3) * UP;
-          double *a2 = acc + ((q0n + 2) % 3) * UP;
-          const double *v = s_lv + s * SH::total + SH::offset(r);
-#pragma unroll
-          for (int kk = 0; kk < KMAX; ++kk) {
-            const int j = tid + kk * NT;
-            if (j < sz) {
-              const double x = v[j];
-              a0[j] += w0 * x;
-              a1[j] += w1 * x;
-              a2[j] += w2 * x;
-            }
-          }
-        }
-      }
-      if (r == R && g.A0 > 1 && A.coarse != nullptr) {
-        for (int idx = tid; idx < cnt * sz; idx += NT) {
-          const int s = idx / sz, j = idx - s * sz;
-          A.coarse[((long long)tile * g.ntf + nb + s) * sz + j] =
-              s_lv[s * SH::total + SH::offset(r) + j];
-        }
-      }
-    }
-    __syncthreads();
   }
-  // final flush of the open time nodes (s_q still holds the last batch)
+  // final flush of the open time nodes (s_q still holds the last batch; the
+  // level-J channels have q0 = 0 throughout, so their nodes are q = 0, 1, 2)
+#pragma unroll
   for (int k = 0; k < 2; ++k) {
     const Channel &C = A.ch[(g.J - 1) * 2 + k];
     if (!C.active) continue;
-    const int ql = s_q[k][last_cnt];
 #pragma unroll
-    for (int o = 0; o < 3; ++o) {
-      if (ql + o >= C.nq) break;
-      const long long base = part_index(k, 0, ql + o);
+    for (int o = 0; o < 3; ++o)
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) A.part[base + tid + e * NT] = racc[e][k][o];
-    }
+      for (int e = 0; e < EPT; ++e)
+        A.part[part_at(C, k, 0, o, (D == 2 ? (fy0 + e) * TS : 0) + fx)] = racc0[e][k][o];
   }
-  for (int r = 1; r <= R; ++r) {
-    const int sz = SH::size(r);
-    const int aoff = SH::offset(r) - SH::size(0);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int r = own[i].r;
+    if (r == 0 || r > R) continue;
+#pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int li = 2 * r + k;
       const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
       if (!C.active) continue;
       const int ql = s_q[li][last_cnt];
-      for (int o = 0; o < 3; ++o) {
-        const int q = ql + o;
-        if (q >= C.nq) break;
-        const long long base = part_index(li, r, q);
-        const double *sl = s_acc + (size_t)k * 3 * UP + aoff + (q % 3) * UP;
-        for (int kk = 0; kk < KMAX; ++kk) {
-          const int j = tid + kk * NT;
-          if (j < sz) A.part[base + j] = sl[j];
-        }
-      }
+#pragma unroll
+      for (int o = 0; o < 3; ++o)
+        if (ql + o < C.nq) A.part[part_at(C, li, r, ql + o, own[i].j)] = racc[i][k][o];
     }
   }
 }
@@ -559,28 +567,25 @@ __global__ void k_prolong_coarse(const Geometry g, const Channel *__restrict__ c
 template <int D, int TS, int TB, int NT, int MODE>
 __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
   using SH = Shape<D, TS, MODE>;
+  constexpr int LTS = SH::LTS;
   constexpr int L0 = SH::size(0);
   constexpr int EPT0 = (L0 + NT - 1) / NT;
   constexpr int UP = SH::upper;
-  constexpr int KMAX = (SH::max_upper_size + NT - 1) / NT;
   constexpr int NO = ipow(TS, D);          // output points per slab
   constexpr int EPTO = NO / NT;
   constexpr int NF = TS + 2 * MODE;
-  constexpr int RS = TB + 2;               // coefficient ring slots per channel
-  constexpr int NCI = 2 * (SH::LTS + 1);   // in-tile channels, li = 2 r + k
+  constexpr int NCI = 2 * (LTS + 1);       // in-tile channels, li = 2 r + k
   constexpr int NTAP = NCI * (TB + 1);
+  constexpr int SZR = SH::size(LTS);
   static_assert(NO % NT == 0, "tile must be a multiple of the block");
-  static_assert(NTAP <= NT, "one thread per staged tap entry");
-  __shared__ double s_v[TB * UP];
-  __shared__ double s_coef[2 * RS * UP];
+  static_assert(NTAP + TB * SZR <= NT, "tap and coarse staging threads");
+  static_assert(UP <= 2 * NT, "two owned upper nodes per thread");
+  static_assert(D == 1 || !MODE || (NT % TS == 0 && EPTO * NT == NO), "column strips");
+  __shared__ double s_v[TB * UP];          // upper levels, unpadded, per slab
   __shared__ double s_f[MODE ? TB * L0 : 1];
   __shared__ int s_q[NCI][TB + 1];         // q0 of slabs nb-1 .. nb+TB-1 (-1: none)
   __shared__ double s_w[NCI][TB][3];       // weights of slabs nb .. nb+TB-1
-  // coarse-level values (levels a < A0, already summed) at the in-tile
-  // level-A0 nodes of the batch; used only when A0 > 1, and then R = LTS
-  constexpr int SZR = SH::size(SH::LTS);
-  static_assert(NTAP + TB * SZR <= NT, "coarse staging threads follow the tap threads");
-  __shared__ double s_co[TB * SZR];
+  __shared__ double s_co[TB * SZR];        // coarse-level values at level-A0 nodes
 
   const Geometry g = A.g;
   const int tid = threadIdx.x;
@@ -592,23 +597,75 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
   const int n1 = min(n0 + g.chunk, g.ntf);
   const long long nsp = (D == 2) ? (long long)g.nxf * g.nxf : g.nxf;
   const int R = g.R;
+  const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
 
-  // coefficient of channel C at time index q for the node with global
-  // positions (Px, Py) of its level (zero outside the interior)
-  auto coef = [&](const Channel &C, int q, int Px, int Py) -> double {
+  // ---- owned upper nodes: coefficient offsets and windows in registers ----
+  Owned<D, TS, MODE> own[2];
+  own[0].set(tid);
+  own[1].set(tid + NT);
+  int coff[2];  // offset of the node in a time plane of its level (-1: boundary)
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    coff[i] = -1;
+    const int r = own[i].r;
+    if (r >= 1 && r <= R) {
+      const int a = g.J - r, na = (1 << a) - 1;
+      const int Px = tile_lo(TS, tx, r, MODE) + own[i].jx;
+      const int Py = (D == 2) ? tile_lo(TS, ty, r, MODE) + own[i].jy : 0;
+      if (interior(Px, na) && (D == 1 || interior(Py, na)))
+        coff[i] = (Px - 1) + (D == 2 ? (Py - 1) * na : 0);
+    }
+  }
+  // window c[0..2] = coefficients q0..q0+2, c[3] = q0+3 (prefetched)
+  double cw[2][2][4];
+  int cq[2][2];  // q0 of the current window
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      cq[i][k] = 0;
+      cw[i][k][0] = cw[i][k][1] = cw[i][k][2] = cw[i][k][3] = 0.0;
+    }
+  auto coef = [&](const Channel &C, int q, int off) -> double {
+    if (off < 0 || q >= C.nq) return 0.0;
     const int na = (1 << C.a) - 1;
-    if (!interior(Px, na) || (D == 2 && !interior(Py, na))) return 0.0;
     const long long nspa = (D == 2) ? (long long)na * na : na;
-    return C.data[(long long)q * nspa + (D == 2 ? (long long)(Py - 1) * na : 0) + (Px - 1)];
+    return C.data[(long long)q * nspa + off];
   };
-
-  double rc[EPT0][2][3];  // level-0 coefficient window (q0, q0+1, q0+2)
 #pragma unroll
-  for (int e = 0; e < EPT0; ++e)
+  for (int i = 0; i < 2; ++i) {
+    const int r = own[i].r;
+    if (r < 1 || r > R) continue;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) rc[e][k][0] = rc[e][k][1] = rc[e][k][2] = 0.0;
-  double basev[EPT0];
+    for (int k = 0; k < 2; ++k) {
+      const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
+      if (!C.active) continue;
+      const int q = C.q0[n0];
+      cq[i][k] = q;
+#pragma unroll
+      for (int o = 0; o < 4; ++o) cw[i][k][o] = coef(C, q + o, coff[i]);
+    }
+  }
+  // level-J channels belong to time level b = 1 (q0 = 0 on every slab)
   const int lo0x = tile_lo(TS, tx, 0, MODE), lo0y = tile_lo(TS, ty, 0, MODE);
+  double rc[EPT0][2][3];
+#pragma unroll
+  for (int e = 0; e < EPT0; ++e) {
+    const int p = tid + e * NT;
+    const int Px = lo0x + p % NF, Py = (D == 2) ? lo0y + p / NF : 0;
+    const int off = (p < L0 && interior(Px, g.nxf) && (D == 1 || interior(Py, g.nxf)))
+                        ? (Px - 1) + (D == 2 ? (Py - 1) * g.nxf : 0)
+                        : -1;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const Channel &C = A.ch[(g.J - 1) * 2 + k];
+      rc[e][k][0] = rc[e][k][1] = rc[e][k][2] = 0.0;
+      if (!C.active) continue;
+#pragma unroll
+      for (int o = 0; o < 3; ++o) rc[e][k][o] = coef(C, o, off);
+    }
+  }
+  double basev[EPT0];
 #pragma unroll
   for (int e = 0; e < EPT0; ++e) {
     basev[e] = 0.0;
@@ -620,7 +677,7 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
     }
   }
 
-  // tap entry staged by this thread (see k_restrict)
+  // ---- tap entries and coarse values of the next batch (registers) ----
   const int my_s = tid % (TB + 1);
   const int *my_q0 = nullptr;
   const double *my_w = nullptr;
@@ -634,11 +691,22 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
       }
     }
   }
-  // tap entries and coarse values of the next batch, prefetched in registers
+  const int co_i = tid - NTAP;
+  int co_off = -1, co_s = 0;
+  if (use_coarse && co_i >= 0 && co_i < TB * SZR) {
+    co_s = co_i / SZR;
+    const int j = co_i - co_s * SZR;
+    constexpr int nrR = SH::nodes(LTS);
+    const int Px = tile_lo(TS, tx, LTS, MODE) + j % nrR;
+    const int Py = (D == 2) ? tile_lo(TS, ty, LTS, MODE) + j / nrR : 0;
+    const int n0a = (1 << g.A0) - 1;
+    if (interior(Px, n0a) && (D == 1 || interior(Py, n0a)))
+      co_off = (Px - 1) + (D == 2 ? (Py - 1) * n0a : 0);
+  }
+  const long long nsp0 = (D == 2) ? (long long)((1 << g.A0) - 1) * ((1 << g.A0) - 1)
+                                  : (1 << g.A0) - 1;
   int pq = -1;
   double pw0 = 0.0, pw1 = 0.0, pw2 = 0.0, pco = 0.0;
-  const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
-  const int co_i = tid - NTAP;  // coarse entry staged by this thread (if >= 0)
   auto fetch_taps = [&](int nb) {
     pq = -1;
     pw0 = pw1 = pw2 = 0.0;
@@ -651,135 +719,76 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
         pw2 = my_w[3 * n + 2];
       }
     }
-    pco = 0.0;
-    if (use_coarse && co_i >= 0 && co_i < TB * SZR) {
-      const int s = co_i / SZR, j = co_i - s * SZR;
-      constexpr int nrR = SH::nodes(SH::LTS);
-      const int Px = tile_lo(TS, tx, SH::LTS, MODE) + j % nrR;
-      const int Py = (D == 2) ? tile_lo(TS, ty, SH::LTS, MODE) + j / nrR : 0;
-      const int n0a = (1 << g.A0) - 1;
-      if (nb + s < n1 && interior(Px, n0a) && (D == 1 || interior(Py, n0a))) {
-        const long long nsp0 = (D == 2) ? (long long)n0a * n0a : n0a;
-        pco = A.coarse[(long long)(nb + s) * nsp0 +
-                       (D == 2 ? (long long)(Py - 1) * n0a : 0) + (Px - 1)];
-      }
-    }
+    pco = (co_off >= 0 && nb + co_s < n1) ? A.coarse[(long long)(nb + co_s) * nsp0 + co_off] : 0.0;
   };
-  // level-J channels belong to time level b = 1 (q0 = 0 on every slab), so
-  // their coefficient window is loaded once
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const Channel &C = A.ch[(g.J - 1) * 2 + k];
-    if (!C.active) continue;
-#pragma unroll
-    for (int e = 0; e < EPT0; ++e) {
-      const int p = tid + e * NT;
-      if (p >= L0) continue;
-      const int Px = lo0x + p % NF, Py = (D == 2) ? lo0y + p / NF : 0;
-      rc[e][k][0] = coef(C, 0, Px, Py);
-      rc[e][k][1] = coef(C, 1, Px, Py);
-      rc[e][k][2] = coef(C, 2, Px, Py);
-    }
-  }
 
   fetch_taps(n0);
   for (int nb = n0; nb < n1; nb += TB) {
     const int cnt = min(TB, n1 - nb);
     if (tid < NTAP) {
-      const int li = tid / (TB + 1), s = tid - li * (TB + 1);
-      s_q[li][s] = pq;
-      if (s > 0) {
-        s_w[li][s - 1][0] = pw0;
-        s_w[li][s - 1][1] = pw1;
-        s_w[li][s - 1][2] = pw2;
+      const int li = tid / (TB + 1);
+      s_q[li][my_s] = pq;
+      if (my_s > 0) {
+        s_w[li][my_s - 1][0] = pw0;
+        s_w[li][my_s - 1][1] = pw1;
+        s_w[li][my_s - 1][2] = pw2;
       }
     } else if (co_i < TB * SZR) {
       s_co[co_i] = pco;
     }
     __syncthreads();
     if (nb + TB < n1) fetch_taps(nb + TB);
-    // phase A: owners evaluate every level r >= 1 in time.  The coefficients
-    // a batch needs beyond those already in the ring are gathered first (all
-    // loads of one level in flight together), then the slabs are evaluated.
-    for (int r = 1; r <= R; ++r) {
-      const int nr = SH::nodes(r), sz = SH::size(r);
-      const int aoff = SH::offset(r) - SH::size(0);
-      const int lox = tile_lo(TS, tx, r, MODE), loy = tile_lo(TS, ty, r, MODE);
-      for (int s = 0; s < cnt; ++s)
+    // phase A: owners evaluate their node in time (register windows)
 #pragma unroll
-        for (int kk = 0; kk < KMAX; ++kk) {
-          const int j = tid + kk * NT;
-          if (j < sz) s_v[s * UP + aoff + j] = 0.0;
+    for (int i = 0; i < 2; ++i) {
+      const int r = own[i].r;
+      if (r < 1 || r > R) continue;
+      for (int s = 0; s < cnt; ++s) {
+        double v = (r == R && use_coarse) ? s_co[s * SZR + own[i].j] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
+          if (!C.active) continue;
+          const int li = 2 * r + k;
+          if (s_q[li][s + 1] > cq[i][k]) {  // advance by one time index
+            cq[i][k] += 1;
+            cw[i][k][0] = cw[i][k][1];
+            cw[i][k][1] = cw[i][k][2];
+            cw[i][k][2] = cw[i][k][3];
+            cw[i][k][3] = coef(C, cq[i][k] + 3, coff[i]);
+          }
+          v += C.scale * (s_w[li][s][0] * cw[i][k][0] + s_w[li][s][1] * cw[i][k][1] +
+                          s_w[li][s][2] * cw[i][k][2]);
         }
-      for (int k = 0; k < 2; ++k) {
-        const int li = 2 * r + k;
-        const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
-        if (!C.active) continue;
-        double *ring = s_coef + (size_t)k * RS * UP + aoff;
-        const int qhi = s_q[li][cnt] + 2;
-        const int qnew = s_q[li][0] >= 0 ? s_q[li][0] + 3 : s_q[li][1];
-        double cv[RS][KMAX];
-#pragma unroll
-        for (int o = 0; o < RS; ++o)
-#pragma unroll
-          for (int kk = 0; kk < KMAX; ++kk) {
-            const int j = tid + kk * NT, q = qnew + o;
-            cv[o][kk] = (q <= qhi && j < sz)
-                            ? coef(C, q, lox + j % nr, (D == 2) ? loy + j / nr : 0)
-                            : 0.0;
-          }
-#pragma unroll
-        for (int o = 0; o < RS; ++o)
-#pragma unroll
-          for (int kk = 0; kk < KMAX; ++kk) {
-            const int j = tid + kk * NT, q = qnew + o;
-            if (q <= qhi && j < sz) ring[(q % RS) * UP + j] = cv[o][kk];
-          }
-        for (int s = 0; s < cnt; ++s) {
-          const int q0n = s_q[li][s + 1];
-          const double w0 = s_w[li][s][0], w1 = s_w[li][s][1], w2 = s_w[li][s][2];
-          const double *c0 = ring + (q0n % RS) * UP;
-          const double *c1 = ring + ((q0n + 1) % RS) * UP;
-          const double *c2 = ring + ((q0n + 2) % RS) * UP;
-#pragma unroll
-          for (int kk = 0; kk < KMAX; ++kk) {
-            const int j = tid + kk * NT;
-            if (j < sz) s_v[s * UP + aoff + j] += C.scale * (w0 * c0[j] + w1 * c1[j] + w2 * c2[j]);
-          }
-        }
+        s_v[s * UP + SH::offset(r) - SH::size(0) + own[i].j] = v;
       }
     }
     __syncthreads();
-    // phase B: top-down interpolation r = R .. 1 (values of level r+1 are final)
-    for (int r = R; r >= 1; --r) {
-      const int nr = SH::nodes(r), sz = SH::size(r);
-      const int aoff = SH::offset(r) - SH::size(0);
+    // phase B: top-down interpolation r = R-1 .. 1 (owners of level r)
+#pragma unroll
+    for (int r = LTS - 1; r >= 1; --r) {
+      if (r >= R) continue;
+      const int nr = SH::nodes(r), pn = SH::nodes(r + 1);
       const int lox = tile_lo(TS, tx, r, MODE), loy = tile_lo(TS, ty, r, MODE);
-      for (int idx = tid; idx < cnt * sz; idx += NT) {
-        const int s = idx / sz, j = idx - s * sz;
-        const int Px = lox + j % nr, Py = (D == 2) ? loy + j / nr : 0;
-        double base = 0.0;
-        if (r == R) {
-          if (use_coarse) base = s_co[s * SZR + j];
-        } else {
-          const int pn = SH::nodes(r + 1);
-          const int paoff = SH::offset(r + 1) - SH::size(0);
-          const int plox = tile_lo(TS, tx, r + 1, MODE), ploy = tile_lo(TS, ty, r + 1, MODE);
-          const double *par = s_v + s * UP + paoff;
-          const int xl = (Px >> 1) - plox, xh = ((Px + 1) >> 1) - plox;
-          if (D == 1) {
-            base = 0.5 * (par[xl] + par[xh]);
-          } else {
-            const int yl = (Py >> 1) - ploy, yh = ((Py + 1) >> 1) - ploy;
-            base = 0.25 * (par[yl * pn + xl] + par[yl * pn + xh] + par[yh * pn + xl] +
-                           par[yh * pn + xh]);
-          }
+      const int plox = tile_lo(TS, tx, r + 1, MODE), ploy = tile_lo(TS, ty, r + 1, MODE);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if (own[i].r != r) continue;
+        const int Px = lox + own[i].jx, Py = (D == 2) ? loy + own[i].jy : 0;
+        const int xl = (Px >> 1) - plox, xh = ((Px + 1) >> 1) - plox;
+        const int yl = (D == 2) ? (Py >> 1) - ploy : 0, yh = (D == 2) ? ((Py + 1) >> 1) - ploy : 0;
+        for (int s = 0; s < cnt; ++s) {
+          const double *par = s_v + s * UP + SH::offset(r + 1) - SH::size(0);
+          const double add = (D == 1) ? 0.5 * (par[xl] + par[xh])
+                                      : 0.25 * (par[yl * pn + xl] + par[yl * pn + xh] +
+                                                par[yh * pn + xl] + par[yh * pn + xh]);
+          s_v[s * UP + SH::offset(r) - SH::size(0) + own[i].j] += add;
         }
-        s_v[s * UP + aoff + j] += base;
+        (void)nr;
       }
       __syncthreads();
     }
-    // phase C: fine nodes (owners, slabs in order for the register window)
+    // phase C: fine nodes
     for (int s = 0; s < cnt; ++s) {
       const int n = nb + s;
       double tv[EPT0];
@@ -827,30 +836,36 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
     }
     if (MODE) {
       __syncthreads();
+      // mass stencil on the tile (separable; 2-D threads own column strips)
+      const int fx = (D == 2) ? tid % TS : tid;
+      const int fy0 = (D == 2) ? (tid / TS) * EPTO : 0;
       for (int s = 0; s < cnt; ++s) {
         const int n = nb + s;
         const double *f = s_f + s * L0;
+        double o[EPTO];
+        if (D == 1) {
+          o[0] = A.sx * (f[fx] + f[fx + 2] + 4.0 * f[fx + 1]);
+        } else {
+          double h[EPTO + 2];
+#pragma unroll
+          for (int i2 = 0; i2 < EPTO + 2; ++i2) {
+            const double *row = f + (fy0 + i2) * NF + fx;
+            h[i2] = row[0] + row[2] + 4.0 * row[1];
+          }
+          const double sxy = A.sx * A.sy;
+#pragma unroll
+          for (int e = 0; e < EPTO; ++e) o[e] = sxy * (h[e] + h[e + 2] + 4.0 * h[e + 1]);
+        }
 #pragma unroll
         for (int e = 0; e < EPTO; ++e) {
-          const int p = tid + e * NT;
-          const int ix = p % TS, iy = (D == 2) ? p / TS : 0;
-          const int Px = TS * tx + ix, Py = (D == 2) ? TS * ty + iy : 0;
+          const int Px = TS * tx + fx, Py = (D == 2) ? TS * ty + fy0 + e : 0;
           if (!interior(Px, g.nxf) || (D == 2 && !interior(Py, g.nxf))) continue;
-          double v;
-          if (D == 1) {
-            v = A.sx * (f[ix] + 4.0 * f[ix + 1] + f[ix + 2]);
-          } else {
-            const double *r0 = f + iy * NF + ix, *r1 = r0 + NF, *r2 = r1 + NF;
-            v = A.sy * A.sx * ((r0[0] + 4.0 * r0[1] + r0[2]) + 4.0 * (r1[0] + 4.0 * r1[1] + r1[2]) +
-                               (r2[0] + 4.0 * r2[1] + r2[2]));
-          }
           const long long off = (long long)n * nsp +
                                 (D == 2 ? (long long)(Py - 1) * g.nxf : 0) + (Px - 1);
-          double base = 0.0;
-          if (A.base != nullptr) base = A.base[(D == 2 ? (long long)(Py - 1) * g.nxf : 0) + (Px - 1)];
-          double o = v + base;
-          if (A.accumulate) o += A.out[off];
-          A.out[off] = o;
+          double val = o[e];
+          if (A.base != nullptr) val += A.base[off - (long long)n * nsp];
+          if (A.accumulate) val += A.out[off];
+          A.out[off] = val;
         }
       }
     }
@@ -1348,10 +1363,17 @@ constexpr int kTS2 = 32, kTB2 = 2, kTS1 = 256, kTB1 = 8, kNT = 256;
 hipError_t launch_restrict(const RestrictArgs &a, hipStream_t s) {
   const int nt = a.g.d == 2 ? a.g.ntile * a.g.ntile : a.g.ntile;
   dim3 grid(nt, a.g.nchunk);
-  if (a.g.d == 2)
-    hipLaunchKernelGGL((k_restrict<2, kTS2, kTB2, kNT>), grid, dim3(kNT), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_restrict<1, kTS1, kTB1, kNT>), grid, dim3(kNT), 0, s, a);
+  if (a.g.d == 2) {
+    if (a.stencil)
+      hipLaunchKernelGGL((k_restrict<2, kTS2, kTB2, kNT, 1>), grid, dim3(kNT), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_restrict<2, kTS2, kTB2, kNT, 0>), grid, dim3(kNT), 0, s, a);
+  } else {
+    if (a.stencil)
+      hipLaunchKernelGGL((k_restrict<1, kTS1, kTB1, kNT, 1>), grid, dim3(kNT), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_restrict<1, kTS1, kTB1, kNT, 0>), grid, dim3(kNT), 0, s, a);
+  }
   return hipGetLastError();
 }
 
