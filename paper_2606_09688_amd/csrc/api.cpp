@@ -129,6 +129,7 @@ struct sg_problem {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int refine_nq = 33;
+  int wave_nq = 65;                // time levels with nq >= wave_nq: one wave per mode
   // optional stage events (not recorded while capturing)
   std::vector<hipEvent_t> ev;
   bool capturing = false;
@@ -374,28 +375,35 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
 
 sg_status build_solve_list(sg_problem *p, const std::vector<int> &cset, int transpose,
                            SolveList &L) {
+  // long time levels get one wave per mode (block-parallel recurrences) and
+  // come first, so the critical path starts at once; the rest run one thread
+  // per mode
   std::vector<SolveDesc> v;
   long long th = 0;
-  for (int ci : cset) {
-    const Comp &C = p->comps[ci];
-    SolveDesc sd{};
-    sd.rhs = (p->d == 2 ? p->bufS : p->bufT) + C.off;
-    sd.fac = p->fac + 5 * C.off;
-    sd.scratch = p->scratch + 2 * C.off;
-    sd.nq = C.nq;
-    sd.nmodes = C.nsp;
-    sd.b = C.b;
-    sd.a = C.a;
-    // refinement sweeps against the double-double time matrices: the double
-    // LU is a preconditioner whose quality drops as the time level grows
-    // (the sweeps stop early once the correction is negligible)
-    sd.refine = C.nq < p->refine_nq ? 0 : (C.nq <= 513 ? 4 : 8);
-    sd.transpose = transpose;
-    sd.c2 = p->c2;
-    sd.thread0 = th;
-    th += (C.nsp + 63) / 64 * 64;
-    v.push_back(sd);
-  }
+  for (int pass = 0; pass < 2; ++pass)
+    for (int ci : cset) {
+      const Comp &C = p->comps[ci];
+      const int wave = C.nq >= p->wave_nq ? 1 : 0;
+      if (wave != (pass == 0 ? 1 : 0)) continue;
+      SolveDesc sd{};
+      sd.rhs = (p->d == 2 ? p->bufS : p->bufT) + C.off;
+      sd.fac = p->fac + 5 * C.off;
+      sd.scratch = p->scratch + 2 * C.off;
+      sd.nq = C.nq;
+      sd.nmodes = C.nsp;
+      sd.b = C.b;
+      sd.a = C.a;
+      // refinement sweeps against the double-double time matrices: the double
+      // LU is a preconditioner whose quality drops as the time level grows
+      // (the sweeps stop early once the correction is negligible)
+      sd.refine = C.nq < p->refine_nq ? 0 : (C.nq <= 513 ? 4 : 8);
+      sd.transpose = transpose;
+      sd.wave = wave;
+      sd.c2 = p->c2;
+      sd.thread0 = th;
+      th += wave ? 64LL * C.nsp : (C.nsp + 63) / 64 * 64;
+      v.push_back(sd);
+    }
   sg_status st;
   if ((st = upload(p, v, &L.d)) != SG_OK) return st;
   L.n = (int)v.size();
@@ -479,6 +487,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   if (!p->const_c)
     return bail(fail(SG_ENOTSUP, "variable wave speed is not implemented in this build"));
   if (const char *e = getenv("SG_REFINE_NQ")) p->refine_nq = atoi(e);
+  if (const char *e = getenv("SG_WAVE_NQ")) p->wave_nq = atoi(e);
 
   // components: +1 on jx + jt = L (jx = 1..L-1), -1 on jx + jt = L-1 (jx = 1..L-2)
   long long off = 0;

@@ -1173,9 +1173,11 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
   constexpr int CR = 8;   // rows per register chunk of the residual
   const long long wbase = (long long)blockIdx.x * 64;
   const SolveDesc &S = sds[find_solve(sds, nsd, wbase)];
-  const long long gid = wbase + threadIdx.x;
-  const int j = (int)(gid - S.thread0);
-  if (gid >= total || j >= S.nmodes) return;
+  const int lane = threadIdx.x;
+  const bool wave = S.wave != 0;
+  // wave path: one mode per wave; thread path: one mode per thread
+  const int j = wave ? (int)((wbase - S.thread0) >> 6) : (int)(wbase + lane - S.thread0);
+  if (wbase + lane >= total || j >= S.nmodes) return;  // uniform in the wave path
   const int b = S.b, nq = S.nq, nm = S.nmodes;
   double m, kap;
   mode_scalars(S, j, mt, d, m, kap);
@@ -1188,6 +1190,139 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
   double *Y = S.scratch, *B0 = Y + plane;
   auto idx = [&](int i) -> long long { return (long long)i * nm + j; };
 
+  // residual row i: b_i - (op(E) x)_i with E from the double-double time
+  // matrices, accumulated in double-double; also folds |x_i| into xmax
+  auto resid_row = [&](int i, double &xmax) -> double {
+#pragma clang fp contract(off)
+    dd acc = {B0[idx(i)], 0.0};
+#pragma unroll
+    for (int off = -2; off <= 2; ++off) {
+      const int jj = i + off;
+      if (jj < 0 || jj >= nq) continue;
+      // op(E)[i][jj] = E[i][jj] (or E[jj][i] for the transpose)
+      const int r = tr ? jj : i, c = tr ? 2 - off : off + 2;
+      const double x = rhs[idx(jj)];
+      if (off == 0) xmax = fmax(xmax, fabs(x));
+      dd t1 = triple(m, Ab[r * 5 + c], x);
+      dd t2 = triple(kap, Bb[r * 5 + c], x);
+      t1.l = fma(m * Al[r * 5 + c], x, t1.l);
+      t2.l = fma(kap * Bl[r * 5 + c], x, t2.l);
+      acc = dd_add(acc, {-t1.h, -t1.l});
+      acc = dd_add(acc, {-t2.h, -t2.l});
+    }
+    return acc.h + acc.l;
+  };
+
+  if (wave) {
+    // ---- wave-parallel path: lane l owns rows [l*bk, (l+1)*bk) ----------
+    // Each of the four banded triangular recurrences
+    //   v_i = a_i (r_i - b1_i v_prev - b2_i v_prev2)
+    // is solved block-wise: every lane first derives the affine map of its
+    // block on the carried state (v_prev, v_prev2), an inclusive scan of
+    // these maps across the wave (in recurrence order) gives every block
+    // its entry state, and the block is then swept once more.
+    const int bk = (nq + 63) / 64;
+    const int r0 = min(lane * bk, nq), r1 = min(r0 + bk, nq);
+    // which: 0 L y = r (fwd), 1 U x = y (bwd), 2 U^T w = r (fwd), 3 L^T z = w (bwd)
+    auto coefs = [&](int which, int i, const double *Rin, double &a, double &b1, double &b2,
+                     double &r) {
+      if (which == 0) {
+        a = 1.0; b1 = L1[idx(i)]; b2 = L2[idx(i)]; r = Rin[idx(i)];
+      } else if (which == 1) {
+        a = UD[idx(i)]; b1 = U1[idx(i)]; b2 = U2[idx(i)]; r = Rin[idx(i)];
+      } else if (which == 2) {
+        a = UD[idx(i)];
+        b1 = i >= 1 ? U1[idx(i - 1)] : 0.0;
+        b2 = i >= 2 ? U2[idx(i - 2)] : 0.0;
+        r = Rin[idx(i)];
+      } else {
+        a = 1.0;
+        b1 = i + 1 < nq ? L1[idx(i + 1)] : 0.0;
+        b2 = i + 2 < nq ? L2[idx(i + 2)] : 0.0;
+        r = Rin[idx(i)];
+      }
+    };
+    auto pass = [&](int which, const double *Rin, double *out, bool add) -> double {
+      const bool fwd = (which == 0 || which == 2);
+      const int cnt = r1 - r0;
+      // step 1: block map  S_out = c + H S_in,  S = (v_prev, v_prev2)
+      double c1 = 0.0, c2 = 0.0, h11 = 1.0, h21 = 0.0, h12 = 0.0, h22 = 1.0;
+      for (int t = 0; t < cnt; ++t) {
+        const int i = fwd ? r0 + t : r1 - 1 - t;
+        double a, b1, b2, r;
+        coefs(which, i, Rin, a, b1, b2, r);
+        const double v = a * (r - b1 * c1 - b2 * c2);
+        c2 = c1; c1 = v;
+        const double g1 = -a * (b1 * h11 + b2 * h21);
+        h21 = h11; h11 = g1;
+        const double g2 = -a * (b1 * h12 + b2 * h22);
+        h22 = h12; h12 = g2;
+      }
+      // step 2: inclusive scan of the maps in recurrence order
+#pragma unroll
+      for (int dlt = 1; dlt < 64; dlt <<= 1) {
+        const int src = fwd ? lane - dlt : lane + dlt;
+        const int sl = src < 0 ? 0 : (src > 63 ? 63 : src);
+        const double pc1 = __shfl(c1, sl), pc2 = __shfl(c2, sl);
+        const double p11 = __shfl(h11, sl), p12 = __shfl(h12, sl);
+        const double p21 = __shfl(h21, sl), p22 = __shfl(h22, sl);
+        if (src >= 0 && src <= 63) {
+          // mine o theirs: S -> c + H (pc + P S)
+          const double nc1 = c1 + h11 * pc1 + h12 * pc2;
+          const double nc2 = c2 + h21 * pc1 + h22 * pc2;
+          const double n11 = h11 * p11 + h12 * p21, n12 = h11 * p12 + h12 * p22;
+          const double n21 = h21 * p11 + h22 * p21, n22 = h21 * p12 + h22 * p22;
+          c1 = nc1; c2 = nc2; h11 = n11; h12 = n12; h21 = n21; h22 = n22;
+        }
+      }
+      const int prev = fwd ? lane - 1 : lane + 1;
+      const int psl = prev < 0 ? 0 : (prev > 63 ? 63 : prev);
+      double s1 = __shfl(c1, psl), s2 = __shfl(c2, psl);
+      if (prev < 0 || prev > 63) s1 = s2 = 0.0;
+      // step 3: sweep the block from its entry state
+      double xm = 0.0;
+      for (int t = 0; t < cnt; ++t) {
+        const int i = fwd ? r0 + t : r1 - 1 - t;
+        double a, b1, b2, r;
+        coefs(which, i, Rin, a, b1, b2, r);
+        const double v = a * (r - b1 * s1 - b2 * s2);
+        s2 = s1; s1 = v;
+        out[idx(i)] = add ? out[idx(i)] + v : v;
+        xm = fmax(xm, fabs(v));
+      }
+      __syncthreads();  // rows of other lanes are read by the next sweep
+      return xm;
+    };
+    auto wave_max = [&](double v) -> double {
+#pragma unroll
+      for (int dlt = 32; dlt >= 1; dlt >>= 1) v = fmax(v, __shfl_xor(v, dlt));
+      return v;
+    };
+    auto apply = [&](const double *R, bool add) -> double {
+      if (!tr) {
+        pass(0, R, Y, false);
+        return wave_max(pass(1, Y, rhs, add));
+      }
+      pass(2, R, Y, false);
+      return wave_max(pass(3, Y, rhs, add));
+    };
+    if (S.refine) {
+      for (int i = r0; i < r1; ++i) B0[idx(i)] = rhs[idx(i)];
+      __syncthreads();
+    }
+    apply(rhs, false);
+    for (int it = 0; it < S.refine; ++it) {
+      double xmax = 0.0;
+      for (int i = r0; i < r1; ++i) Y[idx(i)] = resid_row(i, xmax);
+      __syncthreads();
+      xmax = wave_max(xmax);
+      const double dmax = apply(Y, true);
+      if (dmax <= 1e-15 * xmax) break;
+    }
+    return;
+  }
+
+  // ---- thread path: one mode per thread, rows in register chunks ---------
   // x <- op(E)^{-1} r, r read from R (R may be Y: a chunk is read before it is
   // written), result added to (add) or stored into rhs; returns max |x|
   auto apply_inverse = [&](const double *R, bool add) -> double {
@@ -1299,40 +1434,28 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
     }
     return xm;
   };
-  if (S.refine)
-    for (int i = 0; i < nq; ++i) B0[idx(i)] = rhs[idx(i)];
+  if (S.refine) {
+    for (int i0 = 0; i0 < nq; i0 += CH) {
+      double v[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k)
+        if (i0 + k < nq) v[k] = rhs[idx(i0 + k)];
+#pragma unroll
+      for (int k = 0; k < CH; ++k)
+        if (i0 + k < nq) B0[idx(i0 + k)] = v[k];
+    }
+  }
   apply_inverse(rhs, false);
-  // refinement: r = b - op(E) x with E from the double-double time matrices,
-  // accumulated in double-double, then x += op(E)^{-1} r; stop once the
-  // correction is below 1e-15 of the solution (the next one would be below
-  // the rounding of x itself)
+  // refinement: x += op(E)^{-1} (b - op(E) x); stop once the correction is
+  // below 1e-15 of the solution (the next one would be below the rounding
+  // of x itself)
   for (int it = 0; it < S.refine; ++it) {
-#pragma clang fp contract(off)
     double xmax = 0.0;
     for (int i0 = 0; i0 < nq; i0 += CR) {
       double res[CR];
 #pragma unroll
-      for (int k = 0; k < CR; ++k) {
-        const int i = i0 + k;
-        if (i >= nq) continue;
-        dd acc = {B0[idx(i)], 0.0};
-#pragma unroll
-        for (int off = -2; off <= 2; ++off) {
-          const int jj = i + off;
-          if (jj < 0 || jj >= nq) continue;
-          // op(E)[i][jj] = E[i][jj] (or E[jj][i] for the transpose)
-          const int r = tr ? jj : i, c = tr ? 2 - off : off + 2;
-          const double x = rhs[idx(jj)];
-          if (off == 0) xmax = fmax(xmax, fabs(x));
-          dd t1 = triple(m, Ab[r * 5 + c], x);
-          dd t2 = triple(kap, Bb[r * 5 + c], x);
-          t1.l = fma(m * Al[r * 5 + c], x, t1.l);
-          t2.l = fma(kap * Bl[r * 5 + c], x, t2.l);
-          acc = dd_add(acc, {-t1.h, -t1.l});
-          acc = dd_add(acc, {-t2.h, -t2.l});
-        }
-        res[k] = acc.h + acc.l;
-      }
+      for (int k = 0; k < CR; ++k)
+        if (i0 + k < nq) res[k] = resid_row(i0 + k, xmax);
 #pragma unroll
       for (int k = 0; k < CR; ++k)
         if (i0 + k < nq) Y[idx(i0 + k)] = res[k];

@@ -63,6 +63,7 @@ struct SolveDesc {
   int b, a;              // time level, spatial level
   int refine;            // maximum refinement sweeps (double-double residual)
   int transpose;         // solve with the transposed time matrices
+  int wave;              // 1: one wave per mode (long time levels), 0: one thread
   double c2;             // wave speed squared (constant-speed path)
   long long thread0;     // first global thread, a multiple of 64 (one wave
                          // never spans two descriptors)
