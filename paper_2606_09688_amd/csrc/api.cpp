@@ -158,7 +158,7 @@ Geometry make_geometry(int d, int J, int ntf, int chunk_target_wg) {
   g.ntile = g.N >= g.TS ? g.N / g.TS : 1;
   g.R = std::min(g.lts, J - 1);
   g.A0 = J - g.R;
-  const int tb = d == 2 ? 2 : 8;
+  const int tb = 8;  // chunks are multiples of every batch size the kernels use
   const int ntileD = d == 2 ? g.ntile * g.ntile : g.ntile;
   int nch = std::max(1, chunk_target_wg / ntileD);
   int chunk = (ntf + nch - 1) / nch;
@@ -275,6 +275,12 @@ sg_status run_restrict(sg_problem *p, const Pass &P, const double *X, int stenci
   ra.sx = hx / 6.0;
   ra.sy = hy / 6.0;
   std::copy(P.h_ch.begin(), P.h_ch.end(), ra.ch);
+  for (const Channel &C : P.h_ch)
+    if (C.active) {
+      ra.safe_q0 = C.q0;
+      ra.safe_w = C.w;
+      break;
+    }
   ra.part = p->part;
   ra.coarse = g.A0 > 1 ? p->cpart : nullptr;
   if (ev_begin >= 0) MARK(p, ev_begin, s);
@@ -294,6 +300,12 @@ sg_status run_prolong(sg_problem *p, const Pass &P, const double *base, double *
   ProlongArgs pa{};
   pa.g = g;
   std::copy(P.h_ch.begin(), P.h_ch.end(), pa.ch);
+  for (const Channel &C : P.h_ch)
+    if (C.active) {
+      pa.safe_q0 = C.q0;
+      pa.safe_w = C.w;
+      break;
+    }
   pa.coarse = nullptr;
   if (g.A0 > 1 && P.n_crs) {
     HIPCHK(launch_prolong_coarse(g, P.d_ch, p->Cpro, stencil, s));

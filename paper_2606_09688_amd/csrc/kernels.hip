@@ -109,8 +109,13 @@ __device__ __forceinline__ double full_weight(const double *src, int PN, int jx,
   }
 }
 
-template <int D, int TS, int TB, int NT, int STENCIL>
-__global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
+// NC0: number of finest-level channels (2 only for the adjoint restriction,
+// whose second finest channel is the time sum of the cotangent)
+#ifndef SG_WPE
+#define SG_WPE 1
+#endif
+template <int D, int TS, int TB, int NT, int STENCIL, int NC0>
+__global__ void __launch_bounds__(NT, SG_WPE) k_restrict(const RestrictArgs A) {
   using SH = Shape<D, TS, 0>;
   using PD = Pad<D, TS, 0>;
   constexpr int LTS = SH::LTS;
@@ -162,17 +167,13 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
   // fine points of this thread: column strip x, rows y0 .. y0+EPT-1 (2-D)
   const int fx = (D == 2) ? tid % TS : tid;
   const int fy0 = (D == 2) ? (tid / TS) * EPT : 0;
-  double fmask[EPT];
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int px = TS * tx + fx, py = TS * ty + fy0 + e;
-    fmask[e] = (interior(px, g.nxf) && (D == 1 || interior(py, g.nxf))) ? 1.0 : 0.0;
-  }
+  auto fine_in = [&](int e) {
+    return interior(TS * tx + fx, g.nxf) && (D == 1 || interior(TS * ty + fy0 + e, g.nxf));
+  };
   // owned upper nodes
   Owned<D, TS, 0> own[2];
   own[0].set(tid);
   own[1].set(tid + NT);
-
   // tap entry staged by this thread: channel li = tid / (TB+1), slab offset my_s
   const int my_s = tid % (TB + 1);
   const int *my_q0 = nullptr;
@@ -187,49 +188,55 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
       }
     }
   }
-  // input gather offsets (slab-relative, -1 outside the interior)
-  int in_s[PF];
-  int in_off[PF];
-#pragma unroll
-  for (int e = 0; e < PF; ++e) {
+  // input gather of staged element e: slab offset and slab-relative
+  // position (-1 outside the interior); recomputed rather than kept in
+  // registers
+  auto in_slab = [&](int e) {
     const int idx = tid + e * NT;
-    const int s = idx / INSZ, loc = idx - s * INSZ;
+    return idx < TB * INSZ ? idx / INSZ : TB;
+  };
+  auto in_pos = [&](int e) {
+    const int idx = tid + e * NT;
+    const int loc = idx % INSZ;
     const int ix = loc % NIN, iy = loc / NIN;
     const int px = TS * tx - 1 + ix;
     const int py = TS * ty - 1 + iy;
-    in_s[e] = idx < TB * INSZ ? s : TB;
-    in_off[e] = (interior(px, g.nxf) && (D == 1 || interior(py, g.nxf)))
-                    ? (px - 1) + (D == 2 ? (py - 1) * g.nxf : 0)
-                    : -1;
-  }
+    return (interior(px, g.nxf) && (D == 1 || interior(py, g.nxf)))
+               ? (px - 1) + (D == 2 ? (py - 1) * g.nxf : 0)
+               : -1;
+  };
   double pin[PF];
   int pq = -1;
   double pw0 = 0.0, pw1 = 0.0, pw2 = 0.0;
+  // Loads are issued unconditionally from clamped, valid addresses and the
+  // unwanted results are discarded with selects: a load inside a divergent
+  // branch makes the compiler wait for every earlier load before the next
+  // one, which would serialise the prefetch.
+  const int *tq0 = my_q0 != nullptr ? my_q0 : A.safe_q0;
+  const double *tw = my_q0 != nullptr ? my_w : A.safe_w;
+  // (the selects happen when the batch is staged, a loop iteration later)
+  auto in_ok = [&](int e, int nb) { return in_slab(e) < min(TB, n1 - nb) && in_pos(e) >= 0; };
+  auto tap_ok = [&](int nb) {
+    const int n = nb - 1 + my_s;
+    return my_q0 != nullptr && n >= n0 && n < n1;
+  };
   auto fetch = [&](int nb) {
-    const int cnt = min(TB, n1 - nb);
 #pragma unroll
     for (int e = 0; e < PF; ++e)
-      pin[e] = (in_s[e] < cnt && in_off[e] >= 0) ? A.X[(long long)(nb + in_s[e]) * nsp + in_off[e]]
-                                                 : 0.0;
-    pq = -1;
-    pw0 = pw1 = pw2 = 0.0;
-    const int n = nb - 1 + my_s;
-    if (my_q0 != nullptr && n >= n0 && n < n1) {
-      pq = my_q0[n];
-      if (my_s > 0) {
-        pw0 = my_w[3 * n];
-        pw1 = my_w[3 * n + 1];
-        pw2 = my_w[3 * n + 2];
-      }
-    }
+      pin[e] = A.X[in_ok(e, nb) ? (long long)(nb + in_slab(e)) * nsp + in_pos(e) : 0];
+    const int nc = tap_ok(nb) ? nb - 1 + my_s : 0;
+    pq = tq0[nc];
+    pw0 = tw[3 * nc];
+    pw1 = tw[3 * nc + 1];
+    pw2 = tw[3 * nc + 2];
   };
 
-  double racc0[EPT][2][3];
+  double racc0[EPT][NC0][3];
   double racc[2][2][3];
 #pragma unroll
   for (int e = 0; e < EPT; ++e)
 #pragma unroll
-    for (int k = 0; k < 2; ++k) racc0[e][k][0] = racc0[e][k][1] = racc0[e][k][2] = 0.0;
+    for (int k = 0; k < NC0; ++k) racc0[e][k][0] = racc0[e][k][1] = racc0[e][k][2] = 0.0;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -250,15 +257,16 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
 #pragma unroll
     for (int e = 0; e < PF; ++e) {
       const int idx = tid + e * NT;
-      if (idx < TB * INSZ) s_in[idx] = pin[e];
+      if (idx < TB * INSZ) s_in[idx] = in_ok(e, nb) ? pin[e] : 0.0;
     }
     if (tid < NTAP) {
       const int li = tid / (TB + 1);
-      s_q[li][my_s] = pq;
+      const bool ok = tap_ok(nb);
+      s_q[li][my_s] = ok ? pq : -1;
       if (my_s > 0) {
-        s_w[li][my_s - 1][0] = pw0;
-        s_w[li][my_s - 1][1] = pw1;
-        s_w[li][my_s - 1][2] = pw2;
+        s_w[li][my_s - 1][0] = ok ? pw0 : 0.0;
+        s_w[li][my_s - 1][1] = ok ? pw1 : 0.0;
+        s_w[li][my_s - 1][2] = ok ? pw2 : 0.0;
       }
     }
     __syncthreads();
@@ -268,7 +276,8 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
       const double *in = s_in + s * INSZ;
       double m[EPT];
       if (D == 1) {
-        m[0] = STENCIL ? A.sx * (in[fx] + in[fx + 2] + 4.0 * in[fx + 1]) * fmask[0] : in[fx + 1];
+        m[0] = STENCIL ? (fine_in(0) ? A.sx * (in[fx] + in[fx + 2] + 4.0 * in[fx + 1]) : 0.0)
+                       : in[fx + 1];
       } else if (STENCIL) {
         double h[EPT + 2];
 #pragma unroll
@@ -278,7 +287,8 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
         }
         const double sxy = A.sx * A.sy;
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) m[e] = sxy * (h[e] + h[e + 2] + 4.0 * h[e + 1]) * fmask[e];
+        for (int e = 0; e < EPT; ++e)
+          m[e] = fine_in(e) ? sxy * (h[e] + h[e + 2] + 4.0 * h[e + 1]) : 0.0;
       } else {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) m[e] = in[(fy0 + e + 1) * NIN + fx + 1];
@@ -290,7 +300,7 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
         else l0[(fy0 + e + 1) * PD::pn(0) + fx + 1] = m[e];
       }
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
+      for (int k = 0; k < NC0; ++k) {
         if (!A.ch[(g.J - 1) * 2 + k].active) continue;
         const double w0 = s_w[k][s][0], w1 = s_w[k][s][1], w2 = s_w[k][s][2];
 #pragma unroll
@@ -339,7 +349,7 @@ __global__ void __launch_bounds__(NT) k_restrict(const RestrictArgs A) {
   // final flush of the open time nodes (s_q still holds the last batch; the
   // level-J channels have q0 = 0 throughout, so their nodes are q = 0, 1, 2)
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < NC0; ++k) {
     const Channel &C = A.ch[(g.J - 1) * 2 + k];
     if (!C.active) continue;
 #pragma unroll
@@ -564,8 +574,9 @@ __global__ void k_prolong_coarse(const Geometry g, const Channel *__restrict__ c
   Cout[gid] = acc;
 }
 
-template <int D, int TS, int TB, int NT, int MODE>
-__global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
+// NC0: number of finest-level channels (2 only for the u0/v0 field pass)
+template <int D, int TS, int TB, int NT, int MODE, int NC0>
+__global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
   using SH = Shape<D, TS, MODE>;
   constexpr int LTS = SH::LTS;
   constexpr int L0 = SH::size(0);
@@ -648,7 +659,7 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
   }
   // level-J channels belong to time level b = 1 (q0 = 0 on every slab)
   const int lo0x = tile_lo(TS, tx, 0, MODE), lo0y = tile_lo(TS, ty, 0, MODE);
-  double rc[EPT0][2][3];
+  double rc[EPT0][NC0][3];
 #pragma unroll
   for (int e = 0; e < EPT0; ++e) {
     const int p = tid + e * NT;
@@ -657,7 +668,7 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
                         ? (Px - 1) + (D == 2 ? (Py - 1) * g.nxf : 0)
                         : -1;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < NC0; ++k) {
       const Channel &C = A.ch[(g.J - 1) * 2 + k];
       rc[e][k][0] = rc[e][k][1] = rc[e][k][2] = 0.0;
       if (!C.active) continue;
@@ -707,19 +718,22 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
                                   : (1 << g.A0) - 1;
   int pq = -1;
   double pw0 = 0.0, pw1 = 0.0, pw2 = 0.0, pco = 0.0;
-  auto fetch_taps = [&](int nb) {
-    pq = -1;
-    pw0 = pw1 = pw2 = 0.0;
+  // unconditional loads from valid addresses, results selected (see k_restrict)
+  const int *tq0 = my_q0 != nullptr ? my_q0 : A.safe_q0;
+  const double *tw = my_q0 != nullptr ? my_w : A.safe_w;
+  const double *cbase = use_coarse ? A.coarse : A.safe_w;
+  auto tap_ok = [&](int nb) {
     const int n = nb - 1 + my_s;
-    if (my_q0 != nullptr && n >= n0 && n < n1) {
-      pq = my_q0[n];
-      if (my_s > 0) {
-        pw0 = my_w[3 * n];
-        pw1 = my_w[3 * n + 1];
-        pw2 = my_w[3 * n + 2];
-      }
-    }
-    pco = (co_off >= 0 && nb + co_s < n1) ? A.coarse[(long long)(nb + co_s) * nsp0 + co_off] : 0.0;
+    return my_q0 != nullptr && n >= n0 && n < n1;
+  };
+  auto co_ok = [&](int nb) { return co_off >= 0 && nb + co_s < n1; };
+  auto fetch_taps = [&](int nb) {
+    const int nc = tap_ok(nb) ? nb - 1 + my_s : 0;
+    pq = tq0[nc];
+    pw0 = tw[3 * nc];
+    pw1 = tw[3 * nc + 1];
+    pw2 = tw[3 * nc + 2];
+    pco = cbase[co_ok(nb) ? (long long)(nb + co_s) * nsp0 + co_off : 0];
   };
 
   fetch_taps(n0);
@@ -727,40 +741,45 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
     const int cnt = min(TB, n1 - nb);
     if (tid < NTAP) {
       const int li = tid / (TB + 1);
-      s_q[li][my_s] = pq;
+      const bool ok = tap_ok(nb);
+      s_q[li][my_s] = ok ? pq : -1;
       if (my_s > 0) {
-        s_w[li][my_s - 1][0] = pw0;
-        s_w[li][my_s - 1][1] = pw1;
-        s_w[li][my_s - 1][2] = pw2;
+        s_w[li][my_s - 1][0] = ok ? pw0 : 0.0;
+        s_w[li][my_s - 1][1] = ok ? pw1 : 0.0;
+        s_w[li][my_s - 1][2] = ok ? pw2 : 0.0;
       }
     } else if (co_i < TB * SZR) {
-      s_co[co_i] = pco;
+      s_co[co_i] = co_ok(nb) ? pco : 0.0;
     }
     __syncthreads();
     if (nb + TB < n1) fetch_taps(nb + TB);
-    // phase A: owners evaluate their node in time (register windows)
+    // phase A: owners evaluate their node in time (register windows); the
+    // level loop is unrolled so that channel fields are wave-uniform
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int r = own[i].r;
-      if (r < 1 || r > R) continue;
-      for (int s = 0; s < cnt; ++s) {
-        double v = (r == R && use_coarse) ? s_co[s * SZR + own[i].j] : 0.0;
+    for (int r = 1; r <= LTS; ++r) {
+      if (r > R) break;
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
-          if (!C.active) continue;
-          const int li = 2 * r + k;
-          if (s_q[li][s + 1] > cq[i][k]) {  // advance by one time index
-            cq[i][k] += 1;
-            cw[i][k][0] = cw[i][k][1];
-            cw[i][k][1] = cw[i][k][2];
-            cw[i][k][2] = cw[i][k][3];
-            cw[i][k][3] = coef(C, cq[i][k] + 3, coff[i]);
+      for (int i = 0; i < 2; ++i) {
+        if (own[i].r != r) continue;
+        for (int s = 0; s < cnt; ++s) {
+          double v = (r == R && use_coarse) ? s_co[s * SZR + own[i].j] : 0.0;
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
+            if (!C.active) continue;
+            const int li = 2 * r + k;
+            if (s_q[li][s + 1] > cq[i][k]) {  // advance by one time index
+              cq[i][k] += 1;
+              cw[i][k][0] = cw[i][k][1];
+              cw[i][k][1] = cw[i][k][2];
+              cw[i][k][2] = cw[i][k][3];
+              cw[i][k][3] = coef(C, cq[i][k] + 3, coff[i]);
+            }
+            v += C.scale * (s_w[li][s][0] * cw[i][k][0] + s_w[li][s][1] * cw[i][k][1] +
+                            s_w[li][s][2] * cw[i][k][2]);
           }
-          v += C.scale * (s_w[li][s][0] * cw[i][k][0] + s_w[li][s][1] * cw[i][k][1] +
-                          s_w[li][s][2] * cw[i][k][2]);
+          s_v[s * UP + SH::offset(r) - SH::size(0) + own[i].j] = v;
         }
-        s_v[s * UP + SH::offset(r) - SH::size(0) + own[i].j] = v;
       }
     }
     __syncthreads();
@@ -795,7 +814,7 @@ __global__ void __launch_bounds__(NT) k_prolong(const ProlongArgs A) {
 #pragma unroll
       for (int e = 0; e < EPT0; ++e) tv[e] = 0.0;
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
+      for (int k = 0; k < NC0; ++k) {
         const Channel &C = A.ch[(g.J - 1) * 2 + k];
         if (!C.active) continue;
         const double w0 = s_w[k][s][0], w1 = s_w[k][s][1], w2 = s_w[k][s][2];
@@ -1481,22 +1500,39 @@ static inline unsigned blocks_for(long long n, int bs) {
   return (unsigned)((n + bs - 1) / bs);
 }
 
-constexpr int kTS2 = 32, kTB2 = 2, kTS1 = 256, kTB1 = 8, kNT = 256;
+// tile side and slabs per batch (2-D, 1-D); the plan's time chunks are
+// multiples of 8 slabs
+// (measured on the 2-D level-10 workload: restriction is fastest with one
+// slab per batch, prolongation with four; both are bound by the latency
+// that their two resident waves per SIMD can hide)
+#ifndef SG_TB2
+#define SG_TB2 1
+#endif
+#ifndef SG_TB2P
+#define SG_TB2P 4
+#endif
+constexpr int kTS2 = 32, kTB2 = SG_TB2, kTB2P = SG_TB2P, kTS1 = 256, kTB1 = 8, kNT = 256;
 
 hipError_t launch_restrict(const RestrictArgs &a, hipStream_t s) {
   const int nt = a.g.d == 2 ? a.g.ntile * a.g.ntile : a.g.ntile;
   dim3 grid(nt, a.g.nchunk);
+  const bool two = a.ch[(a.g.J - 1) * 2 + 1].active != 0;
+#define SG_RESTRICT(D, TS, TB, ST, NC)                                                     \
+  hipLaunchKernelGGL((k_restrict<D, TS, TB, kNT, ST, NC>), grid, dim3(kNT), 0, s, a)
   if (a.g.d == 2) {
-    if (a.stencil)
-      hipLaunchKernelGGL((k_restrict<2, kTS2, kTB2, kNT, 1>), grid, dim3(kNT), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_restrict<2, kTS2, kTB2, kNT, 0>), grid, dim3(kNT), 0, s, a);
+    if (a.stencil) {
+      if (two) SG_RESTRICT(2, kTS2, kTB2, 1, 2); else SG_RESTRICT(2, kTS2, kTB2, 1, 1);
+    } else {
+      if (two) SG_RESTRICT(2, kTS2, kTB2, 0, 2); else SG_RESTRICT(2, kTS2, kTB2, 0, 1);
+    }
   } else {
-    if (a.stencil)
-      hipLaunchKernelGGL((k_restrict<1, kTS1, kTB1, kNT, 1>), grid, dim3(kNT), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_restrict<1, kTS1, kTB1, kNT, 0>), grid, dim3(kNT), 0, s, a);
+    if (a.stencil) {
+      if (two) SG_RESTRICT(1, kTS1, kTB1, 1, 2); else SG_RESTRICT(1, kTS1, kTB1, 1, 1);
+    } else {
+      if (two) SG_RESTRICT(1, kTS1, kTB1, 0, 2); else SG_RESTRICT(1, kTS1, kTB1, 0, 1);
+    }
   }
+#undef SG_RESTRICT
   return hipGetLastError();
 }
 
@@ -1551,17 +1587,23 @@ hipError_t launch_prolong_coarse(const Geometry &g, const Channel *ch, double *C
 hipError_t launch_prolong(const ProlongArgs &a, hipStream_t s) {
   const int nt = a.g.d == 2 ? a.g.ntile * a.g.ntile : a.g.ntile;
   dim3 grid(nt, a.g.nchunk);
+  const bool two = a.ch[(a.g.J - 1) * 2 + 1].active != 0;
+#define SG_PROLONG(D, TS, TB, MO, NC)                                                      \
+  hipLaunchKernelGGL((k_prolong<D, TS, TB, kNT, MO, NC>), grid, dim3(kNT), 0, s, a)
   if (a.g.d == 2) {
-    if (a.stencil)
-      hipLaunchKernelGGL((k_prolong<2, kTS2, kTB2, kNT, 1>), grid, dim3(kNT), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_prolong<2, kTS2, kTB2, kNT, 0>), grid, dim3(kNT), 0, s, a);
+    if (a.stencil) {
+      if (two) SG_PROLONG(2, kTS2, kTB2P, 1, 2); else SG_PROLONG(2, kTS2, kTB2P, 1, 1);
+    } else {
+      if (two) SG_PROLONG(2, kTS2, kTB2P, 0, 2); else SG_PROLONG(2, kTS2, kTB2P, 0, 1);
+    }
   } else {
-    if (a.stencil)
-      hipLaunchKernelGGL((k_prolong<1, kTS1, kTB1, kNT, 1>), grid, dim3(kNT), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_prolong<1, kTS1, kTB1, kNT, 0>), grid, dim3(kNT), 0, s, a);
+    if (a.stencil) {
+      if (two) SG_PROLONG(1, kTS1, kTB1, 1, 2); else SG_PROLONG(1, kTS1, kTB1, 1, 1);
+    } else {
+      if (two) SG_PROLONG(1, kTS1, kTB1, 0, 2); else SG_PROLONG(1, kTS1, kTB1, 0, 1);
+    }
   }
+#undef SG_PROLONG
   return hipGetLastError();
 }
 

@@ -21,6 +21,8 @@ struct RestrictArgs {
   double sx, sy;         // h_x/6, h_y/6 of the finest mesh
   double *part;          // partial blocks of the in-tile levels
   double *coarse;        // per-slab partials at level A0 (if A0 > 1)
+  const int *safe_q0;    // tap tables of some active channel: a valid address
+  const double *safe_w;  // for loads whose result is discarded
   Channel ch[kChanMax];  // channel (a-1)*2+k, entries >= 2J unused
 };
 
@@ -34,6 +36,8 @@ struct ProlongArgs {
   int accumulate;        // 1: add to existing out
   int stencil;           // 0 none, 1 mass
   double sx, sy;
+  const int *safe_q0;    // tap tables of some active channel (valid addresses)
+  const double *safe_w;
   Channel ch[kChanMax];
 };
 
