@@ -110,6 +110,7 @@ struct sg_problem {
   double *part = nullptr;          // partial blocks
   double *cpart = nullptr;         // per-slab coarse partials
   double *S0 = nullptr;            // coarse level-A0 arrays
+  double *SL = nullptr;            // their restrictions to the levels a < A0
   double *Cpro = nullptr;          // prolongation coarse array
   // passes
   Pass load, prol, adjr, adjp, fieldr, fieldp;
@@ -289,7 +290,8 @@ sg_status run_restrict(sg_problem *p, const Pass &P, const double *X, int stenci
   if (P.n_red) HIPCHK(launch_reduce(g, P.d_ch, p->part, P.d_red, P.n_red, P.tot_red, s));
   if (g.A0 > 1 && P.n_crs) {
     HIPCHK(launch_coarse_assemble(g, p->cpart, p->S0, s));
-    HIPCHK(launch_coarse_restrict(g, P.d_ch, p->S0, P.d_crs, P.n_crs, P.tot_crs, s));
+    HIPCHK(launch_coarse_pyramid(g, p->S0, p->SL, s));
+    HIPCHK(launch_coarse_restrict(g, P.d_ch, p->SL, P.d_crs, P.n_crs, P.tot_crs, s));
   }
   return SG_OK;
 }
@@ -715,7 +717,15 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
     const long long szR = d == 2 ? (long long)nR * nR : nR;
     const long long na0 = (1 << geo.A0) - 1, nsp0 = d == 2 ? na0 * na0 : na0;
     const long long need = std::max((long long)ntileD * ntf * szR, 1LL);
+    long long ncl = 0;  // coarse levels below A0, per slab
+    for (int a = 1; a < geo.A0; ++a) {
+      const long long n = (1 << a) - 1;
+      ncl += d == 2 ? n * n : n;
+    }
+    if (nsp0 > kCoarseMax)
+      return bail(fail(SG_ENOTSUP, "level too fine for the coarse-level pyramid"));
     if (!(p->cpart = p->dalloc<double>(need)) || !(p->S0 = p->dalloc<double>(ntf * nsp0)) ||
+        !(p->SL = p->dalloc<double>(std::max(1LL, ntf * ncl))) ||
         !(p->Cpro = p->dalloc<double>(ntf * nsp0)))
       return bail(fail(SG_ENOMEM, "hipMalloc of coarse buffers failed"));
   }
@@ -787,8 +797,13 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
       L.c1 = comp_index(a, 1);
       L.fv = p->fv_lv[a];
       L.fu = p->fu_lv[a];
+      int nqmax = 0;
+      if (L.c0 >= 0) nqmax = std::max(nqmax, p->comps[L.c0].nq);
+      if (L.c1 >= 0) nqmax = std::max(nqmax, p->comps[L.c1].nq);
+      L.wave = nqmax >= 64 ? 1 : 0;
+      tt = (tt + 63) / 64 * 64;
       L.start = tt;
-      tt += L.nsp;
+      tt += L.wave ? 64LL * L.nsp : L.nsp;
       lv.push_back(L);
     }
     if ((st = upload(p, lv, &p->d_lev))) return bail(st);

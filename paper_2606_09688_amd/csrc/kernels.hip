@@ -473,11 +473,60 @@ __device__ __forceinline__ int lower_bound_q(const int *q0, int n, int v) {
   return lo;
 }
 
-// Channels of the levels a < A0: gather over the slabs that touch time node q
-// and over the level-A0 nodes in the support of the level-a hat.
+// Offset of level a inside a slab's coarse-level block (levels 1 .. A0-1).
+__host__ __device__ inline long long coarse_off(int d, int a) {
+  long long o = 0;
+  for (int l = 1; l < a; ++l) {
+    const long long n = (1 << l) - 1;
+    o += d == 2 ? n * n : n;
+  }
+  return o;
+}
+
+// One block per slab: full weighting of S0[n] (level A0) down to level 1.
+template <int D>
+__global__ void __launch_bounds__(256) k_coarse_pyramid(const Geometry g,
+                                                        const double *__restrict__ S0,
+                                                        double *__restrict__ SL) {
+  constexpr int MAXN = kCoarseMax;  // doubles per ping-pong level (checked by the plan)
+  __shared__ double s_a[MAXN], s_b[MAXN];
+  const int n = blockIdx.x;
+  const int A0 = g.A0;
+  const int n0a = (1 << A0) - 1;
+  const long long nsp0 = (D == 2) ? (long long)n0a * n0a : n0a;
+  const long long tot = coarse_off(D, A0);
+  for (int i = threadIdx.x; i < nsp0; i += blockDim.x) s_a[i] = S0[(long long)n * nsp0 + i];
+  __syncthreads();
+  double *cur = s_a, *nxt = s_b;
+  for (int a = A0 - 1; a >= 1; --a) {
+    const int na = (1 << a) - 1, nf = (1 << (a + 1)) - 1;
+    const int nspa = (D == 2) ? na * na : na;
+    for (int i = threadIdx.x; i < nspa; i += blockDim.x) {
+      const int Kx = i % na + 1, Ky = (D == 2) ? i / na + 1 : 0;  // level-a node
+      double v = 0.0;
+      for (int dy = (D == 2 ? -1 : 0); dy <= (D == 2 ? 1 : 0); ++dy) {
+        const double wy = dy == 0 ? 1.0 : 0.5;
+        const int fy = 2 * Ky + dy;  // level a+1 node, interior 1..nf
+        double row = 0.0;
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int fx = 2 * Kx + dx;
+          row += (dx == 0 ? 1.0 : 0.5) * cur[(D == 2 ? (fy - 1) * nf : 0) + fx - 1];
+        }
+        v += wy * row;
+      }
+      nxt[i] = v;
+      SL[(long long)n * tot + coarse_off(D, a) + i] = v;
+    }
+    __syncthreads();
+    double *t = cur; cur = nxt; nxt = t;
+  }
+}
+
+// Channels of the levels a < A0: sum over the slabs that touch time node q
+// of the tap weight times the slab's level-a restriction.
 template <int D>
 __global__ void k_coarse_restrict(const Geometry g, const Channel *__restrict__ ch,
-                                  const double *__restrict__ S0,
+                                  const double *__restrict__ SL,
                                   const WorkItem *__restrict__ items, int nitems,
                                   long long total) {
   const long long gid = gid64();
@@ -491,31 +540,14 @@ __global__ void k_coarse_restrict(const Geometry g, const Channel *__restrict__ 
   const long long nsp = (D == 2) ? (long long)na * na : na;
   const int q = (int)(loc / nsp);
   const long long K = loc - (long long)q * nsp;
-  const int Px = (int)(K % na) + 1;
-  const int Py = (D == 2) ? (int)(K / na) + 1 : 0;
-  const int f = 1 << (g.A0 - a);
-  const int n0a = (1 << g.A0) - 1;
-  const long long nsp0 = (D == 2) ? (long long)n0a * n0a : n0a;
+  const long long tot = coarse_off(D, g.A0), off = coarse_off(D, a) + K;
   const int nlo = lower_bound_q(C.q0, g.ntf, q - 2);
   const int nhi = lower_bound_q(C.q0, g.ntf, q + 1);  // exclusive
   double acc = 0.0;
   for (int n = nlo; n < nhi; ++n) {
     const int k = q - C.q0[n];
     if (k < 0 || k > 2) continue;
-    const double wq = C.w[3 * n + k];
-    if (wq == 0.0) continue;
-    const double *S = S0 + (long long)n * nsp0;
-    double val = 0.0;
-    for (int y = (D == 2 ? (Py - 1) * f + 1 : 0); y <= (D == 2 ? (Py + 1) * f - 1 : 0); ++y) {
-      const double wy = (D == 2) ? 1.0 - (double)abs(y - Py * f) / f : 1.0;
-      double row = 0.0;
-      for (int x = (Px - 1) * f + 1; x <= (Px + 1) * f - 1; ++x) {
-        const double wx = 1.0 - (double)abs(x - Px * f) / f;
-        row += wx * S[(D == 2 ? (long long)(y - 1) * n0a : 0) + (x - 1)];
-      }
-      val += wy * row;
-    }
-    acc += wq * val;
+    acc += C.w[3 * n + k] * SL[(long long)n * tot + off];
   }
   C.data[loc] = C.scale * acc;
 }
@@ -988,7 +1020,9 @@ __global__ void k_post_adjoint(const CompDesc *__restrict__ cd, int ncomp,
   C.data[loc] = v;
 }
 
-// fv_a[K] = sum_c psi_0'(0) z_c[0][K];  fu_a[K] = sum_c sum_i g_b[i] z_c[i][K]
+// fv_a[K] = sum_c psi_0'(0) z_c[0][K];  fu_a[K] = sum_c sum_i g_b[i] z_c[i][K].
+// Levels whose components have long time levels use one wave per node (lanes
+// split the time sum, then a shuffle reduction); the others one thread.
 __global__ void k_adjoint_fields(const LevelDesc *__restrict__ ld, int nlev,
                                  long long total, const CompDesc *__restrict__ cd,
                                  const KernelTables *__restrict__ kt) {
@@ -997,17 +1031,23 @@ __global__ void k_adjoint_fields(const LevelDesc *__restrict__ ld, int nlev,
   int l = 0;
   while (l + 1 < nlev && ld[l + 1].start <= gid) ++l;
   const LevelDesc &L = ld[l];
-  const long long K = gid - L.start;
+  const long long rel = gid - L.start;
+  const int lane = L.wave ? (int)(rel & 63) : 0, step = L.wave ? 64 : 1;
+  const long long K = L.wave ? rel >> 6 : rel;
+  if (K >= L.nsp) return;  // whole waves in wave levels
   double fv = 0.0, fu = 0.0;
   for (int t = 0; t < 2; ++t) {
     const int c = t == 0 ? L.c0 : L.c1;
     if (c < 0) continue;
     const CompDesc &C = cd[c];
-    fv += kt->Dlo[C.b][0] * C.z[K];
+    if (lane == 0) fv += kt->Dlo[C.b][0] * C.z[K];
     const double *gb = kt->g[C.b];
-    double s = 0.0;
-    for (int i = 0; i < C.nq; ++i) s += gb[i] * C.z[(long long)i * C.nsp + K];
-    fu += s;
+    for (int i = lane; i < C.nq; i += step) fu += gb[i] * C.z[(long long)i * C.nsp + K];
+  }
+  if (L.wave) {
+#pragma unroll
+    for (int dlt = 32; dlt >= 1; dlt >>= 1) fu += __shfl_xor(fu, dlt);
+    if (lane != 0) return;
   }
   L.fv[K] = fv;
   L.fu[K] = fu;
@@ -1560,16 +1600,26 @@ hipError_t launch_coarse_assemble(const Geometry &g, const double *cp, double *S
   return hipGetLastError();
 }
 
-hipError_t launch_coarse_restrict(const Geometry &g, const Channel *ch, const double *S0,
+hipError_t launch_coarse_pyramid(const Geometry &g, const double *S0, double *SL,
+                                 hipStream_t s) {
+  if (g.A0 <= 1) return hipSuccess;
+  if (g.d == 2)
+    hipLaunchKernelGGL(k_coarse_pyramid<2>, dim3(g.ntf), dim3(256), 0, s, g, S0, SL);
+  else
+    hipLaunchKernelGGL(k_coarse_pyramid<1>, dim3(g.ntf), dim3(256), 0, s, g, S0, SL);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_restrict(const Geometry &g, const Channel *ch, const double *SL,
                                   const WorkItem *items, int nitems, long long total,
                                   hipStream_t s) {
   if (total == 0) return hipSuccess;
   if (g.d == 2)
     hipLaunchKernelGGL(k_coarse_restrict<2>, dim3(blocks_for(total, 128)), dim3(128), 0, s,
-                       g, ch, S0, items, nitems, total);
+                       g, ch, SL, items, nitems, total);
   else
     hipLaunchKernelGGL(k_coarse_restrict<1>, dim3(blocks_for(total, 128)), dim3(128), 0, s,
-                       g, ch, S0, items, nitems, total);
+                       g, ch, SL, items, nitems, total);
   return hipGetLastError();
 }
 

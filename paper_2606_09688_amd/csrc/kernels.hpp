@@ -96,7 +96,9 @@ struct LevelDesc {       // adjoint fields of one spatial level
   int c0, c1;            // component indices at this level (-1 if none)
   double *fv;            // sum_c psi_0'(0) z_c[0]
   double *fu;            // sum_c sum_i g_c[i] z_c[i]
-  long long start;
+  int wave;              // 1: one wave per node (long time sums), 0: one thread
+  int pad;
+  long long start;       // first global thread (a multiple of 64 for wave levels)
 };
 
 // launch wrappers (return hipError_t of the launch)
@@ -106,8 +108,14 @@ hipError_t launch_reduce(const Geometry &g, const Channel *ch, const double *par
                          hipStream_t s);
 hipError_t launch_coarse_assemble(const Geometry &g, const double *coarse_part,
                                   double *S0, hipStream_t s);
+// largest level-A0 array (nodes) the coarse pyramid kernel holds in LDS
+constexpr int kCoarseMax = 4096;
+// per-slab restriction of the level-A0 array S0[n] to the levels a < A0:
+// SL[n][off_a + K], off_a = sum_{a' < a} (2^a' - 1)^d
+hipError_t launch_coarse_pyramid(const Geometry &g, const double *S0, double *SL,
+                                 hipStream_t s);
 hipError_t launch_coarse_restrict(const Geometry &g, const Channel *ch,
-                                  const double *S0, const WorkItem *items,
+                                  const double *SL, const WorkItem *items,
                                   int nitems, long long total, hipStream_t s);
 hipError_t launch_prolong_coarse(const Geometry &g, const Channel *ch,
                                  double *C, int mode, hipStream_t s);
