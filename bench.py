@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of one fine array (counter scaling)")
     return ap.parse_args()
 
 
@@ -71,8 +73,50 @@ def cpu_baseline(spec, data, budget_s):
                        f"({dofs} DoFs, {el:.1f} s, smallest first, 1 BLAS thread)")}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c3_L10.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2606_09688_amd", "csrc", "kernels.hip")
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when there is none or the kernels changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_hip_sha256") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch", {}).get(kernel)
+
+
+def copy_calibration(args):
+    """A plain device copy of one fine array (known bytes), for scaling the
+    FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    import paper_2606_09688_amd as sg
+    spec, _ = __import__("workloads").c3(L=args.L, with_cotangent=False)
+    n = spec.nt() * spec.nx() ** spec.d
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": 8 * n, "bytes_written": 8 * n,
+                                           "launches": 3, "library": sg.__name__}}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -94,23 +138,44 @@ def main():
     nfull = sv.n_full
 
     # ---- batched: forward + adjoint in one captured graph ------------------
+    # The stage events are captured as event-record nodes, so every replay
+    # times its own kernels on the launch stream; each step is synchronised
+    # to read them (the sync is inside the timed region).
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(15)]
+    sv.set_events(ev)
+    kern_ev = {"k_restrict (load of f)": (1, 2), "k_prolong (combination into U)": (5, 6),
+               "k_restrict (cotangent g)": (8, 9), "k_prolong (df, with mass stencil)": (12, 13)}
+    kern_t = {k: 0.0 for k in kern_ev}
+    graph_events = True
+    try:
+        with torch.cuda.stream(stream):
+            sv.capture(f, u0, v0, U, g, df, du0, dv0, stream=stream)
+    except sg.SGError:
+        graph_events = False  # runtime without captured event records
+        sv.set_events(None)
+        with torch.cuda.stream(stream):
+            sv.capture(f, u0, v0, U, g, df, du0, dv0, stream=stream)
     with torch.cuda.stream(stream):
-        sv.capture(f, u0, v0, U, g, df, du0, dv0, stream=stream)
         for _ in range(args.warmup):
             sv.replay(stream=stream)
     stream.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        for _ in range(args.steps):
+    for _ in range(args.steps):
+        with torch.cuda.stream(stream):
             sv.replay(stream=stream)
+        if graph_events:
+            stream.synchronize()
+            for k, (a, b) in kern_ev.items():
+                kern_t[k] += ev[a].elapsed_time(ev[b]) * 1e-3
     stream.synchronize()
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - t0) / args.steps
+    kern_t = {k: v / args.steps for k, v in kern_t.items()}
+    sv.set_events(ev)
+    U_graph, df_graph = U.clone(), df.clone()
 
     # ---- eager runs with stage events (forward, adjoint) --------------------
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(15)]
-    sv.set_events(ev)
     reps = max(3, args.steps // 2)
     stage = {k: 0.0 for k in ("fwd", "load_restrict", "solves", "combine", "adj",
                               "adj_restrict", "adj_solves", "df_prolong")}
@@ -134,6 +199,8 @@ def main():
         stage["df_prolong"] += el(12, 13)
     sv.set_events(None)
     stage = {k: v / reps for k, v in stage.items()}
+    graph_equals_eager = bool(torch.equal(U_graph, U) and torch.equal(df_graph, df))
+    del U_graph, df_graph
 
     # ---- plain per-component loop (forward) ---------------------------------
     t_plain, plain_diff = float("nan"), float("nan")
@@ -151,14 +218,20 @@ def main():
         plain_diff = float((Up - U).norm() / U.norm())
         del Up
 
-    # dominant fine-grid kernel: each streams 8 bytes per fine-grid value
-    kern = {"k_restrict (load of f)": stage["load_restrict"],
-            "k_prolong (combination into U)": stage["combine"],
-            "k_restrict (cotangent g)": stage["adj_restrict"],
-            "k_prolong (df, with mass stencil)": stage["df_prolong"]}
-    name = max(kern, key=kern.get)
+    # dominant fine-grid kernel (timed inside the graph replays when the
+    # runtime records captured events, else in the eager runs): each streams
+    # 8 bytes per fine-grid value
+    eager_t = {"k_restrict (load of f)": stage["load_restrict"],
+               "k_prolong (combination into U)": stage["combine"],
+               "k_restrict (cotangent g)": stage["adj_restrict"],
+               "k_prolong (df, with mass stencil)": stage["df_prolong"]}
+    if graph_events and not all(0.5 < kern_t[k] / eager_t[k] < 2.0 for k in kern_t):
+        graph_events = False  # event nodes did not bracket the kernels
+    if not graph_events:
+        kern_t = eager_t
+    name = max(kern_t, key=kern_t.get)
     bytes_alg = 8.0 * nfull
-    achieved = bytes_alg / kern[name] / 1e9
+    achieved = bytes_alg / kern_t[name] / 1e9
     ns = sv.n_sparse
     out = {
         "metric": METRIC,
@@ -184,7 +257,10 @@ def main():
             "batched_fwd_over_plain_fwd_speedup": t_plain / stage["fwd"],
             "fwd_adj_over_fwd": (stage["fwd"] + stage["adj"]) / stage["fwd"],
             "plain_vs_fused_rel_l2": plain_diff,
+            "graph_equals_eager": graph_equals_eager,
             "stage_ms": {k: v * 1e3 for k, v in stage.items()},
+            "kernel_ms": {k: v * 1e3 for k, v in kern_t.items()},
+            "kernel_ms_from": "graph replays" if graph_events else "eager runs",
         },
         "roofline": {
             "bound": "hbm",
@@ -193,7 +269,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(name),
         },
     }
     if not args.no_cpu_baseline:

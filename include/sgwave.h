@@ -110,7 +110,8 @@ sg_status sg_graph_launch(sg_problem *p, hipStream_t stream);
 /*
  * Stage timing: when ev is not NULL, sg_solve and sg_adjoint record
  * ev[i] (caller-created hipEvent_t, at least SG_NUM_EVENTS of them) on the
- * call's stream at these points (not during graph capture):
+ * call's stream at these points; events set when sg_graph_capture runs are
+ * captured as event-record nodes and recorded by every replay:
  *   0 forward begin        1 before the load restriction   2 after it
  *   3 before the solves    4 after the solves              5 before the
  *   combination pass       6 after it (forward end)

@@ -25,11 +25,15 @@ sg_status fail(sg_status st, const std::string &msg) {
   return st;
 }
 
+// On failure the runtime's pending error is cleared as well, so that a later
+// launch check does not report it again.
 #define HIPCHK(expr)                                                             \
   do {                                                                           \
     hipError_t e_ = (expr);                                                      \
-    if (e_ != hipSuccess)                                                        \
+    if (e_ != hipSuccess) {                                                      \
+      (void)hipGetLastError();                                                   \
       return fail(SG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    }                                                                            \
   } while (0)
 
 struct Comp {
@@ -131,9 +135,11 @@ struct sg_problem {
   hipGraphExec_t gexec = nullptr;
   int refine_nq = 33;
   int wave_nq = 65;                // time levels with nq >= wave_nq: one wave per mode
-  // optional stage events (not recorded while capturing)
+  // optional stage events; during capture the dependencies at each mark
   std::vector<hipEvent_t> ev;
   bool capturing = false;
+  std::vector<hipGraphNode_t> cap_deps[SG_NUM_EVENTS];
+  bool cap_seen[SG_NUM_EVENTS] = {};
 };
 
 namespace {
@@ -255,7 +261,53 @@ sg_status build_pass(sg_problem *p, Pass &P, const Geometry &geo, F spec,
 }
 
 sg_status mark(sg_problem *p, int id, hipStream_t s) {
-  if (!p->capturing && id < (int)p->ev.size()) HIPCHK(hipEventRecord(p->ev[id], s));
+  if (id >= (int)p->ev.size()) return SG_OK;
+  if (!p->capturing) {
+    HIPCHK(hipEventRecord(p->ev[id], s));
+    return SG_OK;
+  }
+  // During capture remember the graph nodes the next operation will depend
+  // on; event-record nodes around the timed kernels are added after capture.
+  hipStreamCaptureStatus st;
+  unsigned long long cid = 0;
+  hipGraph_t gr = nullptr;
+  const hipGraphNode_t *deps = nullptr;
+  size_t nd = 0;
+  HIPCHK(hipStreamGetCaptureInfo_v2(s, &st, &cid, &gr, &deps, &nd));
+  p->cap_deps[id].assign(deps, deps + nd);
+  p->cap_seen[id] = true;
+  return SG_OK;
+}
+
+// Bracket every timed kernel of the captured (linear) graph with
+// event-record nodes spliced into the chain: predecessors -> begin ->
+// kernel -> end -> successors, so that no event node sits on a side branch.
+sg_status add_graph_events(sg_problem *p, hipGraph_t graph) {
+  static const int pairs[][2] = {{1, 2}, {5, 6}, {8, 9}, {12, 13}};
+  for (const auto &pr : pairs) {
+    const int b = pr[0], e = pr[1];
+    if (!p->cap_seen[b] || !p->cap_seen[e] || p->cap_deps[e].size() != 1) continue;
+    hipGraphNode_t kern = p->cap_deps[e][0];
+    // the kernel's actual predecessors and successors in the graph
+    size_t np = 0;
+    HIPCHK(hipGraphNodeGetDependencies(kern, nullptr, &np));
+    std::vector<hipGraphNode_t> db(np);
+    if (np) HIPCHK(hipGraphNodeGetDependencies(kern, db.data(), &np));
+    size_t ns = 0;
+    HIPCHK(hipGraphNodeGetDependentNodes(kern, nullptr, &ns));
+    std::vector<hipGraphNode_t> succ(ns);
+    if (ns) HIPCHK(hipGraphNodeGetDependentNodes(kern, succ.data(), &ns));
+    hipGraphNode_t nb = nullptr, ne = nullptr;
+    HIPCHK(hipGraphAddEventRecordNode(&nb, graph, db.empty() ? nullptr : db.data(), db.size(),
+                                      p->ev[b]));
+    for (hipGraphNode_t d : db) HIPCHK(hipGraphRemoveDependencies(graph, &d, &kern, 1));
+    HIPCHK(hipGraphAddDependencies(graph, &nb, &kern, 1));
+    HIPCHK(hipGraphAddEventRecordNode(&ne, graph, &kern, 1, p->ev[e]));
+    for (hipGraphNode_t sn : succ) {
+      HIPCHK(hipGraphRemoveDependencies(graph, &kern, &sn, 1));
+      HIPCHK(hipGraphAddDependencies(graph, &ne, &sn, 1));
+    }
+  }
   return SG_OK;
 }
 
@@ -974,6 +1026,10 @@ sg_status sg_graph_capture(sg_problem *p, const double *f, const double *u0,
   }
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   p->capturing = true;
+  for (int i = 0; i < SG_NUM_EVENTS; ++i) {
+    p->cap_deps[i].clear();
+    p->cap_seen[i] = false;
+  }
   sg_status st = sg_solve(p, f, u0, v0, U, s);
   if (st == SG_OK && g != nullptr) st = sg_adjoint(p, g, df, du0, dv0, s);
   p->capturing = false;
@@ -985,6 +1041,7 @@ sg_status sg_graph_capture(sg_problem *p, const double *f, const double *u0,
   }
   if (e != hipSuccess) return fail(SG_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
   p->graph = graph;
+  if (!p->ev.empty() && (st = add_graph_events(p, graph)) != SG_OK) return st;
   HIPCHK(hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0));
   return SG_OK;
 }

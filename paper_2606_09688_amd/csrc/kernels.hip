@@ -1053,12 +1053,18 @@ __global__ void k_adjoint_fields(const LevelDesc *__restrict__ ld, int nlev,
   L.fu[K] = fu;
 }
 
-// Batched C = A B (row major), 64x64 tiles, 256 threads, 4x4 outputs each.
-__global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ descs,
-                                              int ndesc) {
+// Batched C = A B (row major) on the FP64 matrix cores.  64x64 block tiles,
+// 4 waves, each wave a 32x32 sub-tile of 2x2 v_mfma_f64_16x16x4 blocks; K in
+// steps of 16 through LDS, the next K tile prefetched in registers.
+// Operand layout of the 16x16x4 instruction (lane l of the wave):
+//   a = A[l % 16][l / 16],  b = B[l / 16][l % 16],
+//   result element r of the lane = D[l / 16 + 4 r][l % 16].
+typedef double sg_double4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ descs, int ndesc) {
   constexpr int BM = 64, BN = 64, BK = 16;
-  __shared__ double As[BK][BM + 1];
-  __shared__ double Bs[BK][BN + 1];
+  __shared__ double As[BM][BK + 1];
+  __shared__ double Bs[BK][BN + 2];
   int di = 0;
   while (di + 1 < ndesc && descs[di + 1].tile0 <= (int)blockIdx.x) ++di;
   const GemmDesc &Dd = descs[di];
@@ -1071,45 +1077,68 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ descs
   const double *Bp = Dd.B + bidx * Dd.sB;
   double *Cp = Dd.C + bidx * Dd.sC;
   const int row0 = tmi * BM, col0 = tni * BN;
-  const int tid = threadIdx.x;
-  const int ty = tid / 16, tx = tid % 16;
-  double acc[4][4] = {};
-  for (int k0 = 0; k0 < Dd.K; k0 += BK) {
-    for (int i = tid; i < BM * BK; i += 256) {
-      const int m = i / BK, k = i % BK;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int M = Dd.M, N = Dd.N, K = Dd.K;
+  // global -> register staging (4 + 4 values per thread per K tile); loads
+  // go to clamped valid addresses and are selected, not branched
+  double ra[4], rb[4];
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = tid + e * 256;
+      const int m = i >> 4, k = i & 15;          // A: 64 x 16
       const int gm = row0 + m, gk = k0 + k;
-      As[k][m] = (gm < Dd.M && gk < Dd.K) ? Ap[(long long)gm * Dd.lda + gk] : 0.0;
+      const bool oka = gm < M && gk < K;
+      const double va = Ap[oka ? (long long)gm * Dd.lda + gk : 0];
+      ra[e] = oka ? va : 0.0;
+      const int kb = i >> 6, n = i & 63;          // B: 16 x 64
+      const int gkb = k0 + kb, gn = col0 + n;
+      const bool okb = gkb < K && gn < N;
+      const double vb = Bp[okb ? (long long)gkb * Dd.ldb + gn : 0];
+      rb[e] = okb ? vb : 0.0;
     }
-    for (int i = tid; i < BK * BN; i += 256) {
-      const int k = i / BN, nn = i % BN;
-      const int gk = k0 + k, gn = col0 + nn;
-      Bs[k][nn] = (gk < Dd.K && gn < Dd.N) ? Bp[(long long)gk * Dd.ldb + gn] : 0.0;
+  };
+  sg_double4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = sg_double4{0.0, 0.0, 0.0, 0.0};
+  load_tile(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = tid + e * 256;
+      As[i >> 4][i & 15] = ra[e];
+      Bs[i >> 6][i & 63] = rb[e];
     }
     __syncthreads();
+    if (k0 + BK < K) load_tile(k0 + BK);
 #pragma unroll
-    for (int k = 0; k < BK; ++k) {
-      double av[4], bv[4];
+    for (int kk = 0; kk < BK; kk += 4) {
+      double a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[k][ty * 4 + i];
+      for (int i = 0; i < 2; ++i) a[i] = As[wm + i * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[k][tx * 4 + j];
+      for (int j = 0; j < 2; ++j) b[j] = Bs[kk + (lane >> 4)][wn + j * 16 + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int gm = row0 + ty * 4 + i;
-    if (gm >= Dd.M) continue;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gn = col0 + tx * 4 + j;
-      if (gn < Dd.N) Cp[(long long)gm * Dd.ldc + gn] = acc[i][j];
-    }
-  }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = row0 + wm + i * 16 + (lane >> 4) + 4 * r;
+        const int gn = col0 + wn + j * 16 + (lane & 15);
+        if (gm < M && gn < N) Cp[(long long)gm * Dd.ldc + gn] = acc[i][j][r];
+      }
 }
 
 // ---- per-mode banded time solve ------------------------------------------

@@ -113,8 +113,13 @@ def test_plain_loop_and_graph_match_fused(case):
     s = torch.cuda.Stream()
     Ug = torch.empty_like(U)
     dfg, du0g, dv0g = torch.empty_like(df), torch.empty_like(du0), torch.empty_like(dv0)
+    # capture with the stage events set: their record nodes are spliced into
+    # the graph around the streaming kernels and must not change any result
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(15)]
+    sv.set_events(ev)
     with torch.cuda.stream(s):
         sv.capture(f, u0, v0, Ug, g, dfg, du0g, dv0g, stream=s)
+    sv.set_events(None)
     for rep in range(3):
         Ug.zero_()
         dfg.zero_()
