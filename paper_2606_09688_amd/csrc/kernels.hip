@@ -53,6 +53,19 @@ __device__ __forceinline__ long long gid64() {
 
 // --------------------------------------------------------- restriction -----
 
+// XCD-aware block order for the streaming kernels.  Workgroups are dealt
+// round-robin to the 8 XCDs (each with its own L2); the logical (chunk, tile)
+// of hardware block b is chosen so that every XCD holds a contiguous run of
+// tiles of one time chunk, and neighbouring tiles - which read each other's
+// halo rows - share an L2.
+__device__ __forceinline__ void stream_block(int ntileD, int nchunk, int &tile, int &chunk) {
+  const int total = ntileD * nchunk;
+  int lin = blockIdx.y * gridDim.x + blockIdx.x;
+  if (total % 8 == 0) lin = (lin & 7) * (total >> 3) + (lin >> 3);
+  chunk = lin / ntileD;
+  tile = lin - chunk * ntileD;
+}
+
 // Zero-halo LDS layout of the in-tile levels (one copy per slab).  Level r
 // keeps its nodes(r)^D values at padded index (jy+1)*pn(r) + (jx+1); the halo
 // entries stay zero, so the full-weighting stencil of a level-(r+1) node reads
@@ -142,13 +155,13 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_restrict(const RestrictArgs A) {
 
   const Geometry g = A.g;
   const int tid = threadIdx.x;
-  const int tile = blockIdx.x;
+  const int ntileD = (D == 2) ? g.ntile * g.ntile : g.ntile;
+  int tile, chunk;
+  stream_block(ntileD, g.nchunk, tile, chunk);
   const int tx = tile % g.ntile;
   const int ty = (D == 2) ? tile / g.ntile : 0;
-  const int chunk = blockIdx.y;
   const int n0 = chunk * g.chunk;
   const int n1 = min(n0 + g.chunk, g.ntf);
-  const int ntileD = (D == 2) ? g.ntile * g.ntile : g.ntile;
   const long long nsp = (D == 2) ? (long long)g.nxf * g.nxf : g.nxf;
   const int R = g.R;
   const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
@@ -632,10 +645,10 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
 
   const Geometry g = A.g;
   const int tid = threadIdx.x;
-  const int tile = blockIdx.x;
+  int tile, chunk;
+  stream_block((D == 2) ? g.ntile * g.ntile : g.ntile, g.nchunk, tile, chunk);
   const int tx = tile % g.ntile;
   const int ty = (D == 2) ? tile / g.ntile : 0;
-  const int chunk = blockIdx.y;
   const int n0 = chunk * g.chunk;
   const int n1 = min(n0 + g.chunk, g.ntf);
   const long long nsp = (D == 2) ? (long long)g.nxf * g.nxf : g.nxf;
