@@ -170,6 +170,17 @@ sg_status sg_destroy(sg_problem *p);
 /* Message describing the last error of the calling thread ("" if none). */
 const char *sg_last_error(void);
 
+/*
+ * Host table (exported for tests; no device work): generalised eigenpairs of
+ * the level-a P1 pencil (K(c), M) on (0,len) with c piecewise constant on
+ * ncell uniform blocks (eq. (9), spatial matrices; variable wave speed in
+ * 1-D).  V: (2^a-1)^2 doubles, row-major, column k = eigenvector k with
+ * V^T M V = I; lam: 2^a-1 eigenvalues.  Caller-owned host buffers.
+ * SG_EINVAL unless 1 <= a <= 8.
+ */
+sg_status sg_host_pencil(int a, double len, int ncell, const double *c_vals, double *V,
+                         double *lam);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,4 +9,4 @@ this package only marshals torch tensors into it.
 """
 
 from .binding import (SparseGridWave, SGWaveFunction, SGError, sgwave,  # noqa: F401
-                      host_taps, host_time_level, lib, LIB_PATH)
+                      host_pencil, host_taps, host_time_level, lib, LIB_PATH)

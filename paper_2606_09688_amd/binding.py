@@ -40,6 +40,8 @@ SIGNATURES = {
     "sg_host_time_level": (ctypes.c_int, [ctypes.c_int, ctypes.c_double] + [_c_dp] * 7),
     "sg_host_taps": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_double, _c_ip, _c_dp]),
+    "sg_host_pencil": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, _c_dp,
+                                      _c_dp, _c_dp]),
     "sg_set_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                      ctypes.c_int]),
     "sg_destroy": (ctypes.c_int, [ctypes.c_void_p]),
@@ -115,6 +117,20 @@ def host_taps(kind, b, J, T):
     check(lib().sg_host_taps(kind, b, J, float(T), q0.ctypes.data_as(_c_ip),
                              w.ctypes.data_as(_c_dp)), "sg_host_taps")
     return q0, w
+
+
+def host_pencil(a, length, c_vals):
+    """(V, lam): M-orthonormal eigenpairs of the level-a P1 pencil (K(c), M)
+    on (0, length), c piecewise constant on len(c_vals) uniform blocks."""
+    import numpy as np
+    c = np.ascontiguousarray(c_vals, dtype=np.float64)
+    n = 2 ** a - 1
+    V = np.zeros((n, n))
+    lam = np.zeros(n)
+    check(lib().sg_host_pencil(a, float(length), len(c), c.ctypes.data_as(_c_dp),
+                               V.ctypes.data_as(_c_dp), lam.ctypes.data_as(_c_dp)),
+          "sg_host_pencil")
+    return V, lam
 
 
 class SparseGridWave:

@@ -18,6 +18,10 @@ using namespace sg;
 
 namespace {
 
+// largest spatial level whose variable-speed modes come from a dense
+// eigen-decomposition (2^8 - 1 = 255 nodes)
+constexpr int kEigMaxLevel = 8;
+
 thread_local std::string g_last_error;
 
 sg_status fail(sg_status st, const std::string &msg) {
@@ -101,7 +105,9 @@ struct sg_problem {
   // tables
   KernelTables *d_kt = nullptr;
   ModeTables *d_mt = nullptr;
-  std::vector<double *> dst;      // per spatial level (const c)
+  std::vector<double *> tf, ti;    // per spatial level: forward / inverse transform
+                                   // (DST-I for constant c, M-orthonormal
+                                   // eigenvectors V / V^T for variable c, d = 1)
   double *d_ce = nullptr;         // fine-element c^2
   // buffers (N^sparse each)
   double *bufZ = nullptr, *bufB = nullptr, *bufT = nullptr, *bufS = nullptr,
@@ -389,7 +395,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
   for (int ci : cset) {
     const Comp &C = p->comps[ci];
     const int na = (1 << C.a) - 1;
-    const double *Q = p->dst[C.a];
+    const double *Q = p->tf[C.a], *Qi = p->ti[C.a];
     const int ny = p->d == 2 ? na : 1;
     auto tiles = [](int M, int N) { return ((M + 63) / 64) * ((N + 63) / 64); };
     // forward x: T = B * Q   ([nq*ny x na] x [na x na])
@@ -401,10 +407,10 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
       tx += tiles(g.M, g.N);
       vx.push_back(g);
     }
-    // inverse x: U = T * Q
+    // inverse x: U = T * Q^{-1}
     {
       GemmDesc g{};
-      g.A = p->bufT + C.off; g.B = Q; g.C = x_out + C.off;
+      g.A = p->bufT + C.off; g.B = Qi; g.C = x_out + C.off;
       g.M = C.nq * ny; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
       g.batch = 1; g.tm = (g.M + 63) / 64; g.tn = (g.N + 63) / 64; g.tile0 = tix;
       tix += tiles(g.M, g.N);
@@ -550,8 +556,11 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   p->N = N;
   p->const_c = std::all_of(p->c.begin(), p->c.end(), [&](double v) { return v == p->c[0]; });
   p->c2 = p->c[0] * p->c[0];
-  if (!p->const_c)
-    return bail(fail(SG_ENOTSUP, "variable wave speed is not implemented in this build"));
+  if (!p->const_c && d == 2)
+    return bail(fail(SG_ENOTSUP, "variable wave speed in 2-D is not implemented in this build"));
+  if (!p->const_c && J > kEigMaxLevel)
+    return bail(fail(SG_ENOTSUP, "variable wave speed needs spatial levels <= 8 in this build"));
+  if (!p->const_c) p->c2 = 1.0;  // the eigenvalues carry c
   if (const char *e = getenv("SG_REFINE_NQ")) p->refine_nq = atoi(e);
   if (const char *e = getenv("SG_WAVE_NQ")) p->wave_nq = atoi(e);
 
@@ -622,19 +631,35 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
 
   // ---- spatial tables ---------------------------------------------------
   ModeTables mt{};
-  p->dst.assign(J + 1, nullptr);
+  p->tf.assign(J + 1, nullptr);
+  p->ti.assign(J + 1, nullptr);
   for (int a = 1; a <= J; ++a) {
     std::vector<double> m, k;
-    p1_eigen(a, p->len[0], m, k);
     double *dm, *dk;
-    if ((st = upload(p, m, &dm)) || (st = upload(p, k, &dk))) return bail(st);
-    mt.mx[a] = dm; mt.kx[a] = dk;
-    if (d == 2) {
-      p1_eigen(a, p->len[1], m, k);
+    if (p->const_c) {
+      p1_eigen(a, p->len[0], m, k);
       if ((st = upload(p, m, &dm)) || (st = upload(p, k, &dk))) return bail(st);
-      mt.my[a] = dm; mt.ky[a] = dk;
+      mt.mx[a] = dm; mt.kx[a] = dk;
+      if (d == 2) {
+        p1_eigen(a, p->len[1], m, k);
+        if ((st = upload(p, m, &dm)) || (st = upload(p, k, &dk))) return bail(st);
+        mt.my[a] = dm; mt.ky[a] = dk;
+      }
+      if ((st = upload(p, dst_matrix(a), &p->tf[a]))) return bail(st);
+      p->ti[a] = p->tf[a];  // the DST-I matrix is its own inverse
+    } else {
+      // d = 1: modes of the pencil (K(c), M), mass 1 and stiffness lambda
+      std::vector<double> V, lam;
+      pencil_eigen(a, p->len[0], element_c2(a, p->len[0], p->ncell[0], p->c.data()), V, lam);
+      const int n = (1 << a) - 1;
+      std::vector<double> Vt((size_t)n * n);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Vt[(size_t)j * n + i] = V[(size_t)i * n + j];
+      m.assign(n, 1.0);
+      if ((st = upload(p, m, &dm)) || (st = upload(p, lam, &dk))) return bail(st);
+      mt.mx[a] = dm; mt.kx[a] = dk;
+      if ((st = upload(p, V, &p->tf[a])) || (st = upload(p, Vt, &p->ti[a]))) return bail(st);
     }
-    if ((st = upload(p, dst_matrix(a), &p->dst[a]))) return bail(st);
   }
   if ((st = upload(p, std::vector<ModeTables>{mt}, &p->d_mt))) return bail(st);
   // per fine element c^2 (the finest mesh resolves the blocks)
@@ -999,6 +1024,17 @@ sg_status sg_host_time_level(int b, double T, double *A, double *Alo, double *B,
   if (Dlo) std::memcpy(Dlo, tl.Dlo.data(), n * sizeof(double));
   if (Dhi) std::memcpy(Dhi, tl.Dhi.data(), n * sizeof(double));
   if (g) std::memcpy(g, tl.g.data(), n * sizeof(double));
+  return SG_OK;
+}
+
+sg_status sg_host_pencil(int a, double len, int ncell, const double *c_vals, double *V,
+                         double *lam) {
+  if (a < 1 || a > kEigMaxLevel || !(len > 0) || ncell < 1 || !c_vals)
+    return fail(SG_EINVAL, "need 1 <= a <= 8, len > 0, ncell >= 1");
+  std::vector<double> v, l;
+  pencil_eigen(a, len, element_c2(a, len, ncell, c_vals), v, l);
+  if (V) std::memcpy(V, v.data(), v.size() * sizeof(double));
+  if (lam) std::memcpy(lam, l.data(), l.size() * sizeof(double));
   return SG_OK;
 }
 

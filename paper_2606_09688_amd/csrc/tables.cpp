@@ -17,6 +17,7 @@
 // the exact entries.  Everything else is rounded once to double.
 #include "tables.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <stdexcept>
 
@@ -287,6 +288,136 @@ std::vector<double> dst_matrix(int a) {
       Q[(size_t)(j - 1) * m + (k - 1)] = (double)(sc * sinl(pi * r / n));
     }
   return Q;
+}
+
+}  // namespace sg
+
+namespace sg {
+
+// ---------------------------------------------------------------------------
+// Variable wave speed, d = 1.
+
+std::vector<double> element_c2(int a, double len, int ncell, const double *c_vals) {
+  const int ne = 1 << a;
+  std::vector<double> out(ne, 0.0);
+  // element e = [e, e+1] * len / ne, block b = [b, b+1] * len / ncell; the
+  // overlap in units of len / (ne * ncell) is an integer count
+  for (int e = 0; e < ne; ++e) {
+    const long long lo = (long long)e * ncell, hi = lo + ncell;  // element in fine units
+    long double acc = 0.0L;
+    for (int b = 0; b < ncell; ++b) {
+      const long long blo = (long long)b * ne, bhi = blo + ne;
+      const long long ov = std::min(hi, bhi) - std::max(lo, blo);
+      if (ov > 0) acc += (long double)c_vals[b] * c_vals[b] * ov;
+    }
+    out[e] = (double)(acc / ncell);
+  }
+  return out;
+}
+
+// Symmetric eigen-decomposition by the cyclic Jacobi method: on return C is
+// (numerically) diagonal and Q (row-major, columns = eigenvectors) satisfies
+// C_in = Q diag(C) Q^T.
+static void jacobi_eigen(int n, std::vector<long double> &C, std::vector<long double> &Q) {
+  Q.assign((size_t)n * n, 0.0L);
+  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0L;
+  auto c = [&](int i, int j) -> long double & { return C[(size_t)i * n + j]; };
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    long double off = 0.0L, diag = 0.0L;
+    for (int i = 0; i < n; ++i) {
+      diag += c(i, i) * c(i, i);
+      for (int j = i + 1; j < n; ++j) off += c(i, j) * c(i, j);
+    }
+    if (off <= 1e-38L * diag) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const long double apq = c(p, q);
+        if (apq == 0.0L) continue;
+        const long double theta = (c(q, q) - c(p, p)) / (2.0L * apq);
+        const long double t = (theta >= 0 ? 1.0L : -1.0L) /
+                              (fabsl(theta) + sqrtl(theta * theta + 1.0L));
+        const long double cs = 1.0L / sqrtl(t * t + 1.0L), sn = t * cs;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const long double kp = c(k, p), kq = c(k, q);
+          c(k, p) = cs * kp - sn * kq;
+          c(k, q) = sn * kp + cs * kq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const long double pk = c(p, k), qk = c(q, k);
+          c(p, k) = cs * pk - sn * qk;
+          c(q, k) = sn * pk + cs * qk;
+        }
+        c(p, q) = c(q, p) = 0.0L;
+        for (int k = 0; k < n; ++k) {
+          long double &kp = Q[(size_t)k * n + p], &kq = Q[(size_t)k * n + q];
+          const long double a0 = kp, a1 = kq;
+          kp = cs * a0 - sn * a1;
+          kq = sn * a0 + cs * a1;
+        }
+      }
+  }
+}
+
+void pencil_eigen(int a, double len, const std::vector<double> &c2e, std::vector<double> &V,
+                  std::vector<double> &lam) {
+  const int ne = 1 << a, n = ne - 1;
+  const long double h = (long double)len / ne;
+  // M = h/6 tridiag(1,4,1); K[i][i] = (c2_{i} + c2_{i+1})/h, K[i][i+1] = -c2_{i+1}/h
+  // (interior node i+1 sits between elements i and i+1)
+  std::vector<long double> md(n, 4.0L * h / 6.0L), mo(n, h / 6.0L);
+  std::vector<long double> kd(n), ko(n, 0.0L);
+  for (int i = 0; i < n; ++i) {
+    kd[i] = (c2e[i] + c2e[i + 1]) / h;
+    if (i + 1 < n) ko[i] = -(long double)c2e[i + 1] / h;
+  }
+  // M = L L^T, L lower bidiagonal (diagonal ld, subdiagonal ls)
+  std::vector<long double> ld(n), ls(n, 0.0L);
+  for (int i = 0; i < n; ++i) {
+    const long double d = md[i] - (i > 0 ? ls[i - 1] * ls[i - 1] : 0.0L);
+    ld[i] = sqrtl(d);
+    if (i + 1 < n) ls[i] = mo[i] / ld[i];
+  }
+  // C = L^{-1} K L^{-T}: X = L^{-1} K (columns), C = L^{-1} X^T, symmetrised
+  std::vector<long double> X((size_t)n * n, 0.0L), C((size_t)n * n, 0.0L);
+  for (int j = 0; j < n; ++j) {
+    long double prev = 0.0L;
+    for (int i = 0; i < n; ++i) {
+      long double kij = 0.0L;
+      if (i == j) kij = kd[i];
+      else if (i == j + 1) kij = ko[j];
+      else if (j == i + 1) kij = ko[i];
+      const long double x = (kij - (i > 0 ? ls[i - 1] * prev : 0.0L)) / ld[i];
+      X[(size_t)i * n + j] = x;
+      prev = x;
+    }
+  }
+  for (int j = 0; j < n; ++j) {  // column j of C = L^{-1} (row j of X)
+    long double prev = 0.0L;
+    for (int i = 0; i < n; ++i) {
+      const long double x = (X[(size_t)j * n + i] - (i > 0 ? ls[i - 1] * prev : 0.0L)) / ld[i];
+      C[(size_t)i * n + j] = x;
+      prev = x;
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      const long double s = 0.5L * (C[(size_t)i * n + j] + C[(size_t)j * n + i]);
+      C[(size_t)i * n + j] = C[(size_t)j * n + i] = s;
+    }
+  std::vector<long double> Q;
+  jacobi_eigen(n, C, Q);
+  lam.resize(n);
+  for (int k = 0; k < n; ++k) lam[k] = (double)C[(size_t)k * n + k];
+  // V = L^{-T} Q (back substitution per column); V^T M V = I
+  V.assign((size_t)n * n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    long double next = 0.0L;
+    for (int i = n - 1; i >= 0; --i) {
+      const long double v = (Q[(size_t)i * n + k] - (i + 1 < n ? ls[i] * next : 0.0L)) / ld[i];
+      V[(size_t)i * n + k] = (double)v;
+      next = v;
+    }
+  }
 }
 
 }  // namespace sg

@@ -50,6 +50,15 @@ Taps sum_taps(int J);
 // m_k = h/6 (4 + 2 cos(k pi/n)), kappa_k = 4/h sin^2(k pi/(2n)), k = 1..n-1.
 void p1_eigen(int a, double len, std::vector<double> &m, std::vector<double> &k);
 
+// Variable wave speed (d = 1): average of c^2 over every element of level a
+// of (0, len) for c piecewise constant on ncell uniform blocks.
+std::vector<double> element_c2(int a, double len, int ncell, const double *c_vals);
+// Generalised eigenpairs of the level-a P1 pencil (K(c), M): K V = M V diag(lam),
+// V^T M V = I.  V is row-major (n-1)^2, column k = eigenvector k.  c2e holds the
+// element averages of c^2 (2^a values).
+void pencil_eigen(int a, double len, const std::vector<double> &c2e, std::vector<double> &V,
+                  std::vector<double> &lam);
+
 // Orthonormal DST-I matrix of level a: Q[j][k] = sqrt(2/n) sin(pi j k/n),
 // j,k = 1..n-1, n = 2^a (symmetric, Q Q = I), row-major (n-1)^2.
 std::vector<double> dst_matrix(int a);

@@ -94,6 +94,45 @@ def test_forward_and_adjoint_parity(case):
         assert e <= TOL, name
 
 
+VARC = [
+    # (lengths, c on uniform blocks, T, L): piecewise-constant speed in 1-D
+    ([1.0], [1.0, 0.5], 2.0, 6),                       # two-speed medium
+    ([2.0], [0.6, 1.4, 0.9, 2.0], 1.3, 8),
+    ([1.0], [0.5, 2.0, 1.7, 0.8, 1.1, 0.6, 1.9, 1.2], 1.0, 9),  # 8 cells, levels up to 8
+]
+
+
+@pytest.mark.parametrize("case", VARC, ids=lambda c: f"d1L{c[3]}c{len(c[1])}")
+def test_variable_speed_parity(case):
+    """c piecewise constant (1-D): spatial modes of the pencil (K(c), M),
+    the same time solves; forward, components and adjoint vs the oracle."""
+    torch = _torch()
+    lengths, cv, T, L = case
+    spec = workloads.Spec(1, lengths, [len(cv)], cv, T, L)
+    data = workloads.random_data(spec, 300 + L)
+    print(f"case d=1 L={L} c={cv} T={T}", flush=True)
+    orc = Problem(*spec.args())
+    U_ref = orc.forward(data["f"], data["u0"], data["v0"]).reshape(spec.shape())
+    df_ref, du0_ref, dv0_ref = orc.adjoint(data["g"])
+    sv = _solver(spec)
+    f, u0, v0, g = (_dev(data[k]) for k in ("f", "u0", "v0", "g"))
+    U = sv.solve(f, u0, v0)
+    torch.cuda.synchronize()
+    e = rel(U.cpu().numpy(), U_ref)
+    print(f"  forward rel l2 {e:.3e}", flush=True)
+    assert e <= TOL
+    for ci, (jx, jt, s) in enumerate(orc.comps):
+        b_ref = orc.load(jx, jt, data["f"], data["u0"], data["v0"])
+        assert rel(sv.component(ci, 0), b_ref) <= TOL, (jx, jt)
+        assert rel(sv.component(ci, 1), orc.solve(jx, jt, b_ref)) <= TOL, (jx, jt)
+    df, du0, dv0 = sv.adjoint(g)
+    torch.cuda.synchronize()
+    for name, got, ref in (("df", df, df_ref), ("du0", du0, du0_ref), ("dv0", dv0, dv0_ref)):
+        e = rel(got.cpu().numpy(), ref)
+        print(f"  adjoint {name} rel l2 {e:.3e}", flush=True)
+        assert e <= TOL, name
+
+
 @pytest.mark.parametrize("case", [CASES[2], CASES[4], CASES[7], CASES[9]],
                          ids=lambda c: f"d{c[0]}L{c[4]}")
 def test_plain_loop_and_graph_match_fused(case):

@@ -85,3 +85,27 @@ def test_host_taps_compose_to_oracle_load_and_evaluation(b, J, T):
     assert np.all(np.diff(q0s) >= 0) and np.all(np.diff(q0s) <= 1)
     Psi = _dense_taps(q0s, ws, nq).T                # (n, i)
     assert np.abs(Psi - timemat.eval_at_nodes(b, J, T)).max() <= 1e-15
+
+
+@pytest.mark.parametrize("a,length,cv", [(1, 1.0, [0.8]), (3, 1.0, [1.0, 0.5]),
+                                         (5, 2.0, [0.5, 2.0, 1.3, 0.7]),
+                                         (6, 1.0, list(np.linspace(0.5, 2.0, 8))),
+                                         (8, 1.0, [1.0, 0.5])])
+def test_host_pencil_eigenpairs_of_oracle_matrices(a, length, cv):
+    """The variable-speed modes (1-D) are the generalised eigenpairs of the
+    oracle's own P1 matrices: K V = M V diag(lam), V^T M V = I (eq. (9),
+    spatial matrices with c^2 integrated exactly over each element)."""
+    import paper_2606_09688_amd as sg
+    from oracle.space import Medium, mass, stiff
+    med = Medium([length], [len(cv)], cv)
+    M = mass(a, med).toarray()
+    K = stiff(a, med).toarray()
+    V, lam = sg.host_pencil(a, length, cv)
+    n = 2 ** a - 1
+    assert V.shape == (n, n)
+    scale = np.abs(K).max()
+    assert np.abs(K @ V - M @ V * lam[None, :]).max() <= 1e-13 * scale * max(1.0, np.abs(V).max())
+    assert np.abs(V.T @ M @ V - np.eye(n)).max() <= 1e-13
+    # the eigenvalues are those of the pencil (dense reference for small n)
+    ref = np.sort(np.linalg.eigvals(np.linalg.solve(M, K)).real)
+    assert np.allclose(np.sort(lam), ref, rtol=1e-10, atol=0)
