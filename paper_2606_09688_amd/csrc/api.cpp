@@ -76,6 +76,11 @@ struct CompList {
   long long total = 0;
 };
 
+struct BlockList {       // components solved by block LU + refinement
+  BlockDesc *d = nullptr;
+  int n = 0;
+};
+
 }  // namespace
 
 struct sg_problem {
@@ -131,6 +136,9 @@ struct sg_problem {
   std::vector<GemmList> pgx, pgy, pgiy, pgix;
   SolveList sfwd, sadj;
   std::vector<SolveList> psfwd;
+  std::vector<char> blockc;        // per component: solved by block LU (1-D, variable c)
+  BlockList bfwd, badj;
+  std::vector<BlockList> pbfwd;
   CompList cload, cadj;
   std::vector<CompList> pcload;
   LevelDesc *d_lev = nullptr;
@@ -393,6 +401,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
   std::vector<GemmDesc> vx, vy, viy, vix;
   int tx = 0, ty = 0, tiy = 0, tix = 0;
   for (int ci : cset) {
+    if (p->blockc[ci]) continue;
     const Comp &C = p->comps[ci];
     const int na = (1 << C.a) - 1;
     const double *Q = p->tf[C.a], *Qi = p->ti[C.a];
@@ -454,6 +463,7 @@ sg_status build_solve_list(sg_problem *p, const std::vector<int> &cset, int tran
   long long th = 0;
   for (int pass = 0; pass < 2; ++pass)
     for (int ci : cset) {
+      if (p->blockc[ci]) continue;
       const Comp &C = p->comps[ci];
       const int wave = C.nq >= p->wave_nq ? 1 : 0;
       if (wave != (pass == 0 ? 1 : 0)) continue;
@@ -485,7 +495,8 @@ sg_status build_solve_list(sg_problem *p, const std::vector<int> &cset, int tran
 
 sg_status run_solves(sg_problem *p, const GemmList &gx, const GemmList &gy,
                      const SolveList &sl, const GemmList &giy, const GemmList &gix,
-                     hipStream_t s) {
+                     const BlockList &bl, hipStream_t s) {
+  HIPCHK(launch_block_solve(bl.d, bl.n, p->d_kt, s));
   HIPCHK(launch_gemm(gx.d, gx.n, gx.tiles, s));
   if (p->d == 2) HIPCHK(launch_gemm(gy.d, gy.n, gy.tiles, s));
   HIPCHK(launch_time_solve(sl.d, sl.n, sl.threads, p->d_kt, p->d_mt, p->d, s));
@@ -558,8 +569,6 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   p->c2 = p->c[0] * p->c[0];
   if (!p->const_c && d == 2)
     return bail(fail(SG_ENOTSUP, "variable wave speed in 2-D is not implemented in this build"));
-  if (!p->const_c && J > kEigMaxLevel)
-    return bail(fail(SG_ENOTSUP, "variable wave speed needs spatial levels <= 8 in this build"));
   if (!p->const_c) p->c2 = 1.0;  // the eigenvalues carry c
   if (const char *e = getenv("SG_REFINE_NQ")) p->refine_nq = atoi(e);
   if (const char *e = getenv("SG_WAVE_NQ")) p->wave_nq = atoi(e);
@@ -582,6 +591,15 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   for (int a = 1; a <= J - 1; ++a) add(a, L - 1 - a, -1);
   p->nsparse = off;
   p->nsp_fine = d == 2 ? (long long)(N - 1) * (N - 1) : (N - 1);
+  // 1-D variable speed: spatial levels above kEigMaxLevel are solved by the
+  // block LU of the whole component (time levels there are short)
+  p->blockc.assign(p->comps.size(), 0);
+  for (size_t ci = 0; ci < p->comps.size(); ++ci)
+    if (!p->const_c && p->comps[ci].a > kEigMaxLevel) {
+      if (p->comps[ci].nq > 64)
+        return bail(fail(SG_ENOTSUP, "variable wave speed: time level too fine for the block solver"));
+      p->blockc[ci] = 1;
+    }
   const int ntf = N + 1;
   auto comp_index = [&](int a, int k) -> int {  // k=0 plus, 1 minus
     if (k == 0) return a - 1;
@@ -594,8 +612,10 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   KernelTables kt{};
   std::map<int, std::pair<const int *, const double *>> p1tab, sptab;
   std::map<int, std::vector<int>> p1q0, spq0;
+  std::vector<TimeLevel> tl_host(J + 1);
   for (int b = 1; b <= J; ++b) {
-    TimeLevel tl = time_level(b, T);
+    tl_host[b] = time_level(b, T);
+    const TimeLevel &tl = tl_host[b];
     double *dA, *dB, *dAl, *dBl, *dlo, *dhi, *dg;
     if ((st = upload(p, tl.A, &dA)) || (st = upload(p, tl.B, &dB)) ||
         (st = upload(p, tl.Alo, &dAl)) || (st = upload(p, tl.Blo, &dBl)) ||
@@ -647,6 +667,8 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
       }
       if ((st = upload(p, dst_matrix(a), &p->tf[a]))) return bail(st);
       p->ti[a] = p->tf[a];  // the DST-I matrix is its own inverse
+    } else if (a > kEigMaxLevel) {
+      continue;  // block-LU components: no modes at this level
     } else {
       // d = 1: modes of the pencil (K(c), M), mass 1 and stiffness lambda
       std::vector<double> V, lam;
@@ -818,6 +840,36 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   }
   if ((st = build_solve_list(p, all, 0, p->sfwd))) return bail(st);
   if ((st = build_solve_list(p, all, 1, p->sadj))) return bail(st);
+  // block-LU components: factors, spatial entries, workspace, descriptors
+  {
+    std::vector<BlockDesc> vf, va;
+    p->pbfwd.resize(ncomp);
+    for (int ci = 0; ci < ncomp; ++ci) {
+      if (!p->blockc[ci]) continue;
+      const Comp &C = p->comps[ci];
+      const std::vector<double> mk =
+          space_entries(C.a, p->len[0], element_c2(C.a, p->len[0], p->ncell[0], p->c.data()));
+      std::vector<double> Dinv, Lf;
+      block_lu(tl_host[C.b], mk, C.nsp, Dinv, Lf);
+      BlockDesc bd{};
+      double *dD, *dL, *dmk, *work;
+      if ((st = upload(p, Dinv, &dD)) || (st = upload(p, Lf, &dL)) || (st = upload(p, mk, &dmk)))
+        return bail(st);
+      if (!(work = p->dalloc<double>(3LL * C.nq * C.nsp)))
+        return bail(fail(SG_ENOMEM, "hipMalloc of block-solver workspace failed"));
+      bd.Dinv = dD; bd.Lf = dL; bd.mk = dmk; bd.work = work;
+      bd.nq = C.nq; bd.nx = C.nsp; bd.b = C.b; bd.refine = 4;
+      bd.in = p->bufB + C.off; bd.out = p->bufU + C.off; bd.transpose = 0;
+      vf.push_back(bd);
+      if ((st = upload(p, std::vector<BlockDesc>{bd}, &p->pbfwd[ci].d))) return bail(st);
+      p->pbfwd[ci].n = 1;
+      bd.in = p->bufZ + C.off; bd.out = p->bufW + C.off; bd.transpose = 1;
+      va.push_back(bd);
+    }
+    if ((st = upload(p, vf, &p->bfwd.d)) || (st = upload(p, va, &p->badj.d))) return bail(st);
+    p->bfwd.n = (int)vf.size();
+    p->badj.n = (int)va.size();
+  }
   // LU factors of every mode's time matrix, shared by all later solves
   HIPCHK(launch_time_factor(p->sfwd.d, p->sfwd.n, p->sfwd.threads, p->d_kt, p->d_mt, d,
                             nullptr));
@@ -948,7 +1000,7 @@ sg_status sg_solve(sg_problem *p, const double *f, const double *u0, const doubl
   if ((st = run_restrict(p, p->load, f, 1, s, 1))) return st;
   HIPCHK(launch_post_load(p->cload.d, p->cload.n, p->cload.total, p->d_kt, s));
   MARK(p, 3, s);
-  if ((st = run_solves(p, p->gx, p->gy, p->sfwd, p->giy, p->gix, s))) return st;
+  if ((st = run_solves(p, p->gx, p->gy, p->sfwd, p->giy, p->gix, p->bfwd, s))) return st;
   MARK(p, 4, s);
   return run_prolong(p, p->prol, u0, U, 0, 0, s, 5);
 }
@@ -964,7 +1016,8 @@ sg_status sg_solve_plain(sg_problem *p, const double *f, const double *u0,
   for (size_t ci = 0; ci < p->comps.size(); ++ci) {
     if ((st = run_restrict(p, p->plain_load[ci], f, 1, s))) return st;
     HIPCHK(launch_post_load(p->pcload[ci].d, 1, p->pcload[ci].total, p->d_kt, s));
-    if ((st = run_solves(p, p->pgx[ci], p->pgy[ci], p->psfwd[ci], p->pgiy[ci], p->pgix[ci], s)))
+    if ((st = run_solves(p, p->pgx[ci], p->pgy[ci], p->psfwd[ci], p->pgiy[ci], p->pgix[ci],
+                         p->pbfwd[ci], s)))
       return st;
     if ((st = run_prolong(p, p->plain_prol[ci], nullptr, U, 1, 0, s))) return st;
   }
@@ -981,6 +1034,7 @@ sg_status sg_adjoint(sg_problem *p, const double *g, double *df, double *du0, do
   if ((st = run_restrict(p, p->adjr, g, 0, s, 8))) return st;
   // z_c = S_c^{-T} y_c  (y_c in bufZ, z_c into bufW)
   MARK(p, 10, s);
+  HIPCHK(launch_block_solve(p->badj.d, p->badj.n, p->d_kt, s));
   HIPCHK(launch_gemm(p->agx.d, p->agx.n, p->agx.tiles, s));
   if (p->d == 2) HIPCHK(launch_gemm(p->gy.d, p->gy.n, p->gy.tiles, s));
   HIPCHK(launch_time_solve(p->sadj.d, p->sadj.n, p->sadj.threads, p->d_kt, p->d_mt, p->d, s));

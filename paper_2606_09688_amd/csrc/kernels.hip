@@ -1180,6 +1180,13 @@ __device__ __forceinline__ dd dd_add(dd x, dd y) {
   s.l += x.l + y.l;
   return two_sum(s.h, s.l);
 }
+// (x.h + x.l) * (y.h + y.l) to double-double accuracy
+__device__ __forceinline__ dd dd_mul(dd x, dd y) {
+#pragma clang fp contract(off)
+  dd p = two_prod(x.h, y.h);
+  p.l += x.h * y.l + x.l * y.h;
+  return two_sum(p.h, p.l);
+}
 // (p * q) * x with p, q, x doubles, as a double-double
 __device__ __forceinline__ dd triple(double p, double q, double x) {
 #pragma clang fp contract(off)
@@ -1566,6 +1573,170 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
   }
 }
 
+// ---- block LU solve with double-double refinement (1-D, variable c) -----
+
+// One wave per component.  x <- op(S)^{-1} r with the block LU S = L U in
+// space-major order: L unit lower block bidiagonal (L_k), U upper block
+// bidiagonal (D_k, S_{k,k+1}); S^T = U^T L^T for the adjoint.  The
+// off-diagonal blocks S_{k,k+1} = M_{k,k+1} A_b + K_{k,k+1} B_b are applied
+// through the banded time matrices.  Lane j < nq owns row j of every block.
+__global__ void __launch_bounds__(64) k_block_solve(const BlockDesc *__restrict__ bds,
+                                                    const KernelTables *__restrict__ kt) {
+  constexpr int MAXQ = 64;
+  __shared__ double s_v[MAXQ], s_u[MAXQ];
+  const BlockDesc &B = bds[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int nq = B.nq, nx = B.nx;
+  const bool tr = B.transpose != 0;
+  const double *Ah = kt->A[B.b], *Bh = kt->B[B.b], *Al = kt->Alo[B.b], *Bl = kt->Blo[B.b];
+  double *b0 = B.work, *res = b0 + (long long)nq * nx, *tmp = res + (long long)nq * nx;
+  auto at = [&](int i, int k) -> long long { return (long long)i * nx + k; };
+  // (T v)_j for the banded time matrix T (A or B, high parts), T or T^T
+  auto band = [&](const double *T, const double *v, int j, bool trans) -> double {
+    double acc = 0.0;
+    for (int off = -2; off <= 2; ++off) {
+      const int i = j + off;
+      if (i < 0 || i >= nq) continue;
+      acc += (trans ? T[i * 5 + 2 - off] : T[j * 5 + off + 2]) * v[i];
+    }
+    return acc;
+  };
+  // x <- op(S)^{-1} r (r read from R, result into X, may add); returns max |x|
+  auto apply = [&](const double *R, double *X, bool add) -> double {
+    double xm = 0.0;
+    if (!tr) {
+      // L y = r: y_k = r_k - L_k y_{k-1}   (y stored in tmp)
+      for (int k = 0; k < nx; ++k) {
+        double y = 0.0;
+        if (lane < nq) {
+          y = R[at(lane, k)];
+          if (k > 0) {
+            const double *Lk = B.Lf + ((long long)k * nq + lane) * nq;
+            for (int i = 0; i < nq; ++i) y -= Lk[i] * s_v[i];
+          }
+        }
+        __syncthreads();
+        if (lane < nq) {
+          s_v[lane] = y;
+          tmp[at(lane, k)] = y;
+        }
+        __syncthreads();
+      }
+      // U x = y: x_k = D_k^{-1} (y_k - S_{k,k+1} x_{k+1})
+      for (int k = nx - 1; k >= 0; --k) {
+        if (lane < nq) {
+          double w = tmp[at(lane, k)];
+          if (k + 1 < nx)
+            w -= B.mk[4 * k + 1] * band(Ah, s_v, lane, false) + B.mk[4 * k + 3] * band(Bh, s_v, lane, false);
+          s_u[lane] = w;
+        }
+        __syncthreads();
+        double x = 0.0;
+        if (lane < nq) {
+          const double *Dk = B.Dinv + ((long long)k * nq + lane) * nq;
+          for (int i = 0; i < nq; ++i) x += Dk[i] * s_u[i];
+        }
+        __syncthreads();
+        if (lane < nq) {
+          s_v[lane] = x;
+          const double o = add ? X[at(lane, k)] + x : x;
+          X[at(lane, k)] = o;
+          xm = fmax(xm, fabs(x));
+        }
+        __syncthreads();
+      }
+    } else {
+      // U^T w = r: w_k = D_k^{-T} (r_k - S_{k-1,k}^T w_{k-1})   (w in tmp)
+      for (int k = 0; k < nx; ++k) {
+        if (lane < nq) {
+          double w = R[at(lane, k)];
+          if (k > 0)
+            w -= B.mk[4 * (k - 1) + 1] * band(Ah, s_v, lane, true) +
+                 B.mk[4 * (k - 1) + 3] * band(Bh, s_v, lane, true);
+          s_u[lane] = w;
+        }
+        __syncthreads();
+        double x = 0.0;
+        if (lane < nq)
+          for (int i = 0; i < nq; ++i) x += B.Dinv[((long long)k * nq + i) * nq + lane] * s_u[i];
+        __syncthreads();
+        if (lane < nq) {
+          s_v[lane] = x;
+          tmp[at(lane, k)] = x;
+        }
+        __syncthreads();
+      }
+      // L^T z = w: z_k = w_k - L_{k+1}^T z_{k+1}
+      for (int k = nx - 1; k >= 0; --k) {
+        double z = 0.0;
+        if (lane < nq) {
+          z = tmp[at(lane, k)];
+          if (k + 1 < nx) {
+            const double *Lk = B.Lf + (long long)(k + 1) * nq * nq;
+            for (int i = 0; i < nq; ++i) z -= Lk[(long long)i * nq + lane] * s_v[i];
+          }
+        }
+        __syncthreads();
+        if (lane < nq) {
+          s_v[lane] = z;
+          const double o = add ? X[at(lane, k)] + z : z;
+          X[at(lane, k)] = o;
+          xm = fmax(xm, fabs(z));
+        }
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int dlt = 32; dlt >= 1; dlt >>= 1) xm = fmax(xm, __shfl_xor(xm, dlt));
+    return xm;
+  };
+  // b - op(S) x, every product and sum in double-double (time matrices hi+lo,
+  // spatial entries in double); also returns max |x|
+  auto residual = [&](const double *X, double *Rout) -> double {
+#pragma clang fp contract(off)
+    double xmax = 0.0;
+    for (long long e = lane; e < (long long)nq * nx; e += 64) {
+      const int i = (int)(e / nx), k = (int)(e - (long long)i * nx);
+      dd acc = {b0[e], 0.0};
+      xmax = fmax(xmax, fabs(X[e]));
+      for (int off = -2; off <= 2; ++off) {
+        const int ii = i + off;
+        if (ii < 0 || ii >= nq) continue;
+        // spatial products (M x)_k and (K x)_k of row ii, in double-double
+        dd ym = {0.0, 0.0}, yk = {0.0, 0.0};
+        for (int sft = -1; sft <= 1; ++sft) {
+          const int kk = k + sft;
+          if (kk < 0 || kk >= nx) continue;
+          const int lo = sft < 0 ? kk : k;  // M, K symmetric tridiagonal
+          const double mv = sft == 0 ? B.mk[4 * k] : B.mk[4 * lo + 1];
+          const double kv = sft == 0 ? B.mk[4 * k + 2] : B.mk[4 * lo + 3];
+          const double x = X[at(ii, kk)];
+          ym = dd_add(ym, two_prod(mv, x));
+          yk = dd_add(yk, two_prod(kv, x));
+        }
+        const int r = tr ? ii : i, c = tr ? 2 - off : off + 2;
+        const dd ta = dd_mul(dd{Ah[r * 5 + c], Al[r * 5 + c]}, ym);
+        const dd tb = dd_mul(dd{Bh[r * 5 + c], Bl[r * 5 + c]}, yk);
+        acc = dd_add(acc, dd{-ta.h, -ta.l});
+        acc = dd_add(acc, dd{-tb.h, -tb.l});
+      }
+      Rout[e] = acc.h + acc.l;
+    }
+#pragma unroll
+    for (int dlt = 32; dlt >= 1; dlt >>= 1) xmax = fmax(xmax, __shfl_xor(xmax, dlt));
+    __syncthreads();
+    return xmax;
+  };
+  for (long long e = lane; e < (long long)nq * nx; e += 64) b0[e] = B.in[e];
+  __syncthreads();
+  apply(b0, B.out, false);
+  for (int it = 0; it < B.refine; ++it) {
+    const double xmax = residual(B.out, res);
+    const double dmax = apply(res, B.out, true);
+    if (dmax <= 1e-15 * xmax) break;
+  }
+}
+
 __global__ void k_fill(double *p, long long n, double v) {
   const long long i = gid64();
   if (i < n) p[i] = v;
@@ -1757,6 +1928,13 @@ hipError_t launch_time_solve(const SolveDesc *sd, int nsd, long long total,
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_time_solve, dim3(blocks_for(total, 64)), dim3(64), 0, s, sd, nsd,
                      total, kt, mt, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_solve(const BlockDesc *bd, int nbd, const KernelTables *kt,
+                              hipStream_t s) {
+  if (nbd == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_block_solve, dim3(nbd), dim3(64), 0, s, bd, kt);
   return hipGetLastError();
 }
 

@@ -73,6 +73,23 @@ struct SolveDesc {
                          // never spans two descriptors)
 };
 
+// One component of a 1-D variable-speed problem solved without a spatial
+// eigenbasis: block LU of S = A (x) M + B (x) K in space-major order (blocks
+// of nq x nq, one per spatial node) as an approximate inverse, refined with
+// the double-double residual of the whole component system.
+struct BlockDesc {
+  const double *in;      // right-hand side [nq][nx]
+  double *out;           // solution [nq][nx]
+  const double *Dinv;    // [nx][nq][nq] inverses of the block pivots D_k
+  const double *Lf;      // [nx][nq][nq] multipliers L_k = S_{k,k-1} D_{k-1}^{-1} (k >= 1)
+  const double *mk;      // [nx][4]: M_kk, M_{k,k+1}, K_kk, K_{k,k+1} (last two zero at k = nx-1)
+  double *work;          // 3 planes [nq][nx]: saved rhs, residual, intermediate vector
+  int nq, nx, b;         // time nodes, spatial nodes, time level
+  int transpose;         // solve with S^T
+  int refine;            // maximum refinement sweeps
+  int pad;
+};
+
 struct ModeTables {      // 1-D P1 eigenvalues per level and axis (unit c)
   const double *mx[kMaxLevels + 1];
   const double *kx[kMaxLevels + 1];
@@ -139,6 +156,8 @@ hipError_t launch_time_factor(const SolveDesc *sd, int nsd, long long total,
 hipError_t launch_time_solve(const SolveDesc *sd, int nsd, long long total,
                              const KernelTables *kt, const ModeTables *mt, int d,
                              hipStream_t s);
+hipError_t launch_block_solve(const BlockDesc *bd, int nbd, const KernelTables *kt,
+                              hipStream_t s);
 hipError_t launch_fill(double *p, long long n, double v, hipStream_t s);
 hipError_t launch_broadcast(double *out, const double *base, int nt, long long nsp,
                             hipStream_t s);

@@ -421,3 +421,102 @@ void pencil_eigen(int a, double len, const std::vector<double> &c2e, std::vector
 }
 
 }  // namespace sg
+
+namespace sg {
+
+// Block LU of S = A (x) M + B (x) K in space-major order (see tables.hpp).
+void block_lu(const TimeLevel &tl, const std::vector<double> &mk, int nx,
+              std::vector<double> &Dinv, std::vector<double> &Lf) {
+  const int nq = tl.nq;
+  typedef long double R;
+  auto band = [&](const std::vector<double> &hi, const std::vector<double> &lo, int i,
+                  int j) -> R {
+    const int off = j - i;
+    if (off < -2 || off > 2) return 0.0L;
+    return (R)hi[(size_t)i * 5 + off + 2] + (R)lo[(size_t)i * 5 + off + 2];
+  };
+  std::vector<R> Ad((size_t)nq * nq), Bd((size_t)nq * nq);
+  for (int i = 0; i < nq; ++i)
+    for (int j = 0; j < nq; ++j) {
+      Ad[(size_t)i * nq + j] = band(tl.A, tl.Alo, i, j);
+      Bd[(size_t)i * nq + j] = band(tl.B, tl.Blo, i, j);
+    }
+  auto blockS = [&](R m, R k, std::vector<R> &S) {
+    for (size_t e = 0; e < S.size(); ++e) S[e] = m * Ad[e] + k * Bd[e];
+  };
+  // inverse by Gauss-Jordan elimination with partial pivoting
+  auto invert = [&](std::vector<R> D, std::vector<R> &Inv) {
+    Inv.assign((size_t)nq * nq, 0.0L);
+    for (int i = 0; i < nq; ++i) Inv[(size_t)i * nq + i] = 1.0L;
+    for (int c = 0; c < nq; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < nq; ++r)
+        if (fabsl(D[(size_t)r * nq + c]) > fabsl(D[(size_t)piv * nq + c])) piv = r;
+      if (piv != c)
+        for (int j = 0; j < nq; ++j) {
+          std::swap(D[(size_t)c * nq + j], D[(size_t)piv * nq + j]);
+          std::swap(Inv[(size_t)c * nq + j], Inv[(size_t)piv * nq + j]);
+        }
+      const R d = D[(size_t)c * nq + c];
+      for (int j = 0; j < nq; ++j) {
+        D[(size_t)c * nq + j] /= d;
+        Inv[(size_t)c * nq + j] /= d;
+      }
+      for (int r = 0; r < nq; ++r) {
+        if (r == c) continue;
+        const R f = D[(size_t)r * nq + c];
+        if (f == 0.0L) continue;
+        for (int j = 0; j < nq; ++j) {
+          D[(size_t)r * nq + j] -= f * D[(size_t)c * nq + j];
+          Inv[(size_t)r * nq + j] -= f * Inv[(size_t)c * nq + j];
+        }
+      }
+    }
+  };
+  const size_t bs = (size_t)nq * nq;
+  Dinv.assign(bs * nx, 0.0);
+  Lf.assign(bs * nx, 0.0);
+  std::vector<R> D(bs), Di(bs), Soff(bs), Lk(bs), tmp(bs);
+  blockS(mk[0], mk[2], D);
+  invert(D, Di);
+  for (size_t e = 0; e < bs; ++e) Dinv[e] = (double)Di[e];
+  for (int k = 1; k < nx; ++k) {
+    // S_{k,k-1} = S_{k-1,k} (M and K symmetric)
+    blockS(mk[4 * (k - 1) + 1], mk[4 * (k - 1) + 3], Soff);
+    for (int i = 0; i < nq; ++i)
+      for (int j = 0; j < nq; ++j) {
+        R acc = 0.0L;
+        for (int l = 0; l < nq; ++l) acc += Soff[(size_t)i * nq + l] * Di[(size_t)l * nq + j];
+        Lk[(size_t)i * nq + j] = acc;
+      }
+    blockS(mk[4 * k], mk[4 * k + 2], D);
+    for (int i = 0; i < nq; ++i)
+      for (int j = 0; j < nq; ++j) {
+        R acc = 0.0L;
+        for (int l = 0; l < nq; ++l) acc += Lk[(size_t)i * nq + l] * Soff[(size_t)l * nq + j];
+        D[(size_t)i * nq + j] -= acc;
+      }
+    invert(D, Di);
+    for (size_t e = 0; e < bs; ++e) {
+      Dinv[bs * k + e] = (double)Di[e];
+      Lf[bs * k + e] = (double)Lk[e];
+    }
+  }
+}
+
+std::vector<double> space_entries(int a, double len, const std::vector<double> &c2e) {
+  const int ne = 1 << a, n = ne - 1;
+  const double h = len / ne;
+  std::vector<double> mk((size_t)4 * n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    mk[4 * k] = 4.0 * h / 6.0;
+    mk[4 * k + 2] = (c2e[k] + c2e[k + 1]) / h;
+    if (k + 1 < n) {
+      mk[4 * k + 1] = h / 6.0;
+      mk[4 * k + 3] = -c2e[k + 1] / h;
+    }
+  }
+  return mk;
+}
+
+}  // namespace sg

@@ -59,6 +59,17 @@ std::vector<double> element_c2(int a, double len, int ncell, const double *c_val
 void pencil_eigen(int a, double len, const std::vector<double> &c2e, std::vector<double> &V,
                   std::vector<double> &lam);
 
+// Tridiagonal M and K(c) of level a (d = 1) per interior node k:
+// [M_kk, M_{k,k+1}, K_kk, K_{k,k+1}] (the coupling entries are 0 at the last node).
+std::vector<double> space_entries(int a, double len, const std::vector<double> &c2e);
+// Block LU of the component matrix S = A (x) M + B (x) K in space-major
+// order (block k = the time values at spatial node k): D_0 = S_00,
+// L_k = S_{k,k-1} D_{k-1}^{-1}, D_k = S_kk - L_k S_{k-1,k}.  Computed in
+// extended precision from the double-double time matrices; outputs Dinv[k]
+// = D_k^{-1} and Lf[k] = L_k (row-major nq x nq each, Lf[0] unused).
+void block_lu(const TimeLevel &tl, const std::vector<double> &mk, int nx,
+              std::vector<double> &Dinv, std::vector<double> &Lf);
+
 // Orthonormal DST-I matrix of level a: Q[j][k] = sqrt(2/n) sin(pi j k/n),
 // j,k = 1..n-1, n = 2^a (symmetric, Q Q = I), row-major (n-1)^2.
 std::vector<double> dst_matrix(int a);

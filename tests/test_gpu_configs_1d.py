@@ -1,0 +1,115 @@
+"""1-D configurations with a piecewise-constant wave speed, on the GPU.
+
+* two-speed medium (c = 1 on (0, 1/2), 1/2 on (1/2, 1); L = 12, T = 2): forward
+  and adjoint element by element against the oracle; the distance to the
+  full-grid solution at level 8/8 is reported (a discretisation error, not a
+  parity check);
+* differentiation workload (8 random speeds, L = 14): gradient of the
+  least-squares misfit through torch.autograd (hand-written adjoint) against
+  the oracle's gradient (stored samples, written by
+  tests/golden/make_c4_golden.py) and against central finite differences on
+  32 unit directions.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import Problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+GOLDEN_C4 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                         "c4_L14_samples.json")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64).reshape(-1), np.asarray(b, dtype=np.float64).reshape(-1)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_two_speed_medium_parity():
+    torch = _torch()
+    import paper_2606_09688_amd as sg
+    spec, data = workloads.c2()
+    g = workloads.random_data(spec, 12)["g"]
+    print("two-speed medium: d=1 L=12 T=2", flush=True)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+    sv = sg.SparseGridWave(*spec.args())
+    U = sv.solve(dev(data["f"]), dev(data["u0"]), dev(data["v0"])).cpu().numpy()
+    df, du0, dv0 = (x.cpu().numpy() for x in sv.adjoint(dev(g)))
+    orc = Problem(*spec.args())
+    U_ref = orc.forward(data["f"], data["u0"], data["v0"]).reshape(spec.shape())
+    eU = _rel(U, U_ref)
+    print(f"  forward rel l2 {eU:.3e}", flush=True)
+    assert eU <= TOL
+    df_ref, du0_ref, dv0_ref = orc.adjoint(g)
+    for name, got, ref in (("df", df, df_ref), ("du0", du0, du0_ref), ("dv0", dv0, dv0_ref)):
+        e = _rel(got, ref)
+        print(f"  adjoint {name} rel l2 {e:.3e}", flush=True)
+        assert e <= TOL, name
+    # reported: sparse-grid solution vs the full grid P_{8,8} at its nodes
+    P88 = orc.full_grid(8, data["f"], data["u0"], data["v0"]).reshape(spec.shape())
+    step = 2 ** (spec.J - 8)
+    sub = (slice(None, None, step), slice(step - 1, None, step))
+    print(f"  |U - P_88| / |P_88| on the level-8 nodes: {_rel(U[sub], P88[sub]):.3e}", flush=True)
+
+
+def test_gradient_of_misfit():
+    torch = _torch()
+    import paper_2606_09688_amd as sg
+    with open(GOLDEN_C4) as fh:
+        gold = json.load(fh)
+    spec, data = workloads.c4()
+    print("differentiation workload: d=1 L=14, 8 speeds", flush=True)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+    sv = sg.SparseGridWave(*spec.args())
+    zero = torch.zeros(spec.space_shape(), dtype=torch.float64, device="cuda")
+    U_obs = sv.solve(dev(data["f_true"]), zero, zero) + dev(data["noise"])
+    f = dev(data["f"]).requires_grad_(True)
+    u0 = dev(data["u0"]).requires_grad_(True)
+    v0 = dev(data["v0"])
+
+    def loss(f_, u0_):
+        U = sg.sgwave(sv, f_, u0_, v0)
+        return 0.5 * torch.sum((U - U_obs) ** 2)
+
+    J = loss(f, u0)
+    J.backward()
+    gf, gu0 = f.grad.detach(), u0.grad.detach()
+    # against the oracle (stored samples of its gradient)
+    pn, pm, ps = (np.asarray(gold[k]) for k in ("pos_n", "pos_m", "pos_s"))
+    edf = _rel(gf.cpu().numpy()[pn, pm], gold["df"])
+    edu = _rel(gu0.cpu().numpy()[ps], gold["du0"])
+    eJ = abs(float(J) - gold["loss"]) / abs(gold["loss"])
+    print(f"  vs oracle: loss {eJ:.2e}  df {edf:.2e}  du0 {edu:.2e}", flush=True)
+    assert max(edf, edu) <= TOL and eJ <= TOL
+    # central finite differences on unit directions over (f, u0); J is
+    # quadratic, so the difference quotient equals the directional derivative
+    # up to rounding of the loss (~eps |J| / h)
+    h = 1e-6
+    worst = 0.0
+    with torch.no_grad():
+        for k in range(32):
+            d_f, d_u0 = workloads.c4_direction(spec, k)
+            d_f, d_u0 = dev(d_f), dev(d_u0)
+            jp = float(loss(f + h * d_f, u0 + h * d_u0))
+            jm = float(loss(f - h * d_f, u0 - h * d_u0))
+            fd = (jp - jm) / (2 * h)
+            an = float(torch.sum(gf * d_f) + torch.sum(gu0 * d_u0))
+            err = abs(fd - an) / max(abs(an), 1e-300)
+            worst = max(worst, err)
+    print(f"  finite differences (32 directions, h = 1e-6): worst rel {worst:.2e}", flush=True)
+    assert worst <= 1e-5
