@@ -171,6 +171,26 @@ sg_status sg_destroy(sg_problem *p);
 const char *sg_last_error(void);
 
 /*
+ * Batches of independent problems (any mix of d, L and wave speeds).  A batch
+ * references n assembled handles (the caller keeps them alive and owns them)
+ * and captures the forward solve - and the adjoint when g is not NULL - of
+ * every problem into one HIP graph with one parallel branch per problem
+ * (forked from and joined into the capturing stream through events).
+ * Argument arrays hold n device pointers each (host arrays); g, df, du0, dv0
+ * may be NULL as a whole, or df / du0 / dv0 entries NULL per problem.
+ * A handle must not belong to two batches or be used elsewhere while its
+ * batch graph runs.
+ */
+typedef struct sg_batch sg_batch;
+sg_status sg_batch_create(int n, sg_problem *const *problems, sg_batch **out);
+sg_status sg_batch_capture(sg_batch *b, const double *const *f, const double *const *u0,
+                           const double *const *v0, double *const *U, const double *const *g,
+                           double *const *df, double *const *du0, double *const *dv0,
+                           hipStream_t stream);
+sg_status sg_batch_launch(sg_batch *b, hipStream_t stream);
+sg_status sg_batch_destroy(sg_batch *b);
+
+/*
  * Host table (exported for tests; no device work): generalised eigenpairs of
  * the level-a P1 pencil (K(c), M) on (0,len) with c piecewise constant on
  * ncell uniform blocks (eq. (9), spatial matrices; variable wave speed in

@@ -8,5 +8,5 @@ diagonals jx + jt = L and L-1, prolonged to the finest grid and combined with
 this package only marshals torch tensors into it.
 """
 
-from .binding import (SparseGridWave, SGWaveFunction, SGError, sgwave,  # noqa: F401
+from .binding import (SparseGridWave, SparseGridBatch, SGWaveFunction, SGError, sgwave,  # noqa: F401
                       host_pencil, host_taps, host_time_level, lib, LIB_PATH)

@@ -42,6 +42,12 @@ SIGNATURES = {
                                     ctypes.c_double, _c_ip, _c_dp]),
     "sg_host_pencil": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, _c_dp,
                                       _c_dp, _c_dp]),
+    "sg_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    "sg_batch_capture": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_void_p)] * 8
+                         + [ctypes.c_void_p]),
+    "sg_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sg_set_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                      ctypes.c_int]),
     "sg_destroy": (ctypes.c_int, [ctypes.c_void_p]),
@@ -243,6 +249,55 @@ class SparseGridWave:
 
     def replay(self, stream=None):
         check(lib().sg_graph_launch(self._h, _stream(stream)), "sg_graph_launch")
+
+
+class SparseGridBatch:
+    """Independent problems (any mix of d, L, speeds) captured into one HIP
+    graph, one parallel branch per problem (sg_batch_*).  The solvers must
+    stay alive while the batch exists."""
+
+    def __init__(self, solvers):
+        self._solvers = list(solvers)
+        n = len(self._solvers)
+        arr = (ctypes.c_void_p * n)(*[s._h for s in self._solvers])
+        h = ctypes.c_void_p()
+        check(lib().sg_batch_create(n, arr, ctypes.byref(h)), "sg_batch_create")
+        self._h = h
+        self._keep = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                lib().sg_batch_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def capture(self, f, u0, v0, U, g=None, df=None, du0=None, dv0=None, stream=None):
+        """Lists (one entry per problem) of device tensors, shapes as for
+        SparseGridWave; g/df/du0/dv0 may be None (forward only)."""
+        n = len(self._solvers)
+
+        def ptrs(lst, shapes, name, allow_none=False):
+            if lst is None:
+                return None
+            if len(lst) != n:
+                raise ValueError(f"{name} needs one entry per problem")
+            out = [_ptr(t, shp, f"{name}[{i}]", allow_none)
+                   for i, (t, shp) in enumerate(zip(lst, shapes))]
+            return (ctypes.c_void_p * n)(*[None if v is None else v.value for v in out])
+
+        sh = [s.shape for s in self._solvers]
+        ssh = [s.space_shape for s in self._solvers]
+        args = [ptrs(f, sh, "f"), ptrs(u0, ssh, "u0"), ptrs(v0, ssh, "v0"), ptrs(U, sh, "U"),
+                ptrs(g, sh, "g"), ptrs(df, sh, "df", True), ptrs(du0, ssh, "du0", True),
+                ptrs(dv0, ssh, "dv0", True)]
+        self._keep = (f, u0, v0, U, g, df, du0, dv0)  # buffers referenced by the graph
+        check(lib().sg_batch_capture(self._h, *args, _stream(stream)), "sg_batch_capture")
+
+    def replay(self, stream=None):
+        check(lib().sg_batch_launch(self._h, _stream(stream)), "sg_batch_launch")
 
 
 class SGWaveFunction(torch.autograd.Function):

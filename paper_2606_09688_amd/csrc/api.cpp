@@ -1136,6 +1136,122 @@ sg_status sg_graph_capture(sg_problem *p, const double *f, const double *u0,
   return SG_OK;
 }
 
+}  // extern "C"
+
+struct sg_batch {
+  std::vector<sg_problem *> probs;
+  std::vector<hipStream_t> streams;  // fork/join branches used while capturing
+  std::vector<hipEvent_t> events;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
+extern "C" {
+
+sg_status sg_batch_destroy(sg_batch *b) {
+  if (!b) return SG_OK;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  delete b;
+  return SG_OK;
+}
+
+sg_status sg_batch_create(int n, sg_problem *const *problems, sg_batch **out) {
+  g_last_error.clear();
+  if (!out || !problems || n < 1) return fail(SG_EINVAL, "need n >= 1 problems and an output");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!problems[i]) return fail(SG_EINVAL, "NULL problem handle");
+    for (int j = 0; j < i; ++j)
+      if (problems[j] == problems[i]) return fail(SG_EINVAL, "a handle appears twice");
+  }
+  sg_batch *b = new (std::nothrow) sg_batch();
+  if (!b) return fail(SG_ENOMEM, "host allocation failed");
+  b->probs.assign(problems, problems + n);
+  // a few branch streams (default priority); problems are dealt round-robin
+  const int ns = std::min(n, 8);
+  for (int i = 0; i < ns; ++i) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      sg_batch_destroy(b);
+      return fail(SG_EDEVICE, "hipStreamCreateWithFlags failed");
+    }
+    b->streams.push_back(st);
+  }
+  for (int i = 0; i < 2 * n + 1; ++i) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      sg_batch_destroy(b);
+      return fail(SG_EDEVICE, "hipEventCreateWithFlags failed");
+    }
+    b->events.push_back(e);
+  }
+  *out = b;
+  return SG_OK;
+}
+
+sg_status sg_batch_capture(sg_batch *b, const double *const *f, const double *const *u0,
+                           const double *const *v0, double *const *U, const double *const *g,
+                           double *const *df, double *const *du0, double *const *dv0,
+                           hipStream_t s) {
+  if (!b) return fail(SG_EINVAL, "NULL batch");
+  if (!f || !u0 || !v0 || !U) return fail(SG_EINVAL, "NULL argument array");
+  if (s == nullptr) return fail(SG_ESTATE, "batch capture needs a non-default stream");
+  const int n = (int)b->probs.size();
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  // no stage events inside a batch graph (restored afterwards)
+  std::vector<std::vector<hipEvent_t>> saved(n);
+  for (int i = 0; i < n; ++i) saved[i].swap(b->probs[i]->ev);
+  HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  sg_status st = SG_OK;
+  hipError_t e = hipEventRecord(b->events[2 * n], s);  // fork point
+  for (int i = 0; st == SG_OK && e == hipSuccess && i < n; ++i) {
+    hipStream_t bs = b->streams[i % b->streams.size()];
+    sg_problem *p = b->probs[i];
+    e = hipStreamWaitEvent(bs, b->events[2 * n], 0);
+    if (e != hipSuccess) break;
+    p->capturing = true;
+    st = sg_solve(p, f[i], u0[i], v0[i], U[i], bs);
+    if (st == SG_OK && g != nullptr && g[i] != nullptr)
+      st = sg_adjoint(p, g[i], df ? df[i] : nullptr, du0 ? du0[i] : nullptr,
+                      dv0 ? dv0[i] : nullptr, bs);
+    p->capturing = false;
+    if (st == SG_OK) e = hipEventRecord(b->events[i], bs);
+    if (st == SG_OK && e == hipSuccess) e = hipStreamWaitEvent(s, b->events[i], 0);  // join
+  }
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(s, &graph);
+  for (int i = 0; i < n; ++i) saved[i].swap(b->probs[i]->ev);
+  if (st != SG_OK || e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    if (st != SG_OK) return st;
+    return fail(SG_EDEVICE, std::string("batch capture: ") +
+                                hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  b->graph = graph;
+  HIPCHK(hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0));
+  return SG_OK;
+}
+
+sg_status sg_batch_launch(sg_batch *b, hipStream_t s) {
+  if (!b) return fail(SG_EINVAL, "NULL batch");
+  if (!b->gexec) return fail(SG_ESTATE, "no captured batch graph");
+  HIPCHK(hipGraphLaunch(b->gexec, s));
+  return SG_OK;
+}
+
 sg_status sg_graph_launch(sg_problem *p, hipStream_t s) {
   if (!p) return fail(SG_EINVAL, "NULL handle");
   if (!p->gexec) return fail(SG_ESTATE, "no captured graph");

@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_restrict(const RestrictArgs A) {
     }
     __syncthreads();
     // (3) levels r = 1..R: owners restrict from level r-1 and accumulate
-#pragma unroll
+#pragma unroll 1
     for (int r = 1; r <= LTS; ++r) {
       if (r > R) break;
 #pragma unroll
@@ -800,7 +800,7 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
     if (nb + TB < n1) fetch_taps(nb + TB);
     // phase A: owners evaluate their node in time (register windows); the
     // level loop is unrolled so that channel fields are wave-uniform
-#pragma unroll
+#pragma unroll 1
     for (int r = 1; r <= LTS; ++r) {
       if (r > R) break;
 #pragma unroll
@@ -829,7 +829,7 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
     }
     __syncthreads();
     // phase B: top-down interpolation r = R-1 .. 1 (owners of level r)
-#pragma unroll
+#pragma unroll 1
     for (int r = LTS - 1; r >= 1; --r) {
       if (r >= R) continue;
       const int nr = SH::nodes(r), pn = SH::nodes(r + 1);
@@ -1277,8 +1277,15 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
                                                    int nsd, long long total,
                                                    const KernelTables *__restrict__ kt,
                                                    const ModeTables *__restrict__ mt, int d) {
-  constexpr int CH = 16;  // rows per register chunk of a substitution
-  constexpr int CR = 8;   // rows per register chunk of the residual
+  // rows per register chunk of a substitution / of the residual (thread path)
+#ifndef SG_CH
+#define SG_CH 16
+#endif
+#ifndef SG_CR
+#define SG_CR 8
+#endif
+  constexpr int CH = SG_CH;
+  constexpr int CR = SG_CR;
   const long long wbase = (long long)blockIdx.x * 64;
   const SolveDesc &S = sds[find_solve(sds, nsd, wbase)];
   const int lane = threadIdx.x;
