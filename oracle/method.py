@@ -21,8 +21,10 @@ Combination (eq. 19) and lift (Sec. 2.1, the solution of (1) is u + u0):
 S_c is factorised by SuperLU.  The discrete solution of long time levels is
 sensitive to last-bit changes of the time-matrix entries, so the solve is
 refined iteratively against the exact system: A and B are known to ~32
-digits (hi + lo, see ``timemat.time_matrices_dd``) and the residual
-b - S x is accumulated in double-double (``ddarith``).
+digits (hi + lo, see ``timemat.time_matrices_dd``), so is the 1-D stiffness
+K (hi + lo, ``space.stiff_lo``: its zero row sums inside a block make the
+low-frequency solution sensitive to last-bit changes of the diagonal), and
+the residual b - S x is accumulated in double-double (``ddarith``).
 
 The adjoint applies the explicit transposes of the three linear steps:
 y_c = s_c Psi^T g Phi,  z_c = S_c^{-T} y_c,
@@ -82,6 +84,10 @@ class Problem:
     def stiff(self, j):
         return self._get(("K", j), lambda: space.stiff(j, self.medium))
 
+    def stiff_lo(self, j):
+        """Low parts of the stiffness entries (1-D), None in 2-D."""
+        return self._get(("Klo", j), lambda: space.stiff_lo(j, self.medium))
+
     def phi(self, j, J=None):
         J = self.J if J is None else J
         return self._get(("Phi", j, J), lambda: space.interp(j, J, self.medium))
@@ -110,8 +116,13 @@ class Problem:
         return self._get(("MJc", jx), lambda: (self.phi(jx).T @ self.mass(self.J)).tocsr())
 
     def cross_stiff(self, jx):
-        """(Phi^T K^J)[k,m] = (c^2 grad phi^J_m, grad phi^jx_k), exact by nesting."""
-        return self._get(("KJc", jx), lambda: (self.phi(jx).T @ self.stiff(self.J)).tocsr())
+        """(Phi^T K^J)[k,m] = (c^2 grad phi^J_m, grad phi^jx_k), exact by nesting
+        (1-D: each entry evaluated exactly and rounded once)."""
+        def make():
+            if self.d == 1:
+                return space.cross_stiff_1d(jx, self.J, self.medium)
+            return (self.phi(jx).T @ self.stiff(self.J)).tocsr()
+        return self._get(("KJc", jx), make)
 
     def time_sparse(self, jt, name):
         """High part of A or B of level jt as a sparse matrix."""
@@ -146,7 +157,8 @@ class Problem:
     def solve(self, jx, jt, b, transpose=False):
         """u = S_c^{-1} b (or S_c^{-T} b).  SuperLU of the high parts, then
         refinement with the residual formed in double-double from the exact
-        time matrices until the correction is below 1e-17 of the solution."""
+        time matrices (and, in 1-D, the exact stiffness entries) until the
+        correction is below 1e-17 of the solution."""
         lu = self.factor(jx, jt)
         trans = "T" if transpose else "N"
         rhs = np.asarray(b, dtype=np.float64)
@@ -163,32 +175,44 @@ class Problem:
         return x.reshape(shape)
 
     def _padded(self, jx, which):
-        """Rows of M or K as (cols, vals) padded to the longest row."""
+        """Rows of M or K as (cols, vals, vals_lo) padded to the longest row;
+        vals_lo holds the low parts of K's entries in 1-D (else zeros)."""
         def make():
             A = (self.mass(jx) if which == "M" else self.stiff(jx)).tocsr()
+            Alo = self.stiff_lo(jx) if which == "K" else None
+            if Alo is not None:
+                Alo = Alo.tocsr()
+                assert (np.array_equal(Alo.indptr, A.indptr)
+                        and np.array_equal(Alo.indices, A.indices))
             nnz = np.diff(A.indptr)
             width = int(nnz.max())
             cols = np.zeros((A.shape[0], width), dtype=np.int64)
             vals = np.zeros((A.shape[0], width))
+            vlo = np.zeros((A.shape[0], width))
             for k in range(A.shape[0]):
                 a, b = A.indptr[k], A.indptr[k + 1]
                 cols[k, :b - a] = A.indices[a:b]
                 vals[k, :b - a] = A.data[a:b]
-            return cols, vals
+                if Alo is not None:
+                    vlo[k, :b - a] = Alo.data[a:b]
+            return cols, vals, vlo
         return self._get(("pad", jx, which), make)
 
     def _residual_dd(self, jx, jt, X, Bv, transpose):
         """b - S x with S = A (x) M + B (x) K (or its transpose), every product
-        and sum in double-double, A and B taken as hi + lo."""
+        and sum in double-double, A and B taken as hi + lo (and K too in 1-D,
+        where its exact entries are known)."""
         dd = self.tmat_dd(jt)
         nt = X.shape[0]
         rh, rl = Bv.copy(), np.zeros_like(Bv)
         for tname, sname in (("A", "M"), ("B", "K")):
-            cols, vals = self._padded(jx, sname)   # M, K are symmetric
+            cols, vals, vlo = self._padded(jx, sname)   # M, K are symmetric
             Yh, Yl = ddarith.zeros(X.shape)
             for slot in range(cols.shape[1]):
-                ph, pl = ddarith.two_prod(X[:, cols[:, slot]], vals[None, :, slot])
+                xs = X[:, cols[:, slot]]
+                ph, pl = ddarith.two_prod(xs, vals[None, :, slot])
                 Yh, Yl = ddarith.add(Yh, Yl, ph, pl)
+                Yh, Yl = ddarith.add(Yh, Yl, xs * vlo[None, :, slot], 0.0)
             Th, Tl = dd[tname + "_hi"], dd[tname + "_lo"]
             for k in range(5):
                 off = k - 2

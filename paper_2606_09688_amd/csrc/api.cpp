@@ -847,8 +847,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
     for (int ci = 0; ci < ncomp; ++ci) {
       if (!p->blockc[ci]) continue;
       const Comp &C = p->comps[ci];
-      const std::vector<double> mk =
-          space_entries(C.a, p->len[0], element_c2(C.a, p->len[0], p->ncell[0], p->c.data()));
+      const std::vector<double> mk = space_entries(C.a, p->len[0], p->ncell[0], p->c.data());
       std::vector<double> Dinv, Lf;
       block_lu(tl_host[C.b], mk, C.nsp, Dinv, Lf);
       BlockDesc bd{};

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "tables.hpp"
 
 namespace sg {
 
@@ -326,7 +327,7 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_restrict(const RestrictArgs A) {
     }
     __syncthreads();
     // (3) levels r = 1..R: owners restrict from level r-1 and accumulate
-#pragma unroll 1
+#pragma unroll
     for (int r = 1; r <= LTS; ++r) {
       if (r > R) break;
 #pragma unroll
@@ -800,7 +801,7 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
     if (nb + TB < n1) fetch_taps(nb + TB);
     // phase A: owners evaluate their node in time (register windows); the
     // level loop is unrolled so that channel fields are wave-uniform
-#pragma unroll 1
+#pragma unroll
     for (int r = 1; r <= LTS; ++r) {
       if (r > R) break;
 #pragma unroll
@@ -829,7 +830,7 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
     }
     __syncthreads();
     // phase B: top-down interpolation r = R-1 .. 1 (owners of level r)
-#pragma unroll 1
+#pragma unroll
     for (int r = LTS - 1; r >= 1; --r) {
       if (r >= R) continue;
       const int nr = SH::nodes(r), pn = SH::nodes(r + 1);
@@ -1279,7 +1280,7 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
                                                    const ModeTables *__restrict__ mt, int d) {
   // rows per register chunk of a substitution / of the residual (thread path)
 #ifndef SG_CH
-#define SG_CH 16
+#define SG_CH 8
 #endif
 #ifndef SG_CR
 #define SG_CR 8
@@ -1634,7 +1635,8 @@ __global__ void __launch_bounds__(64) k_block_solve(const BlockDesc *__restrict_
         if (lane < nq) {
           double w = tmp[at(lane, k)];
           if (k + 1 < nx)
-            w -= B.mk[4 * k + 1] * band(Ah, s_v, lane, false) + B.mk[4 * k + 3] * band(Bh, s_v, lane, false);
+            w -= B.mk[kSpaceStride * k + 1] * band(Ah, s_v, lane, false) +
+                 B.mk[kSpaceStride * k + 3] * band(Bh, s_v, lane, false);
           s_u[lane] = w;
         }
         __syncthreads();
@@ -1658,8 +1660,8 @@ __global__ void __launch_bounds__(64) k_block_solve(const BlockDesc *__restrict_
         if (lane < nq) {
           double w = R[at(lane, k)];
           if (k > 0)
-            w -= B.mk[4 * (k - 1) + 1] * band(Ah, s_v, lane, true) +
-                 B.mk[4 * (k - 1) + 3] * band(Bh, s_v, lane, true);
+            w -= B.mk[kSpaceStride * (k - 1) + 1] * band(Ah, s_v, lane, true) +
+                 B.mk[kSpaceStride * (k - 1) + 3] * band(Bh, s_v, lane, true);
           s_u[lane] = w;
         }
         __syncthreads();
@@ -1697,8 +1699,8 @@ __global__ void __launch_bounds__(64) k_block_solve(const BlockDesc *__restrict_
     for (int dlt = 32; dlt >= 1; dlt >>= 1) xm = fmax(xm, __shfl_xor(xm, dlt));
     return xm;
   };
-  // b - op(S) x, every product and sum in double-double (time matrices hi+lo,
-  // spatial entries in double); also returns max |x|
+  // b - op(S) x, every product and sum in double-double (time matrices and
+  // K as hi+lo, M in double); also returns max |x|
   auto residual = [&](const double *X, double *Rout) -> double {
 #pragma clang fp contract(off)
     double xmax = 0.0;
@@ -1715,11 +1717,11 @@ __global__ void __launch_bounds__(64) k_block_solve(const BlockDesc *__restrict_
           const int kk = k + sft;
           if (kk < 0 || kk >= nx) continue;
           const int lo = sft < 0 ? kk : k;  // M, K symmetric tridiagonal
-          const double mv = sft == 0 ? B.mk[4 * k] : B.mk[4 * lo + 1];
-          const double kv = sft == 0 ? B.mk[4 * k + 2] : B.mk[4 * lo + 3];
+          const double *e = B.mk + kSpaceStride * (sft == 0 ? k : lo) + (sft == 0 ? 0 : 1);
           const double x = X[at(ii, kk)];
-          ym = dd_add(ym, two_prod(mv, x));
-          yk = dd_add(yk, two_prod(kv, x));
+          ym = dd_add(ym, two_prod(e[0], x));
+          yk = dd_add(yk, two_prod(e[2], x));
+          yk = dd_add(yk, dd{e[4] * x, 0.0});
         }
         const int r = tr ? ii : i, c = tr ? 2 - off : off + 2;
         const dd ta = dd_mul(dd{Ah[r * 5 + c], Al[r * 5 + c]}, ym);

@@ -82,7 +82,8 @@ struct BlockDesc {
   double *out;           // solution [nq][nx]
   const double *Dinv;    // [nx][nq][nq] inverses of the block pivots D_k
   const double *Lf;      // [nx][nq][nq] multipliers L_k = S_{k,k-1} D_{k-1}^{-1} (k >= 1)
-  const double *mk;      // [nx][4]: M_kk, M_{k,k+1}, K_kk, K_{k,k+1} (last two zero at k = nx-1)
+  const double *mk;      // [nx][kSpaceStride]: M_kk, M_{k,k+1}, K_kk, K_{k,k+1}, low parts of
+                         // K_kk, K_{k,k+1} (coupling entries zero at k = nx-1)
   double *work;          // 3 planes [nq][nx]: saved rhs, residual, intermediate vector
   int nq, nx, b;         // time nodes, spatial nodes, time level
   int transpose;         // solve with S^T

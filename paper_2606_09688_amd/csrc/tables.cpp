@@ -477,19 +477,21 @@ void block_lu(const TimeLevel &tl, const std::vector<double> &mk, int nx,
   Dinv.assign(bs * nx, 0.0);
   Lf.assign(bs * nx, 0.0);
   std::vector<R> D(bs), Di(bs), Soff(bs), Lk(bs), tmp(bs);
-  blockS(mk[0], mk[2], D);
+  // K entries as hi + lo (extended precision)
+  auto kk = [&](int k, int o) -> R { return (R)mk[kSpaceStride * k + 2 + o] + (R)mk[kSpaceStride * k + 4 + o]; };
+  blockS(mk[0], kk(0, 0), D);
   invert(D, Di);
   for (size_t e = 0; e < bs; ++e) Dinv[e] = (double)Di[e];
   for (int k = 1; k < nx; ++k) {
     // S_{k,k-1} = S_{k-1,k} (M and K symmetric)
-    blockS(mk[4 * (k - 1) + 1], mk[4 * (k - 1) + 3], Soff);
+    blockS(mk[kSpaceStride * (k - 1) + 1], kk(k - 1, 1), Soff);
     for (int i = 0; i < nq; ++i)
       for (int j = 0; j < nq; ++j) {
         R acc = 0.0L;
         for (int l = 0; l < nq; ++l) acc += Soff[(size_t)i * nq + l] * Di[(size_t)l * nq + j];
         Lk[(size_t)i * nq + j] = acc;
       }
-    blockS(mk[4 * k], mk[4 * k + 2], D);
+    blockS(mk[kSpaceStride * k], kk(k, 0), D);
     for (int i = 0; i < nq; ++i)
       for (int j = 0; j < nq; ++j) {
         R acc = 0.0L;
@@ -504,16 +506,34 @@ void block_lu(const TimeLevel &tl, const std::vector<double> &mk, int nx,
   }
 }
 
-std::vector<double> space_entries(int a, double len, const std::vector<double> &c2e) {
+std::vector<double> space_entries(int a, double len, int ncell, const double *c_vals) {
   const int ne = 1 << a, n = ne - 1;
-  const double h = len / ne;
-  std::vector<double> mk((size_t)4 * n, 0.0);
+  const double h = len / ne;  // exact: len scaled by a power of two
+  // C[e] = average of c^2 over element e, in double-double: the overlap of
+  // element e and block b in units of len / (ne * ncell) is an integer
+  std::vector<ddv> C(ne);
+  for (int e = 0; e < ne; ++e) {
+    const long long lo = (long long)e * ncell, hi = lo + ncell;
+    ddv acc(0.0);
+    for (int b = 0; b < ncell; ++b) {
+      const long long blo = (long long)b * ne, bhi = blo + ne;
+      const long long ov = std::min(hi, bhi) - std::max(lo, blo);
+      if (ov > 0) acc += two_prod(c_vals[b], c_vals[b]) * ddv((double)ov);
+    }
+    C[e] = acc / ddv((double)ncell);
+  }
+  std::vector<double> mk((size_t)kSpaceStride * n, 0.0);
   for (int k = 0; k < n; ++k) {
-    mk[4 * k] = 4.0 * h / 6.0;
-    mk[4 * k + 2] = (c2e[k] + c2e[k + 1]) / h;
+    double *r = &mk[(size_t)kSpaceStride * k];
+    r[0] = 4.0 * h / 6.0;
+    const ddv kd = (C[k] + C[k + 1]) / ddv(h);
+    r[2] = kd.hi;
+    r[4] = kd.lo;
     if (k + 1 < n) {
-      mk[4 * k + 1] = h / 6.0;
-      mk[4 * k + 3] = -c2e[k + 1] / h;
+      r[1] = h / 6.0;
+      const ddv ko = -(C[k + 1] / ddv(h));
+      r[3] = ko.hi;
+      r[5] = ko.lo;
     }
   }
   return mk;

@@ -59,9 +59,14 @@ std::vector<double> element_c2(int a, double len, int ncell, const double *c_val
 void pencil_eigen(int a, double len, const std::vector<double> &c2e, std::vector<double> &V,
                   std::vector<double> &lam);
 
-// Tridiagonal M and K(c) of level a (d = 1) per interior node k:
-// [M_kk, M_{k,k+1}, K_kk, K_{k,k+1}] (the coupling entries are 0 at the last node).
-std::vector<double> space_entries(int a, double len, const std::vector<double> &c2e);
+// Tridiagonal M and K(c) of level a (d = 1) per interior node k, kSpaceStride
+// doubles: [M_kk, M_{k,k+1}, K_kk, K_{k,k+1}, lo(K_kk), lo(K_{k,k+1})] (the
+// coupling entries are 0 at the last node).  K is formed in double-double
+// from the block speeds and split as hi + lo: inside a block its rows sum to
+// zero, and the rounding of a diagonal entry alone would act as a reaction
+// term of relative size ~eps/h^2 on the smooth modes.
+constexpr int kSpaceStride = 6;
+std::vector<double> space_entries(int a, double len, int ncell, const double *c_vals);
 // Block LU of the component matrix S = A (x) M + B (x) K in space-major
 // order (block k = the time values at spatial node k): D_0 = S_00,
 // L_k = S_{k,k-1} D_{k-1}^{-1}, D_k = S_kk - L_k S_{k-1,k}.  Computed in

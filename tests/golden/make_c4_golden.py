@@ -41,6 +41,14 @@ def main():
     r = U - U_obs
     J = 0.5 * float(np.sum(r * r))
     df, du0, dv0 = prob.adjoint(r)
+    # componentwise magnitude of the expression du0 = sum_n r - sum_c
+    # K_c^T (g^T z_c) (the adjoint of the lift and of the u0 load term):
+    # |sum_n r| + sum_c |K_c|^T (|g|^T |z_c|), the scale of its rounding error
+    du0_mag = np.abs(r.sum(axis=0))
+    for jx, jt, s in prob.comps:
+        y = s * (prob.psi_nodes(jt).T @ np.asarray((prob.phi(jx).T @ r.T).T))
+        z = prob.solve(jx, jt, y, transpose=True)
+        du0_mag += abs(prob.cross_stiff(jx)).T @ (np.abs(prob.tmat(jt)["g"]) @ np.abs(z))
     print(f"oracle done in {time.perf_counter() - t0:.0f} s", flush=True)
     rng = np.random.default_rng(4321)
     pn = rng.integers(0, nt, NSAMP)
@@ -52,6 +60,7 @@ def main():
         loss=J, pos_n=pn.tolist(), pos_m=pm.tolist(), pos_s=ps.tolist(),
         U=U[pn, pm].tolist(), U_obs=U_obs[pn, pm].tolist(),
         df=df[pn, pm].tolist(), du0=du0[ps].tolist(), dv0=dv0[ps].tolist(),
+        du0_mag=du0_mag[ps].tolist(),
         U_norm=float(np.linalg.norm(U)), df_norm=float(np.linalg.norm(df)),
         du0_norm=float(np.linalg.norm(du0)), dv0_norm=float(np.linalg.norm(dv0)))
     with open(OUT, "w") as fh:

@@ -7,10 +7,11 @@
 * differentiation workload (8 random speeds, L = 14): gradient of the
   least-squares misfit through torch.autograd (hand-written adjoint) against
   the oracle's gradient (stored samples, written by
-  tests/golden/make_c4_golden.py) and against central finite differences on
-  32 unit directions (h = 1e-6 as in the workload's definition, bounded by
-  the rounding floor of the loss, and h = 1e-2, where the exact quadratic
-  makes a tight check possible).
+  tests/golden/make_c4_golden.py; du0 within a few units of rounding of its
+  componentwise magnitude, see the test) and against central finite
+  differences on 32 unit directions (h = 1e-6 as in the workload's
+  definition, bounded by the rounding floor of the loss, and h = 1e-2, where
+  the exact quadratic makes a tight check possible).
 """
 
 import json
@@ -94,17 +95,29 @@ def test_gradient_of_misfit():
     # against the oracle (stored samples of its gradient)
     pn, pm, ps = (np.asarray(gold[k]) for k in ("pos_n", "pos_m", "pos_s"))
     edf = _rel(gf.cpu().numpy()[pn, pm], gold["df"])
-    edu = _rel(gu0.cpu().numpy()[ps], gold["du0"])
-    eJ = abs(float(J) - gold["loss"]) / abs(gold["loss"])
-    print(f"  vs oracle: loss {eJ:.2e}  df {edf:.2e}  du0 {edu:.2e}", flush=True)
-    assert max(edf, edu) <= TOL and eJ <= TOL
+    gu = gu0.cpu().numpy()[ps]
+    edu = _rel(gu, gold["du0"])
+    # du0 = sum_n r - sum_c K_c^T (g^T z_c) (adjoint of the lift and of the u0
+    # load term).  At this workload the finest-level summand applies K to a
+    # field ~1e7 larger than the result, and the summands cancel further, so
+    # the FP64 rounding of the expression itself (on either side) is ~1e-9 of
+    # |du0|: du0 is held to a few units of rounding of its componentwise
+    # magnitude |sum_n r| + sum_c |K_c|^T (|g|^T |z_c|) (stored by the oracle;
+    # ~8.5e7 |du0| at the sampled nodes), i.e. to ~7e-7 relative, instead.
+    eps = 2.0 ** -52
+    edu_ulp = float(np.linalg.norm(gu - np.asarray(gold["du0"])) /
+                    (eps * np.linalg.norm(gold["du0_mag"])))
+    eJ = abs(float(J.detach()) - gold["loss"]) / abs(gold["loss"])
+    print(f"  vs oracle: loss {eJ:.2e}  df {edf:.2e}  du0 {edu:.2e} "
+          f"({edu_ulp:.2f} eps of its componentwise magnitude)", flush=True)
+    assert edf <= TOL and eJ <= TOL
+    assert edu <= TOL or edu_ulp <= 8.0
     # central finite differences on unit directions over (f, u0).  J is
     # quadratic, so the difference quotient has no truncation error at any h;
     # its error is the rounding of the two loss values, ~eps |J| / h.  At
     # h = 1e-6 the check is bounded by that floor; at h = 1e-2 the floor is
     # far below 1e-6 of the directional derivative and the check is tight.
-    eps = 2.0 ** -52
-    Jv = abs(float(J))
+    Jv = abs(float(J.detach()))
     with torch.no_grad():
         for h, tight in ((1e-6, False), (1e-2, True)):
             worst = 0.0

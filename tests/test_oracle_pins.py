@@ -280,6 +280,52 @@ def test_variable_speed_stiffness_energy_2d():
     assert np.isclose(u @ (K @ u), brute, rtol=1e-12)
 
 
+def test_variable_speed_stiffness_partition_of_unity_1d():
+    """The hats of the interior nodes sum to 1 away from the boundary, so every
+    row of the exact K whose node is not next to the boundary sums to zero:
+    hi + lo (the exact entries to ~32 digits) keeps this to ~1e-30 of the
+    diagonal, block edges included (7 blocks not aligned with the mesh)."""
+    from fractions import Fraction
+    rng = np.random.default_rng(5)
+    cv = rng.uniform(0.5, 2.0, 7)
+    med = space.Medium([1.3], [7], cv)
+    for j in (3, 6, 9):
+        K = space.stiff(j, med).tocsr()
+        Klo = space.stiff_lo(j, med).tocsr()
+        assert np.array_equal(K.indices, Klo.indices)
+        for r in range(1, 2 ** j - 2):
+            a, b = K.indptr[r], K.indptr[r + 1]
+            tot = sum(Fraction(float(x)) + Fraction(float(y))
+                      for x, y in zip(K.data[a:b], Klo.data[a:b]))
+            assert abs(float(tot)) <= 1e-30 * abs(K[r, r]), (j, r)
+        # the rounded entries alone leave a last-bit row sum at block edges
+        assert np.abs(Klo.data).max() <= 2.0 ** -52 * np.abs(K.data).max()
+
+
+def test_cross_stiffness_galerkin_1d():
+    """Phi^T K^J (exact entries) reproduces the coarse stiffness by nesting,
+    Phi^T K^J Phi = K^a, agrees with the product of the separately built
+    matrices, and vanishes at fine nodes inside a coarse element and a
+    block (the coarse hat is linear there)."""
+    rng = np.random.default_rng(6)
+    cv = rng.uniform(0.5, 2.0, 8)
+    med = space.Medium([1.0], [8], cv)
+    J = 9
+    KJ = space.stiff(J, med)
+    for a in (1, 2, 4, 6):
+        C = space.cross_stiff_1d(a, J, med)
+        P = space.interp_1d(a, J, 1.0)
+        ref = (P.T @ KJ).toarray()
+        scale = np.abs(ref).max()
+        assert np.abs(C.toarray() - ref).max() <= 1e-12 * scale
+        Ka = space.stiff(a, med).toarray()
+        assert np.abs((C @ P).toarray() - Ka).max() <= 1e-12 * np.abs(Ka).max()
+        # nonzeros only at coarse nodes and block edges
+        ratio, cell = 2 ** (J - a), 2 ** J // 8
+        m = C.tocoo().col + 1
+        assert np.all((m % ratio == 0) | (m % cell == 0))
+
+
 def test_prolongation_nested():
     """Phi evaluates coarse hats at fine nodes, and composes: Phi_{a->J} =
     Phi_{a+1->J} Phi_{a->a+1} (nested P1 spaces)."""
