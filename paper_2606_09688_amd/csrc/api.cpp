@@ -57,6 +57,7 @@ struct Pass {
   WorkItem *d_crs = nullptr;      // coarse levels
   int n_crs = 0;
   long long tot_crs = 0;
+  TapEntry *d_taps = nullptr;     // per-slab taps of the in-tile channels (16-tiles)
 };
 
 struct GemmList {
@@ -167,15 +168,18 @@ sg_status upload(sg_problem *p, const std::vector<T> &h, T **out) {
   return SG_OK;
 }
 
-Geometry make_geometry(int d, int J, int ntf, int chunk_target_wg) {
+// Tiles of side ts (0: the prolongation default, 32 in 2-D and 256 in 1-D);
+// time chunks so that tiles x chunks is about chunk_target_wg.
+Geometry make_geometry(int d, int J, int ntf, int chunk_target_wg, int ts = 0) {
   Geometry g{};
   g.d = d;
   g.J = J;
   g.N = 1 << J;
   g.nxf = g.N - 1;
   g.ntf = ntf;
-  g.TS = d == 2 ? 32 : 256;
-  g.lts = d == 2 ? 5 : 8;
+  g.TS = ts > 0 ? ts : (d == 2 ? 32 : 256);
+  g.lts = 0;
+  while ((1 << (g.lts + 1)) <= g.TS) ++g.lts;
   g.ntile = g.N >= g.TS ? g.N / g.TS : 1;
   g.R = std::min(g.lts, J - 1);
   g.A0 = J - g.R;
@@ -202,6 +206,7 @@ struct ChanSpec {
   const int *q0 = nullptr;
   const double *w = nullptr;
   const std::vector<int> *hq0 = nullptr;  // host copy to size partial blocks
+  const std::vector<double> *hw = nullptr;  // host copy of the weights
   double *data = nullptr;
   double scale = 1.0;
 };
@@ -264,6 +269,34 @@ sg_status build_pass(sg_problem *p, Pass &P, const Geometry &geo, F spec,
   }
   *part_need = std::max(*part_need, off);
   sg_status st;
+  if (geo.d == 2 && geo.TS == 16) {
+    // per slab n and in-tile channel li = 2 r + k (level a = J - r): the tap
+    // weights, and where the window's oldest time node goes when it closes
+    const int nci = 2 * (geo.lts + 1);
+    std::vector<TapEntry> taps((size_t)geo.ntf * nci, TapEntry{{0.0, 0.0, 0.0}, -1});
+    for (int li = 0; li < nci; ++li) {
+      const int r = li >> 1, k = li & 1;
+      if (r > geo.R) continue;
+      const Channel &C = P.h_ch[(J - r - 1) * 2 + k];
+      if (!C.active) continue;
+      const ChanSpec cs = spec(J - r, k);
+      const std::vector<int> &q0 = *cs.hq0;
+      const std::vector<double> &w = *cs.hw;
+      if (r == 0 && k == 1)  // the kernel keeps one node for this channel
+        for (int n = 0; n < geo.ntf; ++n)
+          if (w[3 * (size_t)n + 1] != 0.0 || w[3 * (size_t)n + 2] != 0.0)
+            return fail(SG_EINVAL, "internal: second finest channel must be a plain time sum");
+      const int nr = level_nodes(geo, r);
+      const long long sz = (long long)nr * nr;
+      for (int n = 0; n < geo.ntf; ++n) {
+        TapEntry &t = taps[(size_t)n * nci + li];
+        for (int o = 0; o < 3; ++o) t.w[o] = w[3 * (size_t)n + o];
+        const int n0 = n / geo.chunk * geo.chunk;
+        if (n > n0 && q0[n] > q0[n - 1]) t.base = C.part_off + (long long)(q0[n - 1] - q0[n0]) * sz;
+      }
+    }
+    if ((st = upload(p, taps, &P.d_taps)) != SG_OK) return st;
+  }
   if ((st = upload(p, P.h_ch, &P.d_ch)) != SG_OK) return st;
   P.n_red = (int)red.size();
   P.tot_red = tred;
@@ -349,6 +382,7 @@ sg_status run_restrict(sg_problem *p, const Pass &P, const double *X, int stenci
       break;
     }
   ra.part = p->part;
+  ra.taps = P.d_taps;
   ra.coarse = g.A0 > 1 ? p->cpart : nullptr;
   if (ev_begin >= 0) MARK(p, ev_begin, s);
   HIPCHK(launch_restrict(ra, s));
@@ -612,6 +646,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   KernelTables kt{};
   std::map<int, std::pair<const int *, const double *>> p1tab, sptab;
   std::map<int, std::vector<int>> p1q0, spq0;
+  std::map<int, std::vector<double>> p1w, spw;
   std::vector<TimeLevel> tl_host(J + 1);
   for (int b = 1; b <= J; ++b) {
     tl_host[b] = time_level(b, T);
@@ -634,6 +669,8 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
     sptab[b] = {q2, w2};
     p1q0[b] = t1.q0;
     spq0[b] = t2.q0;
+    p1w[b] = t1.w;
+    spw[b] = t2.w;
   }
   Taps ts = sum_taps(J);
   int *qsum;
@@ -733,7 +770,22 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
     return bail(fail(SG_ENOMEM, "hipMalloc of fine fields failed"));
 
   // ---- passes ---------------------------------------------------------------
-  const Geometry geo = make_geometry(d, J, ntf, 1024);
+  // workgroups the time chunks aim at (tiles x chunks); SG_CHUNK_WG overrides
+  int chunk_wg = 1024;
+  if (const char *e = getenv("SG_CHUNK_WG")) chunk_wg = std::max(1, atoi(e));
+  const Geometry geo = make_geometry(d, J, ntf, chunk_wg);
+  // 2-D restrictions stream 16 x 16 tiles, one per wave (four per workgroup),
+  // unless their coarse pyramid (from level J-4) would not fit its LDS buffer.
+  // Their grids are sized to one full round of resident workgroups: 4 per CU
+  // for the load (one finest channel), 3 per CU for the adjoint restriction
+  // (which also carries the time sum of the cotangent).
+  int ncu = 256;
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device);
+  if (ncu <= 0) ncu = 256;
+  const long long n16 = J > 4 ? (1LL << (J - 4)) - 1 : 0;
+  const bool w16 = d == 2 && n16 * n16 <= kCoarseMax;
+  const Geometry geor = w16 ? make_geometry(d, J, ntf, 4 * 4 * ncu, 16) : geo;
+  const Geometry geoa = w16 ? make_geometry(d, J, ntf, 4 * 3 * ncu, 16) : geo;
   const Geometry geof = make_geometry(d, J, 2, 1);
   long long part_need = 0;
   auto chan_comp = [&](int a, int k, bool spline, double *buf, bool signed_, int only) {
@@ -748,11 +800,12 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
     cs.q0 = tab.first;
     cs.w = tab.second;
     cs.hq0 = spline ? &spq0[C.b] : &p1q0[C.b];
+    cs.hw = spline ? &spw[C.b] : &p1w[C.b];
     cs.data = buf + C.off;
     cs.scale = signed_ ? (double)C.sign : 1.0;
     return cs;
   };
-  if ((st = build_pass(p, p->load, geo,
+  if ((st = build_pass(p, p->load, geor,
                        [&](int a, int k) { return chan_comp(a, k, false, p->bufZ, false, -1); },
                        &part_need)))
     return bail(st);
@@ -761,7 +814,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
                        &part_need)))
     return bail(st);
   std::vector<int> sum_q0(ts.q0);
-  if ((st = build_pass(p, p->adjr, geo,
+  if ((st = build_pass(p, p->adjr, geoa,
                        [&](int a, int k) {
                          if (a == J && k == 1) {
                            ChanSpec cs;
@@ -770,6 +823,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
                            cs.q0 = qsum;
                            cs.w = wsum;
                            cs.hq0 = &sum_q0;
+                           cs.hw = &ts.w;
                            cs.data = p->gsum;
                            return cs;
                          }
@@ -789,6 +843,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
       cs.q0 = dfq0;
       cs.w = k == 0 ? dfw0 : dfw1;
       cs.hq0 = &fq0;
+      cs.hw = k == 0 ? &fw0 : &fw1;
       cs.data = k == 0 ? v0[a] : v1[a];
       return cs;
     };
@@ -799,7 +854,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   p->plain_load.resize(ncomp);
   p->plain_prol.resize(ncomp);
   for (int ci = 0; ci < ncomp; ++ci) {
-    if ((st = build_pass(p, p->plain_load[ci], geo,
+    if ((st = build_pass(p, p->plain_load[ci], geor,
                          [&](int a, int k) { return chan_comp(a, k, false, p->bufZ, false, ci); },
                          &part_need)))
       return bail(st);
@@ -811,15 +866,21 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   if (!(p->part = p->dalloc<double>(part_need)))
     return bail(fail(SG_ENOMEM, "hipMalloc of partial blocks failed"));
   {
-    const int ntileD = d == 2 ? geo.ntile * geo.ntile : geo.ntile;
-    const int nR = level_nodes(geo, geo.R);
-    const long long szR = d == 2 ? (long long)nR * nR : nR;
-    const long long na0 = (1 << geo.A0) - 1, nsp0 = d == 2 ? na0 * na0 : na0;
-    const long long need = std::max((long long)ntileD * ntf * szR, 1LL);
-    long long ncl = 0;  // coarse levels below A0, per slab
-    for (int a = 1; a < geo.A0; ++a) {
-      const long long n = (1 << a) - 1;
-      ncl += d == 2 ? n * n : n;
+    // coarse arrays of the restriction (geor) and prolongation (geo) passes
+    long long need = 1, nsp0 = 0, ncl = 0;
+    for (const Geometry *gg : {&geo, &geor, &geoa}) {
+      const int ntileD = d == 2 ? gg->ntile * gg->ntile : gg->ntile;
+      const int nR = level_nodes(*gg, gg->R);
+      const long long szR = d == 2 ? (long long)nR * nR : nR;
+      const long long na0 = (1 << gg->A0) - 1;
+      need = std::max(need, (long long)ntileD * ntf * szR);
+      nsp0 = std::max(nsp0, d == 2 ? na0 * na0 : na0);
+      long long c = 0;  // coarse levels below A0, per slab
+      for (int a = 1; a < gg->A0; ++a) {
+        const long long n = (1 << a) - 1;
+        c += d == 2 ? n * n : n;
+      }
+      ncl = std::max(ncl, c);
     }
     if (nsp0 > kCoarseMax)
       return bail(fail(SG_ENOTSUP, "level too fine for the coarse-level pyramid"));

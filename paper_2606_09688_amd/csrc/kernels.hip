@@ -389,6 +389,257 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_restrict(const RestrictArgs A) {
   }
 }
 
+// Read-only tables (tap offsets and weights) through the scalar cache: a load
+// from the constant address space with a wave-uniform address becomes a
+// scalar load into SGPRs.  The tables are never written by these kernels.
+typedef const __attribute__((address_space(4))) int cint_t;
+typedef const __attribute__((address_space(4))) TapEntry ctap_t;
+__device__ __forceinline__ int ld_const(const int *p, int i) { return ((cint_t *)p)[i]; }
+__device__ __forceinline__ TapEntry ld_const(const TapEntry *p, long long i) {
+  ctap_t *q = (ctap_t *)p + i;
+  TapEntry t;
+  t.w[0] = q->w[0];
+  t.w[1] = q->w[1];
+  t.w[2] = q->w[2];
+  t.base = q->base;
+  return t;
+}
+
+// Order the LDS accesses of one wave around this point (the lanes of a wave
+// see each other's LDS stores in program order; this stops the compiler from
+// moving accesses across it).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 2-D restriction with one 16 x 16 tile per wave.  Every wave streams the
+// slabs of its own tile through its own LDS region, so the slab loop has no
+// workgroup barrier; the four waves of a workgroup take a 2 x 2 block of
+// tiles, which share halo rows in the caches.  Lane l owns the 2 x 2 block of
+// fine nodes at (2 (l % 8), 2 (l / 8)) and the upper-level nodes u = l and
+// u = l + 64 of the tile's levels 1..4.  Same outputs and partial-block
+// layout as k_restrict<2, 16, ...>.
+#ifndef SG_WPEW
+#define SG_WPEW 4
+#endif
+template <int STENCIL, int NC0>
+__global__ void __launch_bounds__(256, NC0 == 2 ? 3 : SG_WPEW) k_restrict_w(const RestrictArgs A) {
+  constexpr int TS = 16, LTS = 4, NIN = TS + 2, INSZ = NIN * NIN;
+  constexpr int PF = (INSZ + 63) / 64;  // staged inputs per lane
+  using SH = Shape<2, TS, 0>;
+  using PD = Pad<2, TS, 0>;
+  constexpr int PT = PD::total;
+  static_assert(SH::upper <= 128, "two owned upper nodes per lane");
+  static_assert(INSZ % 2 == 0, "16-byte aligned rows of the staged input");
+  __shared__ __align__(16) double s_in_w[4][INSZ];
+  __shared__ double s_lv_w[4][PT];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double *s_in = s_in_w[wave];
+  double *s_lv = s_lv_w[wave];
+
+  const Geometry g = A.g;
+  const int nt = g.ntile, ng = (nt + 1) >> 1;
+  int grp, chunk;
+  stream_block(ng * ng, g.nchunk, grp, chunk);
+  const int tx = 2 * (grp % ng) + (wave & 1), ty = 2 * (grp / ng) + (wave >> 1);
+  if (tx >= nt || ty >= nt) return;  // no workgroup barrier below
+  const int tile = ty * nt + tx, ntileD = nt * nt;
+  const int n0 = chunk * g.chunk, n1 = min(n0 + g.chunk, g.ntf);
+  const long long nsp = (long long)g.nxf * g.nxf;
+  const int R = g.R;
+  const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
+  const long long blk = (long long)chunk * ntileD + tile;
+
+  for (int i = lane; i < PT; i += 64) s_lv[i] = 0.0;
+
+  // fine nodes (fx, fy) = (2 lx + c, 2 ly + b) of this lane
+  const int lx = lane & 7, ly = lane >> 3;
+  bool fin[2][2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      fin[b][c] = interior(TS * tx + 2 * lx + c, g.nxf) && interior(TS * ty + 2 * ly + b, g.nxf);
+  Owned<2, TS, 0> own[2];
+  own[0].set(lane);
+  own[1].set(lane + 64);
+
+  // staged input e of this lane: slab-relative offset, -1 outside the interior
+  int pos[PF];
+#pragma unroll
+  for (int e = 0; e < PF; ++e) {
+    const int idx = lane + 64 * e;
+    const int ix = idx % NIN, iy = idx / NIN;
+    const int px = TS * tx - 1 + ix, py = TS * ty - 1 + iy;
+    pos[e] = (idx < INSZ && interior(px, g.nxf) && interior(py, g.nxf))
+                 ? (py - 1) * g.nxf + (px - 1) : -1;
+  }
+  double pin[PF];
+  // unconditional loads from valid addresses; unwanted values are replaced
+  // by zeros when staged (a load in a divergent branch would serialise them)
+  auto fetch = [&](int n) {
+#pragma unroll
+    for (int e = 0; e < PF; ++e) pin[e] = A.X[pos[e] >= 0 ? (long long)n * nsp + pos[e] : 0];
+  };
+
+  // fine-level accumulators; a second finest channel (the adjoint's time sum
+  // of the cotangent) has weights (w, 0, 0) and keeps one node
+  double racc0[2][2][3];
+  double rsum[2][2];
+  double racc[2][2][3];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      racc0[b][c][0] = racc0[b][c][1] = racc0[b][c][2] = 0.0;
+      rsum[b][c] = 0.0;
+    }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) racc[i][k][0] = racc[i][k][1] = racc[i][k][2] = 0.0;
+
+  constexpr int NCI = 2 * (LTS + 1);  // in-tile channels li = 2 r + k
+  // partial-block entry of row `base` (channel offset + chunk-relative row)
+  auto part_at = [&](const Channel &C, long long base, int r, int j) -> long long {
+    return base + blk * C.qb * (long long)SH::size(r) + j;
+  };
+
+  fetch(n0);
+  for (int n = n0; n < n1; ++n) {
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < PF; ++e) {
+      const int idx = lane + 64 * e;
+      if (idx < INSZ) s_in[idx] = pos[e] >= 0 ? pin[e] : 0.0;
+    }
+    if (n + 1 < n1) fetch(n + 1);
+    wave_sync();
+    // (1) fine level: 4 x 4 input window of the lane's 2 x 2 block, one row
+    // at a time (rows i = 0..3 are input rows 2 ly + i)
+    double m[2][2];
+    if (STENCIL) {
+      // row sums h_c(i) = v(i, c) + v(i, c + 2) + 4 v(i, c + 1), folded into
+      // the two output rows as they arrive
+      double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double2 *p = reinterpret_cast<const double2 *>(s_in + (2 * ly + i) * NIN + 2 * lx);
+        const double2 a0 = p[0], a1 = p[1];
+        const double h0 = a0.x + a1.x + 4.0 * a0.y, h1 = a0.y + a1.y + 4.0 * a1.x;
+        // output row b takes input rows b, b+1, b+2 with weights 1, 4, 1
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int d = i - b;
+          if (d < 0 || d > 2) continue;
+          const double wt = d == 1 ? 4.0 : 1.0;
+          acc[b][0] += wt * h0;
+          acc[b][1] += wt * h1;
+        }
+      }
+      const double sxy = A.sx * A.sy;
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) m[b][c] = fin[b][c] ? sxy * acc[b][c] : 0.0;
+    } else {
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const double2 *p = reinterpret_cast<const double2 *>(s_in + (2 * ly + b + 1) * NIN + 2 * lx);
+        const double2 a0 = p[0], a1 = p[1];
+        m[b][0] = a0.y;
+        m[b][1] = a1.x;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) s_lv[(2 * ly + b + 1) * PD::pn(0) + 2 * lx + c + 1] = m[b][c];
+    const TapEntry *tn = A.taps + (long long)n * NCI;
+    if (A.ch[(g.J - 1) * 2].active) {
+      const TapEntry t = ld_const(tn, 0);
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          racc0[b][c][0] += t.w[0] * m[b][c];
+          racc0[b][c][1] += t.w[1] * m[b][c];
+          racc0[b][c][2] += t.w[2] * m[b][c];
+        }
+    }
+    if (NC0 == 2) {
+      const double w = ld_const(tn, 1).w[0];
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) rsum[b][c] += w * m[b][c];
+    }
+    // (2) levels r = 1..R: owners restrict from level r-1 and accumulate
+#pragma unroll
+    for (int r = 1; r <= LTS; ++r) {
+      if (r > R) break;
+      wave_sync();
+      const TapEntry t0 = ld_const(tn, 2 * r), t1 = ld_const(tn, 2 * r + 1);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if (own[i].r != r) continue;
+        const double val = full_weight<2>(s_lv + PD::poff(r - 1), PD::pn(r - 1), own[i].jx, own[i].jy);
+        s_lv[PD::poff(r) + (own[i].jy + 1) * PD::pn(r) + own[i].jx + 1] = val;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
+          if (!C.active) continue;
+          const TapEntry &t = k == 0 ? t0 : t1;
+          if (t.base >= 0) {
+            A.part[part_at(C, t.base, r, own[i].j)] = racc[i][k][0];
+            racc[i][k][0] = racc[i][k][1];
+            racc[i][k][1] = racc[i][k][2];
+            racc[i][k][2] = 0.0;
+          }
+          racc[i][k][0] += t.w[0] * val;
+          racc[i][k][1] += t.w[1] * val;
+          racc[i][k][2] += t.w[2] * val;
+        }
+        if (r == R && use_coarse)
+          A.coarse[((long long)tile * g.ntf + n) * SH::size(r) + own[i].j] = val;
+      }
+    }
+  }
+  // final flush of the open time nodes (level-J channels: q0 = 0 throughout)
+#pragma unroll
+  for (int k = 0; k < NC0; ++k) {
+    const Channel &C = A.ch[(g.J - 1) * 2 + k];
+    if (!C.active) continue;
+#pragma unroll
+    for (int o = 0; o < 3; ++o)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          A.part[part_at(C, C.part_off + (long long)o * SH::size(0), 0,
+                         (2 * ly + b) * TS + 2 * lx + c)] =
+              k == 0 ? racc0[b][c][o] : (o == 0 ? rsum[b][c] : 0.0);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int r = own[i].r;
+    if (r == 0 || r > R) continue;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
+      if (!C.active) continue;
+      const int qlo = ld_const(C.q0, n0), ql = ld_const(C.q0, n1 - 1);
+#pragma unroll
+      for (int o = 0; o < 3; ++o)
+        if (ql + o < C.nq)
+          A.part[part_at(C, C.part_off + (long long)(ql + o - qlo) * SH::size(r), r, own[i].j)] =
+              racc[i][k][o];
+    }
+  }
+}
+
 // Tile range of the tiles whose restriction block holds node P of level
 // offset r (blocks [t s_r, t s_r + s_r], s_r = TS >> r; level 0 not shared).
 __device__ __forceinline__ void tile_range(int TS, int r, int P, int ntile, int &t0,
@@ -1781,7 +2032,17 @@ hipError_t launch_restrict(const RestrictArgs &a, hipStream_t s) {
   const bool two = a.ch[(a.g.J - 1) * 2 + 1].active != 0;
 #define SG_RESTRICT(D, TS, TB, ST, NC)                                                     \
   hipLaunchKernelGGL((k_restrict<D, TS, TB, kNT, ST, NC>), grid, dim3(kNT), 0, s, a)
-  if (a.g.d == 2) {
+#define SG_RESTRICT_W(ST, NC) \
+  hipLaunchKernelGGL((k_restrict_w<ST, NC>), gridw, dim3(256), 0, s, a)
+  if (a.g.d == 2 && a.g.TS == 16) {
+    const int ng = (a.g.ntile + 1) / 2;
+    dim3 gridw(ng * ng, a.g.nchunk);
+    if (a.stencil) {
+      if (two) SG_RESTRICT_W(1, 2); else SG_RESTRICT_W(1, 1);
+    } else {
+      if (two) SG_RESTRICT_W(0, 2); else SG_RESTRICT_W(0, 1);
+    }
+  } else if (a.g.d == 2) {
     if (a.stencil) {
       if (two) SG_RESTRICT(2, kTS2, kTB2, 1, 2); else SG_RESTRICT(2, kTS2, kTB2, 1, 1);
     } else {
@@ -1795,6 +2056,7 @@ hipError_t launch_restrict(const RestrictArgs &a, hipStream_t s) {
     }
   }
 #undef SG_RESTRICT
+#undef SG_RESTRICT_W
   return hipGetLastError();
 }
 
@@ -1802,7 +2064,10 @@ hipError_t launch_reduce(const Geometry &g, const Channel *ch, const double *par
                          const WorkItem *items, int nitems, long long total,
                          hipStream_t s) {
   if (total == 0) return hipSuccess;
-  if (g.d == 2)
+  if (g.d == 2 && g.TS == 16)
+    hipLaunchKernelGGL((k_reduce<2, 16>), dim3(blocks_for(total, 256)), dim3(256), 0, s,
+                       g, ch, part, items, nitems, total);
+  else if (g.d == 2)
     hipLaunchKernelGGL((k_reduce<2, kTS2>), dim3(blocks_for(total, 256)), dim3(256), 0, s,
                        g, ch, part, items, nitems, total);
   else

@@ -11,6 +11,15 @@ namespace sg {
 // kernels read it through scalar loads that cannot alias their stores.
 constexpr int kChanMax = 2 * kMaxLevels;
 
+// Per-slab tap of one in-tile channel (2-D restriction with 16 x 16 tiles):
+// the weights of the three open time nodes, and the partial-block offset
+// (channel offset + chunk-relative row) of the node that closes at this slab,
+// -1 if none closes.  One table per pass, [ntf][2 (lts + 1)].
+struct TapEntry {
+  double w[3];
+  long long base;
+};
+
 // ---- fine-grid streaming restriction ------------------------------------
 // Z_c[q][K] = sum_n sum_m w_c(n,q) phi^a_K(x_m) (S X_n)[m] for every active
 // channel c, S = identity or the fine mass matrix (stencil = 1).
@@ -21,6 +30,7 @@ struct RestrictArgs {
   double sx, sy;         // h_x/6, h_y/6 of the finest mesh
   double *part;          // partial blocks of the in-tile levels
   double *coarse;        // per-slab partials at level A0 (if A0 > 1)
+  const TapEntry *taps;  // per-slab taps of the in-tile channels (16 x 16 tiles only)
   const int *safe_q0;    // tap tables of some active channel: a valid address
   const double *safe_w;  // for loads whose result is discarded
   Channel ch[kChanMax];  // channel (a-1)*2+k, entries >= 2J unused
