@@ -143,8 +143,8 @@ def main():
     # to read them (the sync is inside the timed region).
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(15)]
     sv.set_events(ev)
-    kern_ev = {"k_restrict (load of f)": (1, 2), "k_prolong (combination into U)": (5, 6),
-               "k_restrict (cotangent g)": (8, 9), "k_prolong (df, with mass stencil)": (12, 13)}
+    kern_ev = {"restriction of f": (1, 2), "prolongation into U": (5, 6),
+               "restriction of g": (8, 9), "prolongation into df (mass stencil)": (12, 13)}
     kern_t = {k: 0.0 for k in kern_ev}
     graph_events = True
     try:
@@ -221,10 +221,10 @@ def main():
     # dominant fine-grid kernel (timed inside the graph replays when the
     # runtime records captured events, else in the eager runs): each streams
     # 8 bytes per fine-grid value
-    eager_t = {"k_restrict (load of f)": stage["load_restrict"],
-               "k_prolong (combination into U)": stage["combine"],
-               "k_restrict (cotangent g)": stage["adj_restrict"],
-               "k_prolong (df, with mass stencil)": stage["df_prolong"]}
+    eager_t = {"restriction of f": stage["load_restrict"],
+               "prolongation into U": stage["combine"],
+               "restriction of g": stage["adj_restrict"],
+               "prolongation into df (mass stencil)": stage["df_prolong"]}
     if graph_events and not all(0.5 < kern_t[k] / eager_t[k] < 2.0 for k in kern_t):
         graph_events = False  # event nodes did not bracket the kernels
     if not graph_events:
