@@ -1189,6 +1189,183 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
   }
 }
 
+// 2-D prolongation (no stencil) with one 16 x 16 tile per wave: the
+// counterpart of k_restrict_w, four tiles per workgroup and no workgroup
+// barrier in the slab loop.  Per slab: (A) the owners of the tile's
+// upper-level nodes evaluate their channels in time (register windows of
+// coefficients; the top level adds the levels below the tile from
+// A.coarse), (B) top-down interpolation through the levels, (C) the fine
+// nodes add their level-J channel and the interpolated level-1 values and
+// are written.  Fine nodes are taken row-major, p = lane + 64 e, so that
+// every store instruction writes whole 128-byte rows.  Taps (weights times
+// channel sign, and where the window moves on) come from a per-pass host
+// table.  The prolongation through the mass stencil keeps k_prolong.
+#ifndef SG_WPEP
+#define SG_WPEP 4
+#endif
+__global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A) {
+  constexpr int TS = 16, LTS = 4;
+  using SH = Shape<2, TS, 0>;
+  constexpr int L0 = TS * TS;
+  constexpr int EF = L0 / 64;             // fine nodes per lane
+  constexpr int UP = SH::upper;
+  constexpr int NS = (UP + 63) / 64;      // owned upper-node slots per lane
+  constexpr int NCI = 2 * (LTS + 1);
+  static_assert(NS == 2 && L0 % 64 == 0, "tile shape");
+  __shared__ double s_v_w[4][UP];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double *s_v = s_v_w[wave];
+
+  const Geometry g = A.g;
+  const int nt = g.ntile, ng = (nt + 1) >> 1;
+  int grp, chunk;
+  stream_block(ng * ng, g.nchunk, grp, chunk);
+  const int tx = 2 * (grp % ng) + (wave & 1), ty = 2 * (grp / ng) + (wave >> 1);
+  if (tx >= nt || ty >= nt) return;  // no workgroup barrier below
+  const int n0 = chunk * g.chunk, n1 = min(n0 + g.chunk, g.ntf);
+  const long long nsp = (long long)g.nxf * g.nxf;
+  const int R = g.R;
+  const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
+  const int n0a = (1 << g.A0) - 1;
+  const long long nsp0 = (long long)n0a * n0a;
+
+  // ---- owned upper nodes: coefficient offsets and windows ----
+  Owned<2, TS, 0> own[NS];
+  int coff[NS], cof0[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    own[i].set(lane + 64 * i);
+    coff[i] = -1;
+    cof0[i] = -1;
+    const int r = own[i].r;
+    if (r >= 1 && r <= R) {
+      const int na = (1 << (g.J - r)) - 1;
+      const int Px = tile_lo(TS, tx, r, 0) + own[i].jx;
+      const int Py = tile_lo(TS, ty, r, 0) + own[i].jy;
+      if (interior(Px, na) && interior(Py, na)) coff[i] = (Px - 1) + (Py - 1) * na;
+      if (r == R && use_coarse && interior(Px, n0a) && interior(Py, n0a))
+        cof0[i] = (Px - 1) + (Py - 1) * n0a;
+    }
+  }
+  auto coef = [&](const Channel &C, int q, int off) -> double {
+    if (off < 0 || q >= C.nq) return 0.0;
+    const int na = (1 << C.a) - 1;
+    return C.data[(long long)q * na * na + off];
+  };
+  // coefficient windows q0 .. q0+2 of the owned nodes
+  double cw[NS][2][3];
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      cw[i][k][0] = cw[i][k][1] = cw[i][k][2] = 0.0;
+      const int r = own[i].r;
+      if (r < 1 || r > R) continue;
+      const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
+      if (!C.active) continue;
+      const int q = ld_const(C.q0, n0);
+#pragma unroll
+      for (int o = 0; o < 3; ++o) cw[i][k][o] = coef(C, q + o, coff[i]);
+    }
+
+  // ---- fine nodes: level-J channel (q0 = 0 throughout) and base ----
+  const int lo0x = TS * tx, lo0y = TS * ty;
+  const Channel &CJ = A.ch[(g.J - 1) * 2];
+  double rc[EF][3], basev[EF];
+#pragma unroll
+  for (int e = 0; e < EF; ++e) {
+    const int p = lane + 64 * e;
+    const int Px = lo0x + p % TS, Py = lo0y + p / TS;
+    const int off = interior(Px, g.nxf) && interior(Py, g.nxf) ? (Px - 1) + (Py - 1) * g.nxf : -1;
+#pragma unroll
+    for (int o = 0; o < 3; ++o) rc[e][o] = CJ.active ? coef(CJ, o, off) : 0.0;
+    basev[e] = (A.base != nullptr && off >= 0) ? A.base[off] : 0.0;
+  }
+  // coarse values of the next slab (unconditional loads from valid addresses)
+  const double *cbase = use_coarse ? A.coarse : A.safe_w;
+  double pco[NS];
+  auto fetch_co = [&](int n) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) pco[i] = cbase[cof0[i] >= 0 ? (long long)n * nsp0 + cof0[i] : 0];
+  };
+  const int pn1 = SH::nodes(1);
+  const int plox = tile_lo(TS, tx, 1, 0), ploy = tile_lo(TS, ty, 1, 0);
+
+  fetch_co(n0);
+  for (int n = n0; n < n1; ++n) {
+    const TapEntry *tn = A.taps + (long long)n * NCI;
+    double co[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) co[i] = cof0[i] >= 0 ? pco[i] : 0.0;
+    if (n + 1 < n1) fetch_co(n + 1);
+    wave_sync();
+    // (A) owners evaluate their node in time
+#pragma unroll
+    for (int r = 1; r <= LTS; ++r) {
+      if (r > R) break;
+      const TapEntry t0 = ld_const(tn, 2 * r), t1 = ld_const(tn, 2 * r + 1);
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        if (own[i].r != r) continue;
+        double v = r == R ? co[i] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
+          if (!C.active) continue;
+          const TapEntry &t = k == 0 ? t0 : t1;
+          if (t.base >= 0) {  // the window moves on to q0 = t.base
+            cw[i][k][0] = cw[i][k][1];
+            cw[i][k][1] = cw[i][k][2];
+            cw[i][k][2] = coef(C, (int)t.base + 2, coff[i]);
+          }
+          v += t.w[0] * cw[i][k][0] + t.w[1] * cw[i][k][1] + t.w[2] * cw[i][k][2];
+        }
+        s_v[SH::offset(r) - SH::size(0) + own[i].j] = v;
+      }
+    }
+    // (B) top-down interpolation r = R-1 .. 1
+#pragma unroll
+    for (int r = LTS - 1; r >= 1; --r) {
+      if (r >= R) continue;
+      wave_sync();
+      const int pn = SH::nodes(r + 1);
+      const int lox = tile_lo(TS, tx, r, 0), loy = tile_lo(TS, ty, r, 0);
+      const int qx = tile_lo(TS, tx, r + 1, 0), qy = tile_lo(TS, ty, r + 1, 0);
+      const double *par = s_v + SH::offset(r + 1) - SH::size(0);
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        if (own[i].r != r) continue;
+        const int Px = lox + own[i].jx, Py = loy + own[i].jy;
+        const int xl = (Px >> 1) - qx, xh = ((Px + 1) >> 1) - qx;
+        const int yl = (Py >> 1) - qy, yh = ((Py + 1) >> 1) - qy;
+        s_v[SH::offset(r) - SH::size(0) + own[i].j] +=
+            0.25 * (par[yl * pn + xl] + par[yl * pn + xh] + par[yh * pn + xl] + par[yh * pn + xh]);
+      }
+    }
+    wave_sync();
+    // (C) fine nodes
+    const TapEntry tj = ld_const(tn, 0);
+#pragma unroll
+    for (int e = 0; e < EF; ++e) {
+      const int p = lane + 64 * e;
+      const int Px = lo0x + p % TS, Py = lo0y + p / TS;
+      double v = tj.w[0] * rc[e][0] + tj.w[1] * rc[e][1] + tj.w[2] * rc[e][2];
+      if (R >= 1) {
+        const int xl = (Px >> 1) - plox, xh = ((Px + 1) >> 1) - plox;
+        const int yl = (Py >> 1) - ploy, yh = ((Py + 1) >> 1) - ploy;
+        v += 0.25 * (s_v[yl * pn1 + xl] + s_v[yl * pn1 + xh] + s_v[yh * pn1 + xl] +
+                     s_v[yh * pn1 + xh]);
+      }
+      if (interior(Px, g.nxf) && interior(Py, g.nxf)) {
+        const long long off = (long long)n * nsp + (long long)(Py - 1) * g.nxf + (Px - 1);
+        double o = v + basev[e];
+        if (A.accumulate) o += A.out[off];
+        A.out[off] = o;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------- small kernels -----
 
 // Fine-grid mass and stiffness stencils (per-element c^2 on the finest mesh).
@@ -2127,7 +2304,13 @@ hipError_t launch_prolong(const ProlongArgs &a, hipStream_t s) {
   const bool two = a.ch[(a.g.J - 1) * 2 + 1].active != 0;
 #define SG_PROLONG(D, TS, TB, MO, NC)                                                      \
   hipLaunchKernelGGL((k_prolong<D, TS, TB, kNT, MO, NC>), grid, dim3(kNT), 0, s, a)
-  if (a.g.d == 2) {
+  if (a.g.d == 2 && a.g.TS == 16) {
+    if (two || a.taps == nullptr) return hipErrorInvalidValue;  // one finest channel only
+    if (a.stencil) return hipErrorInvalidValue;  // mass stencil: 32 x 32 tiles only
+    const int ng = (a.g.ntile + 1) / 2;
+    dim3 gridw(ng * ng, a.g.nchunk);
+    hipLaunchKernelGGL(k_prolong_w, gridw, dim3(256), 0, s, a);
+  } else if (a.g.d == 2) {
     if (a.stencil) {
       if (two) SG_PROLONG(2, kTS2, kTB2P, 1, 2); else SG_PROLONG(2, kTS2, kTB2P, 1, 1);
     } else {

@@ -11,10 +11,14 @@ namespace sg {
 // kernels read it through scalar loads that cannot alias their stores.
 constexpr int kChanMax = 2 * kMaxLevels;
 
-// Per-slab tap of one in-tile channel (2-D restriction with 16 x 16 tiles):
-// the weights of the three open time nodes, and the partial-block offset
-// (channel offset + chunk-relative row) of the node that closes at this slab,
-// -1 if none closes.  One table per pass, [ntf][2 (lts + 1)].
+// Per-slab tap of one in-tile channel (2-D passes with 16 x 16 tiles): the
+// weights of the three open time nodes and
+//   restriction:   the partial-block offset (channel offset + chunk-relative
+//                  row) of the node that closes at this slab, -1 if none;
+//   prolongation:  the new first time index q0 if the coefficient window
+//                  moves on by one at this slab, else -1 (the weights include
+//                  the channel sign).
+// One table per pass, [ntf][2 (lts + 1)].
 struct TapEntry {
   double w[3];
   long long base;
@@ -48,6 +52,7 @@ struct ProlongArgs {
   double sx, sy;
   const int *safe_q0;    // tap tables of some active channel (valid addresses)
   const double *safe_w;
+  const TapEntry *taps;  // per-slab taps of the in-tile channels (16 x 16 tiles only)
   Channel ch[kChanMax];
 };
 
