@@ -1497,14 +1497,21 @@ __global__ void k_adjoint_fields(const LevelDesc *__restrict__ ld, int nlev,
 
 // Batched C = A B (row major) on the FP64 matrix cores.  64x64 block tiles,
 // 4 waves, each wave a 32x32 sub-tile of 2x2 v_mfma_f64_16x16x4 blocks; K in
-// steps of 16 through LDS, the next K tile prefetched in registers.
+// steps of SG_GEMM_BK through LDS, the next K tile prefetched in registers.
 // Operand layout of the 16x16x4 instruction (lane l of the wave):
 //   a = A[l % 16][l / 16],  b = B[l / 16][l % 16],
 //   result element r of the lane = D[l / 16 + 4 r][l % 16].
 typedef double sg_double4 __attribute__((ext_vector_type(4)));
 
+#ifndef SG_GEMM_BK
+#define SG_GEMM_BK 64
+#endif
 __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ descs, int ndesc) {
-  constexpr int BM = 64, BN = 64, BK = 16;
+  // K steps of 64: each step is 64 MFMAs per wave (about 1.7 us of matrix
+  // work), enough to cover the global-load latency of the next step's
+  // operands, which are prefetched into registers meanwhile
+  constexpr int BM = 64, BN = 64, BK = SG_GEMM_BK;
+  constexpr int EA = BM * BK / 256, EB = BK * BN / 256;  // staged values per thread
   __shared__ double As[BM][BK + 1];
   __shared__ double Bs[BK][BN + 2];
   int di = 0;
@@ -1522,19 +1529,23 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ descs
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int M = Dd.M, N = Dd.N, K = Dd.K;
-  // global -> register staging (4 + 4 values per thread per K tile); loads
-  // go to clamped valid addresses and are selected, not branched
-  double ra[4], rb[4];
+  // global -> register staging; loads go to clamped valid addresses and are
+  // selected, not branched
+  double ra[EA], rb[EB];
   auto load_tile = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < EA; ++e) {
       const int i = tid + e * 256;
-      const int m = i >> 4, k = i & 15;          // A: 64 x 16
+      const int m = i / BK, k = i % BK;           // A: BM x BK
       const int gm = row0 + m, gk = k0 + k;
       const bool oka = gm < M && gk < K;
       const double va = Ap[oka ? (long long)gm * Dd.lda + gk : 0];
       ra[e] = oka ? va : 0.0;
-      const int kb = i >> 6, n = i & 63;          // B: 16 x 64
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int i = tid + e * 256;
+      const int kb = i / BN, n = i % BN;          // B: BK x BN
       const int gkb = k0 + kb, gn = col0 + n;
       const bool okb = gkb < K && gn < N;
       const double vb = Bp[okb ? (long long)gkb * Dd.ldb + gn : 0];
@@ -1549,15 +1560,19 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ descs
   load_tile(0);
   for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < EA; ++e) {
       const int i = tid + e * 256;
-      As[i >> 4][i & 15] = ra[e];
-      Bs[i >> 6][i & 63] = rb[e];
+      As[i / BK][i % BK] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int i = tid + e * 256;
+      Bs[i / BN][i % BN] = rb[e];
     }
     __syncthreads();
     if (k0 + BK < K) load_tile(k0 + BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
+    const int kend = min(BK, K - k0);  // the rest of the tile is zero
+    for (int kk = 0; kk < kend; kk += 4) {
       double a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) a[i] = As[wm + i * 16 + (lane & 15)][kk + (lane >> 4)];
