@@ -775,8 +775,13 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
     return bail(fail(SG_ENOMEM, "hipMalloc of fine fields failed"));
 
   // ---- passes ---------------------------------------------------------------
-  // workgroups the time chunks aim at (tiles x chunks); SG_CHUNK_WG overrides
-  int chunk_wg = 1024;
+  int ncu = 256;
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device);
+  if (ncu <= 0) ncu = 256;
+  // workgroups the time chunks aim at (tiles x chunks); in 2-D this geometry
+  // only serves the prolongation through the mass stencil, whose 32 x 32
+  // workgroups keep 2 resident per CU.  SG_CHUNK_WG overrides.
+  int chunk_wg = d == 2 ? 2 * ncu : 1024;
   if (const char *e = getenv("SG_CHUNK_WG")) chunk_wg = std::max(1, atoi(e));
   const Geometry geo = make_geometry(d, J, ntf, chunk_wg);
   // 2-D restrictions stream 16 x 16 tiles, one per wave (four per workgroup),
@@ -784,9 +789,6 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   // Their grids are sized to one full round of resident workgroups: 4 per CU
   // for the load (one finest channel), 3 per CU for the adjoint restriction
   // (which also carries the time sum of the cotangent).
-  int ncu = 256;
-  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device);
-  if (ncu <= 0) ncu = 256;
   const long long n16 = J > 4 ? (1LL << (J - 4)) - 1 : 0;
   const bool w16 = d == 2 && n16 * n16 <= kCoarseMax;
   const Geometry geor = w16 ? make_geometry(d, J, ntf, 4 * 4 * ncu, 16) : geo;
