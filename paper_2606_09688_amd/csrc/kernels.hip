@@ -808,12 +808,12 @@ __global__ void k_coarse_restrict(const Geometry g, const Channel *__restrict__ 
   const long long tot = coarse_off(D, g.A0), off = coarse_off(D, a) + K;
   const int nlo = lower_bound_q(C.q0, g.ntf, q - 2);
   const int nhi = lower_bound_q(C.q0, g.ntf, q + 1);  // exclusive
+  // q0 is nondecreasing, so every slab in [nlo, nhi) has q - 2 <= q0[n] <= q:
+  // no test in the loop, whose loads can then be in flight together
   double acc = 0.0;
-  for (int n = nlo; n < nhi; ++n) {
-    const int k = q - C.q0[n];
-    if (k < 0 || k > 2) continue;
-    acc += C.w[3 * n + k] * SL[(long long)n * tot + off];
-  }
+#pragma unroll 4
+  for (int n = nlo; n < nhi; ++n)
+    acc += C.w[3 * n + (q - C.q0[n])] * SL[(long long)n * tot + off];
   C.data[loc] = C.scale * acc;
 }
 
