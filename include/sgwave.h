@@ -64,7 +64,11 @@ typedef enum {
  *           resolves the blocks).
  *   T       final time > 0.   L  sparse level, 2 <= L <= 16.
  * On success *out receives a handle bound to the current HIP device; all
- * tables are uploaded and all workspace is allocated here.
+ * tables are uploaded and all workspace is allocated here.  A wave speed
+ * that varies in 2-D is supported up to L = 7 (spatial levels <= 6, whose
+ * dense pencils are diagonalised here with rocSOLVER); beyond that, and for
+ * 1-D variable speed on spatial levels >= 9 with more than 64 time nodes,
+ * SG_ENOTSUP.
  */
 sg_status sg_assemble(int d, const double *len, const int *ncell,
                       const double *c_vals, double T, int L, sg_problem **out);
@@ -200,6 +204,17 @@ sg_status sg_batch_destroy(sg_batch *b);
  */
 sg_status sg_host_pencil(int a, double len, int ncell, const double *c_vals, double *V,
                          double *lam);
+
+/*
+ * Host table (exported for tests; no device work): the dense level-a Q1
+ * pencil in 2-D, K(c) and M of eq. (9) on (0,len[0]) x (0,len[1]) with c
+ * piecewise constant on ncell[0] x ncell[1] uniform blocks (x fastest).
+ * K, M: caller-owned host buffers of n^4 doubles, n = 2^a - 1, row-major
+ * over the interior nodes (x fastest); either may be NULL.  SG_EINVAL unless
+ * 1 <= a <= 6.
+ */
+sg_status sg_host_pencil_2d(int a, const double *len, const int *ncell, const double *c_vals,
+                            double *K, double *M);
 
 #ifdef __cplusplus
 }

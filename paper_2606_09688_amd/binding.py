@@ -42,6 +42,7 @@ SIGNATURES = {
                                     ctypes.c_double, _c_ip, _c_dp]),
     "sg_host_pencil": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, _c_dp,
                                       _c_dp, _c_dp]),
+    "sg_host_pencil_2d": (ctypes.c_int, [ctypes.c_int, _c_dp, _c_ip, _c_dp, _c_dp, _c_dp]),
     "sg_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
                                        ctypes.POINTER(ctypes.c_void_p)]),
     "sg_batch_capture": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_void_p)] * 8
@@ -123,6 +124,22 @@ def host_taps(kind, b, J, T):
     check(lib().sg_host_taps(kind, b, J, float(T), q0.ctypes.data_as(_c_ip),
                              w.ctypes.data_as(_c_dp)), "sg_host_taps")
     return q0, w
+
+
+def host_pencil_2d(a, lengths, ncell, c_vals):
+    """(K, M): dense level-a Q1 pencil in 2-D (n^2 x n^2, x fastest), c
+    piecewise constant on ncell[0] x ncell[1] uniform blocks."""
+    import numpy as np
+    ln = np.ascontiguousarray(lengths, dtype=np.float64)
+    nc = np.ascontiguousarray(ncell, dtype=np.int32)
+    c = np.ascontiguousarray(c_vals, dtype=np.float64)
+    n2 = (2 ** a - 1) ** 2
+    K = np.zeros((n2, n2))
+    M = np.zeros((n2, n2))
+    check(lib().sg_host_pencil_2d(a, ln.ctypes.data_as(_c_dp), nc.ctypes.data_as(_c_ip),
+                                  c.ctypes.data_as(_c_dp), K.ctypes.data_as(_c_dp),
+                                  M.ctypes.data_as(_c_dp)), "sg_host_pencil_2d")
+    return K, M
 
 
 def host_pencil(a, length, c_vals):

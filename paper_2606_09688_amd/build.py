@@ -21,6 +21,12 @@ FLAGS = [
 ]
 
 
+# rocSOLVER: the generalised eigensolver of the dense 2-D variable-speed
+# pencils at assembly (not on the solve path)
+LIBS = ["-L" + os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib"),
+        "-lrocsolver", "-lrocblas"]
+
+
 def hipcc():
     cand = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
     return cand if os.path.exists(cand) else "hipcc"
@@ -30,7 +36,7 @@ def build(verbose=False):
     """Compile every source into libsgwave.so; raises on failure."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + ["-I", CSRC, "-o", tmp] + srcs
+    cmd = [hipcc()] + FLAGS + ["-I", CSRC, "-o", tmp] + srcs + LIBS
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

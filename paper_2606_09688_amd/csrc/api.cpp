@@ -10,6 +10,8 @@
 #include <string>
 #include <vector>
 
+#include <rocsolver/rocsolver.h>
+
 #include "../../include/sgwave.h"
 #include "kernels.hpp"
 #include "tables.hpp"
@@ -21,6 +23,8 @@ namespace {
 // largest spatial level whose variable-speed modes come from a dense
 // eigen-decomposition (2^8 - 1 = 255 nodes)
 constexpr int kEigMaxLevel = 8;
+// 2-D variable speed: spatial levels solved through the dense pencil (n^2 <= 3969)
+constexpr int kEig2MaxLevel = 6;
 
 thread_local std::string g_last_error;
 
@@ -442,14 +446,18 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
   for (int ci : cset) {
     if (p->blockc[ci]) continue;
     const Comp &C = p->comps[ci];
-    const int na = (1 << C.a) - 1;
+    // 2-D variable speed: one dense transform over the flat spatial index,
+    // straight into the solve buffer (no y transforms)
+    const bool flat = p->d == 2 && !p->const_c;
+    const int na = flat ? (int)C.nsp : (1 << C.a) - 1;
     const double *Q = p->tf[C.a], *Qi = p->ti[C.a];
-    const int ny = p->d == 2 ? na : 1;
+    const int ny = p->d == 2 && !flat ? na : 1;
+    double *mid = flat ? p->bufS : p->bufT;
     auto tiles = [](int M, int N) { return ((M + 63) / 64) * ((N + 63) / 64); };
     // forward x: T = B * Q   ([nq*ny x na] x [na x na])
     {
       GemmDesc g{};
-      g.A = x_in + C.off; g.B = Q; g.C = p->bufT + C.off;
+      g.A = x_in + C.off; g.B = Q; g.C = mid + C.off;
       g.M = C.nq * ny; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
       g.batch = 1; g.tm = (g.M + 63) / 64; g.tn = (g.N + 63) / 64; g.tile0 = tx;
       tx += tiles(g.M, g.N);
@@ -458,13 +466,13 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
     // inverse x: U = T * Q^{-1}
     {
       GemmDesc g{};
-      g.A = p->bufT + C.off; g.B = Qi; g.C = x_out + C.off;
+      g.A = mid + C.off; g.B = Qi; g.C = x_out + C.off;
       g.M = C.nq * ny; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
       g.batch = 1; g.tm = (g.M + 63) / 64; g.tn = (g.N + 63) / 64; g.tile0 = tix;
       tix += tiles(g.M, g.N);
       vix.push_back(g);
     }
-    if (p->d == 2) {
+    if (p->d == 2 && !flat) {
       const long long slab = (long long)na * na;
       // forward y: S_i = Q * T_i
       GemmDesc g{};
@@ -520,6 +528,7 @@ sg_status build_solve_list(sg_problem *p, const std::vector<int> &cset, int tran
       sd.refine = C.nq < p->refine_nq ? 0 : (C.nq <= 513 ? 4 : 8);
       sd.transpose = transpose;
       sd.wave = wave;
+      sd.flat = p->d == 2 && !p->const_c ? 1 : 0;
       sd.c2 = p->c2;
       sd.thread0 = th;
       th += wave ? 64LL * C.nsp : (C.nsp + 63) / 64 * 64;
@@ -606,8 +615,8 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   p->N = N;
   p->const_c = std::all_of(p->c.begin(), p->c.end(), [&](double v) { return v == p->c[0]; });
   p->c2 = p->c[0] * p->c[0];
-  if (!p->const_c && d == 2)
-    return bail(fail(SG_ENOTSUP, "variable wave speed in 2-D is not implemented in this build"));
+  if (!p->const_c && d == 2 && J > kEig2MaxLevel)
+    return bail(fail(SG_ENOTSUP, "variable wave speed in 2-D: spatial levels up to 6 (L <= 7)"));
   if (!p->const_c) p->c2 = 1.0;  // the eigenvalues carry c
   if (const char *e = getenv("SG_REFINE_NQ")) p->refine_nq = atoi(e);
   if (const char *e = getenv("SG_WAVE_NQ")) p->wave_nq = atoi(e);
@@ -709,6 +718,43 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
       }
       if ((st = upload(p, dst_matrix(a), &p->tf[a]))) return bail(st);
       p->ti[a] = p->tf[a];  // the DST-I matrix is its own inverse
+    } else if (d == 2) {
+      // 2-D variable speed: M-orthonormal modes of the dense pencil (K(c), M)
+      // from the generalised symmetric eigensolver of rocSOLVER (set-up only),
+      // used as one flat spatial index: mass 1, stiffness lambda
+      std::vector<double> K, M;
+      pencil_2d(a, p->len, p->ncell, p->c.data(), K, M);
+      const int n2 = ((1 << a) - 1) * ((1 << a) - 1);
+      double *dK = nullptr, *dM = nullptr, *dlam = nullptr, *dE = nullptr;
+      int *dinfo = nullptr;
+      if ((st = upload(p, K, &dK)) || (st = upload(p, M, &dM))) return bail(st);
+      if (!(dlam = p->dalloc<double>(n2)) || !(dE = p->dalloc<double>(n2)) ||
+          !(dinfo = p->dalloc<int>(1)))
+        return bail(fail(SG_ENOMEM, "hipMalloc of eigensolver workspace failed"));
+      rocblas_handle h = nullptr;
+      if (rocblas_create_handle(&h) != rocblas_status_success)
+        return bail(fail(SG_EDEVICE, "rocblas_create_handle failed"));
+      const rocblas_status rs = rocsolver_dsygvd(h, rocblas_eform_ax, rocblas_evect_original,
+                                                 rocblas_fill_upper, n2, dK, n2, dM, n2, dlam,
+                                                 dE, dinfo);
+      HIPCHK(hipDeviceSynchronize());
+      rocblas_destroy_handle(h);
+      int info = -1;
+      HIPCHK(hipMemcpy(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost));
+      if (rs != rocblas_status_success || info != 0)
+        return bail(fail(SG_EDEVICE, "generalised eigensolver of the 2-D pencil failed"));
+      // dK holds the eigenvectors column by column (column-major V): read as
+      // row-major it is V^T, the inverse transform; the forward transform V
+      // is its transpose
+      std::vector<double> Vt((size_t)n2 * n2), V((size_t)n2 * n2);
+      HIPCHK(hipMemcpy(Vt.data(), dK, Vt.size() * sizeof(double), hipMemcpyDeviceToHost));
+      for (int i = 0; i < n2; ++i)
+        for (int j = 0; j < n2; ++j) V[(size_t)i * n2 + j] = Vt[(size_t)j * n2 + i];
+      m.assign(n2, 1.0);
+      if ((st = upload(p, m, &dm))) return bail(st);
+      mt.mx[a] = dm; mt.kx[a] = dlam;
+      if ((st = upload(p, V, &p->tf[a]))) return bail(st);
+      p->ti[a] = dK;
     } else if (a > kEigMaxLevel) {
       continue;  // block-LU components: no modes at this level
     } else {
@@ -1165,6 +1211,18 @@ sg_status sg_host_pencil(int a, double len, int ncell, const double *c_vals, dou
   pencil_eigen(a, len, element_c2(a, len, ncell, c_vals), v, l);
   if (V) std::memcpy(V, v.data(), v.size() * sizeof(double));
   if (lam) std::memcpy(lam, l.data(), l.size() * sizeof(double));
+  return SG_OK;
+}
+
+sg_status sg_host_pencil_2d(int a, const double *len, const int *ncell, const double *c_vals,
+                            double *K, double *M) {
+  if (a < 1 || a > kEig2MaxLevel || !len || !ncell || !c_vals || !(len[0] > 0) ||
+      !(len[1] > 0) || ncell[0] < 1 || ncell[1] < 1)
+    return fail(SG_EINVAL, "need 1 <= a <= 6, len > 0, ncell >= 1");
+  std::vector<double> k, m;
+  pencil_2d(a, len, ncell, c_vals, k, m);
+  if (K) std::memcpy(K, k.data(), k.size() * sizeof(double));
+  if (M) std::memcpy(M, m.data(), m.size() * sizeof(double));
   return SG_OK;
 }
 

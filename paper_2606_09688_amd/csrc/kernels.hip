@@ -1665,7 +1665,7 @@ __device__ __forceinline__ void mode_scalars(const SolveDesc &S, int j,
                                              const ModeTables *mt, int d, double &m,
                                              double &kap) {
   const int a = S.a, na = (1 << a) - 1;
-  if (d == 1) {
+  if (d == 1 || S.flat) {
     m = mt->mx[a][j];
     kap = S.c2 * mt->kx[a][j];
   } else {

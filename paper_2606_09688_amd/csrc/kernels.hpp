@@ -83,6 +83,8 @@ struct SolveDesc {
   int refine;            // maximum refinement sweeps (double-double residual)
   int transpose;         // solve with the transposed time matrices
   int wave;              // 1: one wave per mode (long time levels), 0: one thread
+  int flat;              // 1: modes of a dense spatial pencil (2-D variable speed):
+                         //    mass mx[a][j], stiffness c2 kx[a][j], as in 1-D
   double c2;             // wave speed squared (constant-speed path)
   long long thread0;     // first global thread, a multiple of 64 (one wave
                          // never spans two descriptors)

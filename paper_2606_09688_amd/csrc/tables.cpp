@@ -506,6 +506,70 @@ void block_lu(const TimeLevel &tl, const std::vector<double> &mk, int nx,
   }
 }
 
+// 1-D P1 integrals of level a over [lo, hi] (part of (0, len)), per interior
+// node k: mass and unit stiffness on the diagonal (d) and the coupling of
+// k and k+1 (o).  On element e the hats are 1 - u and u, u = x / h - e.
+struct P1Band {
+  std::vector<long double> md, mo, kd, ko;
+};
+static P1Band p1_on_interval(int a, double len, long double lo, long double hi) {
+  const int ne = 1 << a, n = ne - 1;
+  const long double h = (long double)len / ne;
+  P1Band B;
+  B.md.assign(n, 0.0L); B.mo.assign(n, 0.0L); B.kd.assign(n, 0.0L); B.ko.assign(n, 0.0L);
+  for (int e = 0; e < ne; ++e) {
+    const long double x0 = std::max(lo, e * h), x1 = std::min(hi, (e + 1) * h);
+    if (x1 <= x0) continue;
+    const long double u0 = x0 / h - e, u1 = x1 / h - e;
+    const long double d1 = u1 - u0, d2 = u1 * u1 - u0 * u0, d3 = u1 * u1 * u1 - u0 * u0 * u0;
+    const long double mll = h * (d1 - d2 + d3 / 3), mlr = h * (d2 / 2 - d3 / 3), mrr = h * d3 / 3;
+    const long double kk = d1 / h;
+    if (e >= 1) { B.md[e - 1] += mll; B.kd[e - 1] += kk; }        // left node e
+    if (e + 1 <= n) { B.md[e] += mrr; B.kd[e] += kk; }            // right node e+1
+    if (e >= 1 && e + 1 <= n) { B.mo[e - 1] += mlr; B.ko[e - 1] -= kk; }
+  }
+  return B;
+}
+
+void pencil_2d(int a, const double *len, const int *ncell, const double *c_vals,
+               std::vector<double> &K, std::vector<double> &M) {
+  const int n = (1 << a) - 1;
+  const size_t n2 = (size_t)n * n;
+  auto band = [](const std::vector<long double> &d, const std::vector<long double> &o, int i,
+                 int j) -> long double {
+    if (i == j) return d[i];
+    if (j == i + 1) return o[i];
+    if (i == j + 1) return o[j];
+    return 0.0L;
+  };
+  std::vector<P1Band> bx(ncell[0]), by(ncell[1]);
+  for (int b = 0; b < ncell[0]; ++b)
+    bx[b] = p1_on_interval(a, len[0], (long double)len[0] * b / ncell[0],
+                           (long double)len[0] * (b + 1) / ncell[0]);
+  for (int b = 0; b < ncell[1]; ++b)
+    by[b] = p1_on_interval(a, len[1], (long double)len[1] * b / ncell[1],
+                           (long double)len[1] * (b + 1) / ncell[1]);
+  const P1Band fx = p1_on_interval(a, len[0], 0.0L, len[0]);
+  const P1Band fy = p1_on_interval(a, len[1], 0.0L, len[1]);
+  K.assign(n2 * n2, 0.0);
+  M.assign(n2 * n2, 0.0);
+  for (int iy = 0; iy < n; ++iy)
+    for (int ix = 0; ix < n; ++ix)
+      for (int jy = std::max(0, iy - 1); jy <= std::min(n - 1, iy + 1); ++jy)
+        for (int jx = std::max(0, ix - 1); jx <= std::min(n - 1, ix + 1); ++jx) {
+          long double k = 0.0L;
+          for (int cy = 0; cy < ncell[1]; ++cy)
+            for (int cx = 0; cx < ncell[0]; ++cx) {
+              const long double c = c_vals[(size_t)cy * ncell[0] + cx];
+              k += c * c * (band(by[cy].md, by[cy].mo, iy, jy) * band(bx[cx].kd, bx[cx].ko, ix, jx) +
+                            band(by[cy].kd, by[cy].ko, iy, jy) * band(bx[cx].md, bx[cx].mo, ix, jx));
+            }
+          const size_t r = (size_t)iy * n + ix, c = (size_t)jy * n + jx;
+          K[r * n2 + c] = (double)k;
+          M[r * n2 + c] = (double)(band(fy.md, fy.mo, iy, jy) * band(fx.md, fx.mo, ix, jx));
+        }
+}
+
 std::vector<double> space_entries(int a, double len, int ncell, const double *c_vals) {
   const int ne = 1 << a, n = ne - 1;
   const double h = len / ne;  // exact: len scaled by a power of two

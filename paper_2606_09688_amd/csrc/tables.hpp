@@ -59,6 +59,14 @@ std::vector<double> element_c2(int a, double len, int ncell, const double *c_val
 void pencil_eigen(int a, double len, const std::vector<double> &c2e, std::vector<double> &V,
                   std::vector<double> &lam);
 
+// Dense Q1 pencil of level a in 2-D (n = 2^a - 1 nodes per axis, x fastest):
+// K(c) and M, both row-major n^2 x n^2 and symmetric, on (0,len[0]) x
+// (0,len[1]) with c piecewise constant on ncell[0] x ncell[1] uniform blocks
+// (x fastest).  Every element integral is taken exactly over the part of the
+// element inside each block (in long double) and rounded once.
+void pencil_2d(int a, const double *len, const int *ncell, const double *c_vals,
+               std::vector<double> &K, std::vector<double> &M);
+
 // Tridiagonal M and K(c) of level a (d = 1) per interior node k, kSpaceStride
 // doubles: [M_kk, M_{k,k+1}, K_kk, K_{k,k+1}, lo(K_kk), lo(K_{k,k+1})] (the
 // coupling entries are 0 at the last node).  K is formed in double-double

@@ -102,15 +102,24 @@ VARC = [
 ]
 
 
-@pytest.mark.parametrize("case", VARC, ids=lambda c: f"d1L{c[3]}c{len(c[1])}")
-def test_variable_speed_parity(case):
-    """c piecewise constant (1-D): spatial modes of the pencil (K(c), M),
-    the same time solves; forward, components and adjoint vs the oracle."""
+def _speeds(n, seed):
+    return list(np.random.default_rng(seed).uniform(0.5, 2.0, n))
+
+
+VARC2 = [
+    # (lengths, ncell, c, T, L): piecewise-constant speed in 2-D (x fastest)
+    ([1.0, 1.0], [4, 4], _speeds(16, 71), 1.0, 3),
+    ([1.0, 0.8], [2, 2], _speeds(4, 72), 1.3, 5),
+    ([1.0, 1.0], [4, 4], _speeds(16, 73), 1.0, 6),
+    ([1.0, 1.0], [4, 4], _speeds(16, 74), 1.0, 7),   # spatial level 6: 3969-node pencil
+]
+
+
+def _variable_speed_parity(d, lengths, ncell, cv, T, L):
     torch = _torch()
-    lengths, cv, T, L = case
-    spec = workloads.Spec(1, lengths, [len(cv)], cv, T, L)
+    spec = workloads.Spec(d, lengths, ncell, cv, T, L)
     data = workloads.random_data(spec, 300 + L)
-    print(f"case d=1 L={L} c={cv} T={T}", flush=True)
+    print(f"case d={d} L={L} ncell={ncell} T={T}", flush=True)
     orc = Problem(*spec.args())
     U_ref = orc.forward(data["f"], data["u0"], data["v0"]).reshape(spec.shape())
     df_ref, du0_ref, dv0_ref = orc.adjoint(data["g"])
@@ -131,6 +140,30 @@ def test_variable_speed_parity(case):
         e = rel(got.cpu().numpy(), ref)
         print(f"  adjoint {name} rel l2 {e:.3e}", flush=True)
         assert e <= TOL, name
+
+
+@pytest.mark.parametrize("case", VARC, ids=lambda c: f"d1L{c[3]}c{len(c[1])}")
+def test_variable_speed_parity(case):
+    """c piecewise constant (1-D): spatial modes of the pencil (K(c), M),
+    the same time solves; forward, components and adjoint vs the oracle."""
+    lengths, cv, T, L = case
+    _variable_speed_parity(1, lengths, [len(cv)], cv, T, L)
+
+
+@pytest.mark.parametrize("case", VARC2, ids=lambda c: f"d2L{c[4]}c{c[1][0]}x{c[1][1]}")
+def test_variable_speed_parity_2d(case):
+    """c piecewise constant (2-D): M-orthonormal modes of the dense Q1 pencil
+    (K(c), M) as one flat spatial index, the same time solves; forward,
+    components and adjoint vs the oracle."""
+    lengths, ncell, cv, T, L = case
+    _variable_speed_parity(2, lengths, ncell, cv, T, L)
+
+
+def test_variable_speed_2d_beyond_level_6_is_refused():
+    _torch()
+    import paper_2606_09688_amd as sg
+    with pytest.raises(sg.SGError):
+        sg.SparseGridWave(2, [1.0, 1.0], [2, 2], [1.0, 0.5, 0.7, 1.2], 1.0, 8)
 
 
 @pytest.mark.parametrize("case", [CASES[2], CASES[4], CASES[7], CASES[9]],
@@ -220,7 +253,8 @@ def test_invalid_arguments_raise():
 
 
 def test_batch_graph_of_uneven_problems():
-    """Independent problems of different d, L and speeds in one HIP graph
+    """Independent problems of different d, L and speeds (constant and
+    piecewise constant, 1-D and 2-D) in one HIP graph
     (one branch each): every replay reproduces each problem's own eager
     forward and adjoint bitwise; one problem is also checked against the
     oracle."""
@@ -233,6 +267,7 @@ def test_batch_graph_of_uneven_problems():
         workloads.Spec(2, [1.2, 1.0], [1, 1], [1.1], 0.9, 7),
         workloads.Spec(1, [2.0], [2], [1.0, 0.5], 2.0, 6),
         workloads.Spec(2, [1.0, 1.0], [1, 1], [1.0], 1.0, 3),
+        workloads.Spec(2, [1.0, 1.0], [4, 4], _speeds(16, 75), 1.0, 6),  # variable speed
     ]
     svs, ins, eager = [], [], []
     for k, spec in enumerate(specs):
@@ -264,7 +299,8 @@ def test_batch_graph_of_uneven_problems():
         for k, (o, e) in enumerate(zip(outs, eager)):
             assert all(torch.equal(a, b) for a, b in zip(o, e)), (rep, k)
         _ = sum(float(x[0].sum()) for x in ins)  # unrelated eager work between replays
-    # one member against the oracle
-    spec, data = specs[2], ins[2][4]
-    U_ref = Problem(*spec.args()).forward(data["f"], data["u0"], data["v0"])
-    assert rel(outs[2][0].cpu().numpy(), U_ref) <= TOL
+    # two members (1-D and 2-D variable speed) against the oracle
+    for k in (2, 6):
+        spec, data = specs[k], ins[k][4]
+        U_ref = Problem(*spec.args()).forward(data["f"], data["u0"], data["v0"])
+        assert rel(outs[k][0].cpu().numpy(), U_ref.reshape(spec.shape())) <= TOL, k

@@ -109,3 +109,27 @@ def test_host_pencil_eigenpairs_of_oracle_matrices(a, length, cv):
     # the eigenvalues are those of the pencil (dense reference for small n)
     ref = np.sort(np.linalg.eigvals(np.linalg.solve(M, K)).real)
     assert np.allclose(np.sort(lam), ref, rtol=1e-10, atol=0)
+
+
+@pytest.mark.parametrize("a,lengths,ncell", [(2, [1.0, 1.0], [4, 4]), (3, [1.0, 1.0], [4, 4]),
+                                              (3, [1.0, 0.8], [3, 2]), (4, [1.3, 1.0], [4, 4])])
+def test_host_pencil_2d_matches_oracle_matrices(a, lengths, ncell):
+    """The dense 2-D variable-speed pencil the library diagonalises (rocSOLVER,
+    at assembly) is the oracle's Q1 mass and stiffness of eq. (9), blocks
+    aligned with the mesh or not."""
+    import paper_2606_09688_amd as sg
+    from oracle.space import Medium, mass, stiff
+    rng = np.random.default_rng(10 + a)
+    cv = rng.uniform(0.5, 2.0, ncell[0] * ncell[1])
+    med = Medium(lengths, ncell, cv)
+    K_ref = stiff(a, med).toarray()
+    M_ref = mass(a, med).toarray()
+    K, M = sg.host_pencil_2d(a, lengths, ncell, cv)
+    assert np.array_equal(K, K.T) and np.array_equal(M, M.T)
+    assert np.abs(K - K_ref).max() <= 1e-13 * np.abs(K_ref).max()
+    assert np.abs(M - M_ref).max() <= 1e-13 * np.abs(M_ref).max()
+    # a pencil with a sign or a block slip is not symmetric positive definite
+    # with the oracle's spectrum
+    lam = np.sort(np.linalg.eigvals(np.linalg.solve(M, K)).real)
+    ref = np.sort(np.linalg.eigvals(np.linalg.solve(M_ref, K_ref)).real)
+    assert np.allclose(lam, ref, rtol=1e-10, atol=0) and lam[0] > 0
