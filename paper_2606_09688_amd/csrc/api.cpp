@@ -453,13 +453,14 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
     const double *Q = p->tf[C.a], *Qi = p->ti[C.a];
     const int ny = p->d == 2 && !flat ? na : 1;
     double *mid = flat ? p->bufS : p->bufT;
-    auto tiles = [](int M, int N) { return ((M + 63) / 64) * ((N + 63) / 64); };
+    constexpr int T = kGemmTile;
+    auto tiles = [](int M, int N) { return ((M + T - 1) / T) * ((N + T - 1) / T); };
     // forward x: T = B * Q   ([nq*ny x na] x [na x na])
     {
       GemmDesc g{};
       g.A = x_in + C.off; g.B = Q; g.C = mid + C.off;
       g.M = C.nq * ny; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
-      g.batch = 1; g.tm = (g.M + 63) / 64; g.tn = (g.N + 63) / 64; g.tile0 = tx;
+      g.batch = 1; g.tm = (g.M + T - 1) / T; g.tn = (g.N + T - 1) / T; g.tile0 = tx;
       tx += tiles(g.M, g.N);
       vx.push_back(g);
     }
@@ -468,7 +469,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
       GemmDesc g{};
       g.A = mid + C.off; g.B = Qi; g.C = x_out + C.off;
       g.M = C.nq * ny; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
-      g.batch = 1; g.tm = (g.M + 63) / 64; g.tn = (g.N + 63) / 64; g.tile0 = tix;
+      g.batch = 1; g.tm = (g.M + T - 1) / T; g.tn = (g.N + T - 1) / T; g.tile0 = tix;
       tix += tiles(g.M, g.N);
       vix.push_back(g);
     }
@@ -479,7 +480,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
       g.A = Q; g.B = p->bufT + C.off; g.C = p->bufS + C.off;
       g.M = na; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
       g.sA = 0; g.sB = slab; g.sC = slab;
-      g.batch = C.nq; g.tm = (na + 63) / 64; g.tn = (na + 63) / 64; g.tile0 = ty;
+      g.batch = C.nq; g.tm = (na + T - 1) / T; g.tn = (na + T - 1) / T; g.tile0 = ty;
       ty += C.nq * tiles(na, na);
       vy.push_back(g);
       // inverse y: T_i = Q * S_i

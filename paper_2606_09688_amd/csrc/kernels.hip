@@ -1495,8 +1495,9 @@ __global__ void k_adjoint_fields(const LevelDesc *__restrict__ ld, int nlev,
   L.fu[K] = fu;
 }
 
-// Batched C = A B (row major) on the FP64 matrix cores.  64x64 block tiles,
-// 4 waves, each wave a 32x32 sub-tile of 2x2 v_mfma_f64_16x16x4 blocks; K in
+// Batched C = A B (row major) on the FP64 matrix cores.  Block tiles of
+// kGemmTile square, each wave a 32x32 sub-tile of 2x2 v_mfma_f64_16x16x4
+// blocks; K in
 // steps of SG_GEMM_BK through LDS, the next K tile prefetched in registers.
 // Operand layout of the 16x16x4 instruction (lane l of the wave):
 //   a = A[l % 16][l / 16],  b = B[l / 16][l % 16],
@@ -1506,12 +1507,14 @@ typedef double sg_double4 __attribute__((ext_vector_type(4)));
 #ifndef SG_GEMM_BK
 #define SG_GEMM_BK 64
 #endif
-__global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ descs, int ndesc) {
-  // K steps of 64: each step is 64 MFMAs per wave (about 1.7 us of matrix
-  // work), enough to cover the global-load latency of the next step's
-  // operands, which are prefetched into registers meanwhile
-  constexpr int BM = 64, BN = 64, BK = SG_GEMM_BK;
-  constexpr int EA = BM * BK / 256, EB = BK * BN / 256;  // staged values per thread
+__global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmDesc *__restrict__ descs,
+                                                      int ndesc) {
+  // K steps of SG_GEMM_BK: with 64 each step is 64 MFMAs per wave (about
+  // 1.7 us of matrix work), enough to cover the global-load latency of the
+  // next step's operands, which are prefetched into registers meanwhile
+  constexpr int NT = kGemmThreads, W = SG_GEMM_W;
+  constexpr int BM = kGemmTile, BN = kGemmTile, BK = SG_GEMM_BK;
+  constexpr int EA = BM * BK / NT, EB = BK * BN / NT;  // staged values per thread
   __shared__ double As[BM][BK + 1];
   __shared__ double Bs[BK][BN + 2];
   int di = 0;
@@ -1527,7 +1530,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ descs
   double *Cp = Dd.C + bidx * Dd.sC;
   const int row0 = tmi * BM, col0 = tni * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave / W) * 32, wn = (wave % W) * 32;
   const int M = Dd.M, N = Dd.N, K = Dd.K;
   // global -> register staging; loads go to clamped valid addresses and are
   // selected, not branched
@@ -1535,7 +1538,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ descs
   auto load_tile = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
-      const int i = tid + e * 256;
+      const int i = tid + e * NT;
       const int m = i / BK, k = i % BK;           // A: BM x BK
       const int gm = row0 + m, gk = k0 + k;
       const bool oka = gm < M && gk < K;
@@ -1544,7 +1547,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ descs
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      const int i = tid + e * 256;
+      const int i = tid + e * NT;
       const int kb = i / BN, n = i % BN;          // B: BK x BN
       const int gkb = k0 + kb, gn = col0 + n;
       const bool okb = gkb < K && gn < N;
@@ -1561,12 +1564,12 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ descs
   for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
-      const int i = tid + e * 256;
+      const int i = tid + e * NT;
       As[i / BK][i % BK] = ra[e];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      const int i = tid + e * 256;
+      const int i = tid + e * NT;
       Bs[i / BN][i % BN] = rb[e];
     }
     __syncthreads();
@@ -2381,7 +2384,7 @@ hipError_t launch_adjoint_fields(const LevelDesc *ld, int nlev, long long total,
 
 hipError_t launch_gemm(const GemmDesc *descs, int ndesc, int total_tiles, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemm, dim3(total_tiles), dim3(256), 0, s, descs, ndesc);
+  hipLaunchKernelGGL(k_gemm, dim3(total_tiles), dim3(kGemmThreads), 0, s, descs, ndesc);
   return hipGetLastError();
 }
 

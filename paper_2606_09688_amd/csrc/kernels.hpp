@@ -63,6 +63,14 @@ struct WorkItem {        // flattened per-channel work (reduce / coarse kernels)
   long long count;
 };
 
+// MFMA GEMM tiles: SG_GEMM_W x SG_GEMM_W waves per workgroup, each a 32 x 32
+// sub-tile (tiles of 32 SG_GEMM_W square)
+#ifndef SG_GEMM_W
+#define SG_GEMM_W 2
+#endif
+constexpr int kGemmTile = 32 * SG_GEMM_W;
+constexpr int kGemmThreads = 64 * SG_GEMM_W * SG_GEMM_W;
+
 struct GemmDesc {
   const double *A;
   const double *B;
