@@ -826,8 +826,8 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device);
   if (ncu <= 0) ncu = 256;
   // workgroups the time chunks aim at (tiles x chunks); in 2-D this geometry
-  // only serves the prolongation through the mass stencil, whose 32 x 32
-  // workgroups keep 2 resident per CU.  SG_CHUNK_WG overrides.
+  // serves the 32 x 32 workgroup tiles (2 resident per CU), used where the
+  // 16 x 16 per-wave tiles do not apply.  SG_CHUNK_WG overrides.
   int chunk_wg = d == 2 ? 2 * ncu : 1024;
   if (const char *e = getenv("SG_CHUNK_WG")) chunk_wg = std::max(1, atoi(e));
   const Geometry geo = make_geometry(d, J, ntf, chunk_wg);
@@ -840,15 +840,13 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   const bool w16 = d == 2 && n16 * n16 <= kCoarseMax;
   const Geometry geor = w16 ? make_geometry(d, J, ntf, 4 * 4 * ncu, 16) : geo;
   const Geometry geoa = w16 ? make_geometry(d, J, ntf, 4 * 3 * ncu, 16) : geo;
-  // the prolongation into U likewise (4 workgroups per CU; SG_PROL_WG
-  // overrides).  The prolongation through the mass stencil keeps 32 x 32
-  // tiles per workgroup: its per-wave form needs a one-node ring around every
-  // 16 x 16 tile (27 % more fine nodes, 161 upper nodes per wave) and measured
-  // 1.04 ms against 0.81 ms at d=2 L=10.
-  int pwg = 4;
+  // the prolongations likewise, 4 workgroups per CU each (SG_PROL_WG and
+  // SG_PROLM_WG override for the plain and the mass-stencil prolongation)
+  int pwg = 4, pmwg = 4;
   if (const char *e = getenv("SG_PROL_WG")) pwg = std::max(1, atoi(e));
+  if (const char *e = getenv("SG_PROLM_WG")) pmwg = std::max(1, atoi(e));
   const Geometry geop = w16 ? make_geometry(d, J, ntf, 4 * pwg * ncu, 16) : geo;
-  const Geometry &geom = geo;
+  const Geometry geom = w16 ? make_geometry(d, J, ntf, 4 * pmwg * ncu, 16) : geo;
   const Geometry geof = make_geometry(d, J, 2, 1);
   long long part_need = 0;
   auto chan_comp = [&](int a, int k, bool spline, double *buf, bool signed_, int only) {

@@ -1199,7 +1199,7 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
 // are written.  Fine nodes are taken row-major, p = lane + 64 e, so that
 // every store instruction writes whole 128-byte rows.  Taps (weights times
 // channel sign, and where the window moves on) come from a per-pass host
-// table.  The prolongation through the mass stencil keeps k_prolong.
+// table.  The prolongation through the mass stencil is k_prolong_wm.
 #ifndef SG_WPEP
 #define SG_WPEP 4
 #endif
@@ -1361,6 +1361,220 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
         double o = v + basev[e];
         if (A.accumulate) o += A.out[off];
         A.out[off] = o;
+      }
+    }
+  }
+}
+
+// 2-D prolongation through the fine mass stencil, one 16 x 16 output tile
+// per wave.  The upper levels are evaluated and interpolated as in
+// k_prolong_w, on a region with one more node on each side.  The fine values
+// themselves are never formed: with F = Phi_1 z + (level-J channel), the
+// mass stencil of the interpolant is, per axis, a fixed stencil on level 1
+// (P1 hats, fine spacing h): at an even fine node 2K it is
+// h/12 (z_{K-1} + 10 z_K + z_{K+1}), at an odd node 2K+1 it is
+// h/2 (z_K + z_{K+1}); the 2-D stencil is the tensor product.  The mass
+// stencil of the level-J channel's three coefficient fields is applied once,
+// before the slab loop, and kept in LDS.  Lane l writes column l % 16, rows
+// 4 (l / 16) .. +3, which share four level-1 rows.
+#ifndef SG_WPEM
+#define SG_WPEM 4
+#endif
+__global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A) {
+  constexpr int TS = 16, LTS = 4;
+  using SH = Shape<2, TS, 1>;
+  constexpr int NF = TS + 2;              // fine region with its ring (setup only)
+  constexpr int L0 = NF * NF;
+  constexpr int EF = (L0 + 63) / 64;
+  constexpr int UP = SH::upper;
+  constexpr int NS = (UP + 63) / 64;      // owned upper-node slots per lane
+  constexpr int NCI = 2 * (LTS + 1);
+  constexpr int NO = TS * TS / 64;        // outputs per lane
+  static_assert(NS == 3 && NO == 4, "tile shape");
+  __shared__ double s_v_w[4][UP];
+  __shared__ double s_f_w[4][L0];
+  __shared__ double s_m_w[4][3][TS * TS];  // mass stencil of the level-J coefficients
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double *s_v = s_v_w[wave];
+  double *s_f = s_f_w[wave];
+  double (*s_m)[TS * TS] = s_m_w[wave];
+
+  const Geometry g = A.g;
+  const int nt = g.ntile, ng = (nt + 1) >> 1;
+  int grp, chunk;
+  stream_block(ng * ng, g.nchunk, grp, chunk);
+  const int tx = 2 * (grp % ng) + (wave & 1), ty = 2 * (grp / ng) + (wave >> 1);
+  if (tx >= nt || ty >= nt) return;  // no workgroup barrier below
+  const int n0 = chunk * g.chunk, n1 = min(n0 + g.chunk, g.ntf);
+  const long long nsp = (long long)g.nxf * g.nxf;
+  const int R = g.R;
+  const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
+  const int n0a = (1 << g.A0) - 1;
+  const long long nsp0 = (long long)n0a * n0a;
+  const double hx = 6.0 * A.sx, hy = 6.0 * A.sy;  // fine mesh widths
+
+  // ---- owned upper nodes: coefficient offsets and windows ----
+  Owned<2, TS, 1> own[NS];
+  int coff[NS], cof0[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    own[i].set(lane + 64 * i);
+    coff[i] = -1;
+    cof0[i] = -1;
+    const int r = own[i].r;
+    if (r >= 1 && r <= R) {
+      const int na = (1 << (g.J - r)) - 1;
+      const int Px = tile_lo(TS, tx, r, 1) + own[i].jx;
+      const int Py = tile_lo(TS, ty, r, 1) + own[i].jy;
+      if (interior(Px, na) && interior(Py, na)) coff[i] = (Px - 1) + (Py - 1) * na;
+      if (r == R && use_coarse && interior(Px, n0a) && interior(Py, n0a))
+        cof0[i] = (Px - 1) + (Py - 1) * n0a;
+    }
+  }
+  auto coef = [&](const Channel &C, int q, int off) -> double {
+    if (off < 0 || q >= C.nq) return 0.0;
+    const int na = (1 << C.a) - 1;
+    return C.data[(long long)q * na * na + off];
+  };
+  double cw[NS][2][3];
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      cw[i][k][0] = cw[i][k][1] = cw[i][k][2] = 0.0;
+      const int r = own[i].r;
+      if (r < 1 || r > R) continue;
+      const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
+      if (!C.active) continue;
+      const int q = ld_const(C.q0, n0);
+#pragma unroll
+      for (int o = 0; o < 3; ++o) cw[i][k][o] = coef(C, q + o, coff[i]);
+    }
+
+  // ---- outputs of this lane and the mass stencil of the level-J channel ----
+  const int fx = lane & 15, fy0 = (lane >> 4) * NO;
+  const int lo0x = tile_lo(TS, tx, 0, 1), lo0y = tile_lo(TS, ty, 0, 1);
+  const Channel &CJ = A.ch[(g.J - 1) * 2];
+#pragma unroll
+  for (int o = 0; o < 3; ++o) {
+#pragma unroll
+    for (int e = 0; e < EF; ++e) {
+      const int p = lane + 64 * e;
+      if (p >= L0) continue;
+      const int Px = lo0x + p % NF, Py = lo0y + p / NF;
+      const int off = interior(Px, g.nxf) && interior(Py, g.nxf) ? (Px - 1) + (Py - 1) * g.nxf : -1;
+      s_f[p] = CJ.active ? coef(CJ, o, off) : 0.0;
+    }
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < NO; ++e) {
+      double h[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double *row = s_f + (fy0 + e + i) * NF + fx;
+        h[i] = row[0] + row[2] + 4.0 * row[1];
+      }
+      s_m[o][(fy0 + e) * TS + fx] = A.sx * A.sy * (h[0] + h[2] + 4.0 * h[1]);
+    }
+    wave_sync();
+  }
+  // level-1 stencil of the lane's outputs: x taps (level-1 column, weight)
+  // for column Px = 16 tx + fx, y taps for rows Py = 16 ty + fy0 + e
+  const int pn1 = SH::nodes(1);
+  const int plox = tile_lo(TS, tx, 1, 1), ploy = tile_lo(TS, ty, 1, 1);
+  const int Pxo = TS * tx + fx;
+  const bool xin = interior(Pxo, g.nxf);
+  const int kx = (Pxo >> 1) - plox;
+  const bool xeven = (Pxo & 1) == 0;
+  // even: columns kx-1, kx, kx+1 with h/12 (1, 10, 1); odd: kx, kx+1 with h/2
+  const int cx0 = xeven ? kx - 1 : kx;
+  const double wx0 = xeven ? hx / 12.0 : 0.5 * hx, wx1 = xeven ? 10.0 * hx / 12.0 : 0.5 * hx,
+               wx2 = xeven ? hx / 12.0 : 0.0;
+  const double *cbase = use_coarse ? A.coarse : A.safe_w;
+  double pco[NS];
+  auto fetch_co = [&](int n) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) pco[i] = cbase[cof0[i] >= 0 ? (long long)n * nsp0 + cof0[i] : 0];
+  };
+
+  fetch_co(n0);
+  for (int n = n0; n < n1; ++n) {
+    const TapEntry *tn = A.taps + (long long)n * NCI;
+    double co[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) co[i] = cof0[i] >= 0 ? pco[i] : 0.0;
+    if (n + 1 < n1) fetch_co(n + 1);
+    wave_sync();
+    // (A) owners evaluate their node in time
+#pragma unroll
+    for (int r = 1; r <= LTS; ++r) {
+      if (r > R) break;
+      const TapEntry t0 = ld_const(tn, 2 * r), t1 = ld_const(tn, 2 * r + 1);
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        if (own[i].r != r) continue;
+        double v = r == R ? co[i] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
+          if (!C.active) continue;
+          const TapEntry &t = k == 0 ? t0 : t1;
+          if (t.base >= 0) {  // the window moves on to q0 = t.base
+            cw[i][k][0] = cw[i][k][1];
+            cw[i][k][1] = cw[i][k][2];
+            cw[i][k][2] = coef(C, (int)t.base + 2, coff[i]);
+          }
+          v += t.w[0] * cw[i][k][0] + t.w[1] * cw[i][k][1] + t.w[2] * cw[i][k][2];
+        }
+        s_v[SH::offset(r) - SH::size(0) + own[i].j] = v;
+      }
+    }
+    // (B) top-down interpolation r = R-1 .. 1
+#pragma unroll
+    for (int r = LTS - 1; r >= 1; --r) {
+      if (r >= R) continue;
+      wave_sync();
+      const int pn = SH::nodes(r + 1);
+      const int lox = tile_lo(TS, tx, r, 1), loy = tile_lo(TS, ty, r, 1);
+      const int qx = tile_lo(TS, tx, r + 1, 1), qy = tile_lo(TS, ty, r + 1, 1);
+      const double *par = s_v + SH::offset(r + 1) - SH::size(0);
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        if (own[i].r != r) continue;
+        const int Px = lox + own[i].jx, Py = loy + own[i].jy;
+        const int xl = (Px >> 1) - qx, xh = ((Px + 1) >> 1) - qx;
+        const int yl = (Py >> 1) - qy, yh = ((Py + 1) >> 1) - qy;
+        s_v[SH::offset(r) - SH::size(0) + own[i].j] +=
+            0.25 * (par[yl * pn + xl] + par[yl * pn + xh] + par[yh * pn + xl] + par[yh * pn + xh]);
+      }
+    }
+    wave_sync();
+    // (C) outputs: level-1 stencil plus the level-J channel.  The lane's
+    // four rows Py0 .. Py0+3 (Py0 even) use level-1 rows K0-1 .. K0+2,
+    // K0 = Py0 / 2; each row is first reduced with the x stencil.
+    const TapEntry tj = ld_const(tn, 0);
+    double xs[4] = {0.0, 0.0, 0.0, 0.0};
+    if (R >= 1) {
+      const int r0 = ((TS * ty + fy0) >> 1) - ploy - 1;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double *zr = s_v + (r0 + r) * pn1;
+        xs[r] = wx0 * zr[cx0] + wx1 * zr[cx0 + 1] + wx2 * zr[min(cx0 + 2, pn1 - 1)];
+      }
+    }
+    const double ye = hy / 12.0, yo = 0.5 * hy;
+    const double lev[4] = {ye * (xs[0] + 10.0 * xs[1] + xs[2]), yo * (xs[1] + xs[2]),
+                           ye * (xs[1] + 10.0 * xs[2] + xs[3]), yo * (xs[2] + xs[3])};
+#pragma unroll
+    for (int e = 0; e < NO; ++e) {
+      const int Py = TS * ty + fy0 + e;
+      const int po = (fy0 + e) * TS + fx;
+      double val = tj.w[0] * s_m[0][po] + tj.w[1] * s_m[1][po] + tj.w[2] * s_m[2][po] + lev[e];
+      if (xin && interior(Py, g.nxf)) {
+        const long long off = (long long)n * nsp + (long long)(Py - 1) * g.nxf + (Pxo - 1);
+        if (A.base != nullptr) val += A.base[off - (long long)n * nsp];
+        if (A.accumulate) val += A.out[off];
+        A.out[off] = val;
       }
     }
   }
@@ -2324,10 +2538,12 @@ hipError_t launch_prolong(const ProlongArgs &a, hipStream_t s) {
   hipLaunchKernelGGL((k_prolong<D, TS, TB, kNT, MO, NC>), grid, dim3(kNT), 0, s, a)
   if (a.g.d == 2 && a.g.TS == 16) {
     if (two || a.taps == nullptr) return hipErrorInvalidValue;  // one finest channel only
-    if (a.stencil) return hipErrorInvalidValue;  // mass stencil: 32 x 32 tiles only
     const int ng = (a.g.ntile + 1) / 2;
     dim3 gridw(ng * ng, a.g.nchunk);
-    hipLaunchKernelGGL(k_prolong_w, gridw, dim3(256), 0, s, a);
+    if (a.stencil)
+      hipLaunchKernelGGL(k_prolong_wm, gridw, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL(k_prolong_w, gridw, dim3(256), 0, s, a);
   } else if (a.g.d == 2) {
     if (a.stencil) {
       if (two) SG_PROLONG(2, kTS2, kTB2P, 1, 2); else SG_PROLONG(2, kTS2, kTB2P, 1, 1);

@@ -133,3 +133,26 @@ def test_host_pencil_2d_matches_oracle_matrices(a, lengths, ncell):
     lam = np.sort(np.linalg.eigvals(np.linalg.solve(M, K)).real)
     ref = np.sort(np.linalg.eigvals(np.linalg.solve(M_ref, K_ref)).real)
     assert np.allclose(lam, ref, rtol=1e-10, atol=0) and lam[0] > 0
+
+
+def test_mass_of_level1_interpolant_is_fixed_stencil():
+    """The 2-D df prolongation never forms the fine field: per axis, the fine
+    P1 mass matrix applied to the interpolant of level J-1 values z is
+    h/12 (z_{K-1} + 10 z_K + z_{K+1}) at fine node 2K and h/2 (z_K + z_{K+1})
+    at 2K+1 (checked on the oracle's own matrices, boundary values zero)."""
+    from oracle.space import interp_1d, mass_1d
+    J, length = 6, 1.3
+    h = length / 2 ** J
+    MJ = mass_1d(J, length).toarray()
+    Phi = interp_1d(J - 1, J, length).toarray()
+    z = np.random.default_rng(7).standard_normal(2 ** (J - 1) - 1)
+    ref = MJ @ Phi @ z
+    zp = np.concatenate([[0.0], z, [0.0]])   # level J-1 nodes 0 .. 2^(J-1)
+    got = np.empty(2 ** J - 1)
+    for m in range(1, 2 ** J):
+        K = m // 2
+        if m % 2 == 0:
+            got[m - 1] = h / 12 * (zp[K - 1] + 10 * zp[K] + zp[K + 1])
+        else:
+            got[m - 1] = h / 2 * (zp[K] + zp[K + 1])
+    assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
