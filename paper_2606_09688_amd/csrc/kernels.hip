@@ -1196,8 +1196,9 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
 // coefficients; the top level adds the levels below the tile from
 // A.coarse), (B) top-down interpolation through the levels, (C) the fine
 // nodes add their level-J channel and the interpolated level-1 values and
-// are written.  Fine nodes are taken row-major, p = lane + 64 e, so that
-// every store instruction writes whole 128-byte rows.  Taps (weights times
+// are written.  Lane l takes column l % 16, rows 4 (l / 16) .. +3, which
+// share three level-1 rows; every store instruction writes four whole
+// 128-byte rows.  Taps (weights times
 // channel sign, and where the window moves on) come from a per-pass host
 // table.  The prolongation through the mass stencil is k_prolong_wm.
 #ifndef SG_WPEP
@@ -1268,14 +1269,15 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
       for (int o = 0; o < 3; ++o) cw[i][k][o] = coef(C, q + o, coff[i]);
     }
 
-  // ---- fine nodes: level-J channel (q0 = 0 throughout) and base ----
-  const int lo0x = TS * tx, lo0y = TS * ty;
+  // ---- fine nodes: lane = column fx, rows fy0 .. fy0+3; level-J channel
+  // (q0 = 0 throughout) and base ----
+  const int fx = lane & 15, fy0 = (lane >> 4) * EF;
   const Channel &CJ = A.ch[(g.J - 1) * 2];
+  const int Px = TS * tx + fx;
   double rc[EF][3], basev[EF];
 #pragma unroll
   for (int e = 0; e < EF; ++e) {
-    const int p = lane + 64 * e;
-    const int Px = lo0x + p % TS, Py = lo0y + p / TS;
+    const int Py = TS * ty + fy0 + e;
     const int off = interior(Px, g.nxf) && interior(Py, g.nxf) ? (Px - 1) + (Py - 1) * g.nxf : -1;
 #pragma unroll
     for (int o = 0; o < 3; ++o) rc[e][o] = CJ.active ? coef(CJ, o, off) : 0.0;
@@ -1343,19 +1345,24 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
       }
     }
     wave_sync();
-    // (C) fine nodes
+    // (C) fine nodes: bilinear interpolation from level 1, x first; the
+    // lane's rows fy0 .. fy0+3 (fy0 even) use level-1 rows r0 .. r0+2
     const TapEntry tj = ld_const(tn, 0);
+    double xs[3] = {0.0, 0.0, 0.0};
+    if (R >= 1) {
+      const int kx = (Px >> 1) - plox, r0 = ((TS * ty + fy0) >> 1) - ploy;
+      const double wx1 = (Px & 1) ? 0.5 : 0.0, wx0 = 1.0 - wx1;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const double *zr = s_v + (r0 + r) * pn1 + kx;
+        xs[r] = wx0 * zr[0] + wx1 * zr[1];
+      }
+    }
+    const double lev[EF] = {xs[0], 0.5 * (xs[0] + xs[1]), xs[1], 0.5 * (xs[1] + xs[2])};
 #pragma unroll
     for (int e = 0; e < EF; ++e) {
-      const int p = lane + 64 * e;
-      const int Px = lo0x + p % TS, Py = lo0y + p / TS;
-      double v = tj.w[0] * rc[e][0] + tj.w[1] * rc[e][1] + tj.w[2] * rc[e][2];
-      if (R >= 1) {
-        const int xl = (Px >> 1) - plox, xh = ((Px + 1) >> 1) - plox;
-        const int yl = (Py >> 1) - ploy, yh = ((Py + 1) >> 1) - ploy;
-        v += 0.25 * (s_v[yl * pn1 + xl] + s_v[yl * pn1 + xh] + s_v[yh * pn1 + xl] +
-                     s_v[yh * pn1 + xh]);
-      }
+      const int Py = TS * ty + fy0 + e;
+      const double v = tj.w[0] * rc[e][0] + tj.w[1] * rc[e][1] + tj.w[2] * rc[e][2] + lev[e];
       if (interior(Px, g.nxf) && interior(Py, g.nxf)) {
         const long long off = (long long)n * nsp + (long long)(Py - 1) * g.nxf + (Px - 1);
         double o = v + basev[e];
