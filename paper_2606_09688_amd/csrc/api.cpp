@@ -303,6 +303,14 @@ sg_status build_pass(sg_problem *p, Pass &P, const Geometry &geo, F spec,
           t.base = prolong ? q0[n] : C.part_off + (long long)(q0[n - 1] - q0[n0]) * sz;
       }
     }
+    // entry 0 (the level-J channel, whose window never moves) carries the
+    // bit mask of the entries whose window moves on at the slab
+    for (int n = 0; n < geo.ntf; ++n) {
+      long long mv = 0;
+      for (int li = 2; li < nci; ++li)
+        if (taps[(size_t)n * nci + li].base >= 0) mv |= 1LL << li;
+      taps[(size_t)n * nci].base = mv;
+    }
     if ((st = upload(p, taps, &P.d_taps)) != SG_OK) return st;
   }
   if ((st = upload(p, P.h_ch, &P.d_ch)) != SG_OK) return st;
@@ -833,12 +841,13 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   const Geometry geo = make_geometry(d, J, ntf, chunk_wg);
   // 2-D restrictions stream 16 x 16 tiles, one per wave (four per workgroup),
   // unless their coarse pyramid (from level J-4) would not fit its LDS buffer.
-  // Their grids are sized to one full round of resident workgroups: 4 per CU
-  // for the load (one finest channel), 3 per CU for the adjoint restriction
-  // (which also carries the time sum of the cotangent).
+  // Their grids are sized to one full round of resident workgroups, 3 per CU
+  // (SG_RESTR_WG overrides for the load restriction).
   const long long n16 = J > 4 ? (1LL << (J - 4)) - 1 : 0;
   const bool w16 = d == 2 && n16 * n16 <= kCoarseMax;
-  const Geometry geor = w16 ? make_geometry(d, J, ntf, 4 * 4 * ncu, 16) : geo;
+  int rwg = 3;
+  if (const char *e = getenv("SG_RESTR_WG")) rwg = std::max(1, atoi(e));
+  const Geometry geor = w16 ? make_geometry(d, J, ntf, 4 * rwg * ncu, 16) : geo;
   const Geometry geoa = w16 ? make_geometry(d, J, ntf, 4 * 3 * ncu, 16) : geo;
   // the prolongations likewise, 4 workgroups per CU each (SG_PROL_WG and
   // SG_PROLM_WG override for the plain and the mass-stencil prolongation)

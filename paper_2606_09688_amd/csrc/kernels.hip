@@ -414,18 +414,43 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Per-slab tap block of the 16 x 16 streaming kernels: NCI entries of four
+// doubles (three weights, then the entry's base), copied into the wave's LDS
+// at the top of every slab.  Lane l < 4 NCI prefetches double l of the next
+// slab's block one slab ahead, so the weights never wait on memory; every
+// lane then reads the taps of its own level.  Entry 0 carries in its base the
+// bit mask of the entries whose window moves on at this slab.
+template <int NCI>
+struct SlabTaps {
+  static_assert(4 * NCI <= 64, "one tap double per lane");
+  const double *tab;
+  double next;
+  __device__ void fetch(const TapEntry *taps, int n, int lane) {
+    tab = reinterpret_cast<const double *>(taps);
+    next = tab[(long long)n * (4 * NCI) + min(lane, 4 * NCI - 1)];
+  }
+  __device__ void stage(double *s_t, int lane) const {
+    if (lane < 4 * NCI) s_t[lane] = next;
+  }
+};
+// moving-window mask of the staged slab (uniform)
+__device__ __forceinline__ int slab_moves(const double *s_t) {
+  return __builtin_amdgcn_readfirstlane((int)__double_as_longlong(s_t[3]));
+}
+
 // 2-D restriction with one 16 x 16 tile per wave.  Every wave streams the
 // slabs of its own tile through its own LDS region, so the slab loop has no
 // workgroup barrier; the four waves of a workgroup take a 2 x 2 block of
 // tiles, which share halo rows in the caches.  Lane l owns the 2 x 2 block of
 // fine nodes at (2 (l % 8), 2 (l / 8)) and the upper-level nodes u = l and
 // u = l + 64 of the tile's levels 1..4.  Same outputs and partial-block
-// layout as k_restrict<2, 16, ...>.
+// layout as k_restrict<2, 16, ...>.  Three workgroups per CU: the per-lane
+// taps and accumulators of both instances need up to 168 registers.
 #ifndef SG_WPEW
-#define SG_WPEW 4
+#define SG_WPEW 3
 #endif
 template <int STENCIL, int NC0>
-__global__ void __launch_bounds__(256, NC0 == 2 ? 3 : SG_WPEW) k_restrict_w(const RestrictArgs A) {
+__global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs A) {
   constexpr int TS = 16, LTS = 4, NIN = TS + 2, INSZ = NIN * NIN;
   constexpr int PF = (INSZ + 63) / 64;  // staged inputs per lane
   using SH = Shape<2, TS, 0>;
@@ -435,9 +460,12 @@ __global__ void __launch_bounds__(256, NC0 == 2 ? 3 : SG_WPEW) k_restrict_w(cons
   static_assert(INSZ % 2 == 0, "16-byte aligned rows of the staged input");
   __shared__ __align__(16) double s_in_w[4][INSZ];
   __shared__ double s_lv_w[4][PT];
+  constexpr int NCI = 2 * (LTS + 1);  // in-tile channels li = 2 r + k
+  __shared__ __align__(16) double s_t_w[4][4 * NCI];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double *s_in = s_in_w[wave];
   double *s_lv = s_lv_w[wave];
+  double *s_t = s_t_w[wave];
 
   const Geometry g = A.g;
   const int nt = g.ntile, ng = (nt + 1) >> 1;
@@ -501,11 +529,17 @@ __global__ void __launch_bounds__(256, NC0 == 2 ? 3 : SG_WPEW) k_restrict_w(cons
 #pragma unroll
     for (int k = 0; k < 2; ++k) racc[i][k][0] = racc[i][k][1] = racc[i][k][2] = 0.0;
 
-  constexpr int NCI = 2 * (LTS + 1);  // in-tile channels li = 2 r + k
   // partial-block entry of row `base` (channel offset + chunk-relative row)
   auto part_at = [&](const Channel &C, long long base, int r, int j) -> long long {
     return base + blk * C.qb * (long long)SH::size(r) + j;
   };
+
+  // tap entry of slot i: entries 2 r, 2 r + 1 of its level (0 when idle)
+  int tslot[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) tslot[i] = (own[i].r >= 1 && own[i].r <= R) ? 8 * own[i].r : 0;
+  SlabTaps<NCI> tp;
+  tp.fetch(A.taps, n0, lane);
 
   fetch(n0);
   for (int n = n0; n < n1; ++n) {
@@ -515,7 +549,11 @@ __global__ void __launch_bounds__(256, NC0 == 2 ? 3 : SG_WPEW) k_restrict_w(cons
       const int idx = lane + 64 * e;
       if (idx < INSZ) s_in[idx] = pos[e] >= 0 ? pin[e] : 0.0;
     }
-    if (n + 1 < n1) fetch(n + 1);
+    tp.stage(s_t, lane);
+    if (n + 1 < n1) {
+      fetch(n + 1);
+      tp.fetch(A.taps, n + 1, lane);
+    }
     wave_sync();
     // (1) fine level: 4 x 4 input window of the lane's 2 x 2 block, one row
     // at a time (rows i = 0..3 are input rows 2 ly + i)
@@ -558,53 +596,76 @@ __global__ void __launch_bounds__(256, NC0 == 2 ? 3 : SG_WPEW) k_restrict_w(cons
 #pragma unroll
       for (int c = 0; c < 2; ++c) s_lv[(2 * ly + b + 1) * PD::pn(0) + 2 * lx + c + 1] = m[b][c];
     const TapEntry *tn = A.taps + (long long)n * NCI;
-    if (A.ch[(g.J - 1) * 2].active) {
-      const TapEntry t = ld_const(tn, 0);
+    {  // level-J channel (zero weights when inactive)
+      const double2 w01 = *reinterpret_cast<const double2 *>(s_t);
+      const double w2 = s_t[2];
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          racc0[b][c][0] += t.w[0] * m[b][c];
-          racc0[b][c][1] += t.w[1] * m[b][c];
-          racc0[b][c][2] += t.w[2] * m[b][c];
+          racc0[b][c][0] += w01.x * m[b][c];
+          racc0[b][c][1] += w01.y * m[b][c];
+          racc0[b][c][2] += w2 * m[b][c];
         }
     }
     if (NC0 == 2) {
-      const double w = ld_const(tn, 1).w[0];
+      const double w = s_t[4];
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int c = 0; c < 2; ++c) rsum[b][c] += w * m[b][c];
     }
-    // (2) levels r = 1..R: owners restrict from level r-1 and accumulate
+    // (2) levels r = 1..R: owners restrict from level r-1; the slot values
+    // are accumulated below with the taps of the slot's own level
+    double val[2] = {0.0, 0.0};
 #pragma unroll
     for (int r = 1; r <= LTS; ++r) {
       if (r > R) break;
       wave_sync();
-      const TapEntry t0 = ld_const(tn, 2 * r), t1 = ld_const(tn, 2 * r + 1);
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         if (own[i].r != r) continue;
-        const double val = full_weight<2>(s_lv + PD::poff(r - 1), PD::pn(r - 1), own[i].jx, own[i].jy);
-        s_lv[PD::poff(r) + (own[i].jy + 1) * PD::pn(r) + own[i].jx + 1] = val;
+        val[i] = full_weight<2>(s_lv + PD::poff(r - 1), PD::pn(r - 1), own[i].jx, own[i].jy);
+        s_lv[PD::poff(r) + (own[i].jy + 1) * PD::pn(r) + own[i].jx + 1] = val[i];
+      }
+    }
+    // windows that close their oldest time node at this slab
+    const int mv = slab_moves(s_t);
+    if (mv != 0) {
+#pragma unroll
+      for (int r = 1; r <= LTS; ++r) {
+        if (r > R) break;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
+          if (!((mv >> (2 * r + k)) & 1)) continue;
           const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
-          if (!C.active) continue;
-          const TapEntry &t = k == 0 ? t0 : t1;
-          if (t.base >= 0) {
-            A.part[part_at(C, t.base, r, own[i].j)] = racc[i][k][0];
+          const long long base = ld_const(tn, 2 * r + k).base;
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            if (own[i].r != r) continue;
+            A.part[part_at(C, base, r, own[i].j)] = racc[i][k][0];
             racc[i][k][0] = racc[i][k][1];
             racc[i][k][1] = racc[i][k][2];
             racc[i][k][2] = 0.0;
           }
-          racc[i][k][0] += t.w[0] * val;
-          racc[i][k][1] += t.w[1] * val;
-          racc[i][k][2] += t.w[2] * val;
         }
-        if (r == R && use_coarse)
-          A.coarse[((long long)tile * g.ntf + n) * SH::size(r) + own[i].j] = val;
       }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double *t = s_t + tslot[i];
+      const double2 a0 = *reinterpret_cast<const double2 *>(t);
+      const double2 a1 = *reinterpret_cast<const double2 *>(t + 2);
+      const double2 b0 = *reinterpret_cast<const double2 *>(t + 4);
+      const double2 b1 = *reinterpret_cast<const double2 *>(t + 6);
+      racc[i][0][0] += a0.x * val[i];
+      racc[i][0][1] += a0.y * val[i];
+      racc[i][0][2] += a1.x * val[i];
+      racc[i][1][0] += b0.x * val[i];
+      racc[i][1][1] += b0.y * val[i];
+      racc[i][1][2] += b1.x * val[i];
+      if (use_coarse && own[i].r == R)
+        A.coarse[((long long)tile * g.ntf + n) * SH::size(R) + own[i].j] = val[i];
     }
   }
   // final flush of the open time nodes (level-J channels: q0 = 0 throughout)
@@ -1214,8 +1275,10 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
   constexpr int NCI = 2 * (LTS + 1);
   static_assert(NS == 2 && L0 % 64 == 0, "tile shape");
   __shared__ double s_v_w[4][UP];
+  __shared__ __align__(16) double s_t_w[4][4 * NCI];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double *s_v = s_v_w[wave];
+  double *s_t = s_t_w[wave];
 
   const Geometry g = A.g;
   const int nt = g.ntile, ng = (nt + 1) >> 1;
@@ -1293,37 +1356,62 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
   const int pn1 = SH::nodes(1);
   const int plox = tile_lo(TS, tx, 1, 0), ploy = tile_lo(TS, ty, 1, 0);
 
+  // LDS slot of an owned node and the offset of its level's tap entries
+  int sidx[NS], tslot[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const int r = own[i].r;
+    const bool act = r >= 1 && r <= R;
+    sidx[i] = act ? SH::offset(r) - SH::size(0) + own[i].j : -1;
+    tslot[i] = act ? 8 * r : 0;
+  }
+  SlabTaps<NCI> tp;
+  tp.fetch(A.taps, n0, lane);
+
   fetch_co(n0);
   for (int n = n0; n < n1; ++n) {
     const TapEntry *tn = A.taps + (long long)n * NCI;
     double co[NS];
 #pragma unroll
     for (int i = 0; i < NS; ++i) co[i] = cof0[i] >= 0 ? pco[i] : 0.0;
-    if (n + 1 < n1) fetch_co(n + 1);
+    tp.stage(s_t, lane);
+    if (n + 1 < n1) {
+      fetch_co(n + 1);
+      tp.fetch(A.taps, n + 1, lane);
+    }
     wave_sync();
-    // (A) owners evaluate their node in time
+    // (A) owners evaluate their node in time: windows that move on at this
+    // slab shift first, then every slot applies the taps of its own level
+    const int mv = slab_moves(s_t);
+    if (mv != 0) {
 #pragma unroll
-    for (int r = 1; r <= LTS; ++r) {
-      if (r > R) break;
-      const TapEntry t0 = ld_const(tn, 2 * r), t1 = ld_const(tn, 2 * r + 1);
-#pragma unroll
-      for (int i = 0; i < NS; ++i) {
-        if (own[i].r != r) continue;
-        double v = r == R ? co[i] : 0.0;
+      for (int r = 1; r <= LTS; ++r) {
+        if (r > R) break;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
+          if (!((mv >> (2 * r + k)) & 1)) continue;
           const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
-          if (!C.active) continue;
-          const TapEntry &t = k == 0 ? t0 : t1;
-          if (t.base >= 0) {  // the window moves on to q0 = t.base
+          const int q = (int)ld_const(tn, 2 * r + k).base;  // new first time index
+#pragma unroll
+          for (int i = 0; i < NS; ++i) {
+            if (own[i].r != r) continue;
             cw[i][k][0] = cw[i][k][1];
             cw[i][k][1] = cw[i][k][2];
-            cw[i][k][2] = coef(C, (int)t.base + 2, coff[i]);
+            cw[i][k][2] = coef(C, q + 2, coff[i]);
           }
-          v += t.w[0] * cw[i][k][0] + t.w[1] * cw[i][k][1] + t.w[2] * cw[i][k][2];
         }
-        s_v[SH::offset(r) - SH::size(0) + own[i].j] = v;
       }
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const double *t = s_t + tslot[i];
+      const double2 a0 = *reinterpret_cast<const double2 *>(t);
+      const double2 a1 = *reinterpret_cast<const double2 *>(t + 2);
+      const double2 b0 = *reinterpret_cast<const double2 *>(t + 4);
+      const double2 b1 = *reinterpret_cast<const double2 *>(t + 6);
+      const double v = co[i] + a0.x * cw[i][0][0] + a0.y * cw[i][0][1] + a1.x * cw[i][0][2] +
+                       b0.x * cw[i][1][0] + b0.y * cw[i][1][1] + b1.x * cw[i][1][2];
+      if (sidx[i] >= 0) s_v[sidx[i]] = v;
     }
     // (B) top-down interpolation r = R-1 .. 1
 #pragma unroll
@@ -1347,7 +1435,8 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
     wave_sync();
     // (C) fine nodes: bilinear interpolation from level 1, x first; the
     // lane's rows fy0 .. fy0+3 (fy0 even) use level-1 rows r0 .. r0+2
-    const TapEntry tj = ld_const(tn, 0);
+    const double2 tj01 = *reinterpret_cast<const double2 *>(s_t);  // level-J channel
+    const double tj2 = s_t[2];
     double xs[3] = {0.0, 0.0, 0.0};
     if (R >= 1) {
       const int kx = (Px >> 1) - plox, r0 = ((TS * ty + fy0) >> 1) - ploy;
@@ -1362,7 +1451,7 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
 #pragma unroll
     for (int e = 0; e < EF; ++e) {
       const int Py = TS * ty + fy0 + e;
-      const double v = tj.w[0] * rc[e][0] + tj.w[1] * rc[e][1] + tj.w[2] * rc[e][2] + lev[e];
+      const double v = tj01.x * rc[e][0] + tj01.y * rc[e][1] + tj2 * rc[e][2] + lev[e];
       if (interior(Px, g.nxf) && interior(Py, g.nxf)) {
         const long long off = (long long)n * nsp + (long long)(Py - 1) * g.nxf + (Px - 1);
         double o = v + basev[e];
@@ -1405,6 +1494,7 @@ __global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A
   double *s_v = s_v_w[wave];
   double *s_f = s_f_w[wave];
   double (*s_m)[TS * TS] = s_m_w[wave];
+  double *s_t = s_f;  // the slab taps reuse the set-up region
 
   const Geometry g = A.g;
   const int nt = g.ntile, ng = (nt + 1) >> 1;
@@ -1504,37 +1594,62 @@ __global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A
     for (int i = 0; i < NS; ++i) pco[i] = cbase[cof0[i] >= 0 ? (long long)n * nsp0 + cof0[i] : 0];
   };
 
+  // LDS slot of an owned node and the offset of its level's tap entries
+  int sidx[NS], tslot[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const int r = own[i].r;
+    const bool act = r >= 1 && r <= R;
+    sidx[i] = act ? SH::offset(r) - SH::size(0) + own[i].j : -1;
+    tslot[i] = act ? 8 * r : 0;
+  }
+  SlabTaps<NCI> tp;
+  tp.fetch(A.taps, n0, lane);
+
   fetch_co(n0);
   for (int n = n0; n < n1; ++n) {
     const TapEntry *tn = A.taps + (long long)n * NCI;
     double co[NS];
 #pragma unroll
     for (int i = 0; i < NS; ++i) co[i] = cof0[i] >= 0 ? pco[i] : 0.0;
-    if (n + 1 < n1) fetch_co(n + 1);
+    tp.stage(s_t, lane);
+    if (n + 1 < n1) {
+      fetch_co(n + 1);
+      tp.fetch(A.taps, n + 1, lane);
+    }
     wave_sync();
-    // (A) owners evaluate their node in time
+    // (A) owners evaluate their node in time: windows that move on at this
+    // slab shift first, then every slot applies the taps of its own level
+    const int mv = slab_moves(s_t);
+    if (mv != 0) {
 #pragma unroll
-    for (int r = 1; r <= LTS; ++r) {
-      if (r > R) break;
-      const TapEntry t0 = ld_const(tn, 2 * r), t1 = ld_const(tn, 2 * r + 1);
-#pragma unroll
-      for (int i = 0; i < NS; ++i) {
-        if (own[i].r != r) continue;
-        double v = r == R ? co[i] : 0.0;
+      for (int r = 1; r <= LTS; ++r) {
+        if (r > R) break;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
+          if (!((mv >> (2 * r + k)) & 1)) continue;
           const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
-          if (!C.active) continue;
-          const TapEntry &t = k == 0 ? t0 : t1;
-          if (t.base >= 0) {  // the window moves on to q0 = t.base
+          const int q = (int)ld_const(tn, 2 * r + k).base;  // new first time index
+#pragma unroll
+          for (int i = 0; i < NS; ++i) {
+            if (own[i].r != r) continue;
             cw[i][k][0] = cw[i][k][1];
             cw[i][k][1] = cw[i][k][2];
-            cw[i][k][2] = coef(C, (int)t.base + 2, coff[i]);
+            cw[i][k][2] = coef(C, q + 2, coff[i]);
           }
-          v += t.w[0] * cw[i][k][0] + t.w[1] * cw[i][k][1] + t.w[2] * cw[i][k][2];
         }
-        s_v[SH::offset(r) - SH::size(0) + own[i].j] = v;
       }
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const double *t = s_t + tslot[i];
+      const double2 a0 = *reinterpret_cast<const double2 *>(t);
+      const double2 a1 = *reinterpret_cast<const double2 *>(t + 2);
+      const double2 b0 = *reinterpret_cast<const double2 *>(t + 4);
+      const double2 b1 = *reinterpret_cast<const double2 *>(t + 6);
+      const double v = co[i] + a0.x * cw[i][0][0] + a0.y * cw[i][0][1] + a1.x * cw[i][0][2] +
+                       b0.x * cw[i][1][0] + b0.y * cw[i][1][1] + b1.x * cw[i][1][2];
+      if (sidx[i] >= 0) s_v[sidx[i]] = v;
     }
     // (B) top-down interpolation r = R-1 .. 1
 #pragma unroll
@@ -1559,7 +1674,8 @@ __global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A
     // (C) outputs: level-1 stencil plus the level-J channel.  The lane's
     // four rows Py0 .. Py0+3 (Py0 even) use level-1 rows K0-1 .. K0+2,
     // K0 = Py0 / 2; each row is first reduced with the x stencil.
-    const TapEntry tj = ld_const(tn, 0);
+    const double2 tj01 = *reinterpret_cast<const double2 *>(s_t);  // level-J channel
+    const double tj2 = s_t[2];
     double xs[4] = {0.0, 0.0, 0.0, 0.0};
     if (R >= 1) {
       const int r0 = ((TS * ty + fy0) >> 1) - ploy - 1;
@@ -1576,7 +1692,7 @@ __global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A
     for (int e = 0; e < NO; ++e) {
       const int Py = TS * ty + fy0 + e;
       const int po = (fy0 + e) * TS + fx;
-      double val = tj.w[0] * s_m[0][po] + tj.w[1] * s_m[1][po] + tj.w[2] * s_m[2][po] + lev[e];
+      double val = tj01.x * s_m[0][po] + tj01.y * s_m[1][po] + tj2 * s_m[2][po] + lev[e];
       if (xin && interior(Py, g.nxf)) {
         const long long off = (long long)n * nsp + (long long)(Py - 1) * g.nxf + (Pxo - 1);
         if (A.base != nullptr) val += A.base[off - (long long)n * nsp];

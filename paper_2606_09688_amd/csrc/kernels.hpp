@@ -18,6 +18,8 @@ constexpr int kChanMax = 2 * kMaxLevels;
 //   prolongation:  the new first time index q0 if the coefficient window
 //                  moves on by one at this slab, else -1 (the weights include
 //                  the channel sign).
+// Entry 0 (the level-J channel, whose window never moves) holds instead the
+// bit mask of the entries li whose base is set at this slab.
 // One table per pass, [ntf][2 (lts + 1)].
 struct TapEntry {
   double w[3];
