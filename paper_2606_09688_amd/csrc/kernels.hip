@@ -433,6 +433,14 @@ struct SlabTaps {
     if (lane < 4 * NCI) s_t[lane] = next;
   }
 };
+// A per-lane offset the compiler must treat as new in every iteration, so
+// that it adds it to a uniform row pointer where the load happens instead of
+// keeping a hoisted 64-bit address per lane live across the slab loop.
+__device__ __forceinline__ int lane_off(int o) {
+  asm volatile("" : "+v"(o));
+  return o;
+}
+
 // moving-window mask of the staged slab (uniform)
 __device__ __forceinline__ int slab_moves(const double *s_t) {
   return __builtin_amdgcn_readfirstlane((int)__double_as_longlong(s_t[3]));
@@ -538,6 +546,18 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
   int tslot[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) tslot[i] = (own[i].r >= 1 && own[i].r <= R) ? 8 * own[i].r : 0;
+  // slot 0 holds level-1 nodes only; slot 1 any level: the corner of its
+  // full-weighting stencil in the level below, that level's row pitch and
+  // its own entry in the padded LDS layout
+  static_assert(SH::size(1) >= 64, "slot 0 on level 1");
+  int fw1 = 0, pw1 = 0, st1 = 0;
+#pragma unroll
+  for (int r = 1; r <= LTS; ++r)
+    if (own[1].r == r) {
+      pw1 = PD::pn(r - 1);
+      fw1 = PD::poff(r - 1) + 2 * own[1].jy * pw1 + 2 * own[1].jx;
+      st1 = PD::poff(r) + (own[1].jy + 1) * PD::pn(r) + own[1].jx + 1;
+    }
   SlabTaps<NCI> tp;
   tp.fetch(A.taps, n0, lane);
 
@@ -622,11 +642,13 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
     for (int r = 1; r <= LTS; ++r) {
       if (r > R) break;
       wave_sync();
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        if (own[i].r != r) continue;
-        val[i] = full_weight<2>(s_lv + PD::poff(r - 1), PD::pn(r - 1), own[i].jx, own[i].jy);
-        s_lv[PD::poff(r) + (own[i].jy + 1) * PD::pn(r) + own[i].jx + 1] = val[i];
+      if (r == 1) {
+        val[0] = full_weight<2>(s_lv + PD::poff(0), PD::pn(0), own[0].jx, own[0].jy);
+        s_lv[PD::poff(1) + (own[0].jy + 1) * PD::pn(1) + own[0].jx + 1] = val[0];
+      }
+      if (own[1].r == r) {
+        val[1] = full_weight<2>(s_lv + lane_off(fw1), pw1, 0, 0);
+        s_lv[lane_off(st1)] = val[1];
       }
     }
     // windows that close their oldest time node at this slab
@@ -665,7 +687,7 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
       racc[i][1][1] += b0.y * val[i];
       racc[i][1][2] += b1.x * val[i];
       if (use_coarse && own[i].r == R)
-        A.coarse[((long long)tile * g.ntf + n) * SH::size(R) + own[i].j] = val[i];
+        (A.coarse + ((long long)tile * g.ntf + n) * SH::size(R))[lane_off(own[i].j)] = val[i];
     }
   }
   // final flush of the open time nodes (level-J channels: q0 = 0 throughout)
@@ -1314,7 +1336,7 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
   auto coef = [&](const Channel &C, int q, int off) -> double {
     if (off < 0 || q >= C.nq) return 0.0;
     const int na = (1 << C.a) - 1;
-    return C.data[(long long)q * na * na + off];
+    return (C.data + (long long)q * na * na)[lane_off(off)];
   };
   // coefficient windows q0 .. q0+2 of the owned nodes
   double cw[NS][2][3];
@@ -1350,8 +1372,9 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
   const double *cbase = use_coarse ? A.coarse : A.safe_w;
   double pco[NS];
   auto fetch_co = [&](int n) {
+    const double *row = cbase + (use_coarse ? (long long)n * nsp0 : 0);
 #pragma unroll
-    for (int i = 0; i < NS; ++i) pco[i] = cbase[cof0[i] >= 0 ? (long long)n * nsp0 + cof0[i] : 0];
+    for (int i = 0; i < NS; ++i) pco[i] = row[lane_off(max(cof0[i], 0))];
   };
   const int pn1 = SH::nodes(1);
   const int plox = tile_lo(TS, tx, 1, 0), ploy = tile_lo(TS, ty, 1, 0);
@@ -1531,7 +1554,7 @@ __global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A
   auto coef = [&](const Channel &C, int q, int off) -> double {
     if (off < 0 || q >= C.nq) return 0.0;
     const int na = (1 << C.a) - 1;
-    return C.data[(long long)q * na * na + off];
+    return (C.data + (long long)q * na * na)[lane_off(off)];
   };
   double cw[NS][2][3];
 #pragma unroll
@@ -1590,8 +1613,9 @@ __global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A
   const double *cbase = use_coarse ? A.coarse : A.safe_w;
   double pco[NS];
   auto fetch_co = [&](int n) {
+    const double *row = cbase + (use_coarse ? (long long)n * nsp0 : 0);
 #pragma unroll
-    for (int i = 0; i < NS; ++i) pco[i] = cbase[cof0[i] >= 0 ? (long long)n * nsp0 + cof0[i] : 0];
+    for (int i = 0; i < NS; ++i) pco[i] = row[lane_off(max(cof0[i], 0))];
   };
 
   // LDS slot of an owned node and the offset of its level's tap entries
