@@ -451,7 +451,12 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
   if (!x_out) x_out = p->bufU;
   std::vector<GemmDesc> vx, vy, viy, vix;
   int tx = 0, ty = 0, tiy = 0, tix = 0;
-  for (int ci : cset) {
+  // the finest spatial levels (longest K loops) first: their tiles are
+  // dispatched at once and the many short tiles of coarse levels fill in
+  std::vector<int> order(cset);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int u, int v) { return p->comps[u].a > p->comps[v].a; });
+  for (int ci : order) {
     if (p->blockc[ci]) continue;
     const Comp &C = p->comps[ci];
     // 2-D variable speed: one dense transform over the flat spatial index,
