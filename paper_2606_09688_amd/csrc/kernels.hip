@@ -441,6 +441,10 @@ __device__ __forceinline__ int lane_off(int o) {
   return o;
 }
 
+// Materialise a loaded value at this point of the program (the empty asm is
+// ordered with the stores around it, so the wait for the load lands here).
+__device__ __forceinline__ void take(double &v) { asm volatile("" : "+v"(v)); }
+
 // moving-window mask of the staged slab (uniform)
 __device__ __forceinline__ int slab_moves(const double *s_t) {
   return __builtin_amdgcn_readfirstlane((int)__double_as_longlong(s_t[3]));
@@ -1391,13 +1395,22 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
   SlabTaps<NCI> tp;
   tp.fetch(A.taps, n0, lane);
 
+  // the coarse values and taps of slab n + 1 are taken over at the end of
+  // slab n, before its stores: loads and stores share one completion counter,
+  // so a store issued just before a wait for loads would hold that wait up
+  double co[NS];
+  auto take_next = [&]() {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      co[i] = cof0[i] >= 0 ? pco[i] : 0.0;
+      take(co[i]);
+    }
+    tp.stage(s_t, lane);
+  };
   fetch_co(n0);
+  take_next();
   for (int n = n0; n < n1; ++n) {
     const TapEntry *tn = A.taps + (long long)n * NCI;
-    double co[NS];
-#pragma unroll
-    for (int i = 0; i < NS; ++i) co[i] = cof0[i] >= 0 ? pco[i] : 0.0;
-    tp.stage(s_t, lane);
     if (n + 1 < n1) {
       fetch_co(n + 1);
       tp.fetch(A.taps, n + 1, lane);
@@ -1421,6 +1434,7 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
             cw[i][k][0] = cw[i][k][1];
             cw[i][k][1] = cw[i][k][2];
             cw[i][k][2] = coef(C, q + 2, coff[i]);
+            take(cw[i][k][2]);  // waited for here, on the rare path
           }
         }
       }
@@ -1460,6 +1474,8 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
     // lane's rows fy0 .. fy0+3 (fy0 even) use level-1 rows r0 .. r0+2
     const double2 tj01 = *reinterpret_cast<const double2 *>(s_t);  // level-J channel
     const double tj2 = s_t[2];
+    if (n + 1 < n1) take_next();  // before this slab's stores
+    wave_sync();
     double xs[3] = {0.0, 0.0, 0.0};
     if (R >= 1) {
       const int kx = (Px >> 1) - plox, r0 = ((TS * ty + fy0) >> 1) - ploy;
@@ -1630,13 +1646,22 @@ __global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A
   SlabTaps<NCI> tp;
   tp.fetch(A.taps, n0, lane);
 
+  // the coarse values and taps of slab n + 1 are taken over at the end of
+  // slab n, before its stores: loads and stores share one completion counter,
+  // so a store issued just before a wait for loads would hold that wait up
+  double co[NS];
+  auto take_next = [&]() {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      co[i] = cof0[i] >= 0 ? pco[i] : 0.0;
+      take(co[i]);
+    }
+    tp.stage(s_t, lane);
+  };
   fetch_co(n0);
+  take_next();
   for (int n = n0; n < n1; ++n) {
     const TapEntry *tn = A.taps + (long long)n * NCI;
-    double co[NS];
-#pragma unroll
-    for (int i = 0; i < NS; ++i) co[i] = cof0[i] >= 0 ? pco[i] : 0.0;
-    tp.stage(s_t, lane);
     if (n + 1 < n1) {
       fetch_co(n + 1);
       tp.fetch(A.taps, n + 1, lane);
@@ -1660,6 +1685,7 @@ __global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A
             cw[i][k][0] = cw[i][k][1];
             cw[i][k][1] = cw[i][k][2];
             cw[i][k][2] = coef(C, q + 2, coff[i]);
+            take(cw[i][k][2]);  // waited for here, on the rare path
           }
         }
       }
@@ -1700,6 +1726,8 @@ __global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A
     // K0 = Py0 / 2; each row is first reduced with the x stencil.
     const double2 tj01 = *reinterpret_cast<const double2 *>(s_t);  // level-J channel
     const double tj2 = s_t[2];
+    if (n + 1 < n1) take_next();  // before this slab's stores
+    wave_sync();
     double xs[4] = {0.0, 0.0, 0.0, 0.0};
     if (R >= 1) {
       const int r0 = ((TS * ty + fy0) >> 1) - ploy - 1;
