@@ -565,15 +565,20 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
   SlabTaps<NCI> tp;
   tp.fetch(A.taps, n0, lane);
 
-  fetch(n0);
-  for (int n = n0; n < n1; ++n) {
-    wave_sync();
+  // the input and taps of slab n + 1 are staged at the end of slab n, before
+  // its stores: loads and stores share one completion counter, so a store
+  // issued just before a wait for loads would hold that wait up
+  auto stage_next = [&]() {
 #pragma unroll
     for (int e = 0; e < PF; ++e) {
       const int idx = lane + 64 * e;
       if (idx < INSZ) s_in[idx] = pos[e] >= 0 ? pin[e] : 0.0;
     }
     tp.stage(s_t, lane);
+  };
+  fetch(n0);
+  stage_next();
+  for (int n = n0; n < n1; ++n) {
     if (n + 1 < n1) {
       fetch(n + 1);
       tp.fetch(A.taps, n + 1, lane);
@@ -690,8 +695,14 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
       racc[i][1][0] += b0.x * val[i];
       racc[i][1][1] += b0.y * val[i];
       racc[i][1][2] += b1.x * val[i];
-      if (use_coarse && own[i].r == R)
-        (A.coarse + ((long long)tile * g.ntf + n) * SH::size(R))[lane_off(own[i].j)] = val[i];
+    }
+    if (n + 1 < n1) stage_next();
+    wave_sync();
+    if (use_coarse) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        if (own[i].r == R)
+          (A.coarse + ((long long)tile * g.ntf + n) * SH::size(R))[lane_off(own[i].j)] = val[i];
     }
   }
   // final flush of the open time nodes (level-J channels: q0 = 0 throughout)
