@@ -250,6 +250,8 @@ sg_status build_pass(sg_problem *p, Pass &P, const Geometry &geo, F spec,
       const int na = (1 << a) - 1;
       const long long nspa = geo.d == 2 ? (long long)na * na : na;
       const long long cntw = (long long)cs.nq * nspa;
+      if (cntw >= (1LL << 31))  // the gather kernels index a channel in 32 bits
+        return fail(SG_ENOTSUP, "component too large for 32-bit channel indexing");
       const int r = J - a;
       if (a >= geo.A0) {
         // partial block capacity: max over chunks of touched time nodes
@@ -959,6 +961,8 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
     }
     if (nsp0 > kCoarseMax)
       return bail(fail(SG_ENOTSUP, "level too fine for the coarse-level pyramid"));
+    if (ntf * nsp0 >= (1LL << 31))  // the coarse kernels index slabs in 32 bits
+      return bail(fail(SG_ENOTSUP, "too many time slabs for the coarse-level arrays"));
     if (!(p->cpart = p->dalloc<double>(need)) || !(p->S0 = p->dalloc<double>(ntf * nsp0)) ||
         !(p->SL = p->dalloc<double>(std::max(1LL, ntf * ncl))) ||
         !(p->Cpro = p->dalloc<double>(ntf * nsp0)))

@@ -767,11 +767,12 @@ __global__ void k_reduce(const Geometry g, const Channel *__restrict__ ch,
   const long long loc = gid - items[it].start;
   const int a = C.a, r = g.J - a;
   const int na = (1 << a) - 1;
-  const long long nsp = (D == 2) ? (long long)na * na : na;
-  const int q = (int)(loc / nsp);
-  const long long K = loc - (long long)q * nsp;
-  const int Px = (int)(K % na) + 1;
-  const int Py = (D == 2) ? (int)(K / na) + 1 : 0;
+  // 32-bit index arithmetic: a channel holds fewer than 2^31 coefficients
+  const int nsp = (D == 2) ? na * na : na;
+  const int q = (int)loc / nsp;
+  const int K = (int)loc - q * nsp;
+  const int Py = (D == 2) ? K / na + 1 : 0;
+  const int Px = (D == 2) ? K - (Py - 1) * na + 1 : K + 1;
   const int nr = SH::nodes(r), sz = SH::size(r);
   const int ntileD = (D == 2) ? g.ntile * g.ntile : g.ntile;
   int tx0, tx1, ty0 = 0, ty1 = 0;
@@ -805,13 +806,13 @@ template <int D>
 __global__ void k_coarse_assemble(const Geometry g, const double *__restrict__ cp,
                                   double *__restrict__ S0) {
   const int na = (1 << g.A0) - 1;
-  const long long nsp = (D == 2) ? (long long)na * na : na;
+  const int nsp = (D == 2) ? na * na : na;
   const long long gid = gid64();
-  if (gid >= nsp * g.ntf) return;
-  const int n = (int)(gid / nsp);
-  const long long K = gid - (long long)n * nsp;
-  const int Px = (int)(K % na) + 1;
-  const int Py = (D == 2) ? (int)(K / na) + 1 : 0;
+  if (gid >= (long long)nsp * g.ntf) return;
+  const int n = (int)gid / nsp;  // level-A0 slabs hold fewer than 2^31 values
+  const int K = (int)gid - n * nsp;
+  const int Py = (D == 2) ? K / na + 1 : 0;
+  const int Px = (D == 2) ? K - (Py - 1) * na + 1 : K + 1;
   constexpr int SZ = (D == 2) ? 4 : 2;
   double acc = 0.0;
   for (int ty = (D == 2 ? Py - 1 : 0); ty <= (D == 2 ? Py : 0); ++ty) {
@@ -900,9 +901,9 @@ __global__ void k_coarse_restrict(const Geometry g, const Channel *__restrict__ 
   const long long loc = gid - items[it].start;
   const int a = C.a;
   const int na = (1 << a) - 1;
-  const long long nsp = (D == 2) ? (long long)na * na : na;
-  const int q = (int)(loc / nsp);
-  const long long K = loc - (long long)q * nsp;
+  const int nsp = (D == 2) ? na * na : na;
+  const int q = (int)loc / nsp;  // coarse channels hold fewer than 2^31 values
+  const int K = (int)loc - q * nsp;
   const long long tot = coarse_off(D, g.A0), off = coarse_off(D, a) + K;
   const int nlo = lower_bound_q(C.q0, g.ntf, q - 2);
   const int nhi = lower_bound_q(C.q0, g.ntf, q + 1);  // exclusive
@@ -923,20 +924,20 @@ template <int D>
 __global__ void k_prolong_coarse(const Geometry g, const Channel *__restrict__ ch,
                                  double *__restrict__ Cout) {
   const int n0a = (1 << g.A0) - 1;
-  const long long nsp0 = (D == 2) ? (long long)n0a * n0a : n0a;
+  const int nsp0 = (D == 2) ? n0a * n0a : n0a;
   const long long gid = gid64();
-  if (gid >= nsp0 * g.ntf) return;
-  const int n = (int)(gid / nsp0);
-  const long long K0 = gid - (long long)n * nsp0;
-  const int P0x = (int)(K0 % n0a) + 1;
-  const int P0y = (D == 2) ? (int)(K0 / n0a) + 1 : 0;
+  if (gid >= (long long)nsp0 * g.ntf) return;
+  const int n = (int)gid / nsp0;  // level-A0 slabs hold fewer than 2^31 values
+  const int K0 = (int)gid - n * nsp0;
+  const int P0y = (D == 2) ? K0 / n0a + 1 : 0;
+  const int P0x = (D == 2) ? K0 - (P0y - 1) * n0a + 1 : K0 + 1;
   double acc = 0.0;
   for (int a = 1; a < g.A0; ++a) {
-    const int f = 1 << (g.A0 - a);
+    const int sh = g.A0 - a, f = 1 << sh;
     const int na = (1 << a) - 1;
-    const int Lx = P0x / f, rx = P0x - Lx * f;
+    const int Lx = P0x >> sh, rx = P0x & (f - 1);
     const double fx = (double)rx / f;
-    const int Ly = (D == 2) ? P0y / f : 0, ry = (D == 2) ? P0y - Ly * f : 0;
+    const int Ly = (D == 2) ? P0y >> sh : 0, ry = (D == 2) ? P0y & (f - 1) : 0;
     const double fy = (double)ry / f;
     for (int k = 0; k < 2; ++k) {
       const Channel &C = ch[(a - 1) * 2 + k];
@@ -1839,8 +1840,8 @@ __global__ void k_post_load(const CompDesc *__restrict__ cd, int ncomp, long lon
   if (gid >= total) return;
   const CompDesc &C = cd[find_comp(cd, ncomp, gid)];
   const long long loc = gid - C.start;
-  const int i = (int)(loc / C.nsp);
-  const long long K = loc - (long long)i * C.nsp;
+  const int i = (int)loc / C.nsp;  // a component holds fewer than 2^31 values
+  const int K = (int)loc - i * C.nsp;
   const double *Z = C.z;
   double v = kt->Dlo[C.b][i] * Z[loc];
   if (i + 1 < C.nq) v += kt->Dhi[C.b][i] * Z[loc + C.nsp];
@@ -1856,7 +1857,7 @@ __global__ void k_post_adjoint(const CompDesc *__restrict__ cd, int ncomp,
   if (gid >= total) return;
   const CompDesc &C = cd[find_comp(cd, ncomp, gid)];
   const long long loc = gid - C.start;
-  const int q = (int)(loc / C.nsp);
+  const int q = (int)loc / C.nsp;  // a component holds fewer than 2^31 values
   double v = kt->Dlo[C.b][q] * C.z[loc];
   if (q >= 1) v += kt->Dhi[C.b][q - 1] * C.z[loc - C.nsp];
   C.data[loc] = v;
