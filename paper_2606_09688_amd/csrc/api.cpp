@@ -153,7 +153,7 @@ struct sg_problem {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int refine_nq = 33;
-  int wave_nq = 65;                // time levels with nq >= wave_nq: one wave per mode
+  int wave_nq = 33;                // time levels with nq >= wave_nq: one wave per mode
   // optional stage events; during capture the dependencies at each mark
   std::vector<hipEvent_t> ev;
   bool capturing = false;
