@@ -168,6 +168,29 @@ sg_status sg_host_time_level(int b, double T, double *A, double *Alo, double *B,
                              double *Blo, double *Dlo, double *Dhi, double *g);
 sg_status sg_host_taps(int kind, int b, int J, double T, int *q0, double *w);
 
+/*
+ * Energy of the computed solution (Sec. 6.3, the energy diagnostic):
+ *   E(t) = 1/2 ||d_t u_h(t)||^2_{L2(Omega)} + 1/2 ||c grad u_h(t)||^2_{L2(Omega)}
+ * for u_h = u^CF + u0, the lifted combination solution of the last sg_solve
+ * (or sg_solve_plain) on this handle: its component solutions stay in the
+ * handle's workspace until the next forward solve (sg_adjoint does not touch
+ * them).  u_h(t) is a P1 / Q1 function on the finest mesh, so the integrals
+ * are exact (element mass and stiffness forms with the per-block c^2).
+ *
+ * sg_energy_setup: K >= 1 instants t (host array) in [0, T], ascending, no
+ *   two consecutive instants more than one finest time interval T / 2^J
+ *   apart (a uniform grid of at least 2^J + 1 instants qualifies; SG_EINVAL
+ *   otherwise).  Builds the evaluation tables (spline values and derivatives
+ *   of every time level at the instants) and allocates the workspace (two
+ *   K x n^d arrays, about 16 K n^d bytes); synchronises the device; replaces
+ *   and frees an earlier setup.  SG_ENOMEM if the workspace does not fit.
+ * sg_energy: u0 as given to the forward solve (device, fine space array),
+ *   E device array of K doubles (caller-owned).  Stream ordered; allocates
+ *   nothing.  SG_ESTATE without a setup.
+ */
+sg_status sg_energy_setup(sg_problem *p, int K, const double *t);
+sg_status sg_energy(sg_problem *p, const double *u0, double *E, hipStream_t stream);
+
 /* Release the handle and all device memory it owns.  NULL is accepted. */
 sg_status sg_destroy(sg_problem *p);
 

@@ -358,6 +358,45 @@ def combined_at(prob, sols, tq, xqs, u0_fn=None):
     return out
 
 
+def solution_at(prob, sols, u0, times, deriv=0):
+    """Nodal values on the finest grid of u_h(t) = u0 + sum_c s_c u_c(., t)
+    (deriv = 0) or of d_t u_h(t) (deriv = 1) at the instants ``times``, shape
+    (len(times), n^d).  Spline values/derivatives at arbitrary t from the
+    B-spline recursion, the nested spatial prolongation Phi_{jx -> J}."""
+    from . import basis
+    t = np.atleast_1d(np.asarray(times, dtype=np.float64))
+    out = np.zeros((t.size, prob.ns_fine))
+    if deriv == 0:
+        out += np.asarray(u0, dtype=np.float64).reshape(1, prob.ns_fine)
+    for (jx, jt, s), u in zip(prob.comps, sols):
+        Pt = basis.time_basis(jt, prob.T, t, deriv)           # (K, n_time)
+        uc = np.asarray(u).reshape(Pt.shape[1], -1)            # (n_time, n_space)
+        P = space.interp(jx, prob.J, prob.medium)              # (NS, n_space)
+        out += s * np.asarray((P @ (Pt @ uc).T).T)
+    return out
+
+
+def energy(prob, sols, u0, times):
+    """Energy of the computed solution at the given instants (Sec. 6.3):
+
+        E(t) = 1/2 ||d_t u_h(t)||^2 + 1/2 ||c grad u_h(t)||^2,
+
+    u_h = u0 + sum_c s_c u_c the lifted combination solution.  For fixed t,
+    u_h(t) and d_t u_h(t) are P1/Q1 functions on the finest mesh (the spaces
+    are nested), so with their nodal values w and v the integrals are exactly
+    1/2 v^T M_J v + 1/2 w^T K_J w (K_J exact in c^2; hi + lo in 1-D)."""
+    W = solution_at(prob, sols, u0, times, 0)
+    V = solution_at(prob, sols, u0, times, 1)
+    M = space.mass(prob.J, prob.medium)
+    K = space.stiff(prob.J, prob.medium)
+    Klo = space.stiff_lo(prob.J, prob.medium)
+    KW = np.asarray((K @ W.T).T)
+    if Klo is not None:
+        KW = KW + np.asarray((Klo @ W.T).T)
+    MV = np.asarray((M @ V.T).T)
+    return 0.5 * np.sum(V * MV, axis=1) + 0.5 * np.sum(W * KW, axis=1)
+
+
 def l2_error(prob, sols, u_fn, u0_fn=None, comps=None):
     """(||u - u_h||, ||u||) in L^2(Q_T) by Gauss quadrature on the finest mesh.
 

@@ -9,6 +9,7 @@ not FP64 device tensors, the calls raise.
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -51,6 +52,8 @@ SIGNATURES = {
     "sg_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sg_set_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                      ctypes.c_int]),
+    "sg_energy_setup": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_dp]),
+    "sg_energy": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "sg_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sg_last_error": (ctypes.c_char_p, []),
 }
@@ -251,6 +254,25 @@ class SparseGridWave:
             _ptr(g, self.shape, "g", True), _ptr(df, self.shape, "df", True),
             _ptr(du0, self.space_shape, "du0", True),
             _ptr(dv0, self.space_shape, "dv0", True), _stream(s)), "sg_graph_capture")
+
+    def energy_setup(self, times):
+        """Prepare sg_energy at the given instants (ascending, in [0, T], no two
+        consecutive ones more than one finest time interval apart)."""
+        t = np.ascontiguousarray(np.asarray(times, dtype=np.float64).ravel())
+        check(lib().sg_energy_setup(self._h, int(t.size), t.ctypes.data_as(_c_dp)),
+              "sg_energy_setup")
+        self._energy_k = int(t.size)
+
+    def energy(self, u0, out=None, stream=None):
+        """E(t_k) = 1/2 ||d_t u_h||^2 + 1/2 ||c grad u_h||^2 at the instants of
+        energy_setup, for u_h the lifted solution of the last solve (u0 as given
+        to it)."""
+        k = getattr(self, "_energy_k", 0)
+        if out is None:
+            out = torch.empty(max(k, 1), dtype=torch.float64, device=u0.device)[:k]
+        check(lib().sg_energy(self._h, _ptr(u0, self.space_shape, "u0"), _ptr(out, (k,), "E"),
+                              _stream(stream)), "sg_energy")
+        return out
 
     def set_events(self, events):
         """Record the SG_NUM_EVENTS stage events (torch.cuda.Event list) or None."""

@@ -134,6 +134,13 @@ struct sg_problem {
   double *Cpro = nullptr;          // prolongation coarse array
   // passes
   Pass load, prol, adjr, adjp, fieldr, fieldp;
+  int prol_target = 0, prol_ts = 0;  // grid sizing of the prolongations
+  // energy diagnostic (sg_energy_setup / sg_energy); its device memory is
+  // owned separately and released by the next setup
+  int eK = 0, enblk = 0;
+  Pass eval, eder;
+  double *eU = nullptr, *eUt = nullptr, *epart = nullptr, *ecpro = nullptr;
+  std::vector<void *> eallocs;
   std::vector<Pass> plain_load, plain_prol;
   // descriptor lists
   GemmList gx, gy, giy, gix;       // fused (all components)
@@ -415,7 +422,9 @@ sg_status run_restrict(sg_problem *p, const Pass &P, const double *X, int stenci
 }
 
 sg_status run_prolong(sg_problem *p, const Pass &P, const double *base, double *out,
-                      int accumulate, int stencil, hipStream_t s, int ev_begin = -1) {
+                      int accumulate, int stencil, hipStream_t s, int ev_begin = -1,
+                      double *cpro = nullptr) {
+  if (!cpro) cpro = p->Cpro;  // [ntf][level-A0 nodes] of the pass
   const Geometry &g = P.geo;
   ProlongArgs pa{};
   pa.g = g;
@@ -428,8 +437,8 @@ sg_status run_prolong(sg_problem *p, const Pass &P, const double *base, double *
     }
   pa.coarse = nullptr;
   if (g.A0 > 1 && P.n_crs) {
-    HIPCHK(launch_prolong_coarse(g, P.d_ch, p->Cpro, stencil, s));
-    pa.coarse = p->Cpro;
+    HIPCHK(launch_prolong_coarse(g, P.d_ch, cpro, stencil, s));
+    pa.coarse = cpro;
   }
   pa.taps = P.d_taps;
   pa.base = base;
@@ -583,6 +592,7 @@ sg_status sg_destroy(sg_problem *p) {
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   for (void *a : p->allocs) (void)hipFree(a);
+  for (void *a : p->eallocs) (void)hipFree(a);
   (void)hipSetDevice(cur);
   delete p;
   return SG_OK;
@@ -862,6 +872,8 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   if (const char *e = getenv("SG_PROL_WG")) pwg = std::max(1, atoi(e));
   if (const char *e = getenv("SG_PROLM_WG")) pmwg = std::max(1, atoi(e));
   const Geometry geop = w16 ? make_geometry(d, J, ntf, 4 * pwg * ncu, 16) : geo;
+  p->prol_target = w16 ? 4 * pwg * ncu : chunk_wg;
+  p->prol_ts = w16 ? 16 : 0;
   const Geometry geom = w16 ? make_geometry(d, J, ntf, 4 * pmwg * ncu, 16) : geo;
   const Geometry geof = make_geometry(d, J, 2, 1);
   long long part_need = 0;
@@ -1193,6 +1205,102 @@ sg_status sg_adjoint(sg_problem *p, const double *g, double *df, double *du0, do
                                 dv0, du0, p->gsum, 1, s));
   }
   MARK(p, 14, s);
+  return SG_OK;
+}
+
+sg_status sg_energy_setup(sg_problem *p, int K, const double *times) {
+  if (!p) return fail(SG_EINVAL, "NULL handle");
+  if (K < 1 || !times) return fail(SG_EINVAL, "need K >= 1 instants");
+  const std::vector<double> t(times, times + K);
+  for (int k = 0; k < K; ++k) {
+    if (!(t[k] >= 0.0 && t[k] <= p->T)) return fail(SG_EINVAL, "instants must lie in [0, T]");
+    if (k > 0 && t[k] < t[k - 1]) return fail(SG_EINVAL, "instants must be ascending");
+  }
+  // release an earlier setup
+  HIPCHK(hipDeviceSynchronize());
+  for (void *a : p->eallocs) (void)hipFree(a);
+  p->eallocs.clear();
+  p->eK = 0;
+  p->eval = Pass{};
+  p->eder = Pass{};
+  // spline values and derivatives of every time level at the instants; the
+  // streaming prolongation moves a coefficient window on by at most one
+  // time node per slab
+  std::map<int, Taps> tv, td;
+  for (const Comp &C : p->comps) {
+    if (tv.count(C.b)) continue;
+    tv[C.b] = spline_taps_at(C.b, p->T, t, 0);
+    td[C.b] = spline_taps_at(C.b, p->T, t, 1);
+    const std::vector<int> &q = tv[C.b].q0;
+    for (int k = 1; k < K; ++k)
+      if (q[k] - q[k - 1] > 1)
+        return fail(SG_EINVAL, "consecutive instants more than one finest time interval apart");
+  }
+  // device memory of the setup is kept apart from the handle's own
+  struct Swap {
+    sg_problem *p;
+    ~Swap() { std::swap(p->allocs, p->eallocs); }
+  } swap_back{p};
+  std::swap(p->allocs, p->eallocs);
+  std::map<int, const int *> dq0;
+  std::map<int, const double *> dwv, dwd;
+  sg_status st;
+  for (auto &kv : tv) {
+    int *q = nullptr;
+    double *wv = nullptr, *wd = nullptr;
+    if ((st = upload(p, kv.second.q0, &q)) || (st = upload(p, kv.second.w, &wv)) ||
+        (st = upload(p, td[kv.first].w, &wd)))
+      return st;
+    dq0[kv.first] = q;
+    dwv[kv.first] = wv;
+    dwd[kv.first] = wd;
+  }
+  const int J = p->J;
+  const Geometry ge = make_geometry(p->d, J, K, p->prol_target, p->prol_ts);
+  auto spec = [&](bool deriv) {
+    return [&, deriv](int a, int k) {
+      ChanSpec cs;
+      const int ci = k == 0 ? a - 1 : (a <= J - 1 ? J + a - 1 : -1);
+      if (ci < 0) return cs;
+      const Comp &C = p->comps[ci];
+      cs.active = 1;
+      cs.nq = C.nq;
+      cs.q0 = dq0[C.b];
+      cs.w = deriv ? dwd[C.b] : dwv[C.b];
+      cs.hq0 = &tv[C.b].q0;
+      cs.hw = deriv ? &td[C.b].w : &tv[C.b].w;
+      cs.data = p->bufU + C.off;
+      cs.scale = (double)C.sign;
+      return cs;
+    };
+  };
+  long long part_unused = 0;
+  if ((st = build_pass(p, p->eval, ge, spec(false), &part_unused, true)) ||
+      (st = build_pass(p, p->eder, ge, spec(true), &part_unused, true)))
+    return st;
+  const long long nel = p->d == 2 ? (long long)p->N * p->N : p->N;
+  p->enblk = (int)std::min<long long>(64, (nel + 255) / 256);
+  const long long n0a = (1LL << ge.A0) - 1;
+  const long long nsp0 = p->d == 2 ? n0a * n0a : n0a;
+  if (!(p->eU = p->dalloc<double>((size_t)K * p->nsp_fine)) ||
+      !(p->eUt = p->dalloc<double>((size_t)K * p->nsp_fine)) ||
+      !(p->epart = p->dalloc<double>((size_t)K * p->enblk)) ||
+      !(p->ecpro = p->dalloc<double>(ge.A0 > 1 ? (size_t)K * nsp0 : 1)))
+    return fail(SG_ENOMEM, "hipMalloc of the energy workspace failed");
+  p->eK = K;
+  return SG_OK;
+}
+
+sg_status sg_energy(sg_problem *p, const double *u0, double *E, hipStream_t s) {
+  if (!p) return fail(SG_EINVAL, "NULL handle");
+  if (p->eK == 0) return fail(SG_ESTATE, "sg_energy needs sg_energy_setup first");
+  if (!u0 || !E) return fail(SG_EINVAL, "NULL data pointer");
+  sg_status st;
+  if ((st = run_prolong(p, p->eval, u0, p->eU, 0, 0, s, -1, p->ecpro))) return st;
+  if ((st = run_prolong(p, p->eder, nullptr, p->eUt, 0, 0, s, -1, p->ecpro))) return st;
+  const double hx = p->len[0] / p->N, hy = (p->d == 2 ? p->len[1] : 1.0) / p->N;
+  HIPCHK(launch_energy(p->d, p->N, p->d_ce, hx, hy, p->eU, p->eUt, p->eK, p->enblk, p->epart,
+                       E, s));
   return SG_OK;
 }
 

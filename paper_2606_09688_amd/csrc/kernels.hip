@@ -1827,6 +1827,83 @@ __global__ void k_fine_stencils(int N, const double *__restrict__ ce, double hx,
   }
 }
 
+// Energy of finest-mesh functions, slab by slab (Sec. 6.3): for slab k,
+//   E_k = 1/2 int (ut_k)^2 dx + 1/2 int c^2 |grad w_k|^2 dx
+// with ut_k, w_k the P1 (d=1) / Q1 (d=2) functions of the nodal values
+// Ut[k], W[k] (zero on the boundary), integrated exactly element by element
+// (every element term is a positive semi-definite form, so no cancellation
+// between elements).  Grid (nblk, K): each block sums a fixed set of
+// elements in a fixed tree order into part[k][blk].
+template <int D>
+__global__ void __launch_bounds__(256) k_energy_part(int N, const double *__restrict__ ce,
+                                                     double hx, double hy,
+                                                     const double *__restrict__ W,
+                                                     const double *__restrict__ Ut,
+                                                     double *__restrict__ part) {
+  __shared__ double s_red[256];
+  const int n = N - 1;
+  const long long nsp = (D == 2) ? (long long)n * n : n;
+  const int k = blockIdx.y;
+  const double *w = W + (long long)k * nsp, *ut = Ut + (long long)k * nsp;
+  const long long nel = (D == 2) ? (long long)N * N : N;
+  auto at = [&](const double *f, int x, int y) -> double {
+    if (!interior(x, n) || (D == 2 && !interior(y, n))) return 0.0;
+    return f[(D == 2 ? (long long)(y - 1) * n : 0) + (x - 1)];
+  };
+  double acc = 0.0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nel;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int ex = (D == 2) ? (int)(e % N) : (int)e, ey = (D == 2) ? (int)(e / N) : 0;
+    const double c2 = ce[e];
+    if (D == 1) {
+      const double u0 = at(ut, ex, 0), u1 = at(ut, ex + 1, 0);
+      const double w0 = at(w, ex, 0), w1 = at(w, ex + 1, 0);
+      // mass h/6 [2 1; 1 2], stiffness c^2/h [1 -1; -1 1]
+      acc += 0.5 * (hx / 6.0 * (2.0 * u0 * u0 + 2.0 * u0 * u1 + 2.0 * u1 * u1) +
+                    c2 / hx * (w1 - w0) * (w1 - w0));
+    } else {
+      double u[2][2], v[2][2];
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          u[cy][cx] = at(ut, ex + cx, ey + cy);
+          v[cy][cx] = at(w, ex + cx, ey + cy);
+        }
+      // Q1 element forms with the 1-D mass m = h/6 [2 1; 1 2] and stiffness
+      // k = 1/h [1 -1; -1 1]: mass m_y (x) m_x, stiffness c^2 (m_y (x) k_x + k_y (x) m_x)
+      auto m1 = [](double a, double b) { return 2.0 * a * a + 2.0 * a * b + 2.0 * b * b; };
+      auto mx2 = [](double a0, double a1, double b0, double b1) {  // a^T m b (unscaled)
+        return 2.0 * a0 * b0 + a0 * b1 + a1 * b0 + 2.0 * a1 * b1;
+      };
+      // int ut^2 = (hx/6)(hy/6) sum_{ij} my_{ij} (u_i^T mx u_j), rows i = cy
+      const double mass = hx / 6.0 * hy / 6.0 *
+                          (2.0 * m1(u[0][0], u[0][1]) + 2.0 * m1(u[1][0], u[1][1]) +
+                           2.0 * mx2(u[0][0], u[0][1], u[1][0], u[1][1]));
+      // x derivatives per row, y derivatives per column
+      const double gx0 = v[0][1] - v[0][0], gx1 = v[1][1] - v[1][0];
+      const double gy0 = v[1][0] - v[0][0], gy1 = v[1][1] - v[0][1];
+      const double kx = (hy / 6.0) / hx * (2.0 * gx0 * gx0 + 2.0 * gx0 * gx1 + 2.0 * gx1 * gx1);
+      const double ky = (hx / 6.0) / hy * (2.0 * gy0 * gy0 + 2.0 * gy0 * gy1 + 2.0 * gy1 * gy1);
+      acc += 0.5 * (mass + c2 * (kx + ky));
+    }
+  }
+  s_red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (threadIdx.x < h) s_red[threadIdx.x] += s_red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long long)k * gridDim.x + blockIdx.x] = s_red[0];
+}
+
+__global__ void k_energy_sum(int K, int nblk, const double *__restrict__ part,
+                             double *__restrict__ E) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(long long)k * nblk + b];
+  E[k] = s;
+}
+
 __device__ __forceinline__ int find_comp(const CompDesc *cd, int ncomp, long long gid) {
   int c = 0;
   while (c + 1 < ncomp && cd[c + 1].start <= gid) ++c;
@@ -2745,6 +2822,19 @@ hipError_t launch_prolong(const ProlongArgs &a, hipStream_t s) {
     }
   }
 #undef SG_PROLONG
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(int d, int N, const double *ce, double hx, double hy, const double *W,
+                         const double *Ut, int K, int nblk, double *part, double *E,
+                         hipStream_t s) {
+  if (K <= 0) return hipSuccess;
+  const dim3 grid(nblk, K);
+  if (d == 2)
+    hipLaunchKernelGGL(k_energy_part<2>, grid, dim3(256), 0, s, N, ce, hx, hy, W, Ut, part);
+  else
+    hipLaunchKernelGGL(k_energy_part<1>, grid, dim3(256), 0, s, N, ce, hx, hy, W, Ut, part);
+  hipLaunchKernelGGL(k_energy_sum, dim3((K + 63) / 64), dim3(64), 0, s, K, nblk, part, E);
   return hipGetLastError();
 }
 

@@ -165,6 +165,11 @@ hipError_t launch_coarse_restrict(const Geometry &g, const Channel *ch,
 hipError_t launch_prolong_coarse(const Geometry &g, const Channel *ch,
                                  double *C, int mode, hipStream_t s);
 hipError_t launch_prolong(const ProlongArgs &a, hipStream_t s);
+// Energy 1/2 ||ut_k||^2 + 1/2 ||c grad w_k||^2 of K finest-mesh slabs into E[k]
+// (part: K * nblk doubles of block partial sums).
+hipError_t launch_energy(int d, int N, const double *ce, double hx, double hy, const double *W,
+                         const double *Ut, int K, int nblk, double *part, double *E,
+                         hipStream_t s);
 hipError_t launch_fine_stencils(int d, int N, const double *ce, double hx,
                                 double hy, const double *v_in, const double *u_in,
                                 double *mv_out, double *ku_out,

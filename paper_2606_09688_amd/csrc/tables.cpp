@@ -254,6 +254,33 @@ Taps spline_taps(int b, int J, double T) {
   return tp;
 }
 
+Taps spline_taps_at(int b, double T, const std::vector<double> &t, int deriv) {
+  const int nb = 1 << b;
+  const double h = T / nb;
+  Taps tp;
+  tp.q0.assign(t.size(), 0);
+  tp.w.assign(3 * t.size(), 0.0);
+  double v[3], d1[3], d2[3];
+  for (size_t n = 0; n < t.size(); ++n) {
+    int e = (int)std::floor(t[n] / h);
+    if (e < 0) e = 0;
+    if (e > nb - 1) e = nb - 1;
+    spline_ref(nb, e, t[n] / h - e, v, d1, d2);
+    double vals[3];
+    for (int k = 0; k < 3; ++k) vals[k] = deriv ? d1[k] / h : v[k];
+    // B_{e+k} is psi_{e+k-1}; B_0 (k = 0 on element 0) is not in the space
+    int qmin = e - 1, nv = 3;
+    if (e == 0) {
+      vals[0] = vals[1];
+      vals[1] = vals[2];
+      qmin = 0;
+      nv = 2;
+    }
+    normalise_taps(nb + 1, (int)n, qmin, vals, nv, tp);
+  }
+  return tp;
+}
+
 Taps sum_taps(int J) {
   const int N = 1 << J;
   Taps tp;

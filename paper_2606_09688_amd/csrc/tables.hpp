@@ -43,6 +43,9 @@ struct Taps {
 Taps p1_taps(int b, int J, double T);
 // Spline taps of level b: psi^b_q(t_n).
 Taps spline_taps(int b, int J, double T);
+// Spline taps of level b at arbitrary instants t[n] in [0,T]: psi^b_q(t_n)
+// (deriv = 0) or psi^b_q'(t_n) (deriv = 1).
+Taps spline_taps_at(int b, double T, const std::vector<double> &t, int deriv);
 // Time-sum taps: q0 = 0, w = (1,0,0) for every n (sum over slabs).
 Taps sum_taps(int J);
 

@@ -713,3 +713,93 @@ def test_gradient_central_differences():
         fd = (loss(f + h * pf, u0 + h * pu) - loss(f - h * pf, u0 - h * pu)) / (2 * h)
         ad = np.sum(df * pf) + du0 @ pu
         assert abs(fd - ad) <= 1e-6 * abs(ad) + 1e-6
+
+
+# ---- energy of the computed solution (Sec. 6.3) -----------------------------
+
+def _single_coefficient(prob, jx, jt, i, k):
+    """Component solutions that are zero except u_(jx,jt)[i, k] = 1."""
+    sols = []
+    for cx, ct, _ in prob.comps:
+        u = np.zeros((levels.n_time(ct), levels.n_space(cx, prob.d)))
+        if (cx, ct) == (jx, jt):
+            u[i, k] = 1.0
+        sols.append(u)
+    return sols
+
+
+def test_energy_single_basis_function_closed_form():
+    """u_h = psi_i(t) phi_k(x) with an interior uniform quadratic B-spline psi_i
+    (knot spacing tau) and an interior level-a hat (width h): E(t) =
+    1/2 psi_i'(t)^2 (2h/3) + 1/2 psi_i(t)^2 (2 c^2/h).  At the middle of the
+    spline's central interval psi = 3/4, psi' = 0; at its second knot psi = 1/2,
+    psi' = 1/tau."""
+    prob = Problem(1, [1.0], [1], [1.3], 1.0, 6)            # J = 5
+    jx, jt, i, k = 2, 4, 5, 1                                # h = 1/4, tau = 1/16
+    assert (jx, jt, 1) in prob.comps
+    sols = _single_coefficient(prob, jx, jt, i, k)
+    h, tau, c2 = 0.25, 1.0 / 16, 1.3 ** 2
+    # psi_5 = B_6: support [4 tau, 7 tau]
+    E = method.energy(prob, sols, np.zeros(prob.ns_fine), [5.5 * tau, 5.0 * tau])
+    want = [0.5 * (3 / 4) ** 2 * 2 * c2 / h,
+            0.5 * (1 / tau) ** 2 * 2 * h / 3 + 0.5 * (1 / 2) ** 2 * 2 * c2 / h]
+    np.testing.assert_allclose(E, want, rtol=1e-13)
+
+
+def test_energy_single_basis_function_closed_form_2d():
+    """2-D: phi_k = hat_x hat_y, int phi^2 = (2h/3)^2, int |grad phi|^2 =
+    2 (2/h)(2h/3) (c = 1), at the middle of the spline's central interval."""
+    prob = Problem(2, [1.0, 1.0], [1, 1], [1.0], 1.0, 6)
+    jx, jt, i = 2, 4, 5
+    k = 1 * 3 + 1                                            # centre node of level 2
+    sols = _single_coefficient(prob, jx, jt, i, k)
+    h, tau = 0.25, 1.0 / 16
+    E = method.energy(prob, sols, np.zeros(prob.ns_fine), [5.5 * tau])
+    want = 0.5 * (3 / 4) ** 2 * 2 * (2 / h) * (2 * h / 3)
+    np.testing.assert_allclose(E, [want], rtol=1e-13)
+
+
+def test_solution_at_nodes_equals_combination():
+    """At the finest time nodes the arbitrary-instant evaluation reproduces
+    the nodal combination U (eq. 19 plus the lift)."""
+    prob = Problem(1, [1.0], [2], [1.0, 0.6], 1.0, 5)
+    rng = np.random.default_rng(3)
+    sols = [rng.standard_normal((levels.n_time(jt), levels.n_space(jx, 1)))
+            for jx, jt, _ in prob.comps]
+    u0 = rng.standard_normal(prob.ns_fine)
+    t = np.arange(prob.nt_fine) * prob.T / 2 ** prob.J
+    np.testing.assert_allclose(method.solution_at(prob, sols, u0, t),
+                               prob.combine(sols, u0), rtol=0, atol=1e-12)
+
+
+def test_solution_time_derivative_by_central_difference():
+    """d_t u_h is a quadratic polynomial in t inside every finest interval, so
+    a central difference inside one interval reproduces it to rounding."""
+    prob = Problem(2, [1.0, 1.0], [1, 1], [1.0], 1.0, 4)
+    rng = np.random.default_rng(4)
+    sols = [rng.standard_normal((levels.n_time(jt), levels.n_space(jx, 2)))
+            for jx, jt, _ in prob.comps]
+    u0 = np.zeros(prob.ns_fine)
+    dt = prob.T / 2 ** prob.J
+    t = np.array([0.3, 2.5, 5.7]) * dt                       # inside intervals
+    d = 0.2 * dt
+    fd = (method.solution_at(prob, sols, u0, t + d) -
+          method.solution_at(prob, sols, u0, t - d)) / (2 * d)
+    np.testing.assert_allclose(method.solution_at(prob, sols, u0, t, deriv=1), fd,
+                               rtol=0, atol=1e-9 * np.abs(fd).max())
+
+
+def test_energy_converges_to_the_exact_energy():
+    """f = 0, u0 = 0, v0 = pi sin(pi x), c = 1: u = sin(pi t) sin(pi x) keeps
+    E = pi^2/4; the sparse-grid energy approaches it as L grows."""
+    errs = []
+    for L in (5, 6, 7):
+        prob = Problem(1, [1.0], [1], [1.0], 1.0, L)
+        x = np.arange(1, 2 ** prob.J) / 2 ** prob.J
+        f = np.zeros((prob.nt_fine, prob.ns_fine))
+        u0 = np.zeros(prob.ns_fine)
+        v0 = np.pi * np.sin(np.pi * x)
+        sols = prob.component_solutions(f, u0, v0)
+        E = method.energy(prob, sols, u0, [0.25, 0.5, 0.75])
+        errs.append(np.abs(E / (np.pi ** 2 / 4) - 1).max())
+    assert errs[2] < errs[1] < errs[0] and errs[2] < 1e-2
