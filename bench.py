@@ -217,6 +217,29 @@ def main():
         plain_diff = float((Up - U).norm() / U.norm())
         del Up
 
+    # ---- energy of the solution at 800 instants (Sec. 6.3 diagnostic) ------
+    # two streaming prolongations over the instants (value and time
+    # derivative of u_h) and an element-wise reduction that reads both back
+    K_e = 800
+    sv.energy_setup(np.linspace(0.0, spec.T, K_e))
+    with torch.cuda.stream(stream):
+        E_t = sv.energy(u0, stream=stream)
+    stream.synchronize()
+    reps_e = 5
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for _ in range(reps_e):
+            sv.energy(u0, out=E_t, stream=stream)
+        e1.record(stream)
+    stream.synchronize()
+    t_energy = e0.elapsed_time(e1) * 1e-3 / reps_e
+    bytes_energy = 4.0 * K_e * (nfull // sv.shape[0]) * 8   # write and read two fields
+    energy_out = {"instants": K_e, "ms": t_energy * 1e3, "hbm_bytes": bytes_energy,
+                  "GB_per_s": bytes_energy / t_energy / 1e9,
+                  "E_first_last": [float(E_t[0]), float(E_t[-1])]}
+
     # dominant fine-grid kernel (timed inside the last graph replay when the
     # runtime records captured events, else in the eager runs): each streams
     # 8 bytes per fine-grid value
@@ -257,6 +280,7 @@ def main():
             "fwd_adj_over_fwd": (stage["fwd"] + stage["adj"]) / stage["fwd"],
             "plain_vs_fused_rel_l2": plain_diff,
             "graph_equals_eager": graph_equals_eager,
+            "energy": energy_out,
             "stage_ms": {k: v * 1e3 for k, v in stage.items()},
             "kernel_ms": {k: v * 1e3 for k, v in kern_t.items()},
             "kernel_ms_from": "last timed graph replay" if graph_events else "eager runs",
