@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--L", type=int, default=10)
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-energy", action="store_true",
+                    help="skip the energy diagnostic (counter runs of the streaming kernels)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of one fine array (counter scaling)")
@@ -110,6 +112,29 @@ def copy_calibration(args):
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration": {"bytes_read": 8 * n, "bytes_written": 8 * n,
                                            "launches": 3, "library": sg.__name__}}), flush=True)
+
+
+def time_energy(sv, u0, stream, T, K, nspace, reps=5):
+    """Energy of the last solution at K uniform instants: two streaming
+    prolongations over the instants and an element-wise reduction reading
+    both fields back (4 K nspace doubles of algorithmic traffic)."""
+    import torch
+    sv.energy_setup(np.linspace(0.0, T, K))
+    with torch.cuda.stream(stream):
+        E = sv.energy(u0, stream=stream)
+    stream.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for _ in range(reps):
+            sv.energy(u0, out=E, stream=stream)
+        e1.record(stream)
+    stream.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    nbytes = 4.0 * K * nspace * 8
+    return {"instants": K, "ms": t * 1e3, "hbm_bytes": nbytes, "GB_per_s": nbytes / t / 1e9,
+            "E_first_last": [float(E[0]), float(E[-1])]}
 
 
 def main():
@@ -221,24 +246,9 @@ def main():
     # two streaming prolongations over the instants (value and time
     # derivative of u_h) and an element-wise reduction that reads both back
     K_e = 800
-    sv.energy_setup(np.linspace(0.0, spec.T, K_e))
-    with torch.cuda.stream(stream):
-        E_t = sv.energy(u0, stream=stream)
-    stream.synchronize()
-    reps_e = 5
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(stream):
-        e0.record(stream)
-        for _ in range(reps_e):
-            sv.energy(u0, out=E_t, stream=stream)
-        e1.record(stream)
-    stream.synchronize()
-    t_energy = e0.elapsed_time(e1) * 1e-3 / reps_e
-    bytes_energy = 4.0 * K_e * (nfull // sv.shape[0]) * 8   # write and read two fields
-    energy_out = {"instants": K_e, "ms": t_energy * 1e3, "hbm_bytes": bytes_energy,
-                  "GB_per_s": bytes_energy / t_energy / 1e9,
-                  "E_first_last": [float(E_t[0]), float(E_t[-1])]}
+    energy_out = None
+    if not args.no_energy:
+        energy_out = time_energy(sv, u0, stream, spec.T, K_e, nfull // sv.shape[0])
 
     # dominant fine-grid kernel (timed inside the last graph replay when the
     # runtime records captured events, else in the eager runs): each streams

@@ -1278,8 +1278,7 @@ sg_status sg_energy_setup(sg_problem *p, int K, const double *times) {
   if ((st = build_pass(p, p->eval, ge, spec(false), &part_unused, true)) ||
       (st = build_pass(p, p->eder, ge, spec(true), &part_unused, true)))
     return st;
-  const long long nel = p->d == 2 ? (long long)p->N * p->N : p->N;
-  p->enblk = (int)std::min<long long>(64, (nel + 255) / 256);
+  p->enblk = (p->N + 255) / 256;  // one thread per element (column in 2-D)
   const long long n0a = (1LL << ge.A0) - 1;
   const long long nsp0 = p->d == 2 ? n0a * n0a : n0a;
   if (!(p->eU = p->dalloc<double>((size_t)K * p->nsp_fine)) ||

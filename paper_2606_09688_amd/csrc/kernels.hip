@@ -1832,8 +1832,11 @@ __global__ void k_fine_stencils(int N, const double *__restrict__ ce, double hx,
 // with ut_k, w_k the P1 (d=1) / Q1 (d=2) functions of the nodal values
 // Ut[k], W[k] (zero on the boundary), integrated exactly element by element
 // (every element term is a positive semi-definite form, so no cancellation
-// between elements).  Grid (nblk, K): each block sums a fixed set of
-// elements in a fixed tree order into part[k][blk].
+// between elements).  Grid (nblk, K): in 2-D thread x walks the column of
+// elements ex = x from the bottom row up, carrying the values of the row
+// below (two new values per field and element, coalesced across the
+// threads); in 1-D one element per thread.  Each block sums its threads in
+// a fixed tree order into part[k][blk].
 template <int D>
 __global__ void __launch_bounds__(256) k_energy_part(int N, const double *__restrict__ ce,
                                                      double hx, double hy,
@@ -1845,45 +1848,42 @@ __global__ void __launch_bounds__(256) k_energy_part(int N, const double *__rest
   const long long nsp = (D == 2) ? (long long)n * n : n;
   const int k = blockIdx.y;
   const double *w = W + (long long)k * nsp, *ut = Ut + (long long)k * nsp;
-  const long long nel = (D == 2) ? (long long)N * N : N;
-  auto at = [&](const double *f, int x, int y) -> double {
-    if (!interior(x, n) || (D == 2 && !interior(y, n))) return 0.0;
-    return f[(D == 2 ? (long long)(y - 1) * n : 0) + (x - 1)];
-  };
+  const int ex = blockIdx.x * blockDim.x + threadIdx.x;  // element (column in 2-D)
   double acc = 0.0;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nel;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int ex = (D == 2) ? (int)(e % N) : (int)e, ey = (D == 2) ? (int)(e / N) : 0;
-    const double c2 = ce[e];
+  if (ex < N) {
     if (D == 1) {
-      const double u0 = at(ut, ex, 0), u1 = at(ut, ex + 1, 0);
-      const double w0 = at(w, ex, 0), w1 = at(w, ex + 1, 0);
+      const double u0 = ex >= 1 ? ut[ex - 1] : 0.0, u1 = ex + 1 <= n ? ut[ex] : 0.0;
+      const double w0 = ex >= 1 ? w[ex - 1] : 0.0, w1 = ex + 1 <= n ? w[ex] : 0.0;
       // mass h/6 [2 1; 1 2], stiffness c^2/h [1 -1; -1 1]
-      acc += 0.5 * (hx / 6.0 * (2.0 * u0 * u0 + 2.0 * u0 * u1 + 2.0 * u1 * u1) +
-                    c2 / hx * (w1 - w0) * (w1 - w0));
+      acc = 0.5 * (hx / 6.0 * (2.0 * u0 * u0 + 2.0 * u0 * u1 + 2.0 * u1 * u1) +
+                   ce[ex] / hx * (w1 - w0) * (w1 - w0));
     } else {
-      double u[2][2], v[2][2];
-      for (int cy = 0; cy < 2; ++cy)
-        for (int cx = 0; cx < 2; ++cx) {
-          u[cy][cx] = at(ut, ex + cx, ey + cy);
-          v[cy][cx] = at(w, ex + cx, ey + cy);
+      // node columns ex and ex + 1; node rows 0 and N are on the boundary
+      const bool c0 = ex >= 1, c1 = ex + 1 <= n;
+      const int x0 = c0 ? ex - 1 : 0, x1 = c1 ? ex : 0;
+      double ul0 = 0.0, ul1 = 0.0, wl0 = 0.0, wl1 = 0.0;  // row below (node row 0)
+      for (int ey = 0; ey < N; ++ey) {
+        double uh0 = 0.0, uh1 = 0.0, wh0 = 0.0, wh1 = 0.0;  // node row ey + 1
+        if (ey + 1 <= n) {
+          const long long r = (long long)ey * n;
+          uh0 = c0 ? ut[r + x0] : 0.0;
+          uh1 = c1 ? ut[r + x1] : 0.0;
+          wh0 = c0 ? w[r + x0] : 0.0;
+          wh1 = c1 ? w[r + x1] : 0.0;
         }
-      // Q1 element forms with the 1-D mass m = h/6 [2 1; 1 2] and stiffness
-      // k = 1/h [1 -1; -1 1]: mass m_y (x) m_x, stiffness c^2 (m_y (x) k_x + k_y (x) m_x)
-      auto m1 = [](double a, double b) { return 2.0 * a * a + 2.0 * a * b + 2.0 * b * b; };
-      auto mx2 = [](double a0, double a1, double b0, double b1) {  // a^T m b (unscaled)
-        return 2.0 * a0 * b0 + a0 * b1 + a1 * b0 + 2.0 * a1 * b1;
-      };
-      // int ut^2 = (hx/6)(hy/6) sum_{ij} my_{ij} (u_i^T mx u_j), rows i = cy
-      const double mass = hx / 6.0 * hy / 6.0 *
-                          (2.0 * m1(u[0][0], u[0][1]) + 2.0 * m1(u[1][0], u[1][1]) +
-                           2.0 * mx2(u[0][0], u[0][1], u[1][0], u[1][1]));
-      // x derivatives per row, y derivatives per column
-      const double gx0 = v[0][1] - v[0][0], gx1 = v[1][1] - v[1][0];
-      const double gy0 = v[1][0] - v[0][0], gy1 = v[1][1] - v[0][1];
-      const double kx = (hy / 6.0) / hx * (2.0 * gx0 * gx0 + 2.0 * gx0 * gx1 + 2.0 * gx1 * gx1);
-      const double ky = (hx / 6.0) / hy * (2.0 * gy0 * gy0 + 2.0 * gy0 * gy1 + 2.0 * gy1 * gy1);
-      acc += 0.5 * (mass + c2 * (kx + ky));
+        // Q1 element forms with the 1-D mass m = h/6 [2 1; 1 2] and stiffness
+        // k = 1/h [1 -1; -1 1]: mass m_y (x) m_x, stiffness c^2 (m_y (x) k_x + k_y (x) m_x)
+        const double ml = 2.0 * ul0 * ul0 + 2.0 * ul0 * ul1 + 2.0 * ul1 * ul1;
+        const double mh = 2.0 * uh0 * uh0 + 2.0 * uh0 * uh1 + 2.0 * uh1 * uh1;
+        const double mc = 2.0 * ul0 * uh0 + ul0 * uh1 + ul1 * uh0 + 2.0 * ul1 * uh1;
+        const double mass = hx / 6.0 * hy / 6.0 * (2.0 * ml + 2.0 * mh + 2.0 * mc);
+        const double gx0 = wl1 - wl0, gx1 = wh1 - wh0;  // x differences of the two rows
+        const double gy0 = wh0 - wl0, gy1 = wh1 - wl1;  // y differences of the two columns
+        const double kx = (hy / 6.0) / hx * (2.0 * gx0 * gx0 + 2.0 * gx0 * gx1 + 2.0 * gx1 * gx1);
+        const double ky = (hx / 6.0) / hy * (2.0 * gy0 * gy0 + 2.0 * gy0 * gy1 + 2.0 * gy1 * gy1);
+        acc += 0.5 * (mass + ce[(long long)ey * N + ex] * (kx + ky));
+        ul0 = uh0; ul1 = uh1; wl0 = wh0; wl1 = wh1;
+      }
     }
   }
   s_red[threadIdx.x] = acc;
