@@ -866,9 +866,10 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   if (const char *e = getenv("SG_RESTR_WG")) rwg = std::max(1, atoi(e));
   const Geometry geor = w16 ? make_geometry(d, J, ntf, 4 * rwg * ncu, 16) : geo;
   const Geometry geoa = w16 ? make_geometry(d, J, ntf, 4 * 3 * ncu, 16) : geo;
-  // the prolongations likewise, 4 workgroups per CU each (SG_PROL_WG and
-  // SG_PROLM_WG override for the plain and the mass-stencil prolongation)
-  int pwg = 4, pmwg = 4;
+  // the prolongations likewise, 3 workgroups per CU each (their register
+  // windows and per-lane taps use up to 168 VGPRs; SG_PROL_WG and SG_PROLM_WG
+  // override for the plain and the mass-stencil prolongation)
+  int pwg = 3, pmwg = 3;
   if (const char *e = getenv("SG_PROL_WG")) pwg = std::max(1, atoi(e));
   if (const char *e = getenv("SG_PROLM_WG")) pmwg = std::max(1, atoi(e));
   const Geometry geop = w16 ? make_geometry(d, J, ntf, 4 * pwg * ncu, 16) : geo;

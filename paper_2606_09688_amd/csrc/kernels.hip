@@ -1301,7 +1301,7 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
 // channel sign, and where the window moves on) come from a per-pass host
 // table.  The prolongation through the mass stencil is k_prolong_wm.
 #ifndef SG_WPEP
-#define SG_WPEP 4
+#define SG_WPEP 3
 #endif
 __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A) {
   constexpr int TS = 16, LTS = 4;
@@ -1523,9 +1523,10 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
 // h/2 (z_K + z_{K+1}); the 2-D stencil is the tensor product.  The mass
 // stencil of the level-J channel's three coefficient fields is applied once,
 // before the slab loop, and kept in LDS.  Lane l writes column l % 16, rows
-// 4 (l / 16) .. +3, which share four level-1 rows.
+// 4 (l / 16) .. +3, which share four level-1 rows.  Three workgroups per CU:
+// at four the register budget of 128 spilled the coefficient windows.
 #ifndef SG_WPEM
-#define SG_WPEM 4
+#define SG_WPEM 3
 #endif
 __global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A) {
   constexpr int TS = 16, LTS = 4;

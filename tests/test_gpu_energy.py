@@ -33,6 +33,7 @@ CASES = [
     (1, [1.0], [1], [1.0], 1.0, 5, 40),
     (1, [1.0], [2], [1.0, 0.5], 1.3, 8, 300),          # variable speed
     (1, [2.0], [1], [0.8], 1.0, 11, 1500),             # coarse levels below the tile
+    (1, [1.0], [2], [1.0, 0.5], 1.0, 10, 800),         # block-LU components (levels >= 9)
     (2, [1.0, 1.0], [1, 1], [1.0], 1.0, 3, 9),
     (2, [1.0, 0.8], [1, 1], [0.9], 1.5, 6, 50),
     (2, [1.2, 1.0], [1, 1], [1.1], 0.9, 8, 200),        # 16 x 16 tiles, coarse levels
