@@ -67,6 +67,7 @@ struct Pass {
 struct GemmList {
   GemmDesc *d = nullptr;
   int n = 0, tiles = 0;
+  int fold = 0;                   // GemmDesc.fold mode of every descriptor
 };
 
 struct SolveList {
@@ -118,6 +119,8 @@ struct sg_problem {
   std::vector<double *> tf, ti;    // per spatial level: forward / inverse transform
                                    // (DST-I for constant c, M-orthonormal
                                    // eigenvectors V / V^T for variable c, d = 1)
+  std::vector<double *> th[2];    // constant c: columns of one parity of the DST-I
+                                   // matrix, rows k <= (n-1)/2 (folded transforms)
   double *d_ce = nullptr;         // fine-element c^2
   // buffers (N^sparse each)
   double *bufZ = nullptr, *bufB = nullptr, *bufT = nullptr, *bufS = nullptr,
@@ -161,6 +164,7 @@ struct sg_problem {
   hipGraphExec_t gexec = nullptr;
   int refine_nq = 33;
   int wave_nq = 33;                // time levels with nq >= wave_nq: one wave per mode
+  int gemm_fold = 2;               // folded DST-I transforms (build_gemm_lists)
   // optional stage events; during capture the dependencies at each mark
   std::vector<hipEvent_t> ev;
   bool capturing = false;
@@ -462,6 +466,12 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
   if (!x_out) x_out = p->bufU;
   std::vector<GemmDesc> vx, vy, viy, vix;
   int tx = 0, ty = 0, tiy = 0, tix = 0;
+  // constant c: the transforms are DST-I products, which can be folded into
+  // two half-size products (one per output parity), halving the matrix work;
+  // gemm_fold 1 folds the x transforms, 2 also the y transforms of levels
+  // a >= 7, 3 every transform
+  const int gf = p->const_c ? p->gemm_fold : 0;
+  bool any_fx = false, any_fy = false;
   // the finest spatial levels (longest K loops) first: their tiles are
   // dispatched at once and the many short tiles of coarse levels fill in
   std::vector<int> order(cset);
@@ -479,8 +489,47 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
     double *mid = flat ? p->bufS : p->bufT;
     constexpr int T = kGemmTile;
     auto tiles = [](int M, int N) { return ((M + T - 1) / T) * ((N + T - 1) / T); };
+    const bool fx = gf >= 1, fy = p->d == 2 && (gf == 3 || (gf == 2 && C.a >= 7));
+    if (fx || fy) {
+      // x: C[m][2 j' + par] = sum_k (A[m][k] +- A[m][na-1-k]) H_par[k][j'];
+      // y: C[2 j' + par][x] = sum_k Q[2 j' + par][k] (B[k][x] +- B[na-1-k][x])
+      const long long slab = (long long)na * na;
+      const int h = (na - 1) / 2;
+      for (int par = 0; par < 2; ++par) {
+        const int nh = h + 1 - par;
+        if (nh == 0) continue;
+        for (int inv = 0; inv < 2 && fx; ++inv) {
+          GemmDesc g{};
+          g.A = (inv ? mid : x_in) + C.off; g.B = p->th[par][C.a];
+          g.C = (inv ? x_out : mid) + C.off;
+          g.M = C.nq * ny; g.N = nh; g.K = nh; g.lda = na; g.ldb = nh; g.ldc = na;
+          g.nref = na; g.par = par;
+          g.batch = 1; g.tm = (g.M + T - 1) / T; g.tn = (g.N + T - 1) / T;
+          int &tt = inv ? tix : tx;
+          g.tile0 = tt;
+          tt += tiles(g.M, g.N);
+          (inv ? vix : vx).push_back(g);
+        }
+        if (fy) {
+          for (int inv = 0; inv < 2; ++inv) {
+            GemmDesc g{};
+            g.A = Q + (long long)par * na; g.B = (inv ? p->bufS : p->bufT) + C.off;
+            g.C = (inv ? p->bufT : p->bufS) + C.off;
+            g.M = nh; g.N = na; g.K = nh; g.lda = 2 * na; g.ldb = na; g.ldc = na;
+            g.sA = 0; g.sB = slab; g.sC = slab; g.nref = na; g.par = par;
+            g.batch = C.nq; g.tm = (g.M + T - 1) / T; g.tn = (g.N + T - 1) / T;
+            int &tt = inv ? tiy : ty;
+            g.tile0 = tt;
+            tt += C.nq * tiles(g.M, g.N);
+            (inv ? viy : vy).push_back(g);
+          }
+        }
+      }
+      any_fx = any_fx || fx;
+      any_fy = any_fy || fy;
+    }
     // forward x: T = B * Q   ([nq*ny x na] x [na x na])
-    {
+    if (!fx) {
       GemmDesc g{};
       g.A = x_in + C.off; g.B = Q; g.C = mid + C.off;
       g.M = C.nq * ny; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
@@ -489,7 +538,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
       vx.push_back(g);
     }
     // inverse x: U = T * Q^{-1}
-    {
+    if (!fx) {
       GemmDesc g{};
       g.A = mid + C.off; g.B = Qi; g.C = x_out + C.off;
       g.M = C.nq * ny; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
@@ -497,7 +546,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
       tix += tiles(g.M, g.N);
       vix.push_back(g);
     }
-    if (p->d == 2 && !flat) {
+    if (p->d == 2 && !flat && !fy) {
       const long long slab = (long long)na * na;
       // forward y: S_i = Q * T_i
       GemmDesc g{};
@@ -516,13 +565,13 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
   }
   sg_status st;
   if ((st = upload(p, vx, &gx.d)) != SG_OK) return st;
-  gx.n = (int)vx.size(); gx.tiles = tx;
+  gx.n = (int)vx.size(); gx.tiles = tx; gx.fold = any_fx ? 1 : 0;
   if ((st = upload(p, vix, &gix.d)) != SG_OK) return st;
-  gix.n = (int)vix.size(); gix.tiles = tix;
+  gix.n = (int)vix.size(); gix.tiles = tix; gix.fold = any_fx ? 1 : 0;
   if ((st = upload(p, vy, &gy.d)) != SG_OK) return st;
-  gy.n = (int)vy.size(); gy.tiles = ty;
+  gy.n = (int)vy.size(); gy.tiles = ty; gy.fold = any_fy ? 2 : 0;
   if ((st = upload(p, viy, &giy.d)) != SG_OK) return st;
-  giy.n = (int)viy.size(); giy.tiles = tiy;
+  giy.n = (int)viy.size(); giy.tiles = tiy; giy.fold = any_fy ? 2 : 0;
   return SG_OK;
 }
 
@@ -570,11 +619,11 @@ sg_status run_solves(sg_problem *p, const GemmList &gx, const GemmList &gy,
                      const SolveList &sl, const GemmList &giy, const GemmList &gix,
                      const BlockList &bl, hipStream_t s) {
   HIPCHK(launch_block_solve(bl.d, bl.n, p->d_kt, s));
-  HIPCHK(launch_gemm(gx.d, gx.n, gx.tiles, s));
-  if (p->d == 2) HIPCHK(launch_gemm(gy.d, gy.n, gy.tiles, s));
+  HIPCHK(launch_gemm(gx.d, gx.n, gx.tiles, gx.fold, s));
+  if (p->d == 2) HIPCHK(launch_gemm(gy.d, gy.n, gy.tiles, gy.fold, s));
   HIPCHK(launch_time_solve(sl.d, sl.n, sl.threads, p->d_kt, p->d_mt, p->d, s));
-  if (p->d == 2) HIPCHK(launch_gemm(giy.d, giy.n, giy.tiles, s));
-  HIPCHK(launch_gemm(gix.d, gix.n, gix.tiles, s));
+  if (p->d == 2) HIPCHK(launch_gemm(giy.d, giy.n, giy.tiles, giy.fold, s));
+  HIPCHK(launch_gemm(gix.d, gix.n, gix.tiles, gix.fold, s));
   return SG_OK;
 }
 
@@ -646,6 +695,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   if (!p->const_c) p->c2 = 1.0;  // the eigenvalues carry c
   if (const char *e = getenv("SG_REFINE_NQ")) p->refine_nq = atoi(e);
   if (const char *e = getenv("SG_WAVE_NQ")) p->wave_nq = atoi(e);
+  if (const char *e = getenv("SG_GEMM_FOLD")) p->gemm_fold = std::min(3, std::max(0, atoi(e)));
 
   // components: +1 on jx + jt = L (jx = 1..L-1), -1 on jx + jt = L-1 (jx = 1..L-2)
   long long off = 0;
@@ -730,6 +780,8 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   ModeTables mt{};
   p->tf.assign(J + 1, nullptr);
   p->ti.assign(J + 1, nullptr);
+  p->th[0].assign(J + 1, nullptr);
+  p->th[1].assign(J + 1, nullptr);
   for (int a = 1; a <= J; ++a) {
     std::vector<double> m, k;
     double *dm, *dk;
@@ -742,8 +794,20 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
         if ((st = upload(p, m, &dm)) || (st = upload(p, k, &dk))) return bail(st);
         mt.my[a] = dm; mt.ky[a] = dk;
       }
-      if ((st = upload(p, dst_matrix(a), &p->tf[a]))) return bail(st);
+      const std::vector<double> Q = dst_matrix(a);
+      if ((st = upload(p, Q, &p->tf[a]))) return bail(st);
       p->ti[a] = p->tf[a];  // the DST-I matrix is its own inverse
+      // half tables of the folded transforms: H_par[k][j'] = Q[k][2 j' + par],
+      // k, j' < (n + 1) / 2 - par
+      const int n = (1 << a) - 1, h = (n - 1) / 2;
+      for (int par = 0; par < 2; ++par) {
+        const int nh = h + 1 - par;
+        if (nh == 0) continue;
+        std::vector<double> H((size_t)nh * nh);
+        for (int k = 0; k < nh; ++k)
+          for (int j = 0; j < nh; ++j) H[(size_t)k * nh + j] = Q[(size_t)k * n + 2 * j + par];
+        if ((st = upload(p, H, &p->th[par][a]))) return bail(st);
+      }
     } else if (d == 2) {
       // 2-D variable speed: M-orthonormal modes of the dense pencil (K(c), M)
       // from the generalised symmetric eigensolver of rocSOLVER (set-up only),
@@ -1187,11 +1251,11 @@ sg_status sg_adjoint(sg_problem *p, const double *g, double *df, double *du0, do
   // z_c = S_c^{-T} y_c  (y_c in bufZ, z_c into bufW)
   MARK(p, 10, s);
   HIPCHK(launch_block_solve(p->badj.d, p->badj.n, p->d_kt, s));
-  HIPCHK(launch_gemm(p->agx.d, p->agx.n, p->agx.tiles, s));
-  if (p->d == 2) HIPCHK(launch_gemm(p->gy.d, p->gy.n, p->gy.tiles, s));
+  HIPCHK(launch_gemm(p->agx.d, p->agx.n, p->agx.tiles, p->agx.fold, s));
+  if (p->d == 2) HIPCHK(launch_gemm(p->gy.d, p->gy.n, p->gy.tiles, p->gy.fold, s));
   HIPCHK(launch_time_solve(p->sadj.d, p->sadj.n, p->sadj.threads, p->d_kt, p->d_mt, p->d, s));
-  if (p->d == 2) HIPCHK(launch_gemm(p->giy.d, p->giy.n, p->giy.tiles, s));
-  HIPCHK(launch_gemm(p->agix.d, p->agix.n, p->agix.tiles, s));
+  if (p->d == 2) HIPCHK(launch_gemm(p->giy.d, p->giy.n, p->giy.tiles, p->giy.fold, s));
+  HIPCHK(launch_gemm(p->agix.d, p->agix.n, p->agix.tiles, p->agix.fold, s));
   MARK(p, 11, s);
   // zeta_c = D^T z_c, level fields for du0 / dv0
   HIPCHK(launch_post_adjoint(p->cadj.d, p->cadj.n, p->cadj.total, p->d_kt, s));

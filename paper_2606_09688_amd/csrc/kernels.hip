@@ -1983,9 +1983,13 @@ __global__ void k_adjoint_fields(const LevelDesc *__restrict__ ld, int nlev,
 //   result element r of the lane = D[l / 16 + 4 r][l % 16].
 typedef double sg_double4 __attribute__((ext_vector_type(4)));
 
+// FOLD = 1 / 2: descriptors with nref > 0 fold the summed index k of A's
+// columns / B's rows with its reflection nref-1-k, and their results are the
+// outputs of one parity, stored at every other column / row of C.
 #ifndef SG_GEMM_BK
 #define SG_GEMM_BK 64
 #endif
+template <int FOLD>
 __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmDesc *__restrict__ descs,
                                                       int ndesc) {
   // K steps of SG_GEMM_BK: with 64 each step is 64 MFMAs per wave (about
@@ -1996,8 +2000,17 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmDesc *__restric
   constexpr int EA = BM * BK / NT, EB = BK * BN / NT;  // staged values per thread
   __shared__ double As[BM][BK + 1];
   __shared__ double Bs[BK][BN + 2];
+  // this tile's descriptor: the last one whose first tile is <= blockIdx.x
+  // (tile0 ascends); one gather of tile0 per lane for 64 descriptors at a
+  // time instead of a chain of dependent scalar loads
   int di = 0;
-  while (di + 1 < ndesc && descs[di + 1].tile0 <= (int)blockIdx.x) ++di;
+  for (int base = 0; base < ndesc; base += 64) {
+    const int i = base + (int)(threadIdx.x & 63);
+    const unsigned long long le = __ballot(i < ndesc && descs[i].tile0 <= (int)blockIdx.x);
+    di += __popcll(le);
+    if (le != ~0ull) break;
+  }
+  di = __builtin_amdgcn_readfirstlane(di - 1);
   const GemmDesc &Dd = descs[di];
   int t = blockIdx.x - Dd.tile0;
   const int per = Dd.tm * Dd.tn;
@@ -2011,6 +2024,11 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmDesc *__restric
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / W) * 32, wn = (wave % W) * 32;
   const int M = Dd.M, N = Dd.N, K = Dd.K;
+  // folding: k < h pairs with its reflection, k = h (even parity only) is
+  // the unpaired middle index
+  const bool fd = FOLD != 0 && Dd.nref > 0;
+  const int nr1 = Dd.nref - 1, hmid = nr1 / 2;
+  const double sgn = Dd.par ? -1.0 : 1.0;
   // global -> register staging; loads go to clamped valid addresses and are
   // selected, not branched
   double ra[EA], rb[EB];
@@ -2021,7 +2039,12 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmDesc *__restric
       const int m = i / BK, k = i % BK;           // A: BM x BK
       const int gm = row0 + m, gk = k0 + k;
       const bool oka = gm < M && gk < K;
-      const double va = Ap[oka ? (long long)gm * Dd.lda + gk : 0];
+      const long long ia = oka ? (long long)gm * Dd.lda + gk : 0;
+      double va = Ap[ia];
+      if (FOLD == 1 && fd) {
+        const double vr = Ap[oka ? ia + nr1 - 2 * gk : 0];
+        va = gk == hmid ? va : va + sgn * vr;
+      }
       ra[e] = oka ? va : 0.0;
     }
 #pragma unroll
@@ -2030,7 +2053,11 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmDesc *__restric
       const int kb = i / BN, n = i % BN;          // B: BK x BN
       const int gkb = k0 + kb, gn = col0 + n;
       const bool okb = gkb < K && gn < N;
-      const double vb = Bp[okb ? (long long)gkb * Dd.ldb + gn : 0];
+      double vb = Bp[okb ? (long long)gkb * Dd.ldb + gn : 0];
+      if (FOLD == 2 && fd) {
+        const double vr = Bp[okb ? (long long)(nr1 - gkb) * Dd.ldb + gn : 0];
+        vb = gkb == hmid ? vb : vb + sgn * vr;
+      }
       rb[e] = okb ? vb : 0.0;
     }
   };
@@ -2076,7 +2103,9 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmDesc *__restric
       for (int r = 0; r < 4; ++r) {
         const int gm = row0 + wm + i * 16 + (lane >> 4) + 4 * r;
         const int gn = col0 + wn + j * 16 + (lane & 15);
-        if (gm < M && gn < N) Cp[(long long)gm * Dd.ldc + gn] = acc[i][j][r];
+        const int cm = FOLD == 2 && fd ? 2 * gm + Dd.par : gm;
+        const int cn = FOLD == 1 && fd ? 2 * gn + Dd.par : gn;
+        if (gm < M && gn < N) Cp[(long long)cm * Dd.ldc + cn] = acc[i][j][r];
       }
 }
 
@@ -2876,9 +2905,15 @@ hipError_t launch_adjoint_fields(const LevelDesc *ld, int nlev, long long total,
   return hipGetLastError();
 }
 
-hipError_t launch_gemm(const GemmDesc *descs, int ndesc, int total_tiles, hipStream_t s) {
+hipError_t launch_gemm(const GemmDesc *descs, int ndesc, int total_tiles, int fold,
+                       hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemm, dim3(total_tiles), dim3(kGemmThreads), 0, s, descs, ndesc);
+  if (fold == 1)
+    hipLaunchKernelGGL(k_gemm<1>, dim3(total_tiles), dim3(kGemmThreads), 0, s, descs, ndesc);
+  else if (fold == 2)
+    hipLaunchKernelGGL(k_gemm<2>, dim3(total_tiles), dim3(kGemmThreads), 0, s, descs, ndesc);
+  else
+    hipLaunchKernelGGL(k_gemm<0>, dim3(total_tiles), dim3(kGemmThreads), 0, s, descs, ndesc);
   return hipGetLastError();
 }
 

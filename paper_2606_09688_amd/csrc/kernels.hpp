@@ -82,6 +82,14 @@ struct GemmDesc {
   long long sA, sB, sC;
   int batch, tm, tn;
   int tile0;
+  // folded transforms (launches with fold 1 or 2; a DST-I matrix Q of odd
+  // order nref, whose entry (k, j) and entry (nref-1-k, j) differ by the sign
+  // (-1)^j): the sum over k in C = A B runs over the pairs k, nref-1-k of A's
+  // columns (fold 1) or B's rows (fold 2), added for the outputs j of even
+  // parity (par 0, k = 0..nref/2 with the middle index unpaired) and
+  // subtracted for odd ones (par 1, k < nref/2); C's columns (fold 1) or rows
+  // (fold 2) are the outputs 2 j' + par
+  int nref, par;
 };
 
 struct SolveDesc {
@@ -181,7 +189,7 @@ hipError_t launch_post_adjoint(const CompDesc *cd, int ncomp, long long total,
 hipError_t launch_adjoint_fields(const LevelDesc *ld, int nlev, long long total,
                                  const CompDesc *cd, const KernelTables *kt,
                                  hipStream_t s);
-hipError_t launch_gemm(const GemmDesc *descs, int ndesc, int total_tiles,
+hipError_t launch_gemm(const GemmDesc *descs, int ndesc, int total_tiles, int fold,
                        hipStream_t s);
 hipError_t launch_time_factor(const SolveDesc *sd, int nsd, long long total,
                               const KernelTables *kt, const ModeTables *mt, int d,

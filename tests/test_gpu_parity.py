@@ -94,6 +94,34 @@ def test_forward_and_adjoint_parity(case):
         assert e <= TOL, name
 
 
+_FOLD_CASE = (2, [1.2, 1.0], 1.1, 0.9, 8)  # spatial levels up to 7: folded y products too
+_fold_ref = {}
+
+
+@pytest.mark.parametrize("mode", [0, 1, 3])
+def test_dst_fold_modes(mode, monkeypatch):
+    """The DST products of every fold mode (SG_GEMM_FOLD, read when a problem
+    is assembled: 0 plain, 1 x transforms folded, 3 all folded; the default 2
+    runs in every other test) match the oracle."""
+    torch = _torch()
+    monkeypatch.setenv("SG_GEMM_FOLD", str(mode))
+    d, lengths, c, T, L = _FOLD_CASE
+    spec, data = _case(d, lengths, c, T, L, seed=300)
+    if not _fold_ref:
+        orc = Problem(*spec.args())
+        _fold_ref["U"] = orc.forward(data["f"], data["u0"], data["v0"]).reshape(spec.shape())
+        _fold_ref["adj"] = orc.adjoint(data["g"])
+    print(f"fold mode {mode}: d={d} L={L}", flush=True)
+    sv = _solver(spec)
+    f, u0, v0, g = (_dev(data[k]) for k in ("f", "u0", "v0", "g"))
+    U = sv.solve(f, u0, v0)
+    df, du0, dv0 = sv.adjoint(g)
+    torch.cuda.synchronize()
+    assert rel(U.cpu().numpy(), _fold_ref["U"]) <= TOL
+    for got, ref in zip((df, du0, dv0), _fold_ref["adj"]):
+        assert rel(got.cpu().numpy(), ref) <= TOL
+
+
 VARC = [
     # (lengths, c on uniform blocks, T, L): piecewise-constant speed in 1-D
     ([1.0], [1.0, 0.5], 2.0, 6),                       # two-speed medium
