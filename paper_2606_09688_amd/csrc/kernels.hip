@@ -738,6 +738,27 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
   }
 }
 
+// Index of the last of n items (ascending .start) whose start is <= gid.
+// Every lane of the wave calls it, before any early return: one ballot over
+// the starts finds the item of the wave's first thread, then a lane steps on
+// only across the rare item boundaries inside its wave (a chain of dependent
+// loads from the first item would serialise the latency of each).
+template <class T>
+__device__ __forceinline__ int find_item(const T *items, int n, long long gid) {
+  const long long gw = (long long)blockIdx.x * blockDim.x +
+                       __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u));
+  int it = 0;
+  for (int base = 0; base < n; base += 64) {
+    const int i = base + (int)(threadIdx.x & 63);
+    const unsigned long long le = __ballot(i < n && items[i].start <= gw);
+    it += __popcll(le);
+    if (le != ~0ull) break;
+  }
+  it = it > 0 ? it - 1 : 0;
+  while (it + 1 < n && items[it + 1].start <= gid) ++it;
+  return it;
+}
+
 // Tile range of the tiles whose restriction block holds node P of level
 // offset r (blocks [t s_r, t s_r + s_r], s_r = TS >> r; level 0 not shared).
 __device__ __forceinline__ void tile_range(int TS, int r, int P, int ntile, int &t0,
@@ -760,9 +781,8 @@ __global__ void k_reduce(const Geometry g, const Channel *__restrict__ ch,
                          long long total) {
   using SH = Shape<D, TS, 0>;
   const long long gid = gid64();
+  const int it = find_item(items, nitems, gid);
   if (gid >= total) return;
-  int it = 0;
-  while (it + 1 < nitems && items[it + 1].start <= gid) ++it;
   const Channel &C = ch[items[it].ch];
   const long long loc = gid - items[it].start;
   const int a = C.a, r = g.J - a;
@@ -894,9 +914,8 @@ __global__ void k_coarse_restrict(const Geometry g, const Channel *__restrict__ 
                                   const WorkItem *__restrict__ items, int nitems,
                                   long long total) {
   const long long gid = gid64();
+  const int it = find_item(items, nitems, gid);
   if (gid >= total) return;
-  int it = 0;
-  while (it + 1 < nitems && items[it + 1].start <= gid) ++it;
   const Channel &C = ch[items[it].ch];
   const long long loc = gid - items[it].start;
   const int a = C.a;
@@ -1905,18 +1924,14 @@ __global__ void k_energy_sum(int K, int nblk, const double *__restrict__ part,
   E[k] = s;
 }
 
-__device__ __forceinline__ int find_comp(const CompDesc *cd, int ncomp, long long gid) {
-  int c = 0;
-  while (c + 1 < ncomp && cd[c + 1].start <= gid) ++c;
-  return c;
-}
 
 // b_c[i][K] = sum_q D_b[i][q] Z_c[q][K] + psi_i'(0) MV_a[K] - g_b[i] KU_a[K]
 __global__ void k_post_load(const CompDesc *__restrict__ cd, int ncomp, long long total,
                             const KernelTables *__restrict__ kt) {
   const long long gid = gid64();
+  const int ci = find_item(cd, ncomp, gid);
   if (gid >= total) return;
-  const CompDesc &C = cd[find_comp(cd, ncomp, gid)];
+  const CompDesc &C = cd[ci];
   const long long loc = gid - C.start;
   const int i = (int)loc / C.nsp;  // a component holds fewer than 2^31 values
   const int K = (int)loc - i * C.nsp;
@@ -1932,8 +1947,9 @@ __global__ void k_post_load(const CompDesc *__restrict__ cd, int ncomp, long lon
 __global__ void k_post_adjoint(const CompDesc *__restrict__ cd, int ncomp,
                                long long total, const KernelTables *__restrict__ kt) {
   const long long gid = gid64();
+  const int ci = find_item(cd, ncomp, gid);
   if (gid >= total) return;
-  const CompDesc &C = cd[find_comp(cd, ncomp, gid)];
+  const CompDesc &C = cd[ci];
   const long long loc = gid - C.start;
   const int q = (int)loc / C.nsp;  // a component holds fewer than 2^31 values
   double v = kt->Dlo[C.b][q] * C.z[loc];
@@ -1948,9 +1964,8 @@ __global__ void k_adjoint_fields(const LevelDesc *__restrict__ ld, int nlev,
                                  long long total, const CompDesc *__restrict__ cd,
                                  const KernelTables *__restrict__ kt) {
   const long long gid = gid64();
+  const int l = find_item(ld, nlev, gid);
   if (gid >= total) return;
-  int l = 0;
-  while (l + 1 < nlev && ld[l + 1].start <= gid) ++l;
   const LevelDesc &L = ld[l];
   const long long rel = gid - L.start;
   const int lane = L.wave ? (int)(rel & 63) : 0, step = L.wave ? 64 : 1;
