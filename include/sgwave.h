@@ -114,8 +114,11 @@ sg_status sg_graph_launch(sg_problem *p, hipStream_t stream);
 /*
  * Stage timing: when ev is not NULL, sg_solve and sg_adjoint record
  * ev[i] (caller-created hipEvent_t, at least SG_NUM_EVENTS of them) on the
- * call's stream at these points; events set when sg_graph_capture runs are
- * captured as event-record nodes and recorded by every replay:
+ * call's stream at these points; a NULL entry leaves its point out.  When
+ * sg_graph_capture runs, the pairs (1, 2), (5, 6), (8, 9) and (12, 13) whose
+ * two events are both set become event-record nodes around their kernel,
+ * recorded by every replay (each node costs a few microseconds of the
+ * replay, so a caller timing replays sets only the pairs it reads):
  *   0 forward begin        1 before the load restriction   2 after it
  *   3 before the solves    4 after the solves              5 before the
  *   combination pass       6 after it (forward end)

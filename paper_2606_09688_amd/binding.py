@@ -275,15 +275,17 @@ class SparseGridWave:
         return out
 
     def set_events(self, events):
-        """Record the SG_NUM_EVENTS stage events (torch.cuda.Event list) or None."""
+        """Record the SG_NUM_EVENTS stage events (torch.cuda.Event list, None
+        entries leave their point out) or None."""
         if events is None:
             check(lib().sg_set_events(self._h, None, 0), "sg_set_events")
             return
         for e in events:      # torch creates the underlying event on first record
-            if not e.cuda_event:
+            if e is not None and not e.cuda_event:
                 e.record()
         torch.cuda.synchronize()
-        arr = (ctypes.c_void_p * len(events))(*[e.cuda_event for e in events])
+        arr = (ctypes.c_void_p * len(events))(
+            *[e.cuda_event if e is not None else None for e in events])
         check(lib().sg_set_events(self._h, arr, len(events)), "sg_set_events")
 
     def replay(self, stream=None):

@@ -337,7 +337,7 @@ sg_status build_pass(sg_problem *p, Pass &P, const Geometry &geo, F spec,
 }
 
 sg_status mark(sg_problem *p, int id, hipStream_t s) {
-  if (id >= (int)p->ev.size()) return SG_OK;
+  if (id >= (int)p->ev.size() || p->ev[id] == nullptr) return SG_OK;
   if (!p->capturing) {
     HIPCHK(hipEventRecord(p->ev[id], s));
     return SG_OK;
