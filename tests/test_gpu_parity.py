@@ -220,7 +220,14 @@ def test_plain_loop_and_graph_match_fused(case):
     with torch.cuda.stream(s):
         sv.capture(f, u0, v0, Ug, g, dfg, du0g, dv0g, stream=s)
     sv.set_events(None)
-    for rep in range(3):
+    for rep in range(4):
+        if rep == 2:
+            # a capture with one event pair set (the other entries NULL) times
+            # that kernel only and leaves the results unchanged
+            sv.set_events([e if i in (8, 9) else None for i, e in enumerate(ev)])
+            with torch.cuda.stream(s):
+                sv.capture(f, u0, v0, Ug, g, dfg, du0g, dv0g, stream=s)
+            sv.set_events(None)
         Ug.zero_()
         dfg.zero_()
         torch.cuda.synchronize()
@@ -229,6 +236,8 @@ def test_plain_loop_and_graph_match_fused(case):
         s.synchronize()
         assert torch.equal(Ug, U), rep
         assert torch.equal(dfg, df) and torch.equal(du0g, du0) and torch.equal(dv0g, dv0), rep
+        if rep >= 2:
+            assert ev[8].elapsed_time(ev[9]) > 0.0
         _ = (f * 2.0).sum().item()  # unrelated eager work between replays
 
 
