@@ -246,8 +246,11 @@ class SparseGridWave:
         return df, du0, dv0
 
     def capture(self, f, u0, v0, U, g=None, df=None, du0=None, dv0=None, stream=None):
-        """Capture forward (+ adjoint when g is given) into a HIP graph."""
+        """Capture forward (+ adjoint when g is given) into a HIP graph.  The
+        graph holds the tensors' device addresses, so they are kept alive
+        here until the next capture or the solver's end."""
         s = stream if stream is not None else torch.cuda.current_stream()
+        self._keep = (f, u0, v0, U, g, df, du0, dv0)
         check(lib().sg_graph_capture(
             self._h, _ptr(f, self.shape, "f"), _ptr(u0, self.space_shape, "u0"),
             _ptr(v0, self.space_shape, "v0"), _ptr(U, self.shape, "U"),

@@ -241,6 +241,30 @@ def test_plain_loop_and_graph_match_fused(case):
         _ = (f * 2.0).sum().item()  # unrelated eager work between replays
 
 
+def test_capture_with_temporaries_keeps_them_alive():
+    """A graph captured with temporary tensors stays valid after the caller
+    drops them: the solver keeps the captured tensors, so memory handed out
+    afterwards does not alias the graph's buffers."""
+    torch = _torch()
+    spec, data = _case(2, [1.0, 0.8], 0.9, 1.5, 5, seed=8)
+    sv = _solver(spec)
+    f, u0, v0 = (_dev(data[k]) for k in ("f", "u0", "v0"))
+    U_eager = sv.solve(f, u0, v0)
+    torch.cuda.synchronize()
+    U = torch.empty_like(U_eager)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        sv.capture(f.clone(), u0.clone(), v0.clone(), U, stream=s)
+    s.synchronize()
+    junk = [torch.full_like(f, 7.0), torch.full_like(u0, 7.0), torch.full_like(v0, 7.0)]
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        sv.replay(stream=s)
+    s.synchronize()
+    assert torch.equal(U, U_eager)
+    del junk
+
+
 def test_manufactured_c1_against_closed_form():
     """c1 (d=1, L=6): U matches the oracle to 1e-10 and the closed-form
     solution sin(pi x) sin(pi t) to the discretisation error."""
