@@ -92,6 +92,24 @@ sg_status sg_solve_plain(sg_problem *p, const double *f, const double *u0,
                          const double *v0, double *U, hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): sg_solve with
+ * its per-call scratch (partial sums of the streaming restriction, the
+ * coarse-level arrays and two fine space fields) taken from a statically
+ * allocated device array of 64 MiB instead of the handle's workspace.  Same
+ * arguments, arithmetic and result as sg_solve, bit for bit.  Allocates
+ * nothing and calls no allocating routine.  The array exists once per device
+ * and is shared by every call on that device: calls that overlap on one
+ * device (any handles, any streams) race and must be ordered by the caller.
+ * It keeps the last call's contents; the call clears what must start at zero
+ * itself.  SG_ENOTSUP (message states the need) if the problem needs more
+ * than 64 MiB of scratch; SG_ESTATE if the current device is not the
+ * handle's.
+ */
+sg_status sg_solve_static(sg_problem *p, const double *f, const double *u0,
+                          const double *v0, double *U, hipStream_t stream);
+
+/*
  * Adjoint of the forward map F: (f,u0,v0) -> U.  g has the layout of U;
  * df the layout of f; du0, dv0 fine space arrays.  Computes
  * (df, du0, dv0) = F^T g (transposed combination, transposed component

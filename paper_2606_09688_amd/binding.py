@@ -31,6 +31,7 @@ SIGNATURES = {
                                    ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
     "sg_solve": (ctypes.c_int, [ctypes.c_void_p] * 6),
     "sg_solve_plain": (ctypes.c_int, [ctypes.c_void_p] * 6),
+    "sg_solve_static": (ctypes.c_int, [ctypes.c_void_p] * 6),
     "sg_adjoint": (ctypes.c_int, [ctypes.c_void_p] * 6),
     "sg_graph_capture": (ctypes.c_int, [ctypes.c_void_p] * 10),
     "sg_graph_launch": (ctypes.c_int, [ctypes.c_void_p] * 2),
@@ -221,10 +222,14 @@ class SparseGridWave:
         return out
 
     # ---- solves ---------------------------------------------------------
-    def solve(self, f, u0, v0, out=None, plain=False, stream=None):
+    def solve(self, f, u0, v0, out=None, plain=False, static=False, stream=None):
+        """Forward solve into `out` (allocated if None).  plain: the literal
+        per-component loop (sg_solve_plain); static: the fused path with the
+        static device scratch (sg_solve_static)."""
         if out is None:
             out = torch.empty(self.shape, dtype=torch.float64, device=f.device)
-        fn = lib().sg_solve_plain if plain else lib().sg_solve
+        fn = (lib().sg_solve_plain if plain else
+              lib().sg_solve_static if static else lib().sg_solve)
         check(fn(self._h, _ptr(f, self.shape, "f"), _ptr(u0, self.space_shape, "u0"),
                  _ptr(v0, self.space_shape, "v0"), _ptr(out, self.shape, "U"),
                  _stream(stream)), "sg_solve")

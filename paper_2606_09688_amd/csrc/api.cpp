@@ -87,6 +87,15 @@ struct BlockList {       // components solved by block LU + refinement
   int n = 0;
 };
 
+// Per-call scratch of the streaming passes: partial blocks of the in-tile
+// levels, per-slab coarse partials, the level-A0 arrays and their
+// restrictions, the prolongation's coarse array and two fine space fields.
+// Every entry is written before it is read within one call.
+struct Scratch {
+  double *part = nullptr, *cpart = nullptr, *S0 = nullptr, *SL = nullptr, *Cpro = nullptr,
+         *fine2 = nullptr;
+};
+
 }  // namespace
 
 struct sg_problem {
@@ -135,6 +144,8 @@ struct sg_problem {
   double *S0 = nullptr;            // coarse level-A0 arrays
   double *SL = nullptr;            // their restrictions to the levels a < A0
   double *Cpro = nullptr;          // prolongation coarse array
+  Scratch ws;                      // the handle's own scratch (the buffers above)
+  long long n_part = 0, n_cpart = 0, n_S0 = 0, n_SL = 0;  // their sizes (doubles)
   // passes
   Pass load, prol, adjr, adjp, fieldr, fieldp;
   int prol_target = 0, prol_ts = 0;  // grid sizing of the prolongations
@@ -393,8 +404,8 @@ sg_status add_graph_events(sg_problem *p, hipGraph_t graph) {
     if (st_ != SG_OK) return st_;               \
   } while (0)
 
-sg_status run_restrict(sg_problem *p, const Pass &P, const double *X, int stencil,
-                       hipStream_t s, int ev_begin = -1) {
+sg_status run_restrict(sg_problem *p, const Scratch &ws, const Pass &P, const double *X,
+                       int stencil, hipStream_t s, int ev_begin = -1) {
   const Geometry &g = P.geo;
   RestrictArgs ra{};
   ra.g = g;
@@ -410,17 +421,17 @@ sg_status run_restrict(sg_problem *p, const Pass &P, const double *X, int stenci
       ra.safe_w = C.w;
       break;
     }
-  ra.part = p->part;
+  ra.part = ws.part;
   ra.taps = P.d_taps;
-  ra.coarse = g.A0 > 1 ? p->cpart : nullptr;
+  ra.coarse = g.A0 > 1 ? ws.cpart : nullptr;
   if (ev_begin >= 0) MARK(p, ev_begin, s);
   HIPCHK(launch_restrict(ra, s));
   if (ev_begin >= 0) MARK(p, ev_begin + 1, s);
-  if (P.n_red) HIPCHK(launch_reduce(g, P.d_ch, p->part, P.d_red, P.n_red, P.tot_red, s));
+  if (P.n_red) HIPCHK(launch_reduce(g, P.d_ch, ws.part, P.d_red, P.n_red, P.tot_red, s));
   if (g.A0 > 1 && P.n_crs) {
-    HIPCHK(launch_coarse_assemble(g, p->cpart, p->S0, s));
-    HIPCHK(launch_coarse_pyramid(g, p->S0, p->SL, s));
-    HIPCHK(launch_coarse_restrict(g, P.d_ch, p->SL, P.d_crs, P.n_crs, P.tot_crs, s));
+    HIPCHK(launch_coarse_assemble(g, ws.cpart, ws.S0, s));
+    HIPCHK(launch_coarse_pyramid(g, ws.S0, ws.SL, s));
+    HIPCHK(launch_coarse_restrict(g, P.d_ch, ws.SL, P.d_crs, P.n_crs, P.tot_crs, s));
   }
   return SG_OK;
 }
@@ -678,6 +689,14 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
     return st;
   };
   if (hipGetDevice(&p->device) != hipSuccess) return bail(fail(SG_EDEVICE, "no HIP device"));
+  {
+    // resolve this device's static scratch (sg_solve_static) once, here
+    double *unused = nullptr;
+    if (static_scratch(&unused) != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(fail(SG_EDEVICE, "hipGetSymbolAddress of the static scratch failed"));
+    }
+  }
   p->d = d;
   p->len[0] = len[0];
   p->len[1] = d == 2 ? len[1] : 1.0;
@@ -1019,6 +1038,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   }
   if (!(p->part = p->dalloc<double>(part_need)))
     return bail(fail(SG_ENOMEM, "hipMalloc of partial blocks failed"));
+  p->n_part = part_need;
   {
     // coarse arrays of the restriction (geor) and prolongation (geo) passes
     long long need = 1, nsp0 = 0, ncl = 0;
@@ -1044,6 +1064,10 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
         !(p->SL = p->dalloc<double>(std::max(1LL, ntf * ncl))) ||
         !(p->Cpro = p->dalloc<double>(ntf * nsp0)))
       return bail(fail(SG_ENOMEM, "hipMalloc of coarse buffers failed"));
+    p->n_cpart = need;
+    p->n_S0 = ntf * nsp0;
+    p->n_SL = std::max(1LL, ntf * ncl);
+    p->ws = Scratch{p->part, p->cpart, p->S0, p->SL, p->Cpro, p->fine2};
   }
 
   // ---- descriptor lists -------------------------------------------------------
@@ -1196,29 +1220,65 @@ sg_status sg_component_copy(sg_problem *p, int c, int stage, double *out) {
   return SG_OK;
 }
 
-static sg_status forward_fields(sg_problem *p, const double *u0, const double *v0,
-                                hipStream_t s) {
+static sg_status forward_fields(sg_problem *p, const Scratch &ws, const double *u0,
+                                const double *v0, hipStream_t s) {
   const double hx = p->len[0] / p->N, hy = p->len[1] / p->N;
   // fine M v0 and K u0, then their restriction to every level (q = 0 row)
-  HIPCHK(launch_fine_stencils(p->d, p->N, p->d_ce, hx, hy, v0, u0, p->fine2,
-                              p->fine2 + p->nsp_fine, nullptr, 0, s));
-  return run_restrict(p, p->fieldr, p->fine2, 0, s);
+  HIPCHK(launch_fine_stencils(p->d, p->N, p->d_ce, hx, hy, v0, u0, ws.fine2,
+                              ws.fine2 + p->nsp_fine, nullptr, 0, s));
+  return run_restrict(p, ws, p->fieldr, ws.fine2, 0, s);
 }
 
-sg_status sg_solve(sg_problem *p, const double *f, const double *u0, const double *v0,
-                   double *U, hipStream_t s) {
+// The fused forward pipeline with the given per-call scratch.
+static sg_status solve_fused(sg_problem *p, const Scratch &ws, const double *f,
+                             const double *u0, const double *v0, double *U, hipStream_t s) {
   if (!p) return fail(SG_EINVAL, "NULL handle");
   if (!f || !u0 || !v0 || !U) return fail(SG_EINVAL, "NULL data pointer");
   if (U == f) return fail(SG_EINVAL, "U must not alias f");
   sg_status st;
   MARK(p, 0, s);
-  if ((st = forward_fields(p, u0, v0, s))) return st;
-  if ((st = run_restrict(p, p->load, f, 1, s, 1))) return st;
+  if ((st = forward_fields(p, ws, u0, v0, s))) return st;
+  if ((st = run_restrict(p, ws, p->load, f, 1, s, 1))) return st;
   HIPCHK(launch_post_load(p->cload.d, p->cload.n, p->cload.total, p->d_kt, s));
   MARK(p, 3, s);
   if ((st = run_solves(p, p->gx, p->gy, p->sfwd, p->giy, p->gix, p->bfwd, s))) return st;
   MARK(p, 4, s);
-  return run_prolong(p, p->prol, u0, U, 0, 0, s, 5);
+  return run_prolong(p, p->prol, u0, U, 0, 0, s, 5, ws.Cpro);
+}
+
+sg_status sg_solve(sg_problem *p, const double *f, const double *u0, const double *v0,
+                   double *U, hipStream_t s) {
+  if (!p) return fail(SG_EINVAL, "NULL handle");
+  return solve_fused(p, p->ws, f, u0, v0, U, s);
+}
+
+sg_status sg_solve_static(sg_problem *p, const double *f, const double *u0, const double *v0,
+                          double *U, hipStream_t s) {
+  if (!p) return fail(SG_EINVAL, "NULL handle");
+  // carve the scratch out of the device's static array, 256-byte aligned
+  const long long sizes[6] = {p->n_part, p->n_cpart, p->n_S0, p->n_SL, p->n_S0,
+                              2 * p->nsp_fine};
+  long long off[6], need = 0;
+  for (int i = 0; i < 6; ++i) {
+    off[i] = need;
+    need += (std::max(1LL, sizes[i]) + 31) / 32 * 32;
+  }
+  if (need > kStaticScratchDoubles)
+    return fail(SG_ENOTSUP, "sg_solve_static: the problem needs " + std::to_string(need * 8) +
+                                " bytes of scratch, more than the static " +
+                                std::to_string(kStaticScratchDoubles * 8) + " bytes");
+  int cur = -1;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != p->device) return fail(SG_ESTATE, "sg_solve_static: handle bound to another device");
+  double *base = nullptr;
+  HIPCHK(static_scratch(&base));
+  Scratch ws;
+  double **dst[6] = {&ws.part, &ws.cpart, &ws.S0, &ws.SL, &ws.Cpro, &ws.fine2};
+  for (int i = 0; i < 6; ++i) *dst[i] = base + off[i];
+  // the array keeps the previous call's contents (any problem): start the
+  // partial blocks from zero, as freshly allocated memory would be
+  HIPCHK(launch_fill(ws.part, std::max(1LL, p->n_part), 0.0, s));
+  return solve_fused(p, ws, f, u0, v0, U, s);
 }
 
 sg_status sg_solve_plain(sg_problem *p, const double *f, const double *u0,
@@ -1228,9 +1288,9 @@ sg_status sg_solve_plain(sg_problem *p, const double *f, const double *u0,
   if (U == f) return fail(SG_EINVAL, "U must not alias f");
   sg_status st;
   HIPCHK(launch_broadcast(U, u0, p->N + 1, p->nsp_fine, s));
-  if ((st = forward_fields(p, u0, v0, s))) return st;
+  if ((st = forward_fields(p, p->ws, u0, v0, s))) return st;
   for (size_t ci = 0; ci < p->comps.size(); ++ci) {
-    if ((st = run_restrict(p, p->plain_load[ci], f, 1, s))) return st;
+    if ((st = run_restrict(p, p->ws, p->plain_load[ci], f, 1, s))) return st;
     HIPCHK(launch_post_load(p->pcload[ci].d, 1, p->pcload[ci].total, p->d_kt, s));
     if ((st = run_solves(p, p->pgx[ci], p->pgy[ci], p->psfwd[ci], p->pgiy[ci], p->pgix[ci],
                          p->pbfwd[ci], s)))
@@ -1247,7 +1307,7 @@ sg_status sg_adjoint(sg_problem *p, const double *g, double *df, double *du0, do
   sg_status st;
   MARK(p, 7, s);
   // y_c = s_c Psi^T g Phi (+ time sum of g for du0)
-  if ((st = run_restrict(p, p->adjr, g, 0, s, 8))) return st;
+  if ((st = run_restrict(p, p->ws, p->adjr, g, 0, s, 8))) return st;
   // z_c = S_c^{-T} y_c  (y_c in bufZ, z_c into bufW)
   MARK(p, 10, s);
   HIPCHK(launch_block_solve(p->badj.d, p->badj.n, p->d_kt, s));

@@ -21,6 +21,9 @@
 // double-double residual, then the inverse transforms.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+
 #include "kernels.hpp"
 #include "tables.hpp"
 
@@ -2713,6 +2716,29 @@ __global__ void __launch_bounds__(64) k_block_solve(const BlockDesc *__restrict_
     const double dmax = apply(res, B.out, true);
     if (dmax <= 1e-15 * xmax) break;
   }
+}
+
+// File-scope scratch of sg_solve_static.  In host code `scratch` names a
+// host-side stand-in, not device memory: host code uses only the address
+// that static_scratch looks up.
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+hipError_t static_scratch(double **ptr) {
+  static std::mutex mu;
+  static std::map<int, double *> addr;  // per device
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    it = addr.emplace(dev, static_cast<double *>(p)).first;
+  }
+  *ptr = it->second;
+  return hipSuccess;
 }
 
 __global__ void k_fill(double *p, long long n, double v) {

@@ -200,6 +200,15 @@ hipError_t launch_time_solve(const SolveDesc *sd, int nsd, long long total,
 hipError_t launch_block_solve(const BlockDesc *bd, int nbd, const KernelTables *kt,
                               hipStream_t s);
 hipError_t launch_fill(double *p, long long n, double v, hipStream_t s);
+
+// Statically allocated scratch for callers that cannot allocate device
+// memory: one array per device, kStaticScratchDoubles doubles (64 MiB), held
+// until the process ends.  static_scratch returns the current device's copy
+// (its address is looked up once per device, with that device current).
+// Every call that uses it on one device shares it: such calls must not
+// overlap.
+constexpr long long kStaticScratchDoubles = (64LL << 20) / 8;
+hipError_t static_scratch(double **ptr);
 hipError_t launch_broadcast(double *out, const double *base, int nt, long long nsp,
                             hipStream_t s);
 
