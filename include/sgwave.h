@@ -250,6 +250,23 @@ sg_status sg_host_pencil(int a, double len, int ncell, const double *c_vals, dou
                          double *lam);
 
 /*
+ * Host table (exported for tests; no device work): diagonalisation of the
+ * time matrices of level b on (0,T) (Prop. 1), B^{-1} A = V diag(lam) V^{-1},
+ * used to solve the 2-D variable-speed components of short time levels.
+ * Only the real eigenvalues and one member (Im > 0) of each conjugate pair
+ * are returned, *nu of them.  Complex arrays are interleaved (re, im);
+ * caller-owned host buffers of at least: lam 2*nq, fin/ain 2*nq*nq,
+ * fout/aout 2*nq*nq doubles (nq = 2^b + 1).  With P = (B V)^{-1}:
+ *   fin[u][j] = P[u][j], fout[j][u] = w_u V[j][u]      (forward solve),
+ *   ain[u][j] = V[j][u], aout[j][u] = w_u P[u][j]      (adjoint solve),
+ * w_u = 2 for a conjugate pair and 1 for a real eigenvalue, so that
+ * S^{-1} b = Re sum_u fout[.][u] (lam_u M + K)^{-1} sum_j fin[u][j] b_j.
+ * Any output may be NULL.  SG_EINVAL unless 1 <= b <= 5 and T > 0.
+ */
+sg_status sg_host_time_fdm(int b, double T, int *nu, double *lam, double *fin, double *fout,
+                           double *ain, double *aout);
+
+/*
  * Host table (exported for tests; no device work): the dense level-a Q1
  * pencil in 2-D, K(c) and M of eq. (9) on (0,len[0]) x (0,len[1]) with c
  * piecewise constant on ncell[0] x ncell[1] uniform blocks (x fastest).

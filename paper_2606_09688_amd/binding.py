@@ -45,6 +45,7 @@ SIGNATURES = {
     "sg_host_pencil": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, _c_dp,
                                       _c_dp, _c_dp]),
     "sg_host_pencil_2d": (ctypes.c_int, [ctypes.c_int, _c_dp, _c_ip, _c_dp, _c_dp, _c_dp]),
+    "sg_host_time_fdm": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, _c_ip] + [_c_dp] * 5),
     "sg_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
                                        ctypes.POINTER(ctypes.c_void_p)]),
     "sg_batch_capture": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_void_p)] * 8
@@ -128,6 +129,26 @@ def host_taps(kind, b, J, T):
     check(lib().sg_host_taps(kind, b, J, float(T), q0.ctypes.data_as(_c_ip),
                              w.ctypes.data_as(_c_dp)), "sg_host_taps")
     return q0, w
+
+
+def host_time_fdm(b, T):
+    """Diagonalisation tables of time level b (sg_host_time_fdm): dict of
+    lam (nu,), fin, ain (nu, nq), fout, aout (nq, nu), complex."""
+    import numpy as np
+    nq = 2 ** b + 1
+    nu = ctypes.c_int()
+    bufs = {k: np.zeros(2 * nq * nq) for k in ("lam", "fin", "fout", "ain", "aout")}
+    dp = lambda a: a.ctypes.data_as(_c_dp)
+    check(lib().sg_host_time_fdm(b, float(T), ctypes.byref(nu),
+                                 *[dp(bufs[k]) for k in ("lam", "fin", "fout", "ain", "aout")]),
+          "sg_host_time_fdm")
+    u = nu.value
+    c = lambda a, n: (a[0:2 * n:2] + 1j * a[1:2 * n:2])
+    return {"lam": c(bufs["lam"], u),
+            "fin": c(bufs["fin"], u * nq).reshape(u, nq),
+            "ain": c(bufs["ain"], u * nq).reshape(u, nq),
+            "fout": c(bufs["fout"], nq * u).reshape(nq, u),
+            "aout": c(bufs["aout"], nq * u).reshape(nq, u)}
 
 
 def host_pencil_2d(a, lengths, ncell, c_vals):

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsgwave.so")
-SOURCES = ["kernels.hip", "tables.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "fdm.hip", "tables.cpp", "api.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

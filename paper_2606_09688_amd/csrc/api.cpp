@@ -25,6 +25,15 @@ namespace {
 constexpr int kEigMaxLevel = 8;
 // 2-D variable speed: spatial levels solved through the dense pencil (n^2 <= 3969)
 constexpr int kEig2MaxLevel = 6;
+// time levels that may be diagonalised (2^b + 1 <= 33 nodes)
+constexpr int kFdmMaxLevel = 5;
+// 2-D variable speed solved by time diagonalisation and strips: spatial
+// levels from kFdmMinLevel up, time levels up to kFdmMaxTimeLevel (17 nodes:
+// the eigenvector matrix of the time pencil has condition number <= 1.3e3),
+// interface systems of at most kFdmMaxInterface nodes (dense complex inverse)
+constexpr int kFdmMinLevel = 7;
+constexpr int kFdmMaxTimeLevel = 4;
+constexpr long long kFdmMaxInterface = 4096;
 
 thread_local std::string g_last_error;
 
@@ -87,6 +96,13 @@ struct BlockList {       // components solved by block LU + refinement
   int n = 0;
 };
 
+struct FdmList {         // 2-D variable-speed components solved by time diagonalisation
+  FdmDesc *d = nullptr;
+  int n = 0;
+  FdmTotals t;
+  GemmList gf, gi;       // strip sine transforms X -> Y and Y -> X
+};
+
 // Per-call scratch of the streaming passes: partial blocks of the in-tile
 // levels, per-slab coarse partials, the level-A0 arrays and their
 // restrictions, the prolongation's coarse array and two fine space fields.
@@ -113,6 +129,13 @@ struct sg_problem {
   long long nsp_fine = 0;
 
   std::vector<void *> allocs;
+  void dfree(void *q) {
+    auto it = std::find(allocs.begin(), allocs.end(), q);
+    if (it != allocs.end()) {
+      (void)hipFree(q);
+      allocs.erase(it);
+    }
+  }
   template <class T>
   T *dalloc(size_t n) {
     void *p = nullptr;
@@ -163,6 +186,9 @@ struct sg_problem {
   SolveList sfwd, sadj;
   std::vector<SolveList> psfwd;
   std::vector<char> blockc;        // per component: solved by block LU (1-D, variable c)
+  std::vector<char> fdmc;          // per component: time diagonalisation + strips (2-D, variable c)
+  FdmList ffwd, fadj;              // those components (forward / adjoint transforms)
+  std::vector<FdmList> pffwd;      // one component each (plain loop)
   BlockList bfwd, badj;
   std::vector<BlockList> pbfwd;
   CompList cload, cadj;
@@ -489,7 +515,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
   std::stable_sort(order.begin(), order.end(),
                    [&](int u, int v) { return p->comps[u].a > p->comps[v].a; });
   for (int ci : order) {
-    if (p->blockc[ci]) continue;
+    if (p->blockc[ci] || p->fdmc[ci]) continue;
     const Comp &C = p->comps[ci];
     // 2-D variable speed: one dense transform over the flat spatial index,
     // straight into the solve buffer (no y transforms)
@@ -595,7 +621,7 @@ sg_status build_solve_list(sg_problem *p, const std::vector<int> &cset, int tran
   long long th = 0;
   for (int pass = 0; pass < 2; ++pass)
     for (int ci : cset) {
-      if (p->blockc[ci]) continue;
+      if (p->blockc[ci] || p->fdmc[ci]) continue;
       const Comp &C = p->comps[ci];
       const int wave = C.nq >= p->wave_nq ? 1 : 0;
       if (wave != (pass == 0 ? 1 : 0)) continue;
@@ -626,15 +652,191 @@ sg_status build_solve_list(sg_problem *p, const std::vector<int> &cset, int tran
   return SG_OK;
 }
 
+// time diagonalisation + strip solves of a list of 2-D variable-speed components
+sg_status run_fdm(const FdmList &f, hipStream_t s) {
+  if (f.n == 0) return SG_OK;
+  HIPCHK(launch_fdm_in(f.d, f.n, f.t, s));
+  HIPCHK(launch_gemm(f.gf.d, f.gf.n, f.gf.tiles, 0, s));
+  HIPCHK(launch_fdm_tri(f.d, f.n, f.t, 0, s));
+  HIPCHK(launch_fdm_interface(f.d, f.n, f.t, s));
+  HIPCHK(launch_fdm_tri(f.d, f.n, f.t, 1, s));
+  HIPCHK(launch_gemm(f.gi.d, f.gi.n, f.gi.tiles, 0, s));
+  HIPCHK(launch_fdm_out(f.d, f.n, f.t, s));
+  return SG_OK;
+}
+
 sg_status run_solves(sg_problem *p, const GemmList &gx, const GemmList &gy,
                      const SolveList &sl, const GemmList &giy, const GemmList &gix,
-                     const BlockList &bl, hipStream_t s) {
+                     const BlockList &bl, const FdmList &fl, hipStream_t s) {
+  sg_status st;
+  if ((st = run_fdm(fl, s))) return st;
   HIPCHK(launch_block_solve(bl.d, bl.n, p->d_kt, s));
   HIPCHK(launch_gemm(gx.d, gx.n, gx.tiles, gx.fold, s));
   if (p->d == 2) HIPCHK(launch_gemm(gy.d, gy.n, gy.tiles, gy.fold, s));
   HIPCHK(launch_time_solve(sl.d, sl.n, sl.threads, p->d_kt, p->d_mt, p->d, s));
   if (p->d == 2) HIPCHK(launch_gemm(giy.d, giy.n, giy.tiles, giy.fold, s));
   HIPCHK(launch_gemm(gix.d, gix.n, gix.tiles, gix.fold, s));
+  return SG_OK;
+}
+
+// Tables, workspace and descriptors of the 2-D variable-speed components
+// solved by time diagonalisation and strips (p->fdmc), and their assembly on
+// the device: tridiagonal factors per (eigenvalue, strip, mode) and the
+// inverse interface Schur complements.
+sg_status build_fdm(sg_problem *p, const std::vector<TimeLevel> &tl_host) {
+  const int ncomp = (int)p->comps.size();
+  p->pffwd.assign(ncomp, FdmList{});
+  if (std::none_of(p->fdmc.begin(), p->fdmc.end(), [](char c) { return c != 0; }))
+    return SG_OK;
+  sg_status st;
+  // time tables per time level
+  struct TimeTabs {
+    int nu = 0;
+    double *lam = nullptr, *fin = nullptr, *fout = nullptr, *ain = nullptr, *aout = nullptr;
+  };
+  std::map<int, TimeTabs> tt;
+  std::map<int, double *> dst;  // strip sine matrices by strip row count m
+  std::vector<FdmDesc> vf, va;
+  std::vector<GemmDesc> gf, gi;
+  FdmTotals tot;
+  int tf_tiles = 0, ti_tiles = 0;
+  constexpr int TG = kGemmTile;
+  for (int ci = 0; ci < ncomp; ++ci) {
+    if (!p->fdmc[ci]) continue;
+    const Comp &C = p->comps[ci];
+    if (!tt.count(C.b)) {
+      TimeFdm f;
+      if (!time_fdm(tl_host[C.b], f))
+        return fail(SG_EDEVICE, "diagonalisation of time level " + std::to_string(C.b) + " failed");
+      TimeTabs t;
+      t.nu = f.nu;
+      if ((st = upload(p, f.lam, &t.lam)) || (st = upload(p, f.fin, &t.fin)) ||
+          (st = upload(p, f.fout, &t.fout)) || (st = upload(p, f.ain, &t.ain)) ||
+          (st = upload(p, f.aout, &t.aout)))
+        return st;
+      tt[C.b] = t;
+    }
+    const TimeTabs &T = tt[C.b];
+    const int n = (1 << C.a) - 1, ns = p->ncell[1], m = (n + 1) / ns - 1, ni = ns - 1;
+    if (!dst.count(m)) {
+      int am = 0;
+      while ((1 << am) < m + 1) ++am;
+      double *q = nullptr;
+      if ((st = upload(p, dst_matrix(am), &q))) return st;
+      dst[m] = q;
+    }
+    // x tables per strip (block row), y modes of the strip
+    std::vector<double> xt;
+    for (int k = 0; k < ns; ++k) {
+      const std::vector<double> row =
+          strip_x_tables(C.a, p->len[0], p->ncell[0], p->c.data() + (size_t)k * p->ncell[0]);
+      xt.insert(xt.end(), row.begin(), row.end());
+    }
+    const double hx = p->len[0] / (n + 1), hy = p->len[1] / (n + 1);
+    std::vector<double> ym(3 * (size_t)m);
+    for (int l = 0; l < m; ++l) {
+      const double th = M_PI * (l + 1) / (m + 1), sh = std::sin(0.5 * th);
+      ym[l] = hy / 6.0 * (4.0 + 2.0 * std::cos(th));
+      ym[m + l] = 4.0 / hy * sh * sh;
+      ym[2 * m + l] = std::sqrt(2.0 / (m + 1)) * std::sin(th);
+    }
+    FdmDesc h{};
+    h.nq = C.nq; h.n = n; h.nu = T.nu; h.ns = ns; h.m = m; h.ni = ni;
+    h.hx = hx; h.hy = hy;
+    h.lam = T.lam;
+    const long long nn = (long long)n * n;
+    double *dxt = nullptr, *dym = nullptr;
+    if ((st = upload(p, xt, &dxt)) || (st = upload(p, ym, &dym))) return st;
+    h.xt = dxt;
+    h.ym = dym;
+    const long long NG = (long long)ni * n;
+    if (!(h.X = p->dalloc<double>(2 * T.nu * nn)) || !(h.Y = p->dalloc<double>(2 * T.nu * nn)) ||
+        !(h.E = p->dalloc<double>(2LL * T.nu * ns * 2 * n)) ||
+        !(h.G = p->dalloc<double>(std::max(1LL, 2 * T.nu * NG))) ||
+        !(h.Xg = p->dalloc<double>(std::max(1LL, 2 * T.nu * NG))) ||
+        !(h.Sinv = p->dalloc<double>(std::max(1LL, 2 * T.nu * NG * NG))) ||
+        !(h.fac = p->dalloc<double>(6LL * T.nu * ns * n * m)))
+      return fail(SG_ENOMEM, "hipMalloc of the strip-solver workspace failed");
+    HIPCHK(fdm_assemble(h));
+    h.node0 = tot.node;
+    h.tri0 = tot.tri;
+    h.edge0 = tot.edge;
+    h.if0 = tot.iface;
+    h.gemv0 = tot.gemv;
+    FdmTotals one;
+    one.node = nn;
+    one.tri = (long long)T.nu * ns * m;
+    one.edge = ni > 0 ? (long long)T.nu * ns * n : 0;
+    one.iface = (long long)T.nu * NG;
+    one.gemv = (long long)T.nu * NG;
+    tot.node += one.node;
+    tot.tri += one.tri;
+    tot.edge += one.edge;
+    tot.iface += one.iface;
+    tot.gemv += one.gemv;
+    FdmDesc hf = h, ha = h;
+    hf.in = p->bufB + C.off;
+    hf.out = p->bufU + C.off;
+    hf.tin = T.fin;
+    hf.tout = T.fout;
+    ha.in = p->bufZ + C.off;
+    ha.out = p->bufW + C.off;
+    ha.tin = T.ain;
+    ha.tout = T.aout;
+    vf.push_back(hf);
+    va.push_back(ha);
+    // strip sine transforms along y: per eigenvalue, one GEMM batched over
+    // the strips, [m x m] x [m x 2n] (complex rows as 2n reals)
+    std::vector<GemmDesc> pgf, pgi;
+    int ptf = 0, pti = 0;
+    for (int u = 0; u < T.nu; ++u) {
+      GemmDesc g{};
+      g.A = dst[m];
+      g.M = m; g.N = 2 * n; g.K = m;
+      g.lda = m; g.ldb = 2 * n; g.ldc = 2 * n;
+      g.sA = 0; g.sB = g.sC = 2LL * n * (m + 1);
+      g.batch = ns;
+      g.tm = (m + TG - 1) / TG;
+      g.tn = (2 * n + TG - 1) / TG;
+      const int tiles = ns * g.tm * g.tn;
+      GemmDesc a = g;
+      a.B = h.X + 2 * u * nn;
+      a.C = h.Y + 2 * u * nn;
+      GemmDesc b = g;
+      b.B = h.Y + 2 * u * nn;
+      b.C = h.X + 2 * u * nn;
+      a.tile0 = tf_tiles; tf_tiles += tiles;
+      b.tile0 = ti_tiles; ti_tiles += tiles;
+      gf.push_back(a);
+      gi.push_back(b);
+      a.tile0 = ptf; ptf += tiles;
+      b.tile0 = pti; pti += tiles;
+      pgf.push_back(a);
+      pgi.push_back(b);
+    }
+    // one-component list for the plain loop
+    FdmList &pl = p->pffwd[ci];
+    FdmDesc one_f = hf;
+    one_f.node0 = one_f.tri0 = one_f.edge0 = one_f.if0 = one_f.gemv0 = 0;
+    if ((st = upload(p, std::vector<FdmDesc>{one_f}, &pl.d))) return st;
+    pl.n = 1;
+    pl.t = one;
+    if ((st = upload(p, pgf, &pl.gf.d)) || (st = upload(p, pgi, &pl.gi.d))) return st;
+    pl.gf.n = (int)pgf.size();
+    pl.gf.tiles = ptf;
+    pl.gi.n = (int)pgi.size();
+    pl.gi.tiles = pti;
+  }
+  for (FdmList *L : {&p->ffwd, &p->fadj}) {
+    if ((st = upload(p, L == &p->ffwd ? vf : va, &L->d))) return st;
+    L->n = (int)vf.size();
+    L->t = tot;
+    if ((st = upload(p, gf, &L->gf.d)) || (st = upload(p, gi, &L->gi.d))) return st;
+    L->gf.n = (int)gf.size();
+    L->gf.tiles = tf_tiles;
+    L->gi.n = (int)gi.size();
+    L->gi.tiles = ti_tiles;
+  }
   return SG_OK;
 }
 
@@ -709,8 +911,6 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   p->N = N;
   p->const_c = std::all_of(p->c.begin(), p->c.end(), [&](double v) { return v == p->c[0]; });
   p->c2 = p->c[0] * p->c[0];
-  if (!p->const_c && d == 2 && J > kEig2MaxLevel)
-    return bail(fail(SG_ENOTSUP, "variable wave speed in 2-D: spatial levels up to 6 (L <= 7)"));
   if (!p->const_c) p->c2 = 1.0;  // the eigenvalues carry c
   if (const char *e = getenv("SG_REFINE_NQ")) p->refine_nq = atoi(e);
   if (const char *e = getenv("SG_WAVE_NQ")) p->wave_nq = atoi(e);
@@ -737,12 +937,39 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   // 1-D variable speed: spatial levels above kEigMaxLevel are solved by the
   // block LU of the whole component (time levels there are short)
   p->blockc.assign(p->comps.size(), 0);
+  p->fdmc.assign(p->comps.size(), 0);
   for (size_t ci = 0; ci < p->comps.size(); ++ci)
-    if (!p->const_c && p->comps[ci].a > kEigMaxLevel) {
+    if (!p->const_c && d == 1 && p->comps[ci].a > kEigMaxLevel) {
       if (p->comps[ci].nq > 64)
         return bail(fail(SG_ENOTSUP, "variable wave speed: time level too fine for the block solver"));
       p->blockc[ci] = 1;
     }
+  // 2-D variable speed: spatial levels from fdm_level up (and every level
+  // above the dense pencils) are diagonalised in time and solved by strips,
+  // which needs a short time level, strips of whole mesh rows and an
+  // interface system of bounded size
+  if (!p->const_c && d == 2) {
+    int fdm_level = kFdmMinLevel;
+    if (const char *e = getenv("SG_FDM_LEVEL")) fdm_level = std::max(1, atoi(e));
+    for (size_t ci = 0; ci < p->comps.size(); ++ci) {
+      const Comp &C = p->comps[ci];
+      if (C.a < fdm_level && C.a <= kEig2MaxLevel) continue;
+      const int ns = ncell[1], n1 = 1 << C.a;
+      const long long ng = (long long)(ns - 1) * (n1 - 1);
+      const bool ok = C.b <= kFdmMaxTimeLevel && n1 % ns == 0 && n1 / ns >= 2 &&
+                      ng <= kFdmMaxInterface;
+      if (ok) {
+        p->fdmc[ci] = 1;
+      } else if (C.a > kEig2MaxLevel) {
+        return bail(fail(SG_ENOTSUP,
+                         "variable wave speed in 2-D: component (" + std::to_string(C.a) + "," +
+                             std::to_string(C.b) +
+                             ") needs a time level of at most 17 nodes, at least two mesh "
+                             "rows per speed block along y and at most " +
+                             std::to_string(kFdmMaxInterface) + " interface nodes"));
+      }
+    }
+  }
   const int ntf = N + 1;
   auto comp_index = [&](int a, int k) -> int {  // k=0 plus, 1 minus
     if (k == 0) return a - 1;
@@ -828,6 +1055,10 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
         if ((st = upload(p, H, &p->th[par][a]))) return bail(st);
       }
     } else if (d == 2) {
+      bool dense = false;  // some component of this level uses the dense pencil
+      for (size_t ci = 0; ci < p->comps.size(); ++ci)
+        dense = dense || (p->comps[ci].a == a && !p->fdmc[ci]);
+      if (!dense) continue;
       // 2-D variable speed: M-orthonormal modes of the dense pencil (K(c), M)
       // from the generalised symmetric eigensolver of rocSOLVER (set-up only),
       // used as one flat spatial index: mass 1, stiffness lambda
@@ -850,6 +1081,8 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
       rocblas_destroy_handle(h);
       int info = -1;
       HIPCHK(hipMemcpy(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost));
+      p->dfree(dM);  // the factor of M left by the eigensolver is not used
+      dM = nullptr;
       if (rs != rocblas_status_success || info != 0)
         return bail(fail(SG_EDEVICE, "generalised eigensolver of the 2-D pencil failed"));
       // dK holds the eigenvectors column by column (column-major V): read as
@@ -1110,6 +1343,11 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
     p->bfwd.n = (int)vf.size();
     p->badj.n = (int)va.size();
   }
+  // 2-D variable speed, time diagonalisation + strips
+  {
+    sg_status fst = build_fdm(p, tl_host);
+    if (fst != SG_OK) return bail(fst);
+  }
   // LU factors of every mode's time matrix, shared by all later solves
   HIPCHK(launch_time_factor(p->sfwd.d, p->sfwd.n, p->sfwd.threads, p->d_kt, p->d_mt, d,
                             nullptr));
@@ -1241,7 +1479,8 @@ static sg_status solve_fused(sg_problem *p, const Scratch &ws, const double *f,
   if ((st = run_restrict(p, ws, p->load, f, 1, s, 1))) return st;
   HIPCHK(launch_post_load(p->cload.d, p->cload.n, p->cload.total, p->d_kt, s));
   MARK(p, 3, s);
-  if ((st = run_solves(p, p->gx, p->gy, p->sfwd, p->giy, p->gix, p->bfwd, s))) return st;
+  if ((st = run_solves(p, p->gx, p->gy, p->sfwd, p->giy, p->gix, p->bfwd, p->ffwd, s)))
+    return st;
   MARK(p, 4, s);
   return run_prolong(p, p->prol, u0, U, 0, 0, s, 5, ws.Cpro);
 }
@@ -1293,7 +1532,7 @@ sg_status sg_solve_plain(sg_problem *p, const double *f, const double *u0,
     if ((st = run_restrict(p, p->ws, p->plain_load[ci], f, 1, s))) return st;
     HIPCHK(launch_post_load(p->pcload[ci].d, 1, p->pcload[ci].total, p->d_kt, s));
     if ((st = run_solves(p, p->pgx[ci], p->pgy[ci], p->psfwd[ci], p->pgiy[ci], p->pgix[ci],
-                         p->pbfwd[ci], s)))
+                         p->pbfwd[ci], p->pffwd[ci], s)))
       return st;
     if ((st = run_prolong(p, p->plain_prol[ci], nullptr, U, 1, 0, s))) return st;
   }
@@ -1310,6 +1549,7 @@ sg_status sg_adjoint(sg_problem *p, const double *g, double *df, double *du0, do
   if ((st = run_restrict(p, p->ws, p->adjr, g, 0, s, 8))) return st;
   // z_c = S_c^{-T} y_c  (y_c in bufZ, z_c into bufW)
   MARK(p, 10, s);
+  if ((st = run_fdm(p->fadj, s))) return st;
   HIPCHK(launch_block_solve(p->badj.d, p->badj.n, p->d_kt, s));
   HIPCHK(launch_gemm(p->agx.d, p->agx.n, p->agx.tiles, p->agx.fold, s));
   if (p->d == 2) HIPCHK(launch_gemm(p->gy.d, p->gy.n, p->gy.tiles, p->gy.fold, s));
@@ -1449,6 +1689,24 @@ sg_status sg_host_time_level(int b, double T, double *A, double *Alo, double *B,
   if (Dlo) std::memcpy(Dlo, tl.Dlo.data(), n * sizeof(double));
   if (Dhi) std::memcpy(Dhi, tl.Dhi.data(), n * sizeof(double));
   if (g) std::memcpy(g, tl.g.data(), n * sizeof(double));
+  return SG_OK;
+}
+
+sg_status sg_host_time_fdm(int b, double T, int *nu, double *lam, double *fin, double *fout,
+                           double *ain, double *aout) {
+  if (b < 1 || b > kFdmMaxLevel || !(T > 0))
+    return fail(SG_EINVAL, "need 1 <= b <= 5 and T > 0");
+  TimeFdm f;
+  if (!time_fdm(time_level(b, T), f)) return fail(SG_EDEVICE, "time diagonalisation failed");
+  if (nu) *nu = f.nu;
+  auto cp = [](double *dst, const std::vector<double> &v) {
+    if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(double));
+  };
+  cp(lam, f.lam);
+  cp(fin, f.fin);
+  cp(fout, f.fout);
+  cp(ain, f.ain);
+  cp(aout, f.aout);
   return SG_OK;
 }
 

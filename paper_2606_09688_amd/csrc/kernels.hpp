@@ -199,6 +199,58 @@ hipError_t launch_time_solve(const SolveDesc *sd, int nsd, long long total,
                              hipStream_t s);
 hipError_t launch_block_solve(const BlockDesc *bd, int nbd, const KernelTables *kt,
                               hipStream_t s);
+// ---- 2-D variable-speed components of short time levels -------------------
+// S = A (x) M + B (x) K(c) is diagonalised in time (B^{-1} A = V diag(lam)
+// V^{-1}), leaving one complex spatial system (lam M + K(c)) w = r per
+// eigenvalue (one of each conjugate pair).  Each is solved directly by
+// splitting Omega into the ns strips of wave-speed blocks along y: inside a
+// strip c depends on x only, so a sine transform along the strip's m interior
+// rows diagonalises the y direction and leaves one tridiagonal system in x
+// per y mode,
+//   T_{k,l} = mu_l (lam M_x + K_x^k) + nu_l M_x^k,
+// (K_x^k, M_x^k the c^2-weighted 1-D stiffness and mass of strip k); the
+// ni = ns - 1 interface rows between strips carry a dense Schur complement,
+// inverted at assembly.  Complex values are interleaved (re, im).
+struct FdmDesc {
+  const double *in;      // right-hand side [nq][n][n] (real)
+  double *out;           // solution [nq][n][n] (real)
+  const double *tin;     // time transform in, complex [nu][nq]
+  const double *tout;    // time transform out, complex [nq][nu]
+  const double *lam;     // eigenvalues, complex [nu]
+  double *X, *Y;         // complex [nu][n][n] work arrays (row-major y, x)
+  double *E;             // complex [nu][ns][2][n]: strip solutions at their first / last row
+  double *G;             // complex [nu][ni][n]: interface right-hand sides
+  double *Xg;            // complex [nu][ni][n]: interface solutions
+  double *Sinv;          // complex [nu][ni n][ni n]: inverse interface Schur complements
+  double *fac;           // [nu][ns][n][m][4]: 1/d'_x and the multiplier l_x of T_{k,l} = L D L^T-like LU
+  const double *xt;      // [ns][4][n]: K_x^k diagonal, coupling (x, x+1); M_x^k diagonal, coupling
+  const double *ym;      // [3][m]: mu_l, nu_l, s_l(first row) of the strip sine transform
+  int nq, n, nu, ns, m, ni;
+  double hx, hy;
+  long long node0;       // first thread: time transforms (n^2 per descriptor)
+  long long tri0;        // first thread: tridiagonal solves (nu ns m)
+  long long edge0;       // first thread: strip edge rows (nu ns n)
+  long long if0;         // first thread: interface right-hand sides (nu ni n)
+  long long gemv0;       // first wave: interface solves (nu ni n rows)
+};
+
+struct FdmTotals {       // launch sizes of one list of FdmDesc
+  long long node = 0, tri = 0, edge = 0, iface = 0, gemv = 0;
+};
+
+// solve phase of a list of components (stream ordered; the strip sine
+// transforms are the GEMM lists gf (X -> Y) and gi (Y -> X))
+hipError_t launch_fdm_in(const FdmDesc *d, int nd, const FdmTotals &t, hipStream_t s);
+hipError_t launch_fdm_tri(const FdmDesc *d, int nd, const FdmTotals &t, int correction,
+                          hipStream_t s);
+hipError_t launch_fdm_interface(const FdmDesc *d, int nd, const FdmTotals &t, hipStream_t s);
+hipError_t launch_fdm_out(const FdmDesc *d, int nd, const FdmTotals &t, hipStream_t s);
+// assembly of one component (descriptor h, device pointers): tridiagonal
+// factors, strip Green's functions at the rows next to the interfaces, the
+// interface Schur complements and their inverses (Gauss-Jordan, partial
+// pivoting).  Allocates and frees its temporaries; synchronises the device.
+hipError_t fdm_assemble(const FdmDesc &h);
+
 hipError_t launch_fill(double *p, long long n, double v, hipStream_t s);
 
 // Statically allocated scratch for callers that cannot allocate device

@@ -19,6 +19,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
+#include <limits>
 #include <stdexcept>
 
 #include "dd.hpp"
@@ -558,6 +560,30 @@ static P1Band p1_on_interval(int a, double len, long double lo, long double hi) 
   return B;
 }
 
+std::vector<double> strip_x_tables(int a, double len, int ncell, const double *c_row) {
+  const int n = (1 << a) - 1;
+  std::vector<long double> kd(n, 0.0L), ko(n, 0.0L), md(n, 0.0L), mo(n, 0.0L);
+  for (int bx = 0; bx < ncell; ++bx) {
+    const long double lo = (long double)len * bx / ncell, hi = (long double)len * (bx + 1) / ncell;
+    const P1Band B = p1_on_interval(a, len, lo, hi);
+    const long double c2 = (long double)c_row[bx] * c_row[bx];
+    for (int k = 0; k < n; ++k) {
+      kd[k] += c2 * B.kd[k];
+      ko[k] += c2 * B.ko[k];
+      md[k] += c2 * B.md[k];
+      mo[k] += c2 * B.mo[k];
+    }
+  }
+  std::vector<double> out(4 * (size_t)n);
+  for (int k = 0; k < n; ++k) {
+    out[k] = (double)kd[k];
+    out[n + k] = (double)ko[k];
+    out[2 * n + k] = (double)md[k];
+    out[3 * n + k] = (double)mo[k];
+  }
+  return out;
+}
+
 void pencil_2d(int a, const double *len, const int *ncell, const double *c_vals,
                std::vector<double> &K, std::vector<double> &M) {
   const int n = (1 << a) - 1;
@@ -628,6 +654,260 @@ std::vector<double> space_entries(int a, double len, int ncell, const double *c_
     }
   }
   return mk;
+}
+
+}  // namespace sg
+
+// ---------------------------------------------------------------------------
+// Time-direction diagonalisation of a short time level (2-D variable speed).
+// ---------------------------------------------------------------------------
+namespace sg {
+
+namespace {
+
+typedef long double R;
+typedef std::complex<long double> C;
+
+// Eigenvalues of a complex upper Hessenberg matrix H (n x n, row-major) by
+// the shifted QR iteration with Wilkinson shifts (Givens rotations on the
+// active block, deflation at negligible subdiagonal entries).
+bool hessenberg_eigenvalues(int n, std::vector<C> H, std::vector<C> &ev) {
+  ev.assign(n, C(0));
+  const R eps = std::numeric_limits<R>::epsilon();
+  int hi = n - 1, iter = 0;
+  std::vector<C> cs(n), sn(n);
+  while (hi >= 0) {
+    if (hi == 0) {
+      ev[0] = H[0];
+      break;
+    }
+    int lo = hi;
+    while (lo > 0 && std::abs(H[(size_t)lo * n + lo - 1]) >
+                         eps * (std::abs(H[(size_t)lo * n + lo]) +
+                                std::abs(H[(size_t)(lo - 1) * n + lo - 1])))
+      --lo;
+    if (lo == hi) {
+      ev[hi] = H[(size_t)hi * n + hi];
+      --hi;
+      iter = 0;
+      continue;
+    }
+    if (++iter > 200) return false;
+    // Wilkinson shift: eigenvalue of the trailing 2 x 2 block nearer to its
+    // last diagonal entry (an exceptional shift every 11 iterations)
+    const C a = H[(size_t)(hi - 1) * n + hi - 1], b = H[(size_t)(hi - 1) * n + hi];
+    const C c = H[(size_t)hi * n + hi - 1], d = H[(size_t)hi * n + hi];
+    C shift;
+    if (iter % 11 == 0) {
+      shift = d + C(std::abs(c), 0);
+    } else {
+      const C tr2 = (a + d) / (R)2, disc = std::sqrt(tr2 * tr2 - (a * d - b * c));
+      const C m1 = tr2 + disc, m2 = tr2 - disc;
+      shift = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
+    }
+    for (int k = lo; k <= hi; ++k) H[(size_t)k * n + k] -= shift;
+    // H - shift = Q R: rotations from the left zero the subdiagonal
+    for (int k = lo; k < hi; ++k) {
+      const C x = H[(size_t)k * n + k], y = H[(size_t)(k + 1) * n + k];
+      const R r = std::sqrt(std::norm(x) + std::norm(y));
+      cs[k] = r > 0 ? x / r : C(1);
+      sn[k] = r > 0 ? y / r : C(0);
+      for (int j = k; j <= hi; ++j) {
+        const C u = H[(size_t)k * n + j], v = H[(size_t)(k + 1) * n + j];
+        H[(size_t)k * n + j] = std::conj(cs[k]) * u + std::conj(sn[k]) * v;
+        H[(size_t)(k + 1) * n + j] = -sn[k] * u + cs[k] * v;
+      }
+    }
+    // R Q + shift (rotations from the right keep the Hessenberg form)
+    for (int k = lo; k < hi; ++k)
+      for (int i = lo; i <= std::min(k + 1, hi); ++i) {
+        const C u = H[(size_t)i * n + k], v = H[(size_t)i * n + k + 1];
+        H[(size_t)i * n + k] = u * cs[k] + v * sn[k];
+        H[(size_t)i * n + k + 1] = -u * std::conj(sn[k]) + v * std::conj(cs[k]);
+      }
+    for (int k = lo; k <= hi; ++k) H[(size_t)k * n + k] += shift;
+  }
+  return true;
+}
+
+// Reduction of a real matrix to upper Hessenberg form by Householder
+// reflections (similarity transform; eigenvalues preserved).
+std::vector<C> to_hessenberg(int n, std::vector<R> G) {
+  for (int k = 0; k + 2 < n; ++k) {
+    R alpha = 0;
+    for (int i = k + 1; i < n; ++i) alpha += G[(size_t)i * n + k] * G[(size_t)i * n + k];
+    alpha = std::sqrt(alpha);
+    if (alpha == 0) continue;
+    if (G[(size_t)(k + 1) * n + k] > 0) alpha = -alpha;
+    std::vector<R> v(n, 0);
+    v[k + 1] = G[(size_t)(k + 1) * n + k] - alpha;
+    for (int i = k + 2; i < n; ++i) v[i] = G[(size_t)i * n + k];
+    R vv = 0;
+    for (int i = k + 1; i < n; ++i) vv += v[i] * v[i];
+    if (vv == 0) continue;
+    // G = (I - 2 v v^T / vv) G (I - 2 v v^T / vv)
+    for (int j = 0; j < n; ++j) {
+      R s = 0;
+      for (int i = k + 1; i < n; ++i) s += v[i] * G[(size_t)i * n + j];
+      s *= 2 / vv;
+      for (int i = k + 1; i < n; ++i) G[(size_t)i * n + j] -= s * v[i];
+    }
+    for (int i = 0; i < n; ++i) {
+      R s = 0;
+      for (int j = k + 1; j < n; ++j) s += G[(size_t)i * n + j] * v[j];
+      s *= 2 / vv;
+      for (int j = k + 1; j < n; ++j) G[(size_t)i * n + j] -= s * v[j];
+    }
+  }
+  std::vector<C> H((size_t)n * n);
+  for (size_t e = 0; e < H.size(); ++e) H[e] = C(G[e], 0);
+  return H;
+}
+
+// Solve M x = b in place (complex, Gaussian elimination with partial
+// pivoting); returns false on a zero pivot.
+bool complex_solve(int n, std::vector<C> M, std::vector<C> &b) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::abs(M[(size_t)r * n + c]) > std::abs(M[(size_t)piv * n + c])) piv = r;
+    if (std::abs(M[(size_t)piv * n + c]) == 0) return false;
+    if (piv != c) {
+      for (int j = 0; j < n; ++j) std::swap(M[(size_t)c * n + j], M[(size_t)piv * n + j]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const C f = M[(size_t)r * n + c] / M[(size_t)c * n + c];
+      if (f == C(0)) continue;
+      for (int j = c; j < n; ++j) M[(size_t)r * n + j] -= f * M[(size_t)c * n + j];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    C s = b[r];
+    for (int j = r + 1; j < n; ++j) s -= M[(size_t)r * n + j] * b[j];
+    b[r] = s / M[(size_t)r * n + r];
+  }
+  return true;
+}
+
+}  // namespace
+
+bool time_fdm(const TimeLevel &tl, TimeFdm &out) {
+  const int n = tl.nq;
+  // A and B to ~32 digits (hi + lo), then G = B^{-1} A column by column
+  std::vector<R> A((size_t)n * n, 0), B((size_t)n * n, 0);
+  for (int i = 0; i < n; ++i)
+    for (int o = -2; o <= 2; ++o) {
+      const int j = i + o;
+      if (j < 0 || j >= n) continue;
+      A[(size_t)i * n + j] = (R)tl.A[(size_t)i * 5 + o + 2] + (R)tl.Alo[(size_t)i * 5 + o + 2];
+      B[(size_t)i * n + j] = (R)tl.B[(size_t)i * 5 + o + 2] + (R)tl.Blo[(size_t)i * 5 + o + 2];
+    }
+  std::vector<C> Bc((size_t)n * n);
+  for (size_t e = 0; e < Bc.size(); ++e) Bc[e] = C(B[e], 0);
+  std::vector<R> G((size_t)n * n);
+  for (int j = 0; j < n; ++j) {
+    std::vector<C> col(n);
+    for (int i = 0; i < n; ++i) col[i] = C(A[(size_t)i * n + j], 0);
+    if (!complex_solve(n, Bc, col)) return false;
+    for (int i = 0; i < n; ++i) G[(size_t)i * n + j] = col[i].real();
+  }
+  std::vector<C> ev;
+  if (!hessenberg_eigenvalues(n, to_hessenberg(n, G), ev)) return false;
+  // unique eigenvalues: the real ones and one of each conjugate pair (Im > 0)
+  const R tol = 1e-12L;
+  std::vector<C> uniq;
+  std::vector<int> pair;  // 1: stands for a conjugate pair
+  for (const C &l : ev) {
+    if (std::abs(l.imag()) <= tol * std::abs(l)) {
+      uniq.push_back(C(l.real(), 0));
+      pair.push_back(0);
+    } else if (l.imag() > 0) {
+      uniq.push_back(l);
+      pair.push_back(1);
+    }
+  }
+  int total = 0;
+  for (int p : pair) total += p ? 2 : 1;
+  if (total != n) return false;  // unpaired complex eigenvalue
+  // eigenvectors by inverse iteration on (G - lambda I), columns of V for
+  // the full spectrum (the partner of a pair is the conjugate vector)
+  std::vector<C> V((size_t)n * n);
+  std::vector<int> vcol(uniq.size());
+  int col = 0;
+  for (size_t u = 0; u < uniq.size(); ++u) {
+    const C l = uniq[u];
+    std::vector<C> M((size_t)n * n);
+    const R pert = 64 * std::numeric_limits<R>::epsilon() * (std::abs(l) + 1);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        M[(size_t)i * n + j] = C(G[(size_t)i * n + j], 0) - (i == j ? l + C(pert, 0) : C(0));
+    std::vector<C> v(n, C(1));
+    for (int it = 0; it < 3; ++it) {
+      if (!complex_solve(n, M, v)) return false;
+      R nv = 0;
+      for (const C &x : v) nv += std::norm(x);
+      nv = std::sqrt(nv);
+      // fix the phase so that a real eigenvector comes out real
+      int big = 0;
+      for (int i = 1; i < n; ++i)
+        if (std::abs(v[i]) > std::abs(v[big])) big = i;
+      const C ph = std::abs(v[big]) / v[big];
+      for (C &x : v) x *= ph / nv;
+    }
+    if (!pair[u])
+      for (C &x : v) x = C(x.real(), 0);
+    vcol[u] = col;
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + col] = v[i];
+    ++col;
+    if (pair[u]) {
+      for (int i = 0; i < n; ++i) V[(size_t)i * n + col] = std::conj(v[i]);
+      ++col;
+    }
+  }
+  // P = (B V)^{-1}: solve (B V) P = I column by column
+  std::vector<C> BV((size_t)n * n, C(0));
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      C s(0);
+      for (int k = 0; k < n; ++k) s += B[(size_t)i * n + k] * V[(size_t)k * n + j];
+      BV[(size_t)i * n + j] = s;
+    }
+  std::vector<C> P((size_t)n * n);
+  for (int j = 0; j < n; ++j) {
+    std::vector<C> e(n, C(0));
+    e[j] = C(1);
+    if (!complex_solve(n, BV, e)) return false;
+    for (int i = 0; i < n; ++i) P[(size_t)i * n + j] = e[i];
+  }
+  const int nu = (int)uniq.size();
+  out.nq = n;
+  out.nu = nu;
+  out.lam.assign(2 * (size_t)nu, 0.0);
+  out.fin.assign(2 * (size_t)nu * n, 0.0);
+  out.fout.assign(2 * (size_t)n * nu, 0.0);
+  out.ain.assign(2 * (size_t)nu * n, 0.0);
+  out.aout.assign(2 * (size_t)n * nu, 0.0);
+  for (int u = 0; u < nu; ++u) {
+    out.lam[2 * u] = (double)uniq[u].real();
+    out.lam[2 * u + 1] = (double)uniq[u].imag();
+    const int c = vcol[u];
+    const R w = pair[u] ? 2 : 1;  // a pair contributes 2 Re(.)
+    for (int j = 0; j < n; ++j) {
+      const C fi = P[(size_t)c * n + j], fo = w * V[(size_t)j * n + c];
+      const C ai = V[(size_t)j * n + c], ao = w * P[(size_t)c * n + j];
+      out.fin[2 * ((size_t)u * n + j)] = (double)fi.real();
+      out.fin[2 * ((size_t)u * n + j) + 1] = (double)fi.imag();
+      out.fout[2 * ((size_t)j * nu + u)] = (double)fo.real();
+      out.fout[2 * ((size_t)j * nu + u) + 1] = (double)fo.imag();
+      out.ain[2 * ((size_t)u * n + j)] = (double)ai.real();
+      out.ain[2 * ((size_t)u * n + j) + 1] = (double)ai.imag();
+      out.aout[2 * ((size_t)j * nu + u)] = (double)ao.real();
+      out.aout[2 * ((size_t)j * nu + u) + 1] = (double)ao.imag();
+    }
+  }
+  return true;
 }
 
 }  // namespace sg

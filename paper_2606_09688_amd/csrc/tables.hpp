@@ -70,6 +70,14 @@ void pencil_eigen(int a, double len, const std::vector<double> &c2e, std::vector
 void pencil_2d(int a, const double *len, const int *ncell, const double *c_vals,
                std::vector<double> &K, std::vector<double> &M);
 
+// c^2-weighted 1-D P1 stiffness and mass of level a on (0, len) for c
+// piecewise constant on ncell uniform blocks (c_row: the block values), each
+// entry integrated exactly over the parts of its elements in every block:
+// [4][n] = K diagonal, K coupling (k, k+1), M diagonal, M coupling (k, k+1),
+// n = 2^a - 1 (coupling entries 0 at the last node).  One strip of 2-D
+// wave-speed blocks, whose speed depends on x only.
+std::vector<double> strip_x_tables(int a, double len, int ncell, const double *c_row);
+
 // Tridiagonal M and K(c) of level a (d = 1) per interior node k, kSpaceStride
 // doubles: [M_kk, M_{k,k+1}, K_kk, K_{k,k+1}, lo(K_kk), lo(K_{k,k+1})] (the
 // coupling entries are 0 at the last node).  K is formed in double-double
@@ -85,6 +93,28 @@ std::vector<double> space_entries(int a, double len, int ncell, const double *c_
 // = D_k^{-1} and Lf[k] = L_k (row-major nq x nq each, Lf[0] unused).
 void block_lu(const TimeLevel &tl, const std::vector<double> &mk, int nx,
               std::vector<double> &Dinv, std::vector<double> &Lf);
+
+// Diagonalisation of a short time level (fast diagonalisation in time):
+// B^{-1} A = V diag(lam) V^{-1}, A and B the time matrices of Prop. 1, in
+// extended precision (Hessenberg reduction, shifted complex QR, inverse
+// iteration).  The spectrum of a real pencil is closed under conjugation;
+// only the real eigenvalues and one member (Im > 0) of each conjugate pair
+// are kept, nu in all.  With P = (B V)^{-1} the component system
+// S = A (x) M + B (x) K is solved as
+//   forward:  r_u = sum_j fin[u][j] b_j,   (lam_u M + K) w_u = r_u,
+//             u_j = Re sum_u fout[j][u] w_u;
+//   adjoint (S^T z = y): r_u = sum_j ain[u][j] y_j, the same spatial
+//             systems, z_j = Re sum_u aout[j][u] w_u;
+// fin/ain are P's and V^T's rows, fout/aout V's and P^T's columns, times 2
+// for a conjugate pair (its partner contributes the conjugate).  Complex
+// values are interleaved (re, im).  Returns false if the iteration fails.
+struct TimeFdm {
+  int nq = 0, nu = 0;
+  std::vector<double> lam;         // [nu] complex
+  std::vector<double> fin, ain;    // [nu][nq] complex
+  std::vector<double> fout, aout;  // [nq][nu] complex
+};
+bool time_fdm(const TimeLevel &tl, TimeFdm &out);
 
 // Orthonormal DST-I matrix of level a: Q[j][k] = sqrt(2/n) sin(pi j k/n),
 // j,k = 1..n-1, n = 2^a (symmetric, Q Q = I), row-major (n-1)^2.

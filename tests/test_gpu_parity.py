@@ -140,6 +140,10 @@ VARC2 = [
     ([1.0, 0.8], [2, 2], _speeds(4, 72), 1.3, 5),
     ([1.0, 1.0], [4, 4], _speeds(16, 73), 1.0, 6),
     ([1.0, 1.0], [4, 4], _speeds(16, 74), 1.0, 7),   # spatial level 6: 3969-node pencil
+    # spatial level 7: time diagonalisation + strips (3 interface rows)
+    ([1.0, 1.0], [4, 4], _speeds(16, 75), 1.0, 8),
+    ([1.0, 0.8], [2, 2], _speeds(4, 76), 1.3, 8),    # non-square, one interface row
+    ([1.0, 1.0], [4, 1], _speeds(4, 77), 0.8, 8),    # speed varies in x only: no interface
 ]
 
 
@@ -187,11 +191,26 @@ def test_variable_speed_parity_2d(case):
     _variable_speed_parity(2, lengths, ncell, cv, T, L)
 
 
-def test_variable_speed_2d_beyond_level_6_is_refused():
+@pytest.mark.parametrize("case", [([1.0, 1.0], [4, 4], _speeds(16, 78), 1.0, 6),
+                                  ([1.2, 1.0], [2, 4], _speeds(8, 79), 0.9, 7)],
+                         ids=["d2L6c4x4", "d2L7c2x4"])
+def test_strip_solver_from_level_3(case, monkeypatch):
+    """The time-diagonalisation + strip solver forced down to spatial level 3
+    (SG_FDM_LEVEL): strips of one to seven rows, time levels of 3 to 17 nodes,
+    next to dense-pencil components; forward, components and adjoint vs the
+    oracle."""
+    monkeypatch.setenv("SG_FDM_LEVEL", "3")
+    lengths, ncell, cv, T, L = case
+    _variable_speed_parity(2, lengths, ncell, cv, T, L)
+
+
+def test_variable_speed_2d_long_time_level_is_refused():
+    """Spatial level 7 with a time level of 33 nodes (L = 12) is outside the
+    strip solver (time levels of at most 17 nodes) and the dense pencils."""
     _torch()
     import paper_2606_09688_amd as sg
     with pytest.raises(sg.SGError):
-        sg.SparseGridWave(2, [1.0, 1.0], [2, 2], [1.0, 0.5, 0.7, 1.2], 1.0, 8)
+        sg.SparseGridWave(2, [1.0, 1.0], [2, 2], [1.0, 0.5, 0.7, 1.2], 1.0, 12)
 
 
 @pytest.mark.parametrize("case", [CASES[2], CASES[4], CASES[7], CASES[9]],

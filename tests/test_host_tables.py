@@ -156,3 +156,36 @@ def test_mass_of_level1_interpolant_is_fixed_stencil():
         else:
             got[m - 1] = h / 2 * (zp[K] + zp[K + 1])
     assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("b,T", [(1, 1.0), (2, 1.0), (3, 1.0), (3, 0.7), (4, 1.0), (5, 2.0)])
+def test_host_time_diagonalisation_solves_oracle_systems(b, T):
+    """The time diagonalisation used for the 2-D variable-speed components
+    (B^{-1} A = V diag(lam) V^{-1}, Prop. 1 time matrices): with a scalar
+    spatial pair (M, K) = (1, mu) the component system is A + mu B, and its
+    solution (and that of the transpose) assembled from the returned tables
+    equals a dense solve with the oracle's exact time matrices.  The unique
+    eigenvalues are the oracle's spectrum, one of each conjugate pair."""
+    import paper_2606_09688_amd as sg
+    dd = timemat.time_matrices_dd(b, T)
+    A = timemat.band_to_dense(dd["A_hi"]) + timemat.band_to_dense(dd["A_lo"])
+    B = timemat.band_to_dense(dd["B_hi"]) + timemat.band_to_dense(dd["B_lo"])
+    h = sg.host_time_fdm(b, T)
+    lam = h["lam"]
+    nq = 2 ** b + 1
+    ref = np.linalg.eigvals(np.linalg.solve(B, A))
+    full = np.concatenate([lam, np.conj(lam[np.abs(lam.imag) > 0])])
+    assert full.size == nq
+    key = lambda z: (round(z.real, 6), round(z.imag, 6))
+    assert np.allclose(sorted(full, key=key), sorted(ref, key=key), rtol=1e-10)
+    assert np.all(lam.imag >= 0)
+    rng = np.random.default_rng(b)
+    for mu in (0.0, 3.7, 250.0, 1e5):
+        rhs = rng.standard_normal(nq)
+        S = A + mu * B
+        x_ref = np.linalg.solve(S, rhs)
+        x = np.real(h["fout"] @ ((h["fin"] @ rhs) / (lam + mu)))
+        assert np.abs(x - x_ref).max() <= 1e-12 * np.abs(x_ref).max(), mu
+        z_ref = np.linalg.solve(S.T, rhs)
+        z = np.real(h["aout"] @ ((h["ain"] @ rhs) / (lam + mu)))
+        assert np.abs(z - z_ref).max() <= 1e-12 * np.abs(z_ref).max(), mu
