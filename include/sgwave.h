@@ -65,10 +65,14 @@ typedef enum {
  *   T       final time > 0.   L  sparse level, 2 <= L <= 16.
  * On success *out receives a handle bound to the current HIP device; all
  * tables are uploaded and all workspace is allocated here.  A wave speed
- * that varies in 2-D is supported up to L = 7 (spatial levels <= 6, whose
- * dense pencils are diagonalised here with rocSOLVER); beyond that, and for
- * 1-D variable speed on spatial levels >= 9 with more than 64 time nodes,
- * SG_ENOTSUP.
+ * that varies in 2-D is handled per component: spatial levels <= 5 (and 6
+ * with more than 17 time nodes) through the dense pencil (K(c), M),
+ * diagonalised here with rocSOLVER; spatial levels >= 6 with at most 17 time
+ * nodes by diagonalising the time matrices and solving each shifted spatial
+ * system directly by strips of wave-speed blocks (at least two mesh rows per
+ * block along y, at most 4096 interface nodes).  A component outside both
+ * (e.g. spatial level 7 with 33 time nodes, L >= 12), and 1-D variable speed
+ * on spatial levels >= 9 with more than 64 time nodes: SG_ENOTSUP.
  */
 sg_status sg_assemble(int d, const double *len, const int *ncell,
                       const double *c_vals, double T, int L, sg_problem **out);

@@ -28,10 +28,11 @@ constexpr int kEig2MaxLevel = 6;
 // time levels that may be diagonalised (2^b + 1 <= 33 nodes)
 constexpr int kFdmMaxLevel = 5;
 // 2-D variable speed solved by time diagonalisation and strips: spatial
-// levels from kFdmMinLevel up, time levels up to kFdmMaxTimeLevel (17 nodes:
+// levels from kFdmMinLevel up (level 6 too: its dense pencil would hold two
+// 3969 x 3969 matrices per problem), time levels up to kFdmMaxTimeLevel (17 nodes:
 // the eigenvector matrix of the time pencil has condition number <= 1.3e3),
 // interface systems of at most kFdmMaxInterface nodes (dense complex inverse)
-constexpr int kFdmMinLevel = 7;
+constexpr int kFdmMinLevel = 6;
 constexpr int kFdmMaxTimeLevel = 4;
 constexpr long long kFdmMaxInterface = 4096;
 
