@@ -223,18 +223,33 @@ sg_status sg_destroy(sg_problem *p);
 const char *sg_last_error(void);
 
 /*
- * Batches of independent problems (any mix of d, L and wave speeds).  A batch
- * references n assembled handles (the caller keeps them alive and owns them)
- * and captures the forward solve - and the adjoint when g is not NULL - of
- * every problem into one HIP graph with one parallel branch per problem
- * (forked from and joined into the capturing stream through events).
- * Argument arrays hold n device pointers each (host arrays); g, df, du0, dv0
- * may be NULL as a whole, or df / du0 / dv0 entries NULL per problem.
- * A handle must not belong to two batches or be used elsewhere while its
- * batch graph runs.
+ * Batches of independent problems (any mix of d, L and wave speeds; the
+ * components of every problem are independent, Rem. 2).  A batch references
+ * n assembled handles (the caller keeps them alive and owns them).  The
+ * streaming passes of every problem (restriction of the data, prolongation
+ * into the outputs) run on parallel branch streams forked from and joined
+ * into the caller's stream; each solve stage (time-diagonalised strip
+ * solves, block solves, sine / eigenvector transforms, per-mode time solves,
+ * load and adjoint post-passes) runs as ONE launch over the concatenated
+ * work lists of all problems, longest contractions and time levels first.
+ * Argument arrays hold n device pointers each (host arrays).
+ * sg_batch_create: builds the merged work lists (allocates device memory).
+ * sg_batch_solve / sg_batch_adjoint: the batched forward / adjoint, stream
+ *   ordered, allocation-free; results equal each problem's sg_solve /
+ *   sg_adjoint bit for bit.  In the adjoint, df, du0, dv0 may be NULL as a
+ *   whole or per problem.
+ * sg_batch_capture: captures sg_batch_solve (and sg_batch_adjoint when g is
+ *   not NULL) into one HIP graph owned by the batch; sg_batch_launch replays
+ *   it.
+ * A handle must not belong to two batches that run at once, nor be used
+ * elsewhere while its batch runs.
  */
 typedef struct sg_batch sg_batch;
 sg_status sg_batch_create(int n, sg_problem *const *problems, sg_batch **out);
+sg_status sg_batch_solve(sg_batch *b, const double *const *f, const double *const *u0,
+                         const double *const *v0, double *const *U, hipStream_t stream);
+sg_status sg_batch_adjoint(sg_batch *b, const double *const *g, double *const *df,
+                           double *const *du0, double *const *dv0, hipStream_t stream);
 sg_status sg_batch_capture(sg_batch *b, const double *const *f, const double *const *u0,
                            const double *const *v0, double *const *U, const double *const *g,
                            double *const *df, double *const *du0, double *const *dv0,

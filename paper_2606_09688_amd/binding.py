@@ -51,6 +51,10 @@ SIGNATURES = {
     "sg_batch_capture": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_void_p)] * 8
                          + [ctypes.c_void_p]),
     "sg_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_batch_solve": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_void_p)] * 4
+                       + [ctypes.c_void_p]),
+    "sg_batch_adjoint": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_void_p)] * 4
+                         + [ctypes.c_void_p]),
     "sg_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sg_set_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                      ctypes.c_int]),
@@ -322,9 +326,11 @@ class SparseGridWave:
 
 
 class SparseGridBatch:
-    """Independent problems (any mix of d, L, speeds) captured into one HIP
-    graph, one parallel branch per problem (sg_batch_*).  The solvers must
-    stay alive while the batch exists."""
+    """Independent problems (any mix of d, L, speeds) run together
+    (sg_batch_*): streaming passes per problem on parallel branch streams,
+    one launch per solve stage for all problems; eager (solve, adjoint) or
+    captured into one HIP graph (capture, replay).  The solvers must stay
+    alive while the batch exists."""
 
     def __init__(self, solvers):
         self._solvers = list(solvers)
@@ -344,25 +350,38 @@ class SparseGridBatch:
                 pass
             self._h = None
 
+    def _ptrs(self, lst, space, name, allow_none=False):
+        if lst is None:
+            return None
+        n = len(self._solvers)
+        if len(lst) != n:
+            raise ValueError(f"{name} needs one entry per problem")
+        shapes = [s.space_shape if space else s.shape for s in self._solvers]
+        out = [_ptr(t, shp, f"{name}[{i}]", allow_none)
+               for i, (t, shp) in enumerate(zip(lst, shapes))]
+        return (ctypes.c_void_p * n)(*[None if v is None else v.value for v in out])
+
+    def solve(self, f, u0, v0, U, stream=None):
+        """Batched forward: lists of device tensors (one per problem)."""
+        check(lib().sg_batch_solve(self._h, self._ptrs(f, False, "f"), self._ptrs(u0, True, "u0"),
+                                   self._ptrs(v0, True, "v0"), self._ptrs(U, False, "U"),
+                                   _stream(stream)), "sg_batch_solve")
+
+    def adjoint(self, g, df=None, du0=None, dv0=None, stream=None):
+        """Batched adjoint; df / du0 / dv0 lists (or entries) may be None."""
+        check(lib().sg_batch_adjoint(self._h, self._ptrs(g, False, "g"),
+                                     self._ptrs(df, False, "df", True),
+                                     self._ptrs(du0, True, "du0", True),
+                                     self._ptrs(dv0, True, "dv0", True), _stream(stream)),
+              "sg_batch_adjoint")
+
     def capture(self, f, u0, v0, U, g=None, df=None, du0=None, dv0=None, stream=None):
         """Lists (one entry per problem) of device tensors, shapes as for
         SparseGridWave; g/df/du0/dv0 may be None (forward only)."""
-        n = len(self._solvers)
-
-        def ptrs(lst, shapes, name, allow_none=False):
-            if lst is None:
-                return None
-            if len(lst) != n:
-                raise ValueError(f"{name} needs one entry per problem")
-            out = [_ptr(t, shp, f"{name}[{i}]", allow_none)
-                   for i, (t, shp) in enumerate(zip(lst, shapes))]
-            return (ctypes.c_void_p * n)(*[None if v is None else v.value for v in out])
-
-        sh = [s.shape for s in self._solvers]
-        ssh = [s.space_shape for s in self._solvers]
-        args = [ptrs(f, sh, "f"), ptrs(u0, ssh, "u0"), ptrs(v0, ssh, "v0"), ptrs(U, sh, "U"),
-                ptrs(g, sh, "g"), ptrs(df, sh, "df", True), ptrs(du0, ssh, "du0", True),
-                ptrs(dv0, ssh, "dv0", True)]
+        P = self._ptrs
+        args = [P(f, False, "f"), P(u0, True, "u0"), P(v0, True, "v0"), P(U, False, "U"),
+                P(g, False, "g"), P(df, False, "df", True), P(du0, True, "du0", True),
+                P(dv0, True, "dv0", True)]
         self._keep = (f, u0, v0, U, g, df, du0, dv0)  # buffers referenced by the graph
         check(lib().sg_batch_capture(self._h, *args, _stream(stream)), "sg_batch_capture")
 

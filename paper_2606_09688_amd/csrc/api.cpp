@@ -74,27 +74,33 @@ struct Pass {
   TapEntry *d_taps = nullptr;     // per-slab taps of the in-tile channels (16-tiles)
 };
 
+// Descriptor lists keep a host copy (h) next to the device array (d):
+// batches of problems concatenate the host copies into merged launches.
 struct GemmList {
   GemmDesc *d = nullptr;
   int n = 0, tiles = 0;
   int fold = 0;                   // GemmDesc.fold mode of every descriptor
+  std::vector<GemmDesc> h;
 };
 
 struct SolveList {
   SolveDesc *d = nullptr;
   int n = 0;
   long long threads = 0;
+  std::vector<SolveDesc> h;
 };
 
 struct CompList {
   CompDesc *d = nullptr;
   int n = 0;
   long long total = 0;
+  std::vector<CompDesc> h;
 };
 
 struct BlockList {       // components solved by block LU + refinement
   BlockDesc *d = nullptr;
   int n = 0;
+  std::vector<BlockDesc> h;
 };
 
 struct FdmList {         // 2-D variable-speed components solved by time diagonalisation
@@ -102,6 +108,7 @@ struct FdmList {         // 2-D variable-speed components solved by time diagona
   int n = 0;
   FdmTotals t;
   GemmList gf, gi;       // strip sine transforms X -> Y and Y -> X
+  std::vector<FdmDesc> h;
 };
 
 // Per-call scratch of the streaming passes: partial blocks of the in-tile
@@ -195,6 +202,7 @@ struct sg_problem {
   CompList cload, cadj;
   std::vector<CompList> pcload;
   LevelDesc *d_lev = nullptr;
+  std::vector<LevelDesc> h_lev;
   int nlev = 0;
   long long lev_total = 0;
   // graph
@@ -602,6 +610,10 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
     }
   }
   sg_status st;
+  gx.h = vx;
+  gix.h = vix;
+  gy.h = vy;
+  giy.h = viy;
   if ((st = upload(p, vx, &gx.d)) != SG_OK) return st;
   gx.n = (int)vx.size(); gx.tiles = tx; gx.fold = any_fx ? 1 : 0;
   if ((st = upload(p, vix, &gix.d)) != SG_OK) return st;
@@ -643,10 +655,14 @@ sg_status build_solve_list(sg_problem *p, const std::vector<int> &cset, int tran
       sd.flat = p->d == 2 && !p->const_c ? 1 : 0;
       sd.c2 = p->c2;
       sd.thread0 = th;
+      sd.kt = p->d_kt;
+      sd.mt = p->d_mt;
+      sd.d = p->d;
       th += wave ? 64LL * C.nsp : (C.nsp + 63) / 64 * 64;
       v.push_back(sd);
     }
   sg_status st;
+  L.h = v;
   if ((st = upload(p, v, &L.d)) != SG_OK) return st;
   L.n = (int)v.size();
   L.threads = th;
@@ -671,10 +687,10 @@ sg_status run_solves(sg_problem *p, const GemmList &gx, const GemmList &gy,
                      const BlockList &bl, const FdmList &fl, hipStream_t s) {
   sg_status st;
   if ((st = run_fdm(fl, s))) return st;
-  HIPCHK(launch_block_solve(bl.d, bl.n, p->d_kt, s));
+  HIPCHK(launch_block_solve(bl.d, bl.n, s));
   HIPCHK(launch_gemm(gx.d, gx.n, gx.tiles, gx.fold, s));
   if (p->d == 2) HIPCHK(launch_gemm(gy.d, gy.n, gy.tiles, gy.fold, s));
-  HIPCHK(launch_time_solve(sl.d, sl.n, sl.threads, p->d_kt, p->d_mt, p->d, s));
+  HIPCHK(launch_time_solve(sl.d, sl.n, sl.threads, s));
   if (p->d == 2) HIPCHK(launch_gemm(giy.d, giy.n, giy.tiles, giy.fold, s));
   HIPCHK(launch_gemm(gix.d, gix.n, gix.tiles, gix.fold, s));
   return SG_OK;
@@ -718,6 +734,7 @@ sg_status build_fdm(sg_problem *p, const std::vector<TimeLevel> &tl_host) {
       tt[C.b] = t;
     }
     const TimeTabs &T = tt[C.b];
+    if (T.nu > kFdmMaxNu) return fail(SG_ENOTSUP, "too many time eigenvalues for the strip solver");
     const int n = (1 << C.a) - 1, ns = p->ncell[1], m = (n + 1) / ns - 1, ni = ns - 1;
     if (!dst.count(m)) {
       int am = 0;
@@ -829,7 +846,10 @@ sg_status build_fdm(sg_problem *p, const std::vector<TimeLevel> &tl_host) {
     pl.gi.tiles = pti;
   }
   for (FdmList *L : {&p->ffwd, &p->fadj}) {
-    if ((st = upload(p, L == &p->ffwd ? vf : va, &L->d))) return st;
+    L->h = L == &p->ffwd ? vf : va;
+    L->gf.h = gf;
+    L->gi.h = gi;
+    if ((st = upload(p, L->h, &L->d))) return st;
     L->n = (int)vf.size();
     L->t = tot;
     if ((st = upload(p, gf, &L->gf.d)) || (st = upload(p, gi, &L->gi.d))) return st;
@@ -1333,6 +1353,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
         return bail(fail(SG_ENOMEM, "hipMalloc of block-solver workspace failed"));
       bd.Dinv = dD; bd.Lf = dL; bd.mk = dmk; bd.work = work;
       bd.nq = C.nq; bd.nx = C.nsp; bd.b = C.b; bd.refine = 4;
+      bd.kt = p->d_kt;
       bd.in = p->bufB + C.off; bd.out = p->bufU + C.off; bd.transpose = 0;
       vf.push_back(bd);
       if ((st = upload(p, std::vector<BlockDesc>{bd}, &p->pbfwd[ci].d))) return bail(st);
@@ -1340,6 +1361,8 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
       bd.in = p->bufZ + C.off; bd.out = p->bufW + C.off; bd.transpose = 1;
       va.push_back(bd);
     }
+    p->bfwd.h = vf;
+    p->badj.h = va;
     if ((st = upload(p, vf, &p->bfwd.d)) || (st = upload(p, va, &p->badj.d))) return bail(st);
     p->bfwd.n = (int)vf.size();
     p->badj.n = (int)va.size();
@@ -1350,8 +1373,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
     if (fst != SG_OK) return bail(fst);
   }
   // LU factors of every mode's time matrix, shared by all later solves
-  HIPCHK(launch_time_factor(p->sfwd.d, p->sfwd.n, p->sfwd.threads, p->d_kt, p->d_mt, d,
-                            nullptr));
+  HIPCHK(launch_time_factor(p->sfwd.d, p->sfwd.n, p->sfwd.threads, nullptr));
   p->pgx.resize(ncomp); p->pgy.resize(ncomp); p->pgiy.resize(ncomp); p->pgix.resize(ncomp);
   p->psfwd.resize(ncomp);
   p->pcload.resize(ncomp);
@@ -1373,6 +1395,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
       cd.mv = p->mv_lv[C.a];
       cd.ku = p->ku_lv[C.a];
       cd.a = C.a; cd.b = C.b; cd.nq = C.nq; cd.nsp = C.nsp; cd.sign = C.sign;
+      cd.kt = p->d_kt;
       cd.start = tl;
       tl += (long long)C.nq * C.nsp;
       vl.push_back(cd);
@@ -1388,6 +1411,8 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
       p->pcload[ci].n = 1;
       p->pcload[ci].total = (long long)C.nq * C.nsp;
     }
+    p->cload.h = vl;
+    p->cadj.h = va;
     if ((st = upload(p, vl, &p->cload.d))) return bail(st);
     p->cload.n = ncomp;
     p->cload.total = tl;
@@ -1405,6 +1430,8 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
       L.c1 = comp_index(a, 1);
       L.fv = p->fv_lv[a];
       L.fu = p->fu_lv[a];
+      L.cd = p->cadj.d;
+      L.kt = p->d_kt;
       int nqmax = 0;
       if (L.c0 >= 0) nqmax = std::max(nqmax, p->comps[L.c0].nq);
       if (L.c1 >= 0) nqmax = std::max(nqmax, p->comps[L.c1].nq);
@@ -1414,6 +1441,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
       tt += L.wave ? 64LL * L.nsp : L.nsp;
       lv.push_back(L);
     }
+    p->h_lev = lv;
     if ((st = upload(p, lv, &p->d_lev))) return bail(st);
     p->nlev = J;
     p->lev_total = tt;
@@ -1478,7 +1506,7 @@ static sg_status solve_fused(sg_problem *p, const Scratch &ws, const double *f,
   MARK(p, 0, s);
   if ((st = forward_fields(p, ws, u0, v0, s))) return st;
   if ((st = run_restrict(p, ws, p->load, f, 1, s, 1))) return st;
-  HIPCHK(launch_post_load(p->cload.d, p->cload.n, p->cload.total, p->d_kt, s));
+  HIPCHK(launch_post_load(p->cload.d, p->cload.n, p->cload.total, s));
   MARK(p, 3, s);
   if ((st = run_solves(p, p->gx, p->gy, p->sfwd, p->giy, p->gix, p->bfwd, p->ffwd, s)))
     return st;
@@ -1531,7 +1559,7 @@ sg_status sg_solve_plain(sg_problem *p, const double *f, const double *u0,
   if ((st = forward_fields(p, p->ws, u0, v0, s))) return st;
   for (size_t ci = 0; ci < p->comps.size(); ++ci) {
     if ((st = run_restrict(p, p->ws, p->plain_load[ci], f, 1, s))) return st;
-    HIPCHK(launch_post_load(p->pcload[ci].d, 1, p->pcload[ci].total, p->d_kt, s));
+    HIPCHK(launch_post_load(p->pcload[ci].d, 1, p->pcload[ci].total, s));
     if ((st = run_solves(p, p->pgx[ci], p->pgy[ci], p->psfwd[ci], p->pgiy[ci], p->pgix[ci],
                          p->pbfwd[ci], p->pffwd[ci], s)))
       return st;
@@ -1551,20 +1579,20 @@ sg_status sg_adjoint(sg_problem *p, const double *g, double *df, double *du0, do
   // z_c = S_c^{-T} y_c  (y_c in bufZ, z_c into bufW)
   MARK(p, 10, s);
   if ((st = run_fdm(p->fadj, s))) return st;
-  HIPCHK(launch_block_solve(p->badj.d, p->badj.n, p->d_kt, s));
+  HIPCHK(launch_block_solve(p->badj.d, p->badj.n, s));
   HIPCHK(launch_gemm(p->agx.d, p->agx.n, p->agx.tiles, p->agx.fold, s));
   if (p->d == 2) HIPCHK(launch_gemm(p->gy.d, p->gy.n, p->gy.tiles, p->gy.fold, s));
-  HIPCHK(launch_time_solve(p->sadj.d, p->sadj.n, p->sadj.threads, p->d_kt, p->d_mt, p->d, s));
+  HIPCHK(launch_time_solve(p->sadj.d, p->sadj.n, p->sadj.threads, s));
   if (p->d == 2) HIPCHK(launch_gemm(p->giy.d, p->giy.n, p->giy.tiles, p->giy.fold, s));
   HIPCHK(launch_gemm(p->agix.d, p->agix.n, p->agix.tiles, p->agix.fold, s));
   MARK(p, 11, s);
   // zeta_c = D^T z_c, level fields for du0 / dv0
-  HIPCHK(launch_post_adjoint(p->cadj.d, p->cadj.n, p->cadj.total, p->d_kt, s));
+  HIPCHK(launch_post_adjoint(p->cadj.d, p->cadj.n, p->cadj.total, s));
   if (df) {
     if ((st = run_prolong(p, p->adjp, nullptr, df, 0, 1, s, 12))) return st;
   }
   if (du0 || dv0) {
-    HIPCHK(launch_adjoint_fields(p->d_lev, p->nlev, p->lev_total, p->cadj.d, p->d_kt, s));
+    HIPCHK(launch_adjoint_fields(p->d_lev, p->nlev, p->lev_total, s));
     if ((st = run_prolong(p, p->fieldp, nullptr, p->fine2, 0, 0, s))) return st;
     const double hx = p->len[0] / p->N, hy = p->len[1] / p->N;
     HIPCHK(launch_fine_stencils(p->d, p->N, p->d_ce, hx, hy, p->fine2, p->fine2 + p->nsp_fine,
@@ -1780,13 +1808,260 @@ sg_status sg_graph_capture(sg_problem *p, const double *f, const double *u0,
 
 }  // extern "C"
 
+// A batch of independent assembled problems.  Streaming passes (restriction
+// of the data, prolongation into U / df / du0 / dv0) run per problem on
+// parallel branch streams; every solve stage runs once for all problems,
+// over the concatenated descriptor lists of all their components (the
+// largest components first).
 struct sg_batch {
   std::vector<sg_problem *> probs;
-  std::vector<hipStream_t> streams;  // fork/join branches used while capturing
-  std::vector<hipEvent_t> events;
+  std::vector<hipStream_t> streams;  // branch streams (default priority)
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;   // one per branch stream
+  std::vector<void *> allocs;
+  GemmList gx, gy, giy, gix, agx, agix;
+  SolveList sfwd, sadj;
+  BlockList bfwd, badj;
+  FdmList ffwd, fadj;
+  CompList cload, cadj;
+  LevelDesc *d_lev = nullptr;
+  int nlev = 0;
+  long long lev_total = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
 };
+
+namespace {
+
+template <class T>
+sg_status bupload(sg_batch *b, const std::vector<T> &h, T **out) {
+  void *d = nullptr;
+  if (hipMalloc(&d, std::max<size_t>(1, h.size()) * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SG_ENOMEM, "hipMalloc of batch descriptors failed");
+  }
+  b->allocs.push_back(d);
+  if (!h.empty()) HIPCHK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  *out = static_cast<T *>(d);
+  return SG_OK;
+}
+
+// GEMM descriptors of all problems, longest contraction first (stable),
+// tiles renumbered
+sg_status merge_gemm(sg_batch *b, GemmList sg_problem::*member, GemmList &out) {
+  std::vector<GemmDesc> v;
+  for (sg_problem *p : b->probs) {
+    const GemmList &L = p->*member;
+    v.insert(v.end(), L.h.begin(), L.h.end());
+    out.fold = std::max(out.fold, L.fold);
+  }
+  std::stable_sort(v.begin(), v.end(), [](const GemmDesc &x, const GemmDesc &y) { return x.K > y.K; });
+  int t = 0;
+  for (GemmDesc &g : v) {
+    g.tile0 = t;
+    t += g.batch * g.tm * g.tn;
+  }
+  out.h = v;
+  out.n = (int)v.size();
+  out.tiles = t;
+  return bupload(b, v, &out.d);
+}
+
+sg_status merge_gemm_list(sg_batch *b, const std::vector<const GemmList *> &lists,
+                          GemmList &out) {
+  std::vector<GemmDesc> v;
+  for (const GemmList *L : lists) v.insert(v.end(), L->h.begin(), L->h.end());
+  std::stable_sort(v.begin(), v.end(), [](const GemmDesc &x, const GemmDesc &y) { return x.K > y.K; });
+  int t = 0;
+  for (GemmDesc &g : v) {
+    g.tile0 = t;
+    t += g.batch * g.tm * g.tn;
+  }
+  out.h = v;
+  out.n = (int)v.size();
+  out.tiles = t;
+  return bupload(b, v, &out.d);
+}
+
+// time solves: one-wave-per-mode descriptors first (longest time levels
+// first), then the thread-per-mode ones
+sg_status merge_solve(sg_batch *b, SolveList sg_problem::*member, SolveList &out) {
+  std::vector<SolveDesc> w, t;
+  for (sg_problem *p : b->probs)
+    for (const SolveDesc &d : (p->*member).h) (d.wave ? w : t).push_back(d);
+  std::stable_sort(w.begin(), w.end(), [](const SolveDesc &x, const SolveDesc &y) { return x.nq > y.nq; });
+  std::vector<SolveDesc> v(w);
+  v.insert(v.end(), t.begin(), t.end());
+  long long th = 0;
+  for (SolveDesc &d : v) {
+    d.thread0 = th;
+    th += d.wave ? 64LL * d.nmodes : (d.nmodes + 63) / 64 * 64;
+  }
+  out.h = v;
+  out.n = (int)v.size();
+  out.threads = th;
+  return bupload(b, v, &out.d);
+}
+
+sg_status merge_block(sg_batch *b, BlockList sg_problem::*member, BlockList &out) {
+  std::vector<BlockDesc> v;
+  for (sg_problem *p : b->probs) v.insert(v.end(), (p->*member).h.begin(), (p->*member).h.end());
+  out.h = v;
+  out.n = (int)v.size();
+  return bupload(b, v, &out.d);
+}
+
+sg_status merge_comp(sg_batch *b, CompList sg_problem::*member, CompList &out) {
+  std::vector<CompDesc> v;
+  long long tot = 0;
+  for (sg_problem *p : b->probs)
+    for (CompDesc d : (p->*member).h) {
+      d.start = tot;
+      tot += (long long)d.nq * d.nsp;
+      v.push_back(d);
+    }
+  out.h = v;
+  out.n = (int)v.size();
+  out.total = tot;
+  return bupload(b, v, &out.d);
+}
+
+sg_status merge_fdm(sg_batch *b, FdmList sg_problem::*member, FdmList &out) {
+  std::vector<FdmDesc> v;
+  std::vector<const GemmList *> gf, gi;
+  for (sg_problem *p : b->probs) {
+    const FdmList &L = p->*member;
+    v.insert(v.end(), L.h.begin(), L.h.end());
+    gf.push_back(&L.gf);
+    gi.push_back(&L.gi);
+  }
+  std::stable_sort(v.begin(), v.end(), [](const FdmDesc &x, const FdmDesc &y) { return x.n > y.n; });
+  FdmTotals t;
+  for (FdmDesc &d : v) {
+    d.node0 = t.node;
+    d.tri0 = t.tri;
+    d.edge0 = t.edge;
+    d.if0 = t.iface;
+    d.gemv0 = t.gemv;
+    t.node += (long long)d.n * d.n;
+    t.tri += (long long)d.nu * d.ns * d.m;
+    t.edge += d.ni > 0 ? (long long)d.nu * d.ns * d.n : 0;
+    t.iface += (long long)d.nu * d.ni * d.n;
+    t.gemv += (long long)d.nu * d.ni * d.n;
+  }
+  out.h = v;
+  out.n = (int)v.size();
+  out.t = t;
+  sg_status st;
+  if ((st = bupload(b, v, &out.d))) return st;
+  if ((st = merge_gemm_list(b, gf, out.gf))) return st;
+  return merge_gemm_list(b, gi, out.gi);
+}
+
+// fork the batch's branch streams off s / join them back into s
+sg_status fork(sg_batch *b, hipStream_t s) {
+  HIPCHK(hipEventRecord(b->fork_ev, s));
+  for (hipStream_t bs : b->streams) HIPCHK(hipStreamWaitEvent(bs, b->fork_ev, 0));
+  return SG_OK;
+}
+sg_status join(sg_batch *b, hipStream_t s) {
+  for (size_t k = 0; k < b->streams.size(); ++k) {
+    HIPCHK(hipEventRecord(b->join_ev[k], b->streams[k]));
+    HIPCHK(hipStreamWaitEvent(s, b->join_ev[k], 0));
+  }
+  return SG_OK;
+}
+
+sg_status batch_forward(sg_batch *b, const double *const *f, const double *const *u0,
+                        const double *const *v0, double *const *U, hipStream_t s) {
+  const int n = (int)b->probs.size();
+  if (!f || !u0 || !v0 || !U) return fail(SG_EINVAL, "NULL argument array");
+  for (int i = 0; i < n; ++i) {
+    if (!f[i] || !u0[i] || !v0[i] || !U[i]) return fail(SG_EINVAL, "NULL data pointer");
+    if (U[i] == f[i]) return fail(SG_EINVAL, "U must not alias f");
+  }
+  sg_status st;
+  if ((st = fork(b, s))) return st;
+  for (int i = 0; i < n; ++i) {
+    sg_problem *p = b->probs[i];
+    hipStream_t bs = b->streams[i % b->streams.size()];
+    if ((st = forward_fields(p, p->ws, u0[i], v0[i], bs))) return st;
+    if ((st = run_restrict(p, p->ws, p->load, f[i], 1, bs))) return st;
+  }
+  if ((st = join(b, s))) return st;
+  HIPCHK(launch_post_load(b->cload.d, b->cload.n, b->cload.total, s));
+  if ((st = run_fdm(b->ffwd, s))) return st;
+  HIPCHK(launch_block_solve(b->bfwd.d, b->bfwd.n, s));
+  HIPCHK(launch_gemm(b->gx.d, b->gx.n, b->gx.tiles, b->gx.fold, s));
+  HIPCHK(launch_gemm(b->gy.d, b->gy.n, b->gy.tiles, b->gy.fold, s));
+  HIPCHK(launch_time_solve(b->sfwd.d, b->sfwd.n, b->sfwd.threads, s));
+  HIPCHK(launch_gemm(b->giy.d, b->giy.n, b->giy.tiles, b->giy.fold, s));
+  HIPCHK(launch_gemm(b->gix.d, b->gix.n, b->gix.tiles, b->gix.fold, s));
+  if ((st = fork(b, s))) return st;
+  for (int i = 0; i < n; ++i) {
+    sg_problem *p = b->probs[i];
+    hipStream_t bs = b->streams[i % b->streams.size()];
+    if ((st = run_prolong(p, p->prol, u0[i], U[i], 0, 0, bs, -1, p->ws.Cpro))) return st;
+  }
+  return join(b, s);
+}
+
+sg_status batch_adjoint(sg_batch *b, const double *const *g, double *const *df,
+                        double *const *du0, double *const *dv0, hipStream_t s) {
+  const int n = (int)b->probs.size();
+  if (!g) return fail(SG_EINVAL, "NULL cotangent array");
+  for (int i = 0; i < n; ++i)
+    if (!g[i]) return fail(SG_EINVAL, "NULL cotangent");
+  sg_status st;
+  if ((st = fork(b, s))) return st;
+  for (int i = 0; i < n; ++i) {
+    sg_problem *p = b->probs[i];
+    hipStream_t bs = b->streams[i % b->streams.size()];
+    if ((st = run_restrict(p, p->ws, p->adjr, g[i], 0, bs))) return st;
+  }
+  if ((st = join(b, s))) return st;
+  if ((st = run_fdm(b->fadj, s))) return st;
+  HIPCHK(launch_block_solve(b->badj.d, b->badj.n, s));
+  HIPCHK(launch_gemm(b->agx.d, b->agx.n, b->agx.tiles, b->agx.fold, s));
+  HIPCHK(launch_gemm(b->gy.d, b->gy.n, b->gy.tiles, b->gy.fold, s));
+  HIPCHK(launch_time_solve(b->sadj.d, b->sadj.n, b->sadj.threads, s));
+  HIPCHK(launch_gemm(b->giy.d, b->giy.n, b->giy.tiles, b->giy.fold, s));
+  HIPCHK(launch_gemm(b->agix.d, b->agix.n, b->agix.tiles, b->agix.fold, s));
+  HIPCHK(launch_post_adjoint(b->cadj.d, b->cadj.n, b->cadj.total, s));
+  bool fields = false;
+  for (int i = 0; i < n; ++i) fields = fields || (du0 && du0[i]) || (dv0 && dv0[i]);
+  if (fields) HIPCHK(launch_adjoint_fields(b->d_lev, b->nlev, b->lev_total, s));
+  if ((st = fork(b, s))) return st;
+  for (int i = 0; i < n; ++i) {
+    sg_problem *p = b->probs[i];
+    hipStream_t bs = b->streams[i % b->streams.size()];
+    if (df && df[i] && (st = run_prolong(p, p->adjp, nullptr, df[i], 0, 1, bs, -1, p->ws.Cpro)))
+      return st;
+    double *du = du0 ? du0[i] : nullptr, *dv = dv0 ? dv0[i] : nullptr;
+    if (du || dv) {
+      if ((st = run_prolong(p, p->fieldp, nullptr, p->ws.fine2, 0, 0, bs, -1, p->ws.Cpro)))
+        return st;
+      const double hx = p->len[0] / p->N, hy = p->len[1] / p->N;
+      HIPCHK(launch_fine_stencils(p->d, p->N, p->d_ce, hx, hy, p->ws.fine2,
+                                  p->ws.fine2 + p->nsp_fine, dv, du, p->gsum, 1, bs));
+    }
+  }
+  return join(b, s);
+}
+
+// stage events of the member problems are switched off inside batch work
+struct EventsOff {
+  sg_batch *b;
+  std::vector<std::vector<hipEvent_t>> saved;
+  explicit EventsOff(sg_batch *bb) : b(bb), saved(bb->probs.size()) {
+    for (size_t i = 0; i < b->probs.size(); ++i) saved[i].swap(b->probs[i]->ev);
+  }
+  ~EventsOff() {
+    for (size_t i = 0; i < b->probs.size(); ++i) saved[i].swap(b->probs[i]->ev);
+  }
+};
+
+}  // namespace
 
 extern "C" {
 
@@ -1794,8 +2069,10 @@ sg_status sg_batch_destroy(sg_batch *b) {
   if (!b) return SG_OK;
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+  if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+  for (hipEvent_t e : b->join_ev) (void)hipEventDestroy(e);
   for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  for (void *a : b->allocs) (void)hipFree(a);
   delete b;
   return SG_OK;
 }
@@ -1809,31 +2086,82 @@ sg_status sg_batch_create(int n, sg_problem *const *problems, sg_batch **out) {
     for (int j = 0; j < i; ++j)
       if (problems[j] == problems[i]) return fail(SG_EINVAL, "a handle appears twice");
   }
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  for (int i = 0; i < n; ++i)
+    if (problems[i]->device != dev) return fail(SG_EINVAL, "problems on another device");
   sg_batch *b = new (std::nothrow) sg_batch();
   if (!b) return fail(SG_ENOMEM, "host allocation failed");
   b->probs.assign(problems, problems + n);
+  auto bail = [&](sg_status st) {
+    std::string msg = g_last_error;
+    sg_batch_destroy(b);
+    g_last_error = msg;
+    return st;
+  };
   // a few branch streams (default priority); problems are dealt round-robin
   const int ns = std::min(n, 8);
   for (int i = 0; i < ns; ++i) {
-    hipStream_t st = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    hipStream_t bs = nullptr;
+    if (hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) != hipSuccess) {
       (void)hipGetLastError();
-      sg_batch_destroy(b);
-      return fail(SG_EDEVICE, "hipStreamCreateWithFlags failed");
+      return bail(fail(SG_EDEVICE, "hipStreamCreateWithFlags failed"));
     }
-    b->streams.push_back(st);
-  }
-  for (int i = 0; i < 2 * n + 1; ++i) {
+    b->streams.push_back(bs);
     hipEvent_t e = nullptr;
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
       (void)hipGetLastError();
-      sg_batch_destroy(b);
-      return fail(SG_EDEVICE, "hipEventCreateWithFlags failed");
+      return bail(fail(SG_EDEVICE, "hipEventCreateWithFlags failed"));
     }
-    b->events.push_back(e);
+    b->join_ev.push_back(e);
   }
+  if (hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(SG_EDEVICE, "hipEventCreateWithFlags failed"));
+  }
+  sg_status st;
+  if ((st = merge_gemm(b, &sg_problem::gx, b->gx)) || (st = merge_gemm(b, &sg_problem::gy, b->gy)) ||
+      (st = merge_gemm(b, &sg_problem::giy, b->giy)) ||
+      (st = merge_gemm(b, &sg_problem::gix, b->gix)) ||
+      (st = merge_gemm(b, &sg_problem::agx, b->agx)) ||
+      (st = merge_gemm(b, &sg_problem::agix, b->agix)) ||
+      (st = merge_solve(b, &sg_problem::sfwd, b->sfwd)) ||
+      (st = merge_solve(b, &sg_problem::sadj, b->sadj)) ||
+      (st = merge_block(b, &sg_problem::bfwd, b->bfwd)) ||
+      (st = merge_block(b, &sg_problem::badj, b->badj)) ||
+      (st = merge_fdm(b, &sg_problem::ffwd, b->ffwd)) ||
+      (st = merge_fdm(b, &sg_problem::fadj, b->fadj)) ||
+      (st = merge_comp(b, &sg_problem::cload, b->cload)) ||
+      (st = merge_comp(b, &sg_problem::cadj, b->cadj)))
+    return bail(st);
+  std::vector<LevelDesc> lv;
+  long long tt = 0;
+  for (sg_problem *p : b->probs)
+    for (LevelDesc L : p->h_lev) {
+      tt = (tt + 63) / 64 * 64;
+      L.start = tt;
+      tt += L.wave ? 64LL * L.nsp : L.nsp;
+      lv.push_back(L);
+    }
+  if ((st = bupload(b, lv, &b->d_lev))) return bail(st);
+  b->nlev = (int)lv.size();
+  b->lev_total = tt;
   *out = b;
   return SG_OK;
+}
+
+sg_status sg_batch_solve(sg_batch *b, const double *const *f, const double *const *u0,
+                         const double *const *v0, double *const *U, hipStream_t stream) {
+  if (!b) return fail(SG_EINVAL, "NULL batch");
+  EventsOff off(b);
+  return batch_forward(b, f, u0, v0, U, stream);
+}
+
+sg_status sg_batch_adjoint(sg_batch *b, const double *const *g, double *const *df,
+                           double *const *du0, double *const *dv0, hipStream_t stream) {
+  if (!b) return fail(SG_EINVAL, "NULL batch");
+  EventsOff off(b);
+  return batch_adjoint(b, g, df, du0, dv0, stream);
 }
 
 sg_status sg_batch_capture(sg_batch *b, const double *const *f, const double *const *u0,
@@ -1841,9 +2169,7 @@ sg_status sg_batch_capture(sg_batch *b, const double *const *f, const double *co
                            double *const *df, double *const *du0, double *const *dv0,
                            hipStream_t s) {
   if (!b) return fail(SG_EINVAL, "NULL batch");
-  if (!f || !u0 || !v0 || !U) return fail(SG_EINVAL, "NULL argument array");
   if (s == nullptr) return fail(SG_ESTATE, "batch capture needs a non-default stream");
-  const int n = (int)b->probs.size();
   if (b->gexec) {
     (void)hipGraphExecDestroy(b->gexec);
     b->gexec = nullptr;
@@ -1852,35 +2178,17 @@ sg_status sg_batch_capture(sg_batch *b, const double *const *f, const double *co
     (void)hipGraphDestroy(b->graph);
     b->graph = nullptr;
   }
-  // no stage events inside a batch graph (restored afterwards)
-  std::vector<std::vector<hipEvent_t>> saved(n);
-  for (int i = 0; i < n; ++i) saved[i].swap(b->probs[i]->ev);
+  EventsOff off(b);
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  sg_status st = SG_OK;
-  hipError_t e = hipEventRecord(b->events[2 * n], s);  // fork point
-  for (int i = 0; st == SG_OK && e == hipSuccess && i < n; ++i) {
-    hipStream_t bs = b->streams[i % b->streams.size()];
-    sg_problem *p = b->probs[i];
-    e = hipStreamWaitEvent(bs, b->events[2 * n], 0);
-    if (e != hipSuccess) break;
-    p->capturing = true;
-    st = sg_solve(p, f[i], u0[i], v0[i], U[i], bs);
-    if (st == SG_OK && g != nullptr && g[i] != nullptr)
-      st = sg_adjoint(p, g[i], df ? df[i] : nullptr, du0 ? du0[i] : nullptr,
-                      dv0 ? dv0[i] : nullptr, bs);
-    p->capturing = false;
-    if (st == SG_OK) e = hipEventRecord(b->events[i], bs);
-    if (st == SG_OK && e == hipSuccess) e = hipStreamWaitEvent(s, b->events[i], 0);  // join
-  }
+  sg_status st = batch_forward(b, f, u0, v0, U, s);
+  if (st == SG_OK && g != nullptr) st = batch_adjoint(b, g, df, du0, dv0, s);
   hipGraph_t graph = nullptr;
   const hipError_t e2 = hipStreamEndCapture(s, &graph);
-  for (int i = 0; i < n; ++i) saved[i].swap(b->probs[i]->ev);
-  if (st != SG_OK || e != hipSuccess || e2 != hipSuccess) {
+  if (st != SG_OK || e2 != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
     (void)hipGetLastError();
     if (st != SG_OK) return st;
-    return fail(SG_EDEVICE, std::string("batch capture: ") +
-                                hipGetErrorString(e != hipSuccess ? e : e2));
+    return fail(SG_EDEVICE, std::string("batch capture: ") + hipGetErrorString(e2));
   }
   b->graph = graph;
   HIPCHK(hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0));

@@ -146,21 +146,26 @@ __device__ __forceinline__ double *fac_at(const FdmDesc &D, int u, int k, int x,
 
 // ---------------------------------------------------------------- solve ----
 
-// X[u][node] = sum_j tin[u][j] in[j][node]
+// X[u][node] = sum_j tin[u][j] in[j][node]  (u < nu <= kFdmMaxNu: the
+// accumulators stay in registers)
 __global__ void k_fdm_in(const FdmDesc *__restrict__ ds, int nd, long long total) {
   const long long g = gid64();
   if (g >= total) return;
   const FdmDesc &D = ds[find_fdm(ds, nd, g, kNode)];
   const long long node = g - D.node0, nn = (long long)D.n * D.n;
-  double v[33];
-  const int nq = D.nq;
-#pragma unroll 4
-  for (int j = 0; j < nq; ++j) v[j] = D.in[(long long)j * nn + node];
-  for (int u = 0; u < D.nu; ++u) {
-    cx acc = {0.0, 0.0};
-    for (int j = 0; j < nq; ++j) acc = cadd(acc, cscl(cld(D.tin + 2 * ((size_t)u * nq + j)), v[j]));
-    cst(D.X + 2 * ((long long)u * nn + node), acc);
+  const int nq = D.nq, nu = D.nu;
+  cx acc[kFdmMaxNu];
+#pragma unroll
+  for (int u = 0; u < kFdmMaxNu; ++u) acc[u] = {0.0, 0.0};
+  for (int j = 0; j < nq; ++j) {
+    const double v = D.in[(long long)j * nn + node];
+#pragma unroll
+    for (int u = 0; u < kFdmMaxNu; ++u)
+      if (u < nu) acc[u] = cadd(acc[u], cscl(cld(D.tin + 2 * ((size_t)u * nq + j)), v));
   }
+#pragma unroll
+  for (int u = 0; u < kFdmMaxNu; ++u)
+    if (u < nu) cst(D.X + 2 * ((long long)u * nn + node), acc[u]);
 }
 
 // out[j][node] = Re sum_u tout[j][u] w_u[node], w from X (strip rows) or Xg
@@ -173,16 +178,21 @@ __global__ void k_fdm_out(const FdmDesc *__restrict__ ds, int nd, long long tota
   const int y = (int)(node / D.n), x = (int)(node - (long long)y * D.n);
   const bool iface = (y + 1) % (D.m + 1) == 0;
   const int r = (y + 1) / (D.m + 1);  // 1-based interface index
-  cx w[17];
-  for (int u = 0; u < D.nu; ++u)
-    w[u] = iface ? cld(D.Xg + 2 * (((size_t)u * D.ni + r - 1) * D.n + x))
-                 : cld(D.X + 2 * ((long long)u * nn + node));
+  const int nu = D.nu;
+  cx w[kFdmMaxNu];
+#pragma unroll
+  for (int u = 0; u < kFdmMaxNu; ++u)
+    w[u] = u >= nu ? cx{0.0, 0.0}
+           : iface ? cld(D.Xg + 2 * (((size_t)u * D.ni + r - 1) * D.n + x))
+                   : cld(D.X + 2 * ((long long)u * nn + node));
   for (int j = 0; j < D.nq; ++j) {
     double acc = 0.0;
-    for (int u = 0; u < D.nu; ++u) {
-      const cx t = cld(D.tout + 2 * ((size_t)j * D.nu + u));
-      acc += t.r * w[u].r - t.i * w[u].i;
-    }
+#pragma unroll
+    for (int u = 0; u < kFdmMaxNu; ++u)
+      if (u < nu) {
+        const cx t = cld(D.tout + 2 * ((size_t)j * nu + u));
+        acc += t.r * w[u].r - t.i * w[u].i;
+      }
     D.out[(long long)j * nn + node] = acc;
   }
 }
@@ -194,8 +204,15 @@ __global__ void k_fdm_out(const FdmDesc *__restrict__ ds, int nd, long long tota
 //                 x_lo / x_hi the interface solutions below / above the strip
 //                 (the forward sweep is kept in the same row of X, whose strip
 //                 rows are free at this point)
-__global__ void k_fdm_tri(const FdmDesc *__restrict__ ds, int nd, long long total,
-                          int correction) {
+// Both sweeps run in chunks of FCH rows: the chunk's operands are loaded into
+// registers first (independent loads in flight together), then the
+// recurrence runs on registers.
+#ifndef SG_FDM_CH
+#define SG_FDM_CH 8
+#endif
+__global__ void __launch_bounds__(64) k_fdm_tri(const FdmDesc *__restrict__ ds, int nd,
+                                                long long total, int correction) {
+  constexpr int FCH = SG_FDM_CH;
   const long long g = gid64();
   if (g >= total) return;
   const FdmDesc &D = ds[find_fdm(ds, nd, g, kTri)];
@@ -222,25 +239,47 @@ __global__ void k_fdm_tri(const FdmDesc *__restrict__ ds, int nd, long long tota
     if (xhi) r = cadd(r, cscl(cpl_apply(D, k, lam, xhi, x), s1));
     return r;
   };
-  // forward sweep: y_x = r_x - l_x y_{x-1}
-  cx prev = rhs(0);
-  cst(Wr, prev);
-  for (int x = 1; x < n; ++x) {
-    const double *f = fac_at(D, u, k, x, l);
-    prev = csub(rhs(x), cmul(cx{f[2], f[3]}, prev));
-    cst(Wr + 2 * x, prev);
+  // forward sweep: y_x = r_x - l_x y_{x-1} (l_0 = 0)
+  cx prev = {0.0, 0.0};
+  for (int x0 = 0; x0 < n; x0 += FCH) {
+    cx r[FCH], el[FCH];
+#pragma unroll
+    for (int c = 0; c < FCH; ++c) {
+      const int x = min(x0 + c, n - 1);
+      r[c] = rhs(x);
+      const double *f = fac_at(D, u, k, x, l);
+      el[c] = {f[2], f[3]};
+    }
+#pragma unroll
+    for (int c = 0; c < FCH; ++c) {
+      if (x0 + c < n) {
+        prev = csub(r[c], cmul(el[c], prev));
+        cst(Wr + 2 * (x0 + c), prev);
+      }
+    }
   }
-  // back substitution: z_x = (y_x - of_x z_{x+1}) / d'_x
+  // back substitution: z_x = (y_x - of_x z_{x+1}) / d'_x, chunks from the top
   cx z = {0.0, 0.0};
-  for (int x = n - 1; x >= 0; --x) {
-    cx dg, of;
-    tri_row(D, k, l, lam, x, dg, of);
-    const double *f = fac_at(D, u, k, x, l);
-    z = cmul(csub(cld(Wr + 2 * x), cmul(of, z)), cx{f[0], f[1]});
-    if (correction)
-      cst(Yr + 2 * x, csub(cld(Yr + 2 * x), z));
-    else
-      cst(Yr + 2 * x, z);
+  for (int x1 = n - 1; x1 >= 0; x1 -= FCH) {
+    cx w[FCH], iv[FCH], of[FCH], yo[FCH];
+#pragma unroll
+    for (int c = 0; c < FCH; ++c) {
+      const int x = max(x1 - c, 0);
+      w[c] = cld(Wr + 2 * x);
+      const double *f = fac_at(D, u, k, x, l);
+      iv[c] = {f[0], f[1]};
+      cx dg;
+      tri_row(D, k, l, lam, x, dg, of[c]);
+      if (correction) yo[c] = cld(Yr + 2 * x);
+    }
+#pragma unroll
+    for (int c = 0; c < FCH; ++c) {
+      const int x = x1 - c;
+      if (x >= 0) {
+        z = cmul(csub(w[c], cmul(of[c], z)), iv[c]);
+        cst(Yr + 2 * x, correction ? csub(yo[c], z) : z);
+      }
+    }
   }
 }
 

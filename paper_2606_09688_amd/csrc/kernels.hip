@@ -1929,8 +1929,7 @@ __global__ void k_energy_sum(int K, int nblk, const double *__restrict__ part,
 
 
 // b_c[i][K] = sum_q D_b[i][q] Z_c[q][K] + psi_i'(0) MV_a[K] - g_b[i] KU_a[K]
-__global__ void k_post_load(const CompDesc *__restrict__ cd, int ncomp, long long total,
-                            const KernelTables *__restrict__ kt) {
+__global__ void k_post_load(const CompDesc *__restrict__ cd, int ncomp, long long total) {
   const long long gid = gid64();
   const int ci = find_item(cd, ncomp, gid);
   if (gid >= total) return;
@@ -1939,6 +1938,7 @@ __global__ void k_post_load(const CompDesc *__restrict__ cd, int ncomp, long lon
   const int i = (int)loc / C.nsp;  // a component holds fewer than 2^31 values
   const int K = (int)loc - i * C.nsp;
   const double *Z = C.z;
+  const KernelTables *kt = C.kt;
   double v = kt->Dlo[C.b][i] * Z[loc];
   if (i + 1 < C.nq) v += kt->Dhi[C.b][i] * Z[loc + C.nsp];
   if (i == 0 && C.mv != nullptr) v += kt->Dlo[C.b][0] * C.mv[K];
@@ -1948,13 +1948,14 @@ __global__ void k_post_load(const CompDesc *__restrict__ cd, int ncomp, long lon
 
 // zeta_c[q][K] = sum_i D_b[i][q] z_c[i][K]   (transpose of the above)
 __global__ void k_post_adjoint(const CompDesc *__restrict__ cd, int ncomp,
-                               long long total, const KernelTables *__restrict__ kt) {
+                               long long total) {
   const long long gid = gid64();
   const int ci = find_item(cd, ncomp, gid);
   if (gid >= total) return;
   const CompDesc &C = cd[ci];
   const long long loc = gid - C.start;
   const int q = (int)loc / C.nsp;  // a component holds fewer than 2^31 values
+  const KernelTables *kt = C.kt;
   double v = kt->Dlo[C.b][q] * C.z[loc];
   if (q >= 1) v += kt->Dhi[C.b][q - 1] * C.z[loc - C.nsp];
   C.data[loc] = v;
@@ -1964,12 +1965,13 @@ __global__ void k_post_adjoint(const CompDesc *__restrict__ cd, int ncomp,
 // Levels whose components have long time levels use one wave per node (lanes
 // split the time sum, then a shuffle reduction); the others one thread.
 __global__ void k_adjoint_fields(const LevelDesc *__restrict__ ld, int nlev,
-                                 long long total, const CompDesc *__restrict__ cd,
-                                 const KernelTables *__restrict__ kt) {
+                                 long long total) {
   const long long gid = gid64();
   const int l = find_item(ld, nlev, gid);
   if (gid >= total) return;
   const LevelDesc &L = ld[l];
+  const CompDesc *cd = L.cd;
+  const KernelTables *kt = L.kt;
   const long long rel = gid - L.start;
   const int lane = L.wave ? (int)(rel & 63) : 0, step = L.wave ? 64 : 1;
   const long long K = L.wave ? rel >> 6 : rel;
@@ -2205,11 +2207,12 @@ __device__ __forceinline__ void mode_scalars(const SolveDesc &S, int j,
 }
 
 __global__ void __launch_bounds__(64) k_time_factor(const SolveDesc *__restrict__ sds,
-                                                    int nsd, long long total,
-                                                    const KernelTables *__restrict__ kt,
-                                                    const ModeTables *__restrict__ mt, int d) {
+                                                    int nsd, long long total) {
   const long long wbase = (long long)blockIdx.x * 64;
   const SolveDesc &S = sds[find_solve(sds, nsd, wbase)];
+  const KernelTables *kt = S.kt;
+  const ModeTables *mt = S.mt;
+  const int d = S.d;
   const long long gid = wbase + threadIdx.x;
   const int j = (int)(gid - S.thread0);
   if (gid >= total || j >= S.nmodes) return;
@@ -2247,9 +2250,7 @@ __global__ void __launch_bounds__(64) k_time_factor(const SolveDesc *__restrict_
 }
 
 __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__ sds,
-                                                   int nsd, long long total,
-                                                   const KernelTables *__restrict__ kt,
-                                                   const ModeTables *__restrict__ mt, int d) {
+                                                   int nsd, long long total) {
   // rows per register chunk of a substitution / of the residual (thread path)
 #ifndef SG_CH
 #define SG_CH 8
@@ -2261,6 +2262,9 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
   constexpr int CR = SG_CR;
   const long long wbase = (long long)blockIdx.x * 64;
   const SolveDesc &S = sds[find_solve(sds, nsd, wbase)];
+  const KernelTables *kt = S.kt;
+  const ModeTables *mt = S.mt;
+  const int d = S.d;
   const int lane = threadIdx.x;
   const bool wave = S.wave != 0;
   // wave path: one mode per wave; thread path: one mode per thread
@@ -2560,11 +2564,11 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
 // bidiagonal (D_k, S_{k,k+1}); S^T = U^T L^T for the adjoint.  The
 // off-diagonal blocks S_{k,k+1} = M_{k,k+1} A_b + K_{k,k+1} B_b are applied
 // through the banded time matrices.  Lane j < nq owns row j of every block.
-__global__ void __launch_bounds__(64) k_block_solve(const BlockDesc *__restrict__ bds,
-                                                    const KernelTables *__restrict__ kt) {
+__global__ void __launch_bounds__(64) k_block_solve(const BlockDesc *__restrict__ bds) {
   constexpr int MAXQ = 64;
   __shared__ double s_v[MAXQ], s_u[MAXQ];
   const BlockDesc &B = bds[blockIdx.x];
+  const KernelTables *kt = B.kt;
   const int lane = threadIdx.x;
   const int nq = B.nq, nx = B.nx;
   const bool tr = B.transpose != 0;
@@ -2924,25 +2928,25 @@ hipError_t launch_fine_stencils(int d, int N, const double *ce, double hx, doubl
   return hipGetLastError();
 }
 
-hipError_t launch_post_load(const CompDesc *cd, int ncomp, long long total,
-                            const KernelTables *kt, hipStream_t s) {
+hipError_t launch_post_load(const CompDesc *cd, int ncomp, long long total, hipStream_t s) {
+  if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_post_load, dim3(blocks_for(total, 256)), dim3(256), 0, s, cd, ncomp,
-                     total, kt);
+                     total);
   return hipGetLastError();
 }
 
-hipError_t launch_post_adjoint(const CompDesc *cd, int ncomp, long long total,
-                               const KernelTables *kt, hipStream_t s) {
+hipError_t launch_post_adjoint(const CompDesc *cd, int ncomp, long long total, hipStream_t s) {
+  if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_post_adjoint, dim3(blocks_for(total, 256)), dim3(256), 0, s, cd,
-                     ncomp, total, kt);
+                     ncomp, total);
   return hipGetLastError();
 }
 
 hipError_t launch_adjoint_fields(const LevelDesc *ld, int nlev, long long total,
-                                 const CompDesc *cd, const KernelTables *kt,
                                  hipStream_t s) {
+  if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_adjoint_fields, dim3(blocks_for(total, 256)), dim3(256), 0, s, ld,
-                     nlev, total, cd, kt);
+                     nlev, total);
   return hipGetLastError();
 }
 
@@ -2958,28 +2962,23 @@ hipError_t launch_gemm(const GemmDesc *descs, int ndesc, int total_tiles, int fo
   return hipGetLastError();
 }
 
-hipError_t launch_time_factor(const SolveDesc *sd, int nsd, long long total,
-                              const KernelTables *kt, const ModeTables *mt, int d,
-                              hipStream_t s) {
+hipError_t launch_time_factor(const SolveDesc *sd, int nsd, long long total, hipStream_t s) {
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_time_factor, dim3(blocks_for(total, 64)), dim3(64), 0, s, sd, nsd,
-                     total, kt, mt, d);
+                     total);
   return hipGetLastError();
 }
 
-hipError_t launch_time_solve(const SolveDesc *sd, int nsd, long long total,
-                             const KernelTables *kt, const ModeTables *mt, int d,
-                             hipStream_t s) {
+hipError_t launch_time_solve(const SolveDesc *sd, int nsd, long long total, hipStream_t s) {
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_time_solve, dim3(blocks_for(total, 64)), dim3(64), 0, s, sd, nsd,
-                     total, kt, mt, d);
+                     total);
   return hipGetLastError();
 }
 
-hipError_t launch_block_solve(const BlockDesc *bd, int nbd, const KernelTables *kt,
-                              hipStream_t s) {
+hipError_t launch_block_solve(const BlockDesc *bd, int nbd, hipStream_t s) {
   if (nbd == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_block_solve, dim3(nbd), dim3(64), 0, s, bd, kt);
+  hipLaunchKernelGGL(k_block_solve, dim3(nbd), dim3(64), 0, s, bd);
   return hipGetLastError();
 }
 

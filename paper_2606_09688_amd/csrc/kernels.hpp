@@ -92,6 +92,13 @@ struct GemmDesc {
   int nref, par;
 };
 
+struct ModeTables {      // 1-D P1 eigenvalues per level and axis (unit c)
+  const double *mx[kMaxLevels + 1];
+  const double *kx[kMaxLevels + 1];
+  const double *my[kMaxLevels + 1];
+  const double *ky[kMaxLevels + 1];
+};
+
 struct SolveDesc {
   double *rhs;           // [nq][nmodes], overwritten with the solution
   double *fac;           // 5 planes [nq][nmodes]: L1, L2, 1/U0, U1, U2 of E = L U
@@ -106,6 +113,10 @@ struct SolveDesc {
   double c2;             // wave speed squared (constant-speed path)
   long long thread0;     // first global thread, a multiple of 64 (one wave
                          // never spans two descriptors)
+  const KernelTables *kt;  // the problem's time tables
+  const ModeTables *mt;    // and spatial mode tables
+  int d;                   // its dimension
+  int pad2;
 };
 
 // One component of a 1-D variable-speed problem solved without a spatial
@@ -124,14 +135,9 @@ struct BlockDesc {
   int transpose;         // solve with S^T
   int refine;            // maximum refinement sweeps
   int pad;
+  const KernelTables *kt;  // the problem's time tables
 };
 
-struct ModeTables {      // 1-D P1 eigenvalues per level and axis (unit c)
-  const double *mx[kMaxLevels + 1];
-  const double *kx[kMaxLevels + 1];
-  const double *my[kMaxLevels + 1];
-  const double *ky[kMaxLevels + 1];
-};
 
 struct CompDesc {        // one component for the small post-processing kernels
   double *data;          // output [nq][nsp]: load b_c, or adjoint zeta_c
@@ -142,6 +148,7 @@ struct CompDesc {        // one component for the small post-processing kernels
   int sign;
   int pad;
   long long start;       // first global element of this component's work
+  const KernelTables *kt;  // the problem's time tables
 };
 
 struct LevelDesc {       // adjoint fields of one spatial level
@@ -152,6 +159,8 @@ struct LevelDesc {       // adjoint fields of one spatial level
   int wave;              // 1: one wave per node (long time sums), 0: one thread
   int pad;
   long long start;       // first global thread (a multiple of 64 for wave levels)
+  const CompDesc *cd;    // the problem's adjoint component list (c0, c1 index it)
+  const KernelTables *kt;  // the problem's time tables
 };
 
 // launch wrappers (return hipError_t of the launch)
@@ -182,23 +191,14 @@ hipError_t launch_fine_stencils(int d, int N, const double *ce, double hx,
                                 double hy, const double *v_in, const double *u_in,
                                 double *mv_out, double *ku_out,
                                 const double *gsum, int mode, hipStream_t s);
-hipError_t launch_post_load(const CompDesc *cd, int ncomp, long long total,
-                            const KernelTables *kt, hipStream_t s);
-hipError_t launch_post_adjoint(const CompDesc *cd, int ncomp, long long total,
-                               const KernelTables *kt, hipStream_t s);
-hipError_t launch_adjoint_fields(const LevelDesc *ld, int nlev, long long total,
-                                 const CompDesc *cd, const KernelTables *kt,
-                                 hipStream_t s);
+hipError_t launch_post_load(const CompDesc *cd, int ncomp, long long total, hipStream_t s);
+hipError_t launch_post_adjoint(const CompDesc *cd, int ncomp, long long total, hipStream_t s);
+hipError_t launch_adjoint_fields(const LevelDesc *ld, int nlev, long long total, hipStream_t s);
 hipError_t launch_gemm(const GemmDesc *descs, int ndesc, int total_tiles, int fold,
                        hipStream_t s);
-hipError_t launch_time_factor(const SolveDesc *sd, int nsd, long long total,
-                              const KernelTables *kt, const ModeTables *mt, int d,
-                              hipStream_t s);
-hipError_t launch_time_solve(const SolveDesc *sd, int nsd, long long total,
-                             const KernelTables *kt, const ModeTables *mt, int d,
-                             hipStream_t s);
-hipError_t launch_block_solve(const BlockDesc *bd, int nbd, const KernelTables *kt,
-                              hipStream_t s);
+hipError_t launch_time_factor(const SolveDesc *sd, int nsd, long long total, hipStream_t s);
+hipError_t launch_time_solve(const SolveDesc *sd, int nsd, long long total, hipStream_t s);
+hipError_t launch_block_solve(const BlockDesc *bd, int nbd, hipStream_t s);
 // ---- 2-D variable-speed components of short time levels -------------------
 // S = A (x) M + B (x) K(c) is diagonalised in time (B^{-1} A = V diag(lam)
 // V^{-1}), leaving one complex spatial system (lam M + K(c)) w = r per
@@ -233,6 +233,9 @@ struct FdmDesc {
   long long if0;         // first thread: interface right-hand sides (nu ni n)
   long long gemv0;       // first wave: interface solves (nu ni n rows)
 };
+
+// most eigenvalues kept per time level (2^4 + 1 = 17 nodes: 8 pairs + 1 real)
+constexpr int kFdmMaxNu = 9;
 
 struct FdmTotals {       // launch sizes of one list of FdmDesc
   long long node = 0, tri = 0, edge = 0, iface = 0, gemv = 0;

@@ -334,10 +334,11 @@ def test_invalid_arguments_raise():
 
 def test_batch_graph_of_uneven_problems():
     """Independent problems of different d, L and speeds (constant and
-    piecewise constant, 1-D and 2-D) in one HIP graph
-    (one branch each): every replay reproduces each problem's own eager
-    forward and adjoint bitwise; one problem is also checked against the
-    oracle."""
+    piecewise constant, 1-D and 2-D; every solver path: sine transforms,
+    dense pencils, time-diagonalised strips, 1-D block LU) run as one batch
+    (merged solve stages): the eager batched forward and adjoint and every
+    replay of the captured batch graph reproduce each problem's own eager
+    results bitwise; members are also checked against the oracle."""
     torch = _torch()
     import paper_2606_09688_amd as sg
     specs = [
@@ -348,6 +349,8 @@ def test_batch_graph_of_uneven_problems():
         workloads.Spec(1, [2.0], [2], [1.0, 0.5], 2.0, 6),
         workloads.Spec(2, [1.0, 1.0], [1, 1], [1.0], 1.0, 3),
         workloads.Spec(2, [1.0, 1.0], [4, 4], _speeds(16, 75), 1.0, 6),  # variable speed
+        workloads.Spec(2, [1.0, 1.0], [4, 4], _speeds(16, 80), 1.0, 8),  # strips at levels 6, 7
+        workloads.Spec(1, [1.0], [4], _speeds(4, 81), 1.0, 10),          # 1-D block LU (level 9)
     ]
     svs, ins, eager = [], [], []
     for k, spec in enumerate(specs):
@@ -363,6 +366,22 @@ def test_batch_graph_of_uneven_problems():
     outs = [(torch.empty_like(e[0]), torch.empty_like(e[1]), torch.empty_like(e[2]),
              torch.empty_like(e[3])) for e in eager]
     batch = sg.SparseGridBatch(svs)
+    # eager batched forward and adjoint (du0 / dv0 skipped for one member)
+    outs_e = [(torch.full_like(e[0], 7.0), torch.full_like(e[1], 7.0), torch.full_like(e[2], 7.0),
+               torch.full_like(e[3], 7.0)) for e in eager]
+    batch.solve([x[0] for x in ins], [x[1] for x in ins], [x[2] for x in ins],
+                [o[0] for o in outs_e])
+    skip = 3
+    batch.adjoint([x[3] for x in ins], [o[1] for o in outs_e],
+                  [None if k == skip else o[2] for k, o in enumerate(outs_e)],
+                  [None if k == skip else o[3] for k, o in enumerate(outs_e)])
+    torch.cuda.synchronize()
+    for k, (o, e) in enumerate(zip(outs_e, eager)):
+        assert torch.equal(o[0], e[0]) and torch.equal(o[1], e[1]), k
+        if k == skip:
+            assert bool((o[2] == 7.0).all()) and bool((o[3] == 7.0).all())
+        else:
+            assert torch.equal(o[2], e[2]) and torch.equal(o[3], e[3]), k
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         batch.capture([x[0] for x in ins], [x[1] for x in ins], [x[2] for x in ins],
@@ -379,8 +398,8 @@ def test_batch_graph_of_uneven_problems():
         for k, (o, e) in enumerate(zip(outs, eager)):
             assert all(torch.equal(a, b) for a, b in zip(o, e)), (rep, k)
         _ = sum(float(x[0].sum()) for x in ins)  # unrelated eager work between replays
-    # two members (1-D and 2-D variable speed) against the oracle
-    for k in (2, 6):
+    # members with variable speed against the oracle
+    for k in (2, 6, 7):
         spec, data = specs[k], ins[k][4]
         U_ref = Problem(*spec.args()).forward(data["f"], data["u0"], data["v0"])
         assert rel(outs[k][0].cpu().numpy(), U_ref.reshape(spec.shape())) <= TOL, k
