@@ -10,8 +10,11 @@ component solves, combination) and adjoint (restriction of g, transposed
 solves, df/du0/dv0), replayed from one captured HIP graph (the batched form).
 value = N_sparse DoFs per step / seconds per step.
 
-Also reported (config): forward-only DoFs/s, the per-component plain loop,
-fwd+adj/fwd, and the per-stage times from HIP events on the launch stream.
+Also reported (config): forward-only DoFs/s (eager and from a forward-only
+graph), the per-component plain loop, fwd+adj/fwd, the per-stage times from
+HIP events on the launch stream, and the 256-problem batch (d=2, L ~ U{6..10},
+4x4 wave-speed blocks): its batched graph against the plain per-problem loop
+and the roofline of its merged component solves.
 """
 
 import argparse
@@ -40,39 +43,111 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-energy", action="store_true",
                     help="skip the energy diagnostic (counter runs of the streaming kernels)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-max-dofs", type=int, default=40000,
+                    help="largest component (DoFs) in the oracle's timed sample")
+    ap.add_argument("--cpu-procs", type=int, default=8)
+    ap.add_argument("--no-c5", action="store_true", help="skip the 256-problem batch")
+    ap.add_argument("--c5-n", type=int, default=256)
+    ap.add_argument("--c5-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of one fine array (counter scaling)")
     return ap.parse_args()
 
 
-def cpu_baseline(spec, data, budget_s):
-    """Time the oracle (forward: load, solve, prolongation per component) on
-    the components of the same workload, smallest first, until the budget is
-    used; single-threaded BLAS."""
+def _cpu_solve_phase(spec, data, comps, reps, barrier=None):
+    """Warm the oracle's caches for `comps` (time and spatial matrices, cross
+    operators, sparse LU factors: its assembly), then time `reps` passes of
+    the solve phase (load of eq. 9, solve, prolongation), 1 BLAS thread.
+    Returns (assembly seconds, list of pass seconds)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import Problem
     with threadpool_limits(limits=1):
         prob = Problem(*spec.args())
-        order = sorted(prob.comps, key=lambda c: (2 ** c[0] - 1) ** spec.d * (2 ** c[1] + 1))
-        dofs = 0
-        done = []
         t0 = time.perf_counter()
-        U = np.zeros((spec.nt(), (spec.nx()) ** spec.d))
-        for jx, jt, s in order:
-            b = prob.load(jx, jt, data["f"], data["u0"], data["v0"])
-            u = prob.solve(jx, jt, b)
-            U += s * prob.prolong(jx, jt, u)
-            dofs += u.size
-            done.append(f"({jx},{jt})")
-            if time.perf_counter() - t0 > budget_s:
-                break
-        el = time.perf_counter() - t0
-    return {"value": dofs / el, "unit": "DoF/s", "cores": 1, "kind": "oracle",
-            "sample": (f"forward load+solve+prolongation of {len(done)} of "
-                       f"{len(prob.comps)} components {' '.join(done)} "
-                       f"({dofs} DoFs, {el:.1f} s, smallest first, 1 BLAS thread)")}
+        for jx, jt, s in comps:
+            prob.prolong(jx, jt, prob.solve(jx, jt, prob.load(jx, jt, data["f"], data["u0"],
+                                                               data["v0"])))
+        t_asm = time.perf_counter() - t0
+        times = []
+        for _ in range(reps):
+            if barrier is not None:
+                barrier.wait()
+            t0 = time.perf_counter()
+            U = np.zeros((spec.nt(), spec.nx() ** spec.d))
+            for jx, jt, s in comps:
+                b = prob.load(jx, jt, data["f"], data["u0"], data["v0"])
+                U += s * prob.prolong(jx, jt, prob.solve(jx, jt, b))
+            times.append(time.perf_counter() - t0)
+            if barrier is not None:
+                barrier.wait()
+    return t_asm, times
+
+
+def _pool_worker(spec, data, comps, reps, barrier, q):
+    q.put(_cpu_solve_phase(spec, data, comps, reps, barrier))
+
+
+def _host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
+def cpu_baseline(spec, data, max_dofs, procs, reps=3):
+    """The oracle (plain FP64 CPU code) on a bounded sample of the same
+    workload: every component with at most max_dofs DoFs.  Assembly (its
+    caches) is warmed first and reported apart; the solve phase (load +
+    sparse LU solve with refinement + prolongation) is timed, median of
+    `reps`, in one process and in a pool of `procs` processes that split the
+    components by longest-processing-time on their DoFs (the component solves
+    are independent).  Runs before the GPU is initialised (fork-safe)."""
+    import multiprocessing as mp
+
+    from oracle import levels
+    comps = [c for c in levels.components(spec.L)
+             if levels.n_space(c[0], spec.d) * levels.n_time(c[1]) <= max_dofs]
+    size = lambda c: levels.n_space(c[0], spec.d) * levels.n_time(c[1])
+    dofs = sum(size(c) for c in comps)
+    t_asm, times = _cpu_solve_phase(spec, data, comps, reps)
+    t1 = float(np.median(times))
+    # pool: longest-processing-time assignment of the components to workers
+    P = max(1, min(procs, len(comps), os.cpu_count() or 1))
+    parts = [[] for _ in range(P)]
+    loads = [0] * P
+    for c in sorted(comps, key=size, reverse=True):
+        k = loads.index(min(loads))
+        parts[k].append(c)
+        loads[k] += size(c)
+    ctx = mp.get_context("fork")
+    barrier, q = ctx.Barrier(P), ctx.Queue()
+    ws = [ctx.Process(target=_pool_worker, args=(spec, data, parts[k], reps, barrier, q))
+          for k in range(P)]
+    for w in ws:
+        w.start()
+    res = [q.get() for _ in ws]
+    for w in ws:
+        w.join()
+    # pass r of the pool ends when its slowest worker does
+    tP = float(np.median([max(r[1][i] for r in res) for i in range(reps)]))
+    ncomp = len(levels.components(spec.L))
+    return {"value": dofs / tP, "unit": "DoF/s", "cores": P, "kind": "oracle",
+            "single_process_value": dofs / t1,
+            "assembly_s": t_asm,
+            "host": _host_info(),
+            "sample": (f"solve phase (load + SuperLU solve with refinement + prolongation) of "
+                       f"the {len(comps)} of {ncomp} components with <= {max_dofs} DoFs "
+                       f"({dofs} DoFs) of the same d=2 L={spec.L} workload, caches warmed "
+                       f"first (assembly {t_asm:.1f} s, not timed); median of {reps}; value: "
+                       f"{P} single-threaded processes (LPT split, {tP:.2f} s); single "
+                       f"process {t1:.2f} s")}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c3_L10.json")
@@ -137,6 +212,134 @@ def time_energy(sv, u0, stream, T, K, nspace, reps=5):
             "E_first_last": [float(E[0]), float(E[-1])]}
 
 
+def _gaussians_on_device(spec, centres, dev, width=0.05):
+    """The batch workload's source f (sum of space-time Gaussians with the
+    given centres (x, y, t)) generated directly in device memory; each
+    Gaussian is a product of 1-D factors."""
+    import torch
+    t = torch.arange(spec.nt(), dtype=torch.float64, device=dev) * (spec.T / 2 ** spec.J)
+    x = torch.arange(1, 2 ** spec.J, dtype=torch.float64, device=dev) * (spec.lengths[0] / 2 ** spec.J)
+    y = torch.arange(1, 2 ** spec.J, dtype=torch.float64, device=dev) * (spec.lengths[1] / 2 ** spec.J)
+    f = torch.zeros(spec.shape(), dtype=torch.float64, device=dev)
+    w2 = 2.0 * width * width
+    for cx, cy, ct in centres:
+        gt = torch.exp(-(t - ct) ** 2 / w2)
+        gs = torch.exp(-(y - cy) ** 2 / w2)[:, None] * torch.exp(-(x - cx) ** 2 / w2)[None, :]
+        f.add_(gt[:, None, None] * gs[None, :, :])
+    return f
+
+
+def c5_batch(args, stream):
+    """The 256-problem batch (d=2, L ~ U{6..10}, 4x4 blocks of wave speed in
+    [0.5, 2], f = three space-time Gaussians, u0 = v0 = 0, cotangent g ~ N(0,1)).
+    A step is the forward and the adjoint of every problem, replayed from one
+    captured HIP graph (streaming passes per problem on branch streams, each
+    solve stage one launch over all problems).  U and df of a problem share
+    one buffer (the adjoint does not read U), so three fine arrays per
+    problem are resident (3 x 68 GiB for the seed-0 draw)."""
+    import torch
+
+    import paper_2606_09688_amd as sg
+    import workloads
+    dev = "cuda:0"
+    specs = workloads.c5_specs()[:args.c5_n]
+    t0 = time.perf_counter()
+    svs = [sg.SparseGridWave(*sp.args(), tuned=True) for sp in specs]
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batch = sg.SparseGridBatch(svs)
+    t_merge = time.perf_counter() - t0
+    n, n_sparse, table_bytes = batch.info()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    zeros, fs, gs, Xs, du0s, dv0s = {}, [], [], [], [], []
+    for i, sp in enumerate(specs):
+        fs.append(_gaussians_on_device(sp, workloads.c5_centres(i), dev))
+        gs.append(torch.randn(sp.shape(), generator=gen, dtype=torch.float64, device=dev))
+        Xs.append(torch.empty(sp.shape(), dtype=torch.float64, device=dev))
+        zeros.setdefault(sp.L, torch.zeros(sp.space_shape(), dtype=torch.float64, device=dev))
+        du0s.append(torch.empty(sp.space_shape(), dtype=torch.float64, device=dev))
+        dv0s.append(torch.empty(sp.space_shape(), dtype=torch.float64, device=dev))
+    u0s = [zeros[sp.L] for sp in specs]
+    torch.cuda.synchronize()
+    n_full = sum(sp.nt() * sp.nx() ** 2 for sp in specs)
+    # eager batched pass with stage events (merged solve stages timed)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    batch.set_events(ev)
+    with torch.cuda.stream(stream):
+        for _ in range(2):
+            batch.solve(fs, u0s, u0s, Xs, stream=stream)
+            batch.adjoint(gs, Xs, du0s, dv0s, stream=stream)
+    stream.synchronize()
+    el = lambda a, b: ev[a].elapsed_time(ev[b]) * 1e-3
+    st = {"fwd": el(0, 3), "fwd_solves": el(1, 2), "adj": el(4, 7), "adj_solves": el(5, 6)}
+    batch.set_events(None)
+    # the captured graph: forward + adjoint of all problems
+    with torch.cuda.stream(stream):
+        batch.capture(fs, u0s, u0s, Xs, gs, Xs, du0s, dv0s, stream=stream)
+        batch.replay(stream=stream)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(args.c5_steps):
+            batch.replay(stream=stream)
+    stream.synchronize()
+    t_graph = (time.perf_counter() - t0) / args.c5_steps
+    # plain loop: each problem's literal per-component forward, then its
+    # adjoint, one problem after the other (host-driven launches, no graph)
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        for sv, f, g, X, z, du, dv in zip(svs, fs, gs, Xs, u0s, du0s, dv0s):
+            sv.solve(f, z, z, out=X, plain=True, stream=stream)
+            sv.adjoint(g, X, du, dv, stream=stream)
+        stream.synchronize()
+        t_plain = time.perf_counter() - t0
+    # compulsory component I/O of one direction's solves (read the load,
+    # write the solution) and the tables they read
+    io = 16.0 * n_sparse
+    t_solves = 0.5 * (st["fwd_solves"] + st["adj_solves"])
+    ach_io = io / t_solves / 1e9
+    ach_all = (io + table_bytes) / t_solves / 1e9
+    counts = {}
+    for sp in specs:
+        counts[sp.L] = counts.get(sp.L, 0) + 1
+    out = {
+        "workload": (f"{n} problems d=2 Omega=(0,1)^2 T=1, L ~ U{{6..10}} (seed 0: "
+                     + ", ".join(f"L={L}: {c}" for L, c in sorted(counts.items()))
+                     + "), c on 4x4 blocks ~ U[0.5,2], f = 3 space-time Gaussians, u0=v0=0, "
+                       "g~N(0,1); step = forward + adjoint of all problems (one hipGraph)"),
+        "n_sparse": n_sparse,
+        "n_full": n_full,
+        "assembly_s": t_asm,
+        "batch_merge_s": t_merge,
+        "ms_per_step": t_graph * 1e3,
+        "batched_fwd_adj_dofs_per_s": n_sparse / t_graph,
+        "plain_loop_ms_per_step": t_plain * 1e3,
+        "batched_over_plain_speedup": t_plain / t_graph,
+        "fine_array_GB_per_s": 4 * 8.0 * n_full / t_graph / 1e9,
+        "eager_stage_ms": {k: v * 1e3 for k, v in st.items()},
+        "solve_roofline": {
+            "what": "merged component solves of one direction (mean of forward and adjoint)",
+            "ms": t_solves * 1e3,
+            "component_io_bytes": io,
+            "table_bytes": table_bytes,
+            "achieved_io_GB_per_s": ach_io,
+            "achieved_with_tables_GB_per_s": ach_all,
+            "peak": HBM_PEAK_GBS,
+            "frac_io": ach_io / HBM_PEAK_GBS,
+            "frac_with_tables": ach_all / HBM_PEAK_GBS,
+        },
+        "tuned": sg.tuning_status(),
+    }
+    del fs, gs, Xs
+    batch.close()
+    for sv in svs:
+        sv.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -145,16 +348,22 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    import workloads
+    spec, data = workloads.c3(L=args.L)
+    # the oracle's CPU baseline runs first, before the GPU is initialised, so
+    # that its process pool can fork
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(spec, data, args.cpu_max_dofs, args.cpu_procs)
+
     import torch
 
     import paper_2606_09688_amd as sg
-    import workloads
 
     dev = "cuda:0"
-    spec, data = workloads.c3(L=args.L)
     to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
     f, u0, v0, g = (to(data[k]) for k in ("f", "u0", "v0", "g"))
-    sv = sg.SparseGridWave(*spec.args())
+    sv = sg.SparseGridWave(*spec.args(), tuned=True)
     U = torch.empty(sv.shape, dtype=torch.float64, device=dev)
     df = torch.empty(sv.shape, dtype=torch.float64, device=dev)
     du0 = torch.empty(sv.space_shape, dtype=torch.float64, device=dev)
@@ -241,6 +450,19 @@ def main():
     graph_equals_eager = bool(torch.equal(U_graph, U) and torch.equal(df_graph, df))
     del U_graph, df_graph
 
+    # ---- forward-only graph (the batched forward) ----------------------------
+    sv.set_events(None)
+    with torch.cuda.stream(stream):
+        sv.capture(f, u0, v0, U, stream=stream)
+        sv.replay(stream=stream)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(args.steps):
+            sv.replay(stream=stream)
+    stream.synchronize()
+    t_graph_fwd = (time.perf_counter() - t0) / args.steps
+
     # ---- plain per-component loop (forward) ---------------------------------
     t_plain, plain_diff = float("nan"), float("nan")
     if args.plain_steps > 0:
@@ -300,8 +522,10 @@ def main():
             "n_full": nfull,
             "batched_fwd_adj_dofs_per_s": ns / t_step,
             "eager_fwd_dofs_per_s": ns / stage["fwd"],
+            "graph_fwd_dofs_per_s": ns / t_graph_fwd,
             "plain_fwd_dofs_per_s": ns / t_plain,
-            "batched_fwd_over_plain_fwd_speedup": t_plain / stage["fwd"],
+            "graph_fwd_over_plain_fwd_speedup": t_plain / t_graph_fwd,
+            "eager_fwd_over_plain_fwd_speedup": t_plain / stage["fwd"],
             "fwd_adj_over_fwd": (stage["fwd"] + stage["adj"]) / stage["fwd"],
             "plain_vs_fused_rel_l2": plain_diff,
             "graph_equals_eager": graph_equals_eager,
@@ -321,8 +545,15 @@ def main():
             "traffic": measured_traffic(name),
         },
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, data, args.cpu_seconds)
+    out["config"]["tuned"] = sg.tuning_status()
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    # ---- the 256-problem batch ----------------------------------------------
+    if not args.no_c5:
+        del f, g, U, df, du0, dv0
+        sv.close()
+        torch.cuda.empty_cache()
+        out["config"]["batch_c5"] = c5_batch(args, stream)
     print(json.dumps(out), flush=True)
 
 

@@ -255,6 +255,22 @@ sg_status sg_batch_capture(sg_batch *b, const double *const *f, const double *co
                            double *const *df, double *const *du0, double *const *dv0,
                            hipStream_t stream);
 sg_status sg_batch_launch(sg_batch *b, hipStream_t stream);
+/*
+ * Measurement support.  sg_batch_info: number of problems, the sum of their
+ * component dimensions (N^sparse) and the bytes of the tables one
+ * direction's merged solve stages read (inverse interface Schur complements
+ * and tridiagonal factors of the strip solves, transform matrices, time-solve
+ * LU factors, block-LU factors); outputs may be NULL.
+ * sg_batch_set_events: when ev is not NULL (SG_BATCH_EVENTS caller-created
+ * events), sg_batch_solve / sg_batch_adjoint record them on the caller's
+ * stream at: 0 forward begin, 1 before the merged solves, 2 after them,
+ * 3 forward end, 4 adjoint begin, 5 before the merged solves, 6 after them,
+ * 7 adjoint end.  Not recorded inside a captured batch graph.
+ */
+#define SG_BATCH_EVENTS 8
+sg_status sg_batch_info(const sg_batch *b, int *n, long long *n_sparse,
+                        long long *solve_table_bytes);
+sg_status sg_batch_set_events(sg_batch *b, hipEvent_t *ev, int n);
 sg_status sg_batch_destroy(sg_batch *b);
 
 /*

@@ -51,6 +51,9 @@ SIGNATURES = {
     "sg_batch_capture": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_void_p)] * 8
                          + [ctypes.c_void_p]),
     "sg_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_batch_info": (ctypes.c_int, [ctypes.c_void_p, _c_ip, _c_llp, _c_llp]),
+    "sg_batch_set_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.c_int]),
     "sg_batch_solve": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_void_p)] * 4
                        + [ctypes.c_void_p]),
     "sg_batch_adjoint": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_void_p)] * 4
@@ -193,16 +196,25 @@ class SparseGridWave:
     Arrays: f, U, g, df have shape (nt, n) / (nt, n, n); u0, v0 shape (n,) / (n, n).
     """
 
-    def __init__(self, d, lengths, ncell, c_vals, T, L):
+    def __init__(self, d, lengths, ncell, c_vals, T, L, tuned=False):
+        """tuned: build with the launch shapes the autotuner chose for this
+        shape class on this device (autotune.lookup; library defaults if the
+        class is not in the cache)."""
         import numpy as np
         L_ = lib()
         self.d = int(d)
         ln = (ctypes.c_double * d)(*[float(v) for v in lengths])
         nc = (ctypes.c_int * d)(*[int(v) for v in ncell])
         cv = np.ascontiguousarray(np.asarray(c_vals, dtype=np.float64).reshape(-1))
+        knobs = None
+        if tuned:
+            from . import autotune
+            knobs = autotune.lookup(d, L, bool(np.all(cv == cv[0])))
         h = ctypes.c_void_p()
-        check(L_.sg_assemble(d, ln, nc, cv.ctypes.data_as(_c_dp), float(T), int(L),
-                             ctypes.byref(h)), "sg_assemble")
+        from .autotune import knobs_set
+        with knobs_set(knobs):
+            check(L_.sg_assemble(d, ln, nc, cv.ctypes.data_as(_c_dp), float(T), int(L),
+                                 ctypes.byref(h)), "sg_assemble")
         self._h = h
         nt, n, nc_ = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         ns, nf = ctypes.c_longlong(), ctypes.c_longlong()
@@ -341,14 +353,18 @@ class SparseGridBatch:
         self._h = h
         self._keep = None
 
-    def __del__(self):
+    def close(self):
         h = getattr(self, "_h", None)
         if h:
-            try:
-                lib().sg_batch_destroy(h)
-            except Exception:
-                pass
+            lib().sg_batch_destroy(h)
             self._h = None
+        self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def _ptrs(self, lst, space, name, allow_none=False):
         if lst is None:
@@ -360,6 +376,26 @@ class SparseGridBatch:
         out = [_ptr(t, shp, f"{name}[{i}]", allow_none)
                for i, (t, shp) in enumerate(zip(lst, shapes))]
         return (ctypes.c_void_p * n)(*[None if v is None else v.value for v in out])
+
+    def info(self):
+        """(number of problems, sum of component dimensions, bytes of tables
+        read by one direction's merged solve stages)."""
+        n, ns, tb = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_longlong()
+        check(lib().sg_batch_info(self._h, ctypes.byref(n), ctypes.byref(ns), ctypes.byref(tb)),
+              "sg_batch_info")
+        return n.value, ns.value, tb.value
+
+    def set_events(self, events):
+        """Stage events of the eager batched calls (8 torch.cuda.Event) or None."""
+        if events is None:
+            check(lib().sg_batch_set_events(self._h, None, 0), "sg_batch_set_events")
+            return
+        for e in events:
+            if not e.cuda_event:
+                e.record()
+        torch.cuda.synchronize()
+        arr = (ctypes.c_void_p * len(events))(*[e.cuda_event for e in events])
+        check(lib().sg_batch_set_events(self._h, arr, len(events)), "sg_batch_set_events")
 
     def solve(self, f, u0, v0, U, stream=None):
         """Batched forward: lists of device tensors (one per problem)."""
@@ -401,6 +437,12 @@ class SGWaveFunction(torch.autograd.Function):
     def backward(ctx, gU):
         df, du0, dv0 = ctx.solver.adjoint(gU.contiguous())
         return None, df, du0, dv0
+
+
+def tuning_status():
+    """Which shape classes this process looked up in the tuning cache."""
+    from . import autotune
+    return autotune.status()
 
 
 def sgwave(solver, f, u0, v0):

@@ -57,7 +57,9 @@ sg_status fail(sg_status st, const std::string &msg) {
 struct Comp {
   int a, b, sign;
   int nsp, nq;
-  long long off;  // offset into the component buffers
+  long long off;   // offset into the component buffers (every component)
+  long long off2;  // offset into the transform / time-solve buffers (bufT, bufS,
+                   // fac, scratch), held only by components on that path
 };
 
 // one restriction or prolongation pass: geometry + channel table + work lists
@@ -106,6 +108,7 @@ struct BlockList {       // components solved by block LU + refinement
 struct FdmList {         // 2-D variable-speed components solved by time diagonalisation
   FdmDesc *d = nullptr;
   int n = 0;
+  int chunk = 8;         // rows per register chunk of the tridiagonal sweeps
   FdmTotals t;
   GemmList gf, gi;       // strip sine transforms X -> Y and Y -> X
   std::vector<FdmDesc> h;
@@ -134,6 +137,7 @@ struct sg_problem {
   double c2 = 1;
   std::vector<Comp> comps;
   long long nsparse = 0;
+  long long nsparse2 = 0;          // sum of the components on the transform / time-solve path
   long long nsp_fine = 0;
 
   std::vector<void *> allocs;
@@ -211,6 +215,7 @@ struct sg_problem {
   int refine_nq = 33;
   int wave_nq = 33;                // time levels with nq >= wave_nq: one wave per mode
   int gemm_fold = 2;               // folded DST-I transforms (build_gemm_lists)
+  int fdm_chunk = 8;               // rows per chunk of the strip solver's sweeps
   // optional stage events; during capture the dependencies at each mark
   std::vector<hipEvent_t> ev;
   bool capturing = false;
@@ -532,7 +537,9 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
     const int na = flat ? (int)C.nsp : (1 << C.a) - 1;
     const double *Q = p->tf[C.a], *Qi = p->ti[C.a];
     const int ny = p->d == 2 && !flat ? na : 1;
-    double *mid = flat ? p->bufS : p->bufT;
+    // this component's data (x_in, x_out at off) and transform buffer (at off2)
+    double *cin = x_in + C.off, *cout = x_out + C.off;
+    double *cmid = (flat ? p->bufS : p->bufT) + C.off2;
     constexpr int T = kGemmTile;
     auto tiles = [](int M, int N) { return ((M + T - 1) / T) * ((N + T - 1) / T); };
     const bool fx = gf >= 1, fy = p->d == 2 && (gf == 3 || (gf == 2 && C.a >= 7));
@@ -546,8 +553,8 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
         if (nh == 0) continue;
         for (int inv = 0; inv < 2 && fx; ++inv) {
           GemmDesc g{};
-          g.A = (inv ? mid : x_in) + C.off; g.B = p->th[par][C.a];
-          g.C = (inv ? x_out : mid) + C.off;
+          g.A = inv ? cmid : cin; g.B = p->th[par][C.a];
+          g.C = inv ? cout : cmid;
           g.M = C.nq * ny; g.N = nh; g.K = nh; g.lda = na; g.ldb = nh; g.ldc = na;
           g.nref = na; g.par = par;
           g.batch = 1; g.tm = (g.M + T - 1) / T; g.tn = (g.N + T - 1) / T;
@@ -559,8 +566,8 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
         if (fy) {
           for (int inv = 0; inv < 2; ++inv) {
             GemmDesc g{};
-            g.A = Q + (long long)par * na; g.B = (inv ? p->bufS : p->bufT) + C.off;
-            g.C = (inv ? p->bufT : p->bufS) + C.off;
+            g.A = Q + (long long)par * na; g.B = (inv ? p->bufS : p->bufT) + C.off2;
+            g.C = (inv ? p->bufT : p->bufS) + C.off2;
             g.M = nh; g.N = na; g.K = nh; g.lda = 2 * na; g.ldb = na; g.ldc = na;
             g.sA = 0; g.sB = slab; g.sC = slab; g.nref = na; g.par = par;
             g.batch = C.nq; g.tm = (g.M + T - 1) / T; g.tn = (g.N + T - 1) / T;
@@ -577,7 +584,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
     // forward x: T = B * Q   ([nq*ny x na] x [na x na])
     if (!fx) {
       GemmDesc g{};
-      g.A = x_in + C.off; g.B = Q; g.C = mid + C.off;
+      g.A = cin; g.B = Q; g.C = cmid;
       g.M = C.nq * ny; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
       g.batch = 1; g.tm = (g.M + T - 1) / T; g.tn = (g.N + T - 1) / T; g.tile0 = tx;
       tx += tiles(g.M, g.N);
@@ -586,7 +593,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
     // inverse x: U = T * Q^{-1}
     if (!fx) {
       GemmDesc g{};
-      g.A = mid + C.off; g.B = Qi; g.C = x_out + C.off;
+      g.A = cmid; g.B = Qi; g.C = cout;
       g.M = C.nq * ny; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
       g.batch = 1; g.tm = (g.M + T - 1) / T; g.tn = (g.N + T - 1) / T; g.tile0 = tix;
       tix += tiles(g.M, g.N);
@@ -596,7 +603,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
       const long long slab = (long long)na * na;
       // forward y: S_i = Q * T_i
       GemmDesc g{};
-      g.A = Q; g.B = p->bufT + C.off; g.C = p->bufS + C.off;
+      g.A = Q; g.B = p->bufT + C.off2; g.C = p->bufS + C.off2;
       g.M = na; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
       g.sA = 0; g.sB = slab; g.sC = slab;
       g.batch = C.nq; g.tm = (na + T - 1) / T; g.tn = (na + T - 1) / T; g.tile0 = ty;
@@ -604,7 +611,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
       vy.push_back(g);
       // inverse y: T_i = Q * S_i
       GemmDesc h = g;
-      h.B = p->bufS + C.off; h.C = p->bufT + C.off; h.tile0 = tiy;
+      h.B = p->bufS + C.off2; h.C = p->bufT + C.off2; h.tile0 = tiy;
       tiy += C.nq * tiles(na, na);
       viy.push_back(h);
     }
@@ -639,9 +646,9 @@ sg_status build_solve_list(sg_problem *p, const std::vector<int> &cset, int tran
       const int wave = C.nq >= p->wave_nq ? 1 : 0;
       if (wave != (pass == 0 ? 1 : 0)) continue;
       SolveDesc sd{};
-      sd.rhs = (p->d == 2 ? p->bufS : p->bufT) + C.off;
-      sd.fac = p->fac + 5 * C.off;
-      sd.scratch = p->scratch + 2 * C.off;
+      sd.rhs = (p->d == 2 ? p->bufS : p->bufT) + C.off2;
+      sd.fac = p->fac + 5 * C.off2;
+      sd.scratch = p->scratch + 2 * C.off2;
       sd.nq = C.nq;
       sd.nmodes = C.nsp;
       sd.b = C.b;
@@ -674,9 +681,9 @@ sg_status run_fdm(const FdmList &f, hipStream_t s) {
   if (f.n == 0) return SG_OK;
   HIPCHK(launch_fdm_in(f.d, f.n, f.t, s));
   HIPCHK(launch_gemm(f.gf.d, f.gf.n, f.gf.tiles, 0, s));
-  HIPCHK(launch_fdm_tri(f.d, f.n, f.t, 0, s));
+  HIPCHK(launch_fdm_tri(f.d, f.n, f.t, 0, f.chunk, s));
   HIPCHK(launch_fdm_interface(f.d, f.n, f.t, s));
-  HIPCHK(launch_fdm_tri(f.d, f.n, f.t, 1, s));
+  HIPCHK(launch_fdm_tri(f.d, f.n, f.t, 1, f.chunk, s));
   HIPCHK(launch_gemm(f.gi.d, f.gi.n, f.gi.tiles, 0, s));
   HIPCHK(launch_fdm_out(f.d, f.n, f.t, s));
   return SG_OK;
@@ -834,6 +841,7 @@ sg_status build_fdm(sg_problem *p, const std::vector<TimeLevel> &tl_host) {
     }
     // one-component list for the plain loop
     FdmList &pl = p->pffwd[ci];
+    pl.chunk = p->fdm_chunk;
     FdmDesc one_f = hf;
     one_f.node0 = one_f.tri0 = one_f.edge0 = one_f.if0 = one_f.gemv0 = 0;
     if ((st = upload(p, std::vector<FdmDesc>{one_f}, &pl.d))) return st;
@@ -846,6 +854,7 @@ sg_status build_fdm(sg_problem *p, const std::vector<TimeLevel> &tl_host) {
     pl.gi.tiles = pti;
   }
   for (FdmList *L : {&p->ffwd, &p->fadj}) {
+    L->chunk = p->fdm_chunk;
     L->h = L == &p->ffwd ? vf : va;
     L->gf.h = gf;
     L->gi.h = gi;
@@ -936,6 +945,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   if (const char *e = getenv("SG_REFINE_NQ")) p->refine_nq = atoi(e);
   if (const char *e = getenv("SG_WAVE_NQ")) p->wave_nq = atoi(e);
   if (const char *e = getenv("SG_GEMM_FOLD")) p->gemm_fold = std::min(3, std::max(0, atoi(e)));
+  if (const char *e = getenv("SG_FDM_CH")) p->fdm_chunk = std::min(16, std::max(4, atoi(e)));
 
   // components: +1 on jx + jt = L (jx = 1..L-1), -1 on jx + jt = L-1 (jx = 1..L-2)
   long long off = 0;
@@ -990,6 +1000,12 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
                              std::to_string(kFdmMaxInterface) + " interface nodes"));
       }
     }
+  }
+  // the transform / time-solve buffers hold only the components on that path
+  for (size_t ci = 0; ci < p->comps.size(); ++ci) {
+    Comp &C = p->comps[ci];
+    C.off2 = p->nsparse2;
+    if (!p->blockc[ci] && !p->fdmc[ci]) p->nsparse2 += (long long)C.nsp * C.nq;
   }
   const int ntf = N + 1;
   auto comp_index = [&](int a, int k) -> int {  // k=0 plus, 1 minus
@@ -1159,11 +1175,11 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   // ---- buffers ------------------------------------------------------------
   const long long ns = p->nsparse;
   if (!(p->bufZ = p->dalloc<double>(ns)) || !(p->bufB = p->dalloc<double>(ns)) ||
-      !(p->bufT = p->dalloc<double>(ns)) || !(p->bufS = p->dalloc<double>(ns)) ||
+      !(p->bufT = p->dalloc<double>(p->nsparse2)) || !(p->bufS = p->dalloc<double>(p->nsparse2)) ||
       !(p->bufU = p->dalloc<double>(ns)) || !(p->bufW = p->dalloc<double>(ns)) ||
       !(p->bufY = p->dalloc<double>(ns)) ||
-      !(p->fac = p->dalloc<double>(5 * ns)) ||
-      !(p->scratch = p->dalloc<double>(2 * ns)))
+      !(p->fac = p->dalloc<double>(5 * p->nsparse2)) ||
+      !(p->scratch = p->dalloc<double>(2 * p->nsparse2)))
     return bail(fail(SG_ENOMEM, "hipMalloc of component buffers failed"));
   p->mv_lv.assign(J + 1, nullptr);
   p->ku_lv.assign(J + 1, nullptr);
@@ -1829,9 +1845,17 @@ struct sg_batch {
   long long lev_total = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  std::vector<hipEvent_t> ev;        // optional stage events (eager runs)
+  long long n_sparse = 0;            // sum of the problems' component dimensions
+  long long table_bytes = 0;         // tables read by one direction's solve stages
 };
 
 namespace {
+
+sg_status bmark(sg_batch *b, int id, hipStream_t s) {
+  if (id < (int)b->ev.size() && b->ev[id] != nullptr) HIPCHK(hipEventRecord(b->ev[id], s));
+  return SG_OK;
+}
 
 template <class T>
 sg_status bupload(sg_batch *b, const std::vector<T> &h, T **out) {
@@ -1952,6 +1976,7 @@ sg_status merge_fdm(sg_batch *b, FdmList sg_problem::*member, FdmList &out) {
   out.h = v;
   out.n = (int)v.size();
   out.t = t;
+  out.chunk = (b->probs[0]->*member).chunk;
   sg_status st;
   if ((st = bupload(b, v, &out.d))) return st;
   if ((st = merge_gemm_list(b, gf, out.gf))) return st;
@@ -1981,6 +2006,7 @@ sg_status batch_forward(sg_batch *b, const double *const *f, const double *const
     if (U[i] == f[i]) return fail(SG_EINVAL, "U must not alias f");
   }
   sg_status st;
+  if ((st = bmark(b, 0, s))) return st;
   if ((st = fork(b, s))) return st;
   for (int i = 0; i < n; ++i) {
     sg_problem *p = b->probs[i];
@@ -1990,6 +2016,7 @@ sg_status batch_forward(sg_batch *b, const double *const *f, const double *const
   }
   if ((st = join(b, s))) return st;
   HIPCHK(launch_post_load(b->cload.d, b->cload.n, b->cload.total, s));
+  if ((st = bmark(b, 1, s))) return st;
   if ((st = run_fdm(b->ffwd, s))) return st;
   HIPCHK(launch_block_solve(b->bfwd.d, b->bfwd.n, s));
   HIPCHK(launch_gemm(b->gx.d, b->gx.n, b->gx.tiles, b->gx.fold, s));
@@ -1997,13 +2024,15 @@ sg_status batch_forward(sg_batch *b, const double *const *f, const double *const
   HIPCHK(launch_time_solve(b->sfwd.d, b->sfwd.n, b->sfwd.threads, s));
   HIPCHK(launch_gemm(b->giy.d, b->giy.n, b->giy.tiles, b->giy.fold, s));
   HIPCHK(launch_gemm(b->gix.d, b->gix.n, b->gix.tiles, b->gix.fold, s));
+  if ((st = bmark(b, 2, s))) return st;
   if ((st = fork(b, s))) return st;
   for (int i = 0; i < n; ++i) {
     sg_problem *p = b->probs[i];
     hipStream_t bs = b->streams[i % b->streams.size()];
     if ((st = run_prolong(p, p->prol, u0[i], U[i], 0, 0, bs, -1, p->ws.Cpro))) return st;
   }
-  return join(b, s);
+  if ((st = join(b, s))) return st;
+  return bmark(b, 3, s);
 }
 
 sg_status batch_adjoint(sg_batch *b, const double *const *g, double *const *df,
@@ -2013,6 +2042,7 @@ sg_status batch_adjoint(sg_batch *b, const double *const *g, double *const *df,
   for (int i = 0; i < n; ++i)
     if (!g[i]) return fail(SG_EINVAL, "NULL cotangent");
   sg_status st;
+  if ((st = bmark(b, 4, s))) return st;
   if ((st = fork(b, s))) return st;
   for (int i = 0; i < n; ++i) {
     sg_problem *p = b->probs[i];
@@ -2020,6 +2050,7 @@ sg_status batch_adjoint(sg_batch *b, const double *const *g, double *const *df,
     if ((st = run_restrict(p, p->ws, p->adjr, g[i], 0, bs))) return st;
   }
   if ((st = join(b, s))) return st;
+  if ((st = bmark(b, 5, s))) return st;
   if ((st = run_fdm(b->fadj, s))) return st;
   HIPCHK(launch_block_solve(b->badj.d, b->badj.n, s));
   HIPCHK(launch_gemm(b->agx.d, b->agx.n, b->agx.tiles, b->agx.fold, s));
@@ -2027,6 +2058,7 @@ sg_status batch_adjoint(sg_batch *b, const double *const *g, double *const *df,
   HIPCHK(launch_time_solve(b->sadj.d, b->sadj.n, b->sadj.threads, s));
   HIPCHK(launch_gemm(b->giy.d, b->giy.n, b->giy.tiles, b->giy.fold, s));
   HIPCHK(launch_gemm(b->agix.d, b->agix.n, b->agix.tiles, b->agix.fold, s));
+  if ((st = bmark(b, 6, s))) return st;
   HIPCHK(launch_post_adjoint(b->cadj.d, b->cadj.n, b->cadj.total, s));
   bool fields = false;
   for (int i = 0; i < n; ++i) fields = fields || (du0 && du0[i]) || (dv0 && dv0[i]);
@@ -2046,7 +2078,8 @@ sg_status batch_adjoint(sg_batch *b, const double *const *g, double *const *df,
                                   p->ws.fine2 + p->nsp_fine, dv, du, p->gsum, 1, bs));
     }
   }
-  return join(b, s);
+  if ((st = join(b, s))) return st;
+  return bmark(b, 7, s);
 }
 
 // stage events of the member problems are switched off inside batch work
@@ -2146,7 +2179,41 @@ sg_status sg_batch_create(int n, sg_problem *const *problems, sg_batch **out) {
   if ((st = bupload(b, lv, &b->d_lev))) return bail(st);
   b->nlev = (int)lv.size();
   b->lev_total = tt;
+  // sizes for measurement: component DoFs, and the tables one direction's
+  // solve stages read (inverse interface Schur complements and tridiagonal
+  // factors of the strip solves, dense transform matrices, time-solve LU
+  // factors, block-LU factors)
+  for (sg_problem *p : b->probs) b->n_sparse += p->nsparse;
+  long long tb = 0;
+  for (const FdmDesc &d : b->ffwd.h) {
+    const long long NG = (long long)d.ni * d.n;
+    tb += 16LL * d.nu * NG * NG + 2LL * 48 * d.nu * d.ns * d.n * d.m;
+  }
+  for (const GemmList *L : {&b->gx, &b->gy, &b->giy, &b->gix})
+    for (const GemmDesc &g : L->h)
+      tb += 8LL * (g.sA == 0 && g.batch > 1 ? (long long)g.M * g.K : (long long)g.K * g.N);
+  for (const SolveDesc &d : b->sfwd.h) tb += 8LL * 5 * d.nq * d.nmodes;
+  for (const BlockDesc &d : b->bfwd.h) tb += 8LL * 2 * d.nq * d.nq * d.nx;
+  b->table_bytes = tb;
   *out = b;
+  return SG_OK;
+}
+
+sg_status sg_batch_info(const sg_batch *b, int *n, long long *n_sparse,
+                        long long *solve_table_bytes) {
+  if (!b) return fail(SG_EINVAL, "NULL batch");
+  if (n) *n = (int)b->probs.size();
+  if (n_sparse) *n_sparse = b->n_sparse;
+  if (solve_table_bytes) *solve_table_bytes = b->table_bytes;
+  return SG_OK;
+}
+
+sg_status sg_batch_set_events(sg_batch *b, hipEvent_t *ev, int n) {
+  if (!b) return fail(SG_EINVAL, "NULL batch");
+  b->ev.clear();
+  if (ev == nullptr) return SG_OK;
+  if (n < SG_BATCH_EVENTS) return fail(SG_EINVAL, "need SG_BATCH_EVENTS events");
+  b->ev.assign(ev, ev + n);
   return SG_OK;
 }
 
@@ -2179,6 +2246,13 @@ sg_status sg_batch_capture(sg_batch *b, const double *const *f, const double *co
     b->graph = nullptr;
   }
   EventsOff off(b);
+  std::vector<hipEvent_t> bev;  // no stage events inside the batch graph
+  bev.swap(b->ev);
+  struct Restore {
+    sg_batch *b;
+    std::vector<hipEvent_t> &v;
+    ~Restore() { v.swap(b->ev); }
+  } restore{b, bev};
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   sg_status st = batch_forward(b, f, u0, v0, U, s);
   if (st == SG_OK && g != nullptr) st = batch_adjoint(b, g, df, du0, dv0, s);

@@ -207,12 +207,9 @@ __global__ void k_fdm_out(const FdmDesc *__restrict__ ds, int nd, long long tota
 // Both sweeps run in chunks of FCH rows: the chunk's operands are loaded into
 // registers first (independent loads in flight together), then the
 // recurrence runs on registers.
-#ifndef SG_FDM_CH
-#define SG_FDM_CH 8
-#endif
+template <int FCH>
 __global__ void __launch_bounds__(64) k_fdm_tri(const FdmDesc *__restrict__ ds, int nd,
                                                 long long total, int correction) {
-  constexpr int FCH = SG_FDM_CH;
   const long long g = gid64();
   if (g >= total) return;
   const FdmDesc &D = ds[find_fdm(ds, nd, g, kTri)];
@@ -652,10 +649,15 @@ hipError_t launch_fdm_in(const FdmDesc *d, int nd, const FdmTotals &t, hipStream
 }
 
 hipError_t launch_fdm_tri(const FdmDesc *d, int nd, const FdmTotals &t, int correction,
-                          hipStream_t s) {
+                          int chunk, hipStream_t s) {
   if (nd == 0 || t.tri == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fdm_tri, dim3(nblk(t.tri, 64)), dim3(64), 0, s, d, nd, t.tri,
-                     correction);
+  const dim3 grid(nblk(t.tri, 64));
+  if (chunk <= 4)
+    hipLaunchKernelGGL(k_fdm_tri<4>, grid, dim3(64), 0, s, d, nd, t.tri, correction);
+  else if (chunk <= 8)
+    hipLaunchKernelGGL(k_fdm_tri<8>, grid, dim3(64), 0, s, d, nd, t.tri, correction);
+  else
+    hipLaunchKernelGGL(k_fdm_tri<16>, grid, dim3(64), 0, s, d, nd, t.tri, correction);
   return hipGetLastError();
 }
 

@@ -244,8 +244,9 @@ struct FdmTotals {       // launch sizes of one list of FdmDesc
 // solve phase of a list of components (stream ordered; the strip sine
 // transforms are the GEMM lists gf (X -> Y) and gi (Y -> X))
 hipError_t launch_fdm_in(const FdmDesc *d, int nd, const FdmTotals &t, hipStream_t s);
+// chunk: rows per register chunk of the sweeps (4, 8 or 16)
 hipError_t launch_fdm_tri(const FdmDesc *d, int nd, const FdmTotals &t, int correction,
-                          hipStream_t s);
+                          int chunk, hipStream_t s);
 hipError_t launch_fdm_interface(const FdmDesc *d, int nd, const FdmTotals &t, hipStream_t s);
 hipError_t launch_fdm_out(const FdmDesc *d, int nd, const FdmTotals &t, hipStream_t s);
 // assembly of one component (descriptor h, device pointers): tridiagonal

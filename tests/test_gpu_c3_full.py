@@ -94,3 +94,34 @@ def test_whole_array_properties(run):
     assert torch.equal(run["Ug"], run["U"]) and torch.equal(run["dfg"], run["df"])
     assert torch.equal(run["du0g"], run["du0"]) and torch.equal(run["dv0g"], run["dv0"])
     assert bool(torch.isfinite(run["U"]).all()) and bool(torch.isfinite(run["df"]).all())
+
+
+SKETCH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_sketch.json")
+
+
+def test_whole_arrays_against_oracle_sketches(run):
+    """Whole-array parity at full size: the oracle's norms and 16 separable
+    random projections of U, df, du0, dv0 (make_sketch_golden.py c3) against
+    the same projections of the library's arrays (eager and graph); the
+    estimated relative l2 error of every whole array is <= 1e-10.  Every
+    component's load and solution likewise."""
+    from sketchcheck import sketch_error
+    if not os.path.exists(SKETCH):
+        pytest.skip("no stored c3 sketches")
+    with open(SKETCH) as fh:
+        gold = json.load(fh)
+    spec = run["spec"]
+    shp, sshp = spec.shape(), spec.space_shape()
+    for tag, sfx in (("eager", ""), ("graph", "g")):
+        errs = {}
+        for name, shape in (("U", shp), ("df", shp), ("du0", sshp), ("dv0", sshp)):
+            est, dn = sketch_error(run[name + sfx].reshape(shape), gold[name])
+            errs[name] = est
+            assert est <= TOL and dn <= TOL, (tag, name, est, dn)
+        print(f"  {tag}: " + "  ".join(f"{n} {e:.1e}" for n, e in errs.items()), flush=True)
+    for (b, u), gc in zip(run["comps"], gold["components"]):
+        na = 2 ** gc["jx"] - 1
+        for arr, ent in ((b, gc["load"]), (u, gc["sol"])):
+            got = np.asarray(workloads.sketch(arr.reshape(-1, na, na), len(ent["sketch"])))
+            est = float(np.sqrt(np.mean((got - np.asarray(ent["sketch"])) ** 2)) / ent["norm"])
+            assert est <= TOL, (gc["jx"], gc["jt"], est)

@@ -1,0 +1,101 @@
+"""The 256-problem batch workload (d=2, L ~ U{6..10}, 4x4 wave-speed blocks,
+three space-time Gaussian sources): a stratified subset (the first two
+problems of every level) runs as one batch, eagerly and from the captured
+graph, and is compared with the oracle's stored sketches of U, df, du0 and
+dv0 (tests/golden/make_sketch_golden.py c5): estimated whole-array relative
+l2 error <= 1e-10.  Every problem of the subset runs at its full size."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from sketchcheck import sketch_error
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_sketch.json")
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def run():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if not os.path.exists(GOLDEN):
+        pytest.skip("no stored c5 sketches")
+    import paper_2606_09688_amd as sg
+    with open(GOLDEN) as fh:
+        gold = json.load(fh)["problems"]
+    specs = workloads.c5_specs()
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+    svs, ins = [], []
+    for p in gold:
+        spec = specs[p["index"]]
+        print(f"batch subset: problem {p['index']} L={spec.L}", flush=True)
+        data = workloads.c5_data(spec, p["index"])
+        ins.append(tuple(dev(data[k]) for k in ("f", "u0", "v0", "g")))
+        svs.append(sg.SparseGridWave(*spec.args()))
+    batch = sg.SparseGridBatch(svs)
+    mk = lambda t: torch.empty_like(t)
+    U = [mk(x[0]) for x in ins]
+    df = [mk(x[0]) for x in ins]
+    du0 = [mk(x[1]) for x in ins]
+    dv0 = [mk(x[1]) for x in ins]
+    batch.solve([x[0] for x in ins], [x[1] for x in ins], [x[2] for x in ins], U)
+    batch.adjoint([x[3] for x in ins], df, du0, dv0)
+    torch.cuda.synchronize()
+    yield dict(gold=gold, specs=specs, svs=svs, ins=ins, batch=batch, U=U, df=df, du0=du0,
+               dv0=dv0)
+    batch.close()
+
+
+def test_subset_against_oracle_sketches(run):
+    for k, p in enumerate(run["gold"]):
+        errs = {}
+        for name in ("U", "df", "du0", "dv0"):
+            est, dn = sketch_error(run[name][k], p[name])
+            errs[name] = est
+            assert est <= TOL and dn <= TOL, (p["index"], name, est, dn)
+        print(f"  problem {p['index']} L={p['L']}: " +
+              "  ".join(f"{n} {e:.1e}" for n, e in errs.items()), flush=True)
+
+
+def test_graph_replay_equals_eager(run):
+    import torch
+    ins, batch = run["ins"], run["batch"]
+    U2 = [torch.empty_like(x) for x in run["U"]]
+    df2 = [torch.empty_like(x) for x in run["df"]]
+    du2 = [torch.empty_like(x) for x in run["du0"]]
+    dv2 = [torch.empty_like(x) for x in run["dv0"]]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        batch.capture([x[0] for x in ins], [x[1] for x in ins], [x[2] for x in ins], U2,
+                      [x[3] for x in ins], df2, du2, dv2, stream=s)
+    for rep in range(2):
+        for t in U2 + df2:
+            t.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            batch.replay(stream=s)
+        s.synchronize()
+        for k in range(len(ins)):
+            assert torch.equal(U2[k], run["U"][k]) and torch.equal(df2[k], run["df"][k]), (rep, k)
+            assert torch.equal(du2[k], run["du0"][k]) and torch.equal(dv2[k], run["dv0"][k])
+
+
+def test_batch_equals_each_problems_own_solve(run):
+    """The merged solve stages give each problem's own sg_solve / sg_adjoint
+    result bit for bit (checked on the two largest problems)."""
+    import torch
+    for k in (len(run["gold"]) - 2, len(run["gold"]) - 1):
+        sv = run["svs"][k]
+        f, u0, v0, g = run["ins"][k]
+        U = sv.solve(f, u0, v0)
+        df, du0, dv0 = sv.adjoint(g)
+        torch.cuda.synchronize()
+        assert torch.equal(U, run["U"][k]) and torch.equal(df, run["df"][k]), k
+        assert torch.equal(du0, run["du0"][k]) and torch.equal(dv0, run["dv0"][k]), k

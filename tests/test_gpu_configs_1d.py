@@ -133,3 +133,30 @@ def test_gradient_of_misfit():
                 worst = max(worst, abs(fd - an) / max(abs(an), 1e-300))
             print(f"  finite differences (32 directions, h = {h:g}): worst rel {worst:.2e} "
                   f"(|J| = {Jv:.3e})", flush=True)
+
+
+def test_adjoint_of_a_stored_cotangent_at_full_size():
+    """The differentiation workload's adjoint on the SAME seeded cotangent as
+    the oracle (workloads.c4_cotangent; make_sketch_golden.py c4), so that no
+    forward rounding enters the comparison: du0 and dv0 element by element
+    in full, df and the forward U at the gradient point through whole-array
+    sketches, all to 1e-10 relative l2."""
+    torch = _torch()
+    import paper_2606_09688_amd as sg
+    from sketchcheck import sketch_error
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_sketch.json")
+    with open(path) as fh:
+        gold = json.load(fh)
+    spec, data = workloads.c4()
+    print("differentiation workload: adjoint of a stored cotangent, d=1 L=14", flush=True)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+    sv = sg.SparseGridWave(*spec.args())
+    U = sv.solve(dev(data["f"]), dev(data["u0"]), dev(data["v0"]))
+    df, du0, dv0 = sv.adjoint(dev(workloads.c4_cotangent(spec)))
+    torch.cuda.synchronize()
+    edu = _rel(du0.cpu().numpy(), np.asarray(gold["du0_full"]))
+    edv = _rel(dv0.cpu().numpy(), np.asarray(gold["dv0_full"]))
+    eU, _ = sketch_error(U, gold["U"])
+    edf, _ = sketch_error(df, gold["df"])
+    print(f"  U {eU:.2e}  df {edf:.2e}  du0 {edu:.2e}  dv0 {edv:.2e}", flush=True)
+    assert max(eU, edf, edu, edv) <= TOL

@@ -161,6 +161,12 @@ def c5_specs(n=256, seed=0):
     return specs
 
 
+def c5_centres(index, seed=0):
+    """Centres (x, y, t) of problem `index`'s three Gaussians: the first draws
+    of its substream [seed, index] (as in c5_data)."""
+    return np.random.default_rng([seed, index]).uniform(0.0, 1.0, (3, 3))
+
+
 def c5_data(spec, index, seed=0):
     """Data of problem `index`: f = sum of 3 Gaussians with centres from a
     per-problem substream; u0 = v0 = 0; cotangent g ~ N(0,1)."""
@@ -179,3 +185,37 @@ def random_data(spec, seed):
                 u0=rng.standard_normal(spec.space_shape()),
                 v0=rng.standard_normal(spec.space_shape()),
                 g=rng.standard_normal(spec.shape()))
+
+
+# ------------------------------------------------- full-array parity sketches --
+#
+# A full-size array X is compared through k separable random projections
+# s_k = <X, v_k0 (x) v_k1 (x) ...> with N(0,1) vectors per axis: for an error
+# D, E[<D, v_0 (x) v_1 ...>^2] = ||D||^2, so the root mean square of the
+# sketch differences estimates the whole-array l2 error without storing X,
+# and an error anywhere (one slab, one tile) shows up.
+
+def sketch_vectors(shape, k, seed=0):
+    """Per-axis N(0,1) vectors of projection k (substream [seed, 7000 + k, axis])."""
+    return [np.random.default_rng([seed, 7000 + k, ax]).standard_normal(n)
+            for ax, n in enumerate(shape)]
+
+
+def sketch(X, nproj=16, seed=0):
+    """The nproj separable projections of X (any number of axes), contracting
+    the last axis first."""
+    X = np.asarray(X, dtype=np.float64)
+    out = []
+    for k in range(nproj):
+        v = sketch_vectors(X.shape, k, seed)
+        Y = X
+        for ax in range(X.ndim - 1, -1, -1):
+            Y = Y @ v[ax]
+        out.append(float(Y))
+    return out
+
+
+def c4_cotangent(spec, seed=0):
+    """A seeded N(0,1) cotangent of the differentiation workload's shape
+    (substream [seed, 2000]): both sides run the adjoint on the same input."""
+    return np.random.default_rng([seed, 2000]).standard_normal(spec.shape())
