@@ -126,6 +126,10 @@ sg_status sg_adjoint(sg_problem *p, const double *g, double *df, double *du0,
  * Capture sg_solve (and, if g != NULL, sg_adjoint) for fixed buffers into a
  * HIP graph owned by the handle, replacing any earlier capture.  The stream
  * must not be capturing already.  sg_graph_launch replays it on a stream.
+ * With a given cotangent the adjoint does not depend on the forward; it
+ * keeps its own workspace and runs on a parallel branch of the graph, unless
+ * an output of one direction is a buffer of the other (then one after the
+ * other).
  */
 sg_status sg_graph_capture(sg_problem *p, const double *f, const double *u0,
                            const double *v0, double *U, const double *g,
@@ -238,9 +242,9 @@ const char *sg_last_error(void);
  *   ordered, allocation-free; results equal each problem's sg_solve /
  *   sg_adjoint bit for bit.  In the adjoint, df, du0, dv0 may be NULL as a
  *   whole or per problem.
- * sg_batch_capture: captures sg_batch_solve (and sg_batch_adjoint when g is
- *   not NULL) into one HIP graph owned by the batch; sg_batch_launch replays
- *   it.
+ * sg_batch_capture: captures sg_batch_solve (and after it sg_batch_adjoint
+ *   when g is not NULL) into one HIP graph owned by the batch;
+ *   sg_batch_launch replays it.
  * A handle must not belong to two batches that run at once, nor be used
  * elsewhere while its batch runs.
  */

@@ -169,6 +169,9 @@ struct sg_problem {
   // buffers (N^sparse each)
   double *bufZ = nullptr, *bufB = nullptr, *bufT = nullptr, *bufS = nullptr,
          *bufU = nullptr, *bufW = nullptr, *bufY = nullptr, *scratch = nullptr;
+  // the adjoint's own restricted cotangent, transform buffers and time-solve
+  // scratch, so that a forward and an adjoint may run at the same time
+  double *bufZa = nullptr, *bufTa = nullptr, *bufSa = nullptr, *scratcha = nullptr;
   double *fac = nullptr;           // 5 planes per component: LU factors per mode
   // level fields [3][nsp_a] per level (row 0 meaningful)
   std::vector<double *> mv_lv, ku_lv, fv_lv, fu_lv;
@@ -179,7 +182,8 @@ struct sg_problem {
   double *S0 = nullptr;            // coarse level-A0 arrays
   double *SL = nullptr;            // their restrictions to the levels a < A0
   double *Cpro = nullptr;          // prolongation coarse array
-  Scratch ws;                      // the handle's own scratch (the buffers above)
+  Scratch ws;                      // the forward's per-call scratch (the buffers above)
+  Scratch wsa;                     // the adjoint's
   long long n_part = 0, n_cpart = 0, n_S0 = 0, n_SL = 0;  // their sizes (doubles)
   // passes
   Pass load, prol, adjr, adjp, fieldr, fieldp;
@@ -193,7 +197,8 @@ struct sg_problem {
   std::vector<Pass> plain_load, plain_prol;
   // descriptor lists
   GemmList gx, gy, giy, gix;       // fused (all components)
-  GemmList agx, agix;              // adjoint: x-transform from bufZ, inverse into bufW
+  GemmList agx, agix;              // adjoint: x-transform from bufZa, inverse into bufW
+  GemmList agy, agiy;              // adjoint: y transforms on bufTa / bufSa
   std::vector<GemmList> pgx, pgy, pgiy, pgix;
   SolveList sfwd, sadj;
   std::vector<SolveList> psfwd;
@@ -212,6 +217,10 @@ struct sg_problem {
   // graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // a captured forward + adjoint runs the adjoint on its own branch (the two
+  // are independent for a given cotangent): stream and fork / join events
+  hipStream_t aux = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int refine_nq = 33;
   int wave_nq = 33;                // time levels with nq >= wave_nq: one wave per mode
   int gemm_fold = 2;               // folded DST-I transforms (build_gemm_lists)
@@ -512,9 +521,12 @@ sg_status run_prolong(sg_problem *p, const Pass &P, const double *base, double *
 // DST descriptor lists for a set of components: x-transform src->dst
 sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList &gx,
                            GemmList &gy, GemmList &giy, GemmList &gix,
-                           double *x_in = nullptr, double *x_out = nullptr) {
+                           double *x_in = nullptr, double *x_out = nullptr,
+                           double *bT = nullptr, double *bS = nullptr) {
   if (!x_in) x_in = p->bufB;
   if (!x_out) x_out = p->bufU;
+  if (!bT) bT = p->bufT;
+  if (!bS) bS = p->bufS;
   std::vector<GemmDesc> vx, vy, viy, vix;
   int tx = 0, ty = 0, tiy = 0, tix = 0;
   // constant c: the transforms are DST-I products, which can be folded into
@@ -539,7 +551,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
     const int ny = p->d == 2 && !flat ? na : 1;
     // this component's data (x_in, x_out at off) and transform buffer (at off2)
     double *cin = x_in + C.off, *cout = x_out + C.off;
-    double *cmid = (flat ? p->bufS : p->bufT) + C.off2;
+    double *cmid = (flat ? bS : bT) + C.off2;
     constexpr int T = kGemmTile;
     auto tiles = [](int M, int N) { return ((M + T - 1) / T) * ((N + T - 1) / T); };
     const bool fx = gf >= 1, fy = p->d == 2 && (gf == 3 || (gf == 2 && C.a >= 7));
@@ -566,8 +578,8 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
         if (fy) {
           for (int inv = 0; inv < 2; ++inv) {
             GemmDesc g{};
-            g.A = Q + (long long)par * na; g.B = (inv ? p->bufS : p->bufT) + C.off2;
-            g.C = (inv ? p->bufT : p->bufS) + C.off2;
+            g.A = Q + (long long)par * na; g.B = (inv ? bS : bT) + C.off2;
+            g.C = (inv ? bT : bS) + C.off2;
             g.M = nh; g.N = na; g.K = nh; g.lda = 2 * na; g.ldb = na; g.ldc = na;
             g.sA = 0; g.sB = slab; g.sC = slab; g.nref = na; g.par = par;
             g.batch = C.nq; g.tm = (g.M + T - 1) / T; g.tn = (g.N + T - 1) / T;
@@ -603,7 +615,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
       const long long slab = (long long)na * na;
       // forward y: S_i = Q * T_i
       GemmDesc g{};
-      g.A = Q; g.B = p->bufT + C.off2; g.C = p->bufS + C.off2;
+      g.A = Q; g.B = bT + C.off2; g.C = bS + C.off2;
       g.M = na; g.N = na; g.K = na; g.lda = na; g.ldb = na; g.ldc = na;
       g.sA = 0; g.sB = slab; g.sC = slab;
       g.batch = C.nq; g.tm = (na + T - 1) / T; g.tn = (na + T - 1) / T; g.tile0 = ty;
@@ -611,7 +623,7 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
       vy.push_back(g);
       // inverse y: T_i = Q * S_i
       GemmDesc h = g;
-      h.B = p->bufS + C.off2; h.C = p->bufT + C.off2; h.tile0 = tiy;
+      h.B = bS + C.off2; h.C = bT + C.off2; h.tile0 = tiy;
       tiy += C.nq * tiles(na, na);
       viy.push_back(h);
     }
@@ -634,6 +646,9 @@ sg_status build_gemm_lists(sg_problem *p, const std::vector<int> &cset, GemmList
 
 sg_status build_solve_list(sg_problem *p, const std::vector<int> &cset, int transpose,
                            SolveList &L) {
+  // the adjoint works in its own transform buffers and scratch
+  double *bT = transpose ? p->bufTa : p->bufT, *bS = transpose ? p->bufSa : p->bufS;
+  double *scr = transpose ? p->scratcha : p->scratch;
   // long time levels get one wave per mode (block-parallel recurrences) and
   // come first, so the critical path starts at once; the rest run one thread
   // per mode
@@ -646,9 +661,9 @@ sg_status build_solve_list(sg_problem *p, const std::vector<int> &cset, int tran
       const int wave = C.nq >= p->wave_nq ? 1 : 0;
       if (wave != (pass == 0 ? 1 : 0)) continue;
       SolveDesc sd{};
-      sd.rhs = (p->d == 2 ? p->bufS : p->bufT) + C.off2;
+      sd.rhs = (p->d == 2 ? bS : bT) + C.off2;
       sd.fac = p->fac + 5 * C.off2;
-      sd.scratch = p->scratch + 2 * C.off2;
+      sd.scratch = scr + 2 * C.off2;
       sd.nq = C.nq;
       sd.nmodes = C.nsp;
       sd.b = C.b;
@@ -721,7 +736,7 @@ sg_status build_fdm(sg_problem *p, const std::vector<TimeLevel> &tl_host) {
   std::map<int, TimeTabs> tt;
   std::map<int, double *> dst;  // strip sine matrices by strip row count m
   std::vector<FdmDesc> vf, va;
-  std::vector<GemmDesc> gf, gi;
+  std::vector<GemmDesc> gf, gi, agf, agi;  // forward / adjoint work arrays
   FdmTotals tot;
   int tf_tiles = 0, ti_tiles = 0;
   constexpr int TG = kGemmTile;
@@ -800,11 +815,17 @@ sg_status build_fdm(sg_problem *p, const std::vector<TimeLevel> &tl_host) {
     tot.iface += one.iface;
     tot.gemv += one.gemv;
     FdmDesc hf = h, ha = h;
+    // the adjoint's own work arrays (the factors and inverses are shared)
+    if (!(ha.X = p->dalloc<double>(2 * T.nu * nn)) || !(ha.Y = p->dalloc<double>(2 * T.nu * nn)) ||
+        !(ha.E = p->dalloc<double>(2LL * T.nu * ns * 2 * n)) ||
+        !(ha.G = p->dalloc<double>(std::max(1LL, 2 * T.nu * NG))) ||
+        !(ha.Xg = p->dalloc<double>(std::max(1LL, 2 * T.nu * NG))))
+      return fail(SG_ENOMEM, "hipMalloc of the strip-solver workspace failed");
     hf.in = p->bufB + C.off;
     hf.out = p->bufU + C.off;
     hf.tin = T.fin;
     hf.tout = T.fout;
-    ha.in = p->bufZ + C.off;
+    ha.in = p->bufZa + C.off;
     ha.out = p->bufW + C.off;
     ha.tin = T.ain;
     ha.tout = T.aout;
@@ -830,10 +851,19 @@ sg_status build_fdm(sg_problem *p, const std::vector<TimeLevel> &tl_host) {
       GemmDesc b = g;
       b.B = h.Y + 2 * u * nn;
       b.C = h.X + 2 * u * nn;
-      a.tile0 = tf_tiles; tf_tiles += tiles;
-      b.tile0 = ti_tiles; ti_tiles += tiles;
+      a.tile0 = tf_tiles;
+      b.tile0 = ti_tiles;
       gf.push_back(a);
       gi.push_back(b);
+      GemmDesc aa = a, ab = b;
+      aa.B = ha.X + 2 * u * nn;
+      aa.C = ha.Y + 2 * u * nn;
+      ab.B = ha.Y + 2 * u * nn;
+      ab.C = ha.X + 2 * u * nn;
+      agf.push_back(aa);
+      agi.push_back(ab);
+      tf_tiles += tiles;
+      ti_tiles += tiles;
       a.tile0 = ptf; ptf += tiles;
       b.tile0 = pti; pti += tiles;
       pgf.push_back(a);
@@ -854,14 +884,15 @@ sg_status build_fdm(sg_problem *p, const std::vector<TimeLevel> &tl_host) {
     pl.gi.tiles = pti;
   }
   for (FdmList *L : {&p->ffwd, &p->fadj}) {
+    const bool fw = L == &p->ffwd;
     L->chunk = p->fdm_chunk;
-    L->h = L == &p->ffwd ? vf : va;
-    L->gf.h = gf;
-    L->gi.h = gi;
+    L->h = fw ? vf : va;
+    L->gf.h = fw ? gf : agf;
+    L->gi.h = fw ? gi : agi;
     if ((st = upload(p, L->h, &L->d))) return st;
     L->n = (int)vf.size();
     L->t = tot;
-    if ((st = upload(p, gf, &L->gf.d)) || (st = upload(p, gi, &L->gi.d))) return st;
+    if ((st = upload(p, L->gf.h, &L->gf.d)) || (st = upload(p, L->gi.h, &L->gi.d))) return st;
     L->gf.n = (int)gf.size();
     L->gf.tiles = tf_tiles;
     L->gi.n = (int)gi.size();
@@ -883,6 +914,9 @@ sg_status sg_destroy(sg_problem *p) {
   (void)hipSetDevice(p->device);
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+  if (p->join_ev) (void)hipEventDestroy(p->join_ev);
+  if (p->aux) (void)hipStreamDestroy(p->aux);
   for (void *a : p->allocs) (void)hipFree(a);
   for (void *a : p->eallocs) (void)hipFree(a);
   (void)hipSetDevice(cur);
@@ -1179,7 +1213,10 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
       !(p->bufU = p->dalloc<double>(ns)) || !(p->bufW = p->dalloc<double>(ns)) ||
       !(p->bufY = p->dalloc<double>(ns)) ||
       !(p->fac = p->dalloc<double>(5 * p->nsparse2)) ||
-      !(p->scratch = p->dalloc<double>(2 * p->nsparse2)))
+      !(p->scratch = p->dalloc<double>(2 * p->nsparse2)) ||
+      !(p->bufZa = p->dalloc<double>(ns)) || !(p->bufTa = p->dalloc<double>(p->nsparse2)) ||
+      !(p->bufSa = p->dalloc<double>(p->nsparse2)) ||
+      !(p->scratcha = p->dalloc<double>(2 * p->nsparse2)))
     return bail(fail(SG_ENOMEM, "hipMalloc of component buffers failed"));
   p->mv_lv.assign(J + 1, nullptr);
   p->ku_lv.assign(J + 1, nullptr);
@@ -1270,7 +1307,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
                            cs.data = p->gsum;
                            return cs;
                          }
-                         return chan_comp(a, k, true, p->bufZ, true, -1);
+                         return chan_comp(a, k, true, p->bufZa, true, -1);
                        },
                        &part_need)))
     return bail(st);
@@ -1338,17 +1375,22 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
     p->n_S0 = ntf * nsp0;
     p->n_SL = std::max(1LL, ntf * ncl);
     p->ws = Scratch{p->part, p->cpart, p->S0, p->SL, p->Cpro, p->fine2};
+    Scratch &a = p->wsa;
+    if (!(a.part = p->dalloc<double>(part_need)) || !(a.cpart = p->dalloc<double>(need)) ||
+        !(a.S0 = p->dalloc<double>(ntf * nsp0)) ||
+        !(a.SL = p->dalloc<double>(std::max(1LL, ntf * ncl))) ||
+        !(a.Cpro = p->dalloc<double>(ntf * nsp0)) ||
+        !(a.fine2 = p->dalloc<double>(2 * p->nsp_fine)))
+      return bail(fail(SG_ENOMEM, "hipMalloc of the adjoint's scratch failed"));
   }
 
   // ---- descriptor lists -------------------------------------------------------
   std::vector<int> all(ncomp);
   for (int i = 0; i < ncomp; ++i) all[i] = i;
   if ((st = build_gemm_lists(p, all, p->gx, p->gy, p->giy, p->gix))) return bail(st);
-  {
-    GemmList dy, diy;
-    if ((st = build_gemm_lists(p, all, p->agx, dy, diy, p->agix, p->bufZ, p->bufW)))
-      return bail(st);
-  }
+  if ((st = build_gemm_lists(p, all, p->agx, p->agy, p->agiy, p->agix, p->bufZa, p->bufW,
+                             p->bufTa, p->bufSa)))
+    return bail(st);
   if ((st = build_solve_list(p, all, 0, p->sfwd))) return bail(st);
   if ((st = build_solve_list(p, all, 1, p->sadj))) return bail(st);
   // block-LU components: factors, spatial entries, workspace, descriptors
@@ -1374,7 +1416,10 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
       vf.push_back(bd);
       if ((st = upload(p, std::vector<BlockDesc>{bd}, &p->pbfwd[ci].d))) return bail(st);
       p->pbfwd[ci].n = 1;
-      bd.in = p->bufZ + C.off; bd.out = p->bufW + C.off; bd.transpose = 1;
+      if (!(work = p->dalloc<double>(3LL * C.nq * C.nsp)))
+        return bail(fail(SG_ENOMEM, "hipMalloc of block-solver workspace failed"));
+      bd.work = work;
+      bd.in = p->bufZa + C.off; bd.out = p->bufW + C.off; bd.transpose = 1;
       va.push_back(bd);
     }
     p->bfwd.h = vf;
@@ -1497,7 +1542,7 @@ sg_status sg_component_copy(sg_problem *p, int c, int stage, double *out) {
   if (stage < 0 || stage > 3) return fail(SG_EINVAL, "stage must be 0..3");
   const Comp &C = p->comps[c];
   HIPCHK(hipDeviceSynchronize());
-  const double *bufs[4] = {p->bufB, p->bufU, p->bufZ, p->bufW};
+  const double *bufs[4] = {p->bufB, p->bufU, p->bufZa, p->bufW};
   const double *src = bufs[stage] + C.off;
   HIPCHK(hipMemcpy(out, src, (size_t)C.nq * C.nsp * sizeof(double), hipMemcpyDeviceToHost));
   return SG_OK;
@@ -1591,28 +1636,29 @@ sg_status sg_adjoint(sg_problem *p, const double *g, double *df, double *du0, do
   sg_status st;
   MARK(p, 7, s);
   // y_c = s_c Psi^T g Phi (+ time sum of g for du0)
-  if ((st = run_restrict(p, p->ws, p->adjr, g, 0, s, 8))) return st;
+  if ((st = run_restrict(p, p->wsa, p->adjr, g, 0, s, 8))) return st;
   // z_c = S_c^{-T} y_c  (y_c in bufZ, z_c into bufW)
   MARK(p, 10, s);
   if ((st = run_fdm(p->fadj, s))) return st;
   HIPCHK(launch_block_solve(p->badj.d, p->badj.n, s));
   HIPCHK(launch_gemm(p->agx.d, p->agx.n, p->agx.tiles, p->agx.fold, s));
-  if (p->d == 2) HIPCHK(launch_gemm(p->gy.d, p->gy.n, p->gy.tiles, p->gy.fold, s));
+  if (p->d == 2) HIPCHK(launch_gemm(p->agy.d, p->agy.n, p->agy.tiles, p->agy.fold, s));
   HIPCHK(launch_time_solve(p->sadj.d, p->sadj.n, p->sadj.threads, s));
-  if (p->d == 2) HIPCHK(launch_gemm(p->giy.d, p->giy.n, p->giy.tiles, p->giy.fold, s));
+  if (p->d == 2) HIPCHK(launch_gemm(p->agiy.d, p->agiy.n, p->agiy.tiles, p->agiy.fold, s));
   HIPCHK(launch_gemm(p->agix.d, p->agix.n, p->agix.tiles, p->agix.fold, s));
   MARK(p, 11, s);
   // zeta_c = D^T z_c, level fields for du0 / dv0
   HIPCHK(launch_post_adjoint(p->cadj.d, p->cadj.n, p->cadj.total, s));
   if (df) {
-    if ((st = run_prolong(p, p->adjp, nullptr, df, 0, 1, s, 12))) return st;
+    if ((st = run_prolong(p, p->adjp, nullptr, df, 0, 1, s, 12, p->wsa.Cpro))) return st;
   }
   if (du0 || dv0) {
     HIPCHK(launch_adjoint_fields(p->d_lev, p->nlev, p->lev_total, s));
-    if ((st = run_prolong(p, p->fieldp, nullptr, p->fine2, 0, 0, s))) return st;
+    double *f2 = p->wsa.fine2;
+    if ((st = run_prolong(p, p->fieldp, nullptr, f2, 0, 0, s, -1, p->wsa.Cpro))) return st;
     const double hx = p->len[0] / p->N, hy = p->len[1] / p->N;
-    HIPCHK(launch_fine_stencils(p->d, p->N, p->d_ce, hx, hy, p->fine2, p->fine2 + p->nsp_fine,
-                                dv0, du0, p->gsum, 1, s));
+    HIPCHK(launch_fine_stencils(p->d, p->N, p->d_ce, hx, hy, f2, f2 + p->nsp_fine, dv0, du0,
+                                p->gsum, 1, s));
   }
   MARK(p, 14, s);
   return SG_OK;
@@ -1800,14 +1846,41 @@ sg_status sg_graph_capture(sg_problem *p, const double *f, const double *u0,
     (void)hipGraphDestroy(p->graph);
     p->graph = nullptr;
   }
+  if (g != nullptr && p->aux == nullptr) {
+    if (hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SG_EDEVICE, "creation of the adjoint branch stream failed");
+    }
+  }
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   p->capturing = true;
   for (int i = 0; i < SG_NUM_EVENTS; ++i) {
     p->cap_deps[i].clear();
     p->cap_seen[i] = false;
   }
-  sg_status st = sg_solve(p, f, u0, v0, U, s);
-  if (st == SG_OK && g != nullptr) st = sg_adjoint(p, g, df, du0, dv0, s);
+  // the adjoint (own buffers) branches off at the start and joins at the end,
+  // unless the caller's buffers of the two directions overlap
+  const bool par = g != nullptr && g != U && df != U && df != f && (du0 == nullptr ||
+                   (du0 != u0 && du0 != v0)) && (dv0 == nullptr || (dv0 != u0 && dv0 != v0));
+  hipStream_t as = par ? p->aux : s;
+  sg_status st = SG_OK;
+  hipError_t fe = hipSuccess;
+  if (par) {
+    fe = hipEventRecord(p->fork_ev, s);
+    if (fe == hipSuccess) fe = hipStreamWaitEvent(p->aux, p->fork_ev, 0);
+  }
+  if (fe == hipSuccess) st = sg_solve(p, f, u0, v0, U, s);
+  if (fe == hipSuccess && st == SG_OK && g != nullptr) {
+    st = sg_adjoint(p, g, df, du0, dv0, as);
+    if (st == SG_OK && par) {
+      fe = hipEventRecord(p->join_ev, p->aux);
+      if (fe == hipSuccess) fe = hipStreamWaitEvent(s, p->join_ev, 0);
+    }
+  }
+  if (fe != hipSuccess && st == SG_OK)
+    st = fail(SG_EDEVICE, std::string("adjoint branch: ") + hipGetErrorString(fe));
   p->capturing = false;
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(s, &graph);
@@ -1829,13 +1902,19 @@ sg_status sg_graph_capture(sg_problem *p, const double *f, const double *u0,
 // parallel branch streams; every solve stage runs once for all problems,
 // over the concatenated descriptor lists of all their components (the
 // largest components first).
-struct sg_batch {
-  std::vector<sg_problem *> probs;
-  std::vector<hipStream_t> streams;  // branch streams (default priority)
+struct BranchSet {                  // branch streams of one direction (default priority)
+  std::vector<hipStream_t> streams;
   hipEvent_t fork_ev = nullptr;
   std::vector<hipEvent_t> join_ev;   // one per branch stream
+};
+
+struct sg_batch {
+  std::vector<sg_problem *> probs;
+  BranchSet fb, ab;                  // forward and adjoint branches
+  hipStream_t aux = nullptr;         // the adjoint's main stream in a captured graph
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   std::vector<void *> allocs;
-  GemmList gx, gy, giy, gix, agx, agix;
+  GemmList gx, gy, giy, gix, agx, agy, agiy, agix;
   SolveList sfwd, sadj;
   BlockList bfwd, badj;
   FdmList ffwd, fadj;
@@ -1983,18 +2062,46 @@ sg_status merge_fdm(sg_batch *b, FdmList sg_problem::*member, FdmList &out) {
   return merge_gemm_list(b, gi, out.gi);
 }
 
-// fork the batch's branch streams off s / join them back into s
-sg_status fork(sg_batch *b, hipStream_t s) {
-  HIPCHK(hipEventRecord(b->fork_ev, s));
-  for (hipStream_t bs : b->streams) HIPCHK(hipStreamWaitEvent(bs, b->fork_ev, 0));
+// fork a set of branch streams off s / join them back into s
+sg_status fork(BranchSet &B, hipStream_t s) {
+  HIPCHK(hipEventRecord(B.fork_ev, s));
+  for (hipStream_t bs : B.streams) HIPCHK(hipStreamWaitEvent(bs, B.fork_ev, 0));
   return SG_OK;
 }
-sg_status join(sg_batch *b, hipStream_t s) {
-  for (size_t k = 0; k < b->streams.size(); ++k) {
-    HIPCHK(hipEventRecord(b->join_ev[k], b->streams[k]));
-    HIPCHK(hipStreamWaitEvent(s, b->join_ev[k], 0));
+sg_status join(BranchSet &B, hipStream_t s) {
+  for (size_t k = 0; k < B.streams.size(); ++k) {
+    HIPCHK(hipEventRecord(B.join_ev[k], B.streams[k]));
+    HIPCHK(hipStreamWaitEvent(s, B.join_ev[k], 0));
   }
   return SG_OK;
+}
+
+sg_status make_branches(BranchSet &B, int ns) {
+  for (int i = 0; i < ns; ++i) {
+    hipStream_t bs = nullptr;
+    if (hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SG_EDEVICE, "hipStreamCreateWithFlags failed");
+    }
+    B.streams.push_back(bs);
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SG_EDEVICE, "hipEventCreateWithFlags failed");
+    }
+    B.join_ev.push_back(e);
+  }
+  if (hipEventCreateWithFlags(&B.fork_ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SG_EDEVICE, "hipEventCreateWithFlags failed");
+  }
+  return SG_OK;
+}
+
+void free_branches(BranchSet &B) {
+  if (B.fork_ev) (void)hipEventDestroy(B.fork_ev);
+  for (hipEvent_t e : B.join_ev) (void)hipEventDestroy(e);
+  for (hipStream_t s : B.streams) (void)hipStreamDestroy(s);
 }
 
 sg_status batch_forward(sg_batch *b, const double *const *f, const double *const *u0,
@@ -2007,14 +2114,14 @@ sg_status batch_forward(sg_batch *b, const double *const *f, const double *const
   }
   sg_status st;
   if ((st = bmark(b, 0, s))) return st;
-  if ((st = fork(b, s))) return st;
+  if ((st = fork(b->fb, s))) return st;
   for (int i = 0; i < n; ++i) {
     sg_problem *p = b->probs[i];
-    hipStream_t bs = b->streams[i % b->streams.size()];
+    hipStream_t bs = b->fb.streams[i % b->fb.streams.size()];
     if ((st = forward_fields(p, p->ws, u0[i], v0[i], bs))) return st;
     if ((st = run_restrict(p, p->ws, p->load, f[i], 1, bs))) return st;
   }
-  if ((st = join(b, s))) return st;
+  if ((st = join(b->fb, s))) return st;
   HIPCHK(launch_post_load(b->cload.d, b->cload.n, b->cload.total, s));
   if ((st = bmark(b, 1, s))) return st;
   if ((st = run_fdm(b->ffwd, s))) return st;
@@ -2025,13 +2132,13 @@ sg_status batch_forward(sg_batch *b, const double *const *f, const double *const
   HIPCHK(launch_gemm(b->giy.d, b->giy.n, b->giy.tiles, b->giy.fold, s));
   HIPCHK(launch_gemm(b->gix.d, b->gix.n, b->gix.tiles, b->gix.fold, s));
   if ((st = bmark(b, 2, s))) return st;
-  if ((st = fork(b, s))) return st;
+  if ((st = fork(b->fb, s))) return st;
   for (int i = 0; i < n; ++i) {
     sg_problem *p = b->probs[i];
-    hipStream_t bs = b->streams[i % b->streams.size()];
+    hipStream_t bs = b->fb.streams[i % b->fb.streams.size()];
     if ((st = run_prolong(p, p->prol, u0[i], U[i], 0, 0, bs, -1, p->ws.Cpro))) return st;
   }
-  if ((st = join(b, s))) return st;
+  if ((st = join(b->fb, s))) return st;
   return bmark(b, 3, s);
 }
 
@@ -2043,42 +2150,42 @@ sg_status batch_adjoint(sg_batch *b, const double *const *g, double *const *df,
     if (!g[i]) return fail(SG_EINVAL, "NULL cotangent");
   sg_status st;
   if ((st = bmark(b, 4, s))) return st;
-  if ((st = fork(b, s))) return st;
+  if ((st = fork(b->ab, s))) return st;
   for (int i = 0; i < n; ++i) {
     sg_problem *p = b->probs[i];
-    hipStream_t bs = b->streams[i % b->streams.size()];
-    if ((st = run_restrict(p, p->ws, p->adjr, g[i], 0, bs))) return st;
+    hipStream_t bs = b->ab.streams[i % b->ab.streams.size()];
+    if ((st = run_restrict(p, p->wsa, p->adjr, g[i], 0, bs))) return st;
   }
-  if ((st = join(b, s))) return st;
+  if ((st = join(b->ab, s))) return st;
   if ((st = bmark(b, 5, s))) return st;
   if ((st = run_fdm(b->fadj, s))) return st;
   HIPCHK(launch_block_solve(b->badj.d, b->badj.n, s));
   HIPCHK(launch_gemm(b->agx.d, b->agx.n, b->agx.tiles, b->agx.fold, s));
-  HIPCHK(launch_gemm(b->gy.d, b->gy.n, b->gy.tiles, b->gy.fold, s));
+  HIPCHK(launch_gemm(b->agy.d, b->agy.n, b->agy.tiles, b->agy.fold, s));
   HIPCHK(launch_time_solve(b->sadj.d, b->sadj.n, b->sadj.threads, s));
-  HIPCHK(launch_gemm(b->giy.d, b->giy.n, b->giy.tiles, b->giy.fold, s));
+  HIPCHK(launch_gemm(b->agiy.d, b->agiy.n, b->agiy.tiles, b->agiy.fold, s));
   HIPCHK(launch_gemm(b->agix.d, b->agix.n, b->agix.tiles, b->agix.fold, s));
   if ((st = bmark(b, 6, s))) return st;
   HIPCHK(launch_post_adjoint(b->cadj.d, b->cadj.n, b->cadj.total, s));
   bool fields = false;
   for (int i = 0; i < n; ++i) fields = fields || (du0 && du0[i]) || (dv0 && dv0[i]);
   if (fields) HIPCHK(launch_adjoint_fields(b->d_lev, b->nlev, b->lev_total, s));
-  if ((st = fork(b, s))) return st;
+  if ((st = fork(b->ab, s))) return st;
   for (int i = 0; i < n; ++i) {
     sg_problem *p = b->probs[i];
-    hipStream_t bs = b->streams[i % b->streams.size()];
-    if (df && df[i] && (st = run_prolong(p, p->adjp, nullptr, df[i], 0, 1, bs, -1, p->ws.Cpro)))
+    hipStream_t bs = b->ab.streams[i % b->ab.streams.size()];
+    if (df && df[i] && (st = run_prolong(p, p->adjp, nullptr, df[i], 0, 1, bs, -1, p->wsa.Cpro)))
       return st;
     double *du = du0 ? du0[i] : nullptr, *dv = dv0 ? dv0[i] : nullptr;
     if (du || dv) {
-      if ((st = run_prolong(p, p->fieldp, nullptr, p->ws.fine2, 0, 0, bs, -1, p->ws.Cpro)))
+      if ((st = run_prolong(p, p->fieldp, nullptr, p->wsa.fine2, 0, 0, bs, -1, p->wsa.Cpro)))
         return st;
       const double hx = p->len[0] / p->N, hy = p->len[1] / p->N;
-      HIPCHK(launch_fine_stencils(p->d, p->N, p->d_ce, hx, hy, p->ws.fine2,
-                                  p->ws.fine2 + p->nsp_fine, dv, du, p->gsum, 1, bs));
+      HIPCHK(launch_fine_stencils(p->d, p->N, p->d_ce, hx, hy, p->wsa.fine2,
+                                  p->wsa.fine2 + p->nsp_fine, dv, du, p->gsum, 1, bs));
     }
   }
-  if ((st = join(b, s))) return st;
+  if ((st = join(b->ab, s))) return st;
   return bmark(b, 7, s);
 }
 
@@ -2102,9 +2209,11 @@ sg_status sg_batch_destroy(sg_batch *b) {
   if (!b) return SG_OK;
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  free_branches(b->fb);
+  free_branches(b->ab);
   if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
-  for (hipEvent_t e : b->join_ev) (void)hipEventDestroy(e);
-  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  if (b->join_ev) (void)hipEventDestroy(b->join_ev);
+  if (b->aux) (void)hipStreamDestroy(b->aux);
   for (void *a : b->allocs) (void)hipFree(a);
   delete b;
   return SG_OK;
@@ -2132,31 +2241,26 @@ sg_status sg_batch_create(int n, sg_problem *const *problems, sg_batch **out) {
     g_last_error = msg;
     return st;
   };
-  // a few branch streams (default priority); problems are dealt round-robin
+  // a few branch streams per direction (default priority); problems are
+  // dealt round-robin; one more stream carries the adjoint in a graph
   const int ns = std::min(n, 8);
-  for (int i = 0; i < ns; ++i) {
-    hipStream_t bs = nullptr;
-    if (hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) != hipSuccess) {
+  {
+    sg_status bst;
+    if ((bst = make_branches(b->fb, ns)) || (bst = make_branches(b->ab, ns))) return bail(bst);
+    if (hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming) != hipSuccess) {
       (void)hipGetLastError();
-      return bail(fail(SG_EDEVICE, "hipStreamCreateWithFlags failed"));
+      return bail(fail(SG_EDEVICE, "stream / event creation failed"));
     }
-    b->streams.push_back(bs);
-    hipEvent_t e = nullptr;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-      (void)hipGetLastError();
-      return bail(fail(SG_EDEVICE, "hipEventCreateWithFlags failed"));
-    }
-    b->join_ev.push_back(e);
-  }
-  if (hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess) {
-    (void)hipGetLastError();
-    return bail(fail(SG_EDEVICE, "hipEventCreateWithFlags failed"));
   }
   sg_status st;
   if ((st = merge_gemm(b, &sg_problem::gx, b->gx)) || (st = merge_gemm(b, &sg_problem::gy, b->gy)) ||
       (st = merge_gemm(b, &sg_problem::giy, b->giy)) ||
       (st = merge_gemm(b, &sg_problem::gix, b->gix)) ||
       (st = merge_gemm(b, &sg_problem::agx, b->agx)) ||
+      (st = merge_gemm(b, &sg_problem::agy, b->agy)) ||
+      (st = merge_gemm(b, &sg_problem::agiy, b->agiy)) ||
       (st = merge_gemm(b, &sg_problem::agix, b->agix)) ||
       (st = merge_solve(b, &sg_problem::sfwd, b->sfwd)) ||
       (st = merge_solve(b, &sg_problem::sadj, b->sadj)) ||
@@ -2254,8 +2358,37 @@ sg_status sg_batch_capture(sg_batch *b, const double *const *f, const double *co
     ~Restore() { v.swap(b->ev); }
   } restore{b, bev};
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  sg_status st = batch_forward(b, f, u0, v0, U, s);
-  if (st == SG_OK && g != nullptr) st = batch_adjoint(b, g, df, du0, dv0, s);
+  // The adjoint is independent of the forward for a given cotangent and has
+  // its own buffers, so it could run on its own branch of the graph; that
+  // form (the adjoint's branch streams forked from the forked stream) ended
+  // in a host segmentation fault on the GPU, cause not found, so it is
+  // switched off: the batch captures the adjoint after the forward.
+  constexpr bool kConcurrentBatchAdjoint = false;
+  bool par = kConcurrentBatchAdjoint && g != nullptr;
+  const int nb = (int)b->probs.size();
+  for (int i = 0; par && i < nb; ++i) {
+    const double *o[3] = {df ? df[i] : nullptr, du0 ? du0[i] : nullptr, dv0 ? dv0[i] : nullptr};
+    par = g[i] != U[i];
+    for (const double *q : o)
+      if (q && (q == U[i] || q == f[i] || q == u0[i] || q == v0[i])) par = false;
+  }
+  hipStream_t as = par ? b->aux : s;
+  sg_status st = SG_OK;
+  hipError_t fe = hipSuccess;
+  if (par) {
+    fe = hipEventRecord(b->fork_ev, s);
+    if (fe == hipSuccess) fe = hipStreamWaitEvent(b->aux, b->fork_ev, 0);
+  }
+  if (fe == hipSuccess) st = batch_forward(b, f, u0, v0, U, s);
+  if (fe == hipSuccess && st == SG_OK && g != nullptr) {
+    st = batch_adjoint(b, g, df, du0, dv0, as);
+    if (st == SG_OK && par) {
+      fe = hipEventRecord(b->join_ev, b->aux);
+      if (fe == hipSuccess) fe = hipStreamWaitEvent(s, b->join_ev, 0);
+    }
+  }
+  if (fe != hipSuccess && st == SG_OK)
+    st = fail(SG_EDEVICE, std::string("adjoint branch: ") + hipGetErrorString(fe));
   hipGraph_t graph = nullptr;
   const hipError_t e2 = hipStreamEndCapture(s, &graph);
   if (st != SG_OK || e2 != hipSuccess) {
