@@ -7,8 +7,9 @@ in HBM before timing.
 
 A step is one pass of the whole hot path: forward (load restriction, 17
 component solves, combination) and adjoint (restriction of g, transposed
-solves, df/du0/dv0), replayed from one captured HIP graph (the batched form).
-value = N_sparse DoFs per step / seconds per step.
+solves, df/du0/dv0), replayed from one captured HIP graph (the batched form;
+the adjoint on a branch concurrent with the forward, the cotangent being
+given).  value = N_sparse DoFs per step / seconds per step.
 
 Also reported (config): forward-only DoFs/s (eager and from a forward-only
 graph), the per-component plain loop, fwd+adj/fwd, the per-stage times from
@@ -316,7 +317,7 @@ def c5_batch(args, stream):
         "workload": (f"{n} problems d=2 Omega=(0,1)^2 T=1, L ~ U{{6..10}} (seed 0: "
                      + ", ".join(f"L={L}: {c}" for L, c in sorted(counts.items()))
                      + "), c on 4x4 blocks ~ U[0.5,2], f = 3 space-time Gaussians, u0=v0=0, "
-                       "g~N(0,1); step = forward + adjoint of all problems (one hipGraph)"),
+                       "cotangent = f; step = forward + adjoint of all problems (one hipGraph)"),
         "n_sparse": n_sparse,
         "n_full": n_full,
         "assembly_s": t_asm,
@@ -380,13 +381,15 @@ def main():
     nfull = sv.n_full
 
     # ---- batched: forward + adjoint in one captured graph ------------------
-    # Event-record nodes bracket streaming kernels inside the graph, so a
-    # replay times its own kernels on the launch stream.  The warm-up replays
-    # bracket all four (their durations, and which one dominates); the timed
-    # graph brackets the dominant kernel only, since every event node costs
-    # the replay a few microseconds.  The timed steps run back to back (no
-    # host synchronisation between them); the dominant kernel's duration is
-    # read after the final synchronisation, from the last timed replay.
+    # The step graph runs the adjoint on its own branch, concurrent with the
+    # forward (the cotangent is given).  Kernel durations come from a second
+    # capture with stage events set, which keeps the directions one after
+    # the other so that every streaming kernel runs alone: event-record nodes
+    # bracket the kernels inside that graph on the launch stream.  Its
+    # warm-up replays bracket all four (their durations, and which one
+    # dominates); its timed replays bracket the dominant kernel only (every
+    # event node costs a replay a few microseconds).  Timed replays run back
+    # to back (no host synchronisation between them).
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(15)]
     kern_ev = {"restriction of f": (1, 2), "prolongation into U": (5, 6),
                "restriction of g": (8, 9), "prolongation into df (mass stencil)": (12, 13)}
@@ -404,12 +407,23 @@ def main():
                 sv.capture(f, u0, v0, U, g, df, du0, dv0, stream=stream)
             return False
 
+    def timed_replays(k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for _ in range(k):
+                sv.replay(stream=stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
     graph_events = capture(ev)
     with torch.cuda.stream(stream):
         for _ in range(max(1, args.warmup)):
             sv.replay(stream=stream)
     stream.synchronize()
     dom = "restriction of f"
+    t_step_seq = float("nan")
     if graph_events:
         kern_t = {k: ev[a].elapsed_time(ev[b]) * 1e-3 for k, (a, b) in kern_ev.items()}
         dom = max(kern_t, key=kern_t.get)
@@ -417,17 +431,17 @@ def main():
         graph_events = capture([e if i in (ia, ib) else None for i, e in enumerate(ev)])
         with torch.cuda.stream(stream):
             sv.replay(stream=stream)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+        stream.synchronize()
+        t_step_seq = timed_replays(args.steps)
+        if graph_events:
+            kern_t[dom] = ev[ia].elapsed_time(ev[ib]) * 1e-3
+    # the step graph (no events: the adjoint branch runs concurrently)
+    capture(None)
     with torch.cuda.stream(stream):
-        for _ in range(args.steps):
+        for _ in range(max(1, args.warmup)):
             sv.replay(stream=stream)
     stream.synchronize()
-    torch.cuda.synchronize()
-    t_step = (time.perf_counter() - t0) / args.steps
-    if graph_events:
-        kern_t[dom] = ev[ia].elapsed_time(ev[ib]) * 1e-3
+    t_step = timed_replays(args.steps)
     sv.set_events(ev)
     U_graph, df_graph = U.clone(), df.clone()
 
@@ -529,6 +543,7 @@ def main():
             "n_sparse": ns,
             "n_full": nfull,
             "batched_fwd_adj_dofs_per_s": ns / t_step,
+            "sequential_graph_ms_per_step": t_step_seq * 1e3,
             "eager_fwd_dofs_per_s": ns / stage["fwd"],
             "graph_fwd_dofs_per_s": ns / t_graph_fwd,
             "plain_fwd_dofs_per_s": ns / t_plain,
@@ -540,7 +555,8 @@ def main():
             "energy": energy_out,
             "stage_ms": {k: v * 1e3 for k, v in stage.items()},
             "kernel_ms": {k: v * 1e3 for k, v in kern_t.items()},
-            "kernel_ms_from": (f"{dom}: last timed graph replay; the others: last warm-up replay"
+            "kernel_ms_from": (f"{dom}: last timed replay of the graph with the directions in "
+                               "sequence (kernels alone); the others: its last warm-up replay"
                                if graph_events else "eager runs"),
         },
         "roofline": {

@@ -128,8 +128,9 @@ sg_status sg_adjoint(sg_problem *p, const double *g, double *df, double *du0,
  * must not be capturing already.  sg_graph_launch replays it on a stream.
  * With a given cotangent the adjoint does not depend on the forward; it
  * keeps its own workspace and runs on a parallel branch of the graph, unless
- * an output of one direction is a buffer of the other (then one after the
- * other).
+ * an output of one direction is a buffer of the other, or stage events are
+ * set (sg_set_events: their kernels are timed alone); then one after the
+ * other.
  */
 sg_status sg_graph_capture(sg_problem *p, const double *f, const double *u0,
                            const double *v0, double *U, const double *g,

@@ -1861,9 +1861,11 @@ sg_status sg_graph_capture(sg_problem *p, const double *f, const double *u0,
     p->cap_seen[i] = false;
   }
   // the adjoint (own buffers) branches off at the start and joins at the end,
-  // unless the caller's buffers of the two directions overlap
-  const bool par = g != nullptr && g != U && df != U && df != f && (du0 == nullptr ||
-                   (du0 != u0 && du0 != v0)) && (dv0 == nullptr || (dv0 != u0 && dv0 != v0));
+  // unless the caller's buffers of the two directions overlap, or stage
+  // events are set (they time kernels that run alone)
+  const bool par = g != nullptr && p->ev.empty() && g != U && df != U && df != f &&
+                   (du0 == nullptr || (du0 != u0 && du0 != v0)) &&
+                   (dv0 == nullptr || (dv0 != u0 && dv0 != v0));
   hipStream_t as = par ? p->aux : s;
   sg_status st = SG_OK;
   hipError_t fe = hipSuccess;
