@@ -453,28 +453,114 @@ __device__ __forceinline__ int slab_moves(const double *s_t) {
   return __builtin_amdgcn_readfirstlane((int)__double_as_longlong(s_t[3]));
 }
 
+// Upper levels r = 1..4 of a 16 x 16 tile in the per-wave restriction: level
+// r keeps its nodes(r)^2 values at (jy + 1) pitch(r) + jx + 1 with zero halo
+// entries, as Pad does, but with even pitches, so that the first two entries
+// of every full-weighting row are one aligned 16-byte read.
+__host__ __device__ constexpr int up16_nodes(int r) { return (16 >> r) + 1; }
+__host__ __device__ constexpr int up16_pitch(int r) { return (up16_nodes(r) + 3) & ~1; }
+__host__ __device__ constexpr int up16_off(int r) {
+  return r <= 1 ? 0 : up16_off(r - 1) + up16_pitch(r - 1) * up16_pitch(r - 1);
+}
+struct Up16 {
+  __host__ __device__ static constexpr int nodes(int r) { return up16_nodes(r); }
+  __host__ __device__ static constexpr int pitch(int r) { return up16_pitch(r); }
+  __host__ __device__ static constexpr int off(int r) { return up16_off(r); }
+  static constexpr int total = up16_off(5);
+};
+static_assert(Up16::pitch(1) >= 2 * Up16::nodes(2) + 1 && Up16::pitch(2) >= 2 * Up16::nodes(3) + 1 &&
+                  Up16::pitch(3) >= 2 * Up16::nodes(4) + 1,
+              "full-weighting windows inside the padded level below");
+
+// Full weighting from a padded level with an even pitch P; p = the window's
+// corner (even offset).  Same arithmetic as full_weight<2>.
+__device__ __forceinline__ double full_weight_pairs(const double *p, int P) {
+  double r[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double2 a = *reinterpret_cast<const double2 *>(p + i * P);
+    r[i] = 0.5 * (a.x + p[i * P + 2]) + a.y;
+  }
+  return 0.5 * (r[0] + r[2]) + r[1];
+}
+
+// Value of lane l - 1 within each row of 16 lanes (DPP row_shr:1; lanes 0 and
+// 16, 32, 48 read zero).
+__device__ __forceinline__ double row_shr1(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x111, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x111, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Value of lane `src` (mod 64) through the LDS crossbar (no LDS memory).
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const int a = src << 2;
+  const int lo = __builtin_amdgcn_ds_bpermute(a, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(a, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// Upper nodes of a wave's 16 x 16 tile in the per-wave restriction.  Slot 0
+// of lane (lx, ly) = (l % 8, l / 8) is the level-1 node (lx, ly), which the
+// lane builds in registers from its own 2 x 2 fine block and those of its
+// left and upper neighbours.  Slot 1 of lane u: the level-1 nodes (8, u) for
+// u < 9 and (u - 9, 8) for 9 <= u < 17, then the nodes of levels 2, 3, 4 in
+// row-major order (lanes 17 .. 54), none above.  j is the row-major index in
+// the level, as in the partial-block layout.
+struct Slot16 {
+  int r = 0, j = 0, jx = 0, jy = 0;
+  __device__ void set0(int lane) {
+    r = 1;
+    jx = lane & 7;
+    jy = lane >> 3;
+    j = jy * Up16::nodes(1) + jx;
+  }
+  __device__ void set1(int u) {
+    r = 0;
+    if (u < 9) {
+      r = 1, jx = 8, jy = u;
+    } else if (u < 17) {
+      r = 1, jx = u - 9, jy = 8;
+    } else {
+      int v = u - 17;
+#pragma unroll
+      for (int rr = 2; rr <= 4; ++rr) {
+        const int n = Up16::nodes(rr);
+        if (r == 0 && v < n * n) {
+          r = rr, jx = v % n, jy = v / n;
+        } else if (r == 0) {
+          v -= n * n;
+        }
+      }
+    }
+    j = r ? jy * Up16::nodes(r) + jx : 0;
+  }
+};
+
 // 2-D restriction with one 16 x 16 tile per wave.  Every wave streams the
-// slabs of its own tile through its own LDS region, so the slab loop has no
-// workgroup barrier; the four waves of a workgroup take a 2 x 2 block of
-// tiles, which share halo rows in the caches.  Lane l owns the 2 x 2 block of
-// fine nodes at (2 (l % 8), 2 (l / 8)) and the upper-level nodes u = l and
-// u = l + 64 of the tile's levels 1..4.  Same outputs and partial-block
-// layout as k_restrict<2, 16, ...>.  Three workgroups per CU: the per-lane
-// taps and accumulators of both instances need up to 168 registers.
+// slabs of its own tile, so the slab loop has no workgroup barrier; the four
+// waves of a workgroup take a 2 x 2 block of tiles, which share halo rows in
+// the caches.  Lane l owns the 2 x 2 block of fine nodes at (2 (l % 8),
+// 2 (l / 8)).  Per slab it forms the fine values (through the mass stencil
+// from an LDS copy of the 18 x 18 input window, or straight from memory),
+// then its shares of the four level-1 nodes around the block: the shares
+// from the left neighbour arrive by a DPP row shift, those from the row of
+// blocks above through the LDS crossbar, so level 1 is complete in
+// registers.  Level 1 goes to LDS once; levels 2..4 follow by full weighting
+// there.  Same outputs and partial-block layout as k_restrict<2, 16, ...>.
+// Three workgroups per CU.
 #ifndef SG_WPEW
 #define SG_WPEW 3
 #endif
 template <int STENCIL, int NC0>
 __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs A) {
-  constexpr int TS = 16, LTS = 4, NIN = TS + 2, INSZ = NIN * NIN;
-  constexpr int PF = (INSZ + 63) / 64;  // staged inputs per lane
+  constexpr int TS = 16, LTS = 4, NIN = TS + 2, INSZ = NIN * NIN, NP = 24;
+  // loads in flight per lane: the input window (mass stencil) or the block
+  constexpr int PF = STENCIL ? (INSZ + 63) / 64 : 4;
   using SH = Shape<2, TS, 0>;
-  using PD = Pad<2, TS, 0>;
-  constexpr int PT = PD::total;
-  static_assert(SH::upper <= 128, "two owned upper nodes per lane");
   static_assert(INSZ % 2 == 0, "16-byte aligned rows of the staged input");
-  __shared__ __align__(16) double s_in_w[4][INSZ];
-  __shared__ double s_lv_w[4][PT];
+  __shared__ __align__(16) double s_in_w[4][STENCIL ? NIN * NP : 2];
+  __shared__ __align__(16) double s_lv_w[4][Up16::total];
   constexpr int NCI = 2 * (LTS + 1);  // in-tile channels li = 2 r + k
   __shared__ __align__(16) double s_t_w[4][4 * NCI];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -495,7 +581,7 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
   const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
   const long long blk = (long long)chunk * ntileD + tile;
 
-  for (int i = lane; i < PT; i += 64) s_lv[i] = 0.0;
+  for (int i = lane; i < Up16::total; i += 64) s_lv[i] = 0.0;
 
   // fine nodes (fx, fy) = (2 lx + c, 2 ly + b) of this lane
   const int lx = lane & 7, ly = lane >> 3;
@@ -505,21 +591,27 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
 #pragma unroll
     for (int c = 0; c < 2; ++c)
       fin[b][c] = interior(TS * tx + 2 * lx + c, g.nxf) && interior(TS * ty + 2 * ly + b, g.nxf);
-  Owned<2, TS, 0> own[2];
-  own[0].set(lane);
-  own[1].set(lane + 64);
+  Slot16 own[2];
+  own[0].set0(lane);
+  own[1].set1(lane);
 
-  // staged input e of this lane: slab-relative offset, -1 outside the interior
+  // load e of this lane: slab-relative offset, -1 outside the interior
   int pos[PF];
 #pragma unroll
   for (int e = 0; e < PF; ++e) {
-    const int idx = lane + 64 * e;
-    const int ix = idx % NIN, iy = idx / NIN;
-    const int px = TS * tx - 1 + ix, py = TS * ty - 1 + iy;
-    pos[e] = (idx < INSZ && interior(px, g.nxf) && interior(py, g.nxf))
-                 ? (py - 1) * g.nxf + (px - 1) : -1;
+    if (STENCIL) {
+      const int idx = lane + 64 * e;
+      const int ix = idx % NIN, iy = idx / NIN;
+      const int px = TS * tx - 1 + ix, py = TS * ty - 1 + iy;
+      pos[e] = (idx < INSZ && interior(px, g.nxf) && interior(py, g.nxf))
+                   ? (py - 1) * g.nxf + (px - 1) : -1;
+    } else {
+      const int b = e >> 1, c = e & 1;
+      pos[e] = fin[b][c] ? (TS * ty + 2 * ly + b - 1) * g.nxf + (TS * tx + 2 * lx + c - 1) : -1;
+    }
   }
   double pin[PF];
+  double cur[2][2];  // the lane's block of the current slab (identity stencil)
   // unconditional loads from valid addresses; unwanted values are replaced
   // by zeros when staged (a load in a divergent branch would serialise them)
   auto fetch = [&](int n) {
@@ -553,18 +645,17 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
   int tslot[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) tslot[i] = (own[i].r >= 1 && own[i].r <= R) ? 8 * own[i].r : 0;
-  // slot 0 holds level-1 nodes only; slot 1 any level: the corner of its
-  // full-weighting stencil in the level below, that level's row pitch and
-  // its own entry in the padded LDS layout
-  static_assert(SH::size(1) >= 64, "slot 0 on level 1");
+  // slot 1: the corner of its full-weighting window in the level below, that
+  // level's pitch, and its own entry (levels >= 2); a level-1 node only reads
+  // its entry
   int fw1 = 0, pw1 = 0, st1 = 0;
-#pragma unroll
-  for (int r = 1; r <= LTS; ++r)
-    if (own[1].r == r) {
-      pw1 = PD::pn(r - 1);
-      fw1 = PD::poff(r - 1) + 2 * own[1].jy * pw1 + 2 * own[1].jx;
-      st1 = PD::poff(r) + (own[1].jy + 1) * PD::pn(r) + own[1].jx + 1;
+  if (own[1].r >= 1) {
+    st1 = Up16::off(own[1].r) + (own[1].jy + 1) * Up16::pitch(own[1].r) + own[1].jx + 1;
+    if (own[1].r >= 2) {
+      pw1 = Up16::pitch(own[1].r - 1);
+      fw1 = Up16::off(own[1].r - 1) + 2 * own[1].jy * pw1 + 2 * own[1].jx;
     }
+  }
   SlabTaps<NCI> tp;
   tp.fetch(A.taps, n0, lane);
 
@@ -572,10 +663,18 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
   // its stores: loads and stores share one completion counter, so a store
   // issued just before a wait for loads would hold that wait up
   auto stage_next = [&]() {
+    if (STENCIL) {
 #pragma unroll
-    for (int e = 0; e < PF; ++e) {
-      const int idx = lane + 64 * e;
-      if (idx < INSZ) s_in[idx] = pos[e] >= 0 ? pin[e] : 0.0;
+      for (int e = 0; e < PF; ++e) {
+        const int idx = lane + 64 * e;
+        if (idx < INSZ) s_in[(idx / NIN) * NP + idx % NIN] = pos[e] >= 0 ? pin[e] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < PF; ++e) {
+        cur[e >> 1][e & 1] = pos[e] >= 0 ? pin[e] : 0.0;
+        take(cur[e >> 1][e & 1]);
+      }
     }
     tp.stage(s_t, lane);
   };
@@ -587,8 +686,9 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
       tp.fetch(A.taps, n + 1, lane);
     }
     wave_sync();
-    // (1) fine level: 4 x 4 input window of the lane's 2 x 2 block, one row
-    // at a time (rows i = 0..3 are input rows 2 ly + i)
+    // (1) fine level: the mass stencil over the 4 x 4 input window of the
+    // lane's 2 x 2 block, one row at a time (rows i = 0..3 are input rows
+    // 2 ly + i), or the block itself
     double m[2][2];
     if (STENCIL) {
       // row sums h_c(i) = v(i, c) + v(i, c + 2) + 4 v(i, c + 1), folded into
@@ -596,7 +696,7 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
       double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const double2 *p = reinterpret_cast<const double2 *>(s_in + (2 * ly + i) * NIN + 2 * lx);
+        const double2 *p = reinterpret_cast<const double2 *>(s_in + (2 * ly + i) * NP + 2 * lx);
         const double2 a0 = p[0], a1 = p[1];
         const double h0 = a0.x + a1.x + 4.0 * a0.y, h1 = a0.y + a1.y + 4.0 * a1.x;
         // output row b takes input rows b, b+1, b+2 with weights 1, 4, 1
@@ -616,17 +716,10 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
         for (int c = 0; c < 2; ++c) m[b][c] = fin[b][c] ? sxy * acc[b][c] : 0.0;
     } else {
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const double2 *p = reinterpret_cast<const double2 *>(s_in + (2 * ly + b + 1) * NIN + 2 * lx);
-        const double2 a0 = p[0], a1 = p[1];
-        m[b][0] = a0.y;
-        m[b][1] = a1.x;
-      }
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) m[b][c] = cur[b][c];
     }
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) s_lv[(2 * ly + b + 1) * PD::pn(0) + 2 * lx + c + 1] = m[b][c];
     const TapEntry *tn = A.taps + (long long)n * NCI;
     {  // level-J channel (zero weights when inactive)
       const double2 w01 = *reinterpret_cast<const double2 *>(s_t);
@@ -647,20 +740,48 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
 #pragma unroll
         for (int c = 0; c < 2; ++c) rsum[b][c] += w * m[b][c];
     }
-    // (2) levels r = 1..R: owners restrict from level r-1; the slot values
-    // are accumulated below with the taps of the slot's own level
+    // (2) level 1 in registers.  The block's shares: A to node (lx, ly), Ex
+    // to (lx + 1, ly), Ey to (lx, ly + 1), Exy to (lx + 1, ly + 1) (full
+    // weighting: 1 at the node, 1/2 on its edges, 1/4 on its corners).  X1
+    // and Y1 collect what the lane's row of blocks gives to nodes (lx, ly) and
+    // (lx, ly + 1), adding the left neighbour's shares; lanes lx = 7 also hold
+    // the row's shares of the column-8 nodes (Ex, Exy).
     double val[2] = {0.0, 0.0};
-#pragma unroll
-    for (int r = 1; r <= LTS; ++r) {
-      if (r > R) break;
+    if (R >= 1) {
+      const double exy = 0.25 * m[1][1];
+      const double a1 = m[0][0] + 0.5 * (m[0][1] + m[1][0]) + exy;
+      const double ex = 0.5 * m[0][1] + exy, ey = 0.5 * m[1][0] + exy;
+      const double exl = row_shr1(ex), exyl = row_shr1(exy);  // all lanes take part
+      const double x1 = lx ? a1 + exl : a1;
+      const double y1 = lx ? ey + exyl : ey;
+      const double up = lane_value(y1, lane - 8), upe = lane_value(exy, lane - 8);
+      const double l1 = ly ? x1 + up : x1;     // node (lx, ly)
+      const double l1e = ly ? ex + upe : ex;   // node (8, ly) in lanes lx = 7
+      val[0] = l1;
+      double *v1 = s_lv + Up16::off(1);
+      constexpr int P1 = Up16::pitch(1);
+      v1[(ly + 1) * P1 + lx + 1] = l1;
+      // column 8 from lanes lx = 7, row 8 from lanes ly = 7 (lx < 7): only
+      // the row's own shares reach these nodes
+      if (lx == 7 || ly == 7)
+        v1[lx == 7 ? (ly + 1) * P1 + 9 : 9 * P1 + lx + 1] = lx == 7 ? l1e : y1;
+      if (lane == 63)  // nodes (7, 8) and (8, 8): adjacent, 16-byte aligned
+        *reinterpret_cast<double2 *>(v1 + 9 * P1 + 8) = make_double2(y1, exy);
+      static_assert((9 * Up16::pitch(1) + 8) % 2 == 0, "aligned pair");
+    }
+    // (3) levels 2..R by full weighting in LDS (slot 1 owners); slot-1
+    // level-1 nodes read their value
+    if (R >= 1) {
       wave_sync();
-      if (r == 1) {
-        val[0] = full_weight<2>(s_lv + PD::poff(0), PD::pn(0), own[0].jx, own[0].jy);
-        s_lv[PD::poff(1) + (own[0].jy + 1) * PD::pn(1) + own[0].jx + 1] = val[0];
-      }
-      if (own[1].r == r) {
-        val[1] = full_weight<2>(s_lv + lane_off(fw1), pw1, 0, 0);
-        s_lv[lane_off(st1)] = val[1];
+      if (own[1].r == 1) val[1] = s_lv[lane_off(st1)];
+#pragma unroll
+      for (int r = 2; r <= LTS; ++r) {
+        if (r > R) break;
+        if (r > 2) wave_sync();
+        if (own[1].r == r) {
+          val[1] = full_weight_pairs(s_lv + lane_off(fw1), pw1);
+          s_lv[lane_off(st1)] = val[1];
+        }
       }
     }
     // windows that close their oldest time node at this slab
