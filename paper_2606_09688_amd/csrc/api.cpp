@@ -115,12 +115,11 @@ struct FdmList {         // 2-D variable-speed components solved by time diagona
 };
 
 // Per-call scratch of the streaming passes: partial blocks of the in-tile
-// levels, per-slab coarse partials, the level-A0 arrays and their
-// restrictions, the prolongation's coarse array and two fine space fields.
+// levels, per-slab coarse partials, their restrictions to the levels below
+// the tiles, the prolongation's coarse array and two fine space fields.
 // Every entry is written before it is read within one call.
 struct Scratch {
-  double *part = nullptr, *cpart = nullptr, *S0 = nullptr, *SL = nullptr, *Cpro = nullptr,
-         *fine2 = nullptr;
+  double *part = nullptr, *cpart = nullptr, *SL = nullptr, *Cpro = nullptr, *fine2 = nullptr;
 };
 
 }  // namespace
@@ -179,12 +178,11 @@ struct sg_problem {
   double *fine2 = nullptr;         // [2][nsp_fine]
   double *part = nullptr;          // partial blocks
   double *cpart = nullptr;         // per-slab coarse partials
-  double *S0 = nullptr;            // coarse level-A0 arrays
-  double *SL = nullptr;            // their restrictions to the levels a < A0
+  double *SL = nullptr;            // per-slab restrictions to the levels a < A0
   double *Cpro = nullptr;          // prolongation coarse array
   Scratch ws;                      // the forward's per-call scratch (the buffers above)
   Scratch wsa;                     // the adjoint's
-  long long n_part = 0, n_cpart = 0, n_S0 = 0, n_SL = 0;  // their sizes (doubles)
+  long long n_part = 0, n_cpart = 0, n_C0 = 0, n_SL = 0;  // sizes (doubles); n_C0: Cpro
   // passes
   Pass load, prol, adjr, adjp, fieldr, fieldp;
   int prol_target = 0, prol_ts = 0;  // grid sizing of the prolongations
@@ -478,8 +476,7 @@ sg_status run_restrict(sg_problem *p, const Scratch &ws, const Pass &P, const do
   if (ev_begin >= 0) MARK(p, ev_begin + 1, s);
   if (P.n_red) HIPCHK(launch_reduce(g, P.d_ch, ws.part, P.d_red, P.n_red, P.tot_red, s));
   if (g.A0 > 1 && P.n_crs) {
-    HIPCHK(launch_coarse_assemble(g, ws.cpart, ws.S0, s));
-    HIPCHK(launch_coarse_pyramid(g, ws.S0, ws.SL, s));
+    HIPCHK(launch_coarse_pyramid(g, ws.cpart, ws.SL, s));
     HIPCHK(launch_coarse_restrict(g, P.d_ch, ws.SL, P.d_crs, P.n_crs, P.tot_crs, s));
   }
   return SG_OK;
@@ -1367,17 +1364,16 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
       return bail(fail(SG_ENOTSUP, "level too fine for the coarse-level pyramid"));
     if (ntf * nsp0 >= (1LL << 31))  // the coarse kernels index slabs in 32 bits
       return bail(fail(SG_ENOTSUP, "too many time slabs for the coarse-level arrays"));
-    if (!(p->cpart = p->dalloc<double>(need)) || !(p->S0 = p->dalloc<double>(ntf * nsp0)) ||
+    if (!(p->cpart = p->dalloc<double>(need)) ||
         !(p->SL = p->dalloc<double>(std::max(1LL, ntf * ncl))) ||
         !(p->Cpro = p->dalloc<double>(ntf * nsp0)))
       return bail(fail(SG_ENOMEM, "hipMalloc of coarse buffers failed"));
     p->n_cpart = need;
-    p->n_S0 = ntf * nsp0;
+    p->n_C0 = ntf * nsp0;
     p->n_SL = std::max(1LL, ntf * ncl);
-    p->ws = Scratch{p->part, p->cpart, p->S0, p->SL, p->Cpro, p->fine2};
+    p->ws = Scratch{p->part, p->cpart, p->SL, p->Cpro, p->fine2};
     Scratch &a = p->wsa;
     if (!(a.part = p->dalloc<double>(part_need)) || !(a.cpart = p->dalloc<double>(need)) ||
-        !(a.S0 = p->dalloc<double>(ntf * nsp0)) ||
         !(a.SL = p->dalloc<double>(std::max(1LL, ntf * ncl))) ||
         !(a.Cpro = p->dalloc<double>(ntf * nsp0)) ||
         !(a.fine2 = p->dalloc<double>(2 * p->nsp_fine)))
@@ -1585,10 +1581,9 @@ sg_status sg_solve_static(sg_problem *p, const double *f, const double *u0, cons
                           double *U, hipStream_t s) {
   if (!p) return fail(SG_EINVAL, "NULL handle");
   // carve the scratch out of the device's static array, 256-byte aligned
-  const long long sizes[6] = {p->n_part, p->n_cpart, p->n_S0, p->n_SL, p->n_S0,
-                              2 * p->nsp_fine};
-  long long off[6], need = 0;
-  for (int i = 0; i < 6; ++i) {
+  const long long sizes[5] = {p->n_part, p->n_cpart, p->n_SL, p->n_C0, 2 * p->nsp_fine};
+  long long off[5], need = 0;
+  for (int i = 0; i < 5; ++i) {
     off[i] = need;
     need += (std::max(1LL, sizes[i]) + 31) / 32 * 32;
   }
@@ -1602,8 +1597,8 @@ sg_status sg_solve_static(sg_problem *p, const double *f, const double *u0, cons
   double *base = nullptr;
   HIPCHK(static_scratch(&base));
   Scratch ws;
-  double **dst[6] = {&ws.part, &ws.cpart, &ws.S0, &ws.SL, &ws.Cpro, &ws.fine2};
-  for (int i = 0; i < 6; ++i) *dst[i] = base + off[i];
+  double **dst[5] = {&ws.part, &ws.cpart, &ws.SL, &ws.Cpro, &ws.fine2};
+  for (int i = 0; i < 5; ++i) *dst[i] = base + off[i];
   // the array keeps the previous call's contents (any problem): start the
   // partial blocks from zero, as freshly allocated memory would be
   HIPCHK(launch_fill(ws.part, std::max(1LL, p->n_part), 0.0, s));

@@ -863,22 +863,21 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
 }
 
 // Index of the last of n items (ascending .start) whose start is <= gid.
-// Every lane of the wave calls it, before any early return: one ballot over
-// the starts finds the item of the wave's first thread, then a lane steps on
-// only across the rare item boundaries inside its wave (a chain of dependent
-// loads from the first item would serialise the latency of each).
+// A binary search on the wave's first thread (wave-uniform: scalar loads,
+// whose upper levels every wave shares in the scalar cache) finds the item
+// there; a lane then steps on only across the rare item boundaries inside
+// its wave.  Batches of many problems hold thousands of items, so a scan
+// over the starts would cost each wave far more than its own work.
 template <class T>
 __device__ __forceinline__ int find_item(const T *items, int n, long long gid) {
   const long long gw = (long long)blockIdx.x * blockDim.x +
                        __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u));
-  int it = 0;
-  for (int base = 0; base < n; base += 64) {
-    const int i = base + (int)(threadIdx.x & 63);
-    const unsigned long long le = __ballot(i < n && items[i].start <= gw);
-    it += __popcll(le);
-    if (le != ~0ull) break;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].start <= gw) lo = mid; else hi = mid - 1;
   }
-  it = it > 0 ? it - 1 : 0;
+  int it = lo;
   while (it + 1 < n && items[it + 1].start <= gid) ++it;
   return it;
 }
@@ -944,33 +943,6 @@ __global__ void k_reduce(const Geometry g, const Channel *__restrict__ ch,
   C.data[loc] = C.scale * acc;
 }
 
-// S0[n][K0] at the interior nodes of level A0 from the per-slab tile partials
-// (each level-A0 node is shared by the tiles t = P-1 and t = P per axis).
-template <int D>
-__global__ void k_coarse_assemble(const Geometry g, const double *__restrict__ cp,
-                                  double *__restrict__ S0) {
-  const int na = (1 << g.A0) - 1;
-  const int nsp = (D == 2) ? na * na : na;
-  const long long gid = gid64();
-  if (gid >= (long long)nsp * g.ntf) return;
-  const int n = (int)gid / nsp;  // level-A0 slabs hold fewer than 2^31 values
-  const int K = (int)gid - n * nsp;
-  const int Py = (D == 2) ? K / na + 1 : 0;
-  const int Px = (D == 2) ? K - (Py - 1) * na + 1 : K + 1;
-  constexpr int SZ = (D == 2) ? 4 : 2;
-  double acc = 0.0;
-  for (int ty = (D == 2 ? Py - 1 : 0); ty <= (D == 2 ? Py : 0); ++ty) {
-    if (ty < 0 || ty >= g.ntile) continue;
-    for (int tx = Px - 1; tx <= Px; ++tx) {
-      if (tx < 0 || tx >= g.ntile) continue;
-      const int tile = (D == 2) ? ty * g.ntile + tx : tx;
-      const int j = (D == 2) ? (Py - ty) * 2 + (Px - tx) : (Px - tx);
-      acc += cp[((long long)tile * g.ntf + n) * SZ + j];
-    }
-  }
-  S0[gid] = acc;
-}
-
 // first index n with q0[n] >= v (q0 nondecreasing)
 __device__ __forceinline__ int lower_bound_q(const int *q0, int n, int v) {
   int lo = 0, hi = n;
@@ -991,19 +963,37 @@ __host__ __device__ inline long long coarse_off(int d, int a) {
   return o;
 }
 
-// One block per slab: full weighting of S0[n] (level A0) down to level 1.
+// One block per slab: the level-A0 values of slab n from the per-slab tile
+// partials of the restriction (a level-A0 node is shared by the tiles t = P-1
+// and t = P per axis, whose top in-tile level has two nodes per axis), then
+// full weighting down to level 1.
 template <int D>
 __global__ void __launch_bounds__(256) k_coarse_pyramid(const Geometry g,
-                                                        const double *__restrict__ S0,
+                                                        const double *__restrict__ cp,
                                                         double *__restrict__ SL) {
   constexpr int MAXN = kCoarseMax;  // doubles per ping-pong level (checked by the plan)
   __shared__ double s_a[MAXN], s_b[MAXN];
   const int n = blockIdx.x;
   const int A0 = g.A0;
   const int n0a = (1 << A0) - 1;
-  const long long nsp0 = (D == 2) ? (long long)n0a * n0a : n0a;
+  const int nsp0 = (D == 2) ? n0a * n0a : n0a;
   const long long tot = coarse_off(D, A0);
-  for (int i = threadIdx.x; i < nsp0; i += blockDim.x) s_a[i] = S0[(long long)n * nsp0 + i];
+  constexpr int SZ = (D == 2) ? 4 : 2;  // top in-tile level of a tile
+  for (int K = threadIdx.x; K < nsp0; K += blockDim.x) {
+    const int Py = (D == 2) ? K / n0a + 1 : 0;
+    const int Px = (D == 2) ? K - (Py - 1) * n0a + 1 : K + 1;
+    double acc = 0.0;
+    for (int ty = (D == 2 ? Py - 1 : 0); ty <= (D == 2 ? Py : 0); ++ty) {
+      if (ty < 0 || ty >= g.ntile) continue;
+      for (int tx = Px - 1; tx <= Px; ++tx) {
+        if (tx < 0 || tx >= g.ntile) continue;
+        const int tile = (D == 2) ? ty * g.ntile + tx : tx;
+        const int j = (D == 2) ? (Py - ty) * 2 + (Px - tx) : (Px - tx);
+        acc += cp[((long long)tile * g.ntf + n) * SZ + j];
+      }
+    }
+    s_a[K] = acc;
+  }
   __syncthreads();
   double *cur = s_a, *nxt = s_b;
   for (int a = A0 - 1; a >= 1; --a) {
@@ -1062,55 +1052,66 @@ __global__ void k_coarse_restrict(const Geometry g, const Channel *__restrict__ 
 // ---------------------------------------------------------- prolongation ---
 
 // C[n][K0] at the interior level-A0 nodes: sum over the channels of levels
-// a < A0 of their time-evaluated, linearly interpolated values.
+// a < A0 of their time-evaluated values, interpolated linearly.  One block
+// per slab builds the nodal values level by level, coarse to fine (the P1
+// interpolation from level a to level A0 is the composition of the
+// interpolations between consecutive levels): level a takes its channels'
+// values at slab n plus the interpolation of level a-1; level A0 only the
+// interpolation.
 template <int D>
-__global__ void k_prolong_coarse(const Geometry g, const Channel *__restrict__ ch,
-                                 double *__restrict__ Cout) {
-  const int n0a = (1 << g.A0) - 1;
-  const int nsp0 = (D == 2) ? n0a * n0a : n0a;
-  const long long gid = gid64();
-  if (gid >= (long long)nsp0 * g.ntf) return;
-  const int n = (int)gid / nsp0;  // level-A0 slabs hold fewer than 2^31 values
-  const int K0 = (int)gid - n * nsp0;
-  const int P0y = (D == 2) ? K0 / n0a + 1 : 0;
-  const int P0x = (D == 2) ? K0 - (P0y - 1) * n0a + 1 : K0 + 1;
-  double acc = 0.0;
-  for (int a = 1; a < g.A0; ++a) {
-    const int sh = g.A0 - a, f = 1 << sh;
-    const int na = (1 << a) - 1;
-    const int Lx = P0x >> sh, rx = P0x & (f - 1);
-    const double fx = (double)rx / f;
-    const int Ly = (D == 2) ? P0y >> sh : 0, ry = (D == 2) ? P0y & (f - 1) : 0;
-    const double fy = (double)ry / f;
-    for (int k = 0; k < 2; ++k) {
-      const Channel &C = ch[(a - 1) * 2 + k];
-      if (!C.active) continue;
-      const int q0n = C.q0[n];
-      const long long nsp = (D == 2) ? (long long)na * na : na;
+__global__ void __launch_bounds__(256) k_prolong_coarse(const Geometry g,
+                                                        const Channel *__restrict__ ch,
+                                                        double *__restrict__ Cout) {
+  // level A0-1 has fewer than a quarter (a half in 1-D) of the level-A0
+  // nodes, which the plan keeps within kCoarseMax
+  constexpr int MAXN = kCoarseMax / (D == 2 ? 4 : 2);
+  __shared__ double s_a[MAXN], s_b[MAXN];
+  const int n = blockIdx.x;
+  const int A0 = g.A0;
+  double *cur = s_a, *nxt = s_b;
+  for (int a = 1; a <= A0; ++a) {
+    const int na = (1 << a) - 1, nc = (1 << (a - 1)) - 1;
+    const int nspa = (D == 2) ? na * na : na;
+    // value of level a-1 at its node (X, Y); zero on the boundary
+    auto at = [&](int X, int Y) -> double {
+      if (X < 1 || X > nc || (D == 2 && (Y < 1 || Y > nc))) return 0.0;
+      return cur[(D == 2 ? (Y - 1) * nc : 0) + X - 1];
+    };
+    for (int i = threadIdx.x; i < nspa; i += blockDim.x) {
+      const int Px = i % na + 1, Py = (D == 2) ? i / na + 1 : 0;
       double v = 0.0;
-      for (int kk = 0; kk < 3; ++kk) {
-        const double w = C.w[3 * n + kk];
-        if (w == 0.0) continue;
-        const double *Y = C.data + (long long)(q0n + kk) * nsp;
-        double s = 0.0;
-        for (int oy = 0; oy < (D == 2 ? 2 : 1); ++oy) {
-          const int yy = Ly + oy;
-          const double wy = (D == 2) ? (oy == 0 ? 1.0 - fy : fy) : 1.0;
-          if (wy == 0.0) continue;
-          if (D == 2 && !interior(yy, na)) continue;
-          for (int ox = 0; ox < 2; ++ox) {
-            const int xx = Lx + ox;
-            const double wx = ox == 0 ? 1.0 - fx : fx;
-            if (wx == 0.0 || !interior(xx, na)) continue;
-            s += wy * wx * Y[(D == 2 ? (long long)(yy - 1) * na : 0) + (xx - 1)];
-          }
+      if (a > 1) {
+        const int xl = Px >> 1, xh = (Px + 1) >> 1;  // equal at even nodes
+        if (D == 2) {
+          const int yl = Py >> 1, yh = (Py + 1) >> 1;
+          v = 0.25 * (at(xl, yl) + at(xh, yl) + at(xl, yh) + at(xh, yh));
+        } else {
+          v = 0.5 * (at(xl, 0) + at(xh, 0));
         }
-        v += w * s;
       }
-      acc += C.scale * v;
+      if (a == A0) {
+        Cout[(long long)n * nspa + i] = v;
+        continue;
+      }
+      for (int k = 0; k < 2; ++k) {
+        const Channel &C = ch[(a - 1) * 2 + k];
+        if (!C.active) continue;
+        const int q0n = C.q0[n];
+        double sv = 0.0;
+        for (int kk = 0; kk < 3; ++kk) {
+          const double w = C.w[3 * n + kk];
+          if (w == 0.0) continue;  // (a window past the last time node)
+          sv += w * C.data[(long long)(q0n + kk) * nspa + i];
+        }
+        v += C.scale * sv;
+      }
+      nxt[i] = v;
     }
+    __syncthreads();
+    double *t = cur;
+    cur = nxt;
+    nxt = t;
   }
-  Cout[gid] = acc;
 }
 
 // NC0: number of finest-level channels (2 only for the u0/v0 field pass)
@@ -2945,24 +2946,13 @@ hipError_t launch_reduce(const Geometry &g, const Channel *ch, const double *par
   return hipGetLastError();
 }
 
-hipError_t launch_coarse_assemble(const Geometry &g, const double *cp, double *S0,
-                                  hipStream_t s) {
-  const long long na = (1 << g.A0) - 1;
-  const long long n = (g.d == 2 ? na * na : na) * g.ntf;
-  if (g.d == 2)
-    hipLaunchKernelGGL(k_coarse_assemble<2>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, cp, S0);
-  else
-    hipLaunchKernelGGL(k_coarse_assemble<1>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, cp, S0);
-  return hipGetLastError();
-}
-
-hipError_t launch_coarse_pyramid(const Geometry &g, const double *S0, double *SL,
+hipError_t launch_coarse_pyramid(const Geometry &g, const double *cp, double *SL,
                                  hipStream_t s) {
   if (g.A0 <= 1) return hipSuccess;
   if (g.d == 2)
-    hipLaunchKernelGGL(k_coarse_pyramid<2>, dim3(g.ntf), dim3(256), 0, s, g, S0, SL);
+    hipLaunchKernelGGL(k_coarse_pyramid<2>, dim3(g.ntf), dim3(256), 0, s, g, cp, SL);
   else
-    hipLaunchKernelGGL(k_coarse_pyramid<1>, dim3(g.ntf), dim3(256), 0, s, g, S0, SL);
+    hipLaunchKernelGGL(k_coarse_pyramid<1>, dim3(g.ntf), dim3(256), 0, s, g, cp, SL);
   return hipGetLastError();
 }
 
@@ -2981,12 +2971,11 @@ hipError_t launch_coarse_restrict(const Geometry &g, const Channel *ch, const do
 
 hipError_t launch_prolong_coarse(const Geometry &g, const Channel *ch, double *C, int,
                                  hipStream_t s) {
-  const long long na = (1 << g.A0) - 1;
-  const long long n = (g.d == 2 ? na * na : na) * g.ntf;
+  // one block per slab
   if (g.d == 2)
-    hipLaunchKernelGGL(k_prolong_coarse<2>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, ch, C);
+    hipLaunchKernelGGL(k_prolong_coarse<2>, dim3(g.ntf), dim3(256), 0, s, g, ch, C);
   else
-    hipLaunchKernelGGL(k_prolong_coarse<1>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, ch, C);
+    hipLaunchKernelGGL(k_prolong_coarse<1>, dim3(g.ntf), dim3(256), 0, s, g, ch, C);
   return hipGetLastError();
 }
 

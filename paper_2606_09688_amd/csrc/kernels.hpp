@@ -168,13 +168,12 @@ hipError_t launch_restrict(const RestrictArgs &a, hipStream_t s);
 hipError_t launch_reduce(const Geometry &g, const Channel *ch, const double *part,
                          const WorkItem *items, int nitems, long long total,
                          hipStream_t s);
-hipError_t launch_coarse_assemble(const Geometry &g, const double *coarse_part,
-                                  double *S0, hipStream_t s);
 // largest level-A0 array (nodes) the coarse pyramid kernel holds in LDS
 constexpr int kCoarseMax = 4096;
-// per-slab restriction of the level-A0 array S0[n] to the levels a < A0:
+// per-slab level-A0 values assembled from the restriction's per-slab tile
+// partials (coarse_part), restricted to the levels a < A0:
 // SL[n][off_a + K], off_a = sum_{a' < a} (2^a' - 1)^d
-hipError_t launch_coarse_pyramid(const Geometry &g, const double *S0, double *SL,
+hipError_t launch_coarse_pyramid(const Geometry &g, const double *coarse_part, double *SL,
                                  hipStream_t s);
 hipError_t launch_coarse_restrict(const Geometry &g, const Channel *ch,
                                   const double *SL, const WorkItem *items,
