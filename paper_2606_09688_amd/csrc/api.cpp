@@ -2288,7 +2288,8 @@ sg_status sg_batch_create(int n, sg_problem *const *problems, sg_batch **out) {
   long long tb = 0;
   for (const FdmDesc &d : b->ffwd.h) {
     const long long NG = (long long)d.ni * d.n;
-    tb += 16LL * d.nu * NG * NG + 2LL * 48 * d.nu * d.ns * d.n * d.m;
+    // two tridiagonal sweeps per solve, each reading two factor planes
+    tb += 16LL * d.nu * NG * NG + 2LL * 32 * d.nu * d.ns * d.n * d.m;
   }
   for (const GemmList *L : {&b->gx, &b->gy, &b->giy, &b->gix})
     for (const GemmDesc &g : L->h)

@@ -138,10 +138,15 @@ __device__ __forceinline__ void dif_row(const FdmDesc &D, int r, cx lam, int x, 
   }
 }
 
-// factor entry of (u, k, x, l): 1/d'_x (top-down LU pivot), l_x (its
-// multiplier), 1/d''_x (bottom-up pivot)
-__device__ __forceinline__ double *fac_at(const FdmDesc &D, int u, int k, int x, int l) {
-  return D.fac + ((((size_t)u * D.ns + k) * D.n + x) * D.m + l) * 6;
+// factor planes of T_{k,l}: kInvD 1/d'_x (top-down LU pivot), kEll l_x (its
+// multiplier), kInvB 1/d''_x (bottom-up pivot); each plane complex
+// [u][k][x][l], so a sweep over x reads only the plane it needs, the modes l
+// of a wave side by side
+enum FacPlane { kInvD = 0, kEll = 1, kInvB = 2 };
+__device__ __forceinline__ double *fac_at(const FdmDesc &D, int plane, int u, int k, int x,
+                                          int l) {
+  const size_t per = (size_t)D.nu * D.ns * D.n * D.m;
+  return D.fac + 2 * (plane * per + (((size_t)u * D.ns + k) * D.n + x) * D.m + l);
 }
 
 // ---------------------------------------------------------------- solve ----
@@ -244,8 +249,7 @@ __global__ void __launch_bounds__(64) k_fdm_tri(const FdmDesc *__restrict__ ds, 
     for (int c = 0; c < FCH; ++c) {
       const int x = min(x0 + c, n - 1);
       r[c] = rhs(x);
-      const double *f = fac_at(D, u, k, x, l);
-      el[c] = {f[2], f[3]};
+      el[c] = cld(fac_at(D, kEll, u, k, x, l));
     }
 #pragma unroll
     for (int c = 0; c < FCH; ++c) {
@@ -263,8 +267,7 @@ __global__ void __launch_bounds__(64) k_fdm_tri(const FdmDesc *__restrict__ ds, 
     for (int c = 0; c < FCH; ++c) {
       const int x = max(x1 - c, 0);
       w[c] = cld(Wr + 2 * x);
-      const double *f = fac_at(D, u, k, x, l);
-      iv[c] = {f[0], f[1]};
+      iv[c] = cld(fac_at(D, kInvD, u, k, x, l));
       cx dg;
       tri_row(D, k, l, lam, x, dg, of[c]);
       if (correction) yo[c] = cld(Yr + 2 * x);
@@ -361,26 +364,24 @@ __global__ void k_fdm_factor(const FdmDesc D) {
   cx dg, of, ofp;
   tri_row(D, k, l, lam, 0, dg, of);
   cx inv = crcp(dg);
-  double *f = fac_at(D, u, k, 0, l);
-  f[0] = inv.r; f[1] = inv.i; f[2] = 0.0; f[3] = 0.0;
+  cst(fac_at(D, kInvD, u, k, 0, l), inv);
+  cst(fac_at(D, kEll, u, k, 0, l), cx{0.0, 0.0});
   for (int x = 1; x < D.n; ++x) {
     ofp = of;                      // coupling (x-1, x)
     tri_row(D, k, l, lam, x, dg, of);
     const cx ell = cmul(ofp, inv);  // l_x = of_{x-1} / d'_{x-1}
     inv = crcp(csub(dg, cmul(ell, ofp)));
-    f = fac_at(D, u, k, x, l);
-    f[0] = inv.r; f[1] = inv.i; f[2] = ell.r; f[3] = ell.i;
+    cst(fac_at(D, kInvD, u, k, x, l), inv);
+    cst(fac_at(D, kEll, u, k, x, l), ell);
   }
   // bottom-up: d''_{n-1} = dg_{n-1}, d''_x = dg_x - of_x^2 / d''_{x+1}
   tri_row(D, k, l, lam, D.n - 1, dg, of);
   cx invb = crcp(dg);
-  f = fac_at(D, u, k, D.n - 1, l);
-  f[4] = invb.r; f[5] = invb.i;
+  cst(fac_at(D, kInvB, u, k, D.n - 1, l), invb);
   for (int x = D.n - 2; x >= 0; --x) {
     tri_row(D, k, l, lam, x, dg, of);
     invb = crcp(csub(dg, cmul(cmul(of, of), invb)));
-    f = fac_at(D, u, k, x, l);
-    f[4] = invb.r; f[5] = invb.i;
+    cst(fac_at(D, kInvB, u, k, x, l), invb);
   }
 }
 
@@ -431,29 +432,21 @@ __global__ void k_fdm_green(const FdmDesc D, int ngrp, double *P0, double *P1) {
       tri_row(D, k, l, lam, j - 1, d2, ofm);
     }
     cx piv = dg;
-    if (j > 0) {
-      const double *f = fac_at(D, u, k, j - 1, l);
-      piv = csub(piv, cmul(cmul(ofm, ofm), cx{f[0], f[1]}));
-    }
-    if (j + 1 < n) {
-      const double *f = fac_at(D, u, k, j + 1, l);
-      piv = csub(piv, cmul(cmul(of, of), cx{f[4], f[5]}));
-    }
+    if (j > 0) piv = csub(piv, cmul(cmul(ofm, ofm), cld(fac_at(D, kInvD, u, k, j - 1, l))));
+    if (j + 1 < n) piv = csub(piv, cmul(cmul(of, of), cld(fac_at(D, kInvB, u, k, j + 1, l))));
     const cx xj = crcp(piv);
     acc(j, xj);
     cx v = xj;
     for (int i = j - 1; i >= 0; --i) {  // above the pivot row
       cx d2, oi;
       tri_row(D, k, l, lam, i, d2, oi);
-      const double *f = fac_at(D, u, k, i, l);
-      v = cmul(cscl(cmul(oi, cx{f[0], f[1]}), -1.0), v);
+      v = cmul(cscl(cmul(oi, cld(fac_at(D, kInvD, u, k, i, l))), -1.0), v);
       acc(i, v);
     }
     v = xj;
     cx oprev = of;  // coupling (i-1, i) for i = j+1
     for (int i = j + 1; i < n; ++i) {  // below the pivot row
-      const double *f = fac_at(D, u, k, i, l);
-      v = cmul(cscl(cmul(oprev, cx{f[4], f[5]}), -1.0), v);
+      v = cmul(cscl(cmul(oprev, cld(fac_at(D, kInvB, u, k, i, l))), -1.0), v);
       acc(i, v);
       cx d2;
       tri_row(D, k, l, lam, i, d2, oprev);

@@ -1433,8 +1433,10 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
 }
 
 // 2-D prolongation (no stencil) with one 16 x 16 tile per wave: the
-// counterpart of k_restrict_w, four tiles per workgroup and no workgroup
-// barrier in the slab loop.  Per slab: (A) the owners of the tile's
+// counterpart of k_restrict_w, four tiles side by side per workgroup (rows
+// of 64 contiguous outputs per workgroup: fewer cache lines shared with
+// other workgroups than a 2 x 2 block) and no workgroup barrier in the slab
+// loop.  Per slab: (A) the owners of the tile's
 // upper-level nodes evaluate their channels in time (register windows of
 // coefficients; the top level adds the levels below the tile from
 // A.coarse), (B) top-down interpolation through the levels, (C) the fine
@@ -1463,10 +1465,10 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
   double *s_t = s_t_w[wave];
 
   const Geometry g = A.g;
-  const int nt = g.ntile, ng = (nt + 1) >> 1;
+  const int nt = g.ntile, ngx = (nt + 3) >> 2;
   int grp, chunk;
-  stream_block(ng * ng, g.nchunk, grp, chunk);
-  const int tx = 2 * (grp % ng) + (wave & 1), ty = 2 * (grp / ng) + (wave >> 1);
+  stream_block(ngx * nt, g.nchunk, grp, chunk);
+  const int tx = 4 * (grp % ngx) + wave, ty = grp / ngx;
   if (tx >= nt || ty >= nt) return;  // no workgroup barrier below
   const int n0 = chunk * g.chunk, n1 = min(n0 + g.chunk, g.ntf);
   const long long nsp = (long long)g.nxf * g.nxf;
@@ -1693,10 +1695,10 @@ __global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A
   double *s_t = s_f;  // the slab taps reuse the set-up region
 
   const Geometry g = A.g;
-  const int nt = g.ntile, ng = (nt + 1) >> 1;
+  const int nt = g.ntile, ngx = (nt + 3) >> 2;
   int grp, chunk;
-  stream_block(ng * ng, g.nchunk, grp, chunk);
-  const int tx = 2 * (grp % ng) + (wave & 1), ty = 2 * (grp / ng) + (wave >> 1);
+  stream_block(ngx * nt, g.nchunk, grp, chunk);
+  const int tx = 4 * (grp % ngx) + wave, ty = grp / ngx;
   if (tx >= nt || ty >= nt) return;  // no workgroup barrier below
   const int n0 = chunk * g.chunk, n1 = min(n0 + g.chunk, g.ntf);
   const long long nsp = (long long)g.nxf * g.nxf;
@@ -2987,8 +2989,8 @@ hipError_t launch_prolong(const ProlongArgs &a, hipStream_t s) {
   hipLaunchKernelGGL((k_prolong<D, TS, TB, kNT, MO, NC>), grid, dim3(kNT), 0, s, a)
   if (a.g.d == 2 && a.g.TS == 16) {
     if (two || a.taps == nullptr) return hipErrorInvalidValue;  // one finest channel only
-    const int ng = (a.g.ntile + 1) / 2;
-    dim3 gridw(ng * ng, a.g.nchunk);
+    const int ngx = (a.g.ntile + 3) / 4;  // four tiles side by side per workgroup
+    dim3 gridw(ngx * a.g.ntile, a.g.nchunk);
     if (a.stencil)
       hipLaunchKernelGGL(k_prolong_wm, gridw, dim3(256), 0, s, a);
     else

@@ -221,7 +221,7 @@ struct FdmDesc {
   double *G;             // complex [nu][ni][n]: interface right-hand sides
   double *Xg;            // complex [nu][ni][n]: interface solutions
   double *Sinv;          // complex [nu][ni n][ni n]: inverse interface Schur complements
-  double *fac;           // [nu][ns][n][m][4]: 1/d'_x and the multiplier l_x of T_{k,l} = L D L^T-like LU
+  double *fac;           // 3 complex planes [nu][ns][n][m]: 1/d'_x, the multiplier l_x (top-down LU of T_{k,l}), 1/d''_x (bottom-up)
   const double *xt;      // [ns][4][n]: K_x^k diagonal, coupling (x, x+1); M_x^k diagonal, coupling
   const double *ym;      // [3][m]: mu_l, nu_l, s_l(first row) of the strip sine transform
   int nq, n, nu, ns, m, ni;
