@@ -21,6 +21,7 @@ candidate value of one knob at a time, starting from the library defaults
 (coordinate descent), keeps the fastest, and records the chosen values with
 their times.  The cache is a JSON file
     {device key: {class key: {"knobs": {...}, "ms": t, "default_ms": t0}}}
+with the device key "<gfx architecture>|<compute units>cu".
 The committed cache (tuning/tiles.json) holds the results of a run on an
 MI355X; SG_TUNING_CACHE names another file to read and write.
 
@@ -56,10 +57,12 @@ def cache_path():
 
 
 def device_key():
+    """Architecture and compute-unit count (the marketing name is not a
+    stable key: it is empty where the driver's name table is missing)."""
     import torch
     p = torch.cuda.get_device_properties(0)
     arch = getattr(p, "gcnArchName", "") or ""
-    return f"{p.name}|{arch.split(':')[0]}|{p.multi_processor_count}cu"
+    return f"{arch.split(':')[0]}|{p.multi_processor_count}cu"
 
 
 def class_key(d, L, const_c):
