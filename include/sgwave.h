@@ -211,9 +211,14 @@ sg_status sg_host_taps(int kind, int b, int J, double T, int *q0, double *w);
  *   two consecutive instants more than one finest time interval T / 2^J
  *   apart (a uniform grid of at least 2^J + 1 instants qualifies; SG_EINVAL
  *   otherwise).  Builds the evaluation tables (spline values and derivatives
- *   of every time level at the instants) and allocates the workspace (two
- *   K x n^d arrays, about 16 K n^d bytes); synchronises the device; replaces
- *   and frees an earlier setup.  SG_ENOMEM if the workspace does not fit.
+ *   of every time level at the instants) and allocates the workspace:
+ *   in 2-D with 16 x 16 streaming tiles (J <= 10) the element forms are
+ *   applied inside the evaluation: the workspace is one partial sum per
+ *   instant and tile and, per instant, the values of the level below the
+ *   tiles (each about K (n/16)^2 doubles), and no field is written;
+ *   otherwise (1-D, finer 2-D levels) two K x n^d arrays of the fields.  Synchronises the device;
+ *   replaces and frees an earlier setup.  SG_ENOMEM if the workspace does not
+ *   fit.
  * sg_energy: u0 as given to the forward solve (device, fine space array),
  *   E device array of K doubles (caller-owned).  Stream ordered; allocates
  *   nothing.  SG_ESTATE without a setup.

@@ -189,8 +189,9 @@ struct sg_problem {
   // energy diagnostic (sg_energy_setup / sg_energy); its device memory is
   // owned separately and released by the next setup
   int eK = 0, enblk = 0;
+  int efused = 0;                  // 2-D 16 x 16 tiles: element forms inside the evaluation
   Pass eval, eder;
-  double *eU = nullptr, *eUt = nullptr, *epart = nullptr, *ecpro = nullptr;
+  double *eU = nullptr, *eUt = nullptr, *epart = nullptr, *ecpro = nullptr, *ecpro_d = nullptr;
   std::vector<void *> eallocs;
   std::vector<Pass> plain_load, plain_prol;
   // descriptor lists
@@ -482,12 +483,13 @@ sg_status run_restrict(sg_problem *p, const Scratch &ws, const Pass &P, const do
   return SG_OK;
 }
 
-sg_status run_prolong(sg_problem *p, const Pass &P, const double *base, double *out,
-                      int accumulate, int stencil, hipStream_t s, int ev_begin = -1,
-                      double *cpro = nullptr) {
-  if (!cpro) cpro = p->Cpro;  // [ntf][level-A0 nodes] of the pass
+// Arguments of a streaming prolongation of pass P; the levels below the tiles
+// are evaluated into cpro first (launched on s) when the pass has any.
+sg_status prolong_args(sg_problem *p, const Pass &P, const double *base, double *out,
+                       int accumulate, int stencil, double *cpro, hipStream_t s,
+                       ProlongArgs &pa) {
   const Geometry &g = P.geo;
-  ProlongArgs pa{};
+  pa = ProlongArgs{};
   pa.g = g;
   std::copy(P.h_ch.begin(), P.h_ch.end(), pa.ch);
   for (const Channel &C : P.h_ch)
@@ -509,6 +511,16 @@ sg_status run_prolong(sg_problem *p, const Pass &P, const double *base, double *
   const double hx = p->len[0] / p->N, hy = (p->d == 2 ? p->len[1] : 1.0) / p->N;
   pa.sx = hx / 6.0;
   pa.sy = hy / 6.0;
+  return SG_OK;
+}
+
+sg_status run_prolong(sg_problem *p, const Pass &P, const double *base, double *out,
+                      int accumulate, int stencil, hipStream_t s, int ev_begin = -1,
+                      double *cpro = nullptr) {
+  if (!cpro) cpro = p->Cpro;  // [ntf][level-A0 nodes] of the pass
+  ProlongArgs pa;
+  sg_status st = prolong_args(p, P, base, out, accumulate, stencil, cpro, s, pa);
+  if (st) return st;
   if (ev_begin >= 0) MARK(p, ev_begin, s);
   HIPCHK(launch_prolong(pa, s));
   if (ev_begin >= 0) MARK(p, ev_begin + 1, s);
@@ -1672,6 +1684,8 @@ sg_status sg_energy_setup(sg_problem *p, int K, const double *times) {
   for (void *a : p->eallocs) (void)hipFree(a);
   p->eallocs.clear();
   p->eK = 0;
+  p->efused = 0;
+  p->ecpro_d = nullptr;
   p->eval = Pass{};
   p->eder = Pass{};
   // spline values and derivatives of every time level at the instants; the
@@ -1729,14 +1743,25 @@ sg_status sg_energy_setup(sg_problem *p, int K, const double *times) {
   if ((st = build_pass(p, p->eval, ge, spec(false), &part_unused, true)) ||
       (st = build_pass(p, p->eder, ge, spec(true), &part_unused, true)))
     return st;
-  p->enblk = (p->N + 255) / 256;  // one thread per element (column in 2-D)
   const long long n0a = (1LL << ge.A0) - 1;
   const long long nsp0 = p->d == 2 ? n0a * n0a : n0a;
-  if (!(p->eU = p->dalloc<double>((size_t)K * p->nsp_fine)) ||
-      !(p->eUt = p->dalloc<double>((size_t)K * p->nsp_fine)) ||
-      !(p->epart = p->dalloc<double>((size_t)K * p->enblk)) ||
-      !(p->ecpro = p->dalloc<double>(ge.A0 > 1 ? (size_t)K * nsp0 : 1)))
-    return fail(SG_ENOMEM, "hipMalloc of the energy workspace failed");
+  const size_t ncoarse = ge.A0 > 1 ? (size_t)K * nsp0 : 1;
+  p->efused = p->d == 2 && ge.TS == 16;
+  if (p->efused) {
+    // one partial per instant and tile; no field is written
+    p->enblk = ge.ntile * ge.ntile;
+    p->eU = p->eUt = nullptr;
+    if (!(p->epart = p->dalloc<double>((size_t)K * p->enblk)) ||
+        !(p->ecpro = p->dalloc<double>(ncoarse)) || !(p->ecpro_d = p->dalloc<double>(ncoarse)))
+      return fail(SG_ENOMEM, "hipMalloc of the energy workspace failed");
+  } else {
+    p->enblk = (p->N + 255) / 256;  // one thread per element (column in 2-D)
+    if (!(p->eU = p->dalloc<double>((size_t)K * p->nsp_fine)) ||
+        !(p->eUt = p->dalloc<double>((size_t)K * p->nsp_fine)) ||
+        !(p->epart = p->dalloc<double>((size_t)K * p->enblk)) ||
+        !(p->ecpro = p->dalloc<double>(ncoarse)))
+      return fail(SG_ENOMEM, "hipMalloc of the energy workspace failed");
+  }
   p->eK = K;
   return SG_OK;
 }
@@ -1746,9 +1771,18 @@ sg_status sg_energy(sg_problem *p, const double *u0, double *E, hipStream_t s) {
   if (p->eK == 0) return fail(SG_ESTATE, "sg_energy needs sg_energy_setup first");
   if (!u0 || !E) return fail(SG_EINVAL, "NULL data pointer");
   sg_status st;
+  const double hx = p->len[0] / p->N, hy = (p->d == 2 ? p->len[1] : 1.0) / p->N;
+  if (p->efused) {
+    ProlongArgs pv, pd;
+    if ((st = prolong_args(p, p->eval, u0, nullptr, 0, 0, p->ecpro, s, pv)) ||
+        (st = prolong_args(p, p->eder, nullptr, nullptr, 0, 0, p->ecpro_d, s, pd)))
+      return st;
+    HIPCHK(launch_energy_w(pv, pd.taps, pd.coarse, p->d_ce, hx, hy, p->epart, p->eK,
+                           p->enblk, E, s));
+    return SG_OK;
+  }
   if ((st = run_prolong(p, p->eval, u0, p->eU, 0, 0, s, -1, p->ecpro))) return st;
   if ((st = run_prolong(p, p->eder, nullptr, p->eUt, 0, 0, s, -1, p->ecpro))) return st;
-  const double hx = p->len[0] / p->N, hy = (p->d == 2 ? p->len[1] : 1.0) / p->N;
   HIPCHK(launch_energy(p->d, p->N, p->d_ce, hx, hy, p->eU, p->eUt, p->eK, p->enblk, p->epart,
                        E, s));
   return SG_OK;

@@ -1914,6 +1914,293 @@ __global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A
   }
 }
 
+// Energy of u_h at given instants (2-D, 16 x 16 tiles), without forming the
+// fields in memory: per wave one tile and a chunk of instants.  Per instant
+// the tile's upper-level nodes are evaluated in time twice over the same
+// coefficient windows, with the value taps of A.taps and the derivative taps
+// of taps_d (and the levels below the tile from A.coarse and coarse_d), both
+// fields are interpolated down to level 1, and the values of u_h (plus u0 =
+// A.base) and d_t u_h at the tile's 17 x 17 nodes (its own 16 x 16 and the
+// first row and column of the next tiles, which close its elements) go to
+// LDS.  Each lane then applies the Q1 element mass form to d_t u_h and the
+// c^2-weighted stiffness form to u_h on its four elements (lower-left nodes
+// in column l % 16, rows 4 (l / 16) .. +3), and the wave's sum in a fixed
+// order is part[n][tile].  Two workgroups per CU: both fields' windows, taps
+// and level-J coefficients stay in registers.
+__global__ void __launch_bounds__(256, 2) k_energy_w(const ProlongArgs A,
+                                                          const TapEntry *__restrict__ taps_d,
+                                                          const double *__restrict__ coarse_d,
+                                                          const double *__restrict__ ce,
+                                                          double hx, double hy,
+                                                          double *__restrict__ part) {
+  constexpr int TS = 16, LTS = 4, NP = TS + 1;
+  using SH = Shape<2, TS, 0>;
+  constexpr int EF = TS * TS / 64;       // own nodes (and elements) per lane
+  constexpr int UP = SH::upper;
+  constexpr int NS = (UP + 63) / 64;     // owned upper-node slots per lane
+  constexpr int NCI = 2 * (LTS + 1);
+  constexpr int NRING = 2 * TS + 1;      // column 16 (rows 0..16), row 16 (columns 0..15)
+  static_assert(NS == 2 && NRING <= 64, "tile shape");
+  __shared__ double s_v_w[4][2][UP];
+  __shared__ __align__(16) double s_t_w[4][2][4 * NCI];
+  __shared__ double s_f_w[4][2][NP * NP];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double *s_v[2] = {s_v_w[wave][0], s_v_w[wave][1]};  // value, derivative
+  double *s_t[2] = {s_t_w[wave][0], s_t_w[wave][1]};
+  double *s_f[2] = {s_f_w[wave][0], s_f_w[wave][1]};
+
+  const Geometry g = A.g;
+  const int nt = g.ntile, ngx = (nt + 3) >> 2;
+  int grp, chunk;
+  stream_block(ngx * nt, g.nchunk, grp, chunk);
+  const int tx = 4 * (grp % ngx) + wave, ty = grp / ngx;
+  if (tx >= nt || ty >= nt) return;  // no workgroup barrier below
+  const int tile = ty * nt + tx, ntileD = nt * nt;
+  const int n0 = chunk * g.chunk, n1 = min(n0 + g.chunk, g.ntf);
+  const int R = g.R;
+  const int N = g.nxf + 1;  // elements per axis
+  const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
+  const int n0a = (1 << g.A0) - 1;
+  const long long nsp0 = (long long)n0a * n0a;
+
+  // ---- owned upper nodes: coefficient offsets and windows (shared by both
+  // fields: the value and derivative taps have the same windows) ----
+  Owned<2, TS, 0> own[NS];
+  int coff[NS], cof0[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    own[i].set(lane + 64 * i);
+    coff[i] = -1;
+    cof0[i] = -1;
+    const int r = own[i].r;
+    if (r >= 1 && r <= R) {
+      const int na = (1 << (g.J - r)) - 1;
+      const int Px = tile_lo(TS, tx, r, 0) + own[i].jx;
+      const int Py = tile_lo(TS, ty, r, 0) + own[i].jy;
+      if (interior(Px, na) && interior(Py, na)) coff[i] = (Px - 1) + (Py - 1) * na;
+      if (r == R && use_coarse && interior(Px, n0a) && interior(Py, n0a))
+        cof0[i] = (Px - 1) + (Py - 1) * n0a;
+    }
+  }
+  auto coef = [&](const Channel &C, int q, int off) -> double {
+    if (off < 0 || q >= C.nq) return 0.0;
+    const int na = (1 << C.a) - 1;
+    return (C.data + (long long)q * na * na)[lane_off(off)];
+  };
+  double cw[NS][2][3];
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      cw[i][k][0] = cw[i][k][1] = cw[i][k][2] = 0.0;
+      const int r = own[i].r;
+      if (r < 1 || r > R) continue;
+      const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
+      if (!C.active) continue;
+      const int q = ld_const(C.q0, n0);
+#pragma unroll
+      for (int o = 0; o < 3; ++o) cw[i][k][o] = coef(C, q + o, coff[i]);
+    }
+
+  // ---- the lane's nodes: own column fx, rows fy0 .. fy0+3; ring node
+  // lane < 33: (16, lane) for lane <= 16, else (lane - 17, 16).  Level-J
+  // channel coefficients (q0 = 0 throughout) and u0 at each ----
+  const int fx = lane & 15, fy0 = (lane >> 4) * EF;
+  const bool has_ring = lane < NRING;
+  const int rx = lane <= TS ? TS : lane - (TS + 1), ry = lane <= TS ? lane : TS;
+  const Channel &CJ = A.ch[(g.J - 1) * 2];
+  double rc[EF + 1][3], basev[EF + 1];
+#pragma unroll
+  for (int e = 0; e <= EF; ++e) {
+    const int x = e < EF ? fx : rx, y = e < EF ? fy0 + e : ry;
+    const int Px = TS * tx + x, Py = TS * ty + y;
+    const bool in = (e < EF || has_ring) && interior(Px, g.nxf) && interior(Py, g.nxf);
+    const int off = in ? (Px - 1) + (Py - 1) * g.nxf : -1;
+#pragma unroll
+    for (int o = 0; o < 3; ++o) rc[e][o] = CJ.active ? coef(CJ, o, off) : 0.0;
+    basev[e] = (A.base != nullptr && off >= 0) ? A.base[off] : 0.0;
+  }
+  // c^2 of the lane's elements (lower-left nodes (fx, fy0 + e)); zero for
+  // elements outside the domain
+  double c2e[EF];
+#pragma unroll
+  for (int e = 0; e < EF; ++e) {
+    const int ex = TS * tx + fx, ey = TS * ty + fy0 + e;
+    c2e[e] = (ex < N && ey < N) ? ce[(long long)ey * N + ex] : 0.0;
+  }
+  const double *cbase[2] = {use_coarse ? A.coarse : A.safe_w, use_coarse ? coarse_d : A.safe_w};
+  double pco[2][NS];
+  auto fetch_co = [&](int n) {
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      const double *row = cbase[f] + (use_coarse ? (long long)n * nsp0 : 0);
+#pragma unroll
+      for (int i = 0; i < NS; ++i) pco[f][i] = row[lane_off(max(cof0[i], 0))];
+    }
+  };
+  const int pn1 = SH::nodes(1);
+
+  int sidx[NS], tslot[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const int r = own[i].r;
+    const bool act = r >= 1 && r <= R;
+    sidx[i] = act ? SH::offset(r) - SH::size(0) + own[i].j : -1;
+    tslot[i] = act ? 8 * r : 0;
+  }
+  SlabTaps<NCI> tp[2];
+  tp[0].fetch(A.taps, n0, lane);
+  tp[1].fetch(taps_d, n0, lane);
+
+  double co[2][NS];
+  auto take_next = [&]() {
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        co[f][i] = cof0[i] >= 0 ? pco[f][i] : 0.0;
+        take(co[f][i]);
+      }
+      tp[f].stage(s_t[f], lane);
+    }
+  };
+  // level-1 part of a field at the tile's node (x, y), 0 <= x, y <= 16
+  auto lev1 = [&](const double *v1, int x, int y) -> double {
+    const int kx = x >> 1, ky = y >> 1;
+    const bool ox = x & 1, oy = y & 1;
+    const double a = v1[ky * pn1 + kx], b = ox ? v1[ky * pn1 + kx + 1] : a;
+    const double r0 = ox ? 0.5 * (a + b) : a;
+    if (!oy) return r0;
+    const double c = v1[(ky + 1) * pn1 + kx], d = ox ? v1[(ky + 1) * pn1 + kx + 1] : c;
+    const double r1 = ox ? 0.5 * (c + d) : c;
+    return 0.5 * (r0 + r1);
+  };
+  fetch_co(n0);
+  take_next();
+  for (int n = n0; n < n1; ++n) {
+    const TapEntry *tn = A.taps + (long long)n * NCI;
+    if (n + 1 < n1) {
+      fetch_co(n + 1);
+      tp[0].fetch(A.taps, n + 1, lane);
+      tp[1].fetch(taps_d, n + 1, lane);
+    }
+    wave_sync();
+    // (A) windows that move on at this slab shift first (the same for both
+    // fields), then every slot applies the taps of its own level
+    const int mv = slab_moves(s_t[0]);
+    if (mv != 0) {
+#pragma unroll
+      for (int r = 1; r <= LTS; ++r) {
+        if (r > R) break;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          if (!((mv >> (2 * r + k)) & 1)) continue;
+          const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
+          const int q = (int)ld_const(tn, 2 * r + k).base;  // new first time index
+#pragma unroll
+          for (int i = 0; i < NS; ++i) {
+            if (own[i].r != r) continue;
+            cw[i][k][0] = cw[i][k][1];
+            cw[i][k][1] = cw[i][k][2];
+            cw[i][k][2] = coef(C, q + 2, coff[i]);
+            take(cw[i][k][2]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const double *t = s_t[f] + tslot[i];
+        const double2 a0 = *reinterpret_cast<const double2 *>(t);
+        const double2 a1 = *reinterpret_cast<const double2 *>(t + 2);
+        const double2 b0 = *reinterpret_cast<const double2 *>(t + 4);
+        const double2 b1 = *reinterpret_cast<const double2 *>(t + 6);
+        const double v = co[f][i] + a0.x * cw[i][0][0] + a0.y * cw[i][0][1] + a1.x * cw[i][0][2] +
+                         b0.x * cw[i][1][0] + b0.y * cw[i][1][1] + b1.x * cw[i][1][2];
+        if (sidx[i] >= 0) s_v[f][sidx[i]] = v;
+      }
+    // (B) top-down interpolation r = R-1 .. 1, both fields
+#pragma unroll
+    for (int r = LTS - 1; r >= 1; --r) {
+      if (r >= R) continue;
+      wave_sync();
+      const int pn = SH::nodes(r + 1);
+      const int lox = tile_lo(TS, tx, r, 0), loy = tile_lo(TS, ty, r, 0);
+      const int qx = tile_lo(TS, tx, r + 1, 0), qy = tile_lo(TS, ty, r + 1, 0);
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const double *par = s_v[f] + SH::offset(r + 1) - SH::size(0);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          if (own[i].r != r) continue;
+          const int Px = lox + own[i].jx, Py = loy + own[i].jy;
+          const int xl = (Px >> 1) - qx, xh = ((Px + 1) >> 1) - qx;
+          const int yl = (Py >> 1) - qy, yh = ((Py + 1) >> 1) - qy;
+          s_v[f][SH::offset(r) - SH::size(0) + own[i].j] +=
+              0.25 * (par[yl * pn + xl] + par[yl * pn + xh] + par[yh * pn + xl] + par[yh * pn + xh]);
+        }
+      }
+    }
+    wave_sync();
+    // (C) the fields at the lane's nodes (own and ring) into LDS
+    double tj[2][3];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      tj[f][0] = s_t[f][0];
+      tj[f][1] = s_t[f][1];
+      tj[f][2] = s_t[f][2];
+    }
+    if (n + 1 < n1) take_next();
+    wave_sync();
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+#pragma unroll
+      for (int e = 0; e <= EF; ++e) {
+        if (e == EF && !has_ring) continue;
+        const int x = e < EF ? fx : rx, y = e < EF ? fy0 + e : ry;
+        double v = tj[f][0] * rc[e][0] + tj[f][1] * rc[e][1] + tj[f][2] * rc[e][2];
+        if (R >= 1) v += lev1(s_v[f], x, y);
+        if (f == 0) v += basev[e];
+        s_f[f][y * NP + x] = v;
+      }
+    }
+    wave_sync();
+    // (D) element forms of the lane's four elements: rows fy0 .. fy0+4 of
+    // columns fx, fx + 1
+    double w[EF + 1][2], u[EF + 1][2];
+#pragma unroll
+    for (int e = 0; e <= EF; ++e) {
+      w[e][0] = s_f[0][(fy0 + e) * NP + fx];
+      w[e][1] = s_f[0][(fy0 + e) * NP + fx + 1];
+      u[e][0] = s_f[1][(fy0 + e) * NP + fx];
+      u[e][1] = s_f[1][(fy0 + e) * NP + fx + 1];
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < EF; ++e) {
+      // Q1 element forms with the 1-D mass m = h/6 [2 1; 1 2] and stiffness
+      // k = 1/h [1 -1; -1 1]: mass m_y (x) m_x, stiffness c^2 (m_y (x) k_x + k_y (x) m_x)
+      const double ul0 = u[e][0], ul1 = u[e][1], uh0 = u[e + 1][0], uh1 = u[e + 1][1];
+      const double wl0 = w[e][0], wl1 = w[e][1], wh0 = w[e + 1][0], wh1 = w[e + 1][1];
+      const double ml = 2.0 * ul0 * ul0 + 2.0 * ul0 * ul1 + 2.0 * ul1 * ul1;
+      const double mh = 2.0 * uh0 * uh0 + 2.0 * uh0 * uh1 + 2.0 * uh1 * uh1;
+      const double mc = 2.0 * ul0 * uh0 + ul0 * uh1 + ul1 * uh0 + 2.0 * ul1 * uh1;
+      const double mass = hx / 6.0 * hy / 6.0 * (2.0 * ml + 2.0 * mh + 2.0 * mc);
+      const double gx0 = wl1 - wl0, gx1 = wh1 - wh0;
+      const double gy0 = wh0 - wl0, gy1 = wh1 - wl1;
+      const double kx = (hy / 6.0) / hx * (2.0 * gx0 * gx0 + 2.0 * gx0 * gx1 + 2.0 * gx1 * gx1);
+      const double ky = (hx / 6.0) / hy * (2.0 * gy0 * gy0 + 2.0 * gy0 * gy1 + 2.0 * gy1 * gy1);
+      acc += 0.5 * (mass + c2e[e] * (kx + ky));
+    }
+    // wave sum, butterfly order (the same in every lane)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) part[(long long)n * ntileD + tile] = acc;
+  }
+}
+
 // ------------------------------------------------------- small kernels -----
 
 // Fine-grid mass and stiffness stencils (per-element c^2 on the finest mesh).
@@ -2042,13 +2329,18 @@ __global__ void __launch_bounds__(256) k_energy_part(int N, const double *__rest
   if (threadIdx.x == 0) part[(long long)k * gridDim.x + blockIdx.x] = s_red[0];
 }
 
-__global__ void k_energy_sum(int K, int nblk, const double *__restrict__ part,
-                             double *__restrict__ E) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+// E[k] = sum_b part[k][b]: one wave per instant, lane l adding the partials
+// b = l, l + 64, ..., then a butterfly (a fixed order)
+__global__ void __launch_bounds__(64) k_energy_sum(int K, int nblk,
+                                                   const double *__restrict__ part,
+                                                   double *__restrict__ E) {
+  const int k = blockIdx.x;
   if (k >= K) return;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(long long)k * nblk + b];
-  E[k] = s;
+  for (int b = threadIdx.x; b < nblk; b += 64) s += part[(long long)k * nblk + b];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (threadIdx.x == 0) E[k] = s;
 }
 
 
@@ -3021,7 +3313,21 @@ hipError_t launch_energy(int d, int N, const double *ce, double hx, double hy, c
     hipLaunchKernelGGL(k_energy_part<2>, grid, dim3(256), 0, s, N, ce, hx, hy, W, Ut, part);
   else
     hipLaunchKernelGGL(k_energy_part<1>, grid, dim3(256), 0, s, N, ce, hx, hy, W, Ut, part);
-  hipLaunchKernelGGL(k_energy_sum, dim3((K + 63) / 64), dim3(64), 0, s, K, nblk, part, E);
+  hipLaunchKernelGGL(k_energy_sum, dim3(K), dim3(64), 0, s, K, nblk, part, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_w(const ProlongArgs &a, const TapEntry *taps_d, const double *coarse_d,
+                           const double *ce, double hx, double hy, double *part, int K,
+                           int ntile2, double *E, hipStream_t s) {
+  if (K <= 0) return hipSuccess;
+  if (a.g.d != 2 || a.g.TS != 16 || a.taps == nullptr || taps_d == nullptr ||
+      a.g.ntile * a.g.ntile != ntile2 || a.g.ntf != K)
+    return hipErrorInvalidValue;
+  const int ngx = (a.g.ntile + 3) / 4;  // four tiles side by side per workgroup
+  hipLaunchKernelGGL(k_energy_w, dim3(ngx * a.g.ntile, a.g.nchunk), dim3(256), 0, s, a, taps_d,
+                     coarse_d, ce, hx, hy, part);
+  hipLaunchKernelGGL(k_energy_sum, dim3(K), dim3(64), 0, s, K, ntile2, part, E);
   return hipGetLastError();
 }
 

@@ -186,6 +186,11 @@ hipError_t launch_prolong(const ProlongArgs &a, hipStream_t s);
 hipError_t launch_energy(int d, int N, const double *ce, double hx, double hy, const double *W,
                          const double *Ut, int K, int nblk, double *part, double *E,
                          hipStream_t s);
+// fused energy of u_h (2-D, 16 x 16 tiles): value pass a (base = u0), the
+// derivative pass's taps and coarse array; part[K][ntile^2], then E[K]
+hipError_t launch_energy_w(const ProlongArgs &a, const TapEntry *taps_d, const double *coarse_d,
+                           const double *ce, double hx, double hy, double *part, int K,
+                           int ntile2, double *E, hipStream_t s);
 hipError_t launch_fine_stencils(int d, int N, const double *ce, double hx,
                                 double hy, const double *v_in, const double *u_in,
                                 double *mv_out, double *ku_out,
