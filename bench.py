@@ -20,6 +20,7 @@ and the roofline of its merged component solves.
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -222,6 +223,40 @@ def time_energy(sv, u0, stream, T, K, nspace, reps=5):
     return {"instants": K, "ms": t * 1e3, "us_per_instant": t * 1e6 / K,
             "fine_nodes_evaluated_per_s": 2.0 * K * nspace / t,
             "E_first_last": [float(E[0]), float(E[-1])]}
+
+
+def time_l2(sv, u0, stream, reps=3):
+    """Relative L^2(Q_T) error of the manufactured solution u = sin(pi x)
+    sin(pi y) sin(pi t) (the benchmark workload's exact solution) by the
+    library's quadrature: u_h at 3 Gauss instants per finest time interval,
+    2 x 2 Gauss points per finest element; the exact values at the points
+    are generated on the device (separable)."""
+    import torch
+    sv.l2_setup()
+    p = sv.l2_points()
+    dev = u0.device
+    st = torch.sin(math.pi * torch.from_numpy(p["t"]).to(dev))
+    sx = torch.sin(math.pi * torch.from_numpy(p["xq"]).to(dev))
+    sy = torch.sin(math.pi * torch.from_numpy(p["yq"]).to(dev))
+    uq = st[:, None, None] * sy[None, :, None] * sx[None, None, :]
+    with torch.cuda.stream(stream):
+        out = sv.l2_error(u0, uq, stream=stream)
+    stream.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for _ in range(reps):
+            sv.l2_error(u0, uq, out=out, stream=stream)
+        e1.record(stream)
+    stream.synchronize()
+    err, nrm = (float(v) for v in out.cpu())
+    res = {"relative_l2_error": math.sqrt(err / nrm), "norm_exact": math.sqrt(nrm),
+           "ms": e0.elapsed_time(e1) / reps, "instants": int(p["t"].size),
+           "points_per_instant": int(p["xq"].size) ** 2}
+    del uq
+    torch.cuda.empty_cache()
+    return res
 
 
 def _gaussians_on_device(spec, centres, dev, width=0.05):
@@ -507,13 +542,14 @@ def main():
         plain_diff = float((Up - U).norm() / U.norm())
         del Up
 
-    # ---- energy of the solution at 800 instants (Sec. 6.3 diagnostic) ------
-    # two streaming prolongations over the instants (value and time
-    # derivative of u_h) and an element-wise reduction that reads both back
+    # ---- Sec. 6.3 diagnostics: energy at 800 instants (element forms inside
+    # the evaluation over the instants) and the relative L^2(Q_T) error of the
+    # manufactured solution by quadrature
     K_e = 800
-    energy_out = None
+    energy_out, l2_out = None, None
     if not args.no_energy:
         energy_out = time_energy(sv, u0, stream, spec.T, K_e, nfull // sv.shape[0])
+        l2_out = time_l2(sv, u0, stream)
 
     # dominant fine-grid kernel (timed inside the last timed graph replay when
     # the runtime records captured events, else in the eager runs): each
@@ -559,6 +595,7 @@ def main():
             "plain_vs_fused_rel_l2": plain_diff,
             "graph_equals_eager": graph_equals_eager,
             "energy": energy_out,
+            "l2_error": l2_out,
             "stage_ms": {k: v * 1e3 for k, v in stage.items()},
             "kernel_ms": {k: v * 1e3 for k, v in kern_t.items()},
             "kernel_ms_from": (f"{dom}: last timed replay of the graph with the directions in "

@@ -226,6 +226,34 @@ sg_status sg_host_taps(int kind, int b, int J, double T, int *q0, double *w);
 sg_status sg_energy_setup(sg_problem *p, int K, const double *t);
 sg_status sg_energy(sg_problem *p, const double *u0, double *E, hipStream_t stream);
 
+/*
+ * L^2(Q_T) error of the computed solution by quadrature (Sec. 6.3, the
+ * relative errors of the coarse-mesh study): for an exact solution u given
+ * by the caller at the quadrature points,
+ *   out[0] = int_{Q_T} (u - u_h)^2,   out[1] = int_{Q_T} u^2,
+ * u_h = u^CF + u0 of the last forward solve on this handle (u0 read, like
+ * the solver reads it, as its finest-grid interpolant).  The rule is the
+ * tensor Gauss rule with 3 points per finest time interval and 2 points per
+ * finest element along each space axis: exact for u_h^2 (quadratic in t, Q1
+ * in space on every finest cell), of order h^4 for the error integrand.
+ * sg_l2_points: the rule (host arrays, any may be NULL): K = 3 * 2^J
+ *   instants t[K] with weights wt[K] (ascending), nq = 2 * 2^J points per
+ *   space axis xq[nq], yq[nq] (d = 2; the weights are h/2 per point).
+ * sg_l2_setup: evaluation tables at the instants and the workspace (one
+ *   K x n^d array of u_h at the instants, about 24 * 2^J * n^d bytes);
+ *   synchronises the device; replaces an earlier setup.  SG_ENOMEM if it
+ *   does not fit.
+ * sg_l2_error: u0 as given to the forward solve (device, fine space
+ *   array); uq device array [K][nq^d] (d = 2: [K][y][x], x fastest) of u at
+ *   the points; out device array of 2 doubles.  Stream ordered; allocates
+ *   nothing; a fixed summation order.  SG_ESTATE without a setup.
+ */
+sg_status sg_l2_points(const sg_problem *p, int *K, double *t, double *wt, int *nq, double *xq,
+                       double *yq);
+sg_status sg_l2_setup(sg_problem *p);
+sg_status sg_l2_error(sg_problem *p, const double *u0, const double *uq, double *out,
+                      hipStream_t stream);
+
 /* Release the handle and all device memory it owns.  NULL is accepted. */
 sg_status sg_destroy(sg_problem *p);
 

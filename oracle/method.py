@@ -284,12 +284,14 @@ _NQ = 5
 _QX, _QW = np.polynomial.legendre.leggauss(_NQ)
 
 
-def fine_quadrature(J, length):
-    """Gauss points/weights on every element of the level-J mesh of (0,length)."""
+def fine_quadrature(J, length, nq=_NQ):
+    """Gauss points/weights (nq per element) on every element of the level-J
+    mesh of (0,length)."""
+    qx, qw = (_QX, _QW) if nq == _NQ else np.polynomial.legendre.leggauss(nq)
     h = length / 2 ** J
     left = h * np.arange(2 ** J)
-    pts = (left[:, None] + 0.5 * h * (_QX[None, :] + 1.0)).reshape(-1)
-    wts = np.tile(0.5 * h * _QW, 2 ** J)
+    pts = (left[:, None] + 0.5 * h * (qx[None, :] + 1.0)).reshape(-1)
+    wts = np.tile(0.5 * h * qw, 2 ** J)
     return pts, wts
 
 
@@ -419,3 +421,30 @@ def l2_error(prob, sols, u_fn, u0_fn=None, comps=None):
         ue = u_fn(tq[:, None, None], xs[0][0][None, None, :], xs[1][0][None, :, None])
         W = tw[:, None, None] * xs[1][1][None, :, None] * xs[0][1][None, None, :]
     return np.sqrt(np.sum(W * (ue - uh) ** 2)), np.sqrt(np.sum(W * ue ** 2))
+
+
+def l2_error_rule(prob, sols, u0, u_fn, nq_t=3, nq_x=2):
+    """(int (u - u_h)^2, int u^2) over Q_T by the tensor Gauss rule with nq_t
+    points per finest time interval and nq_x points per finest element along
+    each space axis (Sec. 6.3 reports relative L^2(Q_T) errors); u_h = I_J u0
+    + sum_c s_c u_c with the nodal u0 read as its finest-grid interpolant, as
+    the solver reads it.  u_fn(t, x) or u_fn(t, x, y), vectorised."""
+    from . import basis
+    J = prob.J
+    tq, tw = fine_quadrature(J, prob.T, nq_t)
+    xs = [fine_quadrature(J, prob.medium.lengths[a], nq_x) for a in range(prob.d)]
+    uh = combined_at(prob, sols, tq, [x[0] for x in xs])
+    P = [basis.hat_1d(J, prob.medium.lengths[a], xs[a][0]) for a in range(prob.d)]
+    u0 = np.asarray(u0, dtype=np.float64)
+    if prob.d == 1:
+        lift = P[0] @ u0.reshape(-1)
+        ue = u_fn(tq[:, None], xs[0][0][None, :])
+        W = tw[:, None] * xs[0][1][None, :]
+    else:
+        n = 2 ** J - 1
+        lift = P[1] @ u0.reshape(n, n) @ P[0].T                # (y, x)
+        ue = u_fn(tq[:, None, None], xs[0][0][None, None, :], xs[1][0][None, :, None])
+        W = tw[:, None, None] * xs[1][1][None, :, None] * xs[0][1][None, None, :]
+    uh = uh + lift[None]
+    return float(np.sum(W * (ue - uh) ** 2)), float(np.sum(W * ue ** 2))
+

@@ -63,6 +63,10 @@ SIGNATURES = {
                                      ctypes.c_int]),
     "sg_energy_setup": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_dp]),
     "sg_energy": (ctypes.c_int, [ctypes.c_void_p] * 4),
+    "sg_l2_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), _c_dp, _c_dp,
+                                    ctypes.POINTER(ctypes.c_int), _c_dp, _c_dp]),
+    "sg_l2_setup": (ctypes.c_int, [ctypes.c_void_p]),
+    "sg_l2_error": (ctypes.c_int, [ctypes.c_void_p] * 5),
     "sg_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sg_last_error": (ctypes.c_char_p, []),
 }
@@ -317,6 +321,41 @@ class SparseGridWave:
             out = torch.empty(max(k, 1), dtype=torch.float64, device=u0.device)[:k]
         check(lib().sg_energy(self._h, _ptr(u0, self.space_shape, "u0"), _ptr(out, (k,), "E"),
                               _stream(stream)), "sg_energy")
+        return out
+
+    def l2_points(self):
+        """The L^2(Q_T) quadrature rule: dict of t, wt (instants and weights)
+        and the per-axis points xq (and yq in 2-D)."""
+        K, nq = ctypes.c_int(0), ctypes.c_int(0)
+        check(lib().sg_l2_points(self._h, ctypes.byref(K), None, None, ctypes.byref(nq), None,
+                                 None), "sg_l2_points")
+        t, wt = np.empty(K.value), np.empty(K.value)
+        xq = np.empty(nq.value)
+        yq = np.empty(nq.value) if self.d == 2 else None
+        check(lib().sg_l2_points(self._h, None, t.ctypes.data_as(_c_dp), wt.ctypes.data_as(_c_dp),
+                                 None, xq.ctypes.data_as(_c_dp),
+                                 yq.ctypes.data_as(_c_dp) if yq is not None else None),
+              "sg_l2_points")
+        out = {"t": t, "wt": wt, "xq": xq}
+        if yq is not None:
+            out["yq"] = yq
+        return out
+
+    def l2_setup(self):
+        """Prepare sg_l2_error (evaluation tables and workspace)."""
+        check(lib().sg_l2_setup(self._h), "sg_l2_setup")
+        self._l2_ready = True
+
+    def l2_error(self, u0, uq, out=None, stream=None):
+        """(int (u - u_h)^2, int u^2) over Q_T by the library's quadrature,
+        uq the exact solution at the points of l2_points ([K][nq] or
+        [K][nq][nq]); u_h the lifted solution of the last solve."""
+        pts = self.l2_points()
+        shape = (pts["t"].size,) + (pts["xq"].size,) * self.d
+        if out is None:
+            out = torch.empty(2, dtype=torch.float64, device=u0.device)
+        check(lib().sg_l2_error(self._h, _ptr(u0, self.space_shape, "u0"), _ptr(uq, shape, "uq"),
+                                _ptr(out, (2,), "out"), _stream(stream)), "sg_l2_error")
         return out
 
     def set_events(self, events):

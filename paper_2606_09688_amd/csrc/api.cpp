@@ -193,6 +193,11 @@ struct sg_problem {
   Pass eval, eder;
   double *eU = nullptr, *eUt = nullptr, *epart = nullptr, *ecpro = nullptr, *ecpro_d = nullptr;
   std::vector<void *> eallocs;
+  // L^2(Q_T) error by quadrature (sg_l2_setup / sg_l2_error), likewise
+  int lK = 0, lnblk = 0;
+  Pass lval;
+  double *lU = nullptr, *lpart = nullptr, *lcpro = nullptr, *lwt = nullptr;
+  std::vector<void *> lallocs;
   std::vector<Pass> plain_load, plain_prol;
   // descriptor lists
   GemmList gx, gy, giy, gix;       // fused (all components)
@@ -928,6 +933,7 @@ sg_status sg_destroy(sg_problem *p) {
   if (p->aux) (void)hipStreamDestroy(p->aux);
   for (void *a : p->allocs) (void)hipFree(a);
   for (void *a : p->eallocs) (void)hipFree(a);
+  for (void *a : p->lallocs) (void)hipFree(a);
   (void)hipSetDevice(cur);
   delete p;
   return SG_OK;
@@ -1785,6 +1791,123 @@ sg_status sg_energy(sg_problem *p, const double *u0, double *E, hipStream_t s) {
   if ((st = run_prolong(p, p->eder, nullptr, p->eUt, 0, 0, s, -1, p->ecpro))) return st;
   HIPCHK(launch_energy(p->d, p->N, p->d_ce, hx, hy, p->eU, p->eUt, p->eK, p->enblk, p->epart,
                        E, s));
+  return SG_OK;
+}
+
+namespace {
+
+// Gauss rules of the L^2(Q_T) quadrature: 3 points per finest time interval,
+// 2 per finest element and space axis (reference points on [-1, 1])
+constexpr double kL2GaussT[3] = {-0.7745966692414834, 0.0, 0.7745966692414834};
+constexpr double kL2WeightT[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+constexpr double kL2GaussX = 0.5773502691896258;  // 1 / sqrt(3)
+
+void l2_instants(const sg_problem *p, std::vector<double> &t, std::vector<double> &w) {
+  const int nf = 1 << p->J;
+  const double h = p->T / nf;
+  t.resize(3 * (size_t)nf);
+  w.resize(3 * (size_t)nf);
+  for (int i = 0; i < nf; ++i)
+    for (int g = 0; g < 3; ++g) {
+      t[3 * i + g] = h * (i + 0.5 * (1.0 + kL2GaussT[g]));
+      w[3 * i + g] = 0.5 * h * kL2WeightT[g];
+    }
+}
+
+}  // namespace
+
+sg_status sg_l2_points(const sg_problem *p, int *K, double *t, double *wt, int *nq, double *xq,
+                       double *yq) {
+  if (!p) return fail(SG_EINVAL, "NULL handle");
+  std::vector<double> tt, ww;
+  l2_instants(p, tt, ww);
+  if (K) *K = (int)tt.size();
+  if (t) std::copy(tt.begin(), tt.end(), t);
+  if (wt) std::copy(ww.begin(), ww.end(), wt);
+  const int N = p->N;
+  if (nq) *nq = 2 * N;
+  for (int a = 0; a < 2; ++a) {
+    double *q = a == 0 ? xq : yq;
+    if (!q || (a == 1 && p->d == 1)) continue;
+    const double h = p->len[a] / N;
+    for (int e = 0; e < N; ++e) {
+      q[2 * e] = h * (e + 0.5 * (1.0 - kL2GaussX));
+      q[2 * e + 1] = h * (e + 0.5 * (1.0 + kL2GaussX));
+    }
+  }
+  return SG_OK;
+}
+
+sg_status sg_l2_setup(sg_problem *p) {
+  if (!p) return fail(SG_EINVAL, "NULL handle");
+  std::vector<double> t, w;
+  l2_instants(p, t, w);
+  const int K = (int)t.size();
+  HIPCHK(hipDeviceSynchronize());
+  for (void *a : p->lallocs) (void)hipFree(a);
+  p->lallocs.clear();
+  p->lK = 0;
+  p->lval = Pass{};
+  // spline values of every time level at the instants (three per finest
+  // interval: every coefficient window moves on by at most one node)
+  std::map<int, Taps> tv;
+  for (const Comp &C : p->comps)
+    if (!tv.count(C.b)) tv[C.b] = spline_taps_at(C.b, p->T, t, 0);
+  struct Swap {
+    sg_problem *p;
+    ~Swap() { std::swap(p->allocs, p->lallocs); }
+  } swap_back{p};
+  std::swap(p->allocs, p->lallocs);
+  std::map<int, const int *> dq0;
+  std::map<int, const double *> dwv;
+  sg_status st;
+  for (auto &kv : tv) {
+    int *q = nullptr;
+    double *wv = nullptr;
+    if ((st = upload(p, kv.second.q0, &q)) || (st = upload(p, kv.second.w, &wv))) return st;
+    dq0[kv.first] = q;
+    dwv[kv.first] = wv;
+  }
+  const int J = p->J;
+  const Geometry gl = make_geometry(p->d, J, K, p->prol_target, p->prol_ts);
+  auto spec = [&](int a, int k) {
+    ChanSpec cs;
+    const int ci = k == 0 ? a - 1 : (a <= J - 1 ? J + a - 1 : -1);
+    if (ci < 0) return cs;
+    const Comp &C = p->comps[ci];
+    cs.active = 1;
+    cs.nq = C.nq;
+    cs.q0 = dq0[C.b];
+    cs.w = dwv[C.b];
+    cs.hq0 = &tv[C.b].q0;
+    cs.hw = &tv[C.b].w;
+    cs.data = p->bufU + C.off;
+    cs.scale = (double)C.sign;
+    return cs;
+  };
+  long long part_unused = 0;
+  if ((st = build_pass(p, p->lval, gl, spec, &part_unused, true))) return st;
+  p->lnblk = (p->N + 255) / 256;  // one thread per element (column in 2-D)
+  const long long n0a = (1LL << gl.A0) - 1;
+  const long long nsp0 = p->d == 2 ? n0a * n0a : n0a;
+  if (!(p->lU = p->dalloc<double>((size_t)K * p->nsp_fine)) ||
+      !(p->lpart = p->dalloc<double>((size_t)K * p->lnblk * 2)) ||
+      !(p->lcpro = p->dalloc<double>(gl.A0 > 1 ? (size_t)K * nsp0 : 1)))
+    return fail(SG_ENOMEM, "hipMalloc of the L2 error workspace failed");
+  if ((st = upload(p, w, &p->lwt))) return st;
+  p->lK = K;
+  return SG_OK;
+}
+
+sg_status sg_l2_error(sg_problem *p, const double *u0, const double *uq, double *out,
+                      hipStream_t s) {
+  if (!p) return fail(SG_EINVAL, "NULL handle");
+  if (p->lK == 0) return fail(SG_ESTATE, "sg_l2_error needs sg_l2_setup first");
+  if (!u0 || !uq || !out) return fail(SG_EINVAL, "NULL data pointer");
+  sg_status st;
+  if ((st = run_prolong(p, p->lval, u0, p->lU, 0, 0, s, -1, p->lcpro))) return st;
+  const double hx = p->len[0] / p->N, hy = (p->d == 2 ? p->len[1] : 1.0) / p->N;
+  HIPCHK(launch_l2(p->d, p->N, hx, hy, p->lU, uq, p->lK, p->lnblk, p->lpart, p->lwt, out, s));
   return SG_OK;
 }
 

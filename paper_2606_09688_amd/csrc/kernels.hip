@@ -2344,6 +2344,109 @@ __global__ void __launch_bounds__(64) k_energy_sum(int K, int nblk,
 }
 
 
+// L^2(Q_T) error by quadrature: W[k] holds u_h at the k-th Gauss instant on
+// the finest nodes, UQ[k] the exact solution at the 2 x 2 (2-D) or 2 (1-D)
+// Gauss points of every finest element (point 2 e + g of axis-element e,
+// g = 0 at (1 - 1/sqrt 3) h / 2, g = 1 at (1 + 1/sqrt 3) h / 2 from the
+// element's left end).  One thread per element (a column of elements in 2-D,
+// walked bottom to top); per instant and block the sums of w (u - u_h)^2 and
+// w u^2 over the block's elements and points, w the spatial Gauss weight.
+template <int D>
+__global__ void __launch_bounds__(256) k_l2_part(int N, double hx, double hy,
+                                                 const double *__restrict__ W,
+                                                 const double *__restrict__ UQ,
+                                                 double *__restrict__ part) {
+  __shared__ double s_e[256], s_n[256];
+  const int n = N - 1;
+  const long long nsp = (D == 2) ? (long long)n * n : n;
+  const long long nq = (D == 2) ? 4LL * N * N : 2LL * N;
+  const int k = blockIdx.y;
+  const double *w = W + (long long)k * nsp, *uq = UQ + (long long)k * nq;
+  const int ex = blockIdx.x * blockDim.x + threadIdx.x;
+  const double g0 = 0.5 - 0.5 / sqrt(3.0), g1 = 0.5 + 0.5 / sqrt(3.0);  // local points
+  const double xi[2] = {g0, g1};
+  double ae = 0.0, an = 0.0;
+  if (ex < N) {
+    const bool c0 = ex >= 1, c1 = ex + 1 <= n;
+    const int x0 = c0 ? ex - 1 : 0, x1 = c1 ? ex : 0;
+    if (D == 1) {
+      const double w0 = c0 ? w[x0] : 0.0, w1 = c1 ? w[x1] : 0.0;
+      const double wt = 0.5 * hx;
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const double uh = (1.0 - xi[g]) * w0 + xi[g] * w1, u = uq[2 * ex + g];
+        ae += wt * (u - uh) * (u - uh);
+        an += wt * u * u;
+      }
+    } else {
+      const double wt = 0.25 * hx * hy;
+      double wl0 = 0.0, wl1 = 0.0;  // node row ey (row 0 is on the boundary)
+      for (int ey = 0; ey < N; ++ey) {
+        double wh0 = 0.0, wh1 = 0.0;  // node row ey + 1
+        if (ey + 1 <= n) {
+          const long long r = (long long)ey * n;
+          wh0 = c0 ? w[r + x0] : 0.0;
+          wh1 = c1 ? w[r + x1] : 0.0;
+        }
+#pragma unroll
+        for (int gy = 0; gy < 2; ++gy) {
+          const double *uqr = uq + (long long)(2 * ey + gy) * (2 * N) + 2 * ex;
+#pragma unroll
+          for (int gx = 0; gx < 2; ++gx) {
+            const double lo = (1.0 - xi[gx]) * wl0 + xi[gx] * wl1;
+            const double hi = (1.0 - xi[gx]) * wh0 + xi[gx] * wh1;
+            const double uh = (1.0 - xi[gy]) * lo + xi[gy] * hi, u = uqr[gx];
+            ae += wt * (u - uh) * (u - uh);
+            an += wt * u * u;
+          }
+        }
+        wl0 = wh0;
+        wl1 = wh1;
+      }
+    }
+  }
+  s_e[threadIdx.x] = ae;
+  s_n[threadIdx.x] = an;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (threadIdx.x < h) {
+      s_e[threadIdx.x] += s_e[threadIdx.x + h];
+      s_n[threadIdx.x] += s_n[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[((long long)k * gridDim.x + blockIdx.x) * 2] = s_e[0];
+    part[((long long)k * gridDim.x + blockIdx.x) * 2 + 1] = s_n[0];
+  }
+}
+
+// out[0] = sum_k wt[k] sum_b part[k][b][0], out[1] likewise with [1]: one
+// wave, lane l taking the instants l, l + 64, ..., then a butterfly
+__global__ void __launch_bounds__(64) k_l2_sum(int K, int nblk, const double *__restrict__ part,
+                                               const double *__restrict__ wt,
+                                               double *__restrict__ out) {
+  double se = 0.0, sn = 0.0;
+  for (int k = threadIdx.x; k < K; k += 64) {
+    double e = 0.0, m = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+      e += part[((long long)k * nblk + b) * 2];
+      m += part[((long long)k * nblk + b) * 2 + 1];
+    }
+    se += wt[k] * e;
+    sn += wt[k] * m;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    se += __shfl_xor(se, o, 64);
+    sn += __shfl_xor(sn, o, 64);
+  }
+  if (threadIdx.x == 0) {
+    out[0] = se;
+    out[1] = sn;
+  }
+}
+
 // b_c[i][K] = sum_q D_b[i][q] Z_c[q][K] + psi_i'(0) MV_a[K] - g_b[i] KU_a[K]
 __global__ void k_post_load(const CompDesc *__restrict__ cd, int ncomp, long long total) {
   const long long gid = gid64();
@@ -3328,6 +3431,19 @@ hipError_t launch_energy_w(const ProlongArgs &a, const TapEntry *taps_d, const d
   hipLaunchKernelGGL(k_energy_w, dim3(ngx * a.g.ntile, a.g.nchunk), dim3(256), 0, s, a, taps_d,
                      coarse_d, ce, hx, hy, part);
   hipLaunchKernelGGL(k_energy_sum, dim3(K), dim3(64), 0, s, K, ntile2, part, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_l2(int d, int N, double hx, double hy, const double *W, const double *uq,
+                     int K, int nblk, double *part, const double *wt, double *out,
+                     hipStream_t s) {
+  if (K <= 0) return hipSuccess;
+  const dim3 grid(nblk, K);
+  if (d == 2)
+    hipLaunchKernelGGL(k_l2_part<2>, grid, dim3(256), 0, s, N, hx, hy, W, uq, part);
+  else
+    hipLaunchKernelGGL(k_l2_part<1>, grid, dim3(256), 0, s, N, hx, hy, W, uq, part);
+  hipLaunchKernelGGL(k_l2_sum, dim3(1), dim3(64), 0, s, K, nblk, part, wt, out);
   return hipGetLastError();
 }
 

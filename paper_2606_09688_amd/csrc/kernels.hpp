@@ -191,6 +191,12 @@ hipError_t launch_energy(int d, int N, const double *ce, double hx, double hy, c
 hipError_t launch_energy_w(const ProlongArgs &a, const TapEntry *taps_d, const double *coarse_d,
                            const double *ce, double hx, double hy, double *part, int K,
                            int ntile2, double *E, hipStream_t s);
+// L^2(Q_T) error by quadrature: W [K][n^d] u_h at the Gauss instants, uq
+// [K][(2N)^d] the exact solution at the Gauss points; out[0] = int (u - u_h)^2,
+// out[1] = int u^2 (wt: the time weights of the instants); part [K][nblk][2]
+hipError_t launch_l2(int d, int N, double hx, double hy, const double *W, const double *uq,
+                     int K, int nblk, double *part, const double *wt, double *out,
+                     hipStream_t s);
 hipError_t launch_fine_stencils(int d, int N, const double *ce, double hx,
                                 double hy, const double *v_in, const double *u_in,
                                 double *mv_out, double *ku_out,
