@@ -457,8 +457,9 @@ sg_status add_graph_events(sg_problem *p, hipGraph_t graph) {
     if (st_ != SG_OK) return st_;               \
   } while (0)
 
-sg_status run_restrict(sg_problem *p, const Scratch &ws, const Pass &P, const double *X,
-                       int stencil, hipStream_t s, int ev_begin = -1) {
+// Arguments of the streaming restriction of pass P over X with scratch ws.
+RestrictArgs make_restrict_args(const sg_problem *p, const Scratch &ws, const Pass &P,
+                                const double *X, int stencil) {
   const Geometry &g = P.geo;
   RestrictArgs ra{};
   ra.g = g;
@@ -477,6 +478,13 @@ sg_status run_restrict(sg_problem *p, const Scratch &ws, const Pass &P, const do
   ra.part = ws.part;
   ra.taps = P.d_taps;
   ra.coarse = g.A0 > 1 ? ws.cpart : nullptr;
+  return ra;
+}
+
+sg_status run_restrict(sg_problem *p, const Scratch &ws, const Pass &P, const double *X,
+                       int stencil, hipStream_t s, int ev_begin = -1) {
+  const Geometry &g = P.geo;
+  const RestrictArgs ra = make_restrict_args(p, ws, P, X, stencil);
   if (ev_begin >= 0) MARK(p, ev_begin, s);
   HIPCHK(launch_restrict(ra, s));
   if (ev_begin >= 0) MARK(p, ev_begin + 1, s);
@@ -490,12 +498,15 @@ sg_status run_restrict(sg_problem *p, const Scratch &ws, const Pass &P, const do
 
 // Arguments of a streaming prolongation of pass P; the levels below the tiles
 // are evaluated into cpro first (launched on s) when the pass has any.
-sg_status prolong_args(sg_problem *p, const Pass &P, const double *base, double *out,
-                       int accumulate, int stencil, double *cpro, hipStream_t s,
-                       ProlongArgs &pa) {
-  const Geometry &g = P.geo;
-  pa = ProlongArgs{};
-  pa.g = g;
+// does pass P evaluate the levels below its tiles (into a per-slab array)?
+bool pass_has_coarse(const Pass &P) { return P.geo.A0 > 1 && P.n_crs; }
+
+// Arguments of the streaming prolongation of pass P (the levels below the
+// tiles read from cpro when the pass has any).
+ProlongArgs make_prolong_args(const sg_problem *p, const Pass &P, const double *base,
+                              double *out, int accumulate, int stencil, double *cpro) {
+  ProlongArgs pa{};
+  pa.g = P.geo;
   std::copy(P.h_ch.begin(), P.h_ch.end(), pa.ch);
   for (const Channel &C : P.h_ch)
     if (C.active) {
@@ -503,11 +514,7 @@ sg_status prolong_args(sg_problem *p, const Pass &P, const double *base, double 
       pa.safe_w = C.w;
       break;
     }
-  pa.coarse = nullptr;
-  if (g.A0 > 1 && P.n_crs) {
-    HIPCHK(launch_prolong_coarse(g, P.d_ch, cpro, stencil, s));
-    pa.coarse = cpro;
-  }
+  pa.coarse = pass_has_coarse(P) ? cpro : nullptr;
   pa.taps = P.d_taps;
   pa.base = base;
   pa.out = out;
@@ -516,6 +523,15 @@ sg_status prolong_args(sg_problem *p, const Pass &P, const double *base, double 
   const double hx = p->len[0] / p->N, hy = (p->d == 2 ? p->len[1] : 1.0) / p->N;
   pa.sx = hx / 6.0;
   pa.sy = hy / 6.0;
+  return pa;
+}
+
+sg_status prolong_args(sg_problem *p, const Pass &P, const double *base, double *out,
+                       int accumulate, int stencil, double *cpro, hipStream_t s,
+                       ProlongArgs &pa) {
+  const Geometry &g = P.geo;
+  pa = make_prolong_args(p, P, base, out, accumulate, stencil, cpro);
+  if (pass_has_coarse(P)) HIPCHK(launch_prolong_coarse(g, P.d_ch, cpro, stencil, s));
   return SG_OK;
 }
 
@@ -2056,15 +2072,65 @@ sg_status sg_graph_capture(sg_problem *p, const double *f, const double *u0,
 // parallel branch streams; every solve stage runs once for all problems,
 // over the concatenated descriptor lists of all their components (the
 // largest components first).
-struct BranchSet {                  // branch streams of one direction (default priority)
-  std::vector<hipStream_t> streams;
-  hipEvent_t fork_ev = nullptr;
-  std::vector<hipEvent_t> join_ev;   // one per branch stream
+// One stage of a batch over many problems: one launch per kernel variant
+// present (problems of another dimension or tile size run other kernels),
+// over the members' block ranges (each starting at a multiple of 8 blocks).
+template <class A>
+struct ManyStage {
+  int s0 = -1, s1 = -1, s2 = -1, s3 = -1;  // per-call pointer slots (ManyLaunch)
+  struct Group {
+    long long key = 0;
+    std::vector<A> args;
+    std::vector<int> first, nblk, prob;
+    std::vector<long long> work;  // per-block work (slabs), for the launch order
+    int blocks = 0;
+    A *d_args = nullptr;
+    int *d_first = nullptr, *d_nblk = nullptr, *d_prob = nullptr;
+  };
+  std::vector<Group> groups;
+  // work: slabs one block of the member streams (1 for the flat kernels)
+  void add(long long key, const A &a, long long nblk, int prob, long long work = 1) {
+    if (nblk <= 0) return;
+    Group *G = nullptr;
+    for (Group &g : groups)
+      if (g.key == key) G = &g;
+    if (!G) {
+      groups.emplace_back();
+      G = &groups.back();
+      G->key = key;
+    }
+    G->args.push_back(a);
+    G->nblk.push_back((int)nblk);
+    G->prob.push_back(prob);
+    G->work.push_back(work);
+  }
+  // members with the longest blocks first (then the most blocks), so that the
+  // short ones fill the launch's tail; block ranges assigned in that order
+  void order() {
+    for (Group &G : groups) {
+      const size_t n = G.args.size();
+      std::vector<size_t> ix(n);
+      for (size_t i = 0; i < n; ++i) ix[i] = i;
+      std::stable_sort(ix.begin(), ix.end(), [&](size_t a, size_t b) {
+        return G.work[a] != G.work[b] ? G.work[a] > G.work[b] : G.nblk[a] > G.nblk[b];
+      });
+      Group H;
+      H.key = G.key;
+      for (size_t i : ix) {
+        H.args.push_back(G.args[i]);
+        H.nblk.push_back(G.nblk[i]);
+        H.prob.push_back(G.prob[i]);
+        H.work.push_back(G.work[i]);
+        H.first.push_back(H.blocks);
+        H.blocks += (G.nblk[i] + 7) / 8 * 8;
+      }
+      G = H;
+    }
+  }
 };
 
 struct sg_batch {
   std::vector<sg_problem *> probs;
-  BranchSet fb, ab;                  // forward and adjoint branches
   hipStream_t aux = nullptr;         // the adjoint's main stream in a captured graph
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   std::vector<void *> allocs;
@@ -2076,6 +2142,22 @@ struct sg_batch {
   LevelDesc *d_lev = nullptr;
   int nlev = 0;
   long long lev_total = 0;
+  // streaming stages of all problems, in order: forward
+  ManyStage<StencilArgs> f_sten;                       // M v0, K u0
+  ManyStage<RestrictArgs> f_fr, f_lr;                  // field and load restrictions
+  ManyStage<ReduceArgs> f_fred, f_lred, f_fcr, f_lcr;  // their reductions, coarse restrictions
+  ManyStage<CoarseArgs> f_fpy, f_lpy, f_pc;            // coarse pyramids; coarse prolongation
+  ManyStage<ProlongArgs> f_pr;                         // prolongation into U
+  // adjoint
+  ManyStage<RestrictArgs> a_r;
+  ManyStage<ReduceArgs> a_red, a_cr;
+  ManyStage<CoarseArgs> a_py, a_pcd, a_pcf;
+  ManyStage<ProlongArgs> a_pd, a_pf;                   // df (mass stencil); the field pass
+  ManyStage<StencilArgs> a_sten;                       // du0, dv0
+  // per-call pointer tables [kBatchSlots][n]: eager calls (uploaded from the
+  // pinned host copy each call) and the captured graph's own
+  const double **d_tab = nullptr, **d_tab_graph = nullptr, **h_tab = nullptr;
+  hipEvent_t tab_ev = nullptr;       // the last upload has read h_tab
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<hipEvent_t> ev;        // optional stage events (eager runs)
@@ -2217,49 +2299,208 @@ sg_status merge_fdm(sg_batch *b, FdmList sg_problem::*member, FdmList &out) {
 }
 
 // fork a set of branch streams off s / join them back into s
-sg_status fork(BranchSet &B, hipStream_t s) {
-  HIPCHK(hipEventRecord(B.fork_ev, s));
-  for (hipStream_t bs : B.streams) HIPCHK(hipStreamWaitEvent(bs, B.fork_ev, 0));
-  return SG_OK;
+
+// ---- streaming stages of a batch -------------------------------------------
+
+long long variant_key(const Geometry &g, int stencil, const Channel *ch) {
+  const bool two = ch[(g.J - 1) * 2 + 1].active != 0;
+  return ((long long)g.d * 1000 + g.TS) * 4 + stencil * 2 + (two ? 1 : 0);
 }
-sg_status join(BranchSet &B, hipStream_t s) {
-  for (size_t k = 0; k < B.streams.size(); ++k) {
-    HIPCHK(hipEventRecord(B.join_ev[k], B.streams[k]));
-    HIPCHK(hipStreamWaitEvent(s, B.join_ev[k], 0));
+long long restrict_blocks(const Geometry &g) {
+  if (g.d == 2 && g.TS == 16) {
+    const long long ng = (g.ntile + 1) / 2;
+    return ng * ng * g.nchunk;
+  }
+  return (long long)(g.d == 2 ? g.ntile * g.ntile : g.ntile) * g.nchunk;
+}
+long long prolong_blocks(const Geometry &g) {
+  if (g.d == 2 && g.TS == 16) return (long long)((g.ntile + 3) / 4) * g.ntile * g.nchunk;
+  return (long long)(g.d == 2 ? g.ntile * g.ntile : g.ntile) * g.nchunk;
+}
+
+// problem i's restriction of pass P (X: the argument's own input, or null
+// when a per-call slot supplies it), its reduction and coarse levels
+void add_restriction(sg_batch *b, int i, const Scratch &ws, const Pass &P, const double *X,
+                     int stencil, ManyStage<RestrictArgs> &R, ManyStage<ReduceArgs> &Red,
+                     ManyStage<CoarseArgs> &Py, ManyStage<ReduceArgs> &Cr) {
+  const sg_problem *p = b->probs[i];
+  const Geometry &g = P.geo;
+  const RestrictArgs ra = make_restrict_args(p, ws, P, X, stencil);
+  R.add(variant_key(g, stencil, ra.ch), ra, restrict_blocks(g), i, g.chunk);
+  if (P.n_red)
+    Red.add(g.d * 1000 + g.TS, ReduceArgs{g, P.d_ch, ws.part, P.d_red, P.n_red, P.tot_red},
+            (P.tot_red + 255) / 256, i);
+  if (g.A0 > 1 && P.n_crs) {
+    Py.add(g.d, CoarseArgs{g, nullptr, ws.cpart, ws.SL}, g.ntf, i);
+    Cr.add(g.d, ReduceArgs{g, P.d_ch, ws.SL, P.d_crs, P.n_crs, P.tot_crs},
+           (P.tot_crs + 255) / 256, i);
+  }
+}
+
+// problem i's prolongation of pass P (base / out: the argument's own, or
+// null when a per-call slot supplies them) and its coarse levels
+void add_prolongation(sg_batch *b, int i, const Pass &P, const double *base, double *out,
+                      int stencil, double *cpro, ManyStage<CoarseArgs> &Pc,
+                      ManyStage<ProlongArgs> &Pr) {
+  const sg_problem *p = b->probs[i];
+  const Geometry &g = P.geo;
+  const ProlongArgs pa = make_prolong_args(p, P, base, out, 0, stencil, cpro);
+  if (pass_has_coarse(P)) Pc.add(g.d, CoarseArgs{g, P.d_ch, nullptr, cpro}, g.ntf, i);
+  Pr.add(variant_key(g, stencil, pa.ch), pa, prolong_blocks(g), i, g.chunk);
+}
+
+StencilArgs stencil_args(const sg_problem *p, int mode, const double *v, const double *u,
+                         double *mv, double *ku, const double *gsum) {
+  StencilArgs a{};
+  a.N = p->N;
+  a.mode = mode;
+  a.ce = p->d_ce;
+  a.hx = p->len[0] / p->N;
+  a.hy = p->len[1] / p->N;
+  a.v = v;
+  a.u = u;
+  a.mv = mv;
+  a.ku = ku;
+  a.gsum = gsum;
+  return a;
+}
+
+template <class A>
+sg_status upload_stage(sg_batch *b, ManyStage<A> &S) {
+  sg_status st;
+  S.order();
+  for (auto &G : S.groups) {
+    std::vector<int> first = G.first;
+    first.push_back(G.blocks);
+    if ((st = bupload(b, G.args, &G.d_args)) || (st = bupload(b, first, &G.d_first)) ||
+        (st = bupload(b, G.nblk, &G.d_nblk)) || (st = bupload(b, G.prob, &G.d_prob)))
+      return st;
   }
   return SG_OK;
 }
 
-sg_status make_branches(BranchSet &B, int ns) {
-  for (int i = 0; i < ns; ++i) {
-    hipStream_t bs = nullptr;
-    if (hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(SG_EDEVICE, "hipStreamCreateWithFlags failed");
-    }
-    B.streams.push_back(bs);
-    hipEvent_t e = nullptr;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(SG_EDEVICE, "hipEventCreateWithFlags failed");
-    }
-    B.join_ev.push_back(e);
+sg_status build_stages(sg_batch *b) {
+  const int n = (int)b->probs.size();
+  b->f_sten.s0 = kSlotV0;  // M v0 and K u0 into the field scratch
+  b->f_sten.s1 = kSlotU0;
+  b->f_lr.s0 = kSlotF;
+  b->f_pr.s0 = kSlotU0;    // base u0, out U
+  b->f_pr.s1 = kSlotU;
+  b->a_r.s0 = kSlotG;
+  b->a_pd.s1 = kSlotDF;
+  b->a_sten.s2 = kSlotDV0;  // mv -> dv0, ku -> du0
+  b->a_sten.s3 = kSlotDU0;
+  for (int i = 0; i < n; ++i) {
+    sg_problem *p = b->probs[i];
+    const long long nblk = (p->nsp_fine + 255) / 256;
+    b->f_sten.add(p->d, stencil_args(p, 0, nullptr, nullptr, p->ws.fine2,
+                                      p->ws.fine2 + p->nsp_fine, nullptr), nblk, i);
+    add_restriction(b, i, p->ws, p->fieldr, p->ws.fine2, 0, b->f_fr, b->f_fred, b->f_fpy,
+                    b->f_fcr);
+    add_restriction(b, i, p->ws, p->load, nullptr, 1, b->f_lr, b->f_lred, b->f_lpy, b->f_lcr);
+    add_prolongation(b, i, p->prol, nullptr, nullptr, 0, p->ws.Cpro, b->f_pc, b->f_pr);
+    add_restriction(b, i, p->wsa, p->adjr, nullptr, 0, b->a_r, b->a_red, b->a_py, b->a_cr);
+    add_prolongation(b, i, p->adjp, nullptr, nullptr, 1, p->wsa.Cpro, b->a_pcd, b->a_pd);
+    add_prolongation(b, i, p->fieldp, nullptr, p->wsa.fine2, 0, p->wsa.Cpro, b->a_pcf, b->a_pf);
+    b->a_sten.add(p->d, stencil_args(p, 1, p->wsa.fine2, p->wsa.fine2 + p->nsp_fine, nullptr,
+                                      nullptr, p->gsum), nblk, i);
   }
-  if (hipEventCreateWithFlags(&B.fork_ev, hipEventDisableTiming) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(SG_EDEVICE, "hipEventCreateWithFlags failed");
+  sg_status st;
+  if ((st = upload_stage(b, b->f_sten)) || (st = upload_stage(b, b->f_fr)) ||
+      (st = upload_stage(b, b->f_lr)) || (st = upload_stage(b, b->f_fred)) ||
+      (st = upload_stage(b, b->f_lred)) || (st = upload_stage(b, b->f_fcr)) ||
+      (st = upload_stage(b, b->f_lcr)) || (st = upload_stage(b, b->f_fpy)) ||
+      (st = upload_stage(b, b->f_lpy)) || (st = upload_stage(b, b->f_pc)) ||
+      (st = upload_stage(b, b->f_pr)) || (st = upload_stage(b, b->a_r)) ||
+      (st = upload_stage(b, b->a_red)) || (st = upload_stage(b, b->a_cr)) ||
+      (st = upload_stage(b, b->a_py)) || (st = upload_stage(b, b->a_pcd)) ||
+      (st = upload_stage(b, b->a_pcf)) || (st = upload_stage(b, b->a_pd)) ||
+      (st = upload_stage(b, b->a_pf)) || (st = upload_stage(b, b->a_sten)))
+    return st;
+  return SG_OK;
+}
+
+template <class A>
+ManyLaunch many_launch(const sg_batch *b, const ManyStage<A> &S,
+                       const typename ManyStage<A>::Group &G, const double *const *tab) {
+  ManyLaunch M{};
+  M.args = G.d_args;
+  M.first = G.d_first;
+  M.nblk = G.d_nblk;
+  M.prob = G.d_prob;
+  M.ptr = tab;
+  M.n = (int)G.args.size();
+  M.nprob = (int)b->probs.size();
+  M.s0 = S.s0;
+  M.s1 = S.s1;
+  M.s2 = S.s2;
+  M.s3 = S.s3;
+  return M;
+}
+
+sg_status run_stage(const sg_batch *b, const ManyStage<RestrictArgs> &S,
+                    const double *const *tab, hipStream_t s) {
+  for (const auto &G : S.groups)
+    HIPCHK(launch_restrict_many(G.args[0], many_launch(b, S, G, tab), G.blocks, s));
+  return SG_OK;
+}
+sg_status run_stage(const sg_batch *b, const ManyStage<ProlongArgs> &S,
+                    const double *const *tab, hipStream_t s) {
+  for (const auto &G : S.groups)
+    HIPCHK(launch_prolong_many(G.args[0], many_launch(b, S, G, tab), G.blocks, s));
+  return SG_OK;
+}
+sg_status run_stage(const sg_batch *b, const ManyStage<StencilArgs> &S,
+                    const double *const *tab, hipStream_t s) {
+  for (const auto &G : S.groups)
+    HIPCHK(launch_fine_stencils_many((int)G.key, many_launch(b, S, G, tab), G.blocks, s));
+  return SG_OK;
+}
+// reductions of partial blocks (coarse = false) or coarse restrictions
+sg_status run_stage(const sg_batch *b, const ManyStage<ReduceArgs> &S, bool coarse,
+                    const double *const *tab, hipStream_t s) {
+  for (const auto &G : S.groups) {
+    const ManyLaunch M = many_launch(b, S, G, tab);
+    if (coarse)
+      HIPCHK(launch_coarse_restrict_many(G.args[0].g.d, M, G.blocks, s));
+    else
+      HIPCHK(launch_reduce_many(G.args[0].g, M, G.blocks, s));
+  }
+  return SG_OK;
+}
+// coarse pyramids (prolong = false) or coarse prolongations
+sg_status run_stage(const sg_batch *b, const ManyStage<CoarseArgs> &S, bool prolong,
+                    const double *const *tab, hipStream_t s) {
+  for (const auto &G : S.groups) {
+    const ManyLaunch M = many_launch(b, S, G, tab);
+    if (prolong)
+      HIPCHK(launch_prolong_coarse_many(G.args[0].g.d, M, G.blocks, s));
+    else
+      HIPCHK(launch_coarse_pyramid_many(G.args[0].g.d, M, G.blocks, s));
   }
   return SG_OK;
 }
 
-void free_branches(BranchSet &B) {
-  if (B.fork_ev) (void)hipEventDestroy(B.fork_ev);
-  for (hipEvent_t e : B.join_ev) (void)hipEventDestroy(e);
-  for (hipStream_t s : B.streams) (void)hipStreamDestroy(s);
+// per-call pointers of an eager call into the device table (stream ordered;
+// the pinned host copy is rewritten only after the previous upload read it)
+sg_status upload_table(sg_batch *b, const double *const *const (&slot)[kBatchSlots],
+                       hipStream_t s) {
+  const int n = (int)b->probs.size();
+  HIPCHK(hipEventSynchronize(b->tab_ev));
+  for (int k = 0; k < kBatchSlots; ++k)
+    for (int i = 0; i < n; ++i) b->h_tab[(size_t)k * n + i] = slot[k] ? slot[k][i] : nullptr;
+  HIPCHK(hipMemcpyAsync(b->d_tab, b->h_tab, sizeof(double *) * kBatchSlots * n,
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(b->tab_ev, s));
+  return SG_OK;
 }
 
+// Every stage of a direction is one launch over all problems (per kernel
+// variant present); the streaming stages of a problem keep their order
+// (its scratch is reused from one to the next).
 sg_status batch_forward(sg_batch *b, const double *const *f, const double *const *u0,
-                        const double *const *v0, double *const *U, hipStream_t s) {
+                        const double *const *v0, double *const *U, hipStream_t s,
+                        const double *const *tab) {
   const int n = (int)b->probs.size();
   if (!f || !u0 || !v0 || !U) return fail(SG_EINVAL, "NULL argument array");
   for (int i = 0; i < n; ++i) {
@@ -2267,15 +2508,21 @@ sg_status batch_forward(sg_batch *b, const double *const *f, const double *const
     if (U[i] == f[i]) return fail(SG_EINVAL, "U must not alias f");
   }
   sg_status st;
-  if ((st = bmark(b, 0, s))) return st;
-  if ((st = fork(b->fb, s))) return st;
-  for (int i = 0; i < n; ++i) {
-    sg_problem *p = b->probs[i];
-    hipStream_t bs = b->fb.streams[i % b->fb.streams.size()];
-    if ((st = forward_fields(p, p->ws, u0[i], v0[i], bs))) return st;
-    if ((st = run_restrict(p, p->ws, p->load, f[i], 1, bs))) return st;
+  if (tab == nullptr) {
+    const double *const *const slot[kBatchSlots] = {f, u0, v0, U, nullptr, nullptr, nullptr,
+                                                    nullptr};
+    if ((st = upload_table(b, slot, s))) return st;
+    tab = b->d_tab;
   }
-  if ((st = join(b->fb, s))) return st;
+  if ((st = bmark(b, 0, s))) return st;
+  if ((st = run_stage(b, b->f_sten, tab, s)) || (st = run_stage(b, b->f_fr, tab, s)) ||
+      (st = run_stage(b, b->f_fred, false, tab, s)) ||
+      (st = run_stage(b, b->f_fpy, false, tab, s)) ||
+      (st = run_stage(b, b->f_fcr, true, tab, s)) || (st = run_stage(b, b->f_lr, tab, s)) ||
+      (st = run_stage(b, b->f_lred, false, tab, s)) ||
+      (st = run_stage(b, b->f_lpy, false, tab, s)) ||
+      (st = run_stage(b, b->f_lcr, true, tab, s)))
+    return st;
   HIPCHK(launch_post_load(b->cload.d, b->cload.n, b->cload.total, s));
   if ((st = bmark(b, 1, s))) return st;
   if ((st = run_fdm(b->ffwd, s))) return st;
@@ -2286,31 +2533,30 @@ sg_status batch_forward(sg_batch *b, const double *const *f, const double *const
   HIPCHK(launch_gemm(b->giy.d, b->giy.n, b->giy.tiles, b->giy.fold, s));
   HIPCHK(launch_gemm(b->gix.d, b->gix.n, b->gix.tiles, b->gix.fold, s));
   if ((st = bmark(b, 2, s))) return st;
-  if ((st = fork(b->fb, s))) return st;
-  for (int i = 0; i < n; ++i) {
-    sg_problem *p = b->probs[i];
-    hipStream_t bs = b->fb.streams[i % b->fb.streams.size()];
-    if ((st = run_prolong(p, p->prol, u0[i], U[i], 0, 0, bs, -1, p->ws.Cpro))) return st;
-  }
-  if ((st = join(b->fb, s))) return st;
+  if ((st = run_stage(b, b->f_pc, true, tab, s)) || (st = run_stage(b, b->f_pr, tab, s)))
+    return st;
   return bmark(b, 3, s);
 }
 
 sg_status batch_adjoint(sg_batch *b, const double *const *g, double *const *df,
-                        double *const *du0, double *const *dv0, hipStream_t s) {
+                        double *const *du0, double *const *dv0, hipStream_t s,
+                        const double *const *tab) {
   const int n = (int)b->probs.size();
   if (!g) return fail(SG_EINVAL, "NULL cotangent array");
   for (int i = 0; i < n; ++i)
     if (!g[i]) return fail(SG_EINVAL, "NULL cotangent");
   sg_status st;
-  if ((st = bmark(b, 4, s))) return st;
-  if ((st = fork(b->ab, s))) return st;
-  for (int i = 0; i < n; ++i) {
-    sg_problem *p = b->probs[i];
-    hipStream_t bs = b->ab.streams[i % b->ab.streams.size()];
-    if ((st = run_restrict(p, p->wsa, p->adjr, g[i], 0, bs))) return st;
+  if (tab == nullptr) {
+    const double *const *const slot[kBatchSlots] = {
+        nullptr, nullptr, nullptr, nullptr, g, (const double *const *)df,
+        (const double *const *)du0, (const double *const *)dv0};
+    if ((st = upload_table(b, slot, s))) return st;
+    tab = b->d_tab;
   }
-  if ((st = join(b->ab, s))) return st;
+  if ((st = bmark(b, 4, s))) return st;
+  if ((st = run_stage(b, b->a_r, tab, s)) || (st = run_stage(b, b->a_red, false, tab, s)) ||
+      (st = run_stage(b, b->a_py, false, tab, s)) || (st = run_stage(b, b->a_cr, true, tab, s)))
+    return st;
   if ((st = bmark(b, 5, s))) return st;
   if ((st = run_fdm(b->fadj, s))) return st;
   HIPCHK(launch_block_solve(b->badj.d, b->badj.n, s));
@@ -2324,22 +2570,14 @@ sg_status batch_adjoint(sg_batch *b, const double *const *g, double *const *df,
   bool fields = false;
   for (int i = 0; i < n; ++i) fields = fields || (du0 && du0[i]) || (dv0 && dv0[i]);
   if (fields) HIPCHK(launch_adjoint_fields(b->d_lev, b->nlev, b->lev_total, s));
-  if ((st = fork(b->ab, s))) return st;
-  for (int i = 0; i < n; ++i) {
-    sg_problem *p = b->probs[i];
-    hipStream_t bs = b->ab.streams[i % b->ab.streams.size()];
-    if (df && df[i] && (st = run_prolong(p, p->adjp, nullptr, df[i], 0, 1, bs, -1, p->wsa.Cpro)))
-      return st;
-    double *du = du0 ? du0[i] : nullptr, *dv = dv0 ? dv0[i] : nullptr;
-    if (du || dv) {
-      if ((st = run_prolong(p, p->fieldp, nullptr, p->wsa.fine2, 0, 0, bs, -1, p->wsa.Cpro)))
-        return st;
-      const double hx = p->len[0] / p->N, hy = p->len[1] / p->N;
-      HIPCHK(launch_fine_stencils(p->d, p->N, p->d_ce, hx, hy, p->wsa.fine2,
-                                  p->wsa.fine2 + p->nsp_fine, dv, du, p->gsum, 1, bs));
-    }
-  }
-  if ((st = join(b->ab, s))) return st;
+  bool any_df = false;
+  for (int i = 0; i < n; ++i) any_df = any_df || (df && df[i]);
+  if (any_df && ((st = run_stage(b, b->a_pcd, true, tab, s)) ||
+                 (st = run_stage(b, b->a_pd, tab, s))))
+    return st;
+  if (fields && ((st = run_stage(b, b->a_pcf, true, tab, s)) ||
+                 (st = run_stage(b, b->a_pf, tab, s)) || (st = run_stage(b, b->a_sten, tab, s))))
+    return st;
   return bmark(b, 7, s);
 }
 
@@ -2363,8 +2601,9 @@ sg_status sg_batch_destroy(sg_batch *b) {
   if (!b) return SG_OK;
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  free_branches(b->fb);
-  free_branches(b->ab);
+  if (b->tab_ev) (void)hipEventSynchronize(b->tab_ev);
+  if (b->tab_ev) (void)hipEventDestroy(b->tab_ev);
+  if (b->h_tab) (void)hipHostFree(b->h_tab);
   if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
   if (b->join_ev) (void)hipEventDestroy(b->join_ev);
   if (b->aux) (void)hipStreamDestroy(b->aux);
@@ -2395,20 +2634,23 @@ sg_status sg_batch_create(int n, sg_problem *const *problems, sg_batch **out) {
     g_last_error = msg;
     return st;
   };
-  // a few branch streams per direction (default priority); problems are
-  // dealt round-robin; one more stream carries the adjoint in a graph
-  const int ns = std::min(n, 8);
-  {
-    sg_status bst;
-    if ((bst = make_branches(b->fb, ns)) || (bst = make_branches(b->ab, ns))) return bail(bst);
-    if (hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming) != hipSuccess) {
-      (void)hipGetLastError();
-      return bail(fail(SG_EDEVICE, "stream / event creation failed"));
-    }
+  // one more stream (default priority) would carry the adjoint in a graph
+  if (hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->tab_ev, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc(&b->h_tab, sizeof(double *) * kBatchSlots * n) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(SG_EDEVICE, "stream / event / pinned buffer creation failed"));
   }
+  HIPCHK(hipEventRecord(b->tab_ev, nullptr));
   sg_status st;
+  {
+    const std::vector<const double *> none((size_t)kBatchSlots * n, nullptr);
+    if ((st = bupload(b, none, &b->d_tab)) || (st = bupload(b, none, &b->d_tab_graph)))
+      return bail(st);
+  }
+  if ((st = build_stages(b))) return bail(st);
   if ((st = merge_gemm(b, &sg_problem::gx, b->gx)) || (st = merge_gemm(b, &sg_problem::gy, b->gy)) ||
       (st = merge_gemm(b, &sg_problem::giy, b->giy)) ||
       (st = merge_gemm(b, &sg_problem::gix, b->gix)) ||
@@ -2480,14 +2722,14 @@ sg_status sg_batch_solve(sg_batch *b, const double *const *f, const double *cons
                          const double *const *v0, double *const *U, hipStream_t stream) {
   if (!b) return fail(SG_EINVAL, "NULL batch");
   EventsOff off(b);
-  return batch_forward(b, f, u0, v0, U, stream);
+  return batch_forward(b, f, u0, v0, U, stream, nullptr);
 }
 
 sg_status sg_batch_adjoint(sg_batch *b, const double *const *g, double *const *df,
                            double *const *du0, double *const *dv0, hipStream_t stream) {
   if (!b) return fail(SG_EINVAL, "NULL batch");
   EventsOff off(b);
-  return batch_adjoint(b, g, df, du0, dv0, stream);
+  return batch_adjoint(b, g, df, du0, dv0, stream, nullptr);
 }
 
 sg_status sg_batch_capture(sg_batch *b, const double *const *f, const double *const *u0,
@@ -2512,6 +2754,19 @@ sg_status sg_batch_capture(sg_batch *b, const double *const *f, const double *co
     std::vector<hipEvent_t> &v;
     ~Restore() { v.swap(b->ev); }
   } restore{b, bev};
+  {
+    // the graph's own pointer table, written before capture
+    const int nb = (int)b->probs.size();
+    const double *const *const slot[kBatchSlots] = {
+        f, u0, v0, (const double *const *)U, g, (const double *const *)df,
+        (const double *const *)du0, (const double *const *)dv0};
+    std::vector<const double *> tab((size_t)kBatchSlots * nb, nullptr);
+    for (int k = 0; k < kBatchSlots; ++k)
+      for (int i = 0; i < nb; ++i) tab[(size_t)k * nb + i] = slot[k] ? slot[k][i] : nullptr;
+    HIPCHK(hipDeviceSynchronize());  // no replay may read the table while it changes
+    HIPCHK(hipMemcpy(b->d_tab_graph, tab.data(), sizeof(double *) * tab.size(),
+                     hipMemcpyHostToDevice));
+  }
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   // The adjoint is independent of the forward for a given cotangent and has
   // its own buffers, so it could run on its own branch of the graph; that
@@ -2534,9 +2789,9 @@ sg_status sg_batch_capture(sg_batch *b, const double *const *f, const double *co
     fe = hipEventRecord(b->fork_ev, s);
     if (fe == hipSuccess) fe = hipStreamWaitEvent(b->aux, b->fork_ev, 0);
   }
-  if (fe == hipSuccess) st = batch_forward(b, f, u0, v0, U, s);
+  if (fe == hipSuccess) st = batch_forward(b, f, u0, v0, U, s, b->d_tab_graph);
   if (fe == hipSuccess && st == SG_OK && g != nullptr) {
-    st = batch_adjoint(b, g, df, du0, dv0, as);
+    st = batch_adjoint(b, g, df, du0, dv0, as, b->d_tab_graph);
     if (st == SG_OK && par) {
       fe = hipEventRecord(b->join_ev, b->aux);
       if (fe == hipSuccess) fe = hipStreamWaitEvent(s, b->join_ev, 0);

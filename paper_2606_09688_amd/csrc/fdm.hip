@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "gmem.hpp"
 
 namespace sg {
 
@@ -156,7 +157,7 @@ __device__ __forceinline__ double *fac_at(const FdmDesc &D, int plane, int u, in
 __global__ void k_fdm_in(const FdmDesc *__restrict__ ds, int nd, long long total) {
   const long long g = gid64();
   if (g >= total) return;
-  const FdmDesc &D = ds[find_fdm(ds, nd, g, kNode)];
+  const FdmDesc &D = cref(ds, find_fdm(ds, nd, g, kNode));
   const long long node = g - D.node0, nn = (long long)D.n * D.n;
   const int nq = D.nq, nu = D.nu;
   cx acc[kFdmMaxNu];
@@ -178,7 +179,7 @@ __global__ void k_fdm_in(const FdmDesc *__restrict__ ds, int nd, long long total
 __global__ void k_fdm_out(const FdmDesc *__restrict__ ds, int nd, long long total) {
   const long long g = gid64();
   if (g >= total) return;
-  const FdmDesc &D = ds[find_fdm(ds, nd, g, kNode)];
+  const FdmDesc &D = cref(ds, find_fdm(ds, nd, g, kNode));
   const long long node = g - D.node0, nn = (long long)D.n * D.n;
   const int y = (int)(node / D.n), x = (int)(node - (long long)y * D.n);
   const bool iface = (y + 1) % (D.m + 1) == 0;
@@ -217,7 +218,7 @@ __global__ void __launch_bounds__(64) k_fdm_tri(const FdmDesc *__restrict__ ds, 
                                                 long long total, int correction) {
   const long long g = gid64();
   if (g >= total) return;
-  const FdmDesc &D = ds[find_fdm(ds, nd, g, kTri)];
+  const FdmDesc &D = cref(ds, find_fdm(ds, nd, g, kTri));
   const int t = (int)(g - D.tri0);
   const int l = t % D.m, k = (t / D.m) % D.ns, u = t / (D.m * D.ns);
   const cx lam = cld(D.lam + 2 * u);
@@ -288,7 +289,7 @@ __global__ void __launch_bounds__(64) k_fdm_tri(const FdmDesc *__restrict__ ds, 
 __global__ void k_fdm_edge(const FdmDesc *__restrict__ ds, int nd, long long total) {
   const long long g = gid64();
   if (g >= total) return;
-  const FdmDesc &D = ds[find_fdm(ds, nd, g, kEdge)];
+  const FdmDesc &D = cref(ds, find_fdm(ds, nd, g, kEdge));
   const int t = (int)(g - D.edge0);
   const int x = t % D.n, k = (t / D.n) % D.ns, u = t / (D.n * D.ns);
   const double *Y = D.Y + 2 * (((long long)u * D.n + (long long)k * (D.m + 1)) * D.n + x);
@@ -309,7 +310,7 @@ __global__ void k_fdm_edge(const FdmDesc *__restrict__ ds, int nd, long long tot
 __global__ void k_fdm_iface(const FdmDesc *__restrict__ ds, int nd, long long total) {
   const long long g = gid64();
   if (g >= total) return;
-  const FdmDesc &D = ds[find_fdm(ds, nd, g, kIf)];
+  const FdmDesc &D = cref(ds, find_fdm(ds, nd, g, kIf));
   const int t = (int)(g - D.if0);
   const int x = t % D.n, r = (t / D.n) % D.ni + 1, u = t / (D.n * D.ni);
   const cx lam = cld(D.lam + 2 * u);
@@ -328,7 +329,7 @@ __global__ void __launch_bounds__(256) k_fdm_gemv(const FdmDesc *__restrict__ ds
   const long long w = gid64() >> 6;
   const int lane = threadIdx.x & 63;
   if (w >= total) return;
-  const FdmDesc &D = ds[find_fdm(ds, nd, w, kGemv)];
+  const FdmDesc &D = cref(ds, find_fdm(ds, nd, w, kGemv));
   const long long rw = w - D.gemv0;
   const long long NG = (long long)D.ni * D.n;
   const long long u = rw / NG, rho = rw - u * NG;

@@ -25,6 +25,7 @@
 #include <mutex>
 
 #include "kernels.hpp"
+#include "gmem.hpp"
 #include "tables.hpp"
 
 namespace sg {
@@ -55,6 +56,15 @@ __device__ __forceinline__ long long gid64() {
   return (long long)blockIdx.x * blockDim.x + threadIdx.x;
 }
 
+// linear block index of a 2-D launch grid
+__device__ __forceinline__ int block_lin() { return blockIdx.y * gridDim.x + blockIdx.x; }
+
+// first global thread of the calling wave, given its block's first thread
+// (wave-uniform)
+__device__ __forceinline__ long long wave_gid0(long long block_first) {
+  return block_first + __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u));
+}
+
 // --------------------------------------------------------- restriction -----
 
 // XCD-aware block order for the streaming kernels.  Workgroups are dealt
@@ -62,9 +72,11 @@ __device__ __forceinline__ long long gid64() {
 // of hardware block b is chosen so that every XCD holds a contiguous run of
 // tiles of one time chunk, and neighbouring tiles - which read each other's
 // halo rows - share an L2.
-__device__ __forceinline__ void stream_block(int ntileD, int nchunk, int &tile, int &chunk) {
+// lin: the block's linear index in its launch (or, in a launch of many
+// problems, in its problem's range of blocks, which starts at a multiple of 8)
+__device__ __forceinline__ void stream_block(int lin, int ntileD, int nchunk, int &tile,
+                                             int &chunk) {
   const int total = ntileD * nchunk;
-  int lin = blockIdx.y * gridDim.x + blockIdx.x;
   if (total % 8 == 0) lin = (lin & 7) * (total >> 3) + (lin >> 3);
   chunk = lin / ntileD;
   tile = lin - chunk * ntileD;
@@ -132,7 +144,8 @@ __device__ __forceinline__ double full_weight(const double *src, int PN, int jx,
 #define SG_WPE 1
 #endif
 template <int D, int TS, int TB, int NT, int STENCIL, int NC0>
-__global__ void __launch_bounds__(NT, SG_WPE) k_restrict(const RestrictArgs A) {
+__device__ __forceinline__ void restrict_body(const RestrictArgs &A, const double *__restrict__ X,
+                                              int lin) {
   using SH = Shape<D, TS, 0>;
   using PD = Pad<D, TS, 0>;
   constexpr int LTS = SH::LTS;
@@ -161,7 +174,7 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_restrict(const RestrictArgs A) {
   const int tid = threadIdx.x;
   const int ntileD = (D == 2) ? g.ntile * g.ntile : g.ntile;
   int tile, chunk;
-  stream_block(ntileD, g.nchunk, tile, chunk);
+  stream_block(lin, ntileD, g.nchunk, tile, chunk);
   const int tx = tile % g.ntile;
   const int ty = (D == 2) ? tile / g.ntile : 0;
   const int n0 = chunk * g.chunk;
@@ -176,7 +189,7 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_restrict(const RestrictArgs A) {
     int q = 0;
     if (r <= R) {
       const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
-      if (C.active) q = C.q0[n0];
+      if (C.active) q = gld(C.q0, n0);
     }
     s_qlo[tid] = q;
   }
@@ -240,7 +253,7 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_restrict(const RestrictArgs A) {
   auto fetch = [&](int nb) {
 #pragma unroll
     for (int e = 0; e < PF; ++e)
-      pin[e] = A.X[in_ok(e, nb) ? (long long)(nb + in_slab(e)) * nsp + in_pos(e) : 0];
+      pin[e] = X[in_ok(e, nb) ? (long long)(nb + in_slab(e)) * nsp + in_pos(e) : 0];
     const int nc = tap_ok(nb) ? nb - 1 + my_s : 0;
     pq = tq0[nc];
     pw0 = tw[3 * nc];
@@ -390,6 +403,11 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_restrict(const RestrictArgs A) {
         if (ql + o < C.nq) A.part[part_at(C, li, r, ql + o, own[i].j)] = racc[i][k][o];
     }
   }
+}
+
+template <int D, int TS, int TB, int NT, int STENCIL, int NC0>
+__global__ void __launch_bounds__(NT, SG_WPE) k_restrict(const RestrictArgs A) {
+  restrict_body<D, TS, TB, NT, STENCIL, NC0>(A, A.X, block_lin());
 }
 
 // Read-only tables (tap offsets and weights) through the scalar cache: a load
@@ -553,7 +571,8 @@ struct Slot16 {
 #define SG_WPEW 3
 #endif
 template <int STENCIL, int NC0>
-__global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs A) {
+__device__ __forceinline__ void restrict_w_body(const RestrictArgs &A, const double *__restrict__ X,
+                                                int lin) {
   constexpr int TS = 16, LTS = 4, NIN = TS + 2, INSZ = NIN * NIN, NP = 24;
   // loads in flight per lane: the input window (mass stencil) or the block
   constexpr int PF = STENCIL ? (INSZ + 63) / 64 : 4;
@@ -571,7 +590,7 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
   const Geometry g = A.g;
   const int nt = g.ntile, ng = (nt + 1) >> 1;
   int grp, chunk;
-  stream_block(ng * ng, g.nchunk, grp, chunk);
+  stream_block(lin, ng * ng, g.nchunk, grp, chunk);
   const int tx = 2 * (grp % ng) + (wave & 1), ty = 2 * (grp / ng) + (wave >> 1);
   if (tx >= nt || ty >= nt) return;  // no workgroup barrier below
   const int tile = ty * nt + tx, ntileD = nt * nt;
@@ -616,7 +635,7 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
   // by zeros when staged (a load in a divergent branch would serialise them)
   auto fetch = [&](int n) {
 #pragma unroll
-    for (int e = 0; e < PF; ++e) pin[e] = A.X[pos[e] >= 0 ? (long long)n * nsp + pos[e] : 0];
+    for (int e = 0; e < PF; ++e) pin[e] = X[pos[e] >= 0 ? (long long)n * nsp + pos[e] : 0];
   };
 
   // fine-level accumulators; a second finest channel (the adjoint's time sum
@@ -862,6 +881,11 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
   }
 }
 
+template <int STENCIL, int NC0>
+__global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs A) {
+  restrict_w_body<STENCIL, NC0>(A, A.X, block_lin());
+}
+
 // Index of the last of n items (ascending .start) whose start is <= gid.
 // A binary search on the wave's first thread (wave-uniform: scalar loads,
 // whose upper levels every wave shares in the scalar cache) finds the item
@@ -869,9 +893,7 @@ __global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w(const RestrictArgs 
 // its wave.  Batches of many problems hold thousands of items, so a scan
 // over the starts would cost each wave far more than its own work.
 template <class T>
-__device__ __forceinline__ int find_item(const T *items, int n, long long gid) {
-  const long long gw = (long long)blockIdx.x * blockDim.x +
-                       __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u));
+__device__ __forceinline__ int find_item(const T *items, int n, long long gid, long long gw) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -898,13 +920,12 @@ __device__ __forceinline__ void tile_range(int TS, int r, int P, int ntile, int 
 }
 
 template <int D, int TS>
-__global__ void k_reduce(const Geometry g, const Channel *__restrict__ ch,
-                         const double *__restrict__ part,
-                         const WorkItem *__restrict__ items, int nitems,
-                         long long total) {
+__device__ __forceinline__ void reduce_body(const Geometry &g, const Channel *__restrict__ ch,
+                                            const double *__restrict__ part,
+                                            const WorkItem *__restrict__ items, int nitems,
+                                            long long total, long long gid, long long gw) {
   using SH = Shape<D, TS, 0>;
-  const long long gid = gid64();
-  const int it = find_item(items, nitems, gid);
+  const int it = find_item(items, nitems, gid, gw);
   if (gid >= total) return;
   const Channel &C = ch[items[it].ch];
   const long long loc = gid - items[it].start;
@@ -925,7 +946,7 @@ __global__ void k_reduce(const Geometry g, const Channel *__restrict__ ch,
   for (int c = 0; c < g.nchunk; ++c) {
     const int cn0 = c * g.chunk;
     const int cn1 = min(cn0 + g.chunk, g.ntf);
-    const int qlo = C.q0[cn0], qhi = C.q0[cn1 - 1] + 2;
+    const int qlo = gld(C.q0, cn0), qhi = gld(C.q0, cn1 - 1) + 2;
     if (q < qlo || q > qhi) continue;
     for (int ty = ty0; ty <= ty1; ++ty) {
       const int jy = (D == 2) ? Py - tile_lo(TS, ty, r, 0) : 0;
@@ -940,7 +961,16 @@ __global__ void k_reduce(const Geometry g, const Channel *__restrict__ ch,
       }
     }
   }
-  C.data[loc] = C.scale * acc;
+  gst(C.data, loc, C.scale * acc);
+}
+
+template <int D, int TS>
+__global__ void k_reduce(const Geometry g, const Channel *__restrict__ ch,
+                         const double *__restrict__ part,
+                         const WorkItem *__restrict__ items, int nitems,
+                         long long total) {
+  reduce_body<D, TS>(g, ch, part, items, nitems, total, gid64(),
+                     wave_gid0((long long)blockIdx.x * blockDim.x));
 }
 
 // first index n with q0[n] >= v (q0 nondecreasing)
@@ -948,7 +978,7 @@ __device__ __forceinline__ int lower_bound_q(const int *q0, int n, int v) {
   int lo = 0, hi = n;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (q0[mid] < v) lo = mid + 1; else hi = mid;
+    if (gld(q0, mid) < v) lo = mid + 1; else hi = mid;
   }
   return lo;
 }
@@ -968,12 +998,11 @@ __host__ __device__ inline long long coarse_off(int d, int a) {
 // and t = P per axis, whose top in-tile level has two nodes per axis), then
 // full weighting down to level 1.
 template <int D>
-__global__ void __launch_bounds__(256) k_coarse_pyramid(const Geometry g,
-                                                        const double *__restrict__ cp,
-                                                        double *__restrict__ SL) {
+__device__ __forceinline__ void coarse_pyramid_body(const Geometry &g,
+                                                    const double *__restrict__ cp,
+                                                    double *__restrict__ SL, int n) {
   constexpr int MAXN = kCoarseMax;  // doubles per ping-pong level (checked by the plan)
   __shared__ double s_a[MAXN], s_b[MAXN];
-  const int n = blockIdx.x;
   const int A0 = g.A0;
   const int n0a = (1 << A0) - 1;
   const int nsp0 = (D == 2) ? n0a * n0a : n0a;
@@ -1020,15 +1049,23 @@ __global__ void __launch_bounds__(256) k_coarse_pyramid(const Geometry g,
   }
 }
 
+template <int D>
+__global__ void __launch_bounds__(256) k_coarse_pyramid(const Geometry g,
+                                                        const double *__restrict__ cp,
+                                                        double *__restrict__ SL) {
+  coarse_pyramid_body<D>(g, cp, SL, blockIdx.x);
+}
+
 // Channels of the levels a < A0: sum over the slabs that touch time node q
 // of the tap weight times the slab's level-a restriction.
 template <int D>
-__global__ void k_coarse_restrict(const Geometry g, const Channel *__restrict__ ch,
-                                  const double *__restrict__ SL,
-                                  const WorkItem *__restrict__ items, int nitems,
-                                  long long total) {
-  const long long gid = gid64();
-  const int it = find_item(items, nitems, gid);
+__device__ __forceinline__ void coarse_restrict_body(const Geometry &g,
+                                                     const Channel *__restrict__ ch,
+                                                     const double *__restrict__ SL,
+                                                     const WorkItem *__restrict__ items,
+                                                     int nitems, long long total, long long gid,
+                                                     long long gw) {
+  const int it = find_item(items, nitems, gid, gw);
   if (gid >= total) return;
   const Channel &C = ch[items[it].ch];
   const long long loc = gid - items[it].start;
@@ -1045,8 +1082,17 @@ __global__ void k_coarse_restrict(const Geometry g, const Channel *__restrict__ 
   double acc = 0.0;
 #pragma unroll 4
   for (int n = nlo; n < nhi; ++n)
-    acc += C.w[3 * n + (q - C.q0[n])] * SL[(long long)n * tot + off];
-  C.data[loc] = C.scale * acc;
+    acc += gld(C.w, 3 * n + (q - gld(C.q0, n))) * SL[(long long)n * tot + off];
+  gst(C.data, loc, C.scale * acc);
+}
+
+template <int D>
+__global__ void k_coarse_restrict(const Geometry g, const Channel *__restrict__ ch,
+                                  const double *__restrict__ SL,
+                                  const WorkItem *__restrict__ items, int nitems,
+                                  long long total) {
+  coarse_restrict_body<D>(g, ch, SL, items, nitems, total, gid64(),
+                          wave_gid0((long long)blockIdx.x * blockDim.x));
 }
 
 // ---------------------------------------------------------- prolongation ---
@@ -1059,14 +1105,13 @@ __global__ void k_coarse_restrict(const Geometry g, const Channel *__restrict__ 
 // values at slab n plus the interpolation of level a-1; level A0 only the
 // interpolation.
 template <int D>
-__global__ void __launch_bounds__(256) k_prolong_coarse(const Geometry g,
-                                                        const Channel *__restrict__ ch,
-                                                        double *__restrict__ Cout) {
+__device__ __forceinline__ void prolong_coarse_body(const Geometry &g,
+                                                    const Channel *__restrict__ ch,
+                                                    double *__restrict__ Cout, int n) {
   // level A0-1 has fewer than a quarter (a half in 1-D) of the level-A0
   // nodes, which the plan keeps within kCoarseMax
   constexpr int MAXN = kCoarseMax / (D == 2 ? 4 : 2);
   __shared__ double s_a[MAXN], s_b[MAXN];
-  const int n = blockIdx.x;
   const int A0 = g.A0;
   double *cur = s_a, *nxt = s_b;
   for (int a = 1; a <= A0; ++a) {
@@ -1096,12 +1141,12 @@ __global__ void __launch_bounds__(256) k_prolong_coarse(const Geometry g,
       for (int k = 0; k < 2; ++k) {
         const Channel &C = ch[(a - 1) * 2 + k];
         if (!C.active) continue;
-        const int q0n = C.q0[n];
+        const int q0n = gld(C.q0, n);
         double sv = 0.0;
         for (int kk = 0; kk < 3; ++kk) {
-          const double w = C.w[3 * n + kk];
+          const double w = gld(C.w, 3 * n + kk);
           if (w == 0.0) continue;  // (a window past the last time node)
-          sv += w * C.data[(long long)(q0n + kk) * nspa + i];
+          sv += w * gld(C.data, (long long)(q0n + kk) * nspa + i);
         }
         v += C.scale * sv;
       }
@@ -1114,9 +1159,17 @@ __global__ void __launch_bounds__(256) k_prolong_coarse(const Geometry g,
   }
 }
 
+template <int D>
+__global__ void __launch_bounds__(256) k_prolong_coarse(const Geometry g,
+                                                        const Channel *__restrict__ ch,
+                                                        double *__restrict__ Cout) {
+  prolong_coarse_body<D>(g, ch, Cout, blockIdx.x);
+}
+
 // NC0: number of finest-level channels (2 only for the u0/v0 field pass)
 template <int D, int TS, int TB, int NT, int MODE, int NC0>
-__global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
+__device__ __forceinline__ void prolong_body(const ProlongArgs &A, const double *__restrict__ base,
+                                             double *__restrict__ out, int lin) {
   using SH = Shape<D, TS, MODE>;
   constexpr int LTS = SH::LTS;
   constexpr int L0 = SH::size(0);
@@ -1141,7 +1194,7 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
   const Geometry g = A.g;
   const int tid = threadIdx.x;
   int tile, chunk;
-  stream_block((D == 2) ? g.ntile * g.ntile : g.ntile, g.nchunk, tile, chunk);
+  stream_block(lin, (D == 2) ? g.ntile * g.ntile : g.ntile, g.nchunk, tile, chunk);
   const int tx = tile % g.ntile;
   const int ty = (D == 2) ? tile / g.ntile : 0;
   const int n0 = chunk * g.chunk;
@@ -1191,7 +1244,7 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
     for (int k = 0; k < 2; ++k) {
       const Channel &C = A.ch[(g.J - r - 1) * 2 + k];
       if (!C.active) continue;
-      const int q = C.q0[n0];
+      const int q = gld(C.q0, n0);
       cq[i][k] = q;
 #pragma unroll
       for (int o = 0; o < 4; ++o) cw[i][k][o] = coef(C, q + o, coff[i]);
@@ -1221,10 +1274,10 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
   for (int e = 0; e < EPT0; ++e) {
     basev[e] = 0.0;
     const int p = tid + e * NT;
-    if (!MODE && p < L0 && A.base != nullptr) {
+    if (!MODE && p < L0 && base != nullptr) {
       const int Px = lo0x + p % NF, Py = (D == 2) ? lo0y + p / NF : 0;
       if (interior(Px, g.nxf) && (D == 1 || interior(Py, g.nxf)))
-        basev[e] = A.base[(D == 2 ? (long long)(Py - 1) * g.nxf : 0) + (Px - 1)];
+        basev[e] = base[(D == 2 ? (long long)(Py - 1) * g.nxf : 0) + (Px - 1)];
     }
   }
 
@@ -1388,8 +1441,8 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
           const long long off = (long long)n * nsp +
                                 (D == 2 ? (long long)(Py - 1) * g.nxf : 0) + (Px - 1);
           double o = v + basev[e];
-          if (A.accumulate) o += A.out[off];
-          A.out[off] = o;
+          if (A.accumulate) o += out[off];
+          out[off] = o;
         }
       }
     }
@@ -1422,14 +1475,19 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
           const long long off = (long long)n * nsp +
                                 (D == 2 ? (long long)(Py - 1) * g.nxf : 0) + (Px - 1);
           double val = o[e];
-          if (A.base != nullptr) val += A.base[off - (long long)n * nsp];
-          if (A.accumulate) val += A.out[off];
-          A.out[off] = val;
+          if (base != nullptr) val += base[off - (long long)n * nsp];
+          if (A.accumulate) val += out[off];
+          out[off] = val;
         }
       }
     }
     __syncthreads();
   }
+}
+
+template <int D, int TS, int TB, int NT, int MODE, int NC0>
+__global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
+  prolong_body<D, TS, TB, NT, MODE, NC0>(A, A.base, A.out, block_lin());
 }
 
 // 2-D prolongation (no stencil) with one 16 x 16 tile per wave: the
@@ -1449,7 +1507,8 @@ __global__ void __launch_bounds__(NT, SG_WPE) k_prolong(const ProlongArgs A) {
 #ifndef SG_WPEP
 #define SG_WPEP 3
 #endif
-__global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A) {
+__device__ __forceinline__ void prolong_w_body(const ProlongArgs &A, const double *__restrict__ base,
+                                               double *__restrict__ out, int lin) {
   constexpr int TS = 16, LTS = 4;
   using SH = Shape<2, TS, 0>;
   constexpr int L0 = TS * TS;
@@ -1467,7 +1526,7 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
   const Geometry g = A.g;
   const int nt = g.ntile, ngx = (nt + 3) >> 2;
   int grp, chunk;
-  stream_block(ngx * nt, g.nchunk, grp, chunk);
+  stream_block(lin, ngx * nt, g.nchunk, grp, chunk);
   const int tx = 4 * (grp % ngx) + wave, ty = grp / ngx;
   if (tx >= nt || ty >= nt) return;  // no workgroup barrier below
   const int n0 = chunk * g.chunk, n1 = min(n0 + g.chunk, g.ntf);
@@ -1528,7 +1587,7 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
     const int off = interior(Px, g.nxf) && interior(Py, g.nxf) ? (Px - 1) + (Py - 1) * g.nxf : -1;
 #pragma unroll
     for (int o = 0; o < 3; ++o) rc[e][o] = CJ.active ? coef(CJ, o, off) : 0.0;
-    basev[e] = (A.base != nullptr && off >= 0) ? A.base[off] : 0.0;
+    basev[e] = (base != nullptr && off >= 0) ? base[off] : 0.0;
   }
   // coarse values of the next slab (unconditional loads from valid addresses)
   const double *cbase = use_coarse ? A.coarse : A.safe_w;
@@ -1652,11 +1711,15 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
       if (interior(Px, g.nxf) && interior(Py, g.nxf)) {
         const long long off = (long long)n * nsp + (long long)(Py - 1) * g.nxf + (Px - 1);
         double o = v + basev[e];
-        if (A.accumulate) o += A.out[off];
-        A.out[off] = o;
+        if (A.accumulate) o += out[off];
+        out[off] = o;
       }
     }
   }
+}
+
+__global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A) {
+  prolong_w_body(A, A.base, A.out, block_lin());
 }
 
 // 2-D prolongation through the fine mass stencil, one 16 x 16 output tile
@@ -1674,7 +1737,8 @@ __global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w(const ProlongArgs A)
 #ifndef SG_WPEM
 #define SG_WPEM 3
 #endif
-__global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A) {
+__device__ __forceinline__ void prolong_wm_body(const ProlongArgs &A, const double *__restrict__ base,
+                                                double *__restrict__ out, int lin) {
   constexpr int TS = 16, LTS = 4;
   using SH = Shape<2, TS, 1>;
   constexpr int NF = TS + 2;              // fine region with its ring (setup only)
@@ -1697,7 +1761,7 @@ __global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A
   const Geometry g = A.g;
   const int nt = g.ntile, ngx = (nt + 3) >> 2;
   int grp, chunk;
-  stream_block(ngx * nt, g.nchunk, grp, chunk);
+  stream_block(lin, ngx * nt, g.nchunk, grp, chunk);
   const int tx = 4 * (grp % ngx) + wave, ty = grp / ngx;
   if (tx >= nt || ty >= nt) return;  // no workgroup barrier below
   const int n0 = chunk * g.chunk, n1 = min(n0 + g.chunk, g.ntf);
@@ -1906,12 +1970,16 @@ __global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A
       double val = tj01.x * s_m[0][po] + tj01.y * s_m[1][po] + tj2 * s_m[2][po] + lev[e];
       if (xin && interior(Py, g.nxf)) {
         const long long off = (long long)n * nsp + (long long)(Py - 1) * g.nxf + (Pxo - 1);
-        if (A.base != nullptr) val += A.base[off - (long long)n * nsp];
-        if (A.accumulate) val += A.out[off];
-        A.out[off] = val;
+        if (base != nullptr) val += base[off - (long long)n * nsp];
+        if (A.accumulate) val += out[off];
+        out[off] = val;
       }
     }
   }
+}
+
+__global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm(const ProlongArgs A) {
+  prolong_wm_body(A, A.base, A.out, block_lin());
 }
 
 // Energy of u_h at given instants (2-D, 16 x 16 tiles), without forming the
@@ -1952,7 +2020,7 @@ __global__ void __launch_bounds__(256, 2) k_energy_w(const ProlongArgs A,
   const Geometry g = A.g;
   const int nt = g.ntile, ngx = (nt + 3) >> 2;
   int grp, chunk;
-  stream_block(ngx * nt, g.nchunk, grp, chunk);
+  stream_block(block_lin(), ngx * nt, g.nchunk, grp, chunk);
   const int tx = 4 * (grp % ngx) + wave, ty = grp / ngx;
   if (tx >= nt || ty >= nt) return;  // no workgroup barrier below
   const int tile = ty * nt + tx, ntileD = nt * nt;
@@ -2207,14 +2275,15 @@ __global__ void __launch_bounds__(256, 2) k_energy_w(const ProlongArgs A,
 //   mode 0: mv = M v,  ku = K u
 //   mode 1: mv = M v,  ku = gsum - K u      (adjoint of the lift and u0 term)
 template <int D>
-__global__ void k_fine_stencils(int N, const double *__restrict__ ce, double hx,
-                                double hy, const double *__restrict__ v,
-                                const double *__restrict__ u, double *__restrict__ mv,
-                                double *__restrict__ ku, const double *__restrict__ gsum,
-                                int mode) {
+__device__ __forceinline__ void fine_stencils_body(int N, const double *__restrict__ ce,
+                                                   double hx, double hy,
+                                                   const double *__restrict__ v,
+                                                   const double *__restrict__ u,
+                                                   double *__restrict__ mv, double *__restrict__ ku,
+                                                   const double *__restrict__ gsum, int mode,
+                                                   long long gid) {
   const int n = N - 1;
   const long long nsp = (D == 2) ? (long long)n * n : n;
-  const long long gid = gid64();
   if (gid >= nsp) return;
   const int Px = (int)(gid % n) + 1;
   const int Py = (D == 2) ? (int)(gid / n) + 1 : 0;
@@ -2259,6 +2328,129 @@ __global__ void k_fine_stencils(int N, const double *__restrict__ ce, double hx,
     }
     ku[gid] = (mode == 1) ? gsum[gid] - r : r;
   }
+}
+
+template <int D>
+__global__ void k_fine_stencils(int N, const double *__restrict__ ce, double hx,
+                                double hy, const double *__restrict__ v,
+                                const double *__restrict__ u, double *__restrict__ mv,
+                                double *__restrict__ ku, const double *__restrict__ gsum,
+                                int mode) {
+  fine_stencils_body<D>(N, ce, hx, hy, v, u, mv, ku, gsum, mode, gid64());
+}
+
+// ------------------------------------------- launches of many problems ------
+
+// Member of the calling block: the last m with first[m] <= blockIdx.x
+// (wave-uniform: scalar loads).
+__device__ __forceinline__ int many_member(const ManyLaunch &M) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = M.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (M.first[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+// per-call pointer of slot `slot` for member m (own: the struct's pointer)
+template <class T>
+__device__ __forceinline__ T *many_ptr(const ManyLaunch &M, int slot, int m, T *own) {
+  typedef const double *__attribute__((address_space(4))) const cptr_t;
+  return slot < 0 ? own : (T *)((cptr_t *)M.ptr)[(long long)slot * M.nprob + M.prob[m]];
+}
+// member m's argument struct, read through the scalar cache (the array is
+// never written during the launch)
+template <class A>
+__device__ __forceinline__ const A &many_args(const ManyLaunch &M, int m) {
+  typedef const __attribute__((address_space(4))) A cargs_t;
+  return *(const A *)((cargs_t *)M.args + m);
+}
+
+template <int D, int TS, int TB, int NT, int STENCIL, int NC0>
+__global__ void __launch_bounds__(NT, SG_WPE) k_restrict_many(const ManyLaunch M) {
+  const int m = many_member(M), lin = blockIdx.x - M.first[m];
+  if (lin >= M.nblk[m]) return;  // padding of the member's block range
+  const RestrictArgs &A = many_args<RestrictArgs>(M, m);
+  const double *X = many_ptr(M, M.s0, m, A.X);
+  if (X == nullptr) return;
+  restrict_body<D, TS, TB, NT, STENCIL, NC0>(A, X, lin);
+}
+template <int STENCIL, int NC0>
+__global__ void __launch_bounds__(256, SG_WPEW) k_restrict_w_many(const ManyLaunch M) {
+  const int m = many_member(M), lin = blockIdx.x - M.first[m];
+  if (lin >= M.nblk[m]) return;
+  const RestrictArgs &A = many_args<RestrictArgs>(M, m);
+  const double *X = many_ptr(M, M.s0, m, A.X);
+  if (X == nullptr) return;
+  restrict_w_body<STENCIL, NC0>(A, X, lin);
+}
+template <int D, int TS, int TB, int NT, int MODE, int NC0>
+__global__ void __launch_bounds__(NT, SG_WPE) k_prolong_many(const ManyLaunch M) {
+  const int m = many_member(M), lin = blockIdx.x - M.first[m];
+  if (lin >= M.nblk[m]) return;
+  const ProlongArgs &A = many_args<ProlongArgs>(M, m);
+  double *out = many_ptr(M, M.s1, m, A.out);
+  if (out == nullptr) return;
+  prolong_body<D, TS, TB, NT, MODE, NC0>(A, many_ptr(M, M.s0, m, A.base), out, lin);
+}
+__global__ void __launch_bounds__(256, SG_WPEP) k_prolong_w_many(const ManyLaunch M) {
+  const int m = many_member(M), lin = blockIdx.x - M.first[m];
+  if (lin >= M.nblk[m]) return;
+  const ProlongArgs &A = many_args<ProlongArgs>(M, m);
+  double *out = many_ptr(M, M.s1, m, A.out);
+  if (out == nullptr) return;
+  prolong_w_body(A, many_ptr(M, M.s0, m, A.base), out, lin);
+}
+__global__ void __launch_bounds__(256, SG_WPEM) k_prolong_wm_many(const ManyLaunch M) {
+  const int m = many_member(M), lin = blockIdx.x - M.first[m];
+  if (lin >= M.nblk[m]) return;
+  const ProlongArgs &A = many_args<ProlongArgs>(M, m);
+  double *out = many_ptr(M, M.s1, m, A.out);
+  if (out == nullptr) return;
+  prolong_wm_body(A, many_ptr(M, M.s0, m, A.base), out, lin);
+}
+template <int D, int TS>
+__global__ void __launch_bounds__(256) k_reduce_many(const ManyLaunch M) {
+  const int m = many_member(M), lin = blockIdx.x - M.first[m];
+  if (lin >= M.nblk[m]) return;
+  const ReduceArgs &A = many_args<ReduceArgs>(M, m);
+  const long long b0 = (long long)lin * 256;
+  reduce_body<D, TS>(A.g, A.ch, A.in, A.items, A.nitems, A.total, b0 + threadIdx.x,
+                     wave_gid0(b0));
+}
+template <int D>
+__global__ void __launch_bounds__(256) k_coarse_restrict_many(const ManyLaunch M) {
+  const int m = many_member(M), lin = blockIdx.x - M.first[m];
+  if (lin >= M.nblk[m]) return;
+  const ReduceArgs &A = many_args<ReduceArgs>(M, m);
+  const long long b0 = (long long)lin * 256;
+  coarse_restrict_body<D>(A.g, A.ch, A.in, A.items, A.nitems, A.total,
+                          b0 + threadIdx.x, wave_gid0(b0));
+}
+template <int D>
+__global__ void __launch_bounds__(256) k_coarse_pyramid_many(const ManyLaunch M) {
+  const int m = many_member(M), lin = blockIdx.x - M.first[m];
+  if (lin >= M.nblk[m]) return;
+  const CoarseArgs &A = many_args<CoarseArgs>(M, m);
+  coarse_pyramid_body<D>(A.g, A.in, A.out, lin);
+}
+template <int D>
+__global__ void __launch_bounds__(256) k_prolong_coarse_many(const ManyLaunch M) {
+  const int m = many_member(M), lin = blockIdx.x - M.first[m];
+  if (lin >= M.nblk[m]) return;
+  const CoarseArgs &A = many_args<CoarseArgs>(M, m);
+  prolong_coarse_body<D>(A.g, A.ch, A.out, lin);
+}
+template <int D>
+__global__ void __launch_bounds__(256) k_fine_stencils_many(const ManyLaunch M) {
+  const int m = many_member(M), lin = blockIdx.x - M.first[m];
+  if (lin >= M.nblk[m]) return;
+  const StencilArgs &A = many_args<StencilArgs>(M, m);
+  double *mv = many_ptr(M, M.s2, m, A.mv);
+  double *ku = many_ptr(M, M.s3, m, A.ku);
+  fine_stencils_body<D>(A.N, A.ce, A.hx, A.hy, many_ptr(M, M.s0, m, A.v),
+                        many_ptr(M, M.s1, m, A.u), mv, ku, A.gsum, A.mode,
+                        (long long)lin * 256 + threadIdx.x);
 }
 
 // Energy of finest-mesh functions, slab by slab (Sec. 6.3): for slab k,
@@ -2450,34 +2642,35 @@ __global__ void __launch_bounds__(64) k_l2_sum(int K, int nblk, const double *__
 // b_c[i][K] = sum_q D_b[i][q] Z_c[q][K] + psi_i'(0) MV_a[K] - g_b[i] KU_a[K]
 __global__ void k_post_load(const CompDesc *__restrict__ cd, int ncomp, long long total) {
   const long long gid = gid64();
-  const int ci = find_item(cd, ncomp, gid);
+  const int ci = find_item(cd, ncomp, gid, wave_gid0((long long)blockIdx.x * blockDim.x));
   if (gid >= total) return;
-  const CompDesc &C = cd[ci];
+  const CompDesc &C = cref(cd, ci);
   const long long loc = gid - C.start;
   const int i = (int)loc / C.nsp;  // a component holds fewer than 2^31 values
   const int K = (int)loc - i * C.nsp;
   const double *Z = C.z;
-  const KernelTables *kt = C.kt;
-  double v = kt->Dlo[C.b][i] * Z[loc];
-  if (i + 1 < C.nq) v += kt->Dhi[C.b][i] * Z[loc + C.nsp];
-  if (i == 0 && C.mv != nullptr) v += kt->Dlo[C.b][0] * C.mv[K];
-  if (C.ku != nullptr) v -= kt->g[C.b][i] * C.ku[K];
-  C.data[loc] = v;
+  const KernelTables *kt = &cref(C.kt, 0);
+  double v = gld(kt->Dlo[C.b], i) * Z[loc];
+  if (i + 1 < C.nq) v += gld(kt->Dhi[C.b], i) * Z[loc + C.nsp];
+  if (i == 0 && C.mv != nullptr) v += gld(kt->Dlo[C.b], 0) * gld(C.mv, K);
+  if (C.ku != nullptr) v -= gld(kt->g[C.b], i) * gld(C.ku, K);
+  gst(C.data, loc, v);
 }
 
 // zeta_c[q][K] = sum_i D_b[i][q] z_c[i][K]   (transpose of the above)
 __global__ void k_post_adjoint(const CompDesc *__restrict__ cd, int ncomp,
                                long long total) {
   const long long gid = gid64();
-  const int ci = find_item(cd, ncomp, gid);
+  const int ci = find_item(cd, ncomp, gid, wave_gid0((long long)blockIdx.x * blockDim.x));
   if (gid >= total) return;
-  const CompDesc &C = cd[ci];
+  const CompDesc &C = cref(cd, ci);
   const long long loc = gid - C.start;
   const int q = (int)loc / C.nsp;  // a component holds fewer than 2^31 values
-  const KernelTables *kt = C.kt;
-  double v = kt->Dlo[C.b][q] * C.z[loc];
-  if (q >= 1) v += kt->Dhi[C.b][q - 1] * C.z[loc - C.nsp];
-  C.data[loc] = v;
+  const KernelTables *kt = &cref(C.kt, 0);
+  const double *Z = C.z;
+  double v = gld(kt->Dlo[C.b], q) * Z[loc];
+  if (q >= 1) v += gld(kt->Dhi[C.b], q - 1) * Z[loc - C.nsp];
+  gst(C.data, loc, v);
 }
 
 // fv_a[K] = sum_c psi_0'(0) z_c[0][K];  fu_a[K] = sum_c sum_i g_b[i] z_c[i][K].
@@ -2486,11 +2679,11 @@ __global__ void k_post_adjoint(const CompDesc *__restrict__ cd, int ncomp,
 __global__ void k_adjoint_fields(const LevelDesc *__restrict__ ld, int nlev,
                                  long long total) {
   const long long gid = gid64();
-  const int l = find_item(ld, nlev, gid);
+  const int l = find_item(ld, nlev, gid, wave_gid0((long long)blockIdx.x * blockDim.x));
   if (gid >= total) return;
-  const LevelDesc &L = ld[l];
+  const LevelDesc &L = cref(ld, l);
   const CompDesc *cd = L.cd;
-  const KernelTables *kt = L.kt;
+  const KernelTables *kt = &cref(L.kt, 0);
   const long long rel = gid - L.start;
   const int lane = L.wave ? (int)(rel & 63) : 0, step = L.wave ? 64 : 1;
   const long long K = L.wave ? rel >> 6 : rel;
@@ -2499,18 +2692,19 @@ __global__ void k_adjoint_fields(const LevelDesc *__restrict__ ld, int nlev,
   for (int t = 0; t < 2; ++t) {
     const int c = t == 0 ? L.c0 : L.c1;
     if (c < 0) continue;
-    const CompDesc &C = cd[c];
-    if (lane == 0) fv += kt->Dlo[C.b][0] * C.z[K];
-    const double *gb = kt->g[C.b];
-    for (int i = lane; i < C.nq; i += step) fu += gb[i] * C.z[(long long)i * C.nsp + K];
+    const CompDesc &C = cref(cd, c);
+    const double *Z = C.z;
+    if (lane == 0) fv += gld(kt->Dlo[C.b], 0) * Z[K];
+    const gptr<const double> gb = to_g(kt->g[C.b]);
+    for (int i = lane; i < C.nq; i += step) fu += gb[i] * Z[(long long)i * C.nsp + K];
   }
   if (L.wave) {
 #pragma unroll
     for (int dlt = 32; dlt >= 1; dlt >>= 1) fu += __shfl_xor(fu, dlt);
     if (lane != 0) return;
   }
-  L.fv[K] = fv;
-  L.fu[K] = fu;
+  gst(L.fv, K, fv);
+  gst(L.fu, K, fu);
 }
 
 // Batched C = A B (row major) on the FP64 matrix cores.  Block tiles of
@@ -2550,7 +2744,7 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmDesc *__restric
     if (le != ~0ull) break;
   }
   di = __builtin_amdgcn_readfirstlane(di - 1);
-  const GemmDesc &Dd = descs[di];
+  const GemmDesc &Dd = cref(descs, di);
   int t = blockIdx.x - Dd.tile0;
   const int per = Dd.tm * Dd.tn;
   const int bidx = t / per;
@@ -2716,21 +2910,23 @@ __device__ __forceinline__ void mode_scalars(const SolveDesc &S, int j,
                                              double &kap) {
   const int a = S.a, na = (1 << a) - 1;
   if (d == 1 || S.flat) {
-    m = mt->mx[a][j];
-    kap = S.c2 * mt->kx[a][j];
+    m = gld(mt->mx[a], j);
+    kap = S.c2 * gld(mt->kx[a], j);
   } else {
     const int jx = j % na, jy = j / na;
-    m = mt->my[a][jy] * mt->mx[a][jx];
-    kap = S.c2 * (mt->ky[a][jy] * mt->mx[a][jx] + mt->my[a][jy] * mt->kx[a][jx]);
+    const double mx = gld(mt->mx[a], jx), kx = gld(mt->kx[a], jx);
+    const double my = gld(mt->my[a], jy), ky = gld(mt->ky[a], jy);
+    m = my * mx;
+    kap = S.c2 * (ky * mx + my * kx);
   }
 }
 
 __global__ void __launch_bounds__(64) k_time_factor(const SolveDesc *__restrict__ sds,
                                                     int nsd, long long total) {
   const long long wbase = (long long)blockIdx.x * 64;
-  const SolveDesc &S = sds[find_solve(sds, nsd, wbase)];
-  const KernelTables *kt = S.kt;
-  const ModeTables *mt = S.mt;
+  const SolveDesc &S = cref(sds, find_solve(sds, nsd, wbase));
+  const KernelTables *kt = &cref(S.kt, 0);
+  const ModeTables *mt = &cref(S.mt, 0);
   const int d = S.d;
   const long long gid = wbase + threadIdx.x;
   const int j = (int)(gid - S.thread0);
@@ -2738,7 +2934,7 @@ __global__ void __launch_bounds__(64) k_time_factor(const SolveDesc *__restrict_
   const int b = S.b, nq = S.nq, nm = S.nmodes;
   double m, kap;
   mode_scalars(S, j, mt, d, m, kap);
-  const double *Ab = kt->A[b], *Bb = kt->B[b];
+  const gptr<const double> Ab = to_g(kt->A[b]), Bb = to_g(kt->B[b]);
   auto ent = [&](int i, int off) -> double {
     const int jj = i + off;
     if (jj < 0 || jj >= nq) return 0.0;
@@ -2780,9 +2976,9 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
   constexpr int CH = SG_CH;
   constexpr int CR = SG_CR;
   const long long wbase = (long long)blockIdx.x * 64;
-  const SolveDesc &S = sds[find_solve(sds, nsd, wbase)];
-  const KernelTables *kt = S.kt;
-  const ModeTables *mt = S.mt;
+  const SolveDesc &S = cref(sds, find_solve(sds, nsd, wbase));
+  const KernelTables *kt = &cref(S.kt, 0);
+  const ModeTables *mt = &cref(S.mt, 0);
   const int d = S.d;
   const int lane = threadIdx.x;
   const bool wave = S.wave != 0;
@@ -2792,7 +2988,8 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
   const int b = S.b, nq = S.nq, nm = S.nmodes;
   double m, kap;
   mode_scalars(S, j, mt, d, m, kap);
-  const double *Ab = kt->A[b], *Bb = kt->B[b], *Al = kt->Alo[b], *Bl = kt->Blo[b];
+  const gptr<const double> Ab = to_g(kt->A[b]), Bb = to_g(kt->B[b]), Al = to_g(kt->Alo[b]),
+                          Bl = to_g(kt->Blo[b]);
   const bool tr = S.transpose != 0;
   double *rhs = S.rhs;
   const long long plane = (long long)nq * nm;
@@ -3086,16 +3283,17 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
 __global__ void __launch_bounds__(64) k_block_solve(const BlockDesc *__restrict__ bds) {
   constexpr int MAXQ = 64;
   __shared__ double s_v[MAXQ], s_u[MAXQ];
-  const BlockDesc &B = bds[blockIdx.x];
-  const KernelTables *kt = B.kt;
+  const BlockDesc &B = cref(bds, blockIdx.x);
+  const KernelTables &KT = cref(B.kt, 0);
   const int lane = threadIdx.x;
   const int nq = B.nq, nx = B.nx;
   const bool tr = B.transpose != 0;
-  const double *Ah = kt->A[B.b], *Bh = kt->B[B.b], *Al = kt->Alo[B.b], *Bl = kt->Blo[B.b];
+  const gptr<const double> Ah = to_g(KT.A[B.b]), Bh = to_g(KT.B[B.b]), Al = to_g(KT.Alo[B.b]),
+                          Bl = to_g(KT.Blo[B.b]);
   double *b0 = B.work, *res = b0 + (long long)nq * nx, *tmp = res + (long long)nq * nx;
   auto at = [&](int i, int k) -> long long { return (long long)i * nx + k; };
   // (T v)_j for the banded time matrix T (A or B, high parts), T or T^T
-  auto band = [&](const double *T, const double *v, int j, bool trans) -> double {
+  auto band = [&](gptr<const double> T, const double *v, int j, bool trans) -> double {
     double acc = 0.0;
     for (int off = -2; off <= 2; ++off) {
       const int i = j + off;
@@ -3527,6 +3725,118 @@ hipError_t launch_broadcast(double *out, const double *base, int nt, long long n
   const long long n = (long long)nt * nsp;
   hipLaunchKernelGGL(k_broadcast, dim3(blocks_for(n, 256)), dim3(256), 0, s, out, base, nt,
                      nsp);
+  return hipGetLastError();
+}
+
+// ---- launches of many problems -----------------------------------------------
+
+hipError_t launch_restrict_many(const RestrictArgs &a, const ManyLaunch &M, int blocks,
+                                hipStream_t s) {
+  if (blocks <= 0 || M.n <= 0) return hipSuccess;
+  const bool two = a.ch[(a.g.J - 1) * 2 + 1].active != 0;
+  const dim3 grid(blocks);
+#define SG_RM(D, TS, TB, ST, NC) \
+  hipLaunchKernelGGL((k_restrict_many<D, TS, TB, kNT, ST, NC>), grid, dim3(kNT), 0, s, M)
+#define SG_RMW(ST, NC) hipLaunchKernelGGL((k_restrict_w_many<ST, NC>), grid, dim3(256), 0, s, M)
+  if (a.g.d == 2 && a.g.TS == 16) {
+    if (a.stencil) {
+      if (two) SG_RMW(1, 2); else SG_RMW(1, 1);
+    } else {
+      if (two) SG_RMW(0, 2); else SG_RMW(0, 1);
+    }
+  } else if (a.g.d == 2) {
+    if (a.stencil) {
+      if (two) SG_RM(2, kTS2, kTB2, 1, 2); else SG_RM(2, kTS2, kTB2, 1, 1);
+    } else {
+      if (two) SG_RM(2, kTS2, kTB2, 0, 2); else SG_RM(2, kTS2, kTB2, 0, 1);
+    }
+  } else {
+    if (a.stencil) {
+      if (two) SG_RM(1, kTS1, kTB1, 1, 2); else SG_RM(1, kTS1, kTB1, 1, 1);
+    } else {
+      if (two) SG_RM(1, kTS1, kTB1, 0, 2); else SG_RM(1, kTS1, kTB1, 0, 1);
+    }
+  }
+#undef SG_RM
+#undef SG_RMW
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong_many(const ProlongArgs &a, const ManyLaunch &M, int blocks,
+                               hipStream_t s) {
+  if (blocks <= 0 || M.n <= 0) return hipSuccess;
+  const bool two = a.ch[(a.g.J - 1) * 2 + 1].active != 0;
+  const dim3 grid(blocks);
+#define SG_PM(D, TS, TB, MO, NC) \
+  hipLaunchKernelGGL((k_prolong_many<D, TS, TB, kNT, MO, NC>), grid, dim3(kNT), 0, s, M)
+  if (a.g.d == 2 && a.g.TS == 16) {
+    if (two || a.taps == nullptr) return hipErrorInvalidValue;  // one finest channel only
+    if (a.stencil)
+      hipLaunchKernelGGL(k_prolong_wm_many, grid, dim3(256), 0, s, M);
+    else
+      hipLaunchKernelGGL(k_prolong_w_many, grid, dim3(256), 0, s, M);
+  } else if (a.g.d == 2) {
+    if (a.stencil) {
+      if (two) SG_PM(2, kTS2, kTB2P, 1, 2); else SG_PM(2, kTS2, kTB2P, 1, 1);
+    } else {
+      if (two) SG_PM(2, kTS2, kTB2P, 0, 2); else SG_PM(2, kTS2, kTB2P, 0, 1);
+    }
+  } else {
+    if (a.stencil) {
+      if (two) SG_PM(1, kTS1, kTB1, 1, 2); else SG_PM(1, kTS1, kTB1, 1, 1);
+    } else {
+      if (two) SG_PM(1, kTS1, kTB1, 0, 2); else SG_PM(1, kTS1, kTB1, 0, 1);
+    }
+  }
+#undef SG_PM
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_many(const Geometry &g, const ManyLaunch &M, int blocks,
+                              hipStream_t s) {
+  if (blocks <= 0 || M.n <= 0) return hipSuccess;
+  if (g.d == 2 && g.TS == 16)
+    hipLaunchKernelGGL((k_reduce_many<2, 16>), dim3(blocks), dim3(256), 0, s, M);
+  else if (g.d == 2)
+    hipLaunchKernelGGL((k_reduce_many<2, kTS2>), dim3(blocks), dim3(256), 0, s, M);
+  else
+    hipLaunchKernelGGL((k_reduce_many<1, kTS1>), dim3(blocks), dim3(256), 0, s, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_pyramid_many(int d, const ManyLaunch &M, int blocks, hipStream_t s) {
+  if (blocks <= 0 || M.n <= 0) return hipSuccess;
+  if (d == 2)
+    hipLaunchKernelGGL(k_coarse_pyramid_many<2>, dim3(blocks), dim3(256), 0, s, M);
+  else
+    hipLaunchKernelGGL(k_coarse_pyramid_many<1>, dim3(blocks), dim3(256), 0, s, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_restrict_many(int d, const ManyLaunch &M, int blocks, hipStream_t s) {
+  if (blocks <= 0 || M.n <= 0) return hipSuccess;
+  if (d == 2)
+    hipLaunchKernelGGL(k_coarse_restrict_many<2>, dim3(blocks), dim3(256), 0, s, M);
+  else
+    hipLaunchKernelGGL(k_coarse_restrict_many<1>, dim3(blocks), dim3(256), 0, s, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong_coarse_many(int d, const ManyLaunch &M, int blocks, hipStream_t s) {
+  if (blocks <= 0 || M.n <= 0) return hipSuccess;
+  if (d == 2)
+    hipLaunchKernelGGL(k_prolong_coarse_many<2>, dim3(blocks), dim3(256), 0, s, M);
+  else
+    hipLaunchKernelGGL(k_prolong_coarse_many<1>, dim3(blocks), dim3(256), 0, s, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_fine_stencils_many(int d, const ManyLaunch &M, int blocks, hipStream_t s) {
+  if (blocks <= 0 || M.n <= 0) return hipSuccess;
+  if (d == 2)
+    hipLaunchKernelGGL(k_fine_stencils_many<2>, dim3(blocks), dim3(256), 0, s, M);
+  else
+    hipLaunchKernelGGL(k_fine_stencils_many<1>, dim3(blocks), dim3(256), 0, s, M);
   return hipGetLastError();
 }
 

@@ -65,6 +65,50 @@ struct WorkItem {        // flattened per-channel work (reduce / coarse kernels)
   long long count;
 };
 
+// ---- one stage of many problems in one launch ------------------------------
+// Member m of the launch runs blocks [first[m], first[m] + nblk[m]) (first[m]
+// a multiple of 8, so the streaming kernels' XCD-aware block order holds per
+// member) with its argument struct args[m]; the data pointers that change
+// from call to call come from the call's table ptr[slot * nprob + prob[m]]
+// for the slots the stage reads (-1: the argument struct's own pointer).
+// Pointer slots of a batch call:
+enum BatchSlot { kSlotF = 0, kSlotU0, kSlotV0, kSlotU, kSlotG, kSlotDF, kSlotDU0, kSlotDV0,
+                 kBatchSlots };
+struct ManyLaunch {
+  const void *args;          // device array of argument structs
+  const int *first;          // [n + 1]
+  const int *nblk;           // [n]
+  const int *prob;           // [n] member -> problem index
+  const double *const *ptr;  // device pointer table [kBatchSlots][nprob]
+  int n, nprob;
+  int s0, s1, s2, s3;        // slots of the stage's per-call pointers (meaning per kernel)
+};
+
+// argument structs of the flat and per-slab kernels in launches of many problems
+struct ReduceArgs {      // k_reduce / k_coarse_restrict
+  Geometry g;
+  const Channel *ch;
+  const double *in;      // partial blocks (reduce) or per-slab restrictions SL (coarse)
+  const WorkItem *items;
+  int nitems;
+  long long total;
+};
+struct CoarseArgs {      // k_coarse_pyramid (in = coarse partials, out = SL) and
+  Geometry g;            // k_prolong_coarse (ch, out = the level-A0 array)
+  const Channel *ch;
+  const double *in;
+  double *out;
+};
+struct StencilArgs {     // k_fine_stencils
+  int N, mode;
+  const double *ce;
+  double hx, hy;
+  const double *v, *u;
+  double *mv, *ku;
+  const double *gsum;
+};
+
+
 // MFMA GEMM tiles: SG_GEMM_W x SG_GEMM_W waves per workgroup, each a 32 x 32
 // sub-tile (tiles of 32 SG_GEMM_W square)
 #ifndef SG_GEMM_W
@@ -168,6 +212,21 @@ hipError_t launch_restrict(const RestrictArgs &a, hipStream_t s);
 hipError_t launch_reduce(const Geometry &g, const Channel *ch, const double *part,
                          const WorkItem *items, int nitems, long long total,
                          hipStream_t s);
+// launches of many problems (ManyLaunch.args holds RestrictArgs /
+// ProlongArgs / ReduceArgs / CoarseArgs / StencilArgs); proto: any member's
+// arguments (the kernel variant: dimension, tile, stencil, finest channels);
+// slots: restrict X = s0; prolong base = s0, out = s1; stencils v = s0,
+// u = s1, mv = s2, ku = s3 (-1: the struct's own)
+hipError_t launch_restrict_many(const RestrictArgs &proto, const ManyLaunch &M, int blocks,
+                                hipStream_t s);
+hipError_t launch_prolong_many(const ProlongArgs &proto, const ManyLaunch &M, int blocks,
+                               hipStream_t s);
+hipError_t launch_reduce_many(const Geometry &proto, const ManyLaunch &M, int blocks,
+                              hipStream_t s);
+hipError_t launch_coarse_pyramid_many(int d, const ManyLaunch &M, int blocks, hipStream_t s);
+hipError_t launch_coarse_restrict_many(int d, const ManyLaunch &M, int blocks, hipStream_t s);
+hipError_t launch_prolong_coarse_many(int d, const ManyLaunch &M, int blocks, hipStream_t s);
+hipError_t launch_fine_stencils_many(int d, const ManyLaunch &M, int blocks, hipStream_t s);
 // largest level-A0 array (nodes) the coarse pyramid kernel holds in LDS
 constexpr int kCoarseMax = 4096;
 // per-slab level-A0 values assembled from the restriction's per-slab tile
