@@ -14,21 +14,34 @@ level j+1.  With sparse level L the components are
 
 with sign +1 on jx+jt = L and -1 on jx+jt = L-1; this is eq. (19) with
 J = L-2.  The finest level in space and in time is L-1.
+
+Coarsest level (the h_0 of the coarse-mesh study of Sec. 6.3, Fig. 10):
+h_0 = 2^-b0 makes the paper's level j our level j + b0.  Eq. (19) with its
+levels shifted by b0 and the finest level kept at L-1 (J = L-1-b0) is
+
+    C_{L,b0} = {(jx, jt) : jx >= b0, jt >= b0, jx + jt in {L-1+b0, L-2+b0}}
+
+with the same signs; b0 = 1 is C_L above and b0 = L-1 the single full-grid
+component (L-1, L-1).
 """
 
 
-def components(L):
-    """List of (jx, jt, sign) for sparse level L >= 2, eq. (19)."""
+def components(L, b0=1):
+    """List of (jx, jt, sign) for sparse level L >= 2 and coarsest level
+    1 <= b0 <= L-1, eq. (19)."""
     if L < 2:
         raise ValueError("sparse level L must be >= 2")
+    if not 1 <= b0 <= L - 1:
+        raise ValueError("coarsest level b0 must be in [1, L-1]")
     out = []
-    for jx in range(1, L):
-        jt = L - jx
-        if jt >= 1:
+    top = L - 1 + b0                      # jx + jt on the +1 diagonal
+    for jx in range(b0, L):
+        jt = top - jx
+        if jt >= b0:
             out.append((jx, jt, +1))
-    for jx in range(1, L - 1):
-        jt = L - 1 - jx
-        if jt >= 1:
+    for jx in range(b0, L - 1):
+        jt = top - 1 - jx
+        if jt >= b0:
             out.append((jx, jt, -1))
     return out
 
@@ -48,9 +61,9 @@ def n_time(jt):
     return 2 ** jt + 1
 
 
-def n_sparse(L, d):
+def n_sparse(L, d, b0=1):
     """Sum of component dimensions (the paper's N^sparse_DoFs, Sec. 3.2)."""
-    return sum(n_space(jx, d) * n_time(jt) for jx, jt, _ in components(L))
+    return sum(n_space(jx, d) * n_time(jt) for jx, jt, _ in components(L, b0))
 
 
 def n_full(L, d):

@@ -44,9 +44,10 @@ class Problem:
 
     d in {1,2}; lengths: side lengths of Omega = prod (0, len_i);
     ncell, c_vals: piecewise-constant wave speed on a uniform block grid
-    (x fastest); T: final time; L: sparse level (components C_L)."""
+    (x fastest); T: final time; L: sparse level (components C_L); b0:
+    coarsest level of the combination (h_0 = 2^-b0, Sec. 6.3)."""
 
-    def __init__(self, d, lengths, ncell, c_vals, T, L):
+    def __init__(self, d, lengths, ncell, c_vals, T, L, b0=1):
         if d not in (1, 2) or len(lengths) != d or len(ncell) != d:
             raise ValueError("d must be 1 or 2 with one length/ncell per axis")
         if T <= 0 or L < 2:
@@ -54,9 +55,10 @@ class Problem:
         self.d = d
         self.T = float(T)
         self.L = int(L)
+        self.b0 = int(b0)
         self.J = levels.finest_level(L)
         self.medium = space.Medium(lengths, ncell, c_vals)
-        self.comps = levels.components(L)
+        self.comps = levels.components(L, self.b0)
         self._cache = {}
 
     # ----- sizes -------------------------------------------------------

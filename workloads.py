@@ -29,15 +29,17 @@ import numpy as np
 
 
 class Spec:
-    """Problem parameters: d, lengths, ncell, c_vals (x fastest), T, L."""
+    """Problem parameters: d, lengths, ncell, c_vals (x fastest), T, L, and
+    the coarsest level b0 of the combination (keyword; args() leaves it out)."""
 
-    def __init__(self, d, lengths, ncell, c_vals, T, L):
+    def __init__(self, d, lengths, ncell, c_vals, T, L, b0=1):
         self.d = int(d)
         self.lengths = [float(v) for v in lengths]
         self.ncell = [int(v) for v in ncell]
         self.c_vals = np.asarray(c_vals, dtype=np.float64).reshape(-1)
         self.T = float(T)
         self.L = int(L)
+        self.b0 = int(b0)
 
     @property
     def J(self):
@@ -60,7 +62,7 @@ class Spec:
 
     def __repr__(self):
         return (f"Spec(d={self.d}, lengths={self.lengths}, ncell={self.ncell}, "
-                f"T={self.T}, L={self.L})")
+                f"T={self.T}, L={self.L}, b0={self.b0})")
 
 
 def grids(spec):
