@@ -78,6 +78,25 @@ sg_status sg_assemble(int d, const double *len, const int *ncell,
                       const double *c_vals, double T, int L, sg_problem **out);
 
 /*
+ * sg_assemble with the coarsest level of the combination as a parameter: the
+ * coarse-mesh study of Sec. 6.3 (Fig. 10) varies the level-0 mesh size h_0.
+ * Level j of this library has 2^j uniform intervals, so h_0 = 2^-b0 of the
+ * domain side and of T; the components are eq. (19) with its levels shifted
+ * by b0 and the finest level kept at L-1:
+ *   {(jx, jt) : jx, jt >= b0, jx + jt in {L-1+b0, L-2+b0}},
+ * 2(L-1-b0)+1 of them, +1 on the first diagonal and -1 on the second.
+ *   b0      1 <= b0 <= L-1 (b0 = 1 is sg_assemble; b0 = L-1 is the single
+ *           full-grid component (L-1, L-1)); otherwise SG_EINVAL.
+ * Every other argument, the limits and the returned handle are those of
+ * sg_assemble.  The streaming passes cut their time chunks where the finest
+ * spatial level's time window moves (its component has time level b0), so
+ * a large b0 makes the chunks short.
+ */
+sg_status sg_assemble_offset(int d, const double *len, const int *ncell,
+                             const double *c_vals, double T, int L, int b0,
+                             sg_problem **out);
+
+/*
  * Forward solve: U = u0 + sum_c s_c P_c(f, u0, v0) on the finest grid
  * (component solves of eq. (9), combination eq. (19), lift).  f and U are
  * fine space-time arrays, u0 and v0 fine space arrays (device pointers).

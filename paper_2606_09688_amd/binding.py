@@ -29,6 +29,9 @@ _c_llp = ctypes.POINTER(ctypes.c_longlong)
 SIGNATURES = {
     "sg_assemble": (ctypes.c_int, [ctypes.c_int, _c_dp, _c_ip, _c_dp, ctypes.c_double,
                                    ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "sg_assemble_offset": (ctypes.c_int, [ctypes.c_int, _c_dp, _c_ip, _c_dp, ctypes.c_double,
+                                          ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
     "sg_solve": (ctypes.c_int, [ctypes.c_void_p] * 6),
     "sg_solve_plain": (ctypes.c_int, [ctypes.c_void_p] * 6),
     "sg_solve_static": (ctypes.c_int, [ctypes.c_void_p] * 6),
@@ -196,11 +199,12 @@ class SparseGridWave:
     """One assembled problem (sg_assemble) bound to the current HIP device.
 
     d: 1 or 2; lengths: side lengths; ncell: wave-speed blocks per axis;
-    c_vals: block speeds (x fastest); T: final time; L: sparse level.
+    c_vals: block speeds (x fastest); T: final time; L: sparse level;
+    b0: coarsest level of the combination (h_0 = 2^-b0, sg_assemble_offset).
     Arrays: f, U, g, df have shape (nt, n) / (nt, n, n); u0, v0 shape (n,) / (n, n).
     """
 
-    def __init__(self, d, lengths, ncell, c_vals, T, L, tuned=False):
+    def __init__(self, d, lengths, ncell, c_vals, T, L, tuned=False, b0=1):
         """tuned: build with the launch shapes the autotuner chose for this
         shape class on this device (autotune.lookup; library defaults if the
         class is not in the cache)."""
@@ -217,8 +221,8 @@ class SparseGridWave:
         h = ctypes.c_void_p()
         from .autotune import knobs_set
         with knobs_set(knobs):
-            check(L_.sg_assemble(d, ln, nc, cv.ctypes.data_as(_c_dp), float(T), int(L),
-                                 ctypes.byref(h)), "sg_assemble")
+            check(L_.sg_assemble_offset(d, ln, nc, cv.ctypes.data_as(_c_dp), float(T), int(L),
+                                        int(b0), ctypes.byref(h)), "sg_assemble_offset")
         self._h = h
         nt, n, nc_ = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         ns, nf = ctypes.c_longlong(), ctypes.c_longlong()
@@ -231,6 +235,7 @@ class SparseGridWave:
         self.shape = (self.nt,) + self.space_shape
         self.T = float(T)
         self.L = int(L)
+        self.b0 = int(b0)
 
     def close(self):
         if getattr(self, "_h", None) is not None and _lib is not None:

@@ -132,6 +132,8 @@ struct sg_problem {
   std::vector<double> c;
   double T = 1;
   int L = 2, J = 1, N = 2;
+  int b0 = 1;                      // coarsest level of the combination (h_0 = 2^-b0)
+  std::vector<int> cidx;           // [2 (J + 1)]: component of (level a, k = 0 plus / 1 minus), or -1
   bool const_c = true;
   double c2 = 1;
   std::vector<Comp> comps;
@@ -291,9 +293,43 @@ struct ChanSpec {
 };
 
 // prolong: the pass is a prolongation (selects the meaning of its tap table)
+// Time chunks on which the finest level's window q0 (one value per slab) is
+// constant: the streaming kernels keep that level's three time coefficients
+// fixed per block.  Keeps g's chunks where they already are; otherwise the
+// longest chunk length up to g.chunk whose shifted starts fall on every slab
+// where q0 moves (length 1 always does).
+Geometry align_chunks(const Geometry &g, const std::vector<const std::vector<int> *> &q0s) {
+  std::vector<int> moves;
+  for (int n = 1; n < g.ntf; ++n) {
+    bool mv = false;
+    for (const std::vector<int> *q0 : q0s) mv = mv || (*q0)[n] != (*q0)[n - 1];
+    if (mv) moves.push_back(n);
+  }
+  auto fits = [&](const Geometry &h) {
+    for (int n : moves)
+      if ((n + h.phase) % h.chunk != 0) return false;
+    return true;
+  };
+  if (fits(g)) return g;
+  Geometry h = g;
+  for (int c = g.chunk; c >= 1; --c) {
+    h.chunk = c;
+    h.phase = (c - moves[0] % c) % c;
+    if (fits(h)) break;
+  }
+  h.nchunk = (h.ntf + h.phase + h.chunk - 1) / h.chunk;
+  return h;
+}
+
 template <class F>
-sg_status build_pass(sg_problem *p, Pass &P, const Geometry &geo, F spec,
+sg_status build_pass(sg_problem *p, Pass &P, const Geometry &geo_in, F spec,
                      long long *part_need, bool prolong = false) {
+  std::vector<const std::vector<int> *> finest;
+  for (int k = 0; k < 2; ++k) {
+    const ChanSpec cs = spec(geo_in.J, k);
+    if (cs.active) finest.push_back(cs.hq0);
+  }
+  const Geometry geo = align_chunks(geo_in, finest);
   P.geo = geo;
   const int J = geo.J;
   if (2 * J > kChanMax) return fail(SG_EINVAL, "too many levels for the channel table");
@@ -318,9 +354,15 @@ sg_status build_pass(sg_problem *p, Pass &P, const Geometry &geo, F spec,
       if (!cs.active) continue;
       if (a == J) {
         // the streaming kernels keep the level-J coefficient window fixed
-        bool fixed = cs.nq == 3;
-        for (int n = 0; fixed && n < geo.ntf; ++n) fixed = (*cs.hq0)[n] == 0;
-        if (!fixed) return fail(SG_EINVAL, "internal: finest-level channel must have q0 = 0");
+        // within a time chunk
+        bool fixed = cs.nq >= 3;
+        for (int c = 0; fixed && c < geo.nchunk; ++c) {
+          int n0, n1;
+          chunk_span(geo, c, n0, n1);
+          for (int n = n0; fixed && n < n1; ++n) fixed = (*cs.hq0)[n] == (*cs.hq0)[n0];
+        }
+        if (!fixed)
+          return fail(SG_EINVAL, "internal: finest-level window moves inside a time chunk");
       }
       const int na = (1 << a) - 1;
       const long long nspa = geo.d == 2 ? (long long)na * na : na;
@@ -333,8 +375,9 @@ sg_status build_pass(sg_problem *p, Pass &P, const Geometry &geo, F spec,
         const std::vector<int> &q0 = *cs.hq0;
         int qb = 0;
         for (int c = 0; c < geo.nchunk; ++c) {
-          const int n0 = c * geo.chunk, n1 = std::min(n0 + geo.chunk, geo.ntf);
-          qb = std::max(qb, q0[n1 - 1] + 2 - q0[n0] + 1);
+          int n0, n1;
+          chunk_span(geo, c, n0, n1);
+          if (n1 > n0) qb = std::max(qb, q0[n1 - 1] + 2 - q0[n0] + 1);
         }
         C.qb = qb;
         C.part_off = off;
@@ -375,7 +418,8 @@ sg_status build_pass(sg_problem *p, Pass &P, const Geometry &geo, F spec,
       for (int n = 0; n < geo.ntf; ++n) {
         TapEntry &t = taps[(size_t)n * nci + li];
         for (int o = 0; o < 3; ++o) t.w[o] = w[3 * (size_t)n + o] * (prolong ? C.scale : 1.0);
-        const int n0 = n / geo.chunk * geo.chunk;
+        int n0, n1;
+        chunk_span(geo, (n + geo.phase) / geo.chunk, n0, n1);
         if (n > n0 && q0[n] > q0[n - 1])
           t.base = prolong ? q0[n] : C.part_off + (long long)(q0[n - 1] - q0[n0]) * sz;
       }
@@ -957,6 +1001,11 @@ sg_status sg_destroy(sg_problem *p) {
 
 sg_status sg_assemble(int d, const double *len, const int *ncell, const double *c_vals,
                       double T, int L, sg_problem **out) {
+  return sg_assemble_offset(d, len, ncell, c_vals, T, L, 1, out);
+}
+
+sg_status sg_assemble_offset(int d, const double *len, const int *ncell, const double *c_vals,
+                             double T, int L, int b0, sg_problem **out) {
   g_last_error.clear();
   if (!out) return fail(SG_EINVAL, "out is NULL");
   *out = nullptr;
@@ -964,6 +1013,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   if (!len || !ncell || !c_vals) return fail(SG_EINVAL, "NULL argument");
   if (!(T > 0) || !std::isfinite(T)) return fail(SG_EINVAL, "T must be > 0");
   if (L < 2 || L > 16) return fail(SG_EINVAL, "L must be in [2,16]");
+  if (b0 < 1 || b0 > L - 1) return fail(SG_EINVAL, "coarsest level b0 must be in [1, L-1]");
   const int J = L - 1, N = 1 << J;
   int ncl = 1;
   for (int i = 0; i < d; ++i) {
@@ -1002,6 +1052,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   p->c.assign(c_vals, c_vals + ncl);
   p->T = T;
   p->L = L;
+  p->b0 = b0;
   p->J = J;
   p->N = N;
   p->const_c = std::all_of(p->c.begin(), p->c.end(), [&](double v) { return v == p->c[0]; });
@@ -1012,8 +1063,10 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
   if (const char *e = getenv("SG_GEMM_FOLD")) p->gemm_fold = std::min(3, std::max(0, atoi(e)));
   if (const char *e = getenv("SG_FDM_CH")) p->fdm_chunk = std::min(16, std::max(4, atoi(e)));
 
-  // components: +1 on jx + jt = L (jx = 1..L-1), -1 on jx + jt = L-1 (jx = 1..L-2)
+  // components (eq. (19) with its levels shifted by b0, finest level L-1):
+  // +1 on jx + jt = L-1+b0 (jx = b0..L-1), -1 on jx + jt = L-2+b0 (jx = b0..L-2)
   long long off = 0;
+  p->cidx.assign(2 * (J + 1), -1);
   auto add = [&](int a, int b, int sgn) {
     Comp c{};
     c.a = a;
@@ -1024,10 +1077,11 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
     c.nq = (1 << b) + 1;
     c.off = off;
     off += (long long)c.nsp * c.nq;
+    p->cidx[2 * a + (sgn > 0 ? 0 : 1)] = (int)p->comps.size();
     p->comps.push_back(c);
   };
-  for (int a = 1; a <= J; ++a) add(a, L - a, +1);
-  for (int a = 1; a <= J - 1; ++a) add(a, L - 1 - a, -1);
+  for (int a = b0; a <= J; ++a) add(a, L - 1 + b0 - a, +1);
+  for (int a = b0; a <= J - 1; ++a) add(a, L - 2 + b0 - a, -1);
   p->nsparse = off;
   p->nsp_fine = d == 2 ? (long long)(N - 1) * (N - 1) : (N - 1);
   // 1-D variable speed: spatial levels above kEigMaxLevel are solved by the
@@ -1073,11 +1127,7 @@ sg_status sg_assemble(int d, const double *len, const int *ncell, const double *
     if (!p->blockc[ci] && !p->fdmc[ci]) p->nsparse2 += (long long)C.nsp * C.nq;
   }
   const int ntf = N + 1;
-  auto comp_index = [&](int a, int k) -> int {  // k=0 plus, 1 minus
-    if (k == 0) return a - 1;
-    if (a > J - 1) return -1;
-    return J + a - 1;
-  };
+  auto comp_index = [&](int a, int k) -> int { return p->cidx[2 * a + k]; };  // k=0 plus, 1 minus
 
   sg_status st;
   // ---- time levels, tap tables ------------------------------------------
@@ -1747,7 +1797,7 @@ sg_status sg_energy_setup(sg_problem *p, int K, const double *times) {
   auto spec = [&](bool deriv) {
     return [&, deriv](int a, int k) {
       ChanSpec cs;
-      const int ci = k == 0 ? a - 1 : (a <= J - 1 ? J + a - 1 : -1);
+      const int ci = p->cidx[2 * a + k];
       if (ci < 0) return cs;
       const Comp &C = p->comps[ci];
       cs.active = 1;
@@ -1888,7 +1938,7 @@ sg_status sg_l2_setup(sg_problem *p) {
   const Geometry gl = make_geometry(p->d, J, K, p->prol_target, p->prol_ts);
   auto spec = [&](int a, int k) {
     ChanSpec cs;
-    const int ci = k == 0 ? a - 1 : (a <= J - 1 ? J + a - 1 : -1);
+    const int ci = p->cidx[2 * a + k];
     if (ci < 0) return cs;
     const Comp &C = p->comps[ci];
     cs.active = 1;

@@ -177,8 +177,8 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs &A, const doubl
   stream_block(lin, ntileD, g.nchunk, tile, chunk);
   const int tx = tile % g.ntile;
   const int ty = (D == 2) ? tile / g.ntile : 0;
-  const int n0 = chunk * g.chunk;
-  const int n1 = min(n0 + g.chunk, g.ntf);
+  int n0, n1;
+  chunk_span(g, chunk, n0, n1);
   const long long nsp = (D == 2) ? (long long)g.nxf * g.nxf : g.nxf;
   const int R = g.R;
   const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
@@ -377,7 +377,8 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs &A, const doubl
     }
   }
   // final flush of the open time nodes (s_q still holds the last batch; the
-  // level-J channels have q0 = 0 throughout, so their nodes are q = 0, 1, 2)
+  // level-J channels keep one window per time chunk, so their nodes are the
+  // chunk's q0 + 0, 1, 2, stored relative to it)
 #pragma unroll
   for (int k = 0; k < NC0; ++k) {
     const Channel &C = A.ch[(g.J - 1) * 2 + k];
@@ -386,7 +387,8 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs &A, const doubl
     for (int o = 0; o < 3; ++o)
 #pragma unroll
       for (int e = 0; e < EPT; ++e)
-        A.part[part_at(C, k, 0, o, (D == 2 ? (fy0 + e) * TS : 0) + fx)] = racc0[e][k][o];
+        A.part[part_at(C, k, 0, s_qlo[k] + o, (D == 2 ? (fy0 + e) * TS : 0) + fx)] =
+            racc0[e][k][o];
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
@@ -594,7 +596,8 @@ __device__ __forceinline__ void restrict_w_body(const RestrictArgs &A, const dou
   const int tx = 2 * (grp % ng) + (wave & 1), ty = 2 * (grp / ng) + (wave >> 1);
   if (tx >= nt || ty >= nt) return;  // no workgroup barrier below
   const int tile = ty * nt + tx, ntileD = nt * nt;
-  const int n0 = chunk * g.chunk, n1 = min(n0 + g.chunk, g.ntf);
+  int n0, n1;
+  chunk_span(g, chunk, n0, n1);
   const long long nsp = (long long)g.nxf * g.nxf;
   const int R = g.R;
   const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
@@ -848,7 +851,8 @@ __device__ __forceinline__ void restrict_w_body(const RestrictArgs &A, const dou
           (A.coarse + ((long long)tile * g.ntf + n) * SH::size(R))[lane_off(own[i].j)] = val[i];
     }
   }
-  // final flush of the open time nodes (level-J channels: q0 = 0 throughout)
+  // final flush of the open time nodes (level-J channels: one window per
+  // time chunk, stored relative to its q0)
 #pragma unroll
   for (int k = 0; k < NC0; ++k) {
     const Channel &C = A.ch[(g.J - 1) * 2 + k];
@@ -944,8 +948,8 @@ __device__ __forceinline__ void reduce_body(const Geometry &g, const Channel *__
   if (D == 2) tile_range(TS, r, Py, g.ntile, ty0, ty1);
   double acc = 0.0;
   for (int c = 0; c < g.nchunk; ++c) {
-    const int cn0 = c * g.chunk;
-    const int cn1 = min(cn0 + g.chunk, g.ntf);
+    int cn0, cn1;
+    chunk_span(g, c, cn0, cn1);
     const int qlo = gld(C.q0, cn0), qhi = gld(C.q0, cn1 - 1) + 2;
     if (q < qlo || q > qhi) continue;
     for (int ty = ty0; ty <= ty1; ++ty) {
@@ -1197,8 +1201,8 @@ __device__ __forceinline__ void prolong_body(const ProlongArgs &A, const double 
   stream_block(lin, (D == 2) ? g.ntile * g.ntile : g.ntile, g.nchunk, tile, chunk);
   const int tx = tile % g.ntile;
   const int ty = (D == 2) ? tile / g.ntile : 0;
-  const int n0 = chunk * g.chunk;
-  const int n1 = min(n0 + g.chunk, g.ntf);
+  int n0, n1;
+  chunk_span(g, chunk, n0, n1);
   const long long nsp = (D == 2) ? (long long)g.nxf * g.nxf : g.nxf;
   const int R = g.R;
   const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
@@ -1250,7 +1254,8 @@ __device__ __forceinline__ void prolong_body(const ProlongArgs &A, const double 
       for (int o = 0; o < 4; ++o) cw[i][k][o] = coef(C, q + o, coff[i]);
     }
   }
-  // level-J channels belong to time level b = 1 (q0 = 0 on every slab)
+  // level-J channels keep one time window per chunk (the chunks are cut
+  // where it moves): nodes q0(n0) + 0, 1, 2
   const int lo0x = tile_lo(TS, tx, 0, MODE), lo0y = tile_lo(TS, ty, 0, MODE);
   double rc[EPT0][NC0][3];
 #pragma unroll
@@ -1265,8 +1270,9 @@ __device__ __forceinline__ void prolong_body(const ProlongArgs &A, const double 
       const Channel &C = A.ch[(g.J - 1) * 2 + k];
       rc[e][k][0] = rc[e][k][1] = rc[e][k][2] = 0.0;
       if (!C.active) continue;
+      const int qj = gld(C.q0, n0);  // the chunk's window (fixed within the chunk)
 #pragma unroll
-      for (int o = 0; o < 3; ++o) rc[e][k][o] = coef(C, o, off);
+      for (int o = 0; o < 3; ++o) rc[e][k][o] = coef(C, qj + o, off);
     }
   }
   double basev[EPT0];
@@ -1529,7 +1535,8 @@ __device__ __forceinline__ void prolong_w_body(const ProlongArgs &A, const doubl
   stream_block(lin, ngx * nt, g.nchunk, grp, chunk);
   const int tx = 4 * (grp % ngx) + wave, ty = grp / ngx;
   if (tx >= nt || ty >= nt) return;  // no workgroup barrier below
-  const int n0 = chunk * g.chunk, n1 = min(n0 + g.chunk, g.ntf);
+  int n0, n1;
+  chunk_span(g, chunk, n0, n1);
   const long long nsp = (long long)g.nxf * g.nxf;
   const int R = g.R;
   const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
@@ -1576,9 +1583,11 @@ __device__ __forceinline__ void prolong_w_body(const ProlongArgs &A, const doubl
     }
 
   // ---- fine nodes: lane = column fx, rows fy0 .. fy0+3; level-J channel
-  // (q0 = 0 throughout) and base ----
+  // (one time window per chunk) and base ----
   const int fx = lane & 15, fy0 = (lane >> 4) * EF;
   const Channel &CJ = A.ch[(g.J - 1) * 2];
+  // the chunk's time window of the level-J channel (fixed within the chunk)
+  const int qj = CJ.active ? ld_const(CJ.q0, n0) : 0;
   const int Px = TS * tx + fx;
   double rc[EF][3], basev[EF];
 #pragma unroll
@@ -1586,7 +1595,7 @@ __device__ __forceinline__ void prolong_w_body(const ProlongArgs &A, const doubl
     const int Py = TS * ty + fy0 + e;
     const int off = interior(Px, g.nxf) && interior(Py, g.nxf) ? (Px - 1) + (Py - 1) * g.nxf : -1;
 #pragma unroll
-    for (int o = 0; o < 3; ++o) rc[e][o] = CJ.active ? coef(CJ, o, off) : 0.0;
+    for (int o = 0; o < 3; ++o) rc[e][o] = CJ.active ? coef(CJ, qj + o, off) : 0.0;
     basev[e] = (base != nullptr && off >= 0) ? base[off] : 0.0;
   }
   // coarse values of the next slab (unconditional loads from valid addresses)
@@ -1764,7 +1773,8 @@ __device__ __forceinline__ void prolong_wm_body(const ProlongArgs &A, const doub
   stream_block(lin, ngx * nt, g.nchunk, grp, chunk);
   const int tx = 4 * (grp % ngx) + wave, ty = grp / ngx;
   if (tx >= nt || ty >= nt) return;  // no workgroup barrier below
-  const int n0 = chunk * g.chunk, n1 = min(n0 + g.chunk, g.ntf);
+  int n0, n1;
+  chunk_span(g, chunk, n0, n1);
   const long long nsp = (long long)g.nxf * g.nxf;
   const int R = g.R;
   const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
@@ -1814,6 +1824,8 @@ __device__ __forceinline__ void prolong_wm_body(const ProlongArgs &A, const doub
   const int fx = lane & 15, fy0 = (lane >> 4) * NO;
   const int lo0x = tile_lo(TS, tx, 0, 1), lo0y = tile_lo(TS, ty, 0, 1);
   const Channel &CJ = A.ch[(g.J - 1) * 2];
+  // the chunk's time window of the level-J channel (fixed within the chunk)
+  const int qj = CJ.active ? ld_const(CJ.q0, n0) : 0;
 #pragma unroll
   for (int o = 0; o < 3; ++o) {
 #pragma unroll
@@ -1822,7 +1834,7 @@ __device__ __forceinline__ void prolong_wm_body(const ProlongArgs &A, const doub
       if (p >= L0) continue;
       const int Px = lo0x + p % NF, Py = lo0y + p / NF;
       const int off = interior(Px, g.nxf) && interior(Py, g.nxf) ? (Px - 1) + (Py - 1) * g.nxf : -1;
-      s_f[p] = CJ.active ? coef(CJ, o, off) : 0.0;
+      s_f[p] = CJ.active ? coef(CJ, qj + o, off) : 0.0;
     }
     wave_sync();
 #pragma unroll
@@ -2024,7 +2036,8 @@ __global__ void __launch_bounds__(256, 2) k_energy_w(const ProlongArgs A,
   const int tx = 4 * (grp % ngx) + wave, ty = grp / ngx;
   if (tx >= nt || ty >= nt) return;  // no workgroup barrier below
   const int tile = ty * nt + tx, ntileD = nt * nt;
-  const int n0 = chunk * g.chunk, n1 = min(n0 + g.chunk, g.ntf);
+  int n0, n1;
+  chunk_span(g, chunk, n0, n1);
   const int R = g.R;
   const int N = g.nxf + 1;  // elements per axis
   const bool use_coarse = g.A0 > 1 && A.coarse != nullptr;
@@ -2072,11 +2085,13 @@ __global__ void __launch_bounds__(256, 2) k_energy_w(const ProlongArgs A,
 
   // ---- the lane's nodes: own column fx, rows fy0 .. fy0+3; ring node
   // lane < 33: (16, lane) for lane <= 16, else (lane - 17, 16).  Level-J
-  // channel coefficients (q0 = 0 throughout) and u0 at each ----
+  // channel coefficients (one time window per chunk) and u0 at each ----
   const int fx = lane & 15, fy0 = (lane >> 4) * EF;
   const bool has_ring = lane < NRING;
   const int rx = lane <= TS ? TS : lane - (TS + 1), ry = lane <= TS ? lane : TS;
   const Channel &CJ = A.ch[(g.J - 1) * 2];
+  // the chunk's time window of the level-J channel (fixed within the chunk)
+  const int qj = CJ.active ? ld_const(CJ.q0, n0) : 0;
   double rc[EF + 1][3], basev[EF + 1];
 #pragma unroll
   for (int e = 0; e <= EF; ++e) {
@@ -2085,7 +2100,7 @@ __global__ void __launch_bounds__(256, 2) k_energy_w(const ProlongArgs A,
     const bool in = (e < EF || has_ring) && interior(Px, g.nxf) && interior(Py, g.nxf);
     const int off = in ? (Px - 1) + (Py - 1) * g.nxf : -1;
 #pragma unroll
-    for (int o = 0; o < 3; ++o) rc[e][o] = CJ.active ? coef(CJ, o, off) : 0.0;
+    for (int o = 0; o < 3; ++o) rc[e][o] = CJ.active ? coef(CJ, qj + o, off) : 0.0;
     basev[e] = (A.base != nullptr && off >= 0) ? A.base[off] : 0.0;
   }
   // c^2 of the lane's elements (lower-left nodes (fx, fy0 + e)); zero for

@@ -50,7 +50,17 @@ struct Geometry {
   int A0;       // coarsest in-tile spatial level = J - R
   int chunk;    // fine slabs per time chunk
   int nchunk;   // number of chunks
+  int phase;    // chunk c covers slabs [c chunk - phase, (c+1) chunk - phase) within
+                // [0, ntf): shifts the chunk starts onto the slabs where the finest
+                // level's time window moves (a coarsest level above 1)
 };
+
+// Slabs [n0, n1) of time chunk c.
+__host__ __device__ inline void chunk_span(const Geometry &g, int c, int &n0, int &n1) {
+  const int a = c * g.chunk - g.phase;
+  n0 = a > 0 ? a : 0;
+  n1 = a + g.chunk < g.ntf ? a + g.chunk : g.ntf;
+}
 
 // Number of in-tile nodes per axis at level offset r (r = J - a).
 //   mode 0: region [TS t, TS t + TS - 1] (restriction and plain prolongation)

@@ -1,0 +1,211 @@
+"""GPU parity of the coarsest-level parameter b0 (h_0 = 2^-b0, the
+coarse-mesh study of Sec. 6.3) against the oracle's Problem(..., b0).
+
+The finest spatial level's component has time level b0, so its time window
+moves during the stream: the streaming passes cut their time chunks where it
+moves.  Checked: the combined forward U, every component's load and solution,
+the adjoint (df, du0, dv0) on whole arrays; the L^2(Q_T) error by quadrature;
+the energy at instants off the nodes; a batch mixing b0 with the default and
+its captured graph (bitwise against each problem's own runs).  Bar 1e-10.
+"""
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import Problem, method
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def rel(a, b):
+    a = np.asarray(a).reshape(-1)
+    b = np.asarray(b).reshape(-1)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _dev(x):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def _solver(spec):
+    import paper_2606_09688_amd as sg
+    return sg.SparseGridWave(*spec.args(), b0=spec.b0)
+
+
+def _speeds(n, seed):
+    return list(np.random.default_rng(seed).uniform(0.5, 2.0, n))
+
+
+CASES = [
+    # (d, lengths, ncell, c_vals, T, L, b0)
+    (1, [1.0], [1], [1.0], 1.0, 7, 2),
+    (1, [1.3], [1], [0.8], 1.2, 7, 3),
+    (1, [1.0], [1], [1.0], 1.0, 6, 5),                    # b0 = L-1: the full grid
+    (1, [1.0], [4], [1.0, 0.6, 1.7, 0.9], 1.1, 7, 2),     # variable speed
+    (1, [2.0], [1], [1.3], 1.0, 11, 3),                   # 4 tiles, coarse levels
+    (2, [1.0, 0.8], [1, 1], [0.9], 1.5, 5, 2),
+    (2, [1.0, 1.0], [1, 1], [1.0], 1.0, 7, 3),            # 2 x 2 tiles
+    (2, [1.2, 1.0], [1, 1], [1.1], 0.9, 8, 2),            # 16 x 16 tiles, coarse levels
+    (2, [1.0, 1.0], [4, 4], _speeds(16, 91), 1.0, 6, 2),  # variable speed: dense pencils
+    (2, [1.0, 1.0], [4, 4], _speeds(16, 92), 1.0, 8, 2),  # strips at levels 6, 7
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"d{c[0]}L{c[5]}b{c[6]}n{c[2][0]}")
+def test_offset_forward_and_adjoint_parity(case):
+    torch = _torch()
+    d, lengths, ncell, c_vals, T, L, b0 = case
+    print(f"case d={d} L={L} b0={b0} ncell={ncell}", flush=True)
+    spec = workloads.Spec(d, lengths, ncell, c_vals, T, L, b0=b0)
+    data = workloads.random_data(spec, 700 + 10 * L + b0)
+    orc = Problem(*spec.args(), b0=b0)
+    sv = _solver(spec)
+    assert sv.n_components == len(orc.comps) == 2 * (L - 1 - b0) + 1
+    f, u0, v0, g = (_dev(data[k]) for k in ("f", "u0", "v0", "g"))
+    U = sv.solve(f, u0, v0)
+    torch.cuda.synchronize()
+    U_ref = orc.forward(data["f"], data["u0"], data["v0"]).reshape(spec.shape())
+    e = rel(U.cpu().numpy(), U_ref)
+    print(f"  forward rel l2 {e:.3e}", flush=True)
+    assert e <= TOL
+    for ci, (jx, jt, s) in enumerate(orc.comps):
+        assert sv.components()[ci][:3] == (jx, jt, s)
+        b_ref = orc.load(jx, jt, data["f"], data["u0"], data["v0"])
+        assert rel(sv.component(ci, 0), b_ref) <= TOL, (jx, jt)
+        assert rel(sv.component(ci, 1), orc.solve(jx, jt, b_ref)) <= TOL, (jx, jt)
+    df, du0, dv0 = sv.adjoint(g)
+    torch.cuda.synchronize()
+    for name, got, ref in zip(("df", "du0", "dv0"), (df, du0, dv0), orc.adjoint(data["g"])):
+        e = rel(got.cpu().numpy(), ref)
+        print(f"  adjoint {name} rel l2 {e:.3e}", flush=True)
+        assert e <= TOL, name
+
+
+def _u(d):
+    if d == 1:
+        return lambda t, x: np.sin(np.pi * x) * np.sin(2.0 * t)
+    return lambda t, x, y: np.sin(np.pi * x) * np.cos(2.0 * y) * np.sin(2.0 * t)
+
+
+@pytest.mark.parametrize("case", [(1, [1.0], [2], [1.0, 0.5], 1.3, 9, 3),
+                                  (2, [1.0, 0.8], [1, 1], [0.9], 0.8, 6, 2)],
+                         ids=lambda c: f"d{c[0]}L{c[5]}b{c[6]}")
+def test_offset_l2_error_parity(case):
+    _torch()
+    d, lengths, ncell, c_vals, T, L, b0 = case
+    print(f"case d={d} L={L} b0={b0}", flush=True)
+    spec = workloads.Spec(d, lengths, ncell, c_vals, T, L, b0=b0)
+    data = workloads.random_data(spec, 800 + L)
+    orc = Problem(*spec.args(), b0=b0)
+    sols = orc.component_solutions(data["f"], data["u0"], data["v0"])
+    u = _u(d)
+    e_ref, n_ref = method.l2_error_rule(orc, sols, data["u0"], u)
+    sv = _solver(spec)
+    u0 = _dev(data["u0"])
+    sv.solve(_dev(data["f"]), u0, _dev(data["v0"]))
+    sv.l2_setup()
+    pts = sv.l2_points()
+    if d == 1:
+        uq = u(pts["t"][:, None], pts["xq"][None, :])
+    else:
+        uq = u(pts["t"][:, None, None], pts["xq"][None, None, :], pts["yq"][None, :, None])
+    out = sv.l2_error(u0, _dev(uq)).cpu().numpy()
+    ee, en = abs(out[0] - e_ref) / e_ref, abs(out[1] - n_ref) / n_ref
+    print(f"  int (u-u_h)^2 rel err {ee:.3e}, int u^2 rel err {en:.3e}", flush=True)
+    assert ee <= TOL and en <= TOL
+
+
+@pytest.mark.parametrize("case", [(1, [1.0], [1], [1.0], 1.0, 7, 2, 90),
+                                  (2, [1.2, 1.0], [1, 1], [1.1], 0.9, 8, 2, 200)],
+                         ids=lambda c: f"d{c[0]}L{c[5]}b{c[6]}K{c[7]}")
+def test_offset_energy_parity(case):
+    _torch()
+    d, lengths, ncell, c_vals, T, L, b0, K = case
+    print(f"case d={d} L={L} b0={b0} K={K}", flush=True)
+    spec = workloads.Spec(d, lengths, ncell, c_vals, T, L, b0=b0)
+    data = workloads.random_data(spec, 900 + L)
+    orc = Problem(*spec.args(), b0=b0)
+    sols = orc.component_solutions(data["f"], data["u0"], data["v0"])
+    rng = np.random.default_rng(L + b0)
+    t = np.linspace(0.0, T, K)
+    t[1:-1] += rng.uniform(-0.2, 0.2, K - 2) * T / (K - 1)
+    assert np.all(np.diff(t) > 0) and np.diff(t).max() <= T / 2 ** orc.J
+    E_ref = method.energy(orc, sols, data["u0"], t)
+    sv = _solver(spec)
+    u0 = _dev(data["u0"])
+    sv.solve(_dev(data["f"]), u0, _dev(data["v0"]))
+    sv.energy_setup(t)
+    E = sv.energy(u0).cpu().numpy()
+    err = np.abs(E - E_ref).max() / np.abs(E_ref).max()
+    print(f"  energy max rel err {err:.3e}", flush=True)
+    assert err <= TOL
+
+
+def test_offset_in_a_batch_and_its_graph():
+    """Problems with b0 = 1, 2 and 3 in one batch: the eager batch and every
+    replay of its captured graph equal each problem's own runs bitwise."""
+    torch = _torch()
+    import paper_2606_09688_amd as sg
+    specs = [workloads.Spec(2, [1.0, 1.0], [1, 1], [1.0], 1.0, 7, b0=2),
+             workloads.Spec(2, [1.0, 1.0], [1, 1], [1.0], 1.0, 7),
+             workloads.Spec(1, [1.0], [2], [1.0, 0.5], 1.0, 9, b0=3),
+             workloads.Spec(2, [1.2, 1.0], [4, 4], _speeds(16, 93), 0.9, 8, b0=2)]
+    svs, ins, eager = [], [], []
+    for k, spec in enumerate(specs):
+        print(f"member {k}: {spec}", flush=True)
+        sv = _solver(spec)
+        data = workloads.random_data(spec, 950 + k)
+        f, u0, v0, g = (_dev(data[x]) for x in ("f", "u0", "v0", "g"))
+        U = sv.solve(f, u0, v0)
+        df, du0, dv0 = sv.adjoint(g)
+        svs.append(sv)
+        ins.append((f, u0, v0, g, data))
+        eager.append((U.clone(), df.clone(), du0.clone(), dv0.clone()))
+    torch.cuda.synchronize()
+    batch = sg.SparseGridBatch(svs)
+    outs = [tuple(torch.full_like(t, 7.0) for t in e) for e in eager]
+    batch.solve([x[0] for x in ins], [x[1] for x in ins], [x[2] for x in ins],
+                [o[0] for o in outs])
+    batch.adjoint([x[3] for x in ins], [o[1] for o in outs], [o[2] for o in outs],
+                  [o[3] for o in outs])
+    torch.cuda.synchronize()
+    for k, (o, e) in enumerate(zip(outs, eager)):
+        assert all(torch.equal(a, b) for a, b in zip(o, e)), k
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        batch.capture([x[0] for x in ins], [x[1] for x in ins], [x[2] for x in ins],
+                      [o[0] for o in outs], [x[3] for x in ins], [o[1] for o in outs],
+                      [o[2] for o in outs], [o[3] for o in outs], stream=s)
+    for rep in range(2):
+        for o in outs:
+            for t in o:
+                t.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            batch.replay(stream=s)
+        s.synchronize()
+        for k, (o, e) in enumerate(zip(outs, eager)):
+            assert all(torch.equal(a, b) for a, b in zip(o, e)), (rep, k)
+    spec, data = specs[3], ins[3][4]
+    U_ref = Problem(*spec.args(), b0=spec.b0).forward(data["f"], data["u0"], data["v0"])
+    assert rel(outs[3][0].cpu().numpy(), U_ref.reshape(spec.shape())) <= TOL
+
+
+def test_offset_out_of_range_is_refused():
+    _torch()
+    import paper_2606_09688_amd as sg
+    for b0 in (0, 5):
+        with pytest.raises(sg.SGError, match="coarsest level"):
+            sg.SparseGridWave(1, [1.0], [1], [1.0], 1.0, 5, b0=b0)
