@@ -259,6 +259,38 @@ def time_l2(sv, u0, stream, reps=3):
     return res
 
 
+def coarse_mesh_study(sg, spec, sv, f, u0, v0, stream, b0s=(1, 2, 3), reps=3):
+    """The coarse-mesh study of Sec. 6.3 (Fig. 10) on the benchmark workload:
+    the same finest level with coarsest levels b0 (h_0 = 2^-b0): components,
+    sparse DoFs, forward time (eager, after a warm-up) and the relative
+    L^2(Q_T) error of the manufactured solution."""
+    import torch
+    U = torch.empty(sv.shape, dtype=torch.float64, device=u0.device)
+    out = {}
+    for b0 in b0s:
+        svb = sv if b0 == 1 else sg.SparseGridWave(*spec.args(), tuned=True, b0=b0)
+        with torch.cuda.stream(stream):
+            svb.solve(f, u0, v0, out=U, stream=stream)
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            for _ in range(reps):
+                svb.solve(f, u0, v0, out=U, stream=stream)
+            e1.record(stream)
+        stream.synchronize()
+        l2 = time_l2(svb, u0, stream, reps=1)
+        out[str(b0)] = {"components": svb.n_components, "n_sparse": svb.n_sparse,
+                        "forward_ms": e0.elapsed_time(e1) / reps,
+                        "relative_l2_error": l2["relative_l2_error"]}
+        if svb is not sv:
+            svb.close()
+    del U
+    torch.cuda.empty_cache()
+    return out
+
+
 def _gaussians_on_device(spec, centres, dev, width=0.05):
     """The batch workload's source f (sum of space-time Gaussians with the
     given centres (x, y, t)) generated directly in device memory; each
@@ -280,9 +312,8 @@ def c5_batch(args, stream):
     """The 256-problem batch (d=2, L ~ U{6..10}, 4x4 blocks of wave speed in
     [0.5, 2], f = three space-time Gaussians, u0 = v0 = 0).
     A step is the forward and the adjoint of every problem, replayed from one
-    captured HIP graph (streaming passes per problem on branch streams, each
-    solve stage one launch over all problems; the adjoint after the
-    forward).  Three fine arrays per problem fit in HBM
+    captured HIP graph (every stage, streaming or solve, one launch over all
+    problems per kernel variant; the adjoint after the forward).  Three fine arrays per problem fit in HBM
     (3 x 68 GiB for the seed-0 draw): f, U and df; the timed cotangent is the
     source array itself (both directions only read it).  Parity of this
     workload, with an N(0,1) cotangent, is the business of the tests."""
@@ -550,6 +581,7 @@ def main():
     if not args.no_energy:
         energy_out = time_energy(sv, u0, stream, spec.T, K_e, nfull // sv.shape[0])
         l2_out = time_l2(sv, u0, stream)
+        l2_out["coarse_mesh_study"] = coarse_mesh_study(sg, spec, sv, f, u0, v0, stream)
 
     # dominant fine-grid kernel (timed inside the last timed graph replay when
     # the runtime records captured events, else in the eager runs): each
