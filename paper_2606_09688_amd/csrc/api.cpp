@@ -906,23 +906,36 @@ sg_status build_fdm(sg_problem *p, const std::vector<TimeLevel> &tl_host) {
     vf.push_back(hf);
     va.push_back(ha);
     // strip sine transforms along y: per eigenvalue, one GEMM batched over
-    // the strips, [m x m] x [m x 2n] (complex rows as 2n reals)
+    // the strips (complex values as pairs of reals).  The transformed strip
+    // is stored mode-fastest, [x][re/im][l] (2n rows of m), so that the
+    // tridiagonal sweeps along x read the modes of a wave side by side:
+    //   forward  Y_k = X_k^T S   ([2n x m], X_k read transposed)
+    //   inverse  X_k = S Y_k^T   ([m x 2n], Y_k read transposed)
+    // (S, the orthonormal sine transform of the strip's m rows, is symmetric)
     std::vector<GemmDesc> pgf, pgi;
     int ptf = 0, pti = 0;
     for (int u = 0; u < T.nu; ++u) {
-      GemmDesc g{};
-      g.A = dst[m];
-      g.M = m; g.N = 2 * n; g.K = m;
-      g.lda = m; g.ldb = 2 * n; g.ldc = 2 * n;
-      g.sA = 0; g.sB = g.sC = 2LL * n * (m + 1);
-      g.batch = ns;
-      g.tm = (m + TG - 1) / TG;
-      g.tn = (2 * n + TG - 1) / TG;
-      const int tiles = ns * g.tm * g.tn;
-      GemmDesc a = g;
-      a.B = h.X + 2 * u * nn;
+      GemmDesc a{};
+      a.B = dst[m];
+      a.M = 2 * n; a.N = m; a.K = m;
+      a.lda = 2 * n; a.ldb = m; a.ldc = m;
+      a.ta = 1;
+      a.sA = a.sC = 2LL * n * (m + 1); a.sB = 0;
+      a.batch = ns;
+      a.tm = (2 * n + TG - 1) / TG;
+      a.tn = (m + TG - 1) / TG;
+      GemmDesc b{};
+      b.A = dst[m];
+      b.M = m; b.N = 2 * n; b.K = m;
+      b.lda = m; b.ldb = m; b.ldc = 2 * n;
+      b.tb = 1;
+      b.sA = 0; b.sB = b.sC = 2LL * n * (m + 1);
+      b.batch = ns;
+      b.tm = (m + TG - 1) / TG;
+      b.tn = (2 * n + TG - 1) / TG;
+      const int tiles = ns * a.tm * a.tn;
+      a.A = h.X + 2 * u * nn;
       a.C = h.Y + 2 * u * nn;
-      GemmDesc b = g;
       b.B = h.Y + 2 * u * nn;
       b.C = h.X + 2 * u * nn;
       a.tile0 = tf_tiles;
@@ -930,7 +943,7 @@ sg_status build_fdm(sg_problem *p, const std::vector<TimeLevel> &tl_host) {
       gf.push_back(a);
       gi.push_back(b);
       GemmDesc aa = a, ab = b;
-      aa.B = ha.X + 2 * u * nn;
+      aa.A = ha.X + 2 * u * nn;
       aa.C = ha.Y + 2 * u * nn;
       ab.B = ha.Y + 2 * u * nn;
       ab.C = ha.X + 2 * u * nn;

@@ -222,10 +222,21 @@ __global__ void __launch_bounds__(64) k_fdm_tri(const FdmDesc *__restrict__ ds, 
   const int t = (int)(g - D.tri0);
   const int l = t % D.m, k = (t / D.m) % D.ns, u = t / (D.m * D.ns);
   const cx lam = cld(D.lam + 2 * u);
-  const int n = D.n;
-  const long long row = ((long long)u * n + (long long)k * (D.m + 1) + l) * n;
-  double *Yr = D.Y + 2 * row;
-  double *Wr = correction ? D.X + 2 * row : Yr;
+  const int n = D.n, m = D.m;
+  // the strip's transformed values, mode-fastest: (x, re/im, l) at
+  // (2 x + re/im) m + l from the strip's start (the forward sweep of the
+  // correction keeps its values in the same layout in X, whose strip rows
+  // are free at this point); a wave's lanes read side by side
+  const long long strip = 2 * (((long long)u * n + (long long)k * (m + 1)) * n);
+  double *Yr = D.Y + strip + l;
+  double *Wr = (correction ? D.X + strip : D.Y + strip) + l;
+  auto ldv = [&](const double *b, int x) -> cx {
+    return {b[2LL * x * m], b[(2LL * x + 1) * m]};
+  };
+  auto stv = [&](double *b, int x, cx v) {
+    b[2LL * x * m] = v.r;
+    b[(2LL * x + 1) * m] = v.i;
+  };
   const double *xlo = nullptr, *xhi = nullptr;
   double s0 = 0.0, s1 = 0.0;
   if (correction) {
@@ -236,7 +247,7 @@ __global__ void __launch_bounds__(64) k_fdm_tri(const FdmDesc *__restrict__ ds, 
     if (k + 1 <= D.ni) xhi = D.Xg + 2 * (((size_t)u * D.ni + k) * n);
   }
   auto rhs = [&](int x) -> cx {
-    if (!correction) return cld(Yr + 2 * x);
+    if (!correction) return ldv(Yr, x);
     cx r = {0.0, 0.0};
     if (xlo) r = cadd(r, cscl(cpl_apply(D, k, lam, xlo, x), s0));
     if (xhi) r = cadd(r, cscl(cpl_apply(D, k, lam, xhi, x), s1));
@@ -256,7 +267,7 @@ __global__ void __launch_bounds__(64) k_fdm_tri(const FdmDesc *__restrict__ ds, 
     for (int c = 0; c < FCH; ++c) {
       if (x0 + c < n) {
         prev = csub(r[c], cmul(el[c], prev));
-        cst(Wr + 2 * (x0 + c), prev);
+        stv(Wr, x0 + c, prev);
       }
     }
   }
@@ -267,18 +278,18 @@ __global__ void __launch_bounds__(64) k_fdm_tri(const FdmDesc *__restrict__ ds, 
 #pragma unroll
     for (int c = 0; c < FCH; ++c) {
       const int x = max(x1 - c, 0);
-      w[c] = cld(Wr + 2 * x);
+      w[c] = ldv(Wr, x);
       iv[c] = cld(fac_at(D, kInvD, u, k, x, l));
       cx dg;
       tri_row(D, k, l, lam, x, dg, of[c]);
-      if (correction) yo[c] = cld(Yr + 2 * x);
+      if (correction) yo[c] = ldv(Yr, x);
     }
 #pragma unroll
     for (int c = 0; c < FCH; ++c) {
       const int x = x1 - c;
       if (x >= 0) {
         z = cmul(csub(w[c], cmul(of[c], z)), iv[c]);
-        cst(Yr + 2 * x, correction ? csub(yo[c], z) : z);
+        stv(Yr, x, correction ? csub(yo[c], z) : z);
       }
     }
   }
@@ -287,19 +298,33 @@ __global__ void __launch_bounds__(64) k_fdm_tri(const FdmDesc *__restrict__ ds, 
 // E[u][k][0|1][x] = the strip solution at the strip's first / last row:
 // the inverse sine transform restricted to those rows
 __global__ void k_fdm_edge(const FdmDesc *__restrict__ ds, int nd, long long total) {
-  const long long g = gid64();
-  if (g >= total) return;
+  // 16 lanes per (u, k, x): the strip's values at x are mode-fastest (see
+  // k_fdm_tri), so lane j sums the modes l = j, j + 16, ... (coalesced) and
+  // the 16 partial sums are combined by a butterfly within the lane group
+  constexpr int G = 16;
+  const long long g = gid64() / G;
+  const int j = (int)(threadIdx.x % G);
+  if (g >= total) return;  // whole lane groups
   const FdmDesc &D = cref(ds, find_fdm(ds, nd, g, kEdge));
   const int t = (int)(g - D.edge0);
   const int x = t % D.n, k = (t / D.n) % D.ns, u = t / (D.n * D.ns);
-  const double *Y = D.Y + 2 * (((long long)u * D.n + (long long)k * (D.m + 1)) * D.n + x);
+  const double *Y = D.Y + 2 * (((long long)u * D.n + (long long)k * (D.m + 1)) * D.n) +
+                    2LL * x * D.m;
   cx f = {0.0, 0.0}, la = {0.0, 0.0};
-  for (int l = 0; l < D.m; ++l) {
+  for (int l = j; l < D.m; l += G) {
     const double s = D.ym[2 * D.m + l];
-    const cx v = cscl(cld(Y + 2 * (long long)l * D.n), s);
+    const cx v = cscl(cx{Y[l], Y[D.m + l]}, s);
     f = cadd(f, v);
     la = (l & 1) ? csub(la, v) : cadd(la, v);
   }
+#pragma unroll
+  for (int o = G / 2; o >= 1; o >>= 1) {
+    f.r += __shfl_xor(f.r, o);
+    f.i += __shfl_xor(f.i, o);
+    la.r += __shfl_xor(la.r, o);
+    la.i += __shfl_xor(la.i, o);
+  }
+  if (j != 0) return;
   double *E = D.E + 2 * ((((size_t)u * D.ns + k) * 2) * D.n + x);
   cst(E, f);
   cst(E + 2 * D.n, la);
@@ -657,7 +682,7 @@ hipError_t launch_fdm_tri(const FdmDesc *d, int nd, const FdmTotals &t, int corr
 
 hipError_t launch_fdm_interface(const FdmDesc *d, int nd, const FdmTotals &t, hipStream_t s) {
   if (nd == 0 || t.iface == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fdm_edge, dim3(nblk(t.edge, 256)), dim3(256), 0, s, d, nd, t.edge);
+  hipLaunchKernelGGL(k_fdm_edge, dim3(nblk(t.edge * 16, 256)), dim3(256), 0, s, d, nd, t.edge);
   hipLaunchKernelGGL(k_fdm_iface, dim3(nblk(t.iface, 256)), dim3(256), 0, s, d, nd, t.iface);
   hipLaunchKernelGGL(k_fdm_gemv, dim3(nblk(t.gemv * 64, 256)), dim3(256), 0, s, d, nd, t.gemv);
   return hipGetLastError();

@@ -2779,15 +2779,28 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmDesc *__restric
   const double sgn = Dd.par ? -1.0 : 1.0;
   // global -> register staging; loads go to clamped valid addresses and are
   // selected, not branched
+  // staged element e of this thread: (m, k) of the A tile, (kb, n) of the B
+  // tile; consecutive threads take consecutive addresses of the stored
+  // operand (along k for A, n for B, or along m / kb when transposed)
+  const bool ta = FOLD == 0 && Dd.ta != 0, tb = FOLD == 0 && Dd.tb != 0;
+  auto a_at = [&](int e, int &m, int &k) {
+    const int i = tid + e * NT;
+    if (ta) { m = i % BM; k = i / BM; } else { m = i / BK; k = i % BK; }
+  };
+  auto b_at = [&](int e, int &kb, int &n) {
+    const int i = tid + e * NT;
+    if (tb) { kb = i % BK; n = i / BK; } else { kb = i / BN; n = i % BN; }
+  };
   double ra[EA], rb[EB];
   auto load_tile = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
-      const int i = tid + e * NT;
-      const int m = i / BK, k = i % BK;           // A: BM x BK
+      int m, k;
+      a_at(e, m, k);                                // A: BM x BK
       const int gm = row0 + m, gk = k0 + k;
       const bool oka = gm < M && gk < K;
-      const long long ia = oka ? (long long)gm * Dd.lda + gk : 0;
+      const long long ia =
+          oka ? (ta ? (long long)gk * Dd.lda + gm : (long long)gm * Dd.lda + gk) : 0;
       double va = Ap[ia];
       if (FOLD == 1 && fd) {
         const double vr = Ap[oka ? ia + nr1 - 2 * gk : 0];
@@ -2797,11 +2810,13 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmDesc *__restric
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      const int i = tid + e * NT;
-      const int kb = i / BN, n = i % BN;          // B: BK x BN
+      int kb, n;
+      b_at(e, kb, n);                               // B: BK x BN
       const int gkb = k0 + kb, gn = col0 + n;
       const bool okb = gkb < K && gn < N;
-      double vb = Bp[okb ? (long long)gkb * Dd.ldb + gn : 0];
+      const long long ib =
+          okb ? (tb ? (long long)gn * Dd.ldb + gkb : (long long)gkb * Dd.ldb + gn) : 0;
+      double vb = Bp[ib];
       if (FOLD == 2 && fd) {
         const double vr = Bp[okb ? (long long)(nr1 - gkb) * Dd.ldb + gn : 0];
         vb = gkb == hmid ? vb : vb + sgn * vr;
@@ -2818,13 +2833,15 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmDesc *__restric
   for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
-      const int i = tid + e * NT;
-      As[i / BK][i % BK] = ra[e];
+      int m, k;
+      a_at(e, m, k);
+      As[m][k] = ra[e];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      const int i = tid + e * NT;
-      Bs[i / BN][i % BN] = rb[e];
+      int kb, n;
+      b_at(e, kb, n);
+      Bs[kb][n] = rb[e];
     }
     __syncthreads();
     if (k0 + BK < K) load_tile(k0 + BK);

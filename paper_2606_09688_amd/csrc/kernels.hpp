@@ -134,6 +134,9 @@ struct GemmDesc {
   // subtracted for odd ones (par 1, k < nref/2); C's columns (fold 1) or rows
   // (fold 2) are the outputs 2 j' + par
   int nref, par;
+  // transposed operands (plain products only): ta, element (i, k) of A at
+  // k lda + i; tb, element (k, j) of B at j ldb + k
+  int ta, tb;
 };
 
 struct ModeTables {      // 1-D P1 eigenvalues per level and axis (unit c)
@@ -286,7 +289,9 @@ struct FdmDesc {
   const double *tin;     // time transform in, complex [nu][nq]
   const double *tout;    // time transform out, complex [nq][nu]
   const double *lam;     // eigenvalues, complex [nu]
-  double *X, *Y;         // complex [nu][n][n] work arrays (row-major y, x)
+  double *X, *Y;         // complex [nu][n][n] work arrays: X row-major (y, x); Y holds each
+                         // strip's y-transformed values mode-fastest, [x][re, im][l] from the
+                         // strip's first row (X's strip rows likewise during the correction)
   double *E;             // complex [nu][ns][2][n]: strip solutions at their first / last row
   double *G;             // complex [nu][ni][n]: interface right-hand sides
   double *Xg;            // complex [nu][ni][n]: interface solutions
