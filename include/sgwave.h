@@ -218,6 +218,18 @@ sg_status sg_host_time_level(int b, double T, double *A, double *Alo, double *B,
 sg_status sg_host_taps(int kind, int b, int J, double T, int *q0, double *w);
 
 /*
+ * The time chunks a streaming pass uses when the finest level's channel has
+ * the window q0 (ntf host values, one per slab; e.g. from sg_host_taps):
+ * starting from chunks of `chunk` slabs, the longest chunk length whose
+ * starts, shifted back by a phase, fall on every slab where q0 moves (the
+ * kernels keep the finest level's coefficients fixed within a chunk).  Chunk
+ * c covers slabs [c*chunk - phase, (c+1)*chunk - phase) within [0, ntf).
+ * Outputs (host): *out_chunk, *out_phase, *out_nchunk.  Host only.
+ */
+sg_status sg_host_time_chunks(int ntf, int chunk, const int *q0, int *out_chunk,
+                              int *out_phase, int *out_nchunk);
+
+/*
  * Energy of the computed solution (Sec. 6.3, the energy diagnostic):
  *   E(t) = 1/2 ||d_t u_h(t)||^2_{L2(Omega)} + 1/2 ||c grad u_h(t)||^2_{L2(Omega)}
  * for u_h = u^CF + u0, the lifted combination solution of the last sg_solve

@@ -9,6 +9,7 @@ this package only marshals torch tensors into it.
 """
 
 from .binding import (SparseGridWave, SparseGridBatch, SGWaveFunction, SGError, sgwave,  # noqa: F401
-                      host_pencil, host_pencil_2d, host_time_fdm, host_taps, host_time_level, lib,
+                      host_pencil, host_pencil_2d, host_time_fdm, host_taps, host_time_level,
+                      host_time_chunks, lib,
                       tuning_status,
                       LIB_PATH)

@@ -32,6 +32,8 @@ SIGNATURES = {
     "sg_assemble_offset": (ctypes.c_int, [ctypes.c_int, _c_dp, _c_ip, _c_dp, ctypes.c_double,
                                           ctypes.c_int, ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_void_p)]),
+    "sg_host_time_chunks": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_ip, _c_ip, _c_ip,
+                                           _c_ip]),
     "sg_solve": (ctypes.c_int, [ctypes.c_void_p] * 6),
     "sg_solve_plain": (ctypes.c_int, [ctypes.c_void_p] * 6),
     "sg_solve_static": (ctypes.c_int, [ctypes.c_void_p] * 6),
@@ -143,6 +145,17 @@ def host_taps(kind, b, J, T):
     check(lib().sg_host_taps(kind, b, J, float(T), q0.ctypes.data_as(_c_ip),
                              w.ctypes.data_as(_c_dp)), "sg_host_taps")
     return q0, w
+
+
+def host_time_chunks(q0, chunk):
+    """(chunk, phase, nchunk) of a streaming pass whose finest-level window
+    is q0 (sg_host_time_chunks)."""
+    import numpy as np
+    q = np.ascontiguousarray(q0, dtype=np.int32)
+    out = [ctypes.c_int() for _ in range(3)]
+    check(lib().sg_host_time_chunks(int(q.size), int(chunk), q.ctypes.data_as(_c_ip),
+                                    *[ctypes.byref(o) for o in out]), "sg_host_time_chunks")
+    return tuple(o.value for o in out)
 
 
 def host_time_fdm(b, T):

@@ -2064,6 +2064,22 @@ sg_status sg_host_taps(int kind, int b, int J, double T, int *q0, double *w) {
   return SG_OK;
 }
 
+sg_status sg_host_time_chunks(int ntf, int chunk, const int *q0, int *out_chunk,
+                              int *out_phase, int *out_nchunk) {
+  if (ntf < 1 || chunk < 1 || !q0 || !out_chunk || !out_phase || !out_nchunk)
+    return fail(SG_EINVAL, "need ntf >= 1, chunk >= 1 and non-NULL pointers");
+  Geometry g{};
+  g.ntf = ntf;
+  g.chunk = chunk;
+  g.nchunk = (ntf + chunk - 1) / chunk;
+  const std::vector<int> v(q0, q0 + ntf);
+  const Geometry h = align_chunks(g, {&v});
+  *out_chunk = h.chunk;
+  *out_phase = h.phase;
+  *out_nchunk = h.nchunk;
+  return SG_OK;
+}
+
 sg_status sg_graph_capture(sg_problem *p, const double *f, const double *u0,
                            const double *v0, double *U, const double *g, double *df,
                            double *du0, double *dv0, hipStream_t s) {

@@ -189,3 +189,33 @@ def test_host_time_diagonalisation_solves_oracle_systems(b, T):
         z_ref = np.linalg.solve(S.T, rhs)
         z = np.real(h["aout"] @ ((h["ain"] @ rhs) / (lam + mu)))
         assert np.abs(z - z_ref).max() <= 1e-12 * np.abs(z_ref).max(), mu
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("b, J, chunk", [(1, 9, 176), (2, 9, 176), (3, 9, 176), (2, 5, 8),
+                                         (4, 6, 64), (5, 5, 8), (2, 12, 1368)])
+def test_time_chunks_hold_the_finest_window_fixed(kind, b, J, chunk):
+    """The chunks a streaming pass takes when the finest level's component has
+    time level b (a coarsest level b of the combination): they tile the slabs
+    0..2^J in order, none is empty, q0 is constant on each (the kernels keep
+    the finest level's three coefficients fixed per block), and the chunk
+    length is the longest such one up to the requested length (for b = 1,
+    the requested length with no phase)."""
+    import paper_2606_09688_amd as sg
+    q0, _ = sg.host_taps(kind, b, J, 1.0)
+    ntf = 2 ** J + 1
+    c, ph, nch = sg.host_time_chunks(q0, chunk)
+    assert 1 <= c <= chunk and 0 <= ph < c
+    spans = [(max(0, k * c - ph), min((k + 1) * c - ph, ntf)) for k in range(nch)]
+    assert spans[0][0] == 0 and spans[-1][1] == ntf
+    assert all(a < e for a, e in spans)
+    assert all(spans[k][1] == spans[k + 1][0] for k in range(nch - 1))
+    for a, e in spans:
+        assert np.all(q0[a:e] == q0[a])
+    if b == 1:
+        assert (c, ph) == (chunk, 0)
+    # no longer chunk length would do
+    moves = [n for n in range(1, ntf) if q0[n] != q0[n - 1]]
+    for c2 in range(c + 1, chunk + 1):
+        p2 = (c2 - moves[0] % c2) % c2
+        assert any((n + p2) % c2 for n in moves)
