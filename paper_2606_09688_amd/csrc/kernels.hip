@@ -932,8 +932,16 @@ __device__ __forceinline__ void reduce_body(const Geometry &g, const Channel *__
   const int it = find_item(items, nitems, gid, gw);
   if (gid >= total) return;
   const Channel &C = ch[items[it].ch];
+  // the channel's fields once, ahead of the loops (a field read inside a
+  // conditional loop body is read again on every trip, each read one more
+  // memory round trip before the partial it addresses)
+  const int a = C.a, qb = C.qb;
+  const long long part_off = C.part_off;
+  const int *const q0 = C.q0;
+  double *const data = C.data;
+  const double scale = C.scale;
   const long long loc = gid - items[it].start;
-  const int a = C.a, r = g.J - a;
+  const int r = g.J - a;
   const int na = (1 << a) - 1;
   // 32-bit index arithmetic: a channel holds fewer than 2^31 coefficients
   const int nsp = (D == 2) ? na * na : na;
@@ -946,26 +954,44 @@ __device__ __forceinline__ void reduce_body(const Geometry &g, const Channel *__
   int tx0, tx1, ty0 = 0, ty1 = 0;
   tile_range(TS, r, Px, g.ntile, tx0, tx1);
   if (D == 2) tile_range(TS, r, Py, g.ntile, ty0, ty1);
+  // the node's (up to 2 x 2) tiles: offsets within a partial block, or -1
+  constexpr int NY = (D == 2) ? 2 : 1;
+  long long toff[NY][2];
+#pragma unroll
+  for (int dy = 0; dy < NY; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 2; ++dx) {
+      const int ty = ty0 + dy, tx = tx0 + dx;
+      const int jy = (D == 2) ? Py - tile_lo(TS, ty, r, 0) : 0;
+      const int jx = Px - tile_lo(TS, tx, r, 0);
+      const bool ok = ty <= ty1 && tx <= tx1 && jy >= 0 && jy < nr && jx >= 0 && jx < nr;
+      toff[dy][dx] = ok ? (long long)(ty * g.ntile + tx) * qb * sz + jy * nr + jx : -1;
+    }
+  // per chunk whose window holds q: its partials of those tiles, loaded
+  // together and added in the fixed order ty, tx
   double acc = 0.0;
   for (int c = 0; c < g.nchunk; ++c) {
     int cn0, cn1;
     chunk_span(g, c, cn0, cn1);
-    const int qlo = gld(C.q0, cn0), qhi = gld(C.q0, cn1 - 1) + 2;
+    const int qlo = gld(q0, cn0), qhi = gld(q0, cn1 - 1) + 2;
     if (q < qlo || q > qhi) continue;
-    for (int ty = ty0; ty <= ty1; ++ty) {
-      const int jy = (D == 2) ? Py - tile_lo(TS, ty, r, 0) : 0;
-      if (jy < 0 || jy >= nr) continue;
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        const int jx = Px - tile_lo(TS, tx, r, 0);
-        if (jx < 0 || jx >= nr) continue;
-        const int tile = ty * g.ntile + tx;
-        acc += part[C.part_off +
-                    (((long long)c * ntileD + tile) * C.qb + (q - qlo)) * (long long)sz +
-                    jy * nr + jx];
+    const long long base = part_off + ((long long)c * ntileD * qb + (q - qlo)) * (long long)sz;
+    double v[NY][2];
+#pragma unroll
+    for (int dy = 0; dy < NY; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const long long o = toff[dy][dx];
+        const double x = part[o >= 0 ? base + o : base];
+        v[dy][dx] = o >= 0 ? x : 0.0;
       }
+#pragma unroll
+    for (int dy = 0; dy < NY; ++dy) {
+      acc += v[dy][0];
+      acc += v[dy][1];
     }
   }
-  gst(C.data, loc, C.scale * acc);
+  gst(data, loc, scale * acc);
 }
 
 template <int D, int TS>
@@ -1072,22 +1098,26 @@ __device__ __forceinline__ void coarse_restrict_body(const Geometry &g,
   const int it = find_item(items, nitems, gid, gw);
   if (gid >= total) return;
   const Channel &C = ch[items[it].ch];
+  const int a = C.a;  // the channel's fields once, ahead of the loop
+  const int *const q0 = C.q0;
+  const double *const w = C.w;
+  double *const data = C.data;
+  const double scale = C.scale;
   const long long loc = gid - items[it].start;
-  const int a = C.a;
   const int na = (1 << a) - 1;
   const int nsp = (D == 2) ? na * na : na;
   const int q = (int)loc / nsp;  // coarse channels hold fewer than 2^31 values
   const int K = (int)loc - q * nsp;
   const long long tot = coarse_off(D, g.A0), off = coarse_off(D, a) + K;
-  const int nlo = lower_bound_q(C.q0, g.ntf, q - 2);
-  const int nhi = lower_bound_q(C.q0, g.ntf, q + 1);  // exclusive
+  const int nlo = lower_bound_q(q0, g.ntf, q - 2);
+  const int nhi = lower_bound_q(q0, g.ntf, q + 1);  // exclusive
   // q0 is nondecreasing, so every slab in [nlo, nhi) has q - 2 <= q0[n] <= q:
   // no test in the loop, whose loads can then be in flight together
   double acc = 0.0;
 #pragma unroll 4
   for (int n = nlo; n < nhi; ++n)
-    acc += gld(C.w, 3 * n + (q - gld(C.q0, n))) * SL[(long long)n * tot + off];
-  gst(C.data, loc, C.scale * acc);
+    acc += gld(w, 3 * n + (q - gld(q0, n))) * SL[(long long)n * tot + off];
+  gst(data, loc, scale * acc);
 }
 
 template <int D>
@@ -1126,6 +1156,13 @@ __device__ __forceinline__ void prolong_coarse_body(const Geometry &g,
       if (X < 1 || X > nc || (D == 2 && (Y < 1 || Y > nc))) return 0.0;
       return cur[(D == 2 ? (Y - 1) * nc : 0) + X - 1];
     };
+    // the level's two channels, read once per level (uniform)
+    const Channel &C0 = ch[(a - 1) * 2], &C1 = ch[(a - 1) * 2 + 1];
+    const bool act[2] = {a < A0 && C0.active != 0, a < A0 && C1.active != 0};
+    const int *const cq0[2] = {C0.q0, C1.q0};
+    const double *const cw[2] = {C0.w, C1.w};
+    const double *const cdata[2] = {C0.data, C1.data};
+    const double cscale[2] = {C0.scale, C1.scale};
     for (int i = threadIdx.x; i < nspa; i += blockDim.x) {
       const int Px = i % na + 1, Py = (D == 2) ? i / na + 1 : 0;
       double v = 0.0;
@@ -1143,16 +1180,15 @@ __device__ __forceinline__ void prolong_coarse_body(const Geometry &g,
         continue;
       }
       for (int k = 0; k < 2; ++k) {
-        const Channel &C = ch[(a - 1) * 2 + k];
-        if (!C.active) continue;
-        const int q0n = gld(C.q0, n);
+        if (!act[k]) continue;
+        const int q0n = gld(cq0[k], n);
         double sv = 0.0;
         for (int kk = 0; kk < 3; ++kk) {
-          const double w = gld(C.w, 3 * n + kk);
+          const double w = gld(cw[k], 3 * n + kk);
           if (w == 0.0) continue;  // (a window past the last time node)
-          sv += w * gld(C.data, (long long)(q0n + kk) * nspa + i);
+          sv += w * gld(cdata[k], (long long)(q0n + kk) * nspa + i);
         }
-        v += C.scale * sv;
+        v += cscale[k] * sv;
       }
       nxt[i] = v;
     }
