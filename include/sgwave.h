@@ -294,13 +294,17 @@ const char *sg_last_error(void);
 /*
  * Batches of independent problems (any mix of d, L and wave speeds; the
  * components of every problem are independent, Rem. 2).  A batch references
- * n assembled handles (the caller keeps them alive and owns them).  The
- * streaming passes of every problem (restriction of the data, prolongation
- * into the outputs) run on parallel branch streams forked from and joined
- * into the caller's stream; each solve stage (time-diagonalised strip
- * solves, block solves, sine / eigenvector transforms, per-mode time solves,
- * load and adjoint post-passes) runs as ONE launch over the concatenated
- * work lists of all problems, longest contractions and time levels first.
+ * n assembled handles (the caller keeps them alive and owns them).  Every
+ * stage runs as ONE launch over all problems per kernel variant, on the
+ * caller's stream: each streaming stage (fine stencils, restriction of the
+ * data, reductions, coarse levels, prolongation into the outputs) over the
+ * block ranges of all problems, longest blocks first; each solve stage
+ * (time-diagonalised strip solves, block solves, sine / eigenvector
+ * transforms, per-mode time solves, load and adjoint post-passes) over the
+ * concatenated work lists of all problems, longest contractions and time
+ * levels first.  The per-call data pointers go to the device in a table
+ * uploaded by each eager call (stream ordered; the captured graph keeps its
+ * own).
  * Argument arrays hold n device pointers each (host arrays).
  * sg_batch_create: builds the merged work lists (allocates device memory).
  * sg_batch_solve / sg_batch_adjoint: the batched forward / adjoint, stream

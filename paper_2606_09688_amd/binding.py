@@ -396,8 +396,8 @@ class SparseGridWave:
 
 class SparseGridBatch:
     """Independent problems (any mix of d, L, speeds) run together
-    (sg_batch_*): streaming passes per problem on parallel branch streams,
-    one launch per solve stage for all problems; eager (solve, adjoint) or
+    (sg_batch_*): every stage (streaming or solve) one launch over all
+    problems; eager (solve, adjoint) or
     captured into one HIP graph (capture, replay).  The solvers must stay
     alive while the batch exists."""
 

@@ -2146,11 +2146,11 @@ sg_status sg_graph_capture(sg_problem *p, const double *f, const double *u0,
 
 }  // extern "C"
 
-// A batch of independent assembled problems.  Streaming passes (restriction
-// of the data, prolongation into U / df / du0 / dv0) run per problem on
-// parallel branch streams; every solve stage runs once for all problems,
-// over the concatenated descriptor lists of all their components (the
-// largest components first).
+// A batch of independent assembled problems.  Every stage runs once for all
+// problems: the streaming stages (restriction of the data, reductions,
+// coarse levels, prolongation into U / df / du0 / dv0) over the block ranges
+// of all problems, the solve stages over the concatenated descriptor lists of
+// all their components (the largest components first).
 // One stage of a batch over many problems: one launch per kernel variant
 // present (problems of another dimension or tile size run other kernels),
 // over the members' block ranges (each starting at a multiple of 8 blocks).
@@ -2376,8 +2376,6 @@ sg_status merge_fdm(sg_batch *b, FdmList sg_problem::*member, FdmList &out) {
   if ((st = merge_gemm_list(b, gf, out.gf))) return st;
   return merge_gemm_list(b, gi, out.gi);
 }
-
-// fork a set of branch streams off s / join them back into s
 
 // ---- streaming stages of a batch -------------------------------------------
 
@@ -2849,9 +2847,10 @@ sg_status sg_batch_capture(sg_batch *b, const double *const *f, const double *co
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   // The adjoint is independent of the forward for a given cotangent and has
   // its own buffers, so it could run on its own branch of the graph; that
-  // form (the adjoint's branch streams forked from the forked stream) ended
-  // in a host segmentation fault on the GPU, cause not found, so it is
-  // switched off: the batch captures the adjoint after the forward.
+  // form (in an earlier layout whose streaming passes forked branch streams
+  // of their own from the forked stream) ended in a host segmentation fault
+  // on the GPU, cause not found, so it stays switched off: the batch
+  // captures the adjoint after the forward.
   constexpr bool kConcurrentBatchAdjoint = false;
   bool par = kConcurrentBatchAdjoint && g != nullptr;
   const int nb = (int)b->probs.size();
