@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--c5-steps", type=int, default=3)
     ap.add_argument("--no-c5-plain", action="store_true",
                     help="skip the batch's plain per-component loop (profiling runs)")
+    ap.add_argument("--no-1d", action="store_true", help="skip the two 1-D configurations")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of one fine array (counter scaling)")
     return ap.parse_args()
@@ -288,6 +289,52 @@ def coarse_mesh_study(sg, spec, sv, f, u0, v0, stream, b0s=(1, 2, 3), reps=3):
             svb.close()
     del U
     torch.cuda.empty_cache()
+    return out
+
+
+def configs_1d(sg, stream, reps=10):
+    """The two 1-D configurations: c2 (L=12, T=2, c = 1 | 1/2, f = 0,
+    Gaussian u0) and c4 (L=14, c on 8 cells ~ U[0.5, 2], Gaussian source,
+    u0 = 0.1 sin(pi x); seeded N(0,1) cotangent).  Forward + adjoint replayed
+    from one captured graph (adjoint on its concurrent branch): ms per step,
+    sparse DoFs per second and the rate of the four fine-array passes
+    (read f, write U, read g, write df) against 8 TB/s."""
+    import numpy as np
+    import torch
+    import workloads
+    out = {}
+    for name, (spec, data) in (("c2", workloads.c2()), ("c4", workloads.c4())):
+        dev = "cuda:0"
+        to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+        f, u0, v0 = to(data["f"]), to(data["u0"]), to(data["v0"])
+        g = to(np.random.default_rng([0, 2000]).standard_normal(spec.shape()))
+        sv = sg.SparseGridWave(*spec.args(), tuned=True)
+        U = torch.empty(sv.shape, dtype=torch.float64, device=dev)
+        df = torch.empty_like(U)
+        du0 = torch.empty(sv.space_shape, dtype=torch.float64, device=dev)
+        dv0 = torch.empty_like(du0)
+        with torch.cuda.stream(stream):
+            sv.capture(f, u0, v0, U, g, df, du0, dv0, stream=stream)
+            sv.replay(stream=stream)
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            for _ in range(reps):
+                sv.replay(stream=stream)
+            e1.record(stream)
+        stream.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        fine_bytes = 8 * sv.n_full
+        out[name] = {"spec": repr(spec), "n_sparse": sv.n_sparse, "n_full": sv.n_full,
+                     "components": sv.n_components, "ms_per_step": ms,
+                     "fwd_adj_dofs_per_s": sv.n_sparse / (ms * 1e-3),
+                     "fine_pass_GB_per_s": 4 * fine_bytes / (ms * 1e-3) / 1e9,
+                     "fine_pass_frac_of_hbm": 4 * fine_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        sv.close()
+        del f, u0, v0, g, U, df, du0, dv0
+        torch.cuda.empty_cache()
     return out
 
 
@@ -582,6 +629,7 @@ def main():
         energy_out = time_energy(sv, u0, stream, spec.T, K_e, nfull // sv.shape[0])
         l2_out = time_l2(sv, u0, stream)
         l2_out["coarse_mesh_study"] = coarse_mesh_study(sg, spec, sv, f, u0, v0, stream)
+    configs_out = None if args.no_1d else configs_1d(sg, stream)
 
     # dominant fine-grid kernel (timed inside the last timed graph replay when
     # the runtime records captured events, else in the eager runs): each
@@ -628,6 +676,7 @@ def main():
             "graph_equals_eager": graph_equals_eager,
             "energy": energy_out,
             "l2_error": l2_out,
+            "configs_1d": configs_out,
             "stage_ms": {k: v * 1e3 for k, v in stage.items()},
             "kernel_ms": {k: v * 1e3 for k, v in kern_t.items()},
             "kernel_ms_from": (f"{dom}: last timed replay of the graph with the directions in "
