@@ -3360,13 +3360,29 @@ __global__ void __launch_bounds__(64) k_block_solve(const BlockDesc *__restrict_
                           Bl = to_g(KT.Blo[B.b]);
   double *b0 = B.work, *res = b0 + (long long)nq * nx, *tmp = res + (long long)nq * nx;
   auto at = [&](int i, int k) -> long long { return (long long)i * nx + k; };
-  // (T v)_j for the banded time matrix T (A or B, high parts), T or T^T
-  auto band = [&](gptr<const double> T, const double *v, int j, bool trans) -> double {
+  // this lane's entries of the banded time matrices (its row of A and B, or
+  // its column for the transpose), the same at every spatial block: read
+  // once here instead of once per block and sweep (each read a round trip
+  // on the sweep's sequential path)
+  double tA[5], tB[5];
+#pragma unroll
+  for (int o = 0; o < 5; ++o) {
+    const int off = o - 2, i = lane + off;
+    const bool ok = lane < nq && i >= 0 && i < nq;
+    const int e = ok ? (tr ? i * 5 + 2 - off : lane * 5 + off + 2) : 0;
+    const double a = Ah[e], b = Bh[e];
+    tA[o] = ok ? a : 0.0;
+    tB[o] = ok ? b : 0.0;
+  }
+  // (T v)_lane for the banded time matrix T (A or B, high parts), T or T^T,
+  // terms in the order off = -2..2
+  auto band = [&](const double (&t)[5], const double *v) -> double {
     double acc = 0.0;
-    for (int off = -2; off <= 2; ++off) {
-      const int i = j + off;
+#pragma unroll
+    for (int o = 0; o < 5; ++o) {
+      const int i = lane + o - 2;
       if (i < 0 || i >= nq) continue;
-      acc += (trans ? T[i * 5 + 2 - off] : T[j * 5 + off + 2]) * v[i];
+      acc += t[o] * v[i];
     }
     return acc;
   };
@@ -3396,8 +3412,8 @@ __global__ void __launch_bounds__(64) k_block_solve(const BlockDesc *__restrict_
         if (lane < nq) {
           double w = tmp[at(lane, k)];
           if (k + 1 < nx)
-            w -= B.mk[kSpaceStride * k + 1] * band(Ah, s_v, lane, false) +
-                 B.mk[kSpaceStride * k + 3] * band(Bh, s_v, lane, false);
+            w -= B.mk[kSpaceStride * k + 1] * band(tA, s_v) +
+                 B.mk[kSpaceStride * k + 3] * band(tB, s_v);
           s_u[lane] = w;
         }
         __syncthreads();
@@ -3421,8 +3437,8 @@ __global__ void __launch_bounds__(64) k_block_solve(const BlockDesc *__restrict_
         if (lane < nq) {
           double w = R[at(lane, k)];
           if (k > 0)
-            w -= B.mk[kSpaceStride * (k - 1) + 1] * band(Ah, s_v, lane, true) +
-                 B.mk[kSpaceStride * (k - 1) + 3] * band(Bh, s_v, lane, true);
+            w -= B.mk[kSpaceStride * (k - 1) + 1] * band(tA, s_v) +
+                 B.mk[kSpaceStride * (k - 1) + 3] * band(tB, s_v);
           s_u[lane] = w;
         }
         __syncthreads();
