@@ -91,6 +91,8 @@ struct SolveList {
   long long threads = 0;
   std::vector<SolveDesc> h;
 };
+// the direction of a list's systems (one per list: forward or transposed)
+inline int list_transpose(const SolveList &l) { return l.h.empty() ? 0 : l.h[0].transpose; }
 
 struct CompList {
   CompDesc *d = nullptr;
@@ -247,6 +249,18 @@ sg_status upload(sg_problem *p, const std::vector<T> &h, T **out) {
   if (!h.empty()) HIPCHK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
   *out = d;
   return SG_OK;
+}
+
+// k_gemm addresses the operands of one descriptor with 32-bit offsets (the
+// folded reflections included); every descriptor is checked before upload
+sg_status upload(sg_problem *p, const std::vector<GemmDesc> &h, GemmDesc **out) {
+  constexpr long long lim = 0x7fffffffLL;
+  for (const GemmDesc &g : h) {
+    const long long ra = std::max({g.M, g.K, g.nref}) + 1LL, rb = std::max({g.K, g.N, g.nref}) + 1LL;
+    if (ra * g.lda + ra > lim || rb * g.ldb + rb > lim)
+      return fail(SG_ENOTSUP, "transform operand too large for 32-bit offsets");
+  }
+  return upload<GemmDesc>(p, h, out);
 }
 
 // Tiles of side ts (0: the prolongation default, 32 in 2-D and 256 in 1-D);
@@ -786,7 +800,7 @@ sg_status run_solves(sg_problem *p, const GemmList &gx, const GemmList &gy,
   HIPCHK(launch_block_solve(bl.d, bl.n, s));
   HIPCHK(launch_gemm(gx.d, gx.n, gx.tiles, gx.fold, s));
   if (p->d == 2) HIPCHK(launch_gemm(gy.d, gy.n, gy.tiles, gy.fold, s));
-  HIPCHK(launch_time_solve(sl.d, sl.n, sl.threads, s));
+  HIPCHK(launch_time_solve(sl.d, sl.n, sl.threads, list_transpose(sl), s));
   if (p->d == 2) HIPCHK(launch_gemm(giy.d, giy.n, giy.tiles, giy.fold, s));
   HIPCHK(launch_gemm(gix.d, gix.n, gix.tiles, gix.fold, s));
   return SG_OK;
@@ -1735,7 +1749,7 @@ sg_status sg_adjoint(sg_problem *p, const double *g, double *df, double *du0, do
   HIPCHK(launch_block_solve(p->badj.d, p->badj.n, s));
   HIPCHK(launch_gemm(p->agx.d, p->agx.n, p->agx.tiles, p->agx.fold, s));
   if (p->d == 2) HIPCHK(launch_gemm(p->agy.d, p->agy.n, p->agy.tiles, p->agy.fold, s));
-  HIPCHK(launch_time_solve(p->sadj.d, p->sadj.n, p->sadj.threads, s));
+  HIPCHK(launch_time_solve(p->sadj.d, p->sadj.n, p->sadj.threads, list_transpose(p->sadj), s));
   if (p->d == 2) HIPCHK(launch_gemm(p->agiy.d, p->agiy.n, p->agiy.tiles, p->agiy.fold, s));
   HIPCHK(launch_gemm(p->agix.d, p->agix.n, p->agix.tiles, p->agix.fold, s));
   MARK(p, 11, s);
@@ -2606,7 +2620,7 @@ sg_status batch_forward(sg_batch *b, const double *const *f, const double *const
   HIPCHK(launch_block_solve(b->bfwd.d, b->bfwd.n, s));
   HIPCHK(launch_gemm(b->gx.d, b->gx.n, b->gx.tiles, b->gx.fold, s));
   HIPCHK(launch_gemm(b->gy.d, b->gy.n, b->gy.tiles, b->gy.fold, s));
-  HIPCHK(launch_time_solve(b->sfwd.d, b->sfwd.n, b->sfwd.threads, s));
+  HIPCHK(launch_time_solve(b->sfwd.d, b->sfwd.n, b->sfwd.threads, list_transpose(b->sfwd), s));
   HIPCHK(launch_gemm(b->giy.d, b->giy.n, b->giy.tiles, b->giy.fold, s));
   HIPCHK(launch_gemm(b->gix.d, b->gix.n, b->gix.tiles, b->gix.fold, s));
   if ((st = bmark(b, 2, s))) return st;
@@ -2639,7 +2653,7 @@ sg_status batch_adjoint(sg_batch *b, const double *const *g, double *const *df,
   HIPCHK(launch_block_solve(b->badj.d, b->badj.n, s));
   HIPCHK(launch_gemm(b->agx.d, b->agx.n, b->agx.tiles, b->agx.fold, s));
   HIPCHK(launch_gemm(b->agy.d, b->agy.n, b->agy.tiles, b->agy.fold, s));
-  HIPCHK(launch_time_solve(b->sadj.d, b->sadj.n, b->sadj.threads, s));
+  HIPCHK(launch_time_solve(b->sadj.d, b->sadj.n, b->sadj.threads, list_transpose(b->sadj), s));
   HIPCHK(launch_gemm(b->agiy.d, b->agiy.n, b->agiy.tiles, b->agiy.fold, s));
   HIPCHK(launch_gemm(b->agix.d, b->agix.n, b->agix.tiles, b->agix.fold, s));
   if ((st = bmark(b, 6, s))) return st;

@@ -2827,6 +2827,13 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmDesc *__restric
     const int i = tid + e * NT;
     if (tb) { kb = i % BK; n = i / BK; } else { kb = i / BN; n = i % BN; }
   };
+  // Offsets inside one descriptor's operands are 32-bit (checked on the host).
+  // The reflected partner of a folded operand is loaded unconditionally (from
+  // a valid address when it is not used) and added with weight sgn, or 0 at
+  // the unpaired middle index: a conditional add lets the compiler move the
+  // load into a branch that waits for it at once, which serialises the
+  // tile's loads (one memory latency per element instead of one per tile).
+  const int lda = Dd.lda, ldb = Dd.ldb;
   double ra[EA], rb[EB];
   auto load_tile = [&](int k0) {
 #pragma unroll
@@ -2835,12 +2842,11 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmDesc *__restric
       a_at(e, m, k);                                // A: BM x BK
       const int gm = row0 + m, gk = k0 + k;
       const bool oka = gm < M && gk < K;
-      const long long ia =
-          oka ? (ta ? (long long)gk * Dd.lda + gm : (long long)gm * Dd.lda + gk) : 0;
+      const int ia = oka ? (ta ? gk * lda + gm : gm * lda + gk) : 0;
       double va = Ap[ia];
-      if (FOLD == 1 && fd) {
-        const double vr = Ap[oka ? ia + nr1 - 2 * gk : 0];
-        va = gk == hmid ? va : va + sgn * vr;
+      if (FOLD == 1) {
+        const double vr = Ap[fd && oka ? ia + nr1 - 2 * gk : 0];
+        va = fma(fd && gk != hmid ? sgn : 0.0, vr, va);
       }
       ra[e] = oka ? va : 0.0;
     }
@@ -2850,12 +2856,11 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmDesc *__restric
       b_at(e, kb, n);                               // B: BK x BN
       const int gkb = k0 + kb, gn = col0 + n;
       const bool okb = gkb < K && gn < N;
-      const long long ib =
-          okb ? (tb ? (long long)gn * Dd.ldb + gkb : (long long)gkb * Dd.ldb + gn) : 0;
+      const int ib = okb ? (tb ? gn * ldb + gkb : gkb * ldb + gn) : 0;
       double vb = Bp[ib];
-      if (FOLD == 2 && fd) {
-        const double vr = Bp[okb ? (long long)(nr1 - gkb) * Dd.ldb + gn : 0];
-        vb = gkb == hmid ? vb : vb + sgn * vr;
+      if (FOLD == 2) {
+        const double vr = Bp[fd && okb ? (nr1 - gkb) * ldb + gn : 0];
+        vb = fma(fd && gkb != hmid ? sgn : 0.0, vr, vb);
       }
       rb[e] = okb ? vb : 0.0;
     }
@@ -3032,6 +3037,9 @@ __global__ void __launch_bounds__(64) k_time_factor(const SolveDesc *__restrict_
   }
 }
 
+// TR: the transposed (adjoint) systems; one instantiation per direction
+// keeps each kernel's code to the path it runs
+template <int TR>
 __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__ sds,
                                                    int nsd, long long total) {
   // rows per register chunk of a substitution / of the residual (thread path)
@@ -3041,8 +3049,12 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
 #ifndef SG_CR
 #define SG_CR 8
 #endif
+#ifndef SG_CW
+#define SG_CW 4
+#endif
   constexpr int CH = SG_CH;
   constexpr int CR = SG_CR;
+  constexpr int CW = SG_CW;  // rows per chunk of a lane's block (wave path)
   const long long wbase = (long long)blockIdx.x * 64;
   const SolveDesc &S = cref(sds, find_solve(sds, nsd, wbase));
   const KernelTables *kt = &cref(S.kt, 0);
@@ -3058,7 +3070,7 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
   mode_scalars(S, j, mt, d, m, kap);
   const gptr<const double> Ab = to_g(kt->A[b]), Bb = to_g(kt->B[b]), Al = to_g(kt->Alo[b]),
                           Bl = to_g(kt->Blo[b]);
-  const bool tr = S.transpose != 0;
+  constexpr bool tr = TR != 0;
   double *rhs = S.rhs;
   const long long plane = (long long)nq * nm;
   const double *L1 = S.fac, *L2 = L1 + plane, *UD = L2 + plane, *U1 = UD + plane,
@@ -3101,7 +3113,7 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
     const int r0 = min(lane * bk, nq), r1 = min(r0 + bk, nq);
     // which: 0 L y = r (fwd), 1 U x = y (bwd), 2 U^T w = r (fwd), 3 L^T z = w (bwd)
     auto coefs = [&](int which, int i, const double *Rin, double &a, double &b1, double &b2,
-                     double &r) {
+                     double &r) __attribute__((always_inline)) {
       if (which == 0) {
         a = 1.0; b1 = L1[idx(i)]; b2 = L2[idx(i)]; r = Rin[idx(i)];
       } else if (which == 1) {
@@ -3118,21 +3130,32 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
         r = Rin[idx(i)];
       }
     };
-    auto pass = [&](int which, const double *Rin, double *out, bool add) -> double {
+    // the lane's rows are visited in chunks of CW whose coefficients are
+    // loaded together: one memory latency per chunk instead of one per row
+    // on the recurrence's critical path
+    auto pass = [&](int which, const double *Rin, double *out,
+                    bool add) __attribute__((always_inline)) -> double {
       const bool fwd = (which == 0 || which == 2);
       const int cnt = r1 - r0;
       // step 1: block map  S_out = c + H S_in,  S = (v_prev, v_prev2)
       double c1 = 0.0, c2 = 0.0, h11 = 1.0, h21 = 0.0, h12 = 0.0, h22 = 1.0;
-      for (int t = 0; t < cnt; ++t) {
-        const int i = fwd ? r0 + t : r1 - 1 - t;
-        double a, b1, b2, r;
-        coefs(which, i, Rin, a, b1, b2, r);
-        const double v = a * (r - b1 * c1 - b2 * c2);
-        c2 = c1; c1 = v;
-        const double g1 = -a * (b1 * h11 + b2 * h21);
-        h21 = h11; h11 = g1;
-        const double g2 = -a * (b1 * h12 + b2 * h22);
-        h22 = h12; h12 = g2;
+      for (int t0 = 0; t0 < cnt; t0 += CW) {
+        double ca[CW], cb1[CW], cb2[CW], cr[CW];
+#pragma unroll
+        for (int k = 0; k < CW; ++k)
+          if (t0 + k < cnt)
+            coefs(which, fwd ? r0 + t0 + k : r1 - 1 - t0 - k, Rin, ca[k], cb1[k], cb2[k], cr[k]);
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+          if (t0 + k >= cnt) break;
+          const double a = ca[k], b1 = cb1[k], b2 = cb2[k];
+          const double v = a * (cr[k] - b1 * c1 - b2 * c2);
+          c2 = c1; c1 = v;
+          const double g1 = -a * (b1 * h11 + b2 * h21);
+          h21 = h11; h11 = g1;
+          const double g2 = -a * (b1 * h12 + b2 * h22);
+          h22 = h12; h12 = g2;
+        }
       }
       // step 2: inclusive scan of the maps in recurrence order
 #pragma unroll
@@ -3155,16 +3178,27 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
       const int psl = prev < 0 ? 0 : (prev > 63 ? 63 : prev);
       double s1 = __shfl(c1, psl), s2 = __shfl(c2, psl);
       if (prev < 0 || prev > 63) s1 = s2 = 0.0;
-      // step 3: sweep the block from its entry state
+      // step 3: sweep the block from its entry state (a chunk's rows are
+      // read before any of them is written: out may be Rin)
       double xm = 0.0;
-      for (int t = 0; t < cnt; ++t) {
-        const int i = fwd ? r0 + t : r1 - 1 - t;
-        double a, b1, b2, r;
-        coefs(which, i, Rin, a, b1, b2, r);
-        const double v = a * (r - b1 * s1 - b2 * s2);
-        s2 = s1; s1 = v;
-        out[idx(i)] = add ? out[idx(i)] + v : v;
-        xm = fmax(xm, fabs(v));
+      for (int t0 = 0; t0 < cnt; t0 += CW) {
+        double ca[CW], cb1[CW], cb2[CW], cr[CW], old[CW];
+#pragma unroll
+        for (int k = 0; k < CW; ++k)
+          if (t0 + k < cnt) {
+            const int i = fwd ? r0 + t0 + k : r1 - 1 - t0 - k;
+            coefs(which, i, Rin, ca[k], cb1[k], cb2[k], cr[k]);
+            old[k] = add ? out[idx(i)] : 0.0;
+          }
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+          if (t0 + k >= cnt) break;
+          const int i = fwd ? r0 + t0 + k : r1 - 1 - t0 - k;
+          const double v = ca[k] * (cr[k] - cb1[k] * s1 - cb2[k] * s2);
+          s2 = s1; s1 = v;
+          out[idx(i)] = add ? old[k] + v : v;
+          xm = fmax(xm, fabs(v));
+        }
       }
       __syncthreads();  // rows of other lanes are read by the next sweep
       return xm;
@@ -3183,13 +3217,29 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
       return wave_max(pass(3, Y, rhs, add));
     };
     if (S.refine) {
-      for (int i = r0; i < r1; ++i) B0[idx(i)] = rhs[idx(i)];
+      for (int i0 = r0; i0 < r1; i0 += CW) {
+        double v[CW];
+#pragma unroll
+        for (int k = 0; k < CW; ++k)
+          if (i0 + k < r1) v[k] = rhs[idx(i0 + k)];
+#pragma unroll
+        for (int k = 0; k < CW; ++k)
+          if (i0 + k < r1) B0[idx(i0 + k)] = v[k];
+      }
       __syncthreads();
     }
     apply(rhs, false);
     for (int it = 0; it < S.refine; ++it) {
       double xmax = 0.0;
-      for (int i = r0; i < r1; ++i) Y[idx(i)] = resid_row(i, xmax);
+      for (int i0 = r0; i0 < r1; i0 += CR) {
+        double res[CR];
+#pragma unroll
+        for (int k = 0; k < CR; ++k)
+          if (i0 + k < r1) res[k] = resid_row(i0 + k, xmax);
+#pragma unroll
+        for (int k = 0; k < CR; ++k)
+          if (i0 + k < r1) Y[idx(i0 + k)] = res[k];
+      }
       __syncthreads();
       xmax = wave_max(xmax);
       const double dmax = apply(Y, true);
@@ -3785,10 +3835,15 @@ hipError_t launch_time_factor(const SolveDesc *sd, int nsd, long long total, hip
   return hipGetLastError();
 }
 
-hipError_t launch_time_solve(const SolveDesc *sd, int nsd, long long total, hipStream_t s) {
+hipError_t launch_time_solve(const SolveDesc *sd, int nsd, long long total, int transpose,
+                             hipStream_t s) {
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_time_solve, dim3(blocks_for(total, 64)), dim3(64), 0, s, sd, nsd,
-                     total);
+  if (transpose)
+    hipLaunchKernelGGL(k_time_solve<1>, dim3(blocks_for(total, 64)), dim3(64), 0, s, sd, nsd,
+                       total);
+  else
+    hipLaunchKernelGGL(k_time_solve<0>, dim3(blocks_for(total, 64)), dim3(64), 0, s, sd, nsd,
+                       total);
   return hipGetLastError();
 }
 

@@ -269,7 +269,10 @@ hipError_t launch_adjoint_fields(const LevelDesc *ld, int nlev, long long total,
 hipError_t launch_gemm(const GemmDesc *descs, int ndesc, int total_tiles, int fold,
                        hipStream_t s);
 hipError_t launch_time_factor(const SolveDesc *sd, int nsd, long long total, hipStream_t s);
-hipError_t launch_time_solve(const SolveDesc *sd, int nsd, long long total, hipStream_t s);
+// transpose: every descriptor of the list solves the transposed (adjoint)
+// systems (SolveDesc.transpose), else none does
+hipError_t launch_time_solve(const SolveDesc *sd, int nsd, long long total, int transpose,
+                             hipStream_t s);
 hipError_t launch_block_solve(const BlockDesc *bd, int nbd, hipStream_t s);
 // ---- 2-D variable-speed components of short time levels -------------------
 // S = A (x) M + B (x) K(c) is diagonalised in time (B^{-1} A = V diag(lam)
