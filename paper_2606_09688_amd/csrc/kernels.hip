@@ -3037,6 +3037,167 @@ __global__ void __launch_bounds__(64) k_time_factor(const SolveDesc *__restrict_
   }
 }
 
+// Inclusive scan across the wave, in recurrence order, of the affine maps
+// S -> c + H S (S = (v_prev, v_prev2)) of the lanes' row blocks; (s1, s2) is
+// the state entering this lane's block (zero for the first block).
+__device__ __forceinline__ void wave_scan_maps(bool fwd, int lane, double c1, double c2,
+                                               double h11, double h12, double h21, double h22,
+                                               double &s1, double &s2) {
+#pragma unroll
+  for (int dlt = 1; dlt < 64; dlt <<= 1) {
+    const int src = fwd ? lane - dlt : lane + dlt;
+    const int sl = src < 0 ? 0 : (src > 63 ? 63 : src);
+    const double pc1 = __shfl(c1, sl), pc2 = __shfl(c2, sl);
+    const double p11 = __shfl(h11, sl), p12 = __shfl(h12, sl);
+    const double p21 = __shfl(h21, sl), p22 = __shfl(h22, sl);
+    if (src >= 0 && src <= 63) {
+      // mine o theirs: S -> c + H (pc + P S)
+      const double nc1 = c1 + h11 * pc1 + h12 * pc2;
+      const double nc2 = c2 + h21 * pc1 + h22 * pc2;
+      const double n11 = h11 * p11 + h12 * p21, n12 = h11 * p12 + h12 * p22;
+      const double n21 = h21 * p11 + h22 * p21, n22 = h21 * p12 + h22 * p22;
+      c1 = nc1; c2 = nc2; h11 = n11; h12 = n12; h21 = n21; h22 = n22;
+    }
+  }
+  const int prev = fwd ? lane - 1 : lane + 1;
+  const int psl = prev < 0 ? 0 : (prev > 63 ? 63 : prev);
+  s1 = __shfl(c1, psl);
+  s2 = __shfl(c2, psl);
+  if (prev < 0 || prev > 63) s1 = s2 = 0.0;
+}
+
+__device__ __forceinline__ double wave_fmax(double v) {
+#pragma unroll
+  for (int dlt = 32; dlt >= 1; dlt >>= 1) v = fmax(v, __shfl_xor(v, dlt));
+  return v;
+}
+
+// One mode of a time level of nq <= 64 BK rows (BK = 1 or 2; more rows per
+// lane raise the kernel's register count past two waves per SIMD) on one
+// wave with every row in registers: lane l holds rows l BK .. l BK + BK - 1 (the block layout of the
+// general one-wave path for the same nq).  The sweeps, the scans and the
+// double-double refinement are those of the general path, in the same order,
+// but no pass makes a memory round trip: the residual's rows beyond the
+// lane's block come from the lanes beside.  Row indices are constants (a
+// register array indexed at run time would be placed in scratch memory).
+template <int BK, bool TR>
+__device__ __forceinline__ void wave_solve_regs(int lane, int nq, int refine, long long nm, int j,
+                                                double m, double kap, gptr<const double> Ab,
+                                                gptr<const double> Bb, gptr<const double> Al,
+                                                gptr<const double> Bl, const double *L1,
+                                                const double *L2, const double *UD,
+                                                const double *U1, const double *U2,
+                                                double *rhs) {
+  auto idx = [&](int i) -> long long { return (long long)i * nm + j; };
+  const int r0 = min(lane * BK, nq), cnt = min(r0 + BK, nq) - r0;
+  // row t of the lane: coefficients of the forward-in-time sweep (P = 0: L,
+  // or U^T) and of the backward one (P = 1: U, or L^T); the solution x, the
+  // right-hand side b, the intermediate y
+  double pa[2][BK], pb1[2][BK], pb2[2][BK], x[BK], b[BK], y[BK];
+#pragma unroll
+  for (int t = 0; t < BK; ++t) {
+    pa[0][t] = pb1[0][t] = pb2[0][t] = pa[1][t] = pb1[1][t] = pb2[1][t] = 0.0;
+    x[t] = b[t] = y[t] = 0.0;
+    if (t < cnt) {
+      const int i = r0 + t;
+      b[t] = rhs[idx(i)];
+      if (!TR) {
+        pa[0][t] = 1.0; pb1[0][t] = L1[idx(i)]; pb2[0][t] = L2[idx(i)];
+        pa[1][t] = UD[idx(i)]; pb1[1][t] = U1[idx(i)]; pb2[1][t] = U2[idx(i)];
+      } else {
+        pa[0][t] = UD[idx(i)];
+        pb1[0][t] = i >= 1 ? U1[idx(i - 1)] : 0.0;
+        pb2[0][t] = i >= 2 ? U2[idx(i - 2)] : 0.0;
+        pa[1][t] = 1.0;
+        pb1[1][t] = i + 1 < nq ? L1[idx(i + 1)] : 0.0;
+        pb2[1][t] = i + 2 < nq ? L2[idx(i + 2)] : 0.0;
+      }
+    }
+  }
+  auto spass = [&](int P, const double (&in)[BK], double (&out)[BK],
+                   bool add) __attribute__((always_inline)) -> double {
+    const bool fwd = P == 0;
+    double c1 = 0.0, c2 = 0.0, h11 = 1.0, h21 = 0.0, h12 = 0.0, h22 = 1.0;
+#pragma unroll
+    for (int k = 0; k < BK; ++k) {
+      const int t = fwd ? k : BK - 1 - k;
+      if (t >= cnt) continue;
+      const double a = pa[P][t], b1 = pb1[P][t], b2 = pb2[P][t];
+      const double v = a * (in[t] - b1 * c1 - b2 * c2);
+      c2 = c1; c1 = v;
+      const double g1 = -a * (b1 * h11 + b2 * h21);
+      h21 = h11; h11 = g1;
+      const double g2 = -a * (b1 * h12 + b2 * h22);
+      h22 = h12; h12 = g2;
+    }
+    double s1, s2;
+    wave_scan_maps(fwd, lane, c1, c2, h11, h12, h21, h22, s1, s2);
+    double xm = 0.0;
+#pragma unroll
+    for (int k = 0; k < BK; ++k) {
+      const int t = fwd ? k : BK - 1 - k;
+      if (t >= cnt) continue;
+      const double v = pa[P][t] * (in[t] - pb1[P][t] * s1 - pb2[P][t] * s2);
+      s2 = s1; s1 = v;
+      out[t] = add ? out[t] + v : v;
+      xm = fmax(xm, fabs(v));
+    }
+    return xm;
+  };
+  auto apply = [&](const double (&R)[BK], bool add) __attribute__((always_inline)) -> double {
+    spass(0, R, y, false);
+    return wave_fmax(spass(1, y, x, add));
+  };
+  apply(b, false);
+  for (int it = 0; it < refine; ++it) {
+    // rows just outside the block: the two before and the two after it
+    // (lanes two and one to each side when BK = 1, else the lanes beside)
+    const int sm1 = lane > 0 ? lane - 1 : 0, sp1 = lane < 63 ? lane + 1 : 63;
+    const int sm2 = lane > 1 ? lane - 2 : 0, sp2 = lane < 62 ? lane + 2 : 63;
+    const double xm1 = __shfl(x[BK - 1], sm1);
+    const double xm2 = BK >= 2 ? __shfl(x[BK >= 2 ? BK - 2 : 0], sm1) : __shfl(x[0], sm2);
+    const double xp1 = __shfl(x[0], sp1);
+    const double xp2 = BK >= 2 ? __shfl(x[BK >= 2 ? 1 : 0], sp1) : __shfl(x[0], sp2);
+    // x at block position u = -2 .. BK + 1
+    auto xat = [&](int u) __attribute__((always_inline)) -> double {
+      return u == -2 ? xm2 : u == -1 ? xm1 : u == BK ? xp1 : u == BK + 1 ? xp2 : x[u < 0 ? 0 : (u >= BK ? BK - 1 : u)];
+    };
+    double xmax = 0.0, res[BK];
+#pragma unroll
+    for (int t = 0; t < BK; ++t) {
+      res[t] = 0.0;
+      if (t >= cnt) continue;
+      {
+        // residual row i: b_i - (op(E) x)_i, in double-double, as resid_row
+#pragma clang fp contract(off)
+        const int i = r0 + t;
+        dd acc = {b[t], 0.0};
+#pragma unroll
+        for (int off = -2; off <= 2; ++off) {
+          const int jj = i + off;
+          if (jj < 0 || jj >= nq) continue;
+          const int r = TR ? jj : i, c = TR ? 2 - off : off + 2;
+          const double xv = xat(t + off);
+          if (off == 0) xmax = fmax(xmax, fabs(xv));
+          dd t1 = triple(m, Ab[r * 5 + c], xv);
+          dd t2 = triple(kap, Bb[r * 5 + c], xv);
+          t1.l = fma(m * Al[r * 5 + c], xv, t1.l);
+          t2.l = fma(kap * Bl[r * 5 + c], xv, t2.l);
+          acc = dd_add(acc, {-t1.h, -t1.l});
+          acc = dd_add(acc, {-t2.h, -t2.l});
+        }
+        res[t] = acc.h + acc.l;
+      }
+    }
+    xmax = wave_fmax(xmax);
+    const double dmax = apply(res, true);
+    if (dmax <= 1e-15 * xmax) break;
+  }
+#pragma unroll
+  for (int t = 0; t < BK; ++t)
+    if (t < cnt) rhs[idx(r0 + t)] = x[t];
+}
+
 // TR: the transposed (adjoint) systems; one instantiation per direction
 // keeps each kernel's code to the path it runs
 template <int TR>
@@ -3111,38 +3272,11 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
     // its entry state, and the block is then swept once more.
     const int bk = (nq + 63) / 64;
     const int r0 = min(lane * bk, nq), r1 = min(r0 + bk, nq);
-    // inclusive scan across the wave, in recurrence order, of the block maps
-    // S -> c + H S; (s1, s2) = the state entering this lane's block
     auto wave_scan = [&](bool fwd, double c1, double c2, double h11, double h12, double h21,
                          double h22, double &s1, double &s2) __attribute__((always_inline)) {
-#pragma unroll
-      for (int dlt = 1; dlt < 64; dlt <<= 1) {
-        const int src = fwd ? lane - dlt : lane + dlt;
-        const int sl = src < 0 ? 0 : (src > 63 ? 63 : src);
-        const double pc1 = __shfl(c1, sl), pc2 = __shfl(c2, sl);
-        const double p11 = __shfl(h11, sl), p12 = __shfl(h12, sl);
-        const double p21 = __shfl(h21, sl), p22 = __shfl(h22, sl);
-        if (src >= 0 && src <= 63) {
-          // mine o theirs: S -> c + H (pc + P S)
-          const double nc1 = c1 + h11 * pc1 + h12 * pc2;
-          const double nc2 = c2 + h21 * pc1 + h22 * pc2;
-          const double n11 = h11 * p11 + h12 * p21, n12 = h11 * p12 + h12 * p22;
-          const double n21 = h21 * p11 + h22 * p21, n22 = h21 * p12 + h22 * p22;
-          c1 = nc1; c2 = nc2; h11 = n11; h12 = n12; h21 = n21; h22 = n22;
-        }
-      }
-      const int prev = fwd ? lane - 1 : lane + 1;
-      const int psl = prev < 0 ? 0 : (prev > 63 ? 63 : prev);
-      s1 = __shfl(c1, psl);
-      s2 = __shfl(c2, psl);
-      if (prev < 0 || prev > 63) s1 = s2 = 0.0;
+      wave_scan_maps(fwd, lane, c1, c2, h11, h12, h21, h22, s1, s2);
     };
-    auto wave_max = [&](double v) -> double {
-#pragma unroll
-      for (int dlt = 32; dlt >= 1; dlt >>= 1) v = fmax(v, __shfl_xor(v, dlt));
-      return v;
-    };
-    // which: 0 L y = r (fwd), 1 U x = y (bwd), 2 U^T w = r (fwd), 3 L^T z = w (bwd)
+    auto wave_max = [&](double v) -> double { return wave_fmax(v); };
     auto coefs = [&](int which, int i, const double *Rin, double &a, double &b1, double &b2,
                      double &r) __attribute__((always_inline)) {
       if (which == 0) {
@@ -3161,131 +3295,17 @@ __global__ void __launch_bounds__(64) k_time_solve(const SolveDesc *__restrict__
         r = Rin[idx(i)];
       }
     };
-    if (bk <= 2) {
-      // ---- time levels of at most 128 rows: a lane's (at most two) rows stay
-      // in registers for the whole solve and the residual's neighbouring rows
-      // come from the lanes beside, so neither the sweeps nor the refinement
-      // make memory round trips.  The arithmetic is that of the general path
-      // below, in the same order. ----
-      const int cnt = r1 - r0;
-      // row t of the lane: coefficients of the forward-in-time sweep (P = 0:
-      // L, or U^T) and of the backward one (P = 1: U, or L^T); the solution x,
-      // the right-hand side b, the intermediate y
-      double pa[2][2], pb1[2][2], pb2[2][2], x[2], b[2], y[2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        pa[0][t] = pb1[0][t] = pb2[0][t] = pa[1][t] = pb1[1][t] = pb2[1][t] = 0.0;
-        x[t] = b[t] = y[t] = 0.0;
-        if (t < cnt) {
-          double r;
-          coefs(tr ? 2 : 0, r0 + t, rhs, pa[0][t], pb1[0][t], pb2[0][t], b[t]);
-          coefs(tr ? 3 : 1, r0 + t, rhs, pa[1][t], pb1[1][t], pb2[1][t], r);
-        }
-      }
-      // rows are visited with constant indices (no register array indexed at
-      // run time, which the compiler would place in scratch memory): forward
-      // sweeps take row 0 then row 1, backward sweeps row 1 then row 0
-      auto spass = [&](int P, const double (&in)[2], double (&out)[2],
-                       bool add) __attribute__((always_inline)) -> double {
-        const bool fwd = P == 0;
-        double c1 = 0.0, c2 = 0.0, h11 = 1.0, h21 = 0.0, h12 = 0.0, h22 = 1.0;
-        auto map_row = [&](int t) __attribute__((always_inline)) {
-          const double a = pa[P][t], b1 = pb1[P][t], b2 = pb2[P][t];
-          const double v = a * (in[t] - b1 * c1 - b2 * c2);
-          c2 = c1; c1 = v;
-          const double g1 = -a * (b1 * h11 + b2 * h21);
-          h21 = h11; h11 = g1;
-          const double g2 = -a * (b1 * h12 + b2 * h22);
-          h22 = h12; h12 = g2;
-        };
-        if (fwd) {
-          if (cnt > 0) map_row(0);
-          if (cnt > 1) map_row(1);
-        } else {
-          if (cnt > 1) map_row(1);
-          if (cnt > 0) map_row(0);
-        }
-        double s1, s2;
-        wave_scan(fwd, c1, c2, h11, h12, h21, h22, s1, s2);
-        double xm = 0.0;
-        auto sweep_row = [&](int t) __attribute__((always_inline)) {
-          const double v = pa[P][t] * (in[t] - pb1[P][t] * s1 - pb2[P][t] * s2);
-          s2 = s1; s1 = v;
-          out[t] = add ? out[t] + v : v;
-          xm = fmax(xm, fabs(v));
-        };
-        if (fwd) {
-          if (cnt > 0) sweep_row(0);
-          if (cnt > 1) sweep_row(1);
-        } else {
-          if (cnt > 1) sweep_row(1);
-          if (cnt > 0) sweep_row(0);
-        }
-        return xm;
-      };
-      auto sapply = [&](const double (&R)[2], bool add) __attribute__((always_inline)) -> double {
-        spass(0, R, y, false);
-        return wave_max(spass(1, y, x, add));
-      };
-      sapply(b, false);
-      for (int it = 0; it < S.refine; ++it) {
-        // x of the lanes one and two to each side (every lane shuffles)
-        double nb[4][2];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          const int src = lane + (d < 2 ? d - 2 : d - 1);
-          const int sl = src < 0 ? 0 : (src > 63 ? 63 : src);
-          nb[d][0] = __shfl(x[0], sl);
-          nb[d][1] = __shfl(x[1], sl);
-        }
-        // x at rows i - 2 .. i + 2 of the lane's row t (i = r0 + t): with one
-        // row per lane from the lanes two and one to each side, with two rows
-        // per lane from the lanes beside
-        auto xwin = [&](int t, double (&w)[5]) __attribute__((always_inline)) {
-          if (bk == 1) {
-            w[0] = nb[0][0]; w[1] = nb[1][0]; w[2] = x[0]; w[3] = nb[2][0]; w[4] = nb[3][0];
-          } else if (t == 0) {
-            w[0] = nb[1][0]; w[1] = nb[1][1]; w[2] = x[0]; w[3] = x[1]; w[4] = nb[2][0];
-          } else {
-            w[0] = nb[1][1]; w[1] = x[0]; w[2] = x[1]; w[3] = nb[2][0]; w[4] = nb[2][1];
-          }
-        };
-        // residual row r0 + t, as resid_row
-        auto sresid = [&](int t, double &xmax) __attribute__((always_inline)) -> double {
-#pragma clang fp contract(off)
-          const int i = r0 + t;
-          double w[5];
-          xwin(t, w);
-          dd acc = {b[t], 0.0};
-#pragma unroll
-          for (int off = -2; off <= 2; ++off) {
-            const int jj = i + off;
-            if (jj < 0 || jj >= nq) continue;
-            const int r = tr ? jj : i, c = tr ? 2 - off : off + 2;
-            const double xv = w[off + 2];
-            if (off == 0) xmax = fmax(xmax, fabs(xv));
-            dd t1 = triple(m, Ab[r * 5 + c], xv);
-            dd t2 = triple(kap, Bb[r * 5 + c], xv);
-            t1.l = fma(m * Al[r * 5 + c], xv, t1.l);
-            t2.l = fma(kap * Bl[r * 5 + c], xv, t2.l);
-            acc = dd_add(acc, {-t1.h, -t1.l});
-            acc = dd_add(acc, {-t2.h, -t2.l});
-          }
-          return acc.h + acc.l;
-        };
-        double xmax = 0.0, res[2] = {0.0, 0.0};
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-          if (t < cnt) res[t] = sresid(t, xmax);
-        xmax = wave_max(xmax);
-        const double dmax = sapply(res, true);
-        if (dmax <= 1e-15 * xmax) break;
-      }
-#pragma unroll
-      for (int t = 0; t < 2; ++t)
-        if (t < cnt) rhs[idx(r0 + t)] = x[t];
-      return;
-    }
+    // time levels of up to 128 nodes (at most 2 rows per lane): every row in
+    // registers
+#define SG_WAVE_REGS(BKV)                                                                   \
+  if (bk == BKV) {                                                                          \
+    wave_solve_regs<BKV, TR != 0>(lane, nq, S.refine, nm, j, m, kap, Ab, Bb, Al, Bl, L1, L2, \
+                                  UD, U1, U2, rhs);                                        \
+    return;                                                                                 \
+  }
+    SG_WAVE_REGS(1)
+    SG_WAVE_REGS(2)
+#undef SG_WAVE_REGS
     // the lane's rows are visited in chunks of CW whose coefficients are
     // loaded together: one memory latency per chunk instead of one per row
     // on the recurrence's critical path
