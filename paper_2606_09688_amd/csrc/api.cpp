@@ -252,13 +252,17 @@ sg_status upload(sg_problem *p, const std::vector<T> &h, T **out) {
 }
 
 // k_gemm addresses the operands of one descriptor with 32-bit offsets (the
-// folded reflections included); every descriptor is checked before upload
+// folded reflections included), and a list shares one operand layout; every
+// descriptor is checked before upload
 sg_status upload(sg_problem *p, const std::vector<GemmDesc> &h, GemmDesc **out) {
   constexpr long long lim = 0x7fffffffLL;
   for (const GemmDesc &g : h) {
     const long long ra = std::max({g.M, g.K, g.nref}) + 1LL, rb = std::max({g.K, g.N, g.nref}) + 1LL;
     if (ra * g.lda + ra > lim || rb * g.ldb + rb > lim)
       return fail(SG_ENOTSUP, "transform operand too large for 32-bit offsets");
+    // the kernel variant of a list is chosen by its operands' layout
+    if (g.ta != h[0].ta || g.tb != h[0].tb)
+      return fail(SG_EINVAL, "transform list mixes operand layouts");
   }
   return upload<GemmDesc>(p, h, out);
 }
@@ -783,11 +787,11 @@ sg_status build_solve_list(sg_problem *p, const std::vector<int> &cset, int tran
 sg_status run_fdm(const FdmList &f, hipStream_t s) {
   if (f.n == 0) return SG_OK;
   HIPCHK(launch_fdm_in(f.d, f.n, f.t, s));
-  HIPCHK(launch_gemm(f.gf.d, f.gf.n, f.gf.tiles, 0, s));
+  HIPCHK(launch_gemm(f.gf.d, f.gf.n, f.gf.tiles, 3, s));  // A read transposed
   HIPCHK(launch_fdm_tri(f.d, f.n, f.t, 0, f.chunk, s));
   HIPCHK(launch_fdm_interface(f.d, f.n, f.t, s));
   HIPCHK(launch_fdm_tri(f.d, f.n, f.t, 1, f.chunk, s));
-  HIPCHK(launch_gemm(f.gi.d, f.gi.n, f.gi.tiles, 0, s));
+  HIPCHK(launch_gemm(f.gi.d, f.gi.n, f.gi.tiles, 4, s));  // B read transposed
   HIPCHK(launch_fdm_out(f.d, f.n, f.t, s));
   return SG_OK;
 }

@@ -2770,6 +2770,8 @@ typedef double sg_double4 __attribute__((ext_vector_type(4)));
 // FOLD = 1 / 2: descriptors with nref > 0 fold the summed index k of A's
 // columns / B's rows with its reflection nref-1-k, and their results are the
 // outputs of one parity, stored at every other column / row of C.
+// FOLD = 3 / 4: plain products whose A / B operand is read transposed (every
+// descriptor of the list has ta / tb set); FOLD = 0: plain products.
 #ifndef SG_GEMM_BK
 #define SG_GEMM_BK 64
 #endif
@@ -2818,7 +2820,7 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm(const GemmDesc *__restric
   // staged element e of this thread: (m, k) of the A tile, (kb, n) of the B
   // tile; consecutive threads take consecutive addresses of the stored
   // operand (along k for A, n for B, or along m / kb when transposed)
-  const bool ta = FOLD == 0 && Dd.ta != 0, tb = FOLD == 0 && Dd.tb != 0;
+  constexpr bool ta = FOLD == 3, tb = FOLD == 4;
   auto a_at = [&](int e, int &m, int &k) {
     const int i = tid + e * NT;
     if (ta) { m = i % BM; k = i / BM; } else { m = i / BK; k = i % BK; }
@@ -3976,6 +3978,10 @@ hipError_t launch_gemm(const GemmDesc *descs, int ndesc, int total_tiles, int fo
     hipLaunchKernelGGL(k_gemm<1>, dim3(total_tiles), dim3(kGemmThreads), 0, s, descs, ndesc);
   else if (fold == 2)
     hipLaunchKernelGGL(k_gemm<2>, dim3(total_tiles), dim3(kGemmThreads), 0, s, descs, ndesc);
+  else if (fold == 3)
+    hipLaunchKernelGGL(k_gemm<3>, dim3(total_tiles), dim3(kGemmThreads), 0, s, descs, ndesc);
+  else if (fold == 4)
+    hipLaunchKernelGGL(k_gemm<4>, dim3(total_tiles), dim3(kGemmThreads), 0, s, descs, ndesc);
   else
     hipLaunchKernelGGL(k_gemm<0>, dim3(total_tiles), dim3(kGemmThreads), 0, s, descs, ndesc);
   return hipGetLastError();

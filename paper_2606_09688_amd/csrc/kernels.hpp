@@ -135,7 +135,9 @@ struct GemmDesc {
   // (fold 2) are the outputs 2 j' + par
   int nref, par;
   // transposed operands (plain products only): ta, element (i, k) of A at
-  // k lda + i; tb, element (k, j) of B at j ldb + k
+  // k lda + i; tb, element (k, j) of B at j ldb + k.  A list is launched
+  // with the k_gemm variant of its operands (FOLD 3 for ta, 4 for tb), and
+  // its descriptors all share the flag (checked when the list is uploaded)
   int ta, tb;
 };
 
