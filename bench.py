@@ -474,7 +474,7 @@ def main():
         copy_calibration(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import workloads
     spec, data = workloads.c3(L=args.L)

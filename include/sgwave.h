@@ -50,7 +50,7 @@ typedef enum {
   SG_EINVAL = -1,   /* invalid argument (sizes, c <= 0, T <= 0, L < 2, NULL) */
   SG_ENOMEM = -2,   /* device or host allocation failed (assemble only)      */
   SG_EDEVICE = -3,  /* a HIP runtime call failed                             */
-  SG_ENOTSUP = -4,  /* configuration outside what this build implements     */
+  SG_ENOTSUP = -4,  /* configuration outside what the library implements   */
   SG_ESTATE = -5    /* call not valid in the handle's current state          */
 } sg_status;
 

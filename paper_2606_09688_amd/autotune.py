@@ -58,7 +58,7 @@ def cache_path():
 
 def device_key():
     """Architecture and compute-unit count (the marketing name is not a
-    stable key: it is empty where the driver's name table is missing)."""
+    stable key: it is empty where the amdgpu device-name table is missing)."""
     import torch
     p = torch.cuda.get_device_properties(0)
     arch = getattr(p, "gcnArchName", "") or ""
