@@ -2060,6 +2060,10 @@ __global__ void __launch_bounds__(256, 2) k_energy_w(const ProlongArgs A,
   __shared__ double s_v_w[4][2][UP];
   __shared__ __align__(16) double s_t_w[4][2][4 * NCI];
   __shared__ double s_f_w[4][2][NP * NP];
+  // the lanes' element sums of up to RB instants, one padded row per instant
+  // (pitch RP: 16-byte rows that fall on different banks)
+  constexpr int RB = 16, RP = 66;
+  __shared__ __align__(16) double s_r_w[4][RB * RP];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double *s_v[2] = {s_v_w[wave][0], s_v_w[wave][1]};  // value, derivative
   double *s_t[2] = {s_t_w[wave][0], s_t_w[wave][1]};
@@ -2313,10 +2317,27 @@ __global__ void __launch_bounds__(256, 2) k_energy_w(const ProlongArgs A,
       const double ky = (hx / 6.0) / hy * (2.0 * gy0 * gy0 + 2.0 * gy0 * gy1 + 2.0 * gy1 * gy1);
       acc += 0.5 * (mass + c2e[e] * (kx + ky));
     }
-    // wave sum, butterfly order (the same in every lane)
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) part[(long long)n * ntileD + tile] = acc;
+    // sum over the wave: every RB instants (and at the chunk's end) lane i
+    // adds the 64 lane sums of instant i in lane order, instead of a chain of
+    // six cross-lane shuffles per instant
+    double *s_r = s_r_w[wave];
+    const int slot = (n - n0) % RB;
+    s_r[slot * RP + lane] = acc;
+    if (slot == RB - 1 || n + 1 == n1) {
+      wave_sync();
+      if (lane <= slot) {
+        const double2 *row = reinterpret_cast<const double2 *>(s_r + lane * RP);
+        double sum = 0.0;
+#pragma unroll 8
+        for (int l = 0; l < 32; ++l) {
+          const double2 v = row[l];
+          sum += v.x;
+          sum += v.y;
+        }
+        part[(long long)(n - slot + lane) * ntileD + tile] = sum;
+      }
+      wave_sync();
+    }
   }
 }
 
